@@ -1,0 +1,152 @@
+/*
+ * orc_average.c -- oracle particle-to-mesh averaging.
+ * TEST INFRASTRUCTURE ONLY (see orc.h).
+ *
+ * Section 2.4 (Diffusion-Based Averaging Method):
+ *  - Eq. (11): the solid fraction of cell k at pseudo-time 0 is the total
+ *    volume of the particles whose centre lies in k divided by the cell
+ *    volume.  The drag is deposited the same way (per-particle forces summed
+ *    per cell, Section 2.2's coupling scheme), as a force density; the sign
+ *    stored is the force on the particles.  Sums run in particle-ID order.
+ *    A centre on a cell face belongs to the upper cell; centres outside the
+ *    mesh are clamped into the first/last cell.
+ *  - Eq. (12): the deposited field then diffuses with unit diffusivity up to
+ *    pseudo-time tau = b^2/4 (b = bandwidth; the paper states the equivalence
+ *    to Gaussian averaging with bandwidth sqrt(4 tau)).  Space: the
+ *    second-order central finite-volume Laplacian on the CFD mesh (Section
+ *    2.5), periodic in x and y, zero flux through the walls at z = 0 and Lz
+ *    (the no-flux wall condition of Section 2.4).  Time: avg_ntau implicit
+ *    (backward Euler) steps of dtau = tau/avg_ntau, each solved by plain
+ *    conjugate gradients from the previous field to a relative residual of
+ *    cg_rtol.
+ */
+#include "orc.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+int orc_deposit(const orc_params* p, int64_t n, const double* x, const double* d,
+                const double* fdrag, double* raw) {
+  int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
+  double hx = p->Lx / p->nx, hy = p->Ly / p->ny, hz = p->Lz / p->nz;
+  double Vc = hx * hy * hz;
+  memset(raw, 0, sizeof(double) * 4 * (size_t)ncell);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t a = (int64_t)floor(x[3 * i] / hx);
+    int64_t b = (int64_t)floor(x[3 * i + 1] / hy);
+    int64_t c = (int64_t)floor(x[3 * i + 2] / hz);
+    a = a < 0 ? 0 : (a >= p->nx ? p->nx - 1 : a);
+    b = b < 0 ? 0 : (b >= p->ny ? p->ny - 1 : b);
+    c = c < 0 ? 0 : (c >= p->nz ? p->nz - 1 : c);
+    int64_t k = (c * p->ny + b) * p->nx + a;
+    double V = (M_PI / 6.0) * d[i] * d[i] * d[i];
+    raw[k] += V;
+    if (fdrag) {
+      raw[ncell + k] += fdrag[3 * i];
+      raw[2 * ncell + k] += fdrag[3 * i + 1];
+      raw[3 * ncell + k] += fdrag[3 * i + 2];
+    }
+  }
+  for (int64_t k = 0; k < 4 * ncell; ++k) raw[k] /= Vc;
+  return 0;
+}
+
+/* y = (I - dtau L_h) x.  L_h sums, over the six faces of a cell, the
+ * difference to the neighbour divided by the squared spacing; wall faces
+ * carry no flux. */
+void orc_apply_A(const orc_params* p, double dtau, const double* x, double* y) {
+  int nx = p->nx, ny = p->ny, nz = p->nz;
+  double ix2 = 1.0 / ((p->Lx / nx) * (p->Lx / nx));
+  double iy2 = 1.0 / ((p->Ly / ny) * (p->Ly / ny));
+  double iz2 = 1.0 / ((p->Lz / nz) * (p->Lz / nz));
+  for (int k = 0; k < nz; ++k) {
+    for (int j = 0; j < ny; ++j) {
+      for (int i = 0; i < nx; ++i) {
+        int64_t c = ((int64_t)k * ny + j) * nx + i;
+        double xc = x[c];
+        int ip = (i + 1) % nx, im = (i + nx - 1) % nx;
+        int jp = (j + 1) % ny, jm = (j + ny - 1) % ny;
+        double lap = 0.0;
+        lap += (x[((int64_t)k * ny + j) * nx + ip] - xc) * ix2;
+        lap += (x[((int64_t)k * ny + j) * nx + im] - xc) * ix2;
+        lap += (x[((int64_t)k * ny + jp) * nx + i] - xc) * iy2;
+        lap += (x[((int64_t)k * ny + jm) * nx + i] - xc) * iy2;
+        if (k + 1 < nz) lap += (x[((int64_t)(k + 1) * ny + j) * nx + i] - xc) * iz2;
+        if (k > 0) lap += (x[((int64_t)(k - 1) * ny + j) * nx + i] - xc) * iz2;
+        y[c] = xc - dtau * lap;
+      }
+    }
+  }
+}
+
+static double dotn(int64_t n, const double* a, const double* b) {
+  double s = 0.0;
+  for (int64_t k = 0; k < n; ++k) s += a[k] * b[k];
+  return s;
+}
+
+/* Solve (I - dtau L_h) x = b by conjugate gradients, starting from x = b. */
+static int cg_solve(const orc_params* p, double dtau, const double* b, double* x,
+                    int64_t* iters, double* r, double* pv, double* Ap) {
+  int64_t n = (int64_t)p->nx * p->ny * p->nz;
+  memcpy(x, b, sizeof(double) * (size_t)n);
+  double bn = sqrt(dotn(n, b, b));
+  if (bn == 0.0) return 0;
+  orc_apply_A(p, dtau, x, Ap);
+  for (int64_t k = 0; k < n; ++k) r[k] = b[k] - Ap[k];
+  memcpy(pv, r, sizeof(double) * (size_t)n);
+  double rr = dotn(n, r, r);
+  int64_t it = 0;
+  while (sqrt(rr) > p->cg_rtol * bn) {
+    if (it > 10000) return -3;
+    orc_apply_A(p, dtau, pv, Ap);
+    double alpha = rr / dotn(n, pv, Ap);
+    for (int64_t k = 0; k < n; ++k) {
+      x[k] += alpha * pv[k];
+      r[k] -= alpha * Ap[k];
+    }
+    double rr2 = dotn(n, r, r);
+    double beta = rr2 / rr;
+    rr = rr2;
+    for (int64_t k = 0; k < n; ++k) pv[k] = r[k] + beta * pv[k];
+    ++it;
+  }
+  if (iters) *iters += it;
+  return 0;
+}
+
+int orc_diffuse(const orc_params* p, int nch, const double* in, double* out, int64_t* iters) {
+  int64_t n = (int64_t)p->nx * p->ny * p->nz;
+  double tau = 0.25 * p->avg_bandwidth * p->avg_bandwidth;
+  int ntau = p->avg_ntau > 0 ? p->avg_ntau : 1;
+  double dtau = tau / ntau;
+  double* cur = (double*)malloc(sizeof(double) * (size_t)n);
+  double* r = (double*)malloc(sizeof(double) * (size_t)n);
+  double* pv = (double*)malloc(sizeof(double) * (size_t)n);
+  double* Ap = (double*)malloc(sizeof(double) * (size_t)n);
+  int rc = 0;
+  if (iters) *iters = 0;
+  if (!cur || !r || !pv || !Ap) {
+    rc = -2;
+    goto out;
+  }
+  for (int ch = 0; ch < nch; ++ch) {
+    const double* src = in + (size_t)ch * n;
+    double* dst = out + (size_t)ch * n;
+    memcpy(cur, src, sizeof(double) * (size_t)n);
+    for (int m = 0; m < ntau; ++m) {
+      rc = cg_solve(p, dtau, cur, dst, iters, r, pv, Ap);
+      if (rc) goto out;
+      memcpy(cur, dst, sizeof(double) * (size_t)n);
+    }
+    if (ntau == 0) memcpy(dst, cur, sizeof(double) * (size_t)n);
+  }
+out:
+  free(cur), free(r), free(pv), free(Ap);
+  return rc;
+}

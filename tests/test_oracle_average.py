@@ -1,0 +1,174 @@
+"""Pins of the oracle's averaging against the mathematics of Section 2.4 (CPU).
+
+  - PCM deposition (Eq. 11) conserves the total particle volume exactly and
+    puts each particle in exactly one cell;
+  - the implicit diffusion solve (Eq. 12) equals the exact discrete solution
+    obtained by diagonalising the operator with FFTs (periodic x, y) and a
+    DCT-II (zero-flux z walls);
+  - it conserves the integral (the no-flux wall condition), is positive, obeys
+    the maximum principle and leaves a uniform field unchanged;
+  - for a point source it converges to the Gaussian kernel with variance
+    2 tau = b^2/2 per axis: first order in the pseudo-time step, second order
+    in the mesh spacing.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import fft as sfft
+
+import workloads
+
+
+def mesh_prm(nx, ny, nz, L=(4e-3, 3e-3, 2.5e-3), b=1.5e-3, ntau=4, rtol=1e-14):
+    return workloads.base_params(Lx=L[0], Ly=L[1], Lz=L[2], nx=nx, ny=ny, nz=nz,
+                                 avg_bandwidth=b, avg_ntau=ntau, cg_rtol=rtol)
+
+
+def spectral_solve(prm, raw, exact_time=False):
+    """Diagonalise -L_h: FFT on the periodic axes, orthonormal DCT-II on z."""
+    nx, ny, nz = prm["nx"], prm["ny"], prm["nz"]
+    hx, hy, hz = prm["Lx"] / nx, prm["Ly"] / ny, prm["Lz"] / nz
+    tau = prm["avg_bandwidth"] ** 2 / 4
+    f = raw.reshape(nz, ny, nx)
+    F = sfft.dct(np.fft.fft2(f, axes=(1, 2)), type=2, axis=0, norm="ortho")
+    kx = 2 * np.pi * np.arange(nx) / nx
+    ky = 2 * np.pi * np.arange(ny) / ny
+    kz = np.pi * np.arange(nz) / nz
+    lam = ((2 - 2 * np.cos(kz))[:, None, None] / hz ** 2 +
+           (2 - 2 * np.cos(ky))[None, :, None] / hy ** 2 +
+           (2 - 2 * np.cos(kx))[None, None, :] / hx ** 2)
+    if exact_time:
+        G = np.exp(-tau * lam)
+    else:
+        G = (1 + tau / prm["avg_ntau"] * lam) ** (-prm["avg_ntau"])
+    out = np.fft.ifft2(sfft.idct(F * G, type=2, axis=0, norm="ortho"), axes=(1, 2))
+    return out.real.ravel()
+
+
+def test_pcm_conserves_volume(orc):
+    w = workloads.workload("bed1m", n=20000)
+    prm = w["params"]
+    raw = orc.deposit(prm, w["x"], w["d"])
+    Vc = prm["Lx"] / prm["nx"] * prm["Ly"] / prm["ny"] * prm["Lz"] / prm["nz"]
+    total = (math.pi / 6 * w["d"] ** 3).sum()
+    assert abs(raw[0].sum() * Vc - total) < 1e-12 * total
+    assert np.all(raw[0] >= 0)
+
+
+def test_pcm_single_particle_and_faces(orc):
+    prm = mesh_prm(4, 4, 4, L=(4e-3, 4e-3, 4e-3))
+    d = np.array([0.5e-3])
+    Vc = 1e-9
+    for pos, cell in (([0.5e-3, 0.5e-3, 0.5e-3], 0), ([1.0e-3, 0.5e-3, 0.5e-3], 1),
+                      ([1.5e-3, 2.0e-3, 3.0e-3], (3 * 4 + 2) * 4 + 1)):
+        raw = orc.deposit(prm, np.array([pos]), d, np.array([[1.0, 2.0, 3.0]]))
+        nz = np.flatnonzero(raw[0])
+        assert list(nz) == [cell]  # a centre on a face belongs to the upper cell
+        assert raw[0, cell] == pytest.approx(math.pi / 6 * 0.5e-3 ** 3 / Vc, rel=1e-14)
+        assert raw[1:, cell] == pytest.approx(np.array([1.0, 2.0, 3.0]) / Vc, rel=1e-14)
+
+
+@pytest.mark.parametrize("shape,ntau", [((8, 6, 5), 4), ((16, 12, 10), 1), ((10, 10, 24), 8)])
+def test_diffusion_equals_spectral_solution(orc, shape, ntau):
+    prm = mesh_prm(*shape, ntau=ntau)
+    rng = np.random.default_rng(sum(shape))
+    raw = rng.random((2, np.prod(shape))) ** 4
+    out, iters = orc.diffuse(prm, raw)
+    assert iters > 0
+    for c in range(2):
+        ref = spectral_solve(prm, raw[c])
+        assert np.max(np.abs(out[c] - ref)) < 1e-12 * np.max(np.abs(raw[c]))
+
+
+def test_diffusion_conservation_positivity_max_principle(orc):
+    prm = mesh_prm(12, 10, 16)
+    rng = np.random.default_rng(3)
+    raw = np.zeros(12 * 10 * 16)
+    raw[rng.choice(raw.size, 40, replace=False)] = rng.random(40)
+    out, _ = orc.diffuse(prm, raw[None])
+    assert abs(out.sum() - raw.sum()) < 1e-12 * raw.sum()
+    assert out.min() >= 0.0
+    assert out.max() <= raw.max()
+    uni, _ = orc.diffuse(prm, np.full((1, raw.size), 0.37))
+    assert np.max(np.abs(uni - 0.37)) < 1e-14
+
+
+def gaussian_cells(prm, centre, mass):
+    """Cell averages of a point source's heat kernel (variance 2 tau per axis),
+    with periodic images in x, y (walls far away)."""
+    from scipy.special import erf
+    tau = prm["avg_bandwidth"] ** 2 / 4
+    s = math.sqrt(4 * tau)
+    out = []
+    for ax, (L, n) in enumerate(((prm["Lx"], prm["nx"]), (prm["Ly"], prm["ny"]),
+                                 (prm["Lz"], prm["nz"]))):
+        edges = np.arange(n + 1) * (L / n)
+        acc = np.zeros(n)
+        shifts = (-1, 0, 1) if ax < 2 else (0,)
+        for k in shifts:
+            e = (edges - centre[ax] + k * L) / s
+            acc += 0.5 * np.diff(erf(e))
+        out.append(acc / (L / n))
+    gx, gy, gz = out
+    return mass * gz[:, None, None] * gy[None, :, None] * gx[None, None, :]
+
+
+def test_point_source_converges_to_gaussian(orc):
+    b = 1.5e-3
+    sigma = b / math.sqrt(2)
+    L = 12 * sigma
+    # pseudo-time: backward Euler -> semi-discrete (exact in time) at first order
+    prm = mesh_prm(24, 24, 24, L=(L, L, L), b=b)
+    src = np.zeros(24 ** 3)
+    c = (12 * 24 + 12) * 24 + 12
+    src[c] = 1.0
+    semi = spectral_solve(prm, src, exact_time=True)
+    errs = []
+    for nt in (4, 8, 16, 32, 64):
+        out, _ = orc.diffuse(dict(prm, avg_ntau=nt), src[None])
+        errs.append(np.max(np.abs(out[0] - semi)))
+    ratios = [errs[k] / errs[k + 1] for k in range(4)]
+    assert all(r > 1.9 for r in ratios)  # monotone convergence
+    assert 1.9 < ratios[-1] < 2.15 and ratios[-1] < ratios[-2]  # tends to first order
+    # space: the semi-discrete solution -> cell-averaged Gaussian at second order
+    errs = []
+    for n in (24, 48, 96):
+        p = mesh_prm(n, n, n, L=(L, L, L), b=b)
+        h = L / n
+        centre = (np.array([n // 2, n // 2, n // 2]) + 0.5) * h
+        s = np.zeros(n ** 3)
+        s[((n // 2) * n + n // 2) * n + n // 2] = 1.0
+        sol = spectral_solve(p, s, exact_time=True)
+        g = gaussian_cells(p, centre, h ** 3).ravel()  # unit value in one cell
+        errs.append(np.max(np.abs(sol - g)) / g.max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.8 < r2 < 4.4 and r2 < r1 < 5.0  # tends to second order
+    # and the oracle itself on the 48^3 mesh, Richardson-extrapolated in
+    # pseudo-time from 16 and 32 steps, is within the mesh error (3.3%) of the
+    # kernel (a wrong tau = b^2/2 would be off by ~60%)
+    n = 48
+    s = np.zeros(n ** 3)
+    s[((n // 2) * n + n // 2) * n + n // 2] = 1.0
+    o16, _ = orc.diffuse(mesh_prm(n, n, n, L=(L, L, L), b=b, ntau=16), s[None])
+    o32, _ = orc.diffuse(mesh_prm(n, n, n, L=(L, L, L), b=b, ntau=32), s[None])
+    p = mesh_prm(n, n, n, L=(L, L, L), b=b)
+    g = gaussian_cells(p, (np.array([n // 2] * 3) + 0.5) * (L / n), (L / n) ** 3).ravel()
+    ext = 2 * o32[0] - o16[0]
+    assert np.max(np.abs(ext - g)) < 0.04 * g.max()
+
+
+def test_diffusion_apply_matches_stencil_definition(orc):
+    """orc_apply_A on a separable cosine mode returns (1 + dtau lambda) times it."""
+    prm = mesh_prm(8, 6, 5)
+    nx, ny, nz = 8, 6, 5
+    hx, hy, hz = prm["Lx"] / nx, prm["Ly"] / ny, prm["Lz"] / nz
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    mode = (np.cos(2 * np.pi * 3 * i / nx) * np.cos(2 * np.pi * 1 * j / ny) *
+            np.cos(np.pi * 2 * (k + 0.5) / nz)).ravel()
+    lam = ((2 - 2 * math.cos(2 * math.pi * 3 / nx)) / hx ** 2 +
+           (2 - 2 * math.cos(2 * math.pi / ny)) / hy ** 2 +
+           (2 - 2 * math.cos(math.pi * 2 / nz)) / hz ** 2)
+    dtau = 1e-7
+    y = orc.apply_A(prm, dtau, mode)
+    assert np.max(np.abs(y - (1 + dtau * lam) * mode)) < 1e-13

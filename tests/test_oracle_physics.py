@@ -1,0 +1,305 @@
+"""Pins of the oracle's particle step against closed-form physics (CPU only).
+
+Each test isolates one model of Sections 2.1, 2.3 and 2.5 and checks the
+oracle's time stepping against a result fixed by mechanics, not by the code:
+  - restitution coefficient and contact duration of a linear spring-dashpot
+    (two spheres head on, and a sphere on a wall);
+  - a sliding sphere reaches rolling at v = 5/7 v0 after t = 2 v0/(7 mu g);
+  - the lubrication squeeze force stops a sphere at h0 exp(-m v0/(6 pi mu r^2));
+  - Stokes settling with buoyancy and added mass: v_t = (rho_p - rho_f) g d^2/(18 mu)
+    reached with time constant (rho_p + C_add rho_f) d^2/(18 mu);
+  - Di Felice drag tends to Stokes drag (within its 4% low-Re offset);
+  - an elastic, frictionless gas conserves energy and momentum.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+D = workloads.D50
+RHO = workloads.RHO_P
+
+
+def dry(**kw):
+    """No fluid, no gravity, no walls, no friction unless asked."""
+    p = workloads.base_params(nx=1, ny=1, nz=1, drag_law="none", lubrication=0,
+                              fluid_forces=0, bottom_wall=0, top_wall=0, gz=0.0,
+                              friction=0.0)
+    p.update(kw)
+    return p
+
+
+def mass(d=D, rho=RHO):
+    return rho * math.pi / 6 * d ** 3
+
+
+def analytic_e_tc(kn, e, meff):
+    le = math.log(e)
+    zeta = -le / math.sqrt(math.pi ** 2 + le ** 2)
+    gam = 2 * zeta * math.sqrt(meff * kn)
+    wd = math.sqrt(kn / meff - (gam / (2 * meff)) ** 2)
+    return math.exp(-math.pi * zeta / math.sqrt(1 - zeta ** 2)), math.pi / wd
+
+
+def head_on(orc, dt_frac, e=0.9):
+    m = mass()
+    _, tc = analytic_e_tc(1e3, e, m / 2)
+    prm = dry(restitution=e, dt=tc * dt_frac)
+    v0 = 0.05
+    gap = 1e-6
+    xc = 0.5 * prm["Lx"]
+    x = np.array([[xc - 0.5 * D - gap, 1e-3, 2e-3], [xc + 0.5 * D + gap, 1e-3, 2e-3]])
+    v = np.array([[v0, 0, 0], [-v0, 0, 0]])
+    st = orc.State(prm, x, v, np.zeros((2, 3)), np.full(2, D), np.full(2, RHO))
+    st.init_accel()
+    steps_in = 0
+    t_total = 0
+    while True:
+        st.run(1)
+        t_total += 1
+        dist = st.x[1, 0] - st.x[0, 0]
+        if dist < D:
+            steps_in += 1
+        elif steps_in > 0:
+            break
+        assert t_total < 10 * tc / prm["dt"] + 1000
+    vrel_after = st.v[1, 0] - st.v[0, 0]
+    return vrel_after / (2 * v0), steps_in * prm["dt"]
+
+
+def test_head_on_restitution_and_contact_time(orc):
+    e_an, tc_an = analytic_e_tc(1e3, 0.9, mass() / 2)
+    assert abs(tc_an - 2.927e-5) < 0.01e-5  # value quoted for d = 0.5 mm, k = 1e3 N/m
+    errs = []
+    for frac in (1 / 200, 1 / 400, 1 / 800):
+        e_sim, tc_sim = head_on(orc, frac)
+        errs.append(abs(e_sim - e_an))
+        assert abs(tc_sim - tc_an) <= 2 * frac * tc_an
+    assert errs[-1] < 2e-3
+    # convergence in dt
+    assert errs[1] < 0.75 * errs[0] and errs[2] < 0.75 * errs[1]
+
+
+@pytest.mark.parametrize("e", [0.5, 0.97])
+def test_head_on_other_restitution(orc, e):
+    e_an, _ = analytic_e_tc(1e3, e, mass() / 2)
+    e_sim, _ = head_on(orc, 1 / 1000, e=e)
+    assert abs(e_sim - e_an) < 3e-3
+
+
+def test_wall_bounce_restitution(orc):
+    m = mass()
+    e_an, tc_an = analytic_e_tc(1e3, 0.9, m)
+    assert abs(tc_an - 4.140e-5) < 0.01e-5
+    prm = dry(bottom_wall=1, dt=tc_an / 1000)
+    v0 = 0.03
+    x = np.array([[1e-3, 1e-3, 0.5 * D + 1e-7]])
+    st = orc.State(prm, x, np.array([[0, 0, -v0]]), np.zeros((1, 3)), np.full(1, D),
+                   np.full(1, RHO))
+    st.init_accel()
+    touched = False
+    for _ in range(20000):
+        st.run(1)
+        if st.x[0, 2] < 0.5 * D:
+            touched = True
+        elif touched:
+            break
+    assert touched
+    assert abs(st.v[0, 2] / v0 - e_an) < 3e-3
+
+
+def test_sliding_to_rolling(orc):
+    """Coulomb friction + rotation: a sphere launched sliding on a wall
+    decelerates at mu g and rolls at 5/7 v0 from t* = 2 v0 / (7 mu g)."""
+    mu, g, v0 = 0.3, 9.81, 0.1
+    m = mass()
+    prm = dry(bottom_wall=1, friction=mu, gz=-g, dt=1e-6)
+    z0 = 0.5 * D - m * g / prm["kn"]  # static overlap
+    st = orc.State(prm, np.array([[1e-3, 1e-3, z0]]), np.array([[v0, 0, 0]]),
+                   np.zeros((1, 3)), np.full(1, D), np.full(1, RHO))
+    st.init_accel()
+    t_star = 2 * v0 / (7 * mu * g)
+    n_half = int(0.5 * t_star / prm["dt"])
+    st.run(n_half)
+    v_half = st.v[0, 0]
+    assert abs(v_half - (v0 - mu * g * n_half * prm["dt"])) < 2e-3 * v0
+    st.run(int(1.5 * t_star / prm["dt"]) - n_half)
+    vs, ws = [], []
+    for _ in range(200):
+        st.run(5)
+        vs.append(st.v[0, 0])
+        ws.append(st.w[0, 1])
+    v_end, w_end = np.mean(vs), np.mean(ws)
+    assert abs(v_end - 5 / 7 * v0) < 1e-3 * v0
+    # rolling without slip: v = w r, with w about +y for motion along +x
+    assert abs(w_end * 0.5 * D - v_end) < 2e-3 * v0
+
+
+def test_lubrication_stop_distance(orc):
+    """Squeeze-film approach to a wall: m dv/dt = -6 pi mu r^2 v / h
+    integrates to h_f = h0 exp(-m v0 / (6 pi mu r^2))."""
+    m = mass()
+    r = 0.5 * D
+    mu = workloads.MU_F
+    v0 = 0.01
+    prm = dry(bottom_wall=1, lubrication=1, dt=5e-7)
+    h0 = prm["lub_out_frac"] * D * (1 - 1e-9)
+    hf = h0 * math.exp(-m * v0 / (6 * math.pi * mu * r * r))
+    assert abs(hf / h0 - 0.229) < 0.002  # value quoted for d = 0.5 mm, v0 = 1 cm/s
+    assert hf > prm["lub_in_frac"] * D
+    st = orc.State(prm, np.array([[1e-3, 1e-3, r + h0]]), np.array([[0, 0, -v0]]),
+                   np.zeros((1, 3)), np.full(1, D), np.full(1, RHO))
+    st.init_accel()
+    st.run(80000)  # ~50 time constants of the final exponential approach
+    h = st.x[0, 2] - r
+    assert abs(st.v[0, 2]) < 1e-4 * v0
+    assert abs(h - hf) < 2e-3 * h0
+
+
+def stokes_setup(orc, c_add, dt):
+    d = 50e-6
+    g = 9.81
+    prm = workloads.base_params(nx=1, ny=1, nz=1, drag_law="stokes", lubrication=0,
+                                fluid_forces=1, bottom_wall=0, top_wall=0, c_add=c_add,
+                                dt=dt, Lz=0.1)
+    gradp = np.array([[0.0, 0.0, prm["rho_f"] * -g]])  # hydrostatic
+    st = orc.State(prm, np.array([[1e-3, 1e-3, 0.09]]), np.zeros((1, 3)), np.zeros((1, 3)),
+                   np.full(1, d), np.full(1, RHO), U=np.zeros((1, 3)), gradp=gradp,
+                   dudt=np.zeros((1, 3)))
+    st.init_accel()
+    return st, d, g
+
+
+def test_stokes_terminal_velocity_and_time_constant(orc):
+    mu = workloads.MU_F
+    rf = workloads.RHO_F
+    vt = (RHO - rf) * 9.81 * (50e-6) ** 2 / (18 * mu)
+    assert abs(vt - 2.248e-3) < 0.001e-3
+    tau = (RHO + 0.5 * rf) * (50e-6) ** 2 / (18 * mu)
+    errs = []
+    for dt in (tau / 100, tau / 200):
+        st, d, g = stokes_setup(orc, 0.5, dt)
+        n1 = int(round(tau / dt))
+        st.run(n1)
+        v_tau = -st.v[0, 2]
+        errs.append(abs(v_tau - vt * (1 - math.exp(-1))))
+        st.run(20 * n1)
+        assert abs(-st.v[0, 2] - vt) < 1e-9
+    assert errs[-1] < 0.01 * vt
+    assert errs[1] < 0.7 * errs[0]  # the lagged added mass converges with dt
+
+
+def test_added_mass_slows_the_approach(orc):
+    """Added mass raises the inertia (Section 4.1): the velocity after one
+    Stokes time of the bare particle is lower with C_add = 0.5."""
+    tau0 = RHO * (50e-6) ** 2 / (18 * workloads.MU_F)
+    v = []
+    for c in (0.0, 0.5):
+        st, _, _ = stokes_setup(orc, c, tau0 / 200)
+        st.run(200)
+        v.append(-st.v[0, 2])
+    vt = (RHO - workloads.RHO_F) * 9.81 * (50e-6) ** 2 / (18 * workloads.MU_F)
+    assert abs(v[0] - vt * (1 - math.exp(-1))) < 0.01 * vt
+    assert v[1] < v[0]
+
+
+def test_difelice_tends_to_stokes_at_low_re(orc):
+    """C_d = (0.63 + 4.8/sqrt(Re))^2 -> 23.04/Re as Re -> 0, i.e. 0.96 x Stokes."""
+    prm = workloads.base_params(nx=1, ny=1, nz=1, drag_law="difelice", lubrication=0,
+                                fluid_forces=0, bottom_wall=0, top_wall=0)
+    d = 10e-6
+    U = np.array([[1e-6, 0.0, 0.0]])  # Re = 1e-5
+    x = np.array([[1e-3, 1e-3, 1e-3]])
+    comps, _ = orc.forces(prm, x, np.zeros((1, 3)), np.zeros((1, 3)), np.full(1, d),
+                          np.full(1, RHO), U=U)
+    stokes = 3 * math.pi * workloads.MU_F * d * 1e-6
+    ratio = comps["drag"][0, 0] / stokes
+    assert abs(ratio - 0.96) < 0.005
+    # drag points towards the fluid velocity (force on the particle)
+    assert comps["drag"][0, 0] > 0
+
+
+def test_difelice_terminal_velocity_matches_scalar_balance(orc):
+    """d = 0.5 mm sand settling in still water: the stepped terminal velocity
+    equals the root of (rho_p - rho_f) V g = f_drag(v) at eps_f = 1."""
+    from scipy.optimize import brentq
+    d = D
+    rf, mu = workloads.RHO_F, workloads.MU_F
+    V = math.pi / 6 * d ** 3
+
+    def fd(v):
+        Re = rf * d * v / mu
+        cd = (0.63 + 4.8 / math.sqrt(Re)) ** 2
+        return 0.5 * cd * rf * math.pi * d * d / 4 * v * v
+
+    vt = brentq(lambda v: fd(v) - (RHO - rf) * V * 9.81, 1e-4, 1.0)
+    assert 0.05 < vt < 0.09  # the usual 6-8 cm/s for medium sand
+    prm = workloads.base_params(nx=1, ny=1, nz=1, drag_law="difelice", lubrication=0,
+                                fluid_forces=1, bottom_wall=0, top_wall=0, dt=2e-5, Lz=1.0)
+    st = orc.State(prm, np.array([[1e-3, 1e-3, 0.99]]), np.zeros((1, 3)), np.zeros((1, 3)),
+                   np.full(1, d), np.full(1, RHO), U=np.zeros((1, 3)),
+                   gradp=np.array([[0, 0, -rf * 9.81]]), dudt=np.zeros((1, 3)))
+    st.init_accel()
+    st.run(10000)
+    assert abs(-st.v[0, 2] - vt) < 1e-6 * vt
+
+
+def test_elastic_gas_conserves_energy_and_momentum(orc):
+    n = 150
+    prm = dry(restitution=1.0, bottom_wall=1, top_wall=1)
+    m = mass()
+    _, tc = analytic_e_tc(1e3, 0.999999, m / 2)
+    prm["dt"] = tc / 100
+    d = np.full(n, D)
+    x = workloads.rsa(n, d, prm["Lx"], prm["Ly"], prm["Lz"], seed=5)
+    rng = np.random.default_rng(5)
+    v = rng.normal(scale=0.05, size=(n, 3))
+    st = orc.State(prm, x, v, np.zeros((n, 3)), d, np.full(n, RHO))
+    st.init_accel()
+
+    def energy():
+        ke = 0.5 * m * (st.v ** 2).sum()
+        pe = 0.0
+        pr = orc.pairs_brute(dict(prm, lub_out_frac=0.0), st.x, d)
+        for i, j in pr:
+            dx = st.x[j] - st.x[i]
+            dx[0] -= prm["Lx"] * round(dx[0] / prm["Lx"])
+            dx[1] -= prm["Ly"] * round(dx[1] / prm["Ly"])
+            pe += 0.5 * prm["kn"] * (D - np.linalg.norm(dx)) ** 2
+        for z in st.x[:, 2]:
+            for dl in (0.5 * D - z, 0.5 * D - (prm["Lz"] - z)):
+                if dl > 0:
+                    pe += 0.5 * prm["kn"] * dl ** 2
+        return ke + pe
+
+    # energy is measured at synchronized velocities (after a full step)
+    e0 = energy()
+    p0 = m * st.v[:, :2].sum(axis=0)
+    es = []
+    for _ in range(10):
+        st.run(300)
+        es.append(energy())
+    drift = max(abs(e - e0) for e in es) / e0
+    assert drift < 2e-3
+    p1 = m * st.v[:, :2].sum(axis=0)
+    assert np.all(np.abs(p1 - p0) < 1e-12 * m * 0.05 * n)
+    assert st.nhist.value >= 0
+
+
+def test_pair_forces_are_antisymmetric(orc):
+    """Contact + lubrication forces on a periodic, wall-free bed sum to zero."""
+    w = workloads.workload("small")
+    prm = dict(w["params"], bottom_wall=0, top_wall=0, drag_law="none", fluid_forces=0)
+    x = w["x"].copy()
+    # squeeze the spheres together to create contacts and lubrication pairs
+    x[:, 2] *= 0.6
+    rng = np.random.default_rng(1)
+    v = rng.normal(scale=0.01, size=x.shape)
+    wv = rng.normal(scale=10.0, size=x.shape)
+    comps, hist = orc.forces(prm, x, v, wv, w["d"], w["rho"])
+    s = comps["contact"].sum(axis=0) + comps["lub"].sum(axis=0)
+    scale = np.abs(comps["contact"]).sum() + np.abs(comps["lub"]).sum()
+    assert scale > 0
+    assert np.all(np.abs(s) < 1e-13 * scale)
