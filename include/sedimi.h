@@ -1,0 +1,184 @@
+/*
+ * sedimi.h -- C ABI of the MI355X (gfx950) CFD-DEM particle step and
+ * particle-to-mesh diffusion averaging of SediFoam (Sun & Xiao).
+ *
+ * The calls follow the paper's statement of the problem: particles with
+ * diameter, density, position, velocity and angular velocity evolve under
+ * Newton's equations (Eq. 1a-1b) with contact, lubrication and fluid-particle
+ * forces (Sections 2.1, 2.3, 2.5); the fluid is given on an Eulerian mesh
+ * (Section 2.2; frozen here: velocity, pressure gradient and material
+ * derivative per cell); the particles' volume and drag are averaged back onto
+ * the mesh by deposition (Eq. 11) and implicit diffusion (Eq. 12).
+ *
+ * Conventions (SI units throughout):
+ *   - axes: x streamwise and y spanwise, both periodic on [0, L); z
+ *     wall-normal, with optional flat walls at z = 0 and z = Lz;
+ *   - host particle arrays are in particle-ID order (ID = row index at
+ *     sedimi_set_particles), vectors [n][3] row-major, scalars [n];
+ *   - mesh cell (i, j, k) has index (k*ny + j)*nx + i; vector fields are
+ *     [ncell][3], averaged fields are [4][ncell] (channel 0 = solid volume
+ *     fraction, channels 1..3 = drag force density on the particles);
+ *   - host arrays passed in are copied, never retained; host arrays passed
+ *     out are filled before the call returns (those calls synchronise the
+ *     bound stream);
+ *   - all device memory lives in one caller-provided workspace (see
+ *     sedimi_workspace_bytes / sedimi_bind_workspace); the library never
+ *     allocates device memory itself;
+ *   - device work is enqueued on the bound HIP stream (default: the null
+ *     stream); a context is not thread-safe;
+ *   - every call returns SEDIMI_OK (0) or a negative SEDIMI_E* code and never
+ *     aborts; sedimi_last_error() gives a message for the last failure.
+ */
+#ifndef SEDIMI_H
+#define SEDIMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define SEDIMI_OK 0
+#define SEDIMI_EINVAL (-1)    /* bad argument or parameter */
+#define SEDIMI_ENOMEM (-2)    /* workspace missing or too small, or host allocation failed */
+#define SEDIMI_EDEVICE (-3)   /* a HIP runtime call failed */
+#define SEDIMI_EOVERFLOW (-4) /* neighbour slots exceeded or a contact fell out of the list */
+#define SEDIMI_EUNSTABLE (-5) /* non-finite state */
+#define SEDIMI_EESCAPE (-6)   /* a particle left [0, Lz] through a wall plane */
+#define SEDIMI_ENOCONV (-7)   /* diffusion solve above its residual tolerance */
+#define SEDIMI_ESTATE (-8)    /* call out of order (e.g. no particles yet) */
+
+/* drag laws (Section 2.3) */
+#define SEDIMI_DRAG_NONE 0
+#define SEDIMI_DRAG_DIFELICE 1
+#define SEDIMI_DRAG_STOKES 2
+
+/* arithmetic of the force evaluation */
+#define SEDIMI_FP64 0  /* everything in FP64 */
+#define SEDIMI_MIXED 1 /* FP64 state, geometry and integration; FP32 force arithmetic,
+                          FP32 tangential history; FP32 diffusion vectors with FP64
+                          residual reduction */
+
+/* force components for sedimi_get_forces */
+#define SEDIMI_F_CONTACT 0  /* spring-dashpot + friction, particle and wall contacts */
+#define SEDIMI_F_LUB 1      /* lubrication */
+#define SEDIMI_F_DRAG 2     /* drag */
+#define SEDIMI_F_PRESSURE 3 /* -V_p grad p */
+#define SEDIMI_F_ADDED 4    /* added mass */
+#define SEDIMI_F_TOTAL 5    /* sum of the above + m g */
+#define SEDIMI_F_TORQUE 6   /* contact torque */
+
+/* mesh fields for sedimi_get_field / sedimi_set_field, each [4][ncell] */
+#define SEDIMI_FIELD_RAW 0    /* deposited, before smoothing (Eq. 11) */
+#define SEDIMI_FIELD_SMOOTH 1 /* after the diffusion solve (Eq. 12); channel 0
+                                 is the solid fraction the drag reads */
+
+typedef struct sedimi_ctx sedimi_ctx;
+
+typedef struct {
+  double Lx, Ly, Lz;         /* domain (m) */
+  int nx, ny, nz;            /* mesh cells per axis (uniform spacing) */
+  double kn;                 /* normal contact stiffness (N/m) */
+  double restitution;        /* normal restitution e, 0 < e <= 1 */
+  double friction;           /* Coulomb coefficient */
+  double kt_over_kn;         /* tangential stiffness ratio */
+  double gammat_over_gamman; /* tangential damping ratio */
+  double lub_out_frac;       /* lubrication cut-off gap / mean diameter */
+  double lub_in_frac;        /* lubrication gap floor / mean diameter */
+  double rho_f, mu_f;        /* fluid density (kg/m^3), dynamic viscosity (Pa s) */
+  double c_add;              /* added-mass coefficient */
+  double gx, gy, gz;         /* gravity (m/s^2) */
+  double dt;                 /* time step (s) */
+  int drag_law;              /* SEDIMI_DRAG_* */
+  int lubrication;           /* 0/1 */
+  int fluid_forces;          /* 0/1: pressure gradient and added mass */
+  int bottom_wall, top_wall; /* 0/1 */
+  double eps_s_max;          /* clamp of the interpolated solid fraction in the drag */
+  double avg_bandwidth;      /* averaging bandwidth b (m); pseudo-time b^2/4 */
+  int avg_ntau;              /* implicit pseudo-time steps */
+  double avg_rtol;           /* relative residual tolerance of each implicit step */
+  int precision;             /* SEDIMI_FP64 or SEDIMI_MIXED */
+  double d_max;              /* largest particle diameter the context will hold (m);
+                                sets the neighbour-bin size */
+  double skin;               /* neighbour-list skin (m); the list is rebuilt when any
+                                particle has moved skin/2 since the last build */
+  int max_neighbors;         /* neighbour slots per particle, 1..30 */
+} sedimi_params;
+
+typedef struct {
+  int64_t steps;          /* steps taken since sedimi_set_particles */
+  int64_t rebuilds;       /* neighbour-list rebuilds (re-sorts) */
+  int32_t max_neighbors;  /* largest neighbour count seen at a rebuild */
+  int32_t flags;          /* bit 0 slot overflow, 1 lost contact, 2 escape, 3 non-finite */
+  int64_t solve_iters;    /* iterations of the last diffusion solve (all steps) */
+  double solve_residual;  /* largest final relative residual of the last solve */
+} sedimi_stats;
+
+/* Create a context for up to max_particles particles.  Checks the parameters
+ * (EINVAL with a message on failure).  No device memory is touched yet. */
+int sedimi_create(const sedimi_params* p, int64_t max_particles, sedimi_ctx** out);
+void sedimi_destroy(sedimi_ctx* ctx);
+const char* sedimi_last_error(const sedimi_ctx* ctx);
+
+/* Device bytes the context needs; bind a device allocation of at least that
+ * size (256-byte aligned), owned and kept alive by the caller. */
+size_t sedimi_workspace_bytes(const sedimi_ctx* ctx);
+int sedimi_bind_workspace(sedimi_ctx* ctx, void* dev_ptr, size_t bytes);
+/* Bind the HIP stream (hipStream_t passed as void*) all device work goes to. */
+int sedimi_set_stream(sedimi_ctx* ctx, void* hip_stream);
+
+/* Upload particles (host, ID order) and build the neighbour list.  Angular
+ * velocity may be NULL (zero).  Resets accelerations, history and counters. */
+int sedimi_set_particles(sedimi_ctx* ctx, int64_t n, const double* x, const double* v,
+                         const double* omega, const double* diam, const double* rho_p);
+/* Upload the frozen fluid fields (host, [ncell][3] each; NULL = zero). */
+int sedimi_set_fluid(sedimi_ctx* ctx, const double* U, const double* gradp,
+                     const double* dudt);
+/* Overwrite a mesh field (host [4][ncell]). */
+int sedimi_set_field(sedimi_ctx* ctx, int field, const double* in);
+/* Overwrite the stored accelerations a^n (host [n][3], ID order; used by the
+ * added-mass lag and the next half kick). */
+int sedimi_set_accel(sedimi_ctx* ctx, const double* a, const double* alpha);
+
+/* One force evaluation at the current state (no time integration): stores
+ * the per-component breakdown for sedimi_get_forces and the accelerations
+ * a = F/m + g, alpha = T/I (the previous a is the added-mass lag).  The
+ * tangential history advances only if update_history != 0. */
+int sedimi_compute_forces(sedimi_ctx* ctx, int update_history);
+/* nsteps velocity-Verlet steps (half kick, drift, forces at the half-step
+ * velocities, half kick).  If average_every > 0, the averaging runs after
+ * every step whose global index is a multiple of average_every, and its
+ * solid fraction feeds the drag of the following steps. */
+int sedimi_step(sedimi_ctx* ctx, int nsteps, int average_every);
+/* Deposition (Eq. 11) into the RAW field, then the diffusion solve (Eq. 12)
+ * into the SMOOTH field.  Both use the particles' current positions and the
+ * drag of the last force evaluation. */
+int sedimi_average(sedimi_ctx* ctx);
+/* Deposition only (RAW field). */
+int sedimi_deposit(sedimi_ctx* ctx);
+/* Diffusion solve only: SMOOTH <- smoothed RAW, for channels [0, nch). */
+int sedimi_smooth(sedimi_ctx* ctx, int nch);
+
+/* Read back, in ID order.  Any output pointer may be NULL. */
+int sedimi_get_particles(sedimi_ctx* ctx, double* x, double* v, double* omega, double* a);
+int sedimi_get_forces(sedimi_ctx* ctx, int component, double* f);
+int sedimi_get_field(sedimi_ctx* ctx, int field, double* out);
+/* Current contact-pair set (centre distance below contact distance plus the
+ * lubrication cut-off), as (i, j) ID pairs with i < j in ascending order.
+ * *n_out receives the count; returns EOVERFLOW if it exceeds cap. */
+int sedimi_get_pairs(sedimi_ctx* ctx, int64_t cap, int64_t* ij, int64_t* n_out);
+/* Tangential contact history as records {int64 i, int64 j, double xi[3]}:
+ * i < j particle IDs, or j = -1 (wall z = 0) / -2 (wall z = Lz); xi is the
+ * spring displacement of i relative to j.  get: sorted by (i, j); set:
+ * replaces the whole history (any order; pairs must be in the current
+ * neighbour list). */
+int sedimi_get_history(sedimi_ctx* ctx, int64_t cap, void* records, int64_t* n_out);
+int sedimi_set_history(sedimi_ctx* ctx, int64_t n, const void* records);
+int sedimi_get_stats(sedimi_ctx* ctx, sedimi_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SEDIMI_H */

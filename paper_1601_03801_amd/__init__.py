@@ -1,0 +1,273 @@
+"""MI355X-native SediFoam particle step and diffusion averaging (libsedimi).
+
+A thin ctypes binding over the C ABI declared in ``include/sedimi.h``: every
+function here marshals arguments and calls the library of the same name; all
+computation runs in the HIP kernels of ``libsedimi.so``.  PyTorch provides the
+device workspace (one uint8 tensor) and the stream.  Importing works without
+a GPU; creating a :class:`Sedimi` requires the built library and a GPU and
+raises otherwise (there is no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsedimi.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, EUNSTABLE, EESCAPE, ENOCONV, ESTATE = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
+DRAG = {"none": 0, "difelice": 1, "stokes": 2}
+FP64, MIXED = 0, 1
+FORCE = {"contact": 0, "lub": 1, "drag": 2, "pressure": 3, "added": 4, "total": 5,
+         "torque": 6}
+FIELD_RAW, FIELD_SMOOTH = 0, 1
+
+HISTORY_DTYPE = np.dtype([("i", np.int64), ("j", np.int64), ("xi", np.float64, (3,))])
+
+
+class SedimiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"sedimi error {code}: {msg}")
+        self.code = code
+
+
+class sedimi_params(C.Structure):
+    _fields_ = [
+        ("Lx", C.c_double), ("Ly", C.c_double), ("Lz", C.c_double),
+        ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+        ("kn", C.c_double), ("restitution", C.c_double), ("friction", C.c_double),
+        ("kt_over_kn", C.c_double), ("gammat_over_gamman", C.c_double),
+        ("lub_out_frac", C.c_double), ("lub_in_frac", C.c_double),
+        ("rho_f", C.c_double), ("mu_f", C.c_double), ("c_add", C.c_double),
+        ("gx", C.c_double), ("gy", C.c_double), ("gz", C.c_double), ("dt", C.c_double),
+        ("drag_law", C.c_int), ("lubrication", C.c_int), ("fluid_forces", C.c_int),
+        ("bottom_wall", C.c_int), ("top_wall", C.c_int),
+        ("eps_s_max", C.c_double),
+        ("avg_bandwidth", C.c_double), ("avg_ntau", C.c_int), ("avg_rtol", C.c_double),
+        ("precision", C.c_int),
+        ("d_max", C.c_double), ("skin", C.c_double), ("max_neighbors", C.c_int),
+    ]
+
+
+class sedimi_stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("rebuilds", C.c_int64), ("max_neighbors", C.c_int32),
+                ("flags", C.c_int32), ("solve_iters", C.c_int64),
+                ("solve_residual", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsedimi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "paper_1601_03801_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        P, i64, I = C.c_void_p, C.c_int64, C.c_int
+        ctxp = C.POINTER(C.c_void_p)
+        L.sedimi_create.argtypes = [C.POINTER(sedimi_params), i64, ctxp]
+        L.sedimi_destroy.argtypes = [P]
+        L.sedimi_destroy.restype = None
+        L.sedimi_last_error.argtypes = [P]
+        L.sedimi_last_error.restype = C.c_char_p
+        L.sedimi_workspace_bytes.argtypes = [P]
+        L.sedimi_workspace_bytes.restype = C.c_size_t
+        L.sedimi_bind_workspace.argtypes = [P, P, C.c_size_t]
+        L.sedimi_set_stream.argtypes = [P, P]
+        L.sedimi_set_particles.argtypes = [P, i64, P, P, P, P, P]
+        L.sedimi_set_fluid.argtypes = [P, P, P, P]
+        L.sedimi_set_field.argtypes = [P, I, P]
+        L.sedimi_set_accel.argtypes = [P, P, P]
+        L.sedimi_compute_forces.argtypes = [P, I]
+        L.sedimi_step.argtypes = [P, I, I]
+        L.sedimi_average.argtypes = [P]
+        L.sedimi_deposit.argtypes = [P]
+        L.sedimi_smooth.argtypes = [P, I]
+        L.sedimi_get_particles.argtypes = [P, P, P, P, P]
+        L.sedimi_get_forces.argtypes = [P, I, P]
+        L.sedimi_get_field.argtypes = [P, I, P]
+        L.sedimi_get_pairs.argtypes = [P, i64, P, C.POINTER(i64)]
+        L.sedimi_get_history.argtypes = [P, i64, P, C.POINTER(i64)]
+        L.sedimi_set_history.argtypes = [P, i64, P]
+        L.sedimi_get_stats.argtypes = [P, C.POINTER(sedimi_stats)]
+        _lib = L
+    return _lib
+
+
+def make_params(prm: dict, precision="fp64", skin=None, max_neighbors=24, d_max=None,
+                avg_rtol=1e-12) -> sedimi_params:
+    """sedimi_params from a parameter dict (the oracle's keys plus options)."""
+    p = sedimi_params()
+    for name, _ in sedimi_params._fields_:
+        if name in prm:
+            val = prm[name]
+            if name == "drag_law" and isinstance(val, str):
+                val = DRAG[val]
+            setattr(p, name, val)
+    p.avg_rtol = prm.get("avg_rtol", avg_rtol)
+    p.precision = {"fp64": FP64, "mixed": MIXED}[prm.get("precision", precision)]
+    dm = prm.get("d_max", d_max)
+    if dm is None:
+        raise ValueError("d_max (largest particle diameter) is required")
+    p.d_max = dm
+    p.skin = prm.get("skin", 0.1 * dm if skin is None else skin)
+    p.max_neighbors = prm.get("max_neighbors", max_neighbors)
+    return p
+
+
+def _f64(a, shape=None):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a if shape is None else a.reshape(shape)
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class Sedimi:
+    """One sedimi context with its device workspace on the current GPU."""
+
+    def __init__(self, prm: dict, max_particles: int, stream=None, **opts):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("Sedimi needs a GPU (no CPU fallback)")
+        self._L = lib()
+        self.prm = dict(prm)
+        self.params = make_params(prm, **opts)
+        self._ctx = C.c_void_p()
+        rc = self._L.sedimi_create(C.byref(self.params), int(max_particles), C.byref(self._ctx))
+        if rc != OK:
+            raise SedimiError(rc, "sedimi_create rejected the parameters (see stderr)")
+        nbytes = self._L.sedimi_workspace_bytes(self._ctx)
+        self.workspace = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._chk(self._L.sedimi_set_stream(self._ctx, C.c_void_p(self.stream.cuda_stream)))
+        self._chk(self._L.sedimi_bind_workspace(self._ctx, C.c_void_p(aligned), nbytes))
+        self.ncell = prm["nx"] * prm["ny"] * prm["nz"]
+        self.n = 0
+
+    # -- plumbing --
+    def _chk(self, rc):
+        if rc != OK:
+            msg = self._L.sedimi_last_error(self._ctx).decode()
+            raise SedimiError(rc, msg)
+        return rc
+
+    def close(self):
+        if self._ctx:
+            self._L.sedimi_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def workspace_bytes(self):
+        return int(self._L.sedimi_workspace_bytes(self._ctx))
+
+    # -- calls of the C ABI --
+    def set_particles(self, x, v, d, rho, omega=None):
+        x = _f64(x, (-1, 3))
+        n = x.shape[0]
+        v, d, rho, w = _f64(v, (-1, 3)), _f64(d), _f64(rho), _f64(omega, (-1, 3))
+        self._chk(self._L.sedimi_set_particles(self._ctx, n, _ptr(x), _ptr(v), _ptr(w),
+                                               _ptr(d), _ptr(rho)))
+        self.n = n
+
+    def set_fluid(self, U=None, gradp=None, dudt=None):
+        U, gradp, dudt = (_f64(a, (-1, 3)) for a in (U, gradp, dudt))
+        self._chk(self._L.sedimi_set_fluid(self._ctx, _ptr(U), _ptr(gradp), _ptr(dudt)))
+
+    def set_field(self, which, arr):
+        arr = _f64(arr).reshape(4, self.ncell)
+        self._chk(self._L.sedimi_set_field(self._ctx, which, _ptr(arr)))
+
+    def set_accel(self, a=None, alpha=None):
+        a, alpha = _f64(a, (-1, 3)), _f64(alpha, (-1, 3))
+        self._chk(self._L.sedimi_set_accel(self._ctx, _ptr(a), _ptr(alpha)))
+
+    def compute_forces(self, update_history=False):
+        self._chk(self._L.sedimi_compute_forces(self._ctx, 1 if update_history else 0))
+
+    def step(self, nsteps, average_every=0):
+        self._chk(self._L.sedimi_step(self._ctx, int(nsteps), int(average_every)))
+
+    def average(self):
+        self._chk(self._L.sedimi_average(self._ctx))
+
+    def deposit(self):
+        self._chk(self._L.sedimi_deposit(self._ctx))
+
+    def smooth(self, nch=4):
+        self._chk(self._L.sedimi_smooth(self._ctx, int(nch)))
+
+    def get_particles(self):
+        out = [np.zeros((self.n, 3)) for _ in range(4)]
+        self._chk(self._L.sedimi_get_particles(self._ctx, *[_ptr(o) for o in out]))
+        return dict(zip(("x", "v", "omega", "a"), out))
+
+    def get_forces(self, component):
+        f = np.zeros((self.n, 3))
+        comp = FORCE[component] if isinstance(component, str) else component
+        self._chk(self._L.sedimi_get_forces(self._ctx, comp, _ptr(f)))
+        return f
+
+    def get_field(self, which):
+        out = np.zeros((4, self.ncell))
+        self._chk(self._L.sedimi_get_field(self._ctx, which, _ptr(out)))
+        return out
+
+    def get_pairs(self):
+        cnt = C.c_int64(0)
+        cap = 16 * max(self.n, 1)
+        while True:
+            buf = np.zeros((cap, 2), np.int64)
+            rc = self._L.sedimi_get_pairs(self._ctx, cap, _ptr(buf), C.byref(cnt))
+            if rc == EOVERFLOW and cnt.value > cap:
+                cap = cnt.value
+                continue
+            self._chk(rc)
+            return buf[:cnt.value].copy()
+
+    def get_history(self):
+        cnt = C.c_int64(0)
+        cap = 16 * max(self.n, 1)
+        while True:
+            buf = np.zeros(cap, HISTORY_DTYPE)
+            rc = self._L.sedimi_get_history(self._ctx, cap, _ptr(buf), C.byref(cnt))
+            if rc == EOVERFLOW and cnt.value > cap:
+                cap = cnt.value
+                continue
+            self._chk(rc)
+            return buf[:cnt.value].copy()
+
+    def set_history(self, records):
+        rec = np.ascontiguousarray(records, HISTORY_DTYPE)
+        self._chk(self._L.sedimi_set_history(self._ctx, len(rec), _ptr(rec) if len(rec) else None))
+
+    def stats(self):
+        s = sedimi_stats()
+        self._chk(self._L.sedimi_get_stats(self._ctx, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in sedimi_stats._fields_}
+
+
+def exported_symbols():
+    """Names of the C ABI entry points declared in include/sedimi.h."""
+    hdr = os.path.join(os.path.dirname(_HERE), "include", "sedimi.h")
+    import re
+    names = re.findall(r"^\s*(?:int|void|size_t|const char\*)\s+(sedimi_\w+)\s*\(",
+                       open(hdr).read(), re.M)
+    return sorted(set(names))

@@ -1,0 +1,277 @@
+// k_average.hip -- particle-to-mesh averaging (Section 2.4).
+//
+// Deposition (Eq. 11): particles are counting-sorted by mesh cell (integer
+// atomics for the counts only), each cell's members are ordered by particle
+// ID, and one lane per cell sums volume and drag in that order: a segmented
+// reduction with no floating-point atomics, bit-reproducible, and in the
+// same summation order as a plain loop over particle IDs.
+//
+// Diffusion (Eq. 12): avg_ntau backward-Euler pseudo-time steps of unit
+// diffusivity up to tau = b^2/4; each step solves (I - dtau L_h) x = b with
+// the second-order finite-volume Laplacian (periodic x, y; zero-flux walls).
+// The solver is Chebyshev iteration: the operator's spectrum lies in
+// [1, 1 + dtau * sum_a 4/h_a^2] on a uniform mesh, so the iteration needs no
+// inner products, every iteration is one fused stencil sweep, and the number
+// of iterations that guarantees the residual tolerance is known in advance.
+// The final residual of every pseudo-time step is then measured with an FP64
+// reduction (fixed-order block trees, summed on the host in fixed order).
+#include <math.h>
+
+#include <vector>
+
+#include "k_common.h"
+
+namespace sedimi {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__global__ void k_cellkey(DevParams P, DevArrays A) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.n) return;
+  double4 x = A.pos[q];
+  int a = (int)floor(x.x / P.hx), b = (int)floor(x.y / P.hy), c = (int)floor(x.z / P.hz);
+  a = a < 0 ? 0 : (a >= P.nx ? P.nx - 1 : a);
+  b = b < 0 ? 0 : (b >= P.ny ? P.ny - 1 : b);
+  c = c < 0 ? 0 : (c >= P.nz ? P.nz - 1 : c);
+  int k = (c * P.ny + b) * P.nx + a;
+  A.key[q] = k;
+  A.rank[q] = atomicAdd(&A.cell_count[k], 1);
+}
+
+__global__ void k_cellscatter(DevParams P, DevArrays A) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.n) return;
+  A.cperm[A.cell_start[A.key[q]] + A.rank[q]] = q;
+}
+
+// One lane per cell: order the members by particle ID, then sum.
+__global__ void k_cellsum(DevParams P, DevArrays A) {
+#pragma clang fp contract(off)
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+  int s = A.cell_start[c], e = A.cell_start[c + 1];
+  for (int i = s + 1; i < e; ++i) {
+    int q = A.cperm[i];
+    int key = A.id[q];
+    int j = i - 1;
+    while (j >= s && A.id[A.cperm[j]] > key) {
+      A.cperm[j + 1] = A.cperm[j];
+      --j;
+    }
+    A.cperm[j + 1] = q;
+  }
+  double v = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+  for (int i = s; i < e; ++i) {
+    int q = A.cperm[i];
+    double d = 2.0 * A.pos[q].w;
+    double V = (kPi / 6.0) * d * d * d;
+    v += V;
+    double4 f = A.fdr[q];
+    fx += f.x;
+    fy += f.y;
+    fz += f.z;
+  }
+  const size_t nc = (size_t)P.ncell;
+  A.raw[c] = v / P.Vc;
+  A.raw[nc + c] = fx / P.Vc;
+  A.raw[2 * nc + c] = fy / P.Vc;
+  A.raw[3 * nc + c] = fz / P.Vc;
+}
+
+struct Stencil {
+  int nx, ny, nz, ncell;
+  double cx, cy, cz;  // dtau / h^2 per axis
+};
+
+// y = (I - dtau L_h) x at cell c (channel offset already applied to x).
+template <typename T>
+__device__ __forceinline__ double apply_A(const Stencil& S, const T* __restrict__ x, int c) {
+  int i = c % S.nx;
+  int jk = c / S.nx;
+  int j = jk % S.ny;
+  int k = jk / S.ny;
+  double xc = (double)x[c];
+  int ip = i + 1 == S.nx ? c - i : c + 1;
+  int im = i == 0 ? c + S.nx - 1 : c - 1;
+  int rowy = S.nx;
+  int jp = j + 1 == S.ny ? c - j * rowy : c + rowy;
+  int jm = j == 0 ? c + (S.ny - 1) * rowy : c - rowy;
+  double lx = ((double)x[ip] - xc) + ((double)x[im] - xc);
+  double ly = ((double)x[jp] - xc) + ((double)x[jm] - xc);
+  double lz = 0.0;
+  int plane = S.nx * S.ny;
+  if (k + 1 < S.nz) lz += (double)x[c + plane] - xc;
+  if (k > 0) lz += (double)x[c - plane] - xc;
+  return xc - (S.cx * lx + S.cy * ly + S.cz * lz);
+}
+
+// Start of one pseudo-time step: b = src; x = b; r = b - A b; d = r / theta;
+// keep b for the residual check.
+// When src is x itself (pseudo-time steps after the first) x is left as is.
+template <typename T>
+__global__ void k_cheb_init(Stencil S, const T* src, T* x, T* __restrict__ r,
+                            T* __restrict__ d, T* __restrict__ bsave, double inv_theta,
+                            int copy_x) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= S.ncell) return;
+  size_t off = (size_t)blockIdx.y * S.ncell;
+  double b = (double)src[off + c];
+  double rr = b - apply_A<T>(S, src + off, c);
+  if (copy_x) x[off + c] = (T)b;
+  bsave[off + c] = (T)b;
+  r[off + c] = (T)rr;
+  d[off + c] = (T)(rr * inv_theta);
+}
+
+// One Chebyshev iteration: x += d; r -= A d; d' = c1 d + c2 r.
+template <typename T>
+__global__ void k_cheb_iter(Stencil S, const T* __restrict__ d, T* __restrict__ x,
+                            T* __restrict__ r, T* __restrict__ dn, double c1, double c2) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= S.ncell) return;
+  size_t off = (size_t)blockIdx.y * S.ncell;
+  double dc = (double)d[off + c];
+  double Ad = apply_A<T>(S, d + off, c);
+  double xn = (double)x[off + c] + dc;
+  double rn = (double)r[off + c] - Ad;
+  x[off + c] = (T)xn;
+  r[off + c] = (T)rn;
+  dn[off + c] = (T)(c1 * dc + c2 * rn);
+}
+
+// Per-block FP64 sums of (b - A x)^2 and b^2 for each channel.
+template <typename T>
+__global__ void k_residual(Stencil S, const T* __restrict__ b, const T* __restrict__ x,
+                           double* __restrict__ part) {
+  __shared__ double s1[kBlock], s2[kBlock];
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  size_t off = (size_t)blockIdx.y * S.ncell;
+  double rr = 0.0, bb = 0.0;
+  if (c < S.ncell) {
+    double bv = (double)b[off + c];
+    double r = bv - apply_A<T>(S, x + off, c);
+    rr = r * r;
+    bb = bv * bv;
+  }
+  s1[threadIdx.x] = rr;
+  s2[threadIdx.x] = bb;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+      s2[threadIdx.x] += s2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    size_t base = (size_t)blockIdx.y * gridDim.x * 2;
+    part[base + blockIdx.x] = s1[0];
+    part[base + gridDim.x + blockIdx.x] = s2[0];
+  }
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+void launch_deposit(const DevParams& P, DevArrays& A, hipStream_t s) {
+  launch_zero_ints(A.cell_count, P.ncell, false, A.ctl, s);
+  if (P.n > 0) {
+    hipLaunchKernelGGL(k_cellkey, dim3(nblk(P.n)), dim3(kBlock), 0, s, P, A);
+  }
+  launch_exclusive_scan(A.cell_count, A.cell_start, P.ncell, A.scan_tmp, false, A.ctl, s);
+  if (P.n > 0) {
+    hipLaunchKernelGGL(k_cellscatter, dim3(nblk(P.n)), dim3(kBlock), 0, s, P, A);
+  }
+  hipLaunchKernelGGL(k_cellsum, dim3(nblk(P.ncell)), dim3(kBlock), 0, s, P, A);
+}
+
+size_t smooth_red_doubles(int ncell, int nch, int ntau) {
+  return (size_t)((ncell + kBlock - 1) / kBlock) * 2 * nch * (ntau > 0 ? ntau : 1);
+}
+
+int64_t launch_smooth(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
+                      double rtol, bool mixed, hipStream_t s) {
+  (void)mixed;
+  Stencil S;
+  S.nx = P.nx, S.ny = P.ny, S.nz = P.nz, S.ncell = P.ncell;
+  if (ntau <= 0) {
+    (void)hipMemcpyAsync(A.smooth, A.raw, sizeof(double) * nch * P.ncell,
+                         hipMemcpyDeviceToDevice, s);
+    return 0;
+  }
+  double dtau = tau / ntau;
+  S.cx = dtau / (P.hx * P.hx);
+  S.cy = dtau / (P.hy * P.hy);
+  S.cz = dtau / (P.hz * P.hz);
+  // the spectrum of A = I - dtau L_h lies in [1, lmax]
+  double lmax = 1.0 + 4.0 * ((P.nx > 1 ? S.cx : 0.0) + (P.ny > 1 ? S.cy : 0.0) +
+                             (P.nz > 1 ? S.cz : 0.0));
+  double lmin = 1.0;
+  int kiter = 0;
+  if (lmax > lmin * (1.0 + 1e-12)) {
+    // Chebyshev residual bound: |r_k| / |b| <= (kappa - 1) * 2 rho^k
+    double kappa = lmax / lmin;
+    double rho = (sqrt(kappa) - 1.0) / (sqrt(kappa) + 1.0);
+    kiter = (int)ceil(log(rtol / (2.0 * (kappa - 1.0))) / log(rho)) + 1;
+    if (kiter < 1) kiter = 1;
+  }
+  double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  dim3 grid(nblk(P.ncell), nch);
+  const size_t nred = (size_t)grid.x * 2 * nch;
+  double* bsave = A.sx;
+  for (int m = 0; m < ntau; ++m) {
+    const double* src = m == 0 ? A.raw : A.smooth;
+    hipLaunchKernelGGL(k_cheb_init<double>, grid, dim3(kBlock), 0, s, S, src, A.smooth, A.sr,
+                       A.sd0, bsave, kiter > 0 ? 1.0 / theta : 1.0, m == 0 ? 1 : 0);
+    if (kiter > 0) {
+      double sigma1 = theta / delta;
+      double rho_k = 1.0 / sigma1;
+      double* dcur = A.sd0;
+      double* dnext = A.sd1;
+      for (int it = 0; it < kiter; ++it) {
+        double rho_n = 1.0 / (2.0 * sigma1 - rho_k);
+        double c1 = rho_n * rho_k, c2 = 2.0 * rho_n / delta;
+        hipLaunchKernelGGL(k_cheb_iter<double>, grid, dim3(kBlock), 0, s, S, dcur, A.smooth,
+                           A.sr, dnext, c1, c2);
+        rho_k = rho_n;
+        double* t = dcur;
+        dcur = dnext;
+        dnext = t;
+      }
+    }
+    hipLaunchKernelGGL(k_residual<double>, grid, dim3(kBlock), 0, s, S, bsave, A.smooth,
+                       A.red + (size_t)m * nred);
+  }
+  return (int64_t)kiter * ntau;
+}
+
+double read_smooth_residual(const DevParams& P, DevArrays& A, int nch, int ntau,
+                            hipStream_t s) {
+  if (ntau <= 0) return 0.0;
+  unsigned nb = nblk(P.ncell);
+  const size_t nred = (size_t)nb * 2 * nch;
+  std::vector<double> h((size_t)ntau * nred);
+  if (hipMemcpyAsync(h.data(), A.red, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return -1.0;
+  if (hipStreamSynchronize(s) != hipSuccess) return -1.0;
+  double worst = 0.0;
+  for (int m = 0; m < ntau; ++m) {
+    for (int ch = 0; ch < nch; ++ch) {
+      const double* p = h.data() + (size_t)m * nred + (size_t)ch * nb * 2;
+      double rr = 0.0, bb = 0.0;
+      for (unsigned b = 0; b < nb; ++b) {
+        rr += p[b];
+        bb += p[nb + b];
+      }
+      double rel = bb > 0.0 ? sqrt(rr / bb) : sqrt(rr);
+      if (rel > worst) worst = rel;
+    }
+  }
+  return worst;
+}
+
+}  // namespace sedimi

@@ -1,0 +1,345 @@
+// k_forces.hip -- fused force evaluation and second half kick.
+//
+// One lane per particle (bin-sorted order) walks its full neighbour list.
+// Every pair is evaluated on both of its sides with the operands put in
+// lower-ID -> higher-ID order first, so both sides compute bit-identical pair
+// forces and tangential histories: the pair forces are exactly antisymmetric
+// and no atomics are needed.  Per pair (Sections 2.1, 2.5):
+//   - pair set: s = |dx|^2 < ((r_i + r_j)(1 + f_out))^2, exact FP64 test;
+//   - lubrication (Ball & Melrose squeeze term) for every pair in the set:
+//     F = -6 pi mu a_eff^2 u_n / max(h, h_in) n;
+//   - contact when the overlap delta > 0: linear spring-dashpot normal force
+//     -(k_n delta + gamma_n u_n) n, tangential history spring with Coulomb
+//     cap mu |F_n|, torque r n x F_t;
+// then the flat walls at z = 0 / Lz (same models, infinite wall mass), and
+// the fluid-particle forces at the particle centre (Section 2.3): Di Felice
+// (or Stokes) drag towards the interpolated fluid velocity, -V grad p, and
+// added mass C_add rho_f V (DU_f/Dt - a_prev) with a_prev the acceleration of
+// the previous step.  Translational and angular accelerations follow from
+// Eq. (1a)-(1b).
+//
+// Precision: geometry (centre differences, distances, overlaps, normals) is
+// always FP64; with R = float the force arithmetic, the history and the sums
+// are FP32 and only the state update is FP64.
+#include "k_common.h"
+
+namespace sedimi {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+template <typename R>
+__device__ __forceinline__ V3<R> cvt(double a, double b, double c) {
+  return V3<R>{(R)a, (R)b, (R)c};
+}
+
+// Tangential spring: rotate the old history into the tangent plane keeping
+// its length, add v_t dt, F_t = -k_t xi - gamma_t v_t, Coulomb cap mu |F_n|
+// (history reset to the capped force when sliding).
+template <typename R>
+__device__ __forceinline__ V3<R> tangential(R kt, R gt, R mu, R dt, V3<R> n, V3<R> vrel,
+                                            R un, R Fn, V3<R>& xi) {
+  V3<R> vt = vrel - un * n;
+  R old2 = dot(xi, xi);
+  R xn = dot(xi, n);
+  V3<R> xp = xi - xn * n;
+  R pm2 = dot(xp, xp);
+  if (pm2 > (R)0) {
+    xp = sqrt(old2 / pm2) * xp;
+  } else {
+    xp = V3<R>{0, 0, 0};
+  }
+  xi = xp + dt * vt;
+  V3<R> ft = (-kt) * xi - gt * vt;
+  R fm2 = dot(ft, ft);
+  R cap = mu * Fn;
+  if (fm2 > cap * cap) {
+    ft = (cap / sqrt(fm2)) * ft;
+    if (kt > (R)0) xi = ((R)-1 / kt) * (ft + gt * vt);
+  }
+  return ft;
+}
+
+template <typename R>
+__device__ __forceinline__ R drag_coef(const DevParams& P, R d, R eps_f, R wm) {
+  if (P.drag_law == SEDIMI_DRAG_STOKES) return (R)(3.0 * kPi * P.mu_f) * d;
+  if (P.drag_law != SEDIMI_DRAG_DIFELICE) return (R)0;
+  R Re = (R)P.rho_f * d * eps_f * wm / (R)P.mu_f;
+  if (!(Re >= (R)1e-12)) return (R)0;
+  R cd = (R)0.63 + (R)4.8 / sqrt(Re);
+  cd = cd * cd;
+  R lg = (R)1.5 - log10(Re);
+  R chi = (R)3.7 - (R)0.65 * exp((R)-0.5 * lg * lg);
+  R area = (R)(0.25 * kPi) * d * d;
+  return (R)0.5 * cd * (R)P.rho_f * area * pow(eps_f, (R)2 - chi) * wm;
+}
+
+struct Interp {
+  int idx[8];
+  double w[8];
+};
+
+__device__ __forceinline__ Interp interp_weights(const DevParams& P, double x, double y,
+                                                 double z) {
+  Interp I;
+  double sx = x / P.hx - 0.5, sy = y / P.hy - 0.5, sz = z / P.hz - 0.5;
+  // keep indices in range even for non-finite positions (flagged elsewhere)
+  if (!(sx >= -1.0 && sx <= (double)P.nx)) sx = 0.0;
+  if (!(sy >= -1.0 && sy <= (double)P.ny)) sy = 0.0;
+  double fx0 = floor(sx), fy0 = floor(sy);
+  double fx = sx - fx0, fy = sy - fy0;
+  int i0 = (((int)fx0 % P.nx) + P.nx) % P.nx;
+  int i1 = i0 + 1 == P.nx ? 0 : i0 + 1;
+  int j0 = (((int)fy0 % P.ny) + P.ny) % P.ny;
+  int j1 = j0 + 1 == P.ny ? 0 : j0 + 1;
+  int k0, k1;
+  double fz;
+  if (P.nz == 1) {
+    k0 = k1 = 0;
+    fz = 0.0;
+  } else {
+    sz = sz >= 0.0 ? (sz > P.nz - 1 ? (double)(P.nz - 1) : sz) : 0.0;
+    k0 = (int)floor(sz);
+    if (k0 > P.nz - 2) k0 = P.nz - 2;
+    k1 = k0 + 1;
+    fz = sz - (double)k0;
+  }
+  int q = 0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        int ii = a ? i1 : i0, jj = b ? j1 : j0, kk = c ? k1 : k0;
+        I.idx[q] = (kk * P.ny + jj) * P.nx + ii;
+        I.w[q] = (a ? fx : 1.0 - fx) * (b ? fy : 1.0 - fy) * (c ? fz : 1.0 - fz);
+        ++q;
+      }
+  return I;
+}
+
+// One wall of particle i: side -1 bottom (n = -z), +1 top (n = +z).
+template <typename R>
+__device__ __forceinline__ void wall(const DevParams& P, int side, double dist, double r,
+                                     double m, V3<R> v, V3<R> rw, double4& hist,
+                                     bool update, V3<R>& Fc, V3<R>& Fl, V3<R>& T) {
+  double dfull = 2.0 * r;
+  double h = dist - r;
+  if (!(h < P.lub_out * dfull)) {
+    if (update) hist.w = 0.0;
+    return;
+  }
+  V3<R> n{(R)0, (R)0, (R)side};
+  V3<R> vrel = v + cross(rw, n);
+  R un = dot(vrel, n);
+  if (P.lubrication) {
+    double hin = P.lub_in * dfull;
+    R hh = (R)(h > hin ? h : hin);
+    R Flub = (R)(6.0 * kPi * P.mu_f) * (R)(r * r) * un / hh;
+    Fl = Fl - Flub * n;
+  }
+  double delta = r - dist;
+  if (delta > 0.0) {
+    R gn = (R)(2.0 * P.zeta) * sqrt((R)m * (R)P.kn);
+    R gt = (R)P.gt_over_gn * gn;
+    R Frep = (R)P.kn * (R)delta + gn * un;
+    V3<R> xi = hist.w != 0.0 ? cvt<R>(hist.x, hist.y, hist.z) : V3<R>{0, 0, 0};
+    V3<R> ft = tangential<R>((R)P.kt, gt, (R)P.mu, (R)P.dt, n, vrel, un, fabs(Frep), xi);
+    Fc = Fc + (ft - Frep * n);
+    T = T + (R)r * cross(n, ft);
+    if (update) hist = make_double4((double)xi.x, (double)xi.y, (double)xi.z, 1.0);
+  } else if (update) {
+    hist.w = 0.0;
+  }
+}
+
+template <typename R, int MODE>
+__global__ __launch_bounds__(kBlock) void k_forces(DevParams P, DevArrays A,
+                                                   const double* __restrict__ eps_s,
+                                                   int update_history) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0 && A.ctl->rebuild) {
+    A.ctl->rebuilds += 1;
+    A.ctl->rebuild = 0;
+  }
+  if (i >= P.n) return;
+  const int N = P.n;
+  const bool upd = update_history != 0;
+  double4 pi = A.pos[i], vi = A.vel[i], wi = A.omg[i], ai = A.acc[i];
+  const int idi = A.id[i];
+  const double ri = pi.w, mi = vi.w;
+  V3<R> Fc{0, 0, 0}, Fl{0, 0, 0}, T{0, 0, 0};
+  const unsigned mask_old = A.hmask[i];
+  unsigned mask_new = 0;
+  const int cnt = A.ncnt[i];
+  R* hx = (R*)A.hxi;
+  R* hy = hx + (size_t)P.maxn * N;
+  R* hz = hy + (size_t)P.maxn * N;
+  const R kn = (R)P.kn, kt = (R)P.kt, mu = (R)P.mu, dtR = (R)P.dt;
+
+  for (int k = 0; k < cnt; ++k) {
+    const int j = A.nbr[(size_t)k * N + i];
+    const double4 pj = A.pos[j];
+    double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
+    double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
+    double dz = pj.z - pi.z;
+    const double s = pair_s(dx, dy, dz);
+    const double rs = ri + pj.w;
+    if (!pair_in_range(s, rs, P.lub_out)) continue;
+    const int idj = A.id[j];
+    const bool lo = idi < idj;
+    const double4 vj = A.vel[j], wj = A.omg[j];
+    // canonical orientation: from the lower to the higher particle ID
+    const double sg = lo ? 1.0 : -1.0;
+    dx *= sg;
+    dy *= sg;
+    dz *= sg;
+    const double dist = sqrt(s);
+    const double inv = 1.0 / dist;
+    const V3<R> n = cvt<R>(dx * inv, dy * inv, dz * inv);
+    const double4 vlo = lo ? vi : vj, vhi = lo ? vj : vi;
+    const double4 wlo = lo ? wi : wj, whi = lo ? wj : wi;
+    const double rlo = lo ? ri : pj.w, rhi = lo ? pj.w : ri;
+    const V3<R> dv = cvt<R>(vlo.x - vhi.x, vlo.y - vhi.y, vlo.z - vhi.z);
+    const V3<R> rw = (R)rlo * cvt<R>(wlo.x, wlo.y, wlo.z) + (R)rhi * cvt<R>(whi.x, whi.y, whi.z);
+    const V3<R> vrel = dv + cross(rw, n);
+    const R un = dot(vrel, n);
+    V3<R> Fpl{0, 0, 0}, Fpc{0, 0, 0};
+    if (P.lubrication) {
+      const double h = dist - rs, hin = P.lub_in * rs;
+      const R hh = (R)(h > hin ? h : hin);
+      const R aeff = (R)(rlo * rhi / rs);
+      const R Flub = (R)(6.0 * kPi * P.mu_f) * aeff * aeff * un / hh;
+      Fpl = (-Flub) * n;
+    }
+    const double delta = rs - dist;
+    V3<R> Tp{0, 0, 0};
+    if (delta > 0.0) {
+      const double mlo = lo ? mi : vj.w, mhi = lo ? vj.w : mi;
+      const R meff = (R)(mlo * mhi / (mlo + mhi));
+      const R gn = (R)(2.0 * P.zeta) * sqrt(meff * kn);
+      const R gt = (R)P.gt_over_gn * gn;
+      const R Frep = kn * (R)delta + gn * un;
+      V3<R> xi{0, 0, 0};
+      if (mask_old & (1u << k)) {
+        xi = V3<R>{hx[(size_t)k * N + i], hy[(size_t)k * N + i], hz[(size_t)k * N + i]};
+      }
+      const V3<R> ft = tangential<R>(kt, gt, mu, dtR, n, vrel, un, fabs(Frep), xi);
+      Fpc = ft - Frep * n;
+      Tp = (R)(lo ? rlo : rhi) * cross(n, ft);
+      if (upd) {
+        hx[(size_t)k * N + i] = xi.x;
+        hy[(size_t)k * N + i] = xi.y;
+        hz[(size_t)k * N + i] = xi.z;
+        mask_new |= 1u << k;
+      }
+    }
+    if (lo) {
+      Fc = Fc + Fpc;
+      Fl = Fl + Fpl;
+    } else {
+      Fc = Fc - Fpc;
+      Fl = Fl - Fpl;
+    }
+    T = T + Tp;
+  }
+  if (upd) A.hmask[i] = mask_new;
+
+  // flat walls
+  {
+    const V3<R> v = cvt<R>(vi.x, vi.y, vi.z);
+    const V3<R> rw = (R)ri * cvt<R>(wi.x, wi.y, wi.z);
+    if (P.bottom_wall) {
+      double4 h = A.wxi[i];
+      wall<R>(P, -1, pi.z, ri, mi, v, rw, h, upd, Fc, Fl, T);
+      if (upd) A.wxi[i] = h;
+    }
+    if (P.top_wall) {
+      double4 h = A.wxi[(size_t)N + i];
+      wall<R>(P, 1, P.Lz - pi.z, ri, mi, v, rw, h, upd, Fc, Fl, T);
+      if (upd) A.wxi[(size_t)N + i] = h;
+    }
+  }
+
+  // fluid-particle forces at the particle centre
+  const double d = 2.0 * ri;
+  const double Vp = (kPi / 6.0) * d * d * d;
+  const Interp I = interp_weights(P, pi.x, pi.y, pi.z);
+  double Ux = 0, Uy = 0, Uz = 0, gpx = 0, gpy = 0, gpz = 0, dux = 0, duy = 0, duz = 0, es = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double w = I.w[q];
+    const double4 u = A.U[I.idx[q]];
+    Ux += w * u.x;
+    Uy += w * u.y;
+    Uz += w * u.z;
+    if (P.fluid_forces) {
+      const double4 g = A.gp[I.idx[q]], m = A.du[I.idx[q]];
+      gpx += w * g.x;
+      gpy += w * g.y;
+      gpz += w * g.z;
+      dux += w * m.x;
+      duy += w * m.y;
+      duz += w * m.z;
+    }
+    if (eps_s) es += w * eps_s[I.idx[q]];
+  }
+  es = es < 0.0 ? 0.0 : (es > P.eps_s_max ? P.eps_s_max : es);
+  const V3<R> wrel = cvt<R>(Ux - vi.x, Uy - vi.y, Uz - vi.z);
+  const R wm = sqrt(dot(wrel, wrel));
+  const V3<R> Fd = drag_coef<R>(P, (R)d, (R)(1.0 - es), wm) * wrel;
+  V3<R> Fp{0, 0, 0}, Fa{0, 0, 0};
+  if (P.fluid_forces) {
+    Fp = cvt<R>(-Vp * gpx, -Vp * gpy, -Vp * gpz);
+    const double ca = P.c_add * P.rho_f * Vp;
+    Fa = cvt<R>(ca * (dux - ai.x), ca * (duy - ai.y), ca * (duz - ai.z));
+  }
+  const V3<R> F = Fc + Fl + Fd + Fp + Fa;
+  const double im = 1.0 / mi;
+  const double II = 0.4 * mi * ri * ri;
+  const double4 an = make_double4((double)F.x * im + P.gx, (double)F.y * im + P.gy,
+                                  (double)F.z * im + P.gz, 0.0);
+  const double4 al = make_double4((double)T.x / II, (double)T.y / II, (double)T.z / II, 0.0);
+  A.acc[i] = an;
+  A.alp[i] = al;
+  A.fdr[i] = make_double4((double)Fd.x, (double)Fd.y, (double)Fd.z, 0.0);
+  if (MODE == 0) {
+    const double hdt = 0.5 * P.dt;
+    A.vel_t[i] = make_double4(vi.x + hdt * an.x, vi.y + hdt * an.y, vi.z + hdt * an.z, mi);
+    A.omg_t[i] = make_double4(wi.x + hdt * al.x, wi.y + hdt * al.y, wi.z + hdt * al.z, 0.0);
+  } else {
+    double4* c = A.comp;
+    c[(size_t)0 * N + i] = make_double4(Fc.x, Fc.y, Fc.z, 0.0);
+    c[(size_t)1 * N + i] = make_double4(Fl.x, Fl.y, Fl.z, 0.0);
+    c[(size_t)2 * N + i] = make_double4(Fd.x, Fd.y, Fd.z, 0.0);
+    c[(size_t)3 * N + i] = make_double4(Fp.x, Fp.y, Fp.z, 0.0);
+    c[(size_t)4 * N + i] = make_double4(Fa.x, Fa.y, Fa.z, 0.0);
+    c[(size_t)5 * N + i] = make_double4((double)F.x + mi * P.gx, (double)F.y + mi * P.gy,
+                                        (double)F.z + mi * P.gz, 0.0);
+    c[(size_t)6 * N + i] = make_double4(T.x, T.y, T.z, 0.0);
+  }
+}
+
+}  // namespace
+
+void launch_forces(const DevParams& P, DevArrays& A, const double* eps_s, int mode,
+                   bool update_history, bool mixed, hipStream_t s) {
+  if (P.n <= 0) return;
+  unsigned g = (unsigned)((P.n + kBlock - 1) / kBlock);
+  int u = update_history ? 1 : 0;
+  if (mixed) {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_forces<float, 0>), dim3(g), dim3(kBlock), 0, s, P, A, eps_s, u);
+    else
+      hipLaunchKernelGGL((k_forces<float, 1>), dim3(g), dim3(kBlock), 0, s, P, A, eps_s, u);
+  } else {
+    if (mode == 0)
+      hipLaunchKernelGGL((k_forces<double, 0>), dim3(g), dim3(kBlock), 0, s, P, A, eps_s, u);
+    else
+      hipLaunchKernelGGL((k_forces<double, 1>), dim3(g), dim3(kBlock), 0, s, P, A, eps_s, u);
+  }
+}
+
+}  // namespace sedimi

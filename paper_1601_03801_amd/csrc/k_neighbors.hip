@@ -1,0 +1,378 @@
+// k_neighbors.hip -- drift, binning, stable re-sort and neighbour-list build
+// (link-cell binning with neighbour lists, Section 2.5).
+//
+// A rebuild runs only when some particle has moved more than half the skin
+// since the last build (decided on the device in k_kick_drift); every
+// rebuild kernel reads that flag and returns at once when it is clear, so the
+// host can enqueue the whole chain every step without a round trip.
+//
+// Re-sort: counting sort by bin (integer atomics give the counts; the order
+// inside a bin is then fixed by sorting its few members by particle ID), so
+// the sorted order, the neighbour order and hence all force sums are
+// deterministic.  The tangential history survives a re-sort as (partner ID,
+// xi) rows and is matched back onto the new list slots by partner ID.
+#include "k_common.h"
+
+namespace sedimi {
+
+namespace {
+
+__device__ __forceinline__ bool gate(const Ctl* ctl) { return ctl->rebuild != 0; }
+
+__global__ void k_zero_ints(int* p, int64_t n, int gated, const Ctl* ctl) {
+  if (gated && !gate(ctl)) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// First half kick and drift of velocity Verlet; wrap on the periodic axes;
+// escape / non-finite checks; skin test against the positions of the last
+// build (minimum image).
+__global__ void k_kick_drift(DevParams P, DevArrays A) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.n) return;
+  double hdt = 0.5 * P.dt;
+  double4 x = A.pos[q], v = A.vel[q], w = A.omg[q];
+  double4 a = A.acc[q], al = A.alp[q];
+  v.x += hdt * a.x;
+  v.y += hdt * a.y;
+  v.z += hdt * a.z;
+  w.x += hdt * al.x;
+  w.y += hdt * al.y;
+  w.z += hdt * al.z;
+  x.x += P.dt * v.x;
+  x.y += P.dt * v.y;
+  x.z += P.dt * v.z;
+  if (x.x >= P.Lx) x.x -= P.Lx;
+  if (x.x < 0.0) x.x += P.Lx;
+  if (x.x >= P.Lx) x.x = 0.0;
+  if (x.y >= P.Ly) x.y -= P.Ly;
+  if (x.y < 0.0) x.y += P.Ly;
+  if (x.y >= P.Ly) x.y = 0.0;
+  A.pos[q] = x;
+  A.vel[q] = v;
+  A.omg[q] = w;
+  int fl = 0;
+  if (!(x.z >= 0.0 && x.z <= P.Lz)) fl |= 4;
+  if (!(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(v.x) && isfinite(v.y) &&
+        isfinite(v.z)))
+    fl |= 8;
+  if (fl) atomicOr(&A.ctl->flags, fl);
+  double4 b = A.xb[q];
+  double dx = min_image(x.x - b.x, P.Lx, P.hLx), dy = min_image(x.y - b.y, P.Ly, P.hLy),
+         dz = x.z - b.z;
+  if (dx * dx + dy * dy + dz * dz > P.half_skin2) atomicOr(&A.ctl->rebuild, 1);
+}
+
+// Active slot history -> (partner ID, xi) rows, before the re-sort.
+template <typename H>
+__global__ void k_compact(DevParams P, DevArrays A) {
+  if (!gate(A.ctl)) return;
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P.n) return;
+  const int N = P.n;
+  unsigned m = A.hmask[p];
+  int cnt = A.ncnt[p];
+  const H* hx = (const H*)A.hxi;
+  const H* hy = hx + (size_t)P.maxn * N;
+  const H* hz = hy + (size_t)P.maxn * N;
+  int c = 0;
+  for (int k = 0; k < cnt; ++k) {
+    if (!(m & (1u << k))) continue;
+    if (c >= kMaxContacts) {
+      atomicOr(&A.ctl->flags, 1);
+      break;
+    }
+    int j = A.nbr[(size_t)k * N + p];
+    A.cid[(size_t)c * N + p] = A.id[j];
+    A.cxi[((size_t)0 * kMaxContacts + c) * N + p] = (double)hx[(size_t)k * N + p];
+    A.cxi[((size_t)1 * kMaxContacts + c) * N + p] = (double)hy[(size_t)k * N + p];
+    A.cxi[((size_t)2 * kMaxContacts + c) * N + p] = (double)hz[(size_t)k * N + p];
+    ++c;
+  }
+  A.ccnt[p] = c;
+}
+
+__global__ void k_keys(DevParams P, DevArrays A) {
+  if (!gate(A.ctl)) return;
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P.n) return;
+  double4 x = A.pos[p];
+  int b = bin_of(P, x.x, x.y, x.z);
+  A.key[p] = b;
+  A.rank[p] = atomicAdd(&A.bin_count[b], 1);
+}
+
+__global__ void k_scatter(DevParams P, DevArrays A) {
+  if (!gate(A.ctl)) return;
+  int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P.n) return;
+  A.perm[A.bin_start[A.key[p]] + A.rank[p]] = p;
+}
+
+// Order each bin's members by particle ID (bins hold a handful of particles).
+__global__ void k_binsort(DevParams P, DevArrays A) {
+  if (!gate(A.ctl)) return;
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= P.nbins) return;
+  int s = A.bin_start[b], e = A.bin_start[b + 1];
+  for (int i = s + 1; i < e; ++i) {
+    int p = A.perm[i];
+    int key = A.id[p];
+    int j = i - 1;
+    while (j >= s && A.id[A.perm[j]] > key) {
+      A.perm[j + 1] = A.perm[j];
+      --j;
+    }
+    A.perm[j + 1] = p;
+  }
+}
+
+__global__ void k_permute(DevParams P, DevArrays A) {
+  if (!gate(A.ctl)) return;
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.n) return;
+  int p = A.perm[q];
+  A.pos_t[q] = A.pos[p];
+  A.vel_t[q] = A.vel[p];
+  A.omg_t[q] = A.omg[p];
+  A.acc_t[q] = A.acc[p];
+  A.alp_t[q] = A.alp[p];
+  A.fdr_t[q] = A.fdr[p];
+  A.wxi_t[q] = A.wxi[p];
+  A.wxi_t[(size_t)P.n + q] = A.wxi[(size_t)P.n + p];
+  A.id_t[q] = A.id[p];
+}
+
+__global__ void k_copyback(DevParams P, DevArrays A) {
+  if (!gate(A.ctl)) return;
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.n) return;
+  A.pos[q] = A.pos_t[q];
+  A.vel[q] = A.vel_t[q];
+  A.omg[q] = A.omg_t[q];
+  A.acc[q] = A.acc_t[q];
+  A.alp[q] = A.alp_t[q];
+  A.fdr[q] = A.fdr_t[q];
+  A.wxi[q] = A.wxi_t[q];
+  A.wxi[(size_t)P.n + q] = A.wxi_t[(size_t)P.n + q];
+  A.id[q] = A.id_t[q];
+}
+
+// Neighbour list of particle q: every particle in the 27 surrounding bins
+// within (pair range + skin); then the history rows of q's pre-sort slot are
+// matched onto the new slots by partner ID.
+template <typename H>
+__global__ void k_build(DevParams P, DevArrays A) {
+  if (!gate(A.ctl)) return;
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.n) return;
+  const int N = P.n;
+  double4 xi = A.pos[q];
+  int bx = bin_coord(xi.x, P.hbx, P.nbx), by = bin_coord(xi.y, P.hby, P.nby),
+      bz = bin_coord(xi.z, P.hbz, P.nbz);
+  int cnt = 0;
+  for (int dz = -1; dz <= 1; ++dz) {
+    int cz = bz + dz;
+    if (cz < 0 || cz >= P.nbz) continue;
+    for (int dy = -1; dy <= 1; ++dy) {
+      int cy = by + dy;
+      cy = cy < 0 ? cy + P.nby : (cy >= P.nby ? cy - P.nby : cy);
+      for (int dx = -1; dx <= 1; ++dx) {
+        int cx = bx + dx;
+        cx = cx < 0 ? cx + P.nbx : (cx >= P.nbx ? cx - P.nbx : cx);
+        int b = (cz * P.nby + cy) * P.nbx + cx;
+        int s = A.bin_start[b], e = A.bin_start[b + 1];
+        for (int j = s; j < e; ++j) {
+          if (j == q) continue;
+          double4 xj = A.pos[j];
+          double ddx = min_image(xj.x - xi.x, P.Lx, P.hLx);
+          double ddy = min_image(xj.y - xi.y, P.Ly, P.hLy);
+          double ddz = xj.z - xi.z;
+          double s2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          double rs = xi.w + xj.w;
+          double Rl = rs + P.lub_out * rs + P.skin;
+          if (s2 < Rl * Rl * (1.0 + 1e-9)) {
+            if (cnt < P.maxn) A.nbr[(size_t)cnt * N + q] = j;
+            ++cnt;
+          }
+        }
+      }
+    }
+  }
+  if (cnt > P.maxn) {
+    atomicOr(&A.ctl->flags, 1);
+    cnt = P.maxn;
+  }
+  atomicMax(&A.ctl->max_nbr, cnt);
+  A.ncnt[q] = cnt;
+  A.xb[q] = xi;
+  // history: rows of the pre-sort position perm[q]
+  int p = A.perm[q];
+  int nc = A.ccnt[p];
+  unsigned mask = 0;
+  int matched = 0;
+  H* hx = (H*)A.hxi;
+  H* hy = hx + (size_t)P.maxn * N;
+  H* hz = hy + (size_t)P.maxn * N;
+  if (nc > 0) {
+    for (int k = 0; k < cnt; ++k) {
+      int pid = A.id[A.nbr[(size_t)k * N + q]];
+      for (int c = 0; c < nc; ++c) {
+        if (A.cid[(size_t)c * N + p] == pid) {
+          hx[(size_t)k * N + q] = (H)A.cxi[((size_t)0 * kMaxContacts + c) * N + p];
+          hy[(size_t)k * N + q] = (H)A.cxi[((size_t)1 * kMaxContacts + c) * N + p];
+          hz[(size_t)k * N + q] = (H)A.cxi[((size_t)2 * kMaxContacts + c) * N + p];
+          mask |= 1u << k;
+          ++matched;
+          break;
+        }
+      }
+    }
+  }
+  A.hmask[q] = mask;
+  if (matched != nc) atomicOr(&A.ctl->flags, 2);
+}
+
+// ---- exclusive scan of int counts (3 passes, 1024 items per block) ----
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ int block_exclusive(int v, int* lds, int* total) {
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wid] = x;
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int w = 0; w < kBlock / 64; ++w) {
+    int s = lds[w];
+    if (w < wid) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+__global__ void k_scan_tiles(const int* cnt, int* start, int n, int* tile_sums, int gated,
+                             const Ctl* ctl) {
+  if (gated && !gate(ctl)) return;
+  __shared__ int lds[kBlock / 64];
+  int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int sum = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? cnt[base + k] : 0;
+    sum += v[k];
+  }
+  int tot;
+  int ex = block_exclusive(sum, lds, &tot);
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) start[base + k] = ex;
+    ex += v[k];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_top(int* tile_sums, int ntiles, int* start, int n, int gated,
+                           const Ctl* ctl) {
+  if (gated && !gate(ctl)) return;
+  __shared__ int lds[kBlock / 64];
+  int carry = 0;
+  for (int base = 0; base < ntiles; base += kBlock) {
+    int i = base + threadIdx.x;
+    int v = i < ntiles ? tile_sums[i] : 0;
+    int tot;
+    int ex = block_exclusive(v, lds, &tot);
+    if (i < ntiles) tile_sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) start[n] = carry;
+}
+
+__global__ void k_scan_add(int* start, int n, const int* tile_sums, int gated,
+                           const Ctl* ctl) {
+  if (gated && !gate(ctl)) return;
+  int base = blockIdx.x * kScanTile;
+  int off = tile_sums[blockIdx.x];
+  for (int k = threadIdx.x; k < kScanTile; k += kBlock)
+    if (base + k < n) start[base + k] += off;
+}
+
+// Which neighbour slots of each particle are in the pair set right now (the
+// same exact test the force kernel applies); bit k of out[q] = slot k.
+__global__ void k_pairmask(DevParams P, DevArrays A, unsigned* out) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.n) return;
+  const int N = P.n;
+  double4 pi = A.pos[q];
+  unsigned m = 0;
+  for (int k = 0; k < A.ncnt[q]; ++k) {
+    double4 pj = A.pos[A.nbr[(size_t)k * N + q]];
+    double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
+    double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
+    double dz = pj.z - pi.z;
+    if (pair_in_range(pair_s(dx, dy, dz), pi.w + pj.w, P.lub_out)) m |= 1u << k;
+  }
+  out[q] = m;
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+void launch_pairmask(const DevParams& P, DevArrays& A, unsigned* out, hipStream_t s) {
+  if (P.n <= 0) return;
+  hipLaunchKernelGGL(k_pairmask, dim3(nblk(P.n)), dim3(kBlock), 0, s, P, A, out);
+}
+
+void launch_zero_ints(int* p, int64_t n, bool gated, const Ctl* ctl, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero_ints, dim3(nblk(n)), dim3(kBlock), 0, s, p, n, gated ? 1 : 0, ctl);
+}
+
+void launch_exclusive_scan(int* cnt, int* start, int n, int* tmp, bool gated, const Ctl* ctl,
+                           hipStream_t s) {
+  int ntiles = (n + kScanTile - 1) / kScanTile;
+  if (ntiles == 0) ntiles = 1;
+  hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, s, cnt, start, n, tmp,
+                     gated ? 1 : 0, ctl);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, ntiles, start, n,
+                     gated ? 1 : 0, ctl);
+  hipLaunchKernelGGL(k_scan_add, dim3(ntiles), dim3(kBlock), 0, s, start, n, tmp,
+                     gated ? 1 : 0, ctl);
+}
+
+void launch_kick_drift(const DevParams& P, DevArrays& A, hipStream_t s) {
+  if (P.n <= 0) return;
+  hipLaunchKernelGGL(k_kick_drift, dim3(nblk(P.n)), dim3(kBlock), 0, s, P, A);
+}
+
+void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixed,
+                    hipStream_t s) {
+  if (P.n <= 0) return;
+  unsigned g = nblk(P.n);
+  launch_zero_ints(A.bin_count, P.nbins, true, A.ctl, s);
+  if (from_slots) {
+    if (mixed)
+      hipLaunchKernelGGL(k_compact<float>, dim3(g), dim3(kBlock), 0, s, P, A);
+    else
+      hipLaunchKernelGGL(k_compact<double>, dim3(g), dim3(kBlock), 0, s, P, A);
+  }
+  hipLaunchKernelGGL(k_keys, dim3(g), dim3(kBlock), 0, s, P, A);
+  launch_exclusive_scan(A.bin_count, A.bin_start, P.nbins, A.scan_tmp, true, A.ctl, s);
+  hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, P, A);
+  hipLaunchKernelGGL(k_binsort, dim3(nblk(P.nbins)), dim3(kBlock), 0, s, P, A);
+  hipLaunchKernelGGL(k_permute, dim3(g), dim3(kBlock), 0, s, P, A);
+  hipLaunchKernelGGL(k_copyback, dim3(g), dim3(kBlock), 0, s, P, A);
+  if (mixed)
+    hipLaunchKernelGGL(k_build<float>, dim3(g), dim3(kBlock), 0, s, P, A);
+  else
+    hipLaunchKernelGGL(k_build<double>, dim3(g), dim3(kBlock), 0, s, P, A);
+}
+
+}  // namespace sedimi

@@ -1,0 +1,665 @@
+// sedimi_api.cpp -- the C ABI of libsedimi (declared in include/sedimi.h):
+// parameter checks, workspace layout, host<->device transfers, and the
+// enqueueing of the kernel chains for one step and one averaging.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "sedimi_internal.h"
+
+using namespace sedimi;
+
+struct sedimi_ctx {
+  sedimi_params prm;
+  int64_t cap = 0;
+  int64_t n = 0;
+  int64_t step = 0;
+  size_t ws_bytes = 0;
+  char* ws = nullptr;
+  hipStream_t stream = nullptr;
+  DevParams P{};
+  DevArrays A{};
+  bool mixed = false;
+  bool have_particles = false;
+  int64_t last_iters = 0;
+  double last_residual = 0.0;
+  std::string err;
+};
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+int fail(sedimi_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(ctx, SEDIMI_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace carving: the same walk computes the size (base == nullptr) and
+// assigns the pointers.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = align256(off);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += sizeof(T) * (count > 0 ? count : 1);
+    return p;
+  }
+};
+
+size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
+  Carver w{base};
+  const size_t N = (size_t)(c->cap > 0 ? c->cap : 1);
+  const size_t maxn = (size_t)c->P.maxn;
+  const size_t nb = (size_t)c->P.nbins + 1;
+  const size_t nc = (size_t)c->P.ncell;
+  DevArrays a{};
+  a.pos = w.take<double4>(N);
+  a.vel = w.take<double4>(N);
+  a.omg = w.take<double4>(N);
+  a.acc = w.take<double4>(N);
+  a.alp = w.take<double4>(N);
+  a.fdr = w.take<double4>(N);
+  a.xb = w.take<double4>(N);
+  a.wxi = w.take<double4>(2 * N);
+  a.pos_t = w.take<double4>(N);
+  a.vel_t = w.take<double4>(N);
+  a.omg_t = w.take<double4>(N);
+  a.acc_t = w.take<double4>(N);
+  a.alp_t = w.take<double4>(N);
+  a.fdr_t = w.take<double4>(N);
+  a.wxi_t = w.take<double4>(2 * N);
+  a.id = w.take<int>(N);
+  a.id_t = w.take<int>(N);
+  a.nbr = w.take<int>(maxn * N);
+  a.ncnt = w.take<int>(N);
+  a.hmask = w.take<unsigned>(N);
+  a.hxi = w.take<double>(3 * maxn * N);
+  a.cid = w.take<int>((size_t)kMaxContacts * N);
+  a.cxi = w.take<double>(3 * (size_t)kMaxContacts * N);
+  a.ccnt = w.take<int>(N);
+  a.comp = w.take<double4>(7 * N);
+  a.key = w.take<int>(N);
+  a.rank = w.take<int>(N);
+  a.perm = w.take<int>(N);
+  a.cperm = w.take<int>(N);
+  a.bin_count = w.take<int>(nb);
+  a.bin_start = w.take<int>(nb);
+  size_t tiles = (std::max(nb, nc + 1) + 1023) / 1024 + 2;
+  a.scan_tmp = w.take<int>(tiles);
+  a.U = w.take<double4>(nc);
+  a.gp = w.take<double4>(nc);
+  a.du = w.take<double4>(nc);
+  a.raw = w.take<double>(4 * nc);
+  a.smooth = w.take<double>(4 * nc);
+  a.sx = w.take<double>(4 * nc);
+  a.sr = w.take<double>(4 * nc);
+  a.sd0 = w.take<double>(4 * nc);
+  a.sd1 = w.take<double>(4 * nc);
+  a.cell_count = w.take<int>(nc + 1);
+  a.cell_start = w.take<int>(nc + 1);
+  a.red = w.take<double>(smooth_red_doubles((int)nc, 4, std::max(1, c->prm.avg_ntau)));
+  a.ctl = w.take<Ctl>(1);
+  if (A) *A = a;
+  return align256(w.off);
+}
+
+int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
+  if (cap < 0 || cap > (int64_t)INT32_MAX / 32)
+    return fail(c, SEDIMI_EINVAL, "max_particles out of range");
+  if (!(p.Lx > 0 && p.Ly > 0 && p.Lz > 0)) return fail(c, SEDIMI_EINVAL, "domain must be positive");
+  if (p.nx < 1 || p.ny < 1 || p.nz < 1) return fail(c, SEDIMI_EINVAL, "mesh needs >= 1 cell per axis");
+  if ((int64_t)p.nx * p.ny * p.nz > (int64_t)INT32_MAX / 8)
+    return fail(c, SEDIMI_EINVAL, "mesh too large");
+  if (!(p.kn > 0)) return fail(c, SEDIMI_EINVAL, "kn must be positive");
+  if (!(p.restitution > 0 && p.restitution <= 1))
+    return fail(c, SEDIMI_EINVAL, "restitution must be in (0, 1]");
+  if (!(p.friction >= 0 && p.kt_over_kn >= 0 && p.gammat_over_gamman >= 0))
+    return fail(c, SEDIMI_EINVAL, "friction / tangential ratios must be >= 0");
+  if (!(p.lub_out_frac >= 0 && p.lub_in_frac > 0))
+    return fail(c, SEDIMI_EINVAL, "lubrication gaps must be >= 0 (inner > 0)");
+  if (!(p.rho_f >= 0 && p.mu_f > 0 && p.c_add >= 0))
+    return fail(c, SEDIMI_EINVAL, "fluid properties out of range");
+  if (!(p.dt > 0)) return fail(c, SEDIMI_EINVAL, "dt must be positive");
+  if (p.drag_law < 0 || p.drag_law > 2) return fail(c, SEDIMI_EINVAL, "unknown drag law");
+  if (!(p.eps_s_max >= 0 && p.eps_s_max < 1)) return fail(c, SEDIMI_EINVAL, "eps_s_max in [0,1)");
+  if (!(p.avg_bandwidth >= 0) || p.avg_ntau < 0 || !(p.avg_rtol > 0))
+    return fail(c, SEDIMI_EINVAL, "averaging parameters out of range");
+  if (p.precision != SEDIMI_FP64 && p.precision != SEDIMI_MIXED)
+    return fail(c, SEDIMI_EINVAL, "precision must be SEDIMI_FP64 or SEDIMI_MIXED");
+  if (!(p.d_max > 0)) return fail(c, SEDIMI_EINVAL, "d_max must be positive");
+  if (!(p.skin >= 0)) return fail(c, SEDIMI_EINVAL, "skin must be >= 0");
+  if (p.max_neighbors < 1 || p.max_neighbors > 30)
+    return fail(c, SEDIMI_EINVAL, "max_neighbors must be in 1..30");
+  return SEDIMI_OK;
+}
+
+void fill_dev_params(sedimi_ctx* c) {
+  const sedimi_params& p = c->prm;
+  DevParams& P = c->P;
+  P.Lx = p.Lx, P.Ly = p.Ly, P.Lz = p.Lz;
+  P.hLx = 0.5 * p.Lx, P.hLy = 0.5 * p.Ly;
+  P.nx = p.nx, P.ny = p.ny, P.nz = p.nz;
+  P.ncell = p.nx * p.ny * p.nz;
+  P.hx = p.Lx / p.nx, P.hy = p.Ly / p.ny, P.hz = p.Lz / p.nz;
+  P.Vc = P.hx * P.hy * P.hz;
+  P.kn = p.kn;
+  if (p.restitution >= 1.0) {
+    P.zeta = 0.0;
+  } else {
+    double le = log(p.restitution);
+    P.zeta = -le / sqrt(kPi * kPi + le * le);
+  }
+  P.kt = p.kt_over_kn * p.kn;
+  P.gt_over_gn = p.gammat_over_gamman;
+  P.mu = p.friction;
+  P.lub_out = p.lub_out_frac, P.lub_in = p.lub_in_frac;
+  P.rho_f = p.rho_f, P.mu_f = p.mu_f, P.c_add = p.c_add;
+  P.gx = p.gx, P.gy = p.gy, P.gz = p.gz, P.dt = p.dt;
+  P.drag_law = p.drag_law, P.lubrication = p.lubrication ? 1 : 0;
+  P.fluid_forces = p.fluid_forces ? 1 : 0;
+  P.bottom_wall = p.bottom_wall ? 1 : 0, P.top_wall = p.top_wall ? 1 : 0;
+  P.eps_s_max = p.eps_s_max;
+  // neighbour bins: no smaller than the largest pair range plus the skin
+  double hb = p.d_max * (1.0 + p.lub_out_frac) + p.skin;
+  P.nbx = std::max(1, (int)floor(p.Lx / hb));
+  P.nby = std::max(1, (int)floor(p.Ly / hb));
+  P.nbz = std::max(1, (int)floor(p.Lz / hb));
+  P.nbins = P.nbx * P.nby * P.nbz;
+  P.hbx = p.Lx / P.nbx, P.hby = p.Ly / P.nby, P.hbz = p.Lz / P.nbz;
+  P.skin = p.skin;
+  P.half_skin2 = 0.25 * p.skin * p.skin;
+  P.maxn = p.max_neighbors;
+  P.n = 0;
+}
+
+int need_ws(sedimi_ctx* c) {
+  if (!c) return SEDIMI_EINVAL;
+  if (!c->ws) return fail(c, SEDIMI_ENOMEM, "no workspace bound");
+  return SEDIMI_OK;
+}
+int need_particles(sedimi_ctx* c) {
+  int rc = need_ws(c);
+  if (rc) return rc;
+  if (!c->have_particles) return fail(c, SEDIMI_ESTATE, "no particles set");
+  return SEDIMI_OK;
+}
+
+int read_ctl(sedimi_ctx* c, Ctl* out) {
+  HIPCHK(c, hipMemcpyAsync(out, c->A.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int flags_to_rc(sedimi_ctx* c, int flags) {
+  if (flags & 8) return fail(c, SEDIMI_EUNSTABLE, "non-finite particle state");
+  if (flags & 4) return fail(c, SEDIMI_EESCAPE, "a particle left [0, Lz]");
+  if (flags & 1) return fail(c, SEDIMI_EOVERFLOW, "neighbour or contact slots exceeded");
+  if (flags & 2) return fail(c, SEDIMI_EOVERFLOW, "a contact fell out of the neighbour list");
+  return SEDIMI_OK;
+}
+
+int set_rebuild_flag(sedimi_ctx* c) {
+  int one = 1;
+  HIPCHK(c, hipMemcpyAsync(&c->A.ctl->rebuild, &one, sizeof(int), hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+// Download a device array of `count` T's.
+template <typename T>
+int download(sedimi_ctx* c, std::vector<T>& h, const T* d, size_t count) {
+  h.resize(count);
+  if (count == 0) return SEDIMI_OK;
+  HIPCHK(c, hipMemcpyAsync(h.data(), d, sizeof(T) * count, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int64_t do_average(sedimi_ctx* c) {
+  launch_deposit(c->P, c->A, c->stream);
+  double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
+  return launch_smooth(c->P, c->A, 4, c->prm.avg_ntau, tau, c->prm.avg_rtol, c->mixed,
+                       c->stream);
+}
+
+int check_solve(sedimi_ctx* c, int nch) {
+  double res = read_smooth_residual(c->P, c->A, nch, c->prm.avg_ntau, c->stream);
+  if (res < 0) return fail(c, SEDIMI_EDEVICE, "reading the solver residual failed");
+  c->last_residual = res;
+  if (res > c->prm.avg_rtol * 10.0 + 1e-300)
+    return fail(c, SEDIMI_ENOCONV, "diffusion solve residual above tolerance");
+  return SEDIMI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sedimi_create(const sedimi_params* p, int64_t max_particles, sedimi_ctx** out) {
+  if (!p || !out) return SEDIMI_EINVAL;
+  *out = nullptr;
+  sedimi_ctx* c = new (std::nothrow) sedimi_ctx();
+  if (!c) return SEDIMI_ENOMEM;
+  int rc = check_params(c, *p, max_particles);
+  c->prm = *p;
+  c->cap = max_particles;
+  c->mixed = p->precision == SEDIMI_MIXED;
+  if (rc == SEDIMI_OK) {
+    fill_dev_params(c);
+    if (c->P.nbx < 3 || c->P.nby < 3)
+      rc = fail(c, SEDIMI_EINVAL, "domain must span at least 3 neighbour bins in x and y");
+    else if ((int64_t)c->P.nbins > (int64_t)INT32_MAX / 8)
+      rc = fail(c, SEDIMI_EINVAL, "too many neighbour bins");
+  }
+  if (rc != SEDIMI_OK) {
+    // keep the message reachable through a context-less error: print it
+    fprintf(stderr, "sedimi_create: %s\n", c->err.c_str());
+    delete c;
+    return rc;
+  }
+  c->ws_bytes = layout(c, nullptr, nullptr);
+  *out = c;
+  return SEDIMI_OK;
+}
+
+void sedimi_destroy(sedimi_ctx* c) { delete c; }
+
+const char* sedimi_last_error(const sedimi_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+size_t sedimi_workspace_bytes(const sedimi_ctx* c) { return c ? c->ws_bytes : 0; }
+
+int sedimi_bind_workspace(sedimi_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c) return SEDIMI_EINVAL;
+  if (!dev_ptr || ((uintptr_t)dev_ptr & 255)) return fail(c, SEDIMI_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < c->ws_bytes) return fail(c, SEDIMI_ENOMEM, "workspace too small");
+  c->ws = (char*)dev_ptr;
+  layout(c, c->ws, &c->A);
+  HIPCHK(c, hipMemsetAsync(c->ws, 0, c->ws_bytes, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->have_particles = false;
+  return SEDIMI_OK;
+}
+
+int sedimi_set_stream(sedimi_ctx* c, void* s) {
+  if (!c) return SEDIMI_EINVAL;
+  c->stream = (hipStream_t)s;
+  return SEDIMI_OK;
+}
+
+int sedimi_set_particles(sedimi_ctx* c, int64_t n, const double* x, const double* v,
+                         const double* w, const double* d, const double* rho) {
+  int rc = need_ws(c);
+  if (rc) return rc;
+  if (n < 0 || n > c->cap) return fail(c, SEDIMI_EINVAL, "particle count exceeds capacity");
+  if (n > 0 && (!x || !v || !d || !rho)) return fail(c, SEDIMI_EINVAL, "null particle array");
+  std::vector<double4> pos(n), vel(n), omg(n);
+  std::vector<int> id(n);
+  for (int64_t i = 0; i < n; ++i) {
+    double di = d[i];
+    if (!(di > 0 && di <= c->prm.d_max)) return fail(c, SEDIMI_EINVAL, "diameter outside (0, d_max]");
+    if (!(rho[i] > 0)) return fail(c, SEDIMI_EINVAL, "density must be positive");
+    double xi = x[3 * i], yi = x[3 * i + 1], zi = x[3 * i + 2];
+    if (!(xi >= 0 && xi < c->prm.Lx && yi >= 0 && yi < c->prm.Ly && zi >= 0 && zi <= c->prm.Lz))
+      return fail(c, SEDIMI_EINVAL, "particle centre outside the domain");
+    double V = (kPi / 6.0) * di * di * di;
+    pos[i] = make_double4(xi, yi, zi, 0.5 * di);
+    vel[i] = make_double4(v[3 * i], v[3 * i + 1], v[3 * i + 2], rho[i] * V);
+    omg[i] = w ? make_double4(w[3 * i], w[3 * i + 1], w[3 * i + 2], 0.0) : make_double4(0, 0, 0, 0);
+    id[i] = (int)i;
+  }
+  c->n = n;
+  c->P.n = (int)n;
+  c->step = 0;
+  // clear the per-particle arrays (they precede the mesh arrays in the
+  // layout) and the control block; mesh fields are kept
+  HIPCHK(c, hipMemsetAsync(c->ws, 0, (size_t)((char*)c->A.U - c->ws), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->A.ctl, 0, sizeof(Ctl), c->stream));
+  if (n > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->A.pos, pos.data(), sizeof(double4) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->A.vel, vel.data(), sizeof(double4) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->A.omg, omg.data(), sizeof(double4) * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->A.id, id.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->stream));
+  }
+  rc = set_rebuild_flag(c);
+  if (rc) return rc;
+  launch_rebuild(c->P, c->A, false, c->mixed, c->stream);
+  Ctl ctl;
+  rc = read_ctl(c, &ctl);
+  if (rc) return rc;
+  c->have_particles = true;
+  return flags_to_rc(c, ctl.flags);
+}
+
+int sedimi_set_fluid(sedimi_ctx* c, const double* U, const double* gp, const double* du) {
+  int rc = need_ws(c);
+  if (rc) return rc;
+  const int nc = c->P.ncell;
+  std::vector<double4> h(nc);
+  const double* src[3] = {U, gp, du};
+  double4* dst[3] = {c->A.U, c->A.gp, c->A.du};
+  for (int f = 0; f < 3; ++f) {
+    for (int k = 0; k < nc; ++k)
+      h[k] = src[f] ? make_double4(src[f][3 * k], src[f][3 * k + 1], src[f][3 * k + 2], 0.0)
+                    : make_double4(0, 0, 0, 0);
+    HIPCHK(c, hipMemcpyAsync(dst[f], h.data(), sizeof(double4) * nc, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return SEDIMI_OK;
+}
+
+int sedimi_set_field(sedimi_ctx* c, int field, const double* in) {
+  int rc = need_ws(c);
+  if (rc) return rc;
+  if (!in || (field != SEDIMI_FIELD_RAW && field != SEDIMI_FIELD_SMOOTH))
+    return fail(c, SEDIMI_EINVAL, "bad field");
+  double* dst = field == SEDIMI_FIELD_RAW ? c->A.raw : c->A.smooth;
+  HIPCHK(c, hipMemcpyAsync(dst, in, sizeof(double) * 4 * c->P.ncell, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int sedimi_set_accel(sedimi_ctx* c, const double* a, const double* alpha) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  std::vector<int> id;
+  rc = download(c, id, c->A.id, (size_t)c->n);
+  if (rc) return rc;
+  std::vector<double4> ha(c->n), hal(c->n);
+  rc = download(c, ha, c->A.acc, (size_t)c->n);
+  if (rc) return rc;
+  rc = download(c, hal, c->A.alp, (size_t)c->n);
+  if (rc) return rc;
+  for (int64_t q = 0; q < c->n; ++q) {
+    int i = id[q];
+    if (a) ha[q] = make_double4(a[3 * i], a[3 * i + 1], a[3 * i + 2], 0.0);
+    if (alpha) hal[q] = make_double4(alpha[3 * i], alpha[3 * i + 1], alpha[3 * i + 2], 0.0);
+  }
+  HIPCHK(c, hipMemcpyAsync(c->A.acc, ha.data(), sizeof(double4) * c->n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->A.alp, hal.data(), sizeof(double4) * c->n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int sedimi_compute_forces(sedimi_ctx* c, int update_history) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  launch_forces(c->P, c->A, c->A.smooth, 1, update_history != 0, c->mixed, c->stream);
+  HIPCHK(c, hipGetLastError());
+  Ctl ctl;
+  rc = read_ctl(c, &ctl);
+  if (rc) return rc;
+  return flags_to_rc(c, ctl.flags);
+}
+
+int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(c, SEDIMI_EINVAL, "nsteps must be >= 0");
+  bool averaged = false;
+  for (int s = 0; s < nsteps; ++s) {
+    launch_kick_drift(c->P, c->A, c->stream);
+    launch_rebuild(c->P, c->A, true, c->mixed, c->stream);
+    launch_forces(c->P, c->A, c->A.smooth, 0, true, c->mixed, c->stream);
+    std::swap(c->A.vel, c->A.vel_t);
+    std::swap(c->A.omg, c->A.omg_t);
+    ++c->step;
+    if (average_every > 0 && c->step % average_every == 0) {
+      c->last_iters = do_average(c);
+      averaged = true;
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  Ctl ctl;
+  rc = read_ctl(c, &ctl);
+  if (rc) return rc;
+  rc = flags_to_rc(c, ctl.flags);
+  if (rc) return rc;
+  if (averaged) return check_solve(c, 4);
+  return SEDIMI_OK;
+}
+
+int sedimi_average(sedimi_ctx* c) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  c->last_iters = do_average(c);
+  HIPCHK(c, hipGetLastError());
+  return check_solve(c, 4);
+}
+
+int sedimi_deposit(sedimi_ctx* c) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  launch_deposit(c->P, c->A, c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int sedimi_smooth(sedimi_ctx* c, int nch) {
+  int rc = need_ws(c);
+  if (rc) return rc;
+  if (nch < 1 || nch > 4) return fail(c, SEDIMI_EINVAL, "nch must be 1..4");
+  double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
+  c->last_iters = launch_smooth(c->P, c->A, nch, c->prm.avg_ntau, tau, c->prm.avg_rtol,
+                                c->mixed, c->stream);
+  HIPCHK(c, hipGetLastError());
+  return check_solve(c, nch);
+}
+
+int sedimi_get_particles(sedimi_ctx* c, double* x, double* v, double* w, double* a) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  const size_t n = (size_t)c->n;
+  std::vector<int> id;
+  rc = download(c, id, c->A.id, n);
+  if (rc) return rc;
+  double* outs[4] = {x, v, w, a};
+  const double4* srcs[4] = {c->A.pos, c->A.vel, c->A.omg, c->A.acc};
+  std::vector<double4> h;
+  for (int f = 0; f < 4; ++f) {
+    if (!outs[f]) continue;
+    rc = download(c, h, srcs[f], n);
+    if (rc) return rc;
+    for (size_t q = 0; q < n; ++q) {
+      double* o = outs[f] + 3 * (size_t)id[q];
+      o[0] = h[q].x, o[1] = h[q].y, o[2] = h[q].z;
+    }
+  }
+  return SEDIMI_OK;
+}
+
+int sedimi_get_forces(sedimi_ctx* c, int comp, double* f) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  if (comp < 0 || comp > 6 || !f) return fail(c, SEDIMI_EINVAL, "bad force component");
+  const size_t n = (size_t)c->n;
+  std::vector<int> id;
+  rc = download(c, id, c->A.id, n);
+  if (rc) return rc;
+  std::vector<double4> h;
+  rc = download(c, h, c->A.comp + (size_t)comp * n, n);
+  if (rc) return rc;
+  for (size_t q = 0; q < n; ++q) {
+    double* o = f + 3 * (size_t)id[q];
+    o[0] = h[q].x, o[1] = h[q].y, o[2] = h[q].z;
+  }
+  return SEDIMI_OK;
+}
+
+int sedimi_get_field(sedimi_ctx* c, int field, double* out) {
+  int rc = need_ws(c);
+  if (rc) return rc;
+  if (!out || (field != SEDIMI_FIELD_RAW && field != SEDIMI_FIELD_SMOOTH))
+    return fail(c, SEDIMI_EINVAL, "bad field");
+  const double* src = field == SEDIMI_FIELD_RAW ? c->A.raw : c->A.smooth;
+  HIPCHK(c, hipMemcpyAsync(out, src, sizeof(double) * 4 * c->P.ncell, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int sedimi_get_pairs(sedimi_ctx* c, int64_t cap, int64_t* ij, int64_t* n_out) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  if (!n_out) return fail(c, SEDIMI_EINVAL, "null n_out");
+  const size_t n = (size_t)c->n;
+  // the pair test runs on the device (the force kernel's exact predicate);
+  // the key array serves as scratch for the slot masks
+  launch_pairmask(c->P, c->A, (unsigned*)c->A.key, c->stream);
+  HIPCHK(c, hipGetLastError());
+  std::vector<unsigned> mask;
+  std::vector<int> id, cnt, nbr;
+  if ((rc = download(c, mask, (const unsigned*)c->A.key, n))) return rc;
+  if ((rc = download(c, id, c->A.id, n))) return rc;
+  if ((rc = download(c, cnt, c->A.ncnt, n))) return rc;
+  if ((rc = download(c, nbr, c->A.nbr, (size_t)c->P.maxn * n))) return rc;
+  std::vector<std::pair<int64_t, int64_t>> pairs;
+  for (size_t q = 0; q < n; ++q) {
+    for (int k = 0; k < cnt[q]; ++k) {
+      if (!(mask[q] & (1u << k))) continue;
+      int j = nbr[(size_t)k * n + q];
+      if (id[q] < id[j]) pairs.emplace_back(id[q], id[j]);
+    }
+  }
+  std::sort(pairs.begin(), pairs.end());
+  *n_out = (int64_t)pairs.size();
+  if ((int64_t)pairs.size() > cap) return fail(c, SEDIMI_EOVERFLOW, "pair buffer too small");
+  for (size_t k = 0; k < pairs.size(); ++k) {
+    ij[2 * k] = pairs[k].first;
+    ij[2 * k + 1] = pairs[k].second;
+  }
+  return SEDIMI_OK;
+}
+
+struct HistRec {
+  int64_t i, j;
+  double xi[3];
+};
+
+int sedimi_get_history(sedimi_ctx* c, int64_t cap, void* records, int64_t* n_out) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  if (!n_out) return fail(c, SEDIMI_EINVAL, "null n_out");
+  const size_t n = (size_t)c->n, maxn = (size_t)c->P.maxn;
+  std::vector<int> id, cnt, nbr;
+  std::vector<unsigned> mask;
+  std::vector<double4> wxi;
+  if ((rc = download(c, id, c->A.id, n))) return rc;
+  if ((rc = download(c, cnt, c->A.ncnt, n))) return rc;
+  if ((rc = download(c, nbr, c->A.nbr, maxn * n))) return rc;
+  if ((rc = download(c, mask, c->A.hmask, n))) return rc;
+  if ((rc = download(c, wxi, c->A.wxi, 2 * n))) return rc;
+  std::vector<double> hd;
+  std::vector<float> hf;
+  if (c->mixed) {
+    if ((rc = download(c, hf, (const float*)c->A.hxi, 3 * maxn * n))) return rc;
+  } else {
+    if ((rc = download(c, hd, (const double*)c->A.hxi, 3 * maxn * n))) return rc;
+  }
+  auto hx = [&](int comp, size_t k, size_t q) -> double {
+    size_t o = ((size_t)comp * maxn + k) * n + q;
+    return c->mixed ? (double)hf[o] : hd[o];
+  };
+  std::vector<HistRec> out;
+  for (size_t q = 0; q < n; ++q) {
+    for (int k = 0; k < cnt[q]; ++k) {
+      if (!(mask[q] & (1u << k))) continue;
+      int j = nbr[(size_t)k * n + q];
+      if (id[q] < id[j]) out.push_back({id[q], id[j], {hx(0, k, q), hx(1, k, q), hx(2, k, q)}});
+    }
+    for (int side = 0; side < 2; ++side) {
+      const double4& h = wxi[(size_t)side * n + q];
+      if (h.w != 0.0) out.push_back({id[q], side == 0 ? -1 : -2, {h.x, h.y, h.z}});
+    }
+  }
+  std::sort(out.begin(), out.end(), [](const HistRec& a, const HistRec& b) {
+    return a.i != b.i ? a.i < b.i : a.j < b.j;
+  });
+  *n_out = (int64_t)out.size();
+  if ((int64_t)out.size() > cap) return fail(c, SEDIMI_EOVERFLOW, "history buffer too small");
+  if (!out.empty()) memcpy(records, out.data(), sizeof(HistRec) * out.size());
+  return SEDIMI_OK;
+}
+
+int sedimi_set_history(sedimi_ctx* c, int64_t nrec, const void* records) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  if (nrec < 0 || (nrec > 0 && !records)) return fail(c, SEDIMI_EINVAL, "bad history records");
+  const size_t n = (size_t)c->n;
+  std::vector<int> id;
+  if ((rc = download(c, id, c->A.id, n))) return rc;
+  std::vector<int> where(n);
+  for (size_t q = 0; q < n; ++q) where[id[q]] = (int)q;
+  std::vector<int> cid((size_t)kMaxContacts * n, 0), ccnt(n, 0);
+  std::vector<double> cxi(3 * (size_t)kMaxContacts * n, 0.0);
+  std::vector<double4> wxi(2 * n, make_double4(0, 0, 0, 0));
+  const HistRec* r = (const HistRec*)records;
+  auto add = [&](int64_t self, int64_t partner, const double* xi) -> bool {
+    size_t q = (size_t)where[self];
+    int k = ccnt[q];
+    if (k >= kMaxContacts) return false;
+    cid[(size_t)k * n + q] = (int)partner;
+    for (int a = 0; a < 3; ++a) cxi[((size_t)a * kMaxContacts + k) * n + q] = xi[a];
+    ccnt[q] = k + 1;
+    return true;
+  };
+  for (int64_t t = 0; t < nrec; ++t) {
+    int64_t i = r[t].i, j = r[t].j;
+    if (i < 0 || i >= c->n || j < -2 || j >= c->n || (j >= 0 && j <= i))
+      return fail(c, SEDIMI_EINVAL, "history record has bad IDs");
+    if (j < 0) {
+      wxi[(size_t)(j == -1 ? 0 : 1) * n + where[i]] = make_double4(r[t].xi[0], r[t].xi[1], r[t].xi[2], 1.0);
+    } else if (!add(i, j, r[t].xi) || !add(j, i, r[t].xi)) {
+      return fail(c, SEDIMI_EOVERFLOW, "too many contacts for one particle");
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(c->A.cid, cid.data(), sizeof(int) * cid.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->A.cxi, cxi.data(), sizeof(double) * cxi.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->A.ccnt, ccnt.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->A.wxi, wxi.data(), sizeof(double4) * 2 * n, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->A.ctl, 0, sizeof(int) * 2, c->stream));
+  rc = set_rebuild_flag(c);
+  if (rc) return rc;
+  launch_rebuild(c->P, c->A, false, c->mixed, c->stream);
+  // the next force kernel clears the rebuild flag; do it here for a clean state
+  int zero = 0;
+  HIPCHK(c, hipMemcpyAsync(&c->A.ctl->rebuild, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  Ctl ctl;
+  if ((rc = read_ctl(c, &ctl))) return rc;
+  if (ctl.flags & 2) return fail(c, SEDIMI_EINVAL, "a history pair is not in the neighbour list");
+  return flags_to_rc(c, ctl.flags);
+}
+
+int sedimi_get_stats(sedimi_ctx* c, sedimi_stats* out) {
+  int rc = need_ws(c);
+  if (rc) return rc;
+  if (!out) return fail(c, SEDIMI_EINVAL, "null stats");
+  Ctl ctl;
+  if ((rc = read_ctl(c, &ctl))) return rc;
+  out->steps = c->step;
+  out->rebuilds = ctl.rebuilds;
+  out->max_neighbors = ctl.max_nbr;
+  out->flags = ctl.flags;
+  out->solve_iters = c->last_iters;
+  out->solve_residual = c->last_residual;
+  return SEDIMI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+// sedimi_internal.h -- device data layout and kernel launchers of libsedimi.
+//
+// Device layout (all in the caller's workspace, 256-byte aligned arrays):
+//   particles, kept sorted by neighbour bin (x, then y, then z bin; IDs
+//   ascending inside a bin) so that neighbours are near in memory:
+//     pos   double4 (x, y, z, r)          vel double4 (vx, vy, vz, m)
+//     omg   double4 (wx, wy, wz, -)       acc double4 (a^n), alp double4 (alpha^n)
+//     fdr   double4 (drag of the last evaluation)
+//     id    int32 original particle ID
+//     xb    double4 positions at the last neighbour-list build
+//     wxi   double4 [2][N] wall history (bottom, top); .w = 1 when active
+//   neighbour list (full: each pair appears on both sides), slot-major so that
+//   slot k of consecutive particles is contiguous:
+//     nbr   int32 [maxn][N], ncnt int32 [N]
+//     hmask uint32 [N]   bit k set = slot k carries tangential history
+//     hxi   3 x [maxn][N] history of slot k (double, or float in mixed mode),
+//           oriented from the lower to the higher particle ID
+//   compact history (partner ID + xi per contact) used across a re-sort:
+//     cid int32 [maxc][N], cxi 3 x [maxc][N] double, ccnt int32 [N]
+//   mesh: U, gp, du double4 [ncell]; raw, smooth 4 x [ncell] double; solver
+//   vectors; sort scratch; a control block of flags and counters.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/sedimi.h"
+
+namespace sedimi {
+
+constexpr int kBlock = 256;
+constexpr int kMaxContacts = 16;  // contacts per particle kept across a re-sort
+constexpr uint32_t kCtlRebuild = 0;
+
+// Flags and counters living in device memory.
+struct Ctl {
+  int rebuild;       // a rebuild is pending for this step
+  int flags;         // bit 0 overflow, 1 lost contact, 2 escape, 3 non-finite
+  int max_nbr;       // largest neighbour count at a build
+  int pad0;
+  long long rebuilds;
+  long long pad1[5];
+};
+
+// Parameters copied by value into the kernels.
+struct DevParams {
+  double Lx, Ly, Lz, hLx, hLy;
+  int nx, ny, nz, ncell;
+  double hx, hy, hz, Vc;
+  double kn, zeta, kt, gt_over_gn, mu;
+  double lub_out, lub_in;
+  double rho_f, mu_f, c_add;
+  double gx, gy, gz, dt;
+  int drag_law, lubrication, fluid_forces, bottom_wall, top_wall;
+  double eps_s_max;
+  // neighbour bins
+  int nbx, nby, nbz, nbins;
+  double hbx, hby, hbz;
+  double skin, half_skin2;
+  int maxn, n;
+};
+
+// Device pointers of one context.
+struct DevArrays {
+  double4 *pos, *vel, *omg, *acc, *alp, *fdr, *xb, *wxi;  // primary
+  double4 *pos_t, *vel_t, *omg_t, *acc_t, *alp_t, *fdr_t, *wxi_t;  // second buffers
+  int *id, *id_t;
+  int* nbr;
+  int* ncnt;
+  unsigned* hmask;
+  void* hxi;  // 3 x [maxn][N] of double (FP64) or float (mixed)
+  int* cid;
+  double* cxi;
+  int* ccnt;
+  // force breakdown (diagnostic evaluation): 7 x double4 [N]
+  double4* comp;
+  // sort scratch
+  int *key, *rank, *perm, *bin_count, *bin_start, *scan_tmp;
+  // mesh
+  double4 *U, *gp, *du;
+  double *raw, *smooth, *sx, *sr, *sd0, *sd1;
+  int *cell_count, *cell_start, *cperm;
+  double* red;  // reduction partials
+  Ctl* ctl;
+};
+
+// ---- launchers (k_neighbors.hip) ----
+void launch_zero_ints(int* p, int64_t n, bool gated, const Ctl* ctl, hipStream_t s);
+void launch_kick_drift(const DevParams& P, DevArrays& A, hipStream_t s);
+void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixed,
+                    hipStream_t s);
+void launch_pairmask(const DevParams& P, DevArrays& A, unsigned* out, hipStream_t s);
+void launch_exclusive_scan(int* in_out_count, int* start, int n, int* tmp, bool gated,
+                           const Ctl* ctl, hipStream_t s);
+
+// ---- launchers (k_forces.hip) ----
+// mode: 0 = step (second half kick, writes vel_t/omg_t), 1 = evaluation with
+// breakdown (writes comp, acc, alp); update_history as in sedimi_compute_forces.
+void launch_forces(const DevParams& P, DevArrays& A, const double* eps_s, int mode,
+                   bool update_history, bool mixed, hipStream_t s);
+
+// ---- launchers (k_average.hip) ----
+void launch_deposit(const DevParams& P, DevArrays& A, hipStream_t s);
+// Enqueue the smoothing of channels [0, nch) of raw into smooth; returns the
+// total number of solver iterations.  Each pseudo-time step's final residual
+// partials are left in A.red for read_smooth_residual.
+int64_t launch_smooth(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
+                      double rtol, bool mixed, hipStream_t s);
+// Largest relative residual over channels and pseudo-time steps of the last
+// launch_smooth (synchronises the stream); negative on a HIP error.
+double read_smooth_residual(const DevParams& P, DevArrays& A, int nch, int ntau,
+                            hipStream_t s);
+size_t smooth_red_doubles(int ncell, int nch, int ntau);
+
+}  // namespace sedimi

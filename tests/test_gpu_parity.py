@@ -1,0 +1,200 @@
+"""GPU (HIP, through the C ABI) against the FP64 oracle on identical seeded
+inputs.
+
+Bars: pair sets bit-exact; FP64 forces within 1e-12 of the per-particle sum of
+force magnitudes (summation order differs); FP32-force mode within 1e-5 of it;
+deposited solid fraction bit-exact (same per-cell summation order); smoothed
+fields within 1e-6 absolute (far tighter in practice); trajectories reported
+and bounded over a few steps only (dense-bed dynamics is chaotic).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+from gpu_helpers import dense_bed, gpu_context, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_inputs(orc, case, seed):
+    """Seeded history, a_prev and a smoothed solid-fraction field, all made by
+    the oracle alone."""
+    prm = case["params"]
+    comps, hist = orc.forces(prm, case["x"], case["v"], case["w"], case["d"], case["rho"],
+                             U=case["U"], gradp=case["gradp"], dudt=case["dudt"])
+    rng = np.random.default_rng(seed)
+    hist = hist.copy()
+    hist["xi"] = rng.normal(scale=2e-8, size=(len(hist), 3))
+    a_prev = rng.normal(scale=1.0, size=case["x"].shape)
+    raw = orc.deposit(prm, case["x"], case["d"])
+    sm, _ = orc.diffuse(prm, raw)
+    return hist, a_prev, sm
+
+
+@pytest.mark.parametrize("n,seed", [(2000, 1), (5000, 2)])
+def test_pair_set_bit_exact(orc, n, seed):
+    case = dense_bed(n, seed)
+    g = gpu_context(case)
+    got = g.get_pairs()
+    want = orc.pairs_cells(case["params"], case["x"], case["d"])
+    assert len(want) > 2 * n
+    assert np.array_equal(got, want)
+
+
+def test_pair_set_small_workload_vs_brute_force(orc):
+    w = workloads.workload("small")
+    g = gpu_context(w)
+    got = g.get_pairs()
+    want = orc.pairs_brute(w["params"], w["x"], w["d"])
+    assert np.array_equal(got, want)
+
+
+def test_empty_and_single(orc):
+    case = dense_bed(2000, 3)
+    for n in (0, 1):
+        sub = dict(case, x=case["x"][:n], v=case["v"][:n], w=case["w"][:n], d=case["d"][:n],
+                   rho=case["rho"][:n])
+        g = gpu_context(sub, cap=16)
+        assert len(g.get_pairs()) == 0
+        g.compute_forces()
+        g.step(3)
+        g.average()
+        raw = g.get_field(0)
+        if n == 0:
+            assert not raw.any()
+        else:
+            Vc = (case["params"]["Lx"] / case["params"]["nx"] * case["params"]["Ly"] /
+                  case["params"]["ny"] * case["params"]["Lz"] / case["params"]["nz"])
+            assert raw[0].sum() * Vc == pytest.approx(math.pi / 6 * sub["d"][0] ** 3, rel=1e-14)
+
+
+def _force_parity(orc, case, precision, tol, seed):
+    prm = case["params"]
+    hist, a_prev, sm = _oracle_inputs(orc, case, seed)
+    comps, hout = orc.forces(prm, case["x"], case["v"], case["w"], case["d"], case["rho"],
+                             a_prev=a_prev, U=case["U"], gradp=case["gradp"],
+                             dudt=case["dudt"], eps_s=sm[0], hist=hist)
+    g = gpu_context(case, precision=precision)
+    g.set_field(1, sm)
+    g.set_accel(a_prev)
+    g.set_history(hist)
+    assert len(g.get_history()) == len(hist)
+    g.compute_forces(update_history=True)
+    m = case["rho"] * math.pi / 6 * case["d"] ** 3
+    scale = sum(np.linalg.norm(comps[k], axis=1) for k in
+                ("contact", "lub", "drag", "pressure", "added")) + m * 9.81
+    worst = {}
+    for k in ("contact", "lub", "drag", "pressure", "added", "total"):
+        e = rel_err(g.get_forces(k), comps[k], scale)
+        worst[k] = float(e.max())
+    r = 0.5 * case["d"]
+    tscale = np.linalg.norm(comps["torque"], axis=1) + r * scale
+    worst["torque"] = float(rel_err(g.get_forces("torque"), comps["torque"], tscale).max())
+    # history after the evaluation: same contacts, same springs
+    gh = g.get_history()
+    assert np.array_equal(gh["i"], hout["i"]) and np.array_equal(gh["j"], hout["j"])
+    xs = np.abs(hout["xi"]).max() + 1e-30
+    worst["history"] = float(np.abs(gh["xi"] - hout["xi"]).max() / xs)
+    print(precision, worst)
+    for k, v in worst.items():
+        assert v < tol, (k, v)
+    return worst
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_forces_fp64(orc, seed):
+    case = dense_bed(3000, seed)
+    _force_parity(orc, case, "fp64", 1e-12, seed)
+
+
+@pytest.mark.parametrize("seed", [6])
+def test_forces_mixed_fp32(orc, seed):
+    case = dense_bed(3000, seed)
+    _force_parity(orc, case, "mixed", 1e-5, seed)
+
+
+def test_deposit_bit_exact_and_smooth(orc):
+    case = dense_bed(4000, 8)
+    prm = case["params"]
+    comps, _ = orc.forces(prm, case["x"], case["v"], case["w"], case["d"], case["rho"],
+                          U=case["U"], gradp=case["gradp"], dudt=case["dudt"])
+    raw_o = orc.deposit(prm, case["x"], case["d"], comps["drag"])
+    sm_o, _ = orc.diffuse(prm, raw_o)
+    g = gpu_context(case)
+    g.compute_forces()
+    g.average()
+    raw_g = g.get_field(0)
+    sm_g = g.get_field(1)
+    assert np.array_equal(raw_g[0], raw_o[0])  # same per-cell ID-order sums
+    dscale = np.abs(raw_o[1:]).max()
+    assert np.abs(raw_g[1:] - raw_o[1:]).max() < 1e-12 * dscale
+    assert np.abs(sm_g[0] - sm_o[0]).max() < 1e-6
+    assert np.abs(sm_g[0] - sm_o[0]).max() < 1e-11 * raw_o[0].max()
+    assert np.abs(sm_g[1:] - sm_o[1:]).max() < 1e-10 * dscale
+    st = g.stats()
+    assert st["solve_residual"] < 1e-11
+
+
+@pytest.mark.parametrize("shape,ntau", [((16, 16, 8), 4), ((33, 20, 17), 3), ((64, 32, 48), 4)])
+def test_smooth_matches_oracle(orc, shape, ntau):
+    prm = workloads.base_params(Lx=shape[0] * 0.3e-3, Ly=shape[1] * 0.3e-3, Lz=shape[2] * 0.2e-3,
+                                nx=shape[0], ny=shape[1], nz=shape[2], avg_ntau=ntau)
+    rng = np.random.default_rng(sum(shape))
+    raw = rng.random((4, np.prod(shape))) ** 3
+    want, _ = orc.diffuse(prm, raw)
+    case = dict(params=prm, x=np.zeros((0, 3)), v=np.zeros((0, 3)), w=np.zeros((0, 3)),
+                d=np.zeros(0), rho=np.zeros(0))
+    g = gpu_context(case, cap=1)
+    g.set_field(0, raw)
+    g.smooth(4)
+    got = g.get_field(1)
+    assert np.abs(got - want).max() < 1e-11 * raw.max()
+    assert abs(got.sum() - raw.sum()) < 1e-11 * raw.sum()
+
+
+def test_short_trajectory(orc):
+    w = workloads.workload("small")
+    prm = w["params"]
+    st = orc.State(prm, w["x"], w["v"], w["w"], w["d"], w["rho"], U=w["U"], gradp=w["gradp"],
+                   dudt=w["dudt"])
+    st.average()
+    st.init_accel()
+    g = gpu_context(w)
+    g.average()
+    g.compute_forces(update_history=False)
+    nsteps = 40
+    st.run(nsteps, average_every=10)
+    g.step(nsteps, average_every=10)
+    p = g.get_particles()
+    dx = p["x"] - st.x
+    dx[:, 0] -= prm["Lx"] * np.round(dx[:, 0] / prm["Lx"])
+    dx[:, 1] -= prm["Ly"] * np.round(dx[:, 1] / prm["Ly"])
+    err = np.abs(dx).max() / workloads.D50
+    verr = np.abs(p["v"] - st.v).max() / (np.abs(st.v).max() + 1e-30)
+    print("trajectory after", nsteps, "steps: max |dx|/d", err, "max |dv|/|v|max", verr)
+    assert err < 1e-9
+    assert verr < 1e-7
+    smg = g.get_field(1)
+    assert np.abs(smg[0] - st.avg[0]).max() < 1e-6
+
+
+def test_history_survives_resort(orc):
+    """Force a rebuild every step (zero skin) and check history against the
+    oracle after several steps of a dense, sheared bed."""
+    case = dense_bed(2000, 9, jitter=0.001)
+    prm = dict(case["params"], dt=2e-6)
+    case = dict(case, params=prm)
+    st = orc.State(prm, case["x"], case["v"], case["w"], case["d"], case["rho"], U=case["U"],
+                   gradp=case["gradp"], dudt=case["dudt"])
+    st.init_accel()
+    g = gpu_context(case, skin_frac=0.0)
+    g.compute_forces(update_history=False)
+    st.run(5)
+    g.step(5)
+    assert g.stats()["rebuilds"] >= 5
+    gh = g.get_history()
+    oh = st.history()
+    assert np.array_equal(gh["i"], oh["i"]) and np.array_equal(gh["j"], oh["j"])
+    assert np.abs(gh["xi"] - oh["xi"]).max() < 1e-9 * np.abs(oh["xi"]).max()
