@@ -1,0 +1,151 @@
+"""Benchmark: particle-updates/s of the SediFoam particle step + plain
+diffusion averaging on one MI355X.
+
+A bench step is one pass of the hot path: 10 velocity-Verlet particle steps
+(neighbour binning/re-sort when due, contact + lubrication + fluid forces,
+integration) followed by one averaging (PCM deposition + implicit diffusion
+smoothing), as in the 1M-sphere bed workload (averaging every 10 steps).
+Inputs are seeded synthetic beds resident in HBM before the timed region.
+
+Prints one JSON line.  Extra objects: "roofline" (force kernel against the
+HBM peak, from HIP events on the library's stream), "cpu_baseline" (the FP64
+oracle on the host, a few steps of the same bed), "averaging" (plain solve
+timings) and "phases".
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-updates/s at 1M/10M particles; averaging ms plain vs surrogate"
+HBM_PEAK_GBS = 8000.0
+
+
+def force_bytes_per_particle(mean_nbr, mean_contacts, mixed):
+    """Algorithmic HBM bytes of one force-kernel launch per particle:
+    own state read (pos, vel, omg, acc: 4 x 32 B; id, count, mask: 12 B),
+    its neighbour indices (4 B each), read + write of the tangential history
+    of its active contacts (3 components), the state written back (vel, omg,
+    acc, alpha, drag: 5 x 32 B; mask 4 B).  Neighbour states are the same
+    arrays already counted once."""
+    hist = (12 if mixed else 24) * 2
+    return 140 + 4 * mean_nbr + hist * mean_contacts + 164
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed bench steps")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="bed1m")
+    ap.add_argument("--substeps", type=int, default=10)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path "
+              "has no multi-GPU mode", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1601_03801_amd as sm
+    import workloads
+
+    t0 = time.time()
+    w = workloads.workload(args.workload)
+    prm = dict(w["params"])
+    n = len(w["d"])
+    print(f"bench: workload {args.workload}: {n} spheres, mesh {w['meta']['mesh']}, "
+          f"generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    dmax = float(w["d"].max())
+    g = sm.Sedimi(prm, n, precision=args.precision, d_max=dmax, skin=0.1 * dmax,
+                  max_neighbors=24)
+    g.set_fluid(w["U"], w["gradp"], w["dudt"])
+    g.set_particles(w["x"], w["v"], w["d"], w["rho"], omega=w["w"])
+    g.average()
+    g.compute_forces(update_history=False)
+    K, W, S = args.steps, args.warmup, args.substeps
+    for _ in range(W):
+        g.step(S, average_every=S)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(K):
+        g.step(S, average_every=S)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    elapsed = t2 - t1
+    value = n * S * K / elapsed
+    print(f"bench: timed {K} bench steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    # per-phase device times (HIP events on the library's stream)
+    g.set_profiling(True)
+    for _ in range(max(2, K // 4)):
+        g.step(S, average_every=S)
+    prof = g.profile()
+    g.set_profiling(False)
+    st = g.stats()
+    f_ms, f_cnt = prof["forces"]
+    f_avg = f_ms / max(f_cnt, 1)
+    mixed = args.precision == "mixed"
+    bpp = force_bytes_per_particle(st["mean_neighbors"], st["mean_contacts"], mixed)
+    ncell = prm["nx"] * prm["ny"] * prm["nz"]
+    bytes_launch = n * bpp + ncell * (3 * 32 + 8)
+    achieved = bytes_launch / (f_avg * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_forces (step)", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "avg_launch_ms": round(f_avg, 5),
+                "bytes_per_launch": int(bytes_launch),
+                "bytes_per_particle": round(bpp, 1)}
+    phases = {k: {"ms_per_launch": round(v[0] / max(v[1], 1), 5), "launches": v[1]}
+              for k, v in prof.items()}
+    avg_ms = (prof["deposit"][0] + prof["smooth"][0]) / max(prof["smooth"][1], 1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ost = oracle.State(prm, w["x"], w["v"], w["w"], w["d"], w["rho"], U=w["U"],
+                           gradp=w["gradp"], dudt=w["dudt"])
+        ost.average()
+        ost.init_accel()
+        c0 = time.perf_counter()
+        ost.run(args.cpu_steps)
+        c1 = time.perf_counter()
+        cpu = {"value": round(n * args.cpu_steps / (c1 - c0), 1), "unit": "particle-updates/s",
+               "cores": 1, "kind": "oracle",
+               "sample": f"{args.cpu_steps} particle steps of the same {n}-sphere bed "
+                         f"({c1 - c0:.1f} s), no averaging"}
+        print(f"bench: oracle {args.cpu_steps} steps in {c1 - c0:.1f} s", file=sys.stderr,
+              flush=True)
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "particle-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(1000 * elapsed / K, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if not mixed else "f64-state/f32-forces", "data": "synthetic",
+        "config": {"workload": args.workload, "particles": n, "mesh": w["meta"]["mesh"],
+                   "substeps_per_step": S, "average_every": S, "dt": prm["dt"],
+                   "precision": args.precision, "bed_seed": w["meta"].get("bed_seed"),
+                   "field_seed": w["meta"].get("field_seed")},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "averaging": {"plain_ms": round(avg_ms, 4),
+                      "solve_iters": st["solve_iters"], "residual": st["solve_residual"]},
+        "phases": phases,
+        "stats": {"mean_neighbors": round(st["mean_neighbors"], 3),
+                  "mean_contacts": round(st["mean_contacts"], 3),
+                  "rebuilds": st["rebuilds"], "steps": st["steps"]},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

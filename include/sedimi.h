@@ -114,7 +114,21 @@ typedef struct {
   int32_t flags;          /* bit 0 slot overflow, 1 lost contact, 2 escape, 3 non-finite */
   int64_t solve_iters;    /* iterations of the last diffusion solve (all steps) */
   double solve_residual;  /* largest final relative residual of the last solve */
+  double mean_neighbors;  /* mean neighbour-list length per particle (now) */
+  double mean_contacts;   /* mean tangential-history slots in use per particle,
+                             walls included (now) */
 } sedimi_stats;
+
+/* Device time per phase of sedimi_step / sedimi_average, measured with HIP
+ * events recorded on the bound stream around each phase while profiling is
+ * on.  Phases: 0 half kick + drift, 1 neighbour-list rebuild chain (its
+ * kernels return at once when no rebuild is due), 2 force kernel, 3
+ * deposition, 4 diffusion solve. */
+#define SEDIMI_NPHASES 5
+typedef struct {
+  double ms[SEDIMI_NPHASES];
+  int64_t count[SEDIMI_NPHASES];
+} sedimi_profile;
 
 /* Create a context for up to max_particles particles.  Checks the parameters
  * (EINVAL with a message on failure).  No device memory is touched yet. */
@@ -177,6 +191,10 @@ int sedimi_get_pairs(sedimi_ctx* ctx, int64_t cap, int64_t* ij, int64_t* n_out);
 int sedimi_get_history(sedimi_ctx* ctx, int64_t cap, void* records, int64_t* n_out);
 int sedimi_set_history(sedimi_ctx* ctx, int64_t n, const void* records);
 int sedimi_get_stats(sedimi_ctx* ctx, sedimi_stats* out);
+/* Turn phase timing on (1) or off (0); turning it on clears the totals. */
+int sedimi_set_profiling(sedimi_ctx* ctx, int on);
+/* Totals since profiling was turned on (synchronises the stream). */
+int sedimi_get_profile(sedimi_ctx* ctx, sedimi_profile* out);
 
 #ifdef __cplusplus
 }

@@ -55,7 +55,16 @@ class sedimi_params(C.Structure):
 class sedimi_stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("rebuilds", C.c_int64), ("max_neighbors", C.c_int32),
                 ("flags", C.c_int32), ("solve_iters", C.c_int64),
-                ("solve_residual", C.c_double)]
+                ("solve_residual", C.c_double), ("mean_neighbors", C.c_double),
+                ("mean_contacts", C.c_double)]
+
+
+NPHASES = 5
+PHASES = ("drift", "rebuild", "forces", "deposit", "smooth")
+
+
+class sedimi_profile(C.Structure):
+    _fields_ = [("ms", C.c_double * NPHASES), ("count", C.c_int64 * NPHASES)]
 
 
 _lib = None
@@ -96,6 +105,8 @@ def lib():
         L.sedimi_get_history.argtypes = [P, i64, P, C.POINTER(i64)]
         L.sedimi_set_history.argtypes = [P, i64, P]
         L.sedimi_get_stats.argtypes = [P, C.POINTER(sedimi_stats)]
+        L.sedimi_set_profiling.argtypes = [P, I]
+        L.sedimi_get_profile.argtypes = [P, C.POINTER(sedimi_profile)]
         _lib = L
     return _lib
 
@@ -257,6 +268,15 @@ class Sedimi:
     def set_history(self, records):
         rec = np.ascontiguousarray(records, HISTORY_DTYPE)
         self._chk(self._L.sedimi_set_history(self._ctx, len(rec), _ptr(rec) if len(rec) else None))
+
+    def set_profiling(self, on=True):
+        self._chk(self._L.sedimi_set_profiling(self._ctx, 1 if on else 0))
+
+    def profile(self):
+        """{phase: (total ms, launches)} since profiling was turned on."""
+        p = sedimi_profile()
+        self._chk(self._L.sedimi_get_profile(self._ctx, C.byref(p)))
+        return {PHASES[k]: (p.ms[k], p.count[k]) for k in range(NPHASES)}
 
     def stats(self):
         s = sedimi_stats()

@@ -29,6 +29,20 @@ struct sedimi_ctx {
   int64_t last_iters = 0;
   double last_residual = 0.0;
   std::string err;
+  // phase timing
+  bool prof = false;
+  struct Mark {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[SEDIMI_NPHASES] = {0};
+  int64_t prof_count[SEDIMI_NPHASES] = {0};
+  ~sedimi_ctx() {
+    for (auto& m : marks) pool.push_back(m.a), pool.push_back(m.b);
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -233,11 +247,39 @@ int download(sedimi_ctx* c, std::vector<T>& h, const T* d, size_t count) {
   return SEDIMI_OK;
 }
 
+hipEvent_t take_event(sedimi_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Open / close a timed phase on the bound stream (no-ops unless profiling).
+void phase_begin(sedimi_ctx* c, int phase) {
+  if (!c->prof) return;
+  sedimi_ctx::Mark m{phase, take_event(c), take_event(c)};
+  if (m.a) (void)hipEventRecord(m.a, c->stream);
+  c->marks.push_back(m);
+}
+void phase_end(sedimi_ctx* c) {
+  if (!c->prof || c->marks.empty()) return;
+  if (c->marks.back().b) (void)hipEventRecord(c->marks.back().b, c->stream);
+}
+
 int64_t do_average(sedimi_ctx* c) {
+  phase_begin(c, 3);
   launch_deposit(c->P, c->A, c->stream);
+  phase_end(c);
   double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
-  return launch_smooth(c->P, c->A, 4, c->prm.avg_ntau, tau, c->prm.avg_rtol, c->mixed,
-                       c->stream);
+  phase_begin(c, 4);
+  int64_t it = launch_smooth(c->P, c->A, 4, c->prm.avg_ntau, tau, c->prm.avg_rtol, c->mixed,
+                             c->stream);
+  phase_end(c);
+  return it;
 }
 
 int check_solve(sedimi_ctx* c, int nch) {
@@ -415,9 +457,15 @@ int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
   if (nsteps < 0) return fail(c, SEDIMI_EINVAL, "nsteps must be >= 0");
   bool averaged = false;
   for (int s = 0; s < nsteps; ++s) {
+    phase_begin(c, 0);
     launch_kick_drift(c->P, c->A, c->stream);
+    phase_end(c);
+    phase_begin(c, 1);
     launch_rebuild(c->P, c->A, true, c->mixed, c->stream);
+    phase_end(c);
+    phase_begin(c, 2);
     launch_forces(c->P, c->A, c->A.smooth, 0, true, c->mixed, c->stream);
+    phase_end(c);
     std::swap(c->A.vel, c->A.vel_t);
     std::swap(c->A.omg, c->A.omg_t);
     ++c->step;
@@ -659,6 +707,51 @@ int sedimi_get_stats(sedimi_ctx* c, sedimi_stats* out) {
   out->flags = ctl.flags;
   out->solve_iters = c->last_iters;
   out->solve_residual = c->last_residual;
+  out->mean_neighbors = 0.0;
+  out->mean_contacts = 0.0;
+  if (c->have_particles && c->n > 0) {
+    const size_t n = (size_t)c->n;
+    std::vector<int> cnt;
+    std::vector<unsigned> mask;
+    std::vector<double4> wxi;
+    if ((rc = download(c, cnt, c->A.ncnt, n))) return rc;
+    if ((rc = download(c, mask, c->A.hmask, n))) return rc;
+    if ((rc = download(c, wxi, c->A.wxi, 2 * n))) return rc;
+    double sn = 0.0, sc = 0.0;
+    for (size_t q = 0; q < n; ++q) {
+      sn += cnt[q];
+      sc += __builtin_popcount(mask[q]) + (wxi[q].w != 0.0) + (wxi[n + q].w != 0.0);
+    }
+    out->mean_neighbors = sn / n;
+    out->mean_contacts = sc / n;
+  }
+  return SEDIMI_OK;
+}
+
+int sedimi_set_profiling(sedimi_ctx* c, int on) {
+  if (!c) return SEDIMI_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& m : c->marks) c->pool.push_back(m.a), c->pool.push_back(m.b);
+  c->marks.clear();
+  for (int k = 0; k < SEDIMI_NPHASES; ++k) c->prof_ms[k] = 0.0, c->prof_count[k] = 0;
+  c->prof = on != 0;
+  return SEDIMI_OK;
+}
+
+int sedimi_get_profile(sedimi_ctx* c, sedimi_profile* out) {
+  if (!c || !out) return SEDIMI_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& m : c->marks) {
+    float ms = 0.0f;
+    if (m.a && m.b && hipEventElapsedTime(&ms, m.a, m.b) == hipSuccess) {
+      c->prof_ms[m.phase] += ms;
+      c->prof_count[m.phase] += 1;
+    }
+    c->pool.push_back(m.a);
+    c->pool.push_back(m.b);
+  }
+  c->marks.clear();
+  for (int k = 0; k < SEDIMI_NPHASES; ++k) out->ms[k] = c->prof_ms[k], out->count[k] = c->prof_count[k];
   return SEDIMI_OK;
 }
 
