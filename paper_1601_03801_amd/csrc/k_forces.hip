@@ -120,15 +120,18 @@ __device__ __forceinline__ Interp interp_weights(const DevParams& P, double x, d
   return I;
 }
 
-// One wall of particle i: side -1 bottom (n = -z), +1 top (n = +z).
+// One wall of particle i: side -1 bottom (n = -z), +1 top (n = +z).  The
+// wall's history record is touched only when the particle is within the
+// lubrication range of the wall or its history is active (mask bit).
 template <typename R>
 __device__ __forceinline__ void wall(const DevParams& P, int side, double dist, double r,
-                                     double m, V3<R> v, V3<R> rw, double4& hist,
-                                     bool update, V3<R>& Fc, V3<R>& Fl, V3<R>& T) {
+                                     double m, V3<R> v, V3<R> rw, double4* hist, bool active,
+                                     bool update, unsigned bit, unsigned& mask_new, V3<R>& Fc,
+                                     V3<R>& Fl, V3<R>& T) {
   double dfull = 2.0 * r;
   double h = dist - r;
   if (!(h < P.lub_out * dfull)) {
-    if (update) hist.w = 0.0;
+    if (update && active) hist->w = 0.0;
     return;
   }
   V3<R> n{(R)0, (R)0, (R)side};
@@ -145,21 +148,31 @@ __device__ __forceinline__ void wall(const DevParams& P, int side, double dist, 
     R gn = (R)(2.0 * P.zeta) * sqrt((R)m * (R)P.kn);
     R gt = (R)P.gt_over_gn * gn;
     R Frep = (R)P.kn * (R)delta + gn * un;
-    V3<R> xi = hist.w != 0.0 ? cvt<R>(hist.x, hist.y, hist.z) : V3<R>{0, 0, 0};
+    V3<R> xi{0, 0, 0};
+    if (active) {
+      const double4 h0 = *hist;
+      xi = cvt<R>(h0.x, h0.y, h0.z);
+    }
     V3<R> ft = tangential<R>((R)P.kt, gt, (R)P.mu, (R)P.dt, n, vrel, un, fabs(Frep), xi);
     Fc = Fc + (ft - Frep * n);
     T = T + (R)r * cross(n, ft);
-    if (update) hist = make_double4((double)xi.x, (double)xi.y, (double)xi.z, 1.0);
-  } else if (update) {
-    hist.w = 0.0;
+    if (update) {
+      *hist = make_double4((double)xi.x, (double)xi.y, (double)xi.z, 1.0);
+      mask_new |= bit;
+    }
+  } else if (update && active) {
+    hist->w = 0.0;
   }
 }
 
+#ifndef SEDIMI_FORCE_WAVES
+#define SEDIMI_FORCE_WAVES 1
+#endif
+
 template <typename R, int MODE>
-__global__ __launch_bounds__(kBlock) void k_forces(DevParams P, DevArrays A,
-                                                   const double* __restrict__ eps_s,
-                                                   int update_history) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SEDIMI_FORCE_WAVES)))
+void k_forces(DevParams P, DevArrays A, int update_history) {
+  int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (i == 0 && A.ctl->rebuild) {
     A.ctl->rebuilds += 1;
     A.ctl->rebuild = 0;
@@ -245,29 +258,28 @@ __global__ __launch_bounds__(kBlock) void k_forces(DevParams P, DevArrays A,
     }
     T = T + Tp;
   }
-  if (upd) A.hmask[i] = mask_new;
-
-  // flat walls
+  // flat walls (history validity in mask bits 30 / 31)
   {
     const V3<R> v = cvt<R>(vi.x, vi.y, vi.z);
     const V3<R> rw = (R)ri * cvt<R>(wi.x, wi.y, wi.z);
-    if (P.bottom_wall) {
-      double4 h = A.wxi[i];
-      wall<R>(P, -1, pi.z, ri, mi, v, rw, h, upd, Fc, Fl, T);
-      if (upd) A.wxi[i] = h;
-    }
-    if (P.top_wall) {
-      double4 h = A.wxi[(size_t)N + i];
-      wall<R>(P, 1, P.Lz - pi.z, ri, mi, v, rw, h, upd, Fc, Fl, T);
-      if (upd) A.wxi[(size_t)N + i] = h;
-    }
+    if (P.bottom_wall)
+      wall<R>(P, -1, pi.z, ri, mi, v, rw, A.wxi + i, (mask_old >> 30) & 1u, upd, 1u << 30,
+              mask_new, Fc, Fl, T);
+    if (P.top_wall)
+      wall<R>(P, 1, P.Lz - pi.z, ri, mi, v, rw, A.wxi + (size_t)N + i, (mask_old >> 31) & 1u,
+              upd, 1u << 31, mask_new, Fc, Fl, T);
   }
+  if (upd) A.hmask[i] = mask_new;
 
-  // fluid-particle forces at the particle centre
+  // fluid-particle forces at the particle centre; U.w carries the averaged
+  // solid fraction; the step kernel reads the pressure-gradient and added-mass
+  // fields pre-combined as G = -grad p + C_add rho_f DU/Dt (both enter
+  // linearly with the particle volume).
   const double d = 2.0 * ri;
   const double Vp = (kPi / 6.0) * d * d * d;
   const Interp I = interp_weights(P, pi.x, pi.y, pi.z);
-  double Ux = 0, Uy = 0, Uz = 0, gpx = 0, gpy = 0, gpz = 0, dux = 0, duy = 0, duz = 0, es = 0;
+  double Ux = 0, Uy = 0, Uz = 0, es = 0;
+  double gpx = 0, gpy = 0, gpz = 0, dux = 0, duy = 0, duz = 0;
 #pragma unroll
   for (int q = 0; q < 8; ++q) {
     const double w = I.w[q];
@@ -275,16 +287,23 @@ __global__ __launch_bounds__(kBlock) void k_forces(DevParams P, DevArrays A,
     Ux += w * u.x;
     Uy += w * u.y;
     Uz += w * u.z;
+    es += w * u.w;
     if (P.fluid_forces) {
-      const double4 g = A.gp[I.idx[q]], m = A.du[I.idx[q]];
-      gpx += w * g.x;
-      gpy += w * g.y;
-      gpz += w * g.z;
-      dux += w * m.x;
-      duy += w * m.y;
-      duz += w * m.z;
+      if (MODE == 0) {
+        const double4 g = A.G[I.idx[q]];
+        gpx += w * g.x;
+        gpy += w * g.y;
+        gpz += w * g.z;
+      } else {
+        const double4 g = A.gp[I.idx[q]], m = A.du[I.idx[q]];
+        gpx += w * g.x;
+        gpy += w * g.y;
+        gpz += w * g.z;
+        dux += w * m.x;
+        duy += w * m.y;
+        duz += w * m.z;
+      }
     }
-    if (eps_s) es += w * eps_s[I.idx[q]];
   }
   es = es < 0.0 ? 0.0 : (es > P.eps_s_max ? P.eps_s_max : es);
   const V3<R> wrel = cvt<R>(Ux - vi.x, Uy - vi.y, Uz - vi.z);
@@ -292,9 +311,14 @@ __global__ __launch_bounds__(kBlock) void k_forces(DevParams P, DevArrays A,
   const V3<R> Fd = drag_coef<R>(P, (R)d, (R)(1.0 - es), wm) * wrel;
   V3<R> Fp{0, 0, 0}, Fa{0, 0, 0};
   if (P.fluid_forces) {
-    Fp = cvt<R>(-Vp * gpx, -Vp * gpy, -Vp * gpz);
     const double ca = P.c_add * P.rho_f * Vp;
-    Fa = cvt<R>(ca * (dux - ai.x), ca * (duy - ai.y), ca * (duz - ai.z));
+    if (MODE == 0) {
+      // pressure gradient + added mass together
+      Fp = cvt<R>(Vp * gpx - ca * ai.x, Vp * gpy - ca * ai.y, Vp * gpz - ca * ai.z);
+    } else {
+      Fp = cvt<R>(-Vp * gpx, -Vp * gpy, -Vp * gpz);
+      Fa = cvt<R>(ca * (dux - ai.x), ca * (duy - ai.y), ca * (duz - ai.z));
+    }
   }
   const V3<R> F = Fc + Fl + Fd + Fp + Fa;
   const double im = 1.0 / mi;
@@ -322,24 +346,36 @@ __global__ __launch_bounds__(kBlock) void k_forces(DevParams P, DevArrays A,
   }
 }
 
+// Solid fraction of the last averaging into U.w, where the force kernel reads it.
+__global__ void k_pack_eps(DevParams P, DevArrays A) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+  A.U[c].w = A.smooth[c];
+}
+
 }  // namespace
 
-void launch_forces(const DevParams& P, DevArrays& A, const double* eps_s, int mode,
-                   bool update_history, bool mixed, hipStream_t s) {
+void launch_forces(const DevParams& P, DevArrays& A, int mode, bool update_history,
+                   bool mixed, hipStream_t s) {
   if (P.n <= 0) return;
-  unsigned g = (unsigned)((P.n + kBlock - 1) / kBlock);
+  unsigned g = xcd_grid((P.n + kBlock - 1) / kBlock);
   int u = update_history ? 1 : 0;
   if (mixed) {
     if (mode == 0)
-      hipLaunchKernelGGL((k_forces<float, 0>), dim3(g), dim3(kBlock), 0, s, P, A, eps_s, u);
+      hipLaunchKernelGGL((k_forces<float, 0>), dim3(g), dim3(kBlock), 0, s, P, A, u);
     else
-      hipLaunchKernelGGL((k_forces<float, 1>), dim3(g), dim3(kBlock), 0, s, P, A, eps_s, u);
+      hipLaunchKernelGGL((k_forces<float, 1>), dim3(g), dim3(kBlock), 0, s, P, A, u);
   } else {
     if (mode == 0)
-      hipLaunchKernelGGL((k_forces<double, 0>), dim3(g), dim3(kBlock), 0, s, P, A, eps_s, u);
+      hipLaunchKernelGGL((k_forces<double, 0>), dim3(g), dim3(kBlock), 0, s, P, A, u);
     else
-      hipLaunchKernelGGL((k_forces<double, 1>), dim3(g), dim3(kBlock), 0, s, P, A, eps_s, u);
+      hipLaunchKernelGGL((k_forces<double, 1>), dim3(g), dim3(kBlock), 0, s, P, A, u);
   }
+}
+
+void launch_pack_eps(const DevParams& P, DevArrays& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_eps, dim3((P.ncell + kBlock - 1) / kBlock), dim3(kBlock), 0, s, P,
+                     A);
 }
 
 }  // namespace sedimi

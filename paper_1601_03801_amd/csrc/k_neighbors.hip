@@ -6,8 +6,10 @@
 // rebuild kernel reads that flag and returns at once when it is clear, so the
 // host can enqueue the whole chain every step without a round trip.
 //
-// Re-sort: counting sort by bin (integer atomics give the counts; the order
-// inside a bin is then fixed by sorting its few members by particle ID), so
+// Re-sort: counting sort by bin, the bins taken in Morton (Z-curve) order of
+// their 3-D coordinates so that spatial neighbours are also near in memory
+// (integer atomics give the counts; the order inside a bin is then fixed by
+// sorting its few members by particle ID), so
 // the sorted order, the neighbour order and hence all force sums are
 // deterministic.  The tangential history survives a re-sort as (partner ID,
 // xi) rows and is matched back onto the new list slots by partner ID.
@@ -98,7 +100,7 @@ __global__ void k_keys(DevParams P, DevArrays A) {
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P.n) return;
   double4 x = A.pos[p];
-  int b = bin_of(P, x.x, x.y, x.z);
+  int b = A.bin_rank[bin_of(P, x.x, x.y, x.z)];
   A.key[p] = b;
   A.rank[p] = atomicAdd(&A.bin_count[b], 1);
 }
@@ -181,7 +183,7 @@ __global__ void k_build(DevParams P, DevArrays A) {
       for (int dx = -1; dx <= 1; ++dx) {
         int cx = bx + dx;
         cx = cx < 0 ? cx + P.nbx : (cx >= P.nbx ? cx - P.nbx : cx);
-        int b = (cz * P.nby + cy) * P.nbx + cx;
+        int b = A.bin_rank[(cz * P.nby + cy) * P.nbx + cx];
         int s = A.bin_start[b], e = A.bin_start[b + 1];
         for (int j = s; j < e; ++j) {
           if (j == q) continue;
@@ -230,6 +232,8 @@ __global__ void k_build(DevParams P, DevArrays A) {
       }
     }
   }
+  if (A.wxi[q].w != 0.0) mask |= 1u << 30;
+  if (A.wxi[(size_t)N + q].w != 0.0) mask |= 1u << 31;
   A.hmask[q] = mask;
   if (matched != nc) atomicOr(&A.ctl->flags, 2);
 }

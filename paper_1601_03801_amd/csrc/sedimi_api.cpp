@@ -120,6 +120,7 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
   a.U = w.take<double4>(nc);
   a.gp = w.take<double4>(nc);
   a.du = w.take<double4>(nc);
+  a.G = w.take<double4>(nc);
   a.raw = w.take<double>(4 * nc);
   a.smooth = w.take<double>(4 * nc);
   a.sx = w.take<double>(4 * nc);
@@ -129,6 +130,8 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
   a.cell_count = w.take<int>(nc + 1);
   a.cell_start = w.take<int>(nc + 1);
   a.red = w.take<double>(smooth_red_doubles((int)nc, 4, std::max(1, c->prm.avg_ntau)));
+  // kept across sedimi_set_particles (which clears everything before U)
+  a.bin_rank = w.take<int>(nb);
   a.ctl = w.take<Ctl>(1);
   if (A) *A = a;
   return align256(w.off);
@@ -278,6 +281,7 @@ int64_t do_average(sedimi_ctx* c) {
   phase_begin(c, 4);
   int64_t it = launch_smooth(c->P, c->A, 4, c->prm.avg_ntau, tau, c->prm.avg_rtol, c->mixed,
                              c->stream);
+  launch_pack_eps(c->P, c->A, c->stream);
   phase_end(c);
   return it;
 }
@@ -335,6 +339,27 @@ int sedimi_bind_workspace(sedimi_ctx* c, void* dev_ptr, size_t bytes) {
   c->ws = (char*)dev_ptr;
   layout(c, c->ws, &c->A);
   HIPCHK(c, hipMemsetAsync(c->ws, 0, c->ws_bytes, c->stream));
+  {
+    // Morton rank of every bin: interleave the bits of (bx, by, bz)
+    const DevParams& P = c->P;
+    std::vector<std::pair<uint64_t, int>> code((size_t)P.nbins);
+    auto spread = [](uint64_t v) {
+      uint64_t r = 0;
+      for (int b = 0; b < 21; ++b) r |= ((v >> b) & 1ull) << (3 * b);
+      return r;
+    };
+    for (int bz = 0; bz < P.nbz; ++bz)
+      for (int by = 0; by < P.nby; ++by)
+        for (int bx = 0; bx < P.nbx; ++bx) {
+          int b = (bz * P.nby + by) * P.nbx + bx;
+          code[b] = {spread(bx) | (spread(by) << 1) | (spread(bz) << 2), b};
+        }
+    std::sort(code.begin(), code.end());
+    std::vector<int> rank((size_t)P.nbins);
+    for (int r = 0; r < P.nbins; ++r) rank[code[r].second] = r;
+    HIPCHK(c, hipMemcpyAsync(c->A.bin_rank, rank.data(), sizeof(int) * rank.size(),
+                             hipMemcpyHostToDevice, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->have_particles = false;
   return SEDIMI_OK;
@@ -404,6 +429,20 @@ int sedimi_set_fluid(sedimi_ctx* c, const double* U, const double* gp, const dou
     HIPCHK(c, hipMemcpyAsync(dst[f], h.data(), sizeof(double4) * nc, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
+  // G = -grad p + C_add rho_f DU/Dt, the combination the step kernel reads
+  const double ca = c->prm.c_add * c->prm.rho_f;
+  for (int k = 0; k < nc; ++k) {
+    double g[3], m[3];
+    for (int a = 0; a < 3; ++a) {
+      g[a] = gp ? gp[3 * k + a] : 0.0;
+      m[a] = du ? du[3 * k + a] : 0.0;
+    }
+    h[k] = make_double4(-g[0] + ca * m[0], -g[1] + ca * m[1], -g[2] + ca * m[2], 0.0);
+  }
+  HIPCHK(c, hipMemcpyAsync(c->A.G, h.data(), sizeof(double4) * nc, hipMemcpyHostToDevice, c->stream));
+  launch_pack_eps(c->P, c->A, c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return SEDIMI_OK;
 }
 
@@ -414,6 +453,8 @@ int sedimi_set_field(sedimi_ctx* c, int field, const double* in) {
     return fail(c, SEDIMI_EINVAL, "bad field");
   double* dst = field == SEDIMI_FIELD_RAW ? c->A.raw : c->A.smooth;
   HIPCHK(c, hipMemcpyAsync(dst, in, sizeof(double) * 4 * c->P.ncell, hipMemcpyHostToDevice, c->stream));
+  if (field == SEDIMI_FIELD_SMOOTH) launch_pack_eps(c->P, c->A, c->stream);
+  HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return SEDIMI_OK;
 }
@@ -443,7 +484,7 @@ int sedimi_set_accel(sedimi_ctx* c, const double* a, const double* alpha) {
 int sedimi_compute_forces(sedimi_ctx* c, int update_history) {
   int rc = need_particles(c);
   if (rc) return rc;
-  launch_forces(c->P, c->A, c->A.smooth, 1, update_history != 0, c->mixed, c->stream);
+  launch_forces(c->P, c->A, 1, update_history != 0, c->mixed, c->stream);
   HIPCHK(c, hipGetLastError());
   Ctl ctl;
   rc = read_ctl(c, &ctl);
@@ -464,7 +505,7 @@ int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
     launch_rebuild(c->P, c->A, true, c->mixed, c->stream);
     phase_end(c);
     phase_begin(c, 2);
-    launch_forces(c->P, c->A, c->A.smooth, 0, true, c->mixed, c->stream);
+    launch_forces(c->P, c->A, 0, true, c->mixed, c->stream);
     phase_end(c);
     std::swap(c->A.vel, c->A.vel_t);
     std::swap(c->A.omg, c->A.omg_t);
@@ -508,6 +549,7 @@ int sedimi_smooth(sedimi_ctx* c, int nch) {
   double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
   c->last_iters = launch_smooth(c->P, c->A, nch, c->prm.avg_ntau, tau, c->prm.avg_rtol,
                                 c->mixed, c->stream);
+  launch_pack_eps(c->P, c->A, c->stream);
   HIPCHK(c, hipGetLastError());
   return check_solve(c, nch);
 }
@@ -720,7 +762,7 @@ int sedimi_get_stats(sedimi_ctx* c, sedimi_stats* out) {
     double sn = 0.0, sc = 0.0;
     for (size_t q = 0; q < n; ++q) {
       sn += cnt[q];
-      sc += __builtin_popcount(mask[q]) + (wxi[q].w != 0.0) + (wxi[n + q].w != 0.0);
+      sc += __builtin_popcount(mask[q]);  // list slots and the two wall bits
     }
     out->mean_neighbors = sn / n;
     out->mean_contacts = sc / n;

@@ -12,7 +12,8 @@
 //   neighbour list (full: each pair appears on both sides), slot-major so that
 //   slot k of consecutive particles is contiguous:
 //     nbr   int32 [maxn][N], ncnt int32 [N]
-//     hmask uint32 [N]   bit k set = slot k carries tangential history
+//     hmask uint32 [N]   bit k set = slot k carries tangential history;
+//                        bits 30 / 31: bottom / top wall history active
 //     hxi   3 x [maxn][N] history of slot k (double, or float in mixed mode),
 //           oriented from the lower to the higher particle ID
 //   compact history (partner ID + xi per contact) used across a re-sort:
@@ -32,7 +33,17 @@ namespace sedimi {
 
 constexpr int kBlock = 256;
 constexpr int kMaxContacts = 16;  // contacts per particle kept across a re-sort
-constexpr uint32_t kCtlRebuild = 0;
+
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Renumber them so that every XCD works through one contiguous range of
+// particles; launch grids rounded up to a multiple of 8.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int nblocks8) {
+  return (b % kXcds) * (nblocks8 / kXcds) + b / kXcds;
+}
+inline unsigned xcd_grid(int64_t nblocks) {
+  return (unsigned)((nblocks + kXcds - 1) / kXcds * kXcds);
+}
 
 // Flags and counters living in device memory.
 struct Ctl {
@@ -78,8 +89,10 @@ struct DevArrays {
   double4* comp;
   // sort scratch
   int *key, *rank, *perm, *bin_count, *bin_start, *scan_tmp;
+  int* bin_rank;  // Morton rank of each bin (bins are stored in this order)
   // mesh
-  double4 *U, *gp, *du;
+  double4 *U, *gp, *du;  // U.w = averaged solid fraction
+  double4* G;            // -grad p + C_add rho_f DU/Dt (step kernel)
   double *raw, *smooth, *sx, *sr, *sd0, *sd1;
   int *cell_count, *cell_start, *cperm;
   double* red;  // reduction partials
@@ -98,8 +111,10 @@ void launch_exclusive_scan(int* in_out_count, int* start, int n, int* tmp, bool 
 // ---- launchers (k_forces.hip) ----
 // mode: 0 = step (second half kick, writes vel_t/omg_t), 1 = evaluation with
 // breakdown (writes comp, acc, alp); update_history as in sedimi_compute_forces.
-void launch_forces(const DevParams& P, DevArrays& A, const double* eps_s, int mode,
-                   bool update_history, bool mixed, hipStream_t s);
+void launch_forces(const DevParams& P, DevArrays& A, int mode, bool update_history,
+                   bool mixed, hipStream_t s);
+// Copy channel 0 of the smoothed field (solid fraction) into U.w.
+void launch_pack_eps(const DevParams& P, DevArrays& A, hipStream_t s);
 
 // ---- launchers (k_average.hip) ----
 void launch_deposit(const DevParams& P, DevArrays& A, hipStream_t s);
