@@ -101,14 +101,18 @@ def lib():
 
 
 def _declare_cnn(L):
-    P = C.c_void_p
-    i = C.c_int
-    L.orc_conv3d_fwd.argtypes = [i, i, i, i, i, i, i, P, P, P, P]
+    P, i, d, i64 = C.c_void_p, C.c_int, C.c_double, C.c_int64
+    L.orc_conv3d_fwd.argtypes = [i, i, i, i, i, i, P, P, P, P]
     L.orc_conv3d_fwd.restype = None
-    L.orc_conv3d_bwd.argtypes = [i, i, i, i, i, i, i, P, P, P, P, P, P]
+    L.orc_conv3d_bwd.argtypes = [i, i, i, i, i, i, P, P, P, P, P, P]
     L.orc_conv3d_bwd.restype = None
-    L.orc_adam.argtypes = [C.c_int64, P, P, P, P, C.c_double, C.c_double, C.c_double,
-                           C.c_double, C.c_int64]
+    L.orc_nn_param_count.argtypes = [i]
+    L.orc_nn_param_count.restype = i64
+    L.orc_nn_forward.argtypes = [i, i, i, i, d, i, P, P, P, P]
+    L.orc_nn_forward.restype = None
+    L.orc_nn_loss_grad.argtypes = [i, i, i, i, d, i, P, P, P, P]
+    L.orc_nn_loss_grad.restype = d
+    L.orc_adam.argtypes = [i64, P, P, P, P, d, d, d, d, i64]
     L.orc_adam.restype = None
 
 
@@ -283,3 +287,61 @@ def apply_A(prm, dtau, x):
     y = np.zeros_like(x)
     lib().orc_apply_A(C.byref(p), float(dtau), _ptr(x), _ptr(y))
     return y
+
+
+# ---------------------------------------------------------------------------
+# learned stand-in for the diffusion averaging (orc_cnn.c)
+# ---------------------------------------------------------------------------
+NN_DILATIONS = (1, 2, 4, 4, 2, 1)
+
+
+def conv3d_fwd(shape, x, w, b, dil):
+    """shape = (nx, ny, nz); x [n, cin]; w [27, cin, cout]; b [cout] or None."""
+    nx, ny, nz = shape
+    x = _f64(x)
+    w = _f64(w)
+    cin, cout = w.shape[1], w.shape[2]
+    y = np.zeros((nx * ny * nz, cout))
+    bb = None if b is None else _f64(b)
+    lib().orc_conv3d_fwd(nx, ny, nz, cin, cout, dil, _ptr(x), _ptr(w), _ptr(bb), _ptr(y))
+    return y
+
+
+def conv3d_bwd(shape, x, w, dy, dil):
+    nx, ny, nz = shape
+    x, w, dy = _f64(x), _f64(w), _f64(dy)
+    cin, cout = w.shape[1], w.shape[2]
+    dx = np.zeros((nx * ny * nz, cin))
+    dw = np.zeros_like(w)
+    db = np.zeros(cout)
+    lib().orc_conv3d_bwd(nx, ny, nz, cin, cout, dil, _ptr(x), _ptr(w), _ptr(dy), _ptr(dx),
+                         _ptr(dw), _ptr(db))
+    return dx, dw, db
+
+
+def nn_param_count(C=32):
+    return int(lib().orc_nn_param_count(C))
+
+
+def nn_forward(shape, params, x, C=32, alpha=0.1, bf16=False):
+    nx, ny, nz = shape
+    params, x = _f64(params), _f64(x)
+    y = np.zeros((nx * ny * nz, 4))
+    lib().orc_nn_forward(nx, ny, nz, C, alpha, 1 if bf16 else 0, _ptr(params), _ptr(x),
+                         _ptr(y), None)
+    return y
+
+
+def nn_loss_grad(shape, params, x, target, C=32, alpha=0.1, bf16=False):
+    nx, ny, nz = shape
+    params, x, target = _f64(params), _f64(x), _f64(target)
+    g = np.zeros_like(params)
+    loss = lib().orc_nn_loss_grad(nx, ny, nz, C, alpha, 1 if bf16 else 0, _ptr(params),
+                                  _ptr(x), _ptr(target), _ptr(g))
+    return loss, g
+
+
+def adam(w, m, v, g, lr, t, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays w, m, v."""
+    g = _f64(g)
+    lib().orc_adam(len(w), _ptr(w), _ptr(m), _ptr(v), _ptr(g), lr, b1, b2, eps, int(t))
