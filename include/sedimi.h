@@ -105,7 +105,19 @@ typedef struct {
   double skin;               /* neighbour-list skin (m); the list is rebuilt when any
                                 particle has moved skin/2 since the last build */
   int max_neighbors;         /* neighbour slots per particle, 1..30 */
+  /* learned stand-in for the diffusion averaging (not part of the paper) */
+  int nn_enable;             /* 1: allocate the 6-layer, 32-channel 3-D CNN */
+  double nn_alpha;           /* leaky-ReLU slope for negative arguments */
+  double nn_bound;           /* fallback when the sampled relative residual exceeds this */
+  double nn_sample;          /* fraction of cells in the residual sample */
+  uint64_t nn_seed;          /* seed of the residual sample */
 } sedimi_params;
+
+/* averaging modes (sedimi_set_avg_mode) */
+#define SEDIMI_AVG_PLAIN 0             /* deposition + implicit diffusion solve */
+#define SEDIMI_AVG_SURROGATE_CHECKED 1 /* network, sampled residual check, plain
+                                          solve when the check fails */
+#define SEDIMI_AVG_SURROGATE 2         /* network only */
 
 typedef struct {
   int64_t steps;          /* steps taken since sedimi_set_particles */
@@ -117,14 +129,17 @@ typedef struct {
   double mean_neighbors;  /* mean neighbour-list length per particle (now) */
   double mean_contacts;   /* mean tangential-history slots in use per particle,
                              walls included (now) */
+  int64_t nn_calls;       /* averagings answered by the network (checked or not) */
+  int64_t nn_fallbacks;   /* checked averagings that fell back to the plain solve */
+  double nn_last_check;   /* largest per-channel relative residual of the last check */
 } sedimi_stats;
 
 /* Device time per phase of sedimi_step / sedimi_average, measured with HIP
  * events recorded on the bound stream around each phase while profiling is
  * on.  Phases: 0 half kick + drift, 1 neighbour-list rebuild chain (its
  * kernels return at once when no rebuild is due), 2 force kernel, 3
- * deposition, 4 diffusion solve. */
-#define SEDIMI_NPHASES 5
+ * deposition, 4 diffusion solve (or network + check), 5 network training step. */
+#define SEDIMI_NPHASES 6
 typedef struct {
   double ms[SEDIMI_NPHASES];
   int64_t count[SEDIMI_NPHASES];
@@ -191,6 +206,40 @@ int sedimi_get_pairs(sedimi_ctx* ctx, int64_t cap, int64_t* ij, int64_t* n_out);
 int sedimi_get_history(sedimi_ctx* ctx, int64_t cap, void* records, int64_t* n_out);
 int sedimi_set_history(sedimi_ctx* ctx, int64_t n, const void* records);
 int sedimi_get_stats(sedimi_ctx* ctx, sedimi_stats* out);
+/* Averaging mode used by sedimi_average and by the averaging inside
+ * sedimi_step (SEDIMI_AVG_*; the surrogate modes need nn_enable). */
+int sedimi_set_avg_mode(sedimi_ctx* ctx, int mode);
+
+/* ---- learned stand-in for the diffusion averaging ----
+ * A 6-layer 3-D CNN (3x3x3 taps; z dilations 1, 2, 4, 4, 2, 1; 32 channels;
+ * layer 1: 4 -> 32, layers 2-5: 32 -> 32 with identity skips, layer 6: 32 -> 4;
+ * leaky ReLU; output = input + network) mapping the deposited fields to the
+ * smoothed ones in per-channel normalised units; periodic in x, y and zero
+ * padded in z.  BF16 weights and activations, FP32 accumulation and output.
+ * Parameters are a flat FP32 vector: per layer w[27][cin][cout] then b[cout],
+ * tap t = (dz+1)*9 + (dy+1)*3 + (dx+1).  The plain solve stays the fallback:
+ * a checked averaging accepts the network's field y only if, on the seeded
+ * sample of cells, |A^ntau y - raw| / |y| <= nn_bound for every channel
+ * (A = I - dtau L_h, the implicit step's operator; its inverse has norm <= 1,
+ * so the residual bounds the error against the plain solve). */
+int sedimi_nn_param_count(const sedimi_ctx* ctx, int64_t* n);
+/* He-normal initial weights (seeded), zero last layer and biases, zero Adam moments. */
+int sedimi_nn_init(sedimi_ctx* ctx, uint64_t seed);
+int sedimi_nn_set_params(sedimi_ctx* ctx, const float* p, int64_t n);
+int sedimi_nn_get_params(sedimi_ctx* ctx, float* p, int64_t n);
+/* Gradient of the loss from the last sedimi_nn_train_step (same layout). */
+int sedimi_nn_get_grads(sedimi_ctx* ctx, float* g, int64_t n);
+/* Per-channel normalisation x_n = (x - mean) / std of inputs and targets. */
+int sedimi_nn_set_norm(sedimi_ctx* ctx, const double* mean4, const double* std4);
+/* SMOOTH <- network(RAW) (no check). */
+int sedimi_nn_forward(sedimi_ctx* ctx);
+/* One Adam step (lr; beta 0.9 / 0.999; eps 1e-8) on the mean-squared error
+ * between network(RAW) and SMOOTH in normalised units; *loss (may be NULL)
+ * receives the loss before the step.  RAW and SMOOTH are not modified. */
+int sedimi_nn_train_step(sedimi_ctx* ctx, double lr, double* loss);
+/* Sampled relative residual of SMOOTH against RAW, per channel (rel4[4]). */
+int sedimi_nn_check(sedimi_ctx* ctx, double* rel4);
+
 /* Turn phase timing on (1) or off (0); turning it on clears the totals. */
 int sedimi_set_profiling(sedimi_ctx* ctx, int on);
 /* Totals since profiling was turned on (synchronises the stream). */

@@ -49,6 +49,8 @@ class sedimi_params(C.Structure):
         ("avg_bandwidth", C.c_double), ("avg_ntau", C.c_int), ("avg_rtol", C.c_double),
         ("precision", C.c_int),
         ("d_max", C.c_double), ("skin", C.c_double), ("max_neighbors", C.c_int),
+        ("nn_enable", C.c_int), ("nn_alpha", C.c_double), ("nn_bound", C.c_double),
+        ("nn_sample", C.c_double), ("nn_seed", C.c_uint64),
     ]
 
 
@@ -56,11 +58,13 @@ class sedimi_stats(C.Structure):
     _fields_ = [("steps", C.c_int64), ("rebuilds", C.c_int64), ("max_neighbors", C.c_int32),
                 ("flags", C.c_int32), ("solve_iters", C.c_int64),
                 ("solve_residual", C.c_double), ("mean_neighbors", C.c_double),
-                ("mean_contacts", C.c_double)]
+                ("mean_contacts", C.c_double), ("nn_calls", C.c_int64),
+                ("nn_fallbacks", C.c_int64), ("nn_last_check", C.c_double)]
 
 
-NPHASES = 5
-PHASES = ("drift", "rebuild", "forces", "deposit", "smooth")
+NPHASES = 6
+PHASES = ("drift", "rebuild", "forces", "deposit", "smooth", "nn_train")
+AVG_PLAIN, AVG_SURROGATE_CHECKED, AVG_SURROGATE = 0, 1, 2
 
 
 class sedimi_profile(C.Structure):
@@ -106,13 +110,24 @@ def lib():
         L.sedimi_set_history.argtypes = [P, i64, P]
         L.sedimi_get_stats.argtypes = [P, C.POINTER(sedimi_stats)]
         L.sedimi_set_profiling.argtypes = [P, I]
+        L.sedimi_set_avg_mode.argtypes = [P, I]
+        L.sedimi_nn_param_count.argtypes = [P, C.POINTER(i64)]
+        L.sedimi_nn_init.argtypes = [P, C.c_uint64]
+        L.sedimi_nn_set_params.argtypes = [P, P, i64]
+        L.sedimi_nn_get_params.argtypes = [P, P, i64]
+        L.sedimi_nn_get_grads.argtypes = [P, P, i64]
+        L.sedimi_nn_set_norm.argtypes = [P, P, P]
+        L.sedimi_nn_forward.argtypes = [P]
+        L.sedimi_nn_train_step.argtypes = [P, C.c_double, C.POINTER(C.c_double)]
+        L.sedimi_nn_check.argtypes = [P, P]
         L.sedimi_get_profile.argtypes = [P, C.POINTER(sedimi_profile)]
         _lib = L
     return _lib
 
 
 def make_params(prm: dict, precision="fp64", skin=None, max_neighbors=24, d_max=None,
-                avg_rtol=1e-12) -> sedimi_params:
+                avg_rtol=1e-12, nn=False, nn_alpha=0.1, nn_bound=1e-3, nn_sample=0.01,
+                nn_seed=12345) -> sedimi_params:
     """sedimi_params from a parameter dict (the oracle's keys plus options)."""
     p = sedimi_params()
     for name, _ in sedimi_params._fields_:
@@ -129,6 +144,11 @@ def make_params(prm: dict, precision="fp64", skin=None, max_neighbors=24, d_max=
     p.d_max = dm
     p.skin = prm.get("skin", 0.1 * dm if skin is None else skin)
     p.max_neighbors = prm.get("max_neighbors", max_neighbors)
+    p.nn_enable = 1 if prm.get("nn", nn) else 0
+    p.nn_alpha = prm.get("nn_alpha", nn_alpha)
+    p.nn_bound = prm.get("nn_bound", nn_bound)
+    p.nn_sample = prm.get("nn_sample", nn_sample)
+    p.nn_seed = prm.get("nn_seed", nn_seed)
     return p
 
 
@@ -268,6 +288,49 @@ class Sedimi:
     def set_history(self, records):
         rec = np.ascontiguousarray(records, HISTORY_DTYPE)
         self._chk(self._L.sedimi_set_history(self._ctx, len(rec), _ptr(rec) if len(rec) else None))
+
+    def set_avg_mode(self, mode):
+        self._chk(self._L.sedimi_set_avg_mode(self._ctx, int(mode)))
+
+    # -- learned stand-in for the averaging --
+    def nn_param_count(self):
+        n = C.c_int64(0)
+        self._chk(self._L.sedimi_nn_param_count(self._ctx, C.byref(n)))
+        return n.value
+
+    def nn_init(self, seed=0):
+        self._chk(self._L.sedimi_nn_init(self._ctx, int(seed)))
+
+    def nn_set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        self._chk(self._L.sedimi_nn_set_params(self._ctx, _ptr(p), len(p)))
+
+    def nn_get_params(self):
+        p = np.zeros(self.nn_param_count(), np.float32)
+        self._chk(self._L.sedimi_nn_get_params(self._ctx, _ptr(p), len(p)))
+        return p
+
+    def nn_get_grads(self):
+        g = np.zeros(self.nn_param_count(), np.float32)
+        self._chk(self._L.sedimi_nn_get_grads(self._ctx, _ptr(g), len(g)))
+        return g
+
+    def nn_set_norm(self, mean, std):
+        mean, std = _f64(mean), _f64(std)
+        self._chk(self._L.sedimi_nn_set_norm(self._ctx, _ptr(mean), _ptr(std)))
+
+    def nn_forward(self):
+        self._chk(self._L.sedimi_nn_forward(self._ctx))
+
+    def nn_train_step(self, lr):
+        loss = C.c_double(0.0)
+        self._chk(self._L.sedimi_nn_train_step(self._ctx, float(lr), C.byref(loss)))
+        return loss.value
+
+    def nn_check(self):
+        rel = np.zeros(4)
+        self._chk(self._L.sedimi_nn_check(self._ctx, _ptr(rel)))
+        return rel
 
     def set_profiling(self, on=True):
         self._chk(self._L.sedimi_set_profiling(self._ctx, 1 if on else 0))

@@ -172,9 +172,91 @@ __global__ void k_residual(Stencil S, const T* __restrict__ b, const T* __restri
   }
 }
 
+// out = A in for every channel (blockIdx.y).
+__global__ void k_applyA(Stencil S, const double* __restrict__ in, double* __restrict__ out) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= S.ncell) return;
+  size_t off = (size_t)blockIdx.y * S.ncell;
+  out[off + c] = apply_A<double>(S, in + off, c);
+}
+
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Residual of a smoothed field y against the deposited field on a seeded
+// sample of cells: r = Ay - raw with Ay = A^ntau y.  Per-block FP64 sums of
+// r^2 and y^2 for each of the 4 channels (8 values per block).
+__global__ void k_check(int ncell, const double* __restrict__ Ay, const double* __restrict__ raw,
+                        const double* __restrict__ y, uint64_t seed, uint64_t thresh,
+                        double* __restrict__ part) {
+  __shared__ double s[8][kBlock];
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (c < ncell && splitmix64(seed ^ (uint64_t)c) < thresh) {
+    for (int ch = 0; ch < 4; ++ch) {
+      size_t o = (size_t)ch * ncell + c;
+      double r = Ay[o] - raw[o];
+      v[ch] = r * r;
+      v[4 + ch] = y[o] * y[o];
+    }
+  }
+  for (int q = 0; q < 8; ++q) s[q][threadIdx.x] = v[q];
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int q = 0; q < 8; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 8; ++q) part[(size_t)blockIdx.x * 8 + q] = s[q][0];
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
+
+int launch_check(const DevParams& P, DevArrays& A, const double* y, int ntau, double tau,
+                 uint64_t seed, double frac, hipStream_t s) {
+  Stencil S;
+  S.nx = P.nx, S.ny = P.ny, S.nz = P.nz, S.ncell = P.ncell;
+  double dtau = tau / (ntau > 0 ? ntau : 1);
+  S.cx = dtau / (P.hx * P.hx);
+  S.cy = dtau / (P.hy * P.hy);
+  S.cz = dtau / (P.hz * P.hz);
+  dim3 grid(nblk(P.ncell), 4);
+  const double* cur = y;
+  double* bufs[2] = {A.sd0, A.sd1};
+  for (int m = 0; m < ntau; ++m) {
+    hipLaunchKernelGGL(k_applyA, grid, dim3(kBlock), 0, s, S, cur, bufs[m & 1]);
+    cur = bufs[m & 1];
+  }
+  double f = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
+  uint64_t thresh = f >= 1.0 ? ~0ull : (uint64_t)(f * 18446744073709551616.0);
+  hipLaunchKernelGGL(k_check, dim3(nblk(P.ncell)), dim3(kBlock), 0, s, P.ncell, cur, A.raw, y,
+                     seed, thresh, A.red);
+  return (int)nblk(P.ncell);
+}
+
+int read_check(DevArrays& A, int nblocks, double rel[4], hipStream_t s) {
+  std::vector<double> h((size_t)nblocks * 8);
+  if (hipMemcpyAsync(h.data(), A.red, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
+    return -1;
+  if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  for (int ch = 0; ch < 4; ++ch) {
+    double rr = 0.0, yy = 0.0;
+    for (int b = 0; b < nblocks; ++b) {
+      rr += h[(size_t)b * 8 + ch];
+      yy += h[(size_t)b * 8 + 4 + ch];
+    }
+    rel[ch] = yy > 0.0 ? sqrt(rr / yy) : sqrt(rr);
+  }
+  return 0;
+}
 
 void launch_deposit(const DevParams& P, DevArrays& A, hipStream_t s) {
   launch_zero_ints(A.cell_count, P.ncell, false, A.ctl, s);

@@ -1,0 +1,402 @@
+// k_nn.hip -- learned stand-in for the diffusion averaging: a 6-layer 3-D
+// convolutional network (3x3x3 taps, z dilations 1,2,4,4,2,1, 32 channels,
+// residual layers, leaky ReLU, global residual) with BF16 weights and
+// activations, FP32 accumulation on the MFMA units, FP32 output.
+//
+// Convolution as an implicit GEMM on v_mfma_f32_16x16x32_bf16: one wave
+// computes a tile of 16 consecutive cells (M) by 16 output channels (N) per
+// MFMA; K runs over (tap, input channel).  Activations are stored
+// channel-last, so the A fragment of a tap (8 consecutive input channels of
+// one neighbour cell per lane) is a single 16-byte load; the layer's weights
+// sit in LDS in the order the B fragments are read.  With 32 input channels
+// one tap is exactly one K step; with 4 input channels two taps share a lane
+// group and K is padded from 108 to 128.
+//
+// The data gradient of a convolution is the same kernel run with the tap
+// offsets negated and the weights transposed; the weight gradient is a GEMM
+// over cells (K = cells) whose operands are staged through LDS transposed to
+// [channel][cell], with per-block partial sums reduced in a fixed order.
+#include <math.h>
+
+#include "k_nn.h"
+
+namespace sedimi {
+
+namespace {
+
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float leaky(float z, float a) { return z > 0.0f ? z : a * z; }
+__device__ __forceinline__ float dleaky(float z, float a) { return z > 0.0f ? 1.0f : a; }
+__device__ __forceinline__ float bf(float v) { return (float)(__bf16)v; }
+
+// Neighbour cell of (i, j, k) for tap t (offsets negated when neg != 0);
+// -1 when the z index leaves the mesh (zero padding); periodic in x and y.
+__device__ __forceinline__ int tap_cell(const ConvGeom& g, int i, int j, int k, int t) {
+  int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+  if (g.neg) dz = -dz, dy = -dy, dx = -dx;
+  int kk = k + g.dil * dz;
+  if (kk < 0 || kk >= g.nz) return -1;
+  int ii = i + dx;
+  ii = ii < 0 ? ii + g.nx : (ii >= g.nx ? ii - g.nx : ii);
+  int jj = j + dy;
+  jj = jj < 0 ? jj + g.ny : (jj >= g.ny ? jj - g.ny : jj);
+  return (kk * g.ny + jj) * g.nx + ii;
+}
+
+// Weights in LDS, layout for CIN = 32: [27][NT*16][32]; for CIN = 4:
+// [NT*16][128] with k = tap*4 + channel (zero beyond 108).
+template <int CIN, int COUT>
+struct WShape {
+  static constexpr int NT = (COUT + 15) / 16;
+  static constexpr int elems = CIN == 32 ? 27 * NT * 16 * 32 : NT * 16 * 128;
+};
+
+template <int CIN, int COUT, int EPI>
+__global__ __launch_bounds__(256) void k_conv(ConvGeom g, const __bf16* __restrict__ in,
+                                              const __bf16* __restrict__ wpk,
+                                              const float* __restrict__ bias, EpiArgs e) {
+  constexpr int NT = WShape<CIN, COUT>::NT;
+  constexpr int WE = WShape<CIN, COUT>::elems;
+  __shared__ __attribute__((aligned(16))) __bf16 sw[WE];
+  for (int q = threadIdx.x; q < WE / 8; q += blockDim.x)
+    reinterpret_cast<uint4*>(sw)[q] = reinterpret_cast<const uint4*>(wpk)[q];
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, grp = lane >> 4;
+  const int ntiles = (g.ncell + 15) / 16;
+  const v8bf zero8 = {};
+  for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
+    const int c = tile * 16 + row;
+    const bool valid = c < g.ncell;
+    const int ci = valid ? c % g.nx : 0;
+    const int cj = valid ? (c / g.nx) % g.ny : 0;
+    const int ck = valid ? c / (g.nx * g.ny) : 0;
+    v4f acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+    if (CIN == 32) {
+#pragma unroll 3
+      for (int t = 0; t < 27; ++t) {
+        const int q = valid ? tap_cell(g, ci, cj, ck, t) : -1;
+        const v8bf a = q >= 0 ? *reinterpret_cast<const v8bf*>(in + (size_t)q * 32 + grp * 8) : zero8;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const v8bf b = *reinterpret_cast<const v8bf*>(sw + ((t * NT + nt) * 16 + row) * 32 + grp * 8);
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int t0 = 8 * s + 2 * grp, t1 = t0 + 1;
+        v4bf lo = {}, hi = {};
+        if (valid && t0 < 27) {
+          const int q = tap_cell(g, ci, cj, ck, t0);
+          if (q >= 0) lo = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
+        }
+        if (valid && t1 < 27) {
+          const int q = tap_cell(g, ci, cj, ck, t1);
+          if (q >= 0) hi = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
+        }
+        const v8bf a = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const v8bf b = *reinterpret_cast<const v8bf*>(sw + (nt * 16 + row) * 128 + 32 * s + grp * 8);
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
+        }
+      }
+    }
+    // epilogue: acc[nt][r] = output (cell tile*16 + 4*grp + r, channel nt*16 + row)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const int n = nt * 16 + row;
+      if (n >= COUT) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = tile * 16 + 4 * grp + r;
+        if (co >= g.ncell) continue;
+        const size_t o = (size_t)co * COUT + n;
+        float v = acc[nt][r];
+        if (EPI == EPI_FIRST || EPI == EPI_RES) {
+          const float zb = bf(v + bias[n]);
+          if (e.zout) e.zout[o] = (__bf16)zb;
+          float h = leaky(zb, e.alpha);
+          if (EPI == EPI_RES) h += (float)e.hin[o];
+          e.hout[o] = (__bf16)h;
+        } else if (EPI == EPI_LAST) {
+          e.yout[o] = e.xres[o] + v + bias[n];
+        } else {  // EPI_BWD: dh = acc (+ dh of the layer above); dz = dh * phi'(z)
+          float gsum = v + (e.hin ? (float)e.hin[o] : 0.0f);
+          const float gb = bf(gsum);
+          if (e.hout) e.hout[o] = (__bf16)gb;
+          if (e.zout) e.zout[o] = (__bf16)(gb * dleaky((float)e.zin[o], e.alpha));
+        }
+      }
+    }
+  }
+}
+
+// Weight and bias gradients of one convolution: dW[t][i][o] = sum_cells
+// x[nb(c,t)][i] dy[c][o], as per-block partials.  Chunks of 32 cells; wave w
+// owns taps w, w+4, ...; operands transposed through LDS.
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_dw(ConvGeom g, const __bf16* __restrict__ x,
+                                                 const __bf16* __restrict__ dy,
+                                                 float* __restrict__ part,
+                                                 float* __restrict__ part_b) {
+  constexpr int CP = CIN < 16 ? 16 : CIN;    // padded input channels (M)
+  constexpr int OP = COUT < 16 ? 16 : COUT;  // padded output channels (N)
+  constexpr int MT = CP / 16, NT = OP / 16;
+  constexpr int SLOTS = 7;  // taps per wave: ceil(27 / 4)
+  __shared__ __attribute__((aligned(16))) __bf16 dyT[OP][32];
+  __shared__ __attribute__((aligned(16))) __bf16 xT[4][CP][32];
+  __shared__ float bsum[256];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, grp = lane >> 4;
+  for (int q = threadIdx.x; q < OP * 32; q += 256) (&dyT[0][0])[q] = (__bf16)0.0f;
+  for (int q = threadIdx.x; q < 4 * CP * 32; q += 256) (&xT[0][0][0])[q] = (__bf16)0.0f;
+  v4f acc[SLOTS][MT][NT];
+#pragma unroll
+  for (int s = 0; s < SLOTS; ++s)
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int b = 0; b < NT; ++b) acc[s][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  float bacc = 0.0f;  // bias partial for (thread's channel)
+  const int nchunks = (g.ncell + 31) / 32;
+  __syncthreads();
+  for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+    const int c0 = ch * 32;
+    // dY chunk -> dyT[o][cell]; a thread always meets the same channel
+    // o = threadIdx.x % COUT (COUT divides 256), so it also sums that
+    // channel for the bias gradient
+    for (int q = threadIdx.x; q < 32 * COUT; q += 256) {
+      const int cl = q / COUT, o = q % COUT;
+      const int c = c0 + cl;
+      const float v = c < g.ncell ? (float)dy[(size_t)c * COUT + o] : 0.0f;
+      dyT[o][cl] = (__bf16)v;
+      bacc += v;
+    }
+    for (int slot = 0; slot < SLOTS; ++slot) {
+      const int t = wave + 4 * slot;
+      __syncthreads();
+      if (t < 27) {
+        for (int q = lane; q < 32 * CIN; q += 64) {
+          const int cl = q / CIN, i = q % CIN;
+          const int c = c0 + cl;
+          float v = 0.0f;
+          if (c < g.ncell) {
+            const int qq = tap_cell(g, c % g.nx, (c / g.nx) % g.ny, c / (g.nx * g.ny), t);
+            if (qq >= 0) v = (float)x[(size_t)qq * CIN + i];
+          }
+          xT[wave][i][cl] = (__bf16)v;
+        }
+      }
+      __syncthreads();
+      if (t < 27) {
+#pragma unroll
+        for (int a = 0; a < MT; ++a) {
+          const v8bf A = *reinterpret_cast<const v8bf*>(&xT[wave][a * 16 + row][grp * 8]);
+#pragma unroll
+          for (int b = 0; b < NT; ++b) {
+            const v8bf B = *reinterpret_cast<const v8bf*>(&dyT[b * 16 + row][grp * 8]);
+            acc[slot][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[slot][a][b], 0, 0, 0);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // partials: C rows m = a*16 + 4*grp + r (input channel), col n = b*16 + row
+  float* pb = part + (size_t)blockIdx.x * 27 * CIN * COUT;
+#pragma unroll
+  for (int slot = 0; slot < SLOTS; ++slot) {
+    const int t = wave + 4 * slot;
+    if (t >= 27) continue;
+#pragma unroll
+    for (int a = 0; a < MT; ++a)
+#pragma unroll
+      for (int b = 0; b < NT; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = a * 16 + 4 * grp + r, n = b * 16 + row;
+          if (m < CIN && n < COUT) pb[((size_t)t * CIN + m) * COUT + n] = acc[slot][a][b][r];
+        }
+  }
+  bsum[threadIdx.x] = bacc;
+  __syncthreads();
+  if ((int)threadIdx.x < COUT) {
+    float s = 0.0f;
+    for (int q = threadIdx.x; q < 256; q += COUT) s += bsum[q];
+    part_b[(size_t)blockIdx.x * COUT + threadIdx.x] = s;
+  }
+}
+
+// out[k] = sum over blocks of part[b][k], in block order.
+__global__ void k_reduce_parts(const float* __restrict__ part, int nblocks, int len,
+                               float* __restrict__ out) {
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= len) return;
+  float s = 0.0f;
+  for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * len + k];
+  out[k] = s;
+}
+
+// Normalised input: xf [c][4] = (raw[ch][c] - mean) / std, and its BF16 copy.
+__global__ void k_nn_prep(int ncell, const double* __restrict__ raw, NNNorm nm,
+                          float* __restrict__ xf, __bf16* __restrict__ xb) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  for (int ch = 0; ch < 4; ++ch) {
+    float v = (float)((raw[(size_t)ch * ncell + c] - nm.mean[ch]) / nm.std[ch]);
+    xf[(size_t)c * 4 + ch] = v;
+    xb[(size_t)c * 4 + ch] = (__bf16)v;
+  }
+}
+
+// Network output back to the smoothed field: smooth[ch][c] = y*std + mean.
+__global__ void k_nn_out(int ncell, const float* __restrict__ y, NNNorm nm,
+                         double* __restrict__ smooth) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  for (int ch = 0; ch < 4; ++ch)
+    smooth[(size_t)ch * ncell + c] = (double)y[(size_t)c * 4 + ch] * nm.std[ch] + nm.mean[ch];
+}
+
+// Loss gradient: target t = (smooth - mean)/std; dy = 2 (y - t) / (4 n) in
+// BF16; per-block FP64 partial sums of (y - t)^2.
+__global__ void k_nn_loss(int ncell, const float* __restrict__ y,
+                          const double* __restrict__ smooth, NNNorm nm,
+                          __bf16* __restrict__ dy, double* __restrict__ part) {
+  __shared__ double s[256];
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (c < ncell) {
+    const float scale = 2.0f / (4.0f * (float)ncell);
+    for (int ch = 0; ch < 4; ++ch) {
+      float t = (float)((smooth[(size_t)ch * ncell + c] - nm.mean[ch]) / nm.std[ch]);
+      float d = y[(size_t)c * 4 + ch] - t;
+      acc += (double)d * (double)d;
+      dy[(size_t)c * 4 + ch] = (__bf16)(scale * d);
+    }
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// Adam on the FP32 master parameters.
+__global__ void k_adam(int64_t n, float* __restrict__ w, float* __restrict__ m,
+                       float* __restrict__ v, const float* __restrict__ gr, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  float g = gr[k];
+  float mm = b1 * m[k] + (1.0f - b1) * g;
+  float vv = b2 * v[k] + (1.0f - b2) * g * g;
+  m[k] = mm;
+  v[k] = vv;
+  w[k] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+// Pack one layer's FP32 weights w[27][cin][cout] into the BF16 layouts the
+// convolution kernel reads: forward and (for layers > 1) the transposed
+// adjoint used by the data gradient.
+__global__ void k_pack(const float* __restrict__ w, int cin, int cout,
+                       __bf16* __restrict__ fwd, __bf16* __restrict__ adj) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 27 * cin * cout) return;
+  const int t = q / (cin * cout), i = (q / cout) % cin, o = q % cout;
+  const __bf16 v = (__bf16)w[q];
+  // forward: input channels i, output channels o
+  if (cin == 32) {
+    const int ntp = ((cout + 15) / 16) * 16;
+    fwd[((size_t)t * ntp + o) * 32 + i] = v;
+  } else {
+    fwd[(size_t)o * 128 + t * 4 + i] = v;
+  }
+  // adjoint: input channels o, output channels i (offsets negated at run time)
+  if (adj) {
+    if (cout == 32) {
+      const int ntp = ((cin + 15) / 16) * 16;
+      adj[((size_t)t * ntp + i) * 32 + o] = v;
+    } else {
+      adj[(size_t)i * 128 + t * 4 + o] = v;
+    }
+  }
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+size_t nn_packed_elems(int cin, int cout) {
+  int nt = (cout + 15) / 16;
+  return cin == 32 ? (size_t)27 * nt * 16 * 32 : (size_t)nt * 16 * 128;
+}
+
+void launch_conv(int cin, int cout, int epi, const ConvGeom& g, const __bf16* in,
+                 const __bf16* wpk, const float* bias, const EpiArgs& e, hipStream_t s) {
+  int ntiles = (g.ncell + 15) / 16;
+  unsigned grid = (unsigned)((ntiles + 3) / 4);
+  if (grid > 2048) grid = 2048;
+  if (grid == 0) return;
+#define SEDIMI_CONV(CI, CO, EP)                                                             \
+  if (cin == CI && cout == CO && epi == EP) {                                             \
+    hipLaunchKernelGGL((k_conv<CI, CO, EP>), dim3(grid), dim3(256), 0, s, g, in, wpk, bias, e); \
+    return;                                                                               \
+  }
+  SEDIMI_CONV(4, 32, EPI_FIRST)
+  SEDIMI_CONV(32, 32, EPI_RES)
+  SEDIMI_CONV(32, 4, EPI_LAST)
+  SEDIMI_CONV(4, 32, EPI_BWD)
+  SEDIMI_CONV(32, 32, EPI_BWD)
+#undef SEDIMI_CONV
+}
+
+int launch_conv_dw(int cin, int cout, const ConvGeom& g, const __bf16* x, const __bf16* dy,
+                   float* part, float* part_b, float* dw, float* db, int nblocks,
+                   hipStream_t s) {
+  if (cin == 32 && cout == 32)
+    hipLaunchKernelGGL((k_conv_dw<32, 32>), dim3(nblocks), dim3(256), 0, s, g, x, dy, part, part_b);
+  else if (cin == 4 && cout == 32)
+    hipLaunchKernelGGL((k_conv_dw<4, 32>), dim3(nblocks), dim3(256), 0, s, g, x, dy, part, part_b);
+  else if (cin == 32 && cout == 4)
+    hipLaunchKernelGGL((k_conv_dw<32, 4>), dim3(nblocks), dim3(256), 0, s, g, x, dy, part, part_b);
+  else
+    return -1;
+  int len = 27 * cin * cout;
+  hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(len)), dim3(256), 0, s, part, nblocks, len, dw);
+  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, part_b, nblocks, cout, db);
+  return 0;
+}
+
+void launch_nn_prep(int ncell, const double* raw, const NNNorm& nm, float* xf, __bf16* xb,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_nn_prep, dim3(nblk(ncell)), dim3(256), 0, s, ncell, raw, nm, xf, xb);
+}
+void launch_nn_out(int ncell, const float* y, const NNNorm& nm, double* smooth, hipStream_t s) {
+  hipLaunchKernelGGL(k_nn_out, dim3(nblk(ncell)), dim3(256), 0, s, ncell, y, nm, smooth);
+}
+unsigned launch_nn_loss(int ncell, const float* y, const double* smooth, const NNNorm& nm,
+                        __bf16* dy, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_nn_loss, dim3(nblk(ncell)), dim3(256), 0, s, ncell, y, smooth, nm, dy, part);
+  return nblk(ncell);
+}
+void launch_adam(int64_t n, float* w, float* m, float* v, const float* g, float lr, float b1,
+                 float b2, float eps, int64_t t, hipStream_t s) {
+  float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+  hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, s, n, w, m, v, g, lr, b1, b2, eps, c1, c2);
+}
+void launch_pack(const float* w, int cin, int cout, __bf16* fwd, __bf16* adj, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(nblk(27 * cin * cout)), dim3(256), 0, s, w, cin, cout, fwd, adj);
+}
+
+}  // namespace sedimi

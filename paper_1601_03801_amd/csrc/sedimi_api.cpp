@@ -10,12 +10,47 @@
 #include <string>
 #include <vector>
 
+#include "k_nn.h"
 #include "sedimi_internal.h"
 
 using namespace sedimi;
 
+namespace {
+constexpr int kNNC = 32;                       // network width
+constexpr int kNNDil[6] = {1, 2, 4, 4, 2, 1};  // z dilation per layer
+constexpr int kDwBlocks = 512;                 // weight-gradient partial blocks
+
+struct NNBufs {
+  float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;  // parameters, moments, grads
+  __bf16* fwd[6] = {};
+  __bf16* adj[6] = {};
+  float *xf = nullptr, *y = nullptr;
+  __bf16 *xb = nullptr, *dy6 = nullptr;
+  __bf16* z[5] = {};
+  __bf16* h[5] = {};
+  __bf16* dh[2] = {};
+  __bf16* dz[2] = {};
+  float *part = nullptr, *part_b = nullptr;
+};
+
+int nn_cin(int l) { return l == 0 ? 4 : kNNC; }
+int nn_cout(int l) { return l == 5 ? 4 : kNNC; }
+int64_t nn_woff(int l) {
+  int64_t o = 0;
+  for (int q = 0; q < l; ++q) o += 27LL * nn_cin(q) * nn_cout(q) + nn_cout(q);
+  return o;
+}
+int64_t nn_count() { return nn_woff(6); }
+}  // namespace
+
 struct sedimi_ctx {
   sedimi_params prm;
+  int avg_mode = SEDIMI_AVG_PLAIN;
+  NNBufs nn;
+  NNNorm norm{{0, 0, 0, 0}, {1, 1, 1, 1}};
+  int64_t adam_t = 0;
+  int64_t nn_calls = 0, nn_fallbacks = 0;
+  double nn_last_check = 0.0;
   int64_t cap = 0;
   int64_t n = 0;
   int64_t step = 0;
@@ -134,6 +169,29 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
   a.bin_rank = w.take<int>(nb);
   a.ctl = w.take<Ctl>(1);
   if (A) *A = a;
+  if (c->prm.nn_enable) {
+    NNBufs b;
+    const size_t P = (size_t)nn_count();
+    b.w = w.take<float>(P);
+    b.m = w.take<float>(P);
+    b.v = w.take<float>(P);
+    b.g = w.take<float>(P);
+    for (int l = 0; l < 6; ++l) {
+      b.fwd[l] = w.take<__bf16>(nn_packed_elems(nn_cin(l), nn_cout(l)));
+      if (l > 0) b.adj[l] = w.take<__bf16>(nn_packed_elems(nn_cout(l), nn_cin(l)));
+    }
+    b.xf = w.take<float>(4 * nc);
+    b.y = w.take<float>(4 * nc);
+    b.xb = w.take<__bf16>(4 * nc);
+    b.dy6 = w.take<__bf16>(4 * nc);
+    for (int l = 0; l < 5; ++l) b.z[l] = w.take<__bf16>(kNNC * nc);
+    for (int l = 0; l < 5; ++l) b.h[l] = w.take<__bf16>(kNNC * nc);
+    for (int l = 0; l < 2; ++l) b.dh[l] = w.take<__bf16>(kNNC * nc);
+    for (int l = 0; l < 2; ++l) b.dz[l] = w.take<__bf16>(kNNC * nc);
+    b.part = w.take<float>((size_t)kDwBlocks * 27 * kNNC * kNNC);
+    b.part_b = w.take<float>((size_t)kDwBlocks * kNNC);
+    if (base) const_cast<sedimi_ctx*>(c)->nn = b;
+  }
   return align256(w.off);
 }
 
@@ -164,6 +222,8 @@ int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
   if (!(p.skin >= 0)) return fail(c, SEDIMI_EINVAL, "skin must be >= 0");
   if (p.max_neighbors < 1 || p.max_neighbors > 30)
     return fail(c, SEDIMI_EINVAL, "max_neighbors must be in 1..30");
+  if (p.nn_enable && !(p.nn_alpha >= 0 && p.nn_bound > 0 && p.nn_sample > 0 && p.nn_sample <= 1))
+    return fail(c, SEDIMI_EINVAL, "surrogate parameters out of range");
   return SEDIMI_OK;
 }
 
@@ -273,16 +333,44 @@ void phase_end(sedimi_ctx* c) {
   if (c->marks.back().b) (void)hipEventRecord(c->marks.back().b, c->stream);
 }
 
-int64_t do_average(sedimi_ctx* c) {
+void nn_run_forward(sedimi_ctx* c, bool keep);
+int nn_check_smooth(sedimi_ctx* c, double rel[4]);
+
+int64_t do_average_plain(sedimi_ctx* c) {
+  double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
+  return launch_smooth(c->P, c->A, 4, c->prm.avg_ntau, tau, c->prm.avg_rtol, c->mixed,
+                       c->stream);
+}
+
+// One averaging in the current mode.  Returns the solver iterations (0 when
+// the network answered), or a negative SEDIMI_E* code.
+int64_t do_average(sedimi_ctx* c, bool* used_plain) {
   phase_begin(c, 3);
   launch_deposit(c->P, c->A, c->stream);
   phase_end(c);
-  double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
   phase_begin(c, 4);
-  int64_t it = launch_smooth(c->P, c->A, 4, c->prm.avg_ntau, tau, c->prm.avg_rtol, c->mixed,
-                             c->stream);
+  int64_t it = 0;
+  bool plain = true;
+  if (c->avg_mode != SEDIMI_AVG_PLAIN && c->prm.nn_enable) {
+    nn_run_forward(c, false);
+    ++c->nn_calls;
+    plain = false;
+    if (c->avg_mode == SEDIMI_AVG_SURROGATE_CHECKED) {
+      double rel[4];
+      int rc = nn_check_smooth(c, rel);
+      if (rc) return rc;
+      double worst = std::max(std::max(rel[0], rel[1]), std::max(rel[2], rel[3]));
+      c->nn_last_check = worst;
+      if (!(worst <= c->prm.nn_bound)) {
+        ++c->nn_fallbacks;
+        plain = true;
+      }
+    }
+  }
+  if (plain) it = do_average_plain(c);
   launch_pack_eps(c->P, c->A, c->stream);
   phase_end(c);
+  if (used_plain) *used_plain = plain;
   return it;
 }
 
@@ -511,8 +599,11 @@ int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
     std::swap(c->A.omg, c->A.omg_t);
     ++c->step;
     if (average_every > 0 && c->step % average_every == 0) {
-      c->last_iters = do_average(c);
-      averaged = true;
+      bool plain = true;
+      int64_t it = do_average(c, &plain);
+      if (it < 0) return (int)it;
+      c->last_iters = it;
+      averaged = plain;  // residual partials of the last averaging (plain only)
     }
   }
   HIPCHK(c, hipGetLastError());
@@ -528,8 +619,15 @@ int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
 int sedimi_average(sedimi_ctx* c) {
   int rc = need_particles(c);
   if (rc) return rc;
-  c->last_iters = do_average(c);
+  bool plain = true;
+  int64_t it = do_average(c, &plain);
+  if (it < 0) return (int)it;
+  c->last_iters = it;
   HIPCHK(c, hipGetLastError());
+  if (!plain) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SEDIMI_OK;
+  }
   return check_solve(c, 4);
 }
 
@@ -751,6 +849,9 @@ int sedimi_get_stats(sedimi_ctx* c, sedimi_stats* out) {
   out->solve_residual = c->last_residual;
   out->mean_neighbors = 0.0;
   out->mean_contacts = 0.0;
+  out->nn_calls = c->nn_calls;
+  out->nn_fallbacks = c->nn_fallbacks;
+  out->nn_last_check = c->nn_last_check;
   if (c->have_particles && c->n > 0) {
     const size_t n = (size_t)c->n;
     std::vector<int> cnt;
@@ -795,6 +896,258 @@ int sedimi_get_profile(sedimi_ctx* c, sedimi_profile* out) {
   c->marks.clear();
   for (int k = 0; k < SEDIMI_NPHASES; ++k) out->ms[k] = c->prof_ms[k], out->count[k] = c->prof_count[k];
   return SEDIMI_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+ConvGeom geom(const sedimi_ctx* c, int layer, int neg) {
+  ConvGeom g;
+  g.nx = c->P.nx, g.ny = c->P.ny, g.nz = c->P.nz, g.ncell = c->P.ncell;
+  g.dil = kNNDil[layer];
+  g.neg = neg;
+  return g;
+}
+
+void nn_pack_all(sedimi_ctx* c) {
+  for (int l = 0; l < 6; ++l)
+    launch_pack(c->nn.w + nn_woff(l), nn_cin(l), nn_cout(l), c->nn.fwd[l], c->nn.adj[l],
+                c->stream);
+}
+
+// Network forward on the RAW field into nn.y and the SMOOTH field.  keep:
+// store the pre-activations needed by the backward pass.
+void nn_run_forward(sedimi_ctx* c, bool keep) {
+  NNBufs& b = c->nn;
+  const int n = c->P.ncell;
+  launch_nn_prep(n, c->A.raw, c->norm, b.xf, b.xb, c->stream);
+  const float alpha = (float)c->prm.nn_alpha;
+  for (int l = 0; l < 5; ++l) {
+    EpiArgs e{};
+    e.alpha = alpha;
+    e.zout = keep ? b.z[l] : nullptr;
+    e.hout = b.h[l];
+    e.hin = l == 0 ? nullptr : b.h[l - 1];
+    const float* bias = b.w + nn_woff(l) + 27LL * nn_cin(l) * nn_cout(l);
+    launch_conv(nn_cin(l), nn_cout(l), l == 0 ? EPI_FIRST : EPI_RES, geom(c, l, 0),
+                l == 0 ? b.xb : b.h[l - 1], b.fwd[l], bias, e, c->stream);
+  }
+  EpiArgs e{};
+  e.alpha = alpha;
+  e.xres = b.xf;
+  e.yout = b.y;
+  launch_conv(kNNC, 4, EPI_LAST, geom(c, 5, 0), b.h[4], b.fwd[5],
+              b.w + nn_woff(5) + 27LL * kNNC * 4, e, c->stream);
+  launch_nn_out(n, b.y, c->norm, c->A.smooth, c->stream);
+}
+
+int nn_check_smooth(sedimi_ctx* c, double rel[4]) {
+  double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
+  int nb = launch_check(c->P, c->A, c->A.smooth, std::max(1, c->prm.avg_ntau), tau,
+                        c->prm.nn_seed, c->prm.nn_sample, c->stream);
+  if (read_check(c->A, nb, rel, c->stream) != 0)
+    return fail(c, SEDIMI_EDEVICE, "reading the residual check failed");
+  return SEDIMI_OK;
+}
+
+int need_nn(sedimi_ctx* c) {
+  int rc = need_ws(c);
+  if (rc) return rc;
+  if (!c->prm.nn_enable) return fail(c, SEDIMI_ESTATE, "context created without nn_enable");
+  return SEDIMI_OK;
+}
+
+uint64_t mix64(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sedimi_set_avg_mode(sedimi_ctx* c, int mode) {
+  if (!c) return SEDIMI_EINVAL;
+  if (mode < SEDIMI_AVG_PLAIN || mode > SEDIMI_AVG_SURROGATE)
+    return fail(c, SEDIMI_EINVAL, "unknown averaging mode");
+  if (mode != SEDIMI_AVG_PLAIN && !c->prm.nn_enable)
+    return fail(c, SEDIMI_ESTATE, "surrogate modes need nn_enable");
+  c->avg_mode = mode;
+  return SEDIMI_OK;
+}
+
+int sedimi_nn_param_count(const sedimi_ctx* c, int64_t* n) {
+  if (!c || !n) return SEDIMI_EINVAL;
+  *n = nn_count();
+  return SEDIMI_OK;
+}
+
+int sedimi_nn_init(sedimi_ctx* c, uint64_t seed) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  const int64_t P = nn_count();
+  std::vector<float> w((size_t)P, 0.0f);
+  uint64_t s = seed;
+  for (int l = 0; l < 5; ++l) {  // the last layer starts at zero: output = input
+    const double sd = sqrt(2.0 / (27.0 * nn_cin(l)));
+    const int64_t nw = 27LL * nn_cin(l) * nn_cout(l);
+    for (int64_t k = 0; k < nw; k += 2) {
+      double u1 = ((mix64(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+      double u2 = ((mix64(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+      double r = sqrt(-2.0 * log(u1));
+      w[(size_t)(nn_woff(l) + k)] = (float)(sd * r * cos(2.0 * kPi * u2));
+      if (k + 1 < nw) w[(size_t)(nn_woff(l) + k + 1)] = (float)(sd * r * sin(2.0 * kPi * u2));
+    }
+  }
+  return sedimi_nn_set_params(c, w.data(), P);
+}
+
+int sedimi_nn_set_params(sedimi_ctx* c, const float* p, int64_t n) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  const int64_t P = nn_count();
+  if (!p || n != P) return fail(c, SEDIMI_EINVAL, "parameter vector has the wrong length");
+  HIPCHK(c, hipMemcpyAsync(c->nn.w, p, sizeof(float) * P, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->nn.m, 0, sizeof(float) * P, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->nn.v, 0, sizeof(float) * P, c->stream));
+  for (int l = 0; l < 6; ++l) {
+    HIPCHK(c, hipMemsetAsync(c->nn.fwd[l], 0, sizeof(__bf16) * nn_packed_elems(nn_cin(l), nn_cout(l)), c->stream));
+    if (l > 0)
+      HIPCHK(c, hipMemsetAsync(c->nn.adj[l], 0, sizeof(__bf16) * nn_packed_elems(nn_cout(l), nn_cin(l)), c->stream));
+  }
+  c->adam_t = 0;
+  nn_pack_all(c);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int sedimi_nn_get_params(sedimi_ctx* c, float* p, int64_t n) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  if (!p || n != nn_count()) return fail(c, SEDIMI_EINVAL, "parameter vector has the wrong length");
+  HIPCHK(c, hipMemcpyAsync(p, c->nn.w, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int sedimi_nn_get_grads(sedimi_ctx* c, float* g, int64_t n) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  if (!g || n != nn_count()) return fail(c, SEDIMI_EINVAL, "gradient vector has the wrong length");
+  HIPCHK(c, hipMemcpyAsync(g, c->nn.g, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int sedimi_nn_set_norm(sedimi_ctx* c, const double* mean4, const double* std4) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  if (!mean4 || !std4) return fail(c, SEDIMI_EINVAL, "null normalisation");
+  for (int k = 0; k < 4; ++k) {
+    if (!(std4[k] > 0)) return fail(c, SEDIMI_EINVAL, "std must be positive");
+    c->norm.mean[k] = mean4[k];
+    c->norm.std[k] = std4[k];
+  }
+  return SEDIMI_OK;
+}
+
+int sedimi_nn_forward(sedimi_ctx* c) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  phase_begin(c, 4);
+  nn_run_forward(c, false);
+  launch_pack_eps(c->P, c->A, c->stream);
+  phase_end(c);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int sedimi_nn_train_step(sedimi_ctx* c, double lr, double* loss) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  if (!(lr >= 0)) return fail(c, SEDIMI_EINVAL, "learning rate must be >= 0");
+  NNBufs& b = c->nn;
+  const int n = c->P.ncell;
+  const float alpha = (float)c->prm.nn_alpha;
+  phase_begin(c, 5);
+  // forward keeping activations; the network output goes to nn.y only (the
+  // SMOOTH field holds the target and is not touched)
+  launch_nn_prep(n, c->A.raw, c->norm, b.xf, b.xb, c->stream);
+  for (int l = 0; l < 5; ++l) {
+    EpiArgs e{};
+    e.alpha = alpha;
+    e.zout = b.z[l];
+    e.hout = b.h[l];
+    e.hin = l == 0 ? nullptr : b.h[l - 1];
+    launch_conv(nn_cin(l), nn_cout(l), l == 0 ? EPI_FIRST : EPI_RES, geom(c, l, 0),
+                l == 0 ? b.xb : b.h[l - 1], b.fwd[l],
+                b.w + nn_woff(l) + 27LL * nn_cin(l) * nn_cout(l), e, c->stream);
+  }
+  {
+    EpiArgs e{};
+    e.alpha = alpha;
+    e.xres = b.xf;
+    e.yout = b.y;
+    launch_conv(kNNC, 4, EPI_LAST, geom(c, 5, 0), b.h[4], b.fwd[5],
+                b.w + nn_woff(5) + 27LL * kNNC * 4, e, c->stream);
+  }
+  unsigned nlb = launch_nn_loss(n, b.y, c->A.smooth, c->norm, b.dy6, c->A.red, c->stream);
+  const int dwb = std::max(1, std::min(kDwBlocks, (n + 31) / 32));
+  // layer 6
+  launch_conv_dw(kNNC, 4, geom(c, 5, 0), b.h[4], b.dy6, b.part, b.part_b, b.g + nn_woff(5),
+                 b.g + nn_woff(5) + 27LL * kNNC * 4, dwb, c->stream);
+  {
+    EpiArgs e{};
+    e.alpha = alpha;
+    e.zin = b.z[4];
+    e.hout = b.dh[0];
+    e.zout = b.dz[0];
+    launch_conv(4, kNNC, EPI_BWD, geom(c, 5, 1), b.dy6, b.adj[5], nullptr, e, c->stream);
+  }
+  int cur = 0;
+  for (int l = 4; l >= 1; --l) {
+    launch_conv_dw(kNNC, kNNC, geom(c, l, 0), b.h[l - 1], b.dz[cur], b.part, b.part_b,
+                   b.g + nn_woff(l), b.g + nn_woff(l) + 27LL * kNNC * kNNC, dwb, c->stream);
+    EpiArgs e{};
+    e.alpha = alpha;
+    e.hin = b.dh[cur];
+    e.zin = b.z[l - 1];
+    e.hout = b.dh[1 - cur];
+    e.zout = b.dz[1 - cur];
+    launch_conv(kNNC, kNNC, EPI_BWD, geom(c, l, 1), b.dz[cur], b.adj[l], nullptr, e, c->stream);
+    cur = 1 - cur;
+  }
+  launch_conv_dw(4, kNNC, geom(c, 0, 0), b.xb, b.dz[cur], b.part, b.part_b, b.g + nn_woff(0),
+                 b.g + nn_woff(0) + 27LL * 4 * kNNC, dwb, c->stream);
+  const int64_t P = nn_count();
+  c->adam_t += 1;
+  launch_adam(P, b.w, b.m, b.v, b.g, (float)lr, 0.9f, 0.999f, 1e-8f, c->adam_t, c->stream);
+  nn_pack_all(c);
+  phase_end(c);
+  HIPCHK(c, hipGetLastError());
+  if (loss) {
+    std::vector<double> h(nlb);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->A.red, sizeof(double) * nlb, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double sum = 0.0;
+    for (unsigned k = 0; k < nlb; ++k) sum += h[k];
+    *loss = sum / (4.0 * n);
+  } else {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return SEDIMI_OK;
+}
+
+int sedimi_nn_check(sedimi_ctx* c, double* rel4) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  if (!rel4) return fail(c, SEDIMI_EINVAL, "null output");
+  return nn_check_smooth(c, rel4);
 }
 
 }  // extern "C"

@@ -128,5 +128,12 @@ int64_t launch_smooth(const DevParams& P, DevArrays& A, int nch, int ntau, doubl
 double read_smooth_residual(const DevParams& P, DevArrays& A, int nch, int ntau,
                             hipStream_t s);
 size_t smooth_red_doubles(int ncell, int nch, int ntau);
+// Residual check of a smoothed field y (4 channels) against raw on a seeded
+// sample of cells (fraction frac): r = A^ntau y - raw.  Enqueues the work
+// (partials in A.red, A.sd0/A.sd1 as scratch) and returns the block count;
+// read_check then gives |r|/|y| per channel over the sample (synchronises).
+int launch_check(const DevParams& P, DevArrays& A, const double* y, int ntau, double tau,
+                 uint64_t seed, double frac, hipStream_t s);
+int read_check(DevArrays& A, int nblocks, double rel[4], hipStream_t s);
 
 }  // namespace sedimi
