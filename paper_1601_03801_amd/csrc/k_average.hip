@@ -9,14 +9,16 @@
 // Diffusion (Eq. 12): avg_ntau backward-Euler pseudo-time steps of unit
 // diffusivity up to tau = b^2/4; each step solves (I - dtau L_h) x = b with
 // the second-order finite-volume Laplacian (periodic x, y; zero-flux walls).
-// The solver is Chebyshev iteration: the operator's spectrum lies in
-// [1, 1 + dtau * sum_a 4/h_a^2] on a uniform mesh, so the iteration needs no
-// inner products, every iteration is one fused stencil sweep, and the number
+// The solver is Chebyshev iteration preconditioned by the exact z-line
+// (tridiagonal) part of the operator: on a uniform mesh the spectrum of the
+// preconditioned operator is known in closed form, so the iteration needs no
+// inner products, every iteration is one fused column sweep, and the number
 // of iterations that guarantees the residual tolerance is known in advance.
 // The final residual of every pseudo-time step is then measured with an FP64
 // reduction (fixed-order block trees, summed on the host in fixed order).
 #include <math.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "k_common.h"
@@ -107,25 +109,125 @@ __device__ __forceinline__ double apply_A(const Stencil& S, const T* __restrict_
   return xc - (S.cx * lx + S.cy * ly + S.cz * lz);
 }
 
-// Start of one pseudo-time step: b = src; x = b; r = b - A b; d = r / theta;
-// keep b for the residual check.
-// When src is x itself (pseudo-time steps after the first) x is left as is.
+// Preconditioned Chebyshev iteration for (I - dtau L_h) x = b, preconditioner
+// M = I - dtau L_z (the z-part of the operator, exact tridiagonal solve per
+// column by the Thomas algorithm).  On a uniform mesh every Fourier x DCT
+// mode is an eigenvector of both, so the spectrum of M^-1 A is
+// (1 + a + c)/(1 + c) with a in [0, 4 (cx + cy)], c in [0, 4 cz]: it lies in
+// [1, 1 + 4 (cx + cy)], free of the stiff z coupling.  One lane per
+// (x, y) column and channel walks up the column (stencil, update, forward
+// elimination) and back down (back substitution, new direction).
+//
+// ztab: inv_m[k] (reciprocal pivots) then cp[k] (modified super-diagonal).
 template <typename T>
-__global__ void k_cheb_init(Stencil S, const T* src, T* x, T* __restrict__ r,
-                            T* __restrict__ d, T* __restrict__ bsave, double inv_theta,
-                            int copy_x) {
+__device__ __forceinline__ double ld(const T* p, size_t o) {
+  return (double)p[o];
+}
+
+// z-window stencil: A v at level k of column (i, j) given v_{k-1}, v_k,
+// v_{k+1} (the caller passes 0-weighted neighbours outside the mesh).
+template <typename T>
+__device__ __forceinline__ double A_col(const Stencil& S, const T* __restrict__ v, size_t c,
+                                        int i, int j, int k, double vm, double v0, double vp) {
+  size_t ip = i + 1 == S.nx ? c - i : c + 1;
+  size_t im = i == 0 ? c + S.nx - 1 : c - 1;
+  size_t row = (size_t)S.nx;
+  size_t jp = j + 1 == S.ny ? c - (size_t)j * row : c + row;
+  size_t jm = j == 0 ? c + (size_t)(S.ny - 1) * row : c - row;
+  double lx = (ld(v, ip) - v0) + (ld(v, im) - v0);
+  double ly = (ld(v, jp) - v0) + (ld(v, jm) - v0);
+  double lz = 0.0;
+  if (k + 1 < S.nz) lz += vp - v0;
+  if (k > 0) lz += vm - v0;
+  return v0 - (S.cx * lx + S.cy * ly + S.cz * lz);
+}
+
+// Start of a pseudo-time step with b = x (x unchanged): r = b - A b,
+// z = M^-1 r, d = z / theta; b saved for the residual check.
+template <typename T>
+__global__ void k_pcheb_init(Stencil S, const T* __restrict__ x, T* __restrict__ r,
+                             T* __restrict__ d, T* __restrict__ bsave, T* __restrict__ tmp,
+                             const double* __restrict__ ztab, double inv_theta) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const int plane = S.nx * S.ny;
+  if (col >= plane) return;
+  const size_t off = (size_t)blockIdx.y * S.ncell;
+  const T* xv = x + off;
+  const int i = col % S.nx, j = col / S.nx;
+  const double* inv_m = ztab;
+  const double* cp = ztab + S.nz;
+  double vm = 0.0, v0 = ld(xv, col), vp = S.nz > 1 ? ld(xv, (size_t)col + plane) : 0.0;
+  double yp = 0.0;
+  for (int k = 0; k < S.nz; ++k) {
+    const size_t c = (size_t)k * plane + col;
+    const double Ab = A_col<T>(S, xv, c, i, j, k, vm, v0, vp);
+    const double rr = v0 - Ab;
+    r[off + c] = (T)rr;
+    bsave[off + c] = (T)v0;
+    yp = (rr + S.cz * yp) * inv_m[k];
+    tmp[off + c] = (T)yp;
+    vm = v0;
+    v0 = vp;
+    vp = k + 2 < S.nz ? ld(xv, c + 2 * (size_t)plane) : 0.0;
+  }
+  double z = 0.0;
+  for (int k = S.nz - 1; k >= 0; --k) {
+    const size_t c = (size_t)k * plane + col;
+    z = ld(tmp, off + c) - cp[k] * z;
+    d[off + c] = (T)(z * inv_theta);
+  }
+}
+
+// One iteration: x += d; r -= A d; z = M^-1 r; d' = c1 d + c2 z.
+template <typename T>
+__global__ void k_pcheb_iter(Stencil S, const T* __restrict__ d, T* __restrict__ x,
+                             T* __restrict__ r, T* __restrict__ dn, T* __restrict__ tmp,
+                             const double* __restrict__ ztab, double c1, double c2) {
+  const int col = blockIdx.x * blockDim.x + threadIdx.x;
+  const int plane = S.nx * S.ny;
+  if (col >= plane) return;
+  const size_t off = (size_t)blockIdx.y * S.ncell;
+  const T* dv = d + off;
+  const int i = col % S.nx, j = col / S.nx;
+  const double* inv_m = ztab;
+  const double* cp = ztab + S.nz;
+  double vm = 0.0, v0 = ld(dv, col), vp = S.nz > 1 ? ld(dv, (size_t)col + plane) : 0.0;
+  double yp = 0.0;
+  for (int k = 0; k < S.nz; ++k) {
+    const size_t c = (size_t)k * plane + col;
+    const double Ad = A_col<T>(S, dv, c, i, j, k, vm, v0, vp);
+    x[off + c] = (T)(ld(x, off + c) + v0);
+    const double rr = ld(r, off + c) - Ad;
+    r[off + c] = (T)rr;
+    yp = (rr + S.cz * yp) * inv_m[k];
+    tmp[off + c] = (T)yp;
+    vm = v0;
+    v0 = vp;
+    vp = k + 2 < S.nz ? ld(dv, c + 2 * (size_t)plane) : 0.0;
+  }
+  double z = 0.0;
+  for (int k = S.nz - 1; k >= 0; --k) {
+    const size_t c = (size_t)k * plane + col;
+    z = ld(tmp, off + c) - cp[k] * z;
+    dn[off + c] = (T)(c1 * ld(dv, c) + c2 * z);
+  }
+}
+
+// Unpreconditioned variant, one lane per cell (better when the mesh has few
+// columns): x += d; r -= A d; d' = c1 d + c2 r.
+template <typename T>
+__global__ void k_cheb_init(Stencil S, const T* __restrict__ x, T* __restrict__ r,
+                            T* __restrict__ d, T* __restrict__ bsave, double inv_theta) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= S.ncell) return;
   size_t off = (size_t)blockIdx.y * S.ncell;
-  double b = (double)src[off + c];
-  double rr = b - apply_A<T>(S, src + off, c);
-  if (copy_x) x[off + c] = (T)b;
+  double b = (double)x[off + c];
+  double rr = b - apply_A<T>(S, x + off, c);
   bsave[off + c] = (T)b;
   r[off + c] = (T)rr;
   d[off + c] = (T)(rr * inv_theta);
 }
 
-// One Chebyshev iteration: x += d; r -= A d; d' = c1 d + c2 r.
 template <typename T>
 __global__ void k_cheb_iter(Stencil S, const T* __restrict__ d, T* __restrict__ x,
                             T* __restrict__ r, T* __restrict__ dn, double c1, double c2) {
@@ -134,11 +236,16 @@ __global__ void k_cheb_iter(Stencil S, const T* __restrict__ d, T* __restrict__ 
   size_t off = (size_t)blockIdx.y * S.ncell;
   double dc = (double)d[off + c];
   double Ad = apply_A<T>(S, d + off, c);
-  double xn = (double)x[off + c] + dc;
   double rn = (double)r[off + c] - Ad;
-  x[off + c] = (T)xn;
+  x[off + c] = (T)((double)x[off + c] + dc);
   r[off + c] = (T)rn;
   dn[off + c] = (T)(c1 * dc + c2 * rn);
+}
+
+template <typename A_, typename B_>
+__global__ void k_convert(size_t n, const A_* __restrict__ in, B_* __restrict__ out) {
+  size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = (B_)in[k];
 }
 
 // Per-block FP64 sums of (b - A x)^2 and b^2 for each channel.
@@ -274,60 +381,116 @@ size_t smooth_red_doubles(int ncell, int nch, int ntau) {
   return (size_t)((ncell + kBlock - 1) / kBlock) * 2 * nch * (ntau > 0 ? ntau : 1);
 }
 
-int64_t launch_smooth(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
-                      double rtol, bool mixed, hipStream_t s) {
-  (void)mixed;
+void smooth_ztab(const DevParams& P, int ntau, double tau, double* host_tab) {
+  double dtau = tau / (ntau > 0 ? ntau : 1);
+  double cz = dtau / (P.hz * P.hz);
+  double prev_cp = 0.0;
+  for (int k = 0; k < P.nz; ++k) {
+    int nb = (k > 0) + (k + 1 < P.nz);
+    double diag = 1.0 + cz * nb;
+    double m = k == 0 ? diag : diag + cz * prev_cp;
+    double cp = -cz / m;
+    host_tab[k] = 1.0 / m;
+    host_tab[P.nz + k] = cp;
+    prev_cp = cp;
+  }
+}
+
+// Chebyshev iteration count for the residual bound: |r_k| <= pre * 2 rho^k |b|.
+static int cheb_iters(double kappa, double pre, double rtol) {
+  if (kappa <= 1.0 + 1e-12) return 1;
+  double rho = (sqrt(kappa) - 1.0) / (sqrt(kappa) + 1.0);
+  int k = (int)ceil(log(rtol / (2.0 * pre)) / log(rho)) + 1;
+  return k < 1 ? 1 : k;
+}
+
+template <typename T>
+static int64_t smooth_impl(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
+                           double rtol, hipStream_t s) {
   Stencil S;
   S.nx = P.nx, S.ny = P.ny, S.nz = P.nz, S.ncell = P.ncell;
+  double dtau = tau / ntau;
+  S.cx = dtau / (P.hx * P.hx);
+  S.cy = dtau / (P.hy * P.hy);
+  S.cz = dtau / (P.hz * P.hz);
+  const double axy = 4.0 * ((P.nx > 1 ? S.cx : 0.0) + (P.ny > 1 ? S.cy : 0.0));
+  const double az = 4.0 * (P.nz > 1 ? S.cz : 0.0);
+  const double kappaA = 1.0 + axy + az;
+  // plain Chebyshev on A: spectrum [1, kappaA], |r_0| <= (kappaA - 1) |b|
+  const int k_plain = cheb_iters(kappaA, kappaA - 1.0, rtol);
+  // z-line preconditioned: spectrum of M^-1 A in [1, 1 + axy]; the bound
+  // picks up sqrt(cond M) = sqrt(1 + az)
+  const int k_line = cheb_iters(1.0 + axy, sqrt(1.0 + az) * (kappaA - 1.0), rtol);
+  // cost model from measurements on MI355X: the per-cell sweep moves 6
+  // vectors at ~5 TB/s; the column sweep moves 9 and reaches ~3.6 TB/s with
+  // >= 128k column lanes, ~2 TB/s with fewer (latency bound)
+  const double lanes = (double)P.nx * P.ny * nch;
+  const double t_plain = k_plain * 6.0 / 5.0;
+  const double t_line = k_line * 9.0 / (lanes >= 131072.0 ? 3.6 : 2.0);
+  const bool line = t_line < t_plain;
+  const double lmin = 1.0, lmax = line ? 1.0 + axy : kappaA;
+  const int kiter = line ? k_line : k_plain;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  const size_t nall = (size_t)nch * P.ncell;
+  T* x = std::is_same<T, double>::value ? (T*)A.smooth : (T*)A.sxf;
+  T* r = (T*)A.sr;
+  T* d0 = (T*)A.sd0;
+  T* d1 = (T*)A.sd1;
+  T* tmp = (T*)A.stmp;
+  T* bsave = (T*)A.sx;
+  hipLaunchKernelGGL((k_convert<double, T>), dim3((unsigned)((nall + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, nall, (const double*)A.raw, x);
+  dim3 cgrid(nblk((int64_t)P.nx * P.ny), nch);
+  dim3 grid(nblk(P.ncell), nch);
+  const size_t nred = (size_t)grid.x * 2 * nch;
+  for (int m = 0; m < ntau; ++m) {
+    const double inv_theta = delta > 0.0 ? 1.0 / theta : 1.0;
+    if (line)
+      hipLaunchKernelGGL((k_pcheb_init<T>), cgrid, dim3(kBlock), 0, s, S, x, r, d0, bsave, tmp,
+                         A.ztab, inv_theta);
+    else
+      hipLaunchKernelGGL((k_cheb_init<T>), grid, dim3(kBlock), 0, s, S, x, r, d0, bsave,
+                         inv_theta);
+    double sigma1 = delta > 0.0 ? theta / delta : 1.0;
+    double rho_k = 1.0 / sigma1;
+    T* dcur = d0;
+    T* dnext = d1;
+    for (int it = 0; it < kiter; ++it) {
+      double c1 = 0.0, c2 = 0.0;
+      if (delta > 0.0) {
+        double rho_n = 1.0 / (2.0 * sigma1 - rho_k);
+        c1 = rho_n * rho_k;
+        c2 = 2.0 * rho_n / delta;
+        rho_k = rho_n;
+      }
+      if (line)
+        hipLaunchKernelGGL((k_pcheb_iter<T>), cgrid, dim3(kBlock), 0, s, S, dcur, x, r, dnext,
+                           tmp, A.ztab, c1, c2);
+      else
+        hipLaunchKernelGGL((k_cheb_iter<T>), grid, dim3(kBlock), 0, s, S, dcur, x, r, dnext,
+                           c1, c2);
+      T* t = dcur;
+      dcur = dnext;
+      dnext = t;
+    }
+    hipLaunchKernelGGL(k_residual<T>, grid, dim3(kBlock), 0, s, S, bsave, x,
+                       A.red + (size_t)m * nred);
+  }
+  if (!std::is_same<T, double>::value)
+    hipLaunchKernelGGL((k_convert<T, double>), dim3((unsigned)((nall + kBlock - 1) / kBlock)),
+                       dim3(kBlock), 0, s, nall, x, A.smooth);
+  return (int64_t)kiter * ntau;
+}
+
+int64_t launch_smooth(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
+                      double rtol, bool mixed, hipStream_t s) {
   if (ntau <= 0) {
     (void)hipMemcpyAsync(A.smooth, A.raw, sizeof(double) * nch * P.ncell,
                          hipMemcpyDeviceToDevice, s);
     return 0;
   }
-  double dtau = tau / ntau;
-  S.cx = dtau / (P.hx * P.hx);
-  S.cy = dtau / (P.hy * P.hy);
-  S.cz = dtau / (P.hz * P.hz);
-  // the spectrum of A = I - dtau L_h lies in [1, lmax]
-  double lmax = 1.0 + 4.0 * ((P.nx > 1 ? S.cx : 0.0) + (P.ny > 1 ? S.cy : 0.0) +
-                             (P.nz > 1 ? S.cz : 0.0));
-  double lmin = 1.0;
-  int kiter = 0;
-  if (lmax > lmin * (1.0 + 1e-12)) {
-    // Chebyshev residual bound: |r_k| / |b| <= (kappa - 1) * 2 rho^k
-    double kappa = lmax / lmin;
-    double rho = (sqrt(kappa) - 1.0) / (sqrt(kappa) + 1.0);
-    kiter = (int)ceil(log(rtol / (2.0 * (kappa - 1.0))) / log(rho)) + 1;
-    if (kiter < 1) kiter = 1;
-  }
-  double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
-  dim3 grid(nblk(P.ncell), nch);
-  const size_t nred = (size_t)grid.x * 2 * nch;
-  double* bsave = A.sx;
-  for (int m = 0; m < ntau; ++m) {
-    const double* src = m == 0 ? A.raw : A.smooth;
-    hipLaunchKernelGGL(k_cheb_init<double>, grid, dim3(kBlock), 0, s, S, src, A.smooth, A.sr,
-                       A.sd0, bsave, kiter > 0 ? 1.0 / theta : 1.0, m == 0 ? 1 : 0);
-    if (kiter > 0) {
-      double sigma1 = theta / delta;
-      double rho_k = 1.0 / sigma1;
-      double* dcur = A.sd0;
-      double* dnext = A.sd1;
-      for (int it = 0; it < kiter; ++it) {
-        double rho_n = 1.0 / (2.0 * sigma1 - rho_k);
-        double c1 = rho_n * rho_k, c2 = 2.0 * rho_n / delta;
-        hipLaunchKernelGGL(k_cheb_iter<double>, grid, dim3(kBlock), 0, s, S, dcur, A.smooth,
-                           A.sr, dnext, c1, c2);
-        rho_k = rho_n;
-        double* t = dcur;
-        dcur = dnext;
-        dnext = t;
-      }
-    }
-    hipLaunchKernelGGL(k_residual<double>, grid, dim3(kBlock), 0, s, S, bsave, A.smooth,
-                       A.red + (size_t)m * nred);
-  }
-  return (int64_t)kiter * ntau;
+  if (mixed) return smooth_impl<float>(P, A, nch, ntau, tau, rtol, s);
+  return smooth_impl<double>(P, A, nch, ntau, tau, rtol, s);
 }
 
 double read_smooth_residual(const DevParams& P, DevArrays& A, int nch, int ntau,

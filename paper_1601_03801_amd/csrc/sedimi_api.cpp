@@ -162,6 +162,9 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
   a.sr = w.take<double>(4 * nc);
   a.sd0 = w.take<double>(4 * nc);
   a.sd1 = w.take<double>(4 * nc);
+  a.sxf = w.take<double>(4 * nc);
+  a.stmp = w.take<double>(4 * nc);
+  a.ztab = w.take<double>(2 * (size_t)c->P.nz);
   a.cell_count = w.take<int>(nc + 1);
   a.cell_start = w.take<int>(nc + 1);
   a.red = w.take<double>(smooth_red_doubles((int)nc, 4, std::max(1, c->prm.avg_ntau)));
@@ -338,8 +341,8 @@ int nn_check_smooth(sedimi_ctx* c, double rel[4]);
 
 int64_t do_average_plain(sedimi_ctx* c) {
   double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
-  return launch_smooth(c->P, c->A, 4, c->prm.avg_ntau, tau, c->prm.avg_rtol, c->mixed,
-                       c->stream);
+  const double rtol = c->mixed ? std::max(c->prm.avg_rtol, 1e-6) : c->prm.avg_rtol;
+  return launch_smooth(c->P, c->A, 4, c->prm.avg_ntau, tau, rtol, c->mixed, c->stream);
 }
 
 // One averaging in the current mode.  Returns the solver iterations (0 when
@@ -378,7 +381,9 @@ int check_solve(sedimi_ctx* c, int nch) {
   double res = read_smooth_residual(c->P, c->A, nch, c->prm.avg_ntau, c->stream);
   if (res < 0) return fail(c, SEDIMI_EDEVICE, "reading the solver residual failed");
   c->last_residual = res;
-  if (res > c->prm.avg_rtol * 10.0 + 1e-300)
+  // FP32 working vectors cannot go below ~1e-6 relative
+  const double tol = c->mixed ? std::max(c->prm.avg_rtol, 1e-6) : c->prm.avg_rtol;
+  if (res > tol * 10.0 + 1e-300)
     return fail(c, SEDIMI_ENOCONV, "diffusion solve residual above tolerance");
   return SEDIMI_OK;
 }
@@ -447,6 +452,12 @@ int sedimi_bind_workspace(sedimi_ctx* c, void* dev_ptr, size_t bytes) {
     for (int r = 0; r < P.nbins; ++r) rank[code[r].second] = r;
     HIPCHK(c, hipMemcpyAsync(c->A.bin_rank, rank.data(), sizeof(int) * rank.size(),
                              hipMemcpyHostToDevice, c->stream));
+    std::vector<double> zt(2 * (size_t)P.nz);
+    double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
+    smooth_ztab(P, std::max(1, c->prm.avg_ntau), tau, zt.data());
+    HIPCHK(c, hipMemcpyAsync(c->A.ztab, zt.data(), sizeof(double) * zt.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->have_particles = false;
@@ -645,8 +656,9 @@ int sedimi_smooth(sedimi_ctx* c, int nch) {
   if (rc) return rc;
   if (nch < 1 || nch > 4) return fail(c, SEDIMI_EINVAL, "nch must be 1..4");
   double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
-  c->last_iters = launch_smooth(c->P, c->A, nch, c->prm.avg_ntau, tau, c->prm.avg_rtol,
-                                c->mixed, c->stream);
+  const double rtol = c->mixed ? std::max(c->prm.avg_rtol, 1e-6) : c->prm.avg_rtol;
+  c->last_iters = launch_smooth(c->P, c->A, nch, c->prm.avg_ntau, tau, rtol, c->mixed,
+                                c->stream);
   launch_pack_eps(c->P, c->A, c->stream);
   HIPCHK(c, hipGetLastError());
   return check_solve(c, nch);

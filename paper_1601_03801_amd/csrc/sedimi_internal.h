@@ -94,6 +94,8 @@ struct DevArrays {
   double4 *U, *gp, *du;  // U.w = averaged solid fraction
   double4* G;            // -grad p + C_add rho_f DU/Dt (step kernel)
   double *raw, *smooth, *sx, *sr, *sd0, *sd1;
+  double *sxf, *stmp;  // solver: FP32 iterate (mixed mode), column-sweep scratch
+  double* ztab;        // z-line preconditioner: reciprocal pivots, super-diagonal
   int *cell_count, *cell_start, *cperm;
   double* red;  // reduction partials
   Ctl* ctl;
@@ -128,6 +130,8 @@ int64_t launch_smooth(const DevParams& P, DevArrays& A, int nch, int ntau, doubl
 double read_smooth_residual(const DevParams& P, DevArrays& A, int nch, int ntau,
                             hipStream_t s);
 size_t smooth_red_doubles(int ncell, int nch, int ntau);
+// Thomas-algorithm table of the z-line preconditioner (2 * nz doubles).
+void smooth_ztab(const DevParams& P, int ntau, double tau, double* host_tab);
 // Residual check of a smoothed field y (4 channels) against raw on a seeded
 // sample of cells (fraction frac): r = A^ntau y - raw.  Enqueues the work
 // (partials in A.red, A.sd0/A.sd1 as scratch) and returns the block count;
