@@ -47,6 +47,10 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--nn-train-steps", type=int, default=300,
+                    help="surrogate training snapshots (0 skips the surrogate section)")
+    ap.add_argument("--nn-steps", type=int, default=10,
+                    help="coupled steps (averaging every step) per averaging mode")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path "
@@ -125,6 +129,12 @@ def main():
         print(f"bench: oracle {args.cpu_steps} steps in {c1 - c0:.1f} s", file=sys.stderr,
               flush=True)
 
+    surrogate = None
+    if args.nn_train_steps > 0:
+        del g
+        torch.cuda.empty_cache()
+        surrogate = surrogate_section(args)
+
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "particle-updates/s",
         "n_gpus": 1, "steps": K, "warmup": W,
@@ -140,11 +150,127 @@ def main():
         "averaging": {"plain_ms": round(avg_ms, 4),
                       "solve_iters": st["solve_iters"], "residual": st["solve_residual"]},
         "phases": phases,
+        "surrogate": surrogate,
         "stats": {"mean_neighbors": round(st["mean_neighbors"], 3),
                   "mean_contacts": round(st["mean_contacts"], 3),
                   "rebuilds": st["rebuilds"], "steps": st["steps"]},
     }
     print(json.dumps(out))
+
+
+def surrogate_section(args):
+    """Learned stand-in for the averaging on the fine 256 x 128 x 128 mesh
+    (cells of 3.125d x 3.125d x 0.5d): train on snapshots of a 2M-sphere bed
+    (random periodic translations, targets from the plain solve on the GPU),
+    then run the 4M-sphere bed with averaging every step under each averaging
+    mode and compare time, fallback rate and error against the plain solve."""
+    import numpy as np
+    import torch
+
+    import paper_1601_03801_amd as sm
+    import workloads
+
+    t0 = time.time()
+    wtr = workloads.workload("fine2m")
+    w4 = workloads.workload("fine4m")
+    print(f"bench: surrogate beds generated in {time.time() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    prm = dict(w4["params"])
+    dmax = float(max(wtr["d"].max(), w4["d"].max()))
+    n4 = len(w4["d"])
+    g = sm.Sedimi(prm, n4, precision="mixed", d_max=dmax, skin=0.1 * dmax, max_neighbors=24,
+                  nn=True, nn_bound=1e-3, nn_sample=0.01)
+    g.set_fluid(wtr["U"], wtr["gradp"], wtr["dudt"])
+    g.set_particles(wtr["x"], wtr["v"], wtr["d"], wtr["rho"])
+    g.compute_forces()
+    rng = np.random.default_rng(2024)
+    Lx, Ly = prm["Lx"], prm["Ly"]
+
+    def snapshot():
+        g.translate(rng.uniform(0, Lx), rng.uniform(0, Ly))
+        g.compute_forces()
+        g.deposit()
+
+    raws = []
+    for _ in range(4):
+        snapshot()
+        raws.append(g.get_field(0))
+    raws = np.stack(raws)
+    mean = raws.mean(axis=(0, 2))
+    std = raws.std(axis=(0, 2)) + 1e-30
+    g.nn_set_norm(mean, std)
+    g.nn_init(11)
+    T = args.nn_train_steps
+    losses = []
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.set_profiling(True)
+    for it in range(T):
+        snapshot()
+        g.smooth(4)
+        lr = 1e-5 + 0.5 * (1e-3 - 1e-5) * (1 + math.cos(math.pi * it / max(T, 1)))
+        losses.append(g.nn_train_step(lr))
+    prof = g.profile()
+    g.set_profiling(False)
+    train_s = time.perf_counter() - t1
+    step_ms = prof["nn_train"][0] / max(prof["nn_train"][1], 1)
+    print(f"bench: trained {T} steps in {train_s:.1f} s, loss {np.mean(losses[:5]):.3e} -> "
+          f"{np.mean(losses[-5:]):.3e}", file=sys.stderr, flush=True)
+
+    # held-out snapshots: network error against the plain solve, and the check
+    errs, checks = [], []
+    for _ in range(4):
+        snapshot()
+        g.smooth(4)
+        plain = g.get_field(1)
+        g.nn_forward()
+        nn = g.get_field(1)
+        checks.append(float(g.nn_check().max()))
+        rel = np.linalg.norm(nn - plain, axis=1) / (np.linalg.norm(plain, axis=1) + 1e-300)
+        errs.append([float(np.abs(nn[0] - plain[0]).max())] + [float(r) for r in rel])
+    errs = np.array(errs)
+
+    # coupled 4M-sphere run, averaging every step, per averaging mode
+    g.set_fluid(w4["U"], w4["gradp"], w4["dudt"])
+    g.set_particles(w4["x"], w4["v"], w4["d"], w4["rho"])
+    g.average()
+    g.compute_forces()
+    modes = {}
+    K = args.nn_steps
+    for name, mode in (("plain", sm.AVG_PLAIN), ("surrogate_checked", sm.AVG_SURROGATE_CHECKED),
+                       ("surrogate", sm.AVG_SURROGATE)):
+        g.set_avg_mode(mode)
+        g.step(2, average_every=1)
+        st0 = g.stats()
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        g.step(K, average_every=1)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - c0
+        g.set_profiling(True)
+        g.step(3, average_every=1)
+        pr = g.profile()
+        g.set_profiling(False)
+        st1 = g.stats()
+        avg_ms = (pr["deposit"][0] + pr["smooth"][0]) / max(pr["smooth"][1], 1)
+        calls = st1["nn_calls"] - st0["nn_calls"]
+        modes[name] = {"particle_updates_per_s": round(n4 * K / el, 1),
+                       "ms_per_step": round(1000 * el / K, 3),
+                       "averaging_ms": round(avg_ms, 3),
+                       "fallback_rate": (round((st1["nn_fallbacks"] - st0["nn_fallbacks"]) /
+                                               calls, 3) if calls else None)}
+        print(f"bench: 4M bed, {name}: {modes[name]}", file=sys.stderr, flush=True)
+    g.set_avg_mode(sm.AVG_PLAIN)
+    return {
+        "workload": "fine4m", "mesh": w4["meta"]["mesh"], "particles": n4,
+        "train": {"snapshots": T, "bed": "fine2m, random periodic translations",
+                  "seconds": round(train_s, 2), "ms_per_train_step": round(step_ms, 3),
+                  "loss_first": float(np.mean(losses[:5])), "loss_last": float(np.mean(losses[-5:]))},
+        "error_vs_plain": {"eps_s_maxabs": float(errs[:, 0].max()),
+                           "rel_l2_per_channel": [float(v) for v in errs[:, 1:].max(axis=0)],
+                           "sampled_residual": max(checks), "bound": 1e-3},
+        "modes": modes,
+    }
 
 
 if __name__ == "__main__":

@@ -167,6 +167,10 @@ int sedimi_set_fluid(sedimi_ctx* ctx, const double* U, const double* gradp,
                      const double* dudt);
 /* Overwrite a mesh field (host [4][ncell]). */
 int sedimi_set_field(sedimi_ctx* ctx, int field, const double* in);
+/* Translate every particle by (dx, dy) on the periodic axes (positions
+ * wrapped into [0, L)); relative positions, neighbour lists and contact
+ * history are unchanged.  Used to draw shifted copies of a bed. */
+int sedimi_translate(sedimi_ctx* ctx, double dx, double dy);
 /* Overwrite the stored accelerations a^n (host [n][3], ID order; used by the
  * added-mass lag and the next half kick). */
 int sedimi_set_accel(sedimi_ctx* ctx, const double* a, const double* alpha);

@@ -97,6 +97,7 @@ def lib():
         L.sedimi_set_fluid.argtypes = [P, P, P, P]
         L.sedimi_set_field.argtypes = [P, I, P]
         L.sedimi_set_accel.argtypes = [P, P, P]
+        L.sedimi_translate.argtypes = [P, C.c_double, C.c_double]
         L.sedimi_compute_forces.argtypes = [P, I]
         L.sedimi_step.argtypes = [P, I, I]
         L.sedimi_average.argtypes = [P]
@@ -225,6 +226,9 @@ class Sedimi:
     def set_field(self, which, arr):
         arr = _f64(arr).reshape(4, self.ncell)
         self._chk(self._L.sedimi_set_field(self._ctx, which, _ptr(arr)))
+
+    def translate(self, dx, dy):
+        self._chk(self._L.sedimi_translate(self._ctx, float(dx), float(dy)))
 
     def set_accel(self, a=None, alpha=None):
         a, alpha = _f64(a, (-1, 3)), _f64(alpha, (-1, 3))

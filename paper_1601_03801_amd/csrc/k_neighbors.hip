@@ -325,9 +325,32 @@ __global__ void k_pairmask(DevParams P, DevArrays A, unsigned* out) {
   out[q] = m;
 }
 
+// Periodic translation of positions and of the last-build positions.
+__global__ void k_translate(DevParams P, DevArrays A, double dx, double dy) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= P.n) return;
+  double4 x = A.pos[q], b = A.xb[q];
+  double nx = fmod(x.x + dx, P.Lx), ny = fmod(x.y + dy, P.Ly);
+  if (nx < 0.0) nx += P.Lx;
+  if (ny < 0.0) ny += P.Ly;
+  if (nx >= P.Lx) nx = 0.0;
+  if (ny >= P.Ly) ny = 0.0;
+  b.x += nx - x.x;
+  b.y += ny - x.y;
+  x.x = nx;
+  x.y = ny;
+  A.pos[q] = x;
+  A.xb[q] = b;
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
+
+void launch_translate(const DevParams& P, DevArrays& A, double dx, double dy, hipStream_t s) {
+  if (P.n <= 0) return;
+  hipLaunchKernelGGL(k_translate, dim3(nblk(P.n)), dim3(kBlock), 0, s, P, A, dx, dy);
+}
 
 void launch_pairmask(const DevParams& P, DevArrays& A, unsigned* out, hipStream_t s) {
   if (P.n <= 0) return;

@@ -3,6 +3,8 @@
 // enqueueing of the kernel chains for one step and one averaging.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <cmath>
 #include <string.h>
 
 #include <algorithm>
@@ -553,6 +555,16 @@ int sedimi_set_field(sedimi_ctx* c, int field, const double* in) {
   double* dst = field == SEDIMI_FIELD_RAW ? c->A.raw : c->A.smooth;
   HIPCHK(c, hipMemcpyAsync(dst, in, sizeof(double) * 4 * c->P.ncell, hipMemcpyHostToDevice, c->stream));
   if (field == SEDIMI_FIELD_SMOOTH) launch_pack_eps(c->P, c->A, c->stream);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int sedimi_translate(sedimi_ctx* c, double dx, double dy) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  if (!(std::isfinite(dx) && std::isfinite(dy))) return fail(c, SEDIMI_EINVAL, "non-finite shift");
+  launch_translate(c->P, c->A, dx, dy, c->stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return SEDIMI_OK;

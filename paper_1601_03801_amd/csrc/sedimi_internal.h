@@ -107,6 +107,7 @@ void launch_kick_drift(const DevParams& P, DevArrays& A, hipStream_t s);
 void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixed,
                     hipStream_t s);
 void launch_pairmask(const DevParams& P, DevArrays& A, unsigned* out, hipStream_t s);
+void launch_translate(const DevParams& P, DevArrays& A, double dx, double dy, hipStream_t s);
 void launch_exclusive_scan(int* in_out_count, int* start, int n, int* tmp, bool gated,
                            const Ctl* ctl, hipStream_t s);
 
