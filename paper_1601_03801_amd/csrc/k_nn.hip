@@ -3,9 +3,9 @@
 // residual layers, leaky ReLU, global residual) with BF16 weights and
 // activations, FP32 accumulation on the MFMA units, FP32 output.
 //
-// Convolution as an implicit GEMM on v_mfma_f32_16x16x32_bf16: one wave
-// computes a tile of 16 consecutive cells (M) by 16 output channels (N) per
-// MFMA; K runs over (tap, input channel).  Activations are stored
+// Convolution as an implicit GEMM on v_mfma_f32_16x16x32_bf16: each MFMA
+// computes 16 consecutive cells (M) by 16 output channels (N); K runs over
+// (tap, input channel); a wave works on 4 such cell tiles at once.  Activations are stored
 // channel-last, so the A fragment of a tap (8 consecutive input channels of
 // one neighbour cell per lane) is a single 16-byte load; the layer's weights
 // sit in LDS in the order the B fragments are read.  With 32 input channels
@@ -14,8 +14,8 @@
 //
 // The data gradient of a convolution is the same kernel run with the tap
 // offsets negated and the weights transposed; the weight gradient is a GEMM
-// over cells (K = cells) whose operands are staged through LDS transposed to
-// [channel][cell], with per-block partial sums reduced in a fixed order.
+// over cells (K = cells) whose operands come from LDS through transpose
+// reads, with per-block partial sums reduced in a fixed order.
 #include <math.h>
 
 #include "k_nn.h"
@@ -54,8 +54,14 @@ struct WShape {
   static constexpr int elems = CIN == 32 ? 27 * NT * 16 * 32 : NT * 16 * 128;
 };
 
+// Each wave computes TM tiles of 16 cells at once, so per tap it has TM
+// independent neighbour loads in flight and reuses each B fragment TM times.
+constexpr int TM = 4;
+
+constexpr int kConvThreads = 512;
+
 template <int CIN, int COUT, int EPI>
-__global__ __launch_bounds__(256) void k_conv(ConvGeom g, const __bf16* __restrict__ in,
+__global__ __launch_bounds__(kConvThreads) void k_conv(ConvGeom g, const __bf16* __restrict__ in,
                                               const __bf16* __restrict__ wpk,
                                               const float* __restrict__ bias, EpiArgs e) {
   constexpr int NT = WShape<CIN, COUT>::NT;
@@ -66,82 +72,134 @@ __global__ __launch_bounds__(256) void k_conv(ConvGeom g, const __bf16* __restri
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int row = lane & 15, grp = lane >> 4;
-  const int ntiles = (g.ncell + 15) / 16;
+  const int ngroups = (g.ncell + 16 * TM - 1) / (16 * TM);
+  const int wpb = blockDim.x / 64;
   const v8bf zero8 = {};
-  for (int tile = blockIdx.x * 4 + wave; tile < ntiles; tile += gridDim.x * 4) {
-    const int c = tile * 16 + row;
-    const bool valid = c < g.ncell;
-    const int ci = valid ? c % g.nx : 0;
-    const int cj = valid ? (c / g.nx) % g.ny : 0;
-    const int ck = valid ? c / (g.nx * g.ny) : 0;
-    v4f acc[NT];
+  for (int tg = blockIdx.x * wpb + wave; tg < ngroups; tg += gridDim.x * wpb) {
+    int ci[TM], cj[TM], ck[TM];
+    bool valid[TM];
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) acc[nt] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < TM; ++m) {
+      const int c = (tg * TM + m) * 16 + row;
+      valid[m] = c < g.ncell;
+      ci[m] = valid[m] ? c % g.nx : 0;
+      cj[m] = valid[m] ? (c / g.nx) % g.ny : 0;
+      ck[m] = valid[m] ? c / (g.nx * g.ny) : 0;
+    }
+    v4f acc[TM][NT];
+#pragma unroll
+    for (int m = 0; m < TM; ++m)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[m][nt] = v4f{0.f, 0.f, 0.f, 0.f};
     if (CIN == 32) {
-#pragma unroll 3
+      // software pipeline: the next tap's neighbour fragments are in flight
+      // while the current tap's MFMAs run
+      v8bf a[TM], an[TM];
+#pragma unroll
+      for (int m = 0; m < TM; ++m) {
+        const int q = valid[m] ? tap_cell(g, ci[m], cj[m], ck[m], 0) : -1;
+        a[m] = q >= 0 ? *reinterpret_cast<const v8bf*>(in + (size_t)q * 32 + grp * 8) : zero8;
+      }
       for (int t = 0; t < 27; ++t) {
-        const int q = valid ? tap_cell(g, ci, cj, ck, t) : -1;
-        const v8bf a = q >= 0 ? *reinterpret_cast<const v8bf*>(in + (size_t)q * 32 + grp * 8) : zero8;
+        if (t + 1 < 27) {
+#pragma unroll
+          for (int m = 0; m < TM; ++m) {
+            const int q = valid[m] ? tap_cell(g, ci[m], cj[m], ck[m], t + 1) : -1;
+            an[m] = q >= 0 ? *reinterpret_cast<const v8bf*>(in + (size_t)q * 32 + grp * 8) : zero8;
+          }
+        }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           const v8bf b = *reinterpret_cast<const v8bf*>(sw + ((t * NT + nt) * 16 + row) * 32 + grp * 8);
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
+#pragma unroll
+          for (int m = 0; m < TM; ++m)
+            acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][nt], 0, 0, 0);
         }
+#pragma unroll
+        for (int m = 0; m < TM; ++m) a[m] = an[m];
       }
     } else {
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int t0 = 8 * s + 2 * grp, t1 = t0 + 1;
-        v4bf lo = {}, hi = {};
-        if (valid && t0 < 27) {
-          const int q = tap_cell(g, ci, cj, ck, t0);
-          if (q >= 0) lo = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
+        v8bf a[TM];
+#pragma unroll
+        for (int m = 0; m < TM; ++m) {
+          v4bf lo = {}, hi = {};
+          if (valid[m] && t0 < 27) {
+            const int q = tap_cell(g, ci[m], cj[m], ck[m], t0);
+            if (q >= 0) lo = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
+          }
+          if (valid[m] && t1 < 27) {
+            const int q = tap_cell(g, ci[m], cj[m], ck[m], t1);
+            if (q >= 0) hi = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
+          }
+          a[m] = v8bf{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
         }
-        if (valid && t1 < 27) {
-          const int q = tap_cell(g, ci, cj, ck, t1);
-          if (q >= 0) hi = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
-        }
-        const v8bf a = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           const v8bf b = *reinterpret_cast<const v8bf*>(sw + (nt * 16 + row) * 128 + 32 * s + grp * 8);
-          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nt], 0, 0, 0);
+#pragma unroll
+          for (int m = 0; m < TM; ++m)
+            acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][nt], 0, 0, 0);
         }
       }
     }
-    // epilogue: acc[nt][r] = output (cell tile*16 + 4*grp + r, channel nt*16 + row)
+    // epilogue: acc[m][nt][r] = output (cell (tg*TM + m)*16 + 4*grp + r, channel nt*16 + row)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-      const int n = nt * 16 + row;
-      if (n >= COUT) continue;
+    for (int m = 0; m < TM; ++m)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int co = tile * 16 + 4 * grp + r;
-        if (co >= g.ncell) continue;
-        const size_t o = (size_t)co * COUT + n;
-        float v = acc[nt][r];
-        if (EPI == EPI_FIRST || EPI == EPI_RES) {
-          const float zb = bf(v + bias[n]);
-          if (e.zout) e.zout[o] = (__bf16)zb;
-          float h = leaky(zb, e.alpha);
-          if (EPI == EPI_RES) h += (float)e.hin[o];
-          e.hout[o] = (__bf16)h;
-        } else if (EPI == EPI_LAST) {
-          e.yout[o] = e.xres[o] + v + bias[n];
-        } else {  // EPI_BWD: dh = acc (+ dh of the layer above); dz = dh * phi'(z)
-          float gsum = v + (e.hin ? (float)e.hin[o] : 0.0f);
-          const float gb = bf(gsum);
-          if (e.hout) e.hout[o] = (__bf16)gb;
-          if (e.zout) e.zout[o] = (__bf16)(gb * dleaky((float)e.zin[o], e.alpha));
+      for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 16 + row;
+        if (n >= COUT) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int co = (tg * TM + m) * 16 + 4 * grp + r;
+          if (co >= g.ncell) continue;
+          const size_t o = (size_t)co * COUT + n;
+          float v = acc[m][nt][r];
+          if (EPI == EPI_FIRST || EPI == EPI_RES) {
+            const float zb = bf(v + bias[n]);
+            if (e.zout) e.zout[o] = (__bf16)zb;
+            float h = leaky(zb, e.alpha);
+            if (EPI == EPI_RES) h += (float)e.hin[o];
+            e.hout[o] = (__bf16)h;
+          } else if (EPI == EPI_LAST) {
+            e.yout[o] = e.xres[o] + v + bias[n];
+          } else {  // EPI_BWD: dh = acc (+ dh of the layer above); dz = dh * phi'(z)
+            float gsum = v + (e.hin ? (float)e.hin[o] : 0.0f);
+            const float gb = bf(gsum);
+            if (e.hout) e.hout[o] = (__bf16)gb;
+            if (e.zout) e.zout[o] = (__bf16)(gb * dleaky((float)e.zin[o], e.alpha));
+          }
         }
       }
-    }
   }
 }
 
 // Weight and bias gradients of one convolution: dW[t][i][o] = sum_cells
-// x[nb(c,t)][i] dy[c][o], as per-block partials.  Chunks of 32 cells; wave w
-// owns taps w, w+4, ...; operands transposed through LDS.
+// x[nb(c,t)][i] dy[c][o], as per-block partials.  K of the GEMM runs over
+// cells, so both MFMA operands need 8 consecutive cells of one channel per
+// lane while the activations are channel-last.  The chunk (32 consecutive
+// cells of one x-row) and the 9 input row segments it touches (34 cells
+// each, shared by the three x-taps) are copied into LDS unchanged, and the
+// operands are read with the LDS transpose read (ds_read_b64_tr_b16): within
+// each 16-lane group, lane 4b+a receives element a of the 4-element rows
+// addressed by lanes b, b+4, b+8, b+12.  If lane r addresses cell
+// base + r/4, channels 4(r%4) .. 4(r%4)+3, lane t receives cells base..base+3
+// of channel t.  Wave w owns taps w, w+4, ...
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) v4s lds_v4s;
+
+__device__ __forceinline__ v8bf tr_pair(const __bf16* p0, const __bf16* p1) {
+  v4s a = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)p0);
+  v4s b = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4s*)p1);
+  v8bf r;
+  __builtin_memcpy(&r, &a, 8);
+  __builtin_memcpy(reinterpret_cast<char*>(&r) + 8, &b, 8);
+  return r;
+}
+
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void k_conv_dw(ConvGeom g, const __bf16* __restrict__ x,
                                                  const __bf16* __restrict__ dy,
@@ -151,13 +209,15 @@ __global__ __launch_bounds__(256) void k_conv_dw(ConvGeom g, const __bf16* __res
   constexpr int OP = COUT < 16 ? 16 : COUT;  // padded output channels (N)
   constexpr int MT = CP / 16, NT = OP / 16;
   constexpr int SLOTS = 7;  // taps per wave: ceil(27 / 4)
-  __shared__ __attribute__((aligned(16))) __bf16 dyT[OP][32];
-  __shared__ __attribute__((aligned(16))) __bf16 xT[4][CP][32];
-  __shared__ float bsum[256];
+  constexpr int SEG = 34;   // row segment: cells x0-1 .. x0+32
+  __shared__ __attribute__((aligned(16))) __bf16 xs[9][SEG][CP];
+  __shared__ __attribute__((aligned(16))) __bf16 dys[32][OP];
+  __shared__ float bsum[256][8];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row = lane & 15, grp = lane >> 4;
-  for (int q = threadIdx.x; q < OP * 32; q += 256) (&dyT[0][0])[q] = (__bf16)0.0f;
-  for (int q = threadIdx.x; q < 4 * CP * 32; q += 256) (&xT[0][0][0])[q] = (__bf16)0.0f;
+  const int t16 = lane & 15, grp = lane >> 4;
+  // zero the padding channels once (never overwritten)
+  for (int q = threadIdx.x; q < 9 * SEG * CP; q += 256) (&xs[0][0][0])[q] = (__bf16)0.0f;
+  for (int q = threadIdx.x; q < 32 * OP; q += 256) (&dys[0][0])[q] = (__bf16)0.0f;
   v4f acc[SLOTS][MT][NT];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s)
@@ -165,52 +225,69 @@ __global__ __launch_bounds__(256) void k_conv_dw(ConvGeom g, const __bf16* __res
     for (int a = 0; a < MT; ++a)
 #pragma unroll
       for (int b = 0; b < NT; ++b) acc[s][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  float bacc = 0.0f;  // bias partial for (thread's channel)
-  const int nchunks = (g.ncell + 31) / 32;
+  float bacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int nseg = (g.nx + 31) / 32;
+  const int nchunks = g.ny * g.nz * nseg;
+  constexpr int XU = CIN / 4;   // 8-byte units per cell of x
+  constexpr int YU = COUT / 4;  // 8-byte units per cell of dy
   __syncthreads();
   for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-    const int c0 = ch * 32;
-    // dY chunk -> dyT[o][cell]; a thread always meets the same channel
-    // o = threadIdx.x % COUT (COUT divides 256), so it also sums that
-    // channel for the bias gradient
-    for (int q = threadIdx.x; q < 32 * COUT; q += 256) {
-      const int cl = q / COUT, o = q % COUT;
-      const int c = c0 + cl;
-      const float v = c < g.ncell ? (float)dy[(size_t)c * COUT + o] : 0.0f;
-      dyT[o][cl] = (__bf16)v;
-      bacc += v;
+    const int seg = ch % nseg, row = ch / nseg;
+    const int cj = row % g.ny, ck = row / g.ny;
+    const int x0 = seg * 32;
+    const int len = min(32, g.nx - x0);
+    // dy chunk (cells beyond the row end are zero) + bias partial sums
+    for (int u = threadIdx.x; u < 32 * YU; u += 256) {
+      const int cl = u / YU, blk = u % YU;
+      uint2 v = make_uint2(0u, 0u);
+      if (cl < len) {
+        const size_t c = ((size_t)ck * g.ny + cj) * g.nx + x0 + cl;
+        v = *reinterpret_cast<const uint2*>(dy + c * COUT + blk * 4);
+        const __bf16* e = reinterpret_cast<const __bf16*>(&v);
+        for (int q = 0; q < 4; ++q) bacc[q] += (float)e[q];
+      }
+      *reinterpret_cast<uint2*>(&dys[cl][blk * 4]) = v;
     }
+    // 9 input row segments (dz, dy), periodic in x and y, zero outside z
+    for (int u = threadIdx.x; u < 9 * SEG * XU; u += 256) {
+      const int r = u / (SEG * XU), rem = u % (SEG * XU);
+      const int p = rem / XU, blk = rem % XU;
+      const int dz = r / 3 - 1, dyy = r % 3 - 1;
+      const int kk = ck + g.dil * dz;
+      uint2 v = make_uint2(0u, 0u);
+      if (kk >= 0 && kk < g.nz) {
+        int jj = cj + dyy;
+        jj = jj < 0 ? jj + g.ny : (jj >= g.ny ? jj - g.ny : jj);
+        int ii = x0 - 1 + p;
+        ii = ii < 0 ? ii + g.nx : (ii >= g.nx ? ii - g.nx : ii);
+        const size_t c = ((size_t)kk * g.ny + jj) * g.nx + ii;
+        v = *reinterpret_cast<const uint2*>(x + c * CIN + blk * 4);
+      }
+      *reinterpret_cast<uint2*>(&xs[r][p][blk * 4]) = v;
+    }
+    __syncthreads();
+#pragma unroll
     for (int slot = 0; slot < SLOTS; ++slot) {
       const int t = wave + 4 * slot;
-      __syncthreads();
       if (t < 27) {
-        for (int q = lane; q < 32 * CIN; q += 64) {
-          const int cl = q / CIN, i = q % CIN;
-          const int c = c0 + cl;
-          float v = 0.0f;
-          if (c < g.ncell) {
-            const int qq = tap_cell(g, c % g.nx, (c / g.nx) % g.ny, c / (g.nx * g.ny), t);
-            if (qq >= 0) v = (float)x[(size_t)qq * CIN + i];
-          }
-          xT[wave][i][cl] = (__bf16)v;
-        }
-      }
-      __syncthreads();
-      if (t < 27) {
+        const int r = t / 3, dxi = t % 3;  // row (dz, dy) and x shift + 1
 #pragma unroll
         for (int a = 0; a < MT; ++a) {
-          const v8bf A = *reinterpret_cast<const v8bf*>(&xT[wave][a * 16 + row][grp * 8]);
+          const __bf16* pa = &xs[r][8 * grp + (t16 >> 2) + dxi][16 * a + 4 * (t16 & 3)];
+          const v8bf A = tr_pair(pa, pa + 4 * CP);
 #pragma unroll
           for (int b = 0; b < NT; ++b) {
-            const v8bf B = *reinterpret_cast<const v8bf*>(&dyT[b * 16 + row][grp * 8]);
-            acc[slot][a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[slot][a][b], 0, 0, 0);
+            const __bf16* pb = &dys[8 * grp + (t16 >> 2)][16 * b + 4 * (t16 & 3)];
+            const v8bf B = tr_pair(pb, pb + 4 * OP);
+            acc[slot][a][b] =
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[slot][a][b], 0, 0, 0);
           }
         }
       }
     }
     __syncthreads();
   }
-  // partials: C rows m = a*16 + 4*grp + r (input channel), col n = b*16 + row
+  // partials: C rows m = a*16 + 4*grp + q (input channel), col n = b*16 + t16
   float* pb = part + (size_t)blockIdx.x * 27 * CIN * COUT;
 #pragma unroll
   for (int slot = 0; slot < SLOTS; ++slot) {
@@ -221,17 +298,19 @@ __global__ __launch_bounds__(256) void k_conv_dw(ConvGeom g, const __bf16* __res
 #pragma unroll
       for (int b = 0; b < NT; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = a * 16 + 4 * grp + r, n = b * 16 + row;
-          if (m < CIN && n < COUT) pb[((size_t)t * CIN + m) * COUT + n] = acc[slot][a][b][r];
+        for (int q = 0; q < 4; ++q) {
+          const int m = a * 16 + 4 * grp + q, n = b * 16 + t16;
+          if (m < CIN && n < COUT) pb[((size_t)t * CIN + m) * COUT + n] = acc[slot][a][b][q];
         }
   }
-  bsum[threadIdx.x] = bacc;
+  // bias: thread u (< 32 * YU) always loaded channel block u % YU
+  for (int q = 0; q < 4; ++q) bsum[threadIdx.x][q] = bacc[q];
   __syncthreads();
   if ((int)threadIdx.x < COUT) {
-    float s = 0.0f;
-    for (int q = threadIdx.x; q < 256; q += COUT) s += bsum[q];
-    part_b[(size_t)blockIdx.x * COUT + threadIdx.x] = s;
+    const int blk = threadIdx.x / 4, q = threadIdx.x % 4;
+    float s2 = 0.0f;
+    for (int u = blk; u < 256 && u < 32 * YU; u += YU) s2 += bsum[u][q];
+    part_b[(size_t)blockIdx.x * COUT + threadIdx.x] = s2;
   }
 }
 
@@ -344,13 +423,14 @@ size_t nn_packed_elems(int cin, int cout) {
 
 void launch_conv(int cin, int cout, int epi, const ConvGeom& g, const __bf16* in,
                  const __bf16* wpk, const float* bias, const EpiArgs& e, hipStream_t s) {
-  int ntiles = (g.ncell + 15) / 16;
-  unsigned grid = (unsigned)((ntiles + 3) / 4);
-  if (grid > 2048) grid = 2048;
+  int ngroups = (g.ncell + 16 * TM - 1) / (16 * TM);
+  const int wpb = kConvThreads / 64;
+  unsigned grid = (unsigned)((ngroups + wpb - 1) / wpb);
+  if (grid > 1024) grid = 1024;
   if (grid == 0) return;
 #define SEDIMI_CONV(CI, CO, EP)                                                             \
   if (cin == CI && cout == CO && epi == EP) {                                             \
-    hipLaunchKernelGGL((k_conv<CI, CO, EP>), dim3(grid), dim3(256), 0, s, g, in, wpk, bias, e); \
+    hipLaunchKernelGGL((k_conv<CI, CO, EP>), dim3(grid), dim3(kConvThreads), 0, s, g, in, wpk, bias, e); \
     return;                                                                               \
   }
   SEDIMI_CONV(4, 32, EPI_FIRST)

@@ -153,3 +153,17 @@ def test_residual_check_and_fallback():
     g2.set_avg_mode(sm.AVG_SURROGATE)
     g2.step(2, average_every=1)
     assert g2.stats()["nn_calls"] == 3
+
+
+def test_gradients_ragged_mesh(orc):
+    """x-rows shorter than and not a multiple of the 32-cell weight-gradient chunk."""
+    shape = (10, 7, 9)
+    g, params, raw, mean, std, xh = setup(orc, shape, 8)
+    target = raw * 0.8 + 0.05
+    g.set_field(1, target)
+    g.nn_train_step(0.0)
+    gg = g.nn_get_grads().astype(np.float64)
+    th = ((target.T - mean) / std).astype(np.float32).astype(np.float64)
+    _, go = orc.nn_loss_grad(shape, params, xh, th, C=32, alpha=ALPHA, bf16=True)
+    rel = np.linalg.norm(gg - go) / np.linalg.norm(go)
+    assert rel < 2e-3, rel
