@@ -13,6 +13,7 @@ oracle on the host, a few steps of the same bed), "averaging" (plain solve
 timings) and "phases".
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -24,6 +25,37 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-updates/s at 1M/10M particles; averaging ms plain vs surrogate"
 HBM_PEAK_GBS = 8000.0
+
+
+# HBM traffic of the step-mode force kernel on the 1M-sphere bed (FP64), from
+# two rocprofv3 --pmc runs of this script (FETCH_SIZE, then WRITE_SIZE; KiB
+# per dispatch, mean over the profiled step-mode dispatches), scaled by what
+# the same counters read for a 1 GiB device copy (--copy-calibration: the
+# copy's FETCH_SIZE reads 0.5x the bytes read, WRITE_SIZE 1.0x the bytes
+# written).  Valid only for the kernel sources it was measured on.
+FORCE_PMC = None
+FORCE_SOURCES = ("k_forces.hip", "k_common.h", "sedimi_internal.h")
+
+
+def force_sources_sha():
+    h = hashlib.sha256()
+    for f in FORCE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1601_03801_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def copy_calibration():
+    """Three copies of a 1 GiB device buffer (the reference for the PMC byte
+    counters)."""
+    import torch
+    x = torch.empty(256 * 2 ** 20, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    x.fill_(1.0)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print("bench: copied 1 GiB three times", flush=True)
 
 
 def force_bytes_per_particle(mean_nbr, mean_contacts, mixed):
@@ -49,6 +81,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nn-train-steps", type=int, default=300,
                     help="surrogate training snapshots (0 skips the surrogate section)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run the 1 GiB copy used to scale the PMC byte counters")
     ap.add_argument("--nn-steps", type=int, default=10,
                     help="coupled steps (averaging every step) per averaging mode")
     args = ap.parse_args()
@@ -56,6 +90,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path "
               "has no multi-GPU mode", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
@@ -103,9 +140,14 @@ def main():
     ncell = prm["nx"] * prm["ny"] * prm["nz"]
     bytes_launch = n * bpp + ncell * (3 * 32 + 8)
     achieved = bytes_launch / (f_avg * 1e-3) / 1e9
+    traffic = None
+    if (FORCE_PMC is not None and args.workload == "bed1m" and not mixed
+            and FORCE_PMC["sources_sha256"] == force_sources_sha()):
+        traffic = int(1024 * (FORCE_PMC["fetch_kib"] * FORCE_PMC["fetch_scale"]
+                              + FORCE_PMC["write_kib"] * FORCE_PMC["write_scale"]))
     roofline = {"bound": "hbm", "kernel": "k_forces (step)", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_ms": round(f_avg, 5),
+                "traffic": traffic, "avg_launch_ms": round(f_avg, 5),
                 "bytes_per_launch": int(bytes_launch),
                 "bytes_per_particle": round(bpp, 1)}
     phases = {k: {"ms_per_launch": round(v[0] / max(v[1], 1), 5), "launches": v[1]}
@@ -148,6 +190,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "averaging": {"plain_ms": round(avg_ms, 4),
+                      "solver": "direct" if st["solve_iters"] == 0 else "iterative",
                       "solve_iters": st["solve_iters"], "residual": st["solve_residual"]},
         "phases": phases,
         "surrogate": surrogate,

@@ -111,7 +111,16 @@ typedef struct {
   double nn_bound;           /* fallback when the sampled relative residual exceeds this */
   double nn_sample;          /* fraction of cells in the residual sample */
   uint64_t nn_seed;          /* seed of the residual sample */
+  int avg_solver;            /* SEDIMI_SOLVE_*: how the implicit steps are solved */
 } sedimi_params;
+
+/* solvers of the implicit diffusion steps (Eq. 12) */
+#define SEDIMI_SOLVE_AUTO 0      /* direct when every axis has <= 2048 cells */
+#define SEDIMI_SOLVE_DIRECT 1    /* exact diagonalisation on the uniform mesh:
+                                    Hartley transforms in x and y, DCT-II in z;
+                                    all N_tau steps in one pass; FP64 always */
+#define SEDIMI_SOLVE_ITERATIVE 2 /* Chebyshev iteration per step to avg_rtol
+                                    (FP32 vectors with FP64 residuals in mixed mode) */
 
 /* averaging modes (sedimi_set_avg_mode) */
 #define SEDIMI_AVG_PLAIN 0             /* deposition + implicit diffusion solve */

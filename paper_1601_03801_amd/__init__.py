@@ -21,6 +21,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, EUNSTABLE, EESCAPE, ENOCONV, ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
 DRAG = {"none": 0, "difelice": 1, "stokes": 2}
 FP64, MIXED = 0, 1
+SOLVERS = {"auto": 0, "direct": 1, "iterative": 2}
 FORCE = {"contact": 0, "lub": 1, "drag": 2, "pressure": 3, "added": 4, "total": 5,
          "torque": 6}
 FIELD_RAW, FIELD_SMOOTH = 0, 1
@@ -51,6 +52,7 @@ class sedimi_params(C.Structure):
         ("d_max", C.c_double), ("skin", C.c_double), ("max_neighbors", C.c_int),
         ("nn_enable", C.c_int), ("nn_alpha", C.c_double), ("nn_bound", C.c_double),
         ("nn_sample", C.c_double), ("nn_seed", C.c_uint64),
+        ("avg_solver", C.c_int),
     ]
 
 
@@ -128,7 +130,7 @@ def lib():
 
 def make_params(prm: dict, precision="fp64", skin=None, max_neighbors=24, d_max=None,
                 avg_rtol=1e-12, nn=False, nn_alpha=0.1, nn_bound=1e-3, nn_sample=0.01,
-                nn_seed=12345) -> sedimi_params:
+                nn_seed=12345, solver="auto") -> sedimi_params:
     """sedimi_params from a parameter dict (the oracle's keys plus options)."""
     p = sedimi_params()
     for name, _ in sedimi_params._fields_:
@@ -150,6 +152,7 @@ def make_params(prm: dict, precision="fp64", skin=None, max_neighbors=24, d_max=
     p.nn_bound = prm.get("nn_bound", nn_bound)
     p.nn_sample = prm.get("nn_sample", nn_sample)
     p.nn_seed = prm.get("nn_seed", nn_seed)
+    p.avg_solver = SOLVERS[prm.get("solver", solver)]
     return p
 
 

@@ -5,7 +5,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsedimi.so")
-SOURCES = ["sedimi_api.cpp", "k_neighbors.hip", "k_forces.hip", "k_average.hip", "k_nn.hip"]
+SOURCES = ["sedimi_api.cpp", "k_neighbors.hip", "k_forces.hip", "k_average.hip", "k_nn.hip",
+           "k_spectral.hip"]
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]

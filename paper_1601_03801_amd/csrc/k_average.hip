@@ -366,11 +366,11 @@ int read_check(DevArrays& A, int nblocks, double rel[4], hipStream_t s) {
 }
 
 void launch_deposit(const DevParams& P, DevArrays& A, hipStream_t s) {
-  launch_zero_ints(A.cell_count, P.ncell, false, A.ctl, s);
+  launch_zero_ints(A.cell_count, P.ncell, false, A.rb, s);
   if (P.n > 0) {
     hipLaunchKernelGGL(k_cellkey, dim3(nblk(P.n)), dim3(kBlock), 0, s, P, A);
   }
-  launch_exclusive_scan(A.cell_count, A.cell_start, P.ncell, A.scan_tmp, false, A.ctl, s);
+  launch_exclusive_scan(A.cell_count, A.cell_start, P.ncell, A.scan_tmp, false, A.rb, s);
   if (P.n > 0) {
     hipLaunchKernelGGL(k_cellscatter, dim3(nblk(P.n)), dim3(kBlock), 0, s, P, A);
   }

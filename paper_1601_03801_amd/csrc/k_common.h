@@ -30,6 +30,48 @@ __device__ __forceinline__ bool pair_in_range(double s, double rs, double f) {
   return s < R * R;
 }
 
+// Second half kick of velocity Verlet (explicit FMA, see kick_drift_one).
+__device__ __forceinline__ double4 half_kick(double4 v, double4 a, double hdt, double vw) {
+  return make_double4(fma(hdt, a.x, v.x), fma(hdt, a.y, v.y), fma(hdt, a.z, v.z), vw);
+}
+
+// First half kick and drift of velocity Verlet for one particle: v, w at
+// the start of the step in, half-step values out; x drifts with the new v
+// and is wrapped on the periodic axes.  Raises the escape / non-finite flags
+// and, when the particle has moved more than half the skin since the last
+// list build (minimum image), the rebuild flag *rb.
+__device__ __forceinline__ void kick_drift_one(const DevParams& P, const DevArrays& A, int q,
+                                               double4& x, double4& v, double4& w,
+                                               const double4& a, const double4& al, int* rb) {
+  // explicit FMAs: the same bits whichever kernel this is inlined into
+  const double hdt = 0.5 * P.dt;
+  v.x = fma(hdt, a.x, v.x);
+  v.y = fma(hdt, a.y, v.y);
+  v.z = fma(hdt, a.z, v.z);
+  w.x = fma(hdt, al.x, w.x);
+  w.y = fma(hdt, al.y, w.y);
+  w.z = fma(hdt, al.z, w.z);
+  x.x = fma(P.dt, v.x, x.x);
+  x.y = fma(P.dt, v.y, x.y);
+  x.z = fma(P.dt, v.z, x.z);
+  if (x.x >= P.Lx) x.x -= P.Lx;
+  if (x.x < 0.0) x.x += P.Lx;
+  if (x.x >= P.Lx) x.x = 0.0;
+  if (x.y >= P.Ly) x.y -= P.Ly;
+  if (x.y < 0.0) x.y += P.Ly;
+  if (x.y >= P.Ly) x.y = 0.0;
+  int fl = 0;
+  if (!(x.z >= 0.0 && x.z <= P.Lz)) fl |= 4;
+  if (!(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(v.x) && isfinite(v.y) &&
+        isfinite(v.z)))
+    fl |= 8;
+  if (fl) atomicOr(&A.ctl->flags, fl);
+  const double4 b = A.xb[q];
+  const double dx = min_image(x.x - b.x, P.Lx, P.hLx), dy = min_image(x.y - b.y, P.Ly, P.hLy),
+               dz = x.z - b.z;
+  if (dx * dx + dy * dy + dz * dz > P.half_skin2) atomicOr(rb, 1);
+}
+
 // Bin coordinate of a position (clamped into the grid).
 __device__ __forceinline__ int bin_coord(double x, double h, int n) {
   int b = (int)floor(x / h);

@@ -165,6 +165,9 @@ __device__ __forceinline__ void wall(const DevParams& P, int side, double dist, 
   }
 }
 
+#ifndef SEDIMI_FORCE_PF
+#define SEDIMI_FORCE_PF 0
+#endif
 #ifndef SEDIMI_FORCE_WAVES
 #define SEDIMI_FORCE_WAVES 1
 #endif
@@ -173,9 +176,9 @@ template <typename R, int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SEDIMI_FORCE_WAVES)))
 void k_forces(DevParams P, DevArrays A, int update_history) {
   int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (i == 0 && A.ctl->rebuild) {
+  if (i == 0 && *A.rb) {
     A.ctl->rebuilds += 1;
-    A.ctl->rebuild = 0;
+    *A.rb = 0;
   }
   if (i >= P.n) return;
   const int N = P.n;
@@ -192,18 +195,48 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
   R* hz = hy + (size_t)P.maxn * N;
   const R kn = (R)P.kn, kt = (R)P.kt, mu = (R)P.mu, dtR = (R)P.dt;
 
+#if SEDIMI_FORCE_PF == 0
   for (int k = 0; k < cnt; ++k) {
     const int j = A.nbr[(size_t)k * N + i];
     const double4 pj = A.pos[j];
+#else
+  // software pipeline: neighbour index two slots ahead, its state one ahead
+  int jn1 = cnt > 0 ? A.nbr[i] : i;
+  int jn2 = cnt > 1 ? A.nbr[(size_t)N + i] : i;
+  double4 pn = A.pos[jn1];
+#if SEDIMI_FORCE_PF == 2
+  double4 vn = A.vel[jn1], wn = A.omg[jn1];
+  int idn = A.id[jn1];
+#endif
+  for (int k = 0; k < cnt; ++k) {
+    const int j = jn1;
+    const double4 pj = pn;
+#if SEDIMI_FORCE_PF == 2
+    const double4 vj = vn, wj = wn;
+    const int idj = idn;
+#endif
+    jn1 = jn2;
+    if (k + 2 < cnt) jn2 = A.nbr[(size_t)(k + 2) * N + i];
+    if (k + 1 < cnt) {
+      pn = A.pos[jn1];
+#if SEDIMI_FORCE_PF == 2
+      vn = A.vel[jn1];
+      wn = A.omg[jn1];
+      idn = A.id[jn1];
+#endif
+    }
+#endif
     double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
     double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
     double dz = pj.z - pi.z;
     const double s = pair_s(dx, dy, dz);
     const double rs = ri + pj.w;
     if (!pair_in_range(s, rs, P.lub_out)) continue;
+#if SEDIMI_FORCE_PF != 2
     const int idj = A.id[j];
-    const bool lo = idi < idj;
     const double4 vj = A.vel[j], wj = A.omg[j];
+#endif
+    const bool lo = idi < idj;
     // canonical orientation: from the lower to the higher particle ID
     const double sg = lo ? 1.0 : -1.0;
     dx *= sg;
@@ -289,7 +322,7 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
     Uz += w * u.z;
     es += w * u.w;
     if (P.fluid_forces) {
-      if (MODE == 0) {
+      if (MODE != 1) {
         const double4 g = A.G[I.idx[q]];
         gpx += w * g.x;
         gpy += w * g.y;
@@ -312,7 +345,7 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
   V3<R> Fp{0, 0, 0}, Fa{0, 0, 0};
   if (P.fluid_forces) {
     const double ca = P.c_add * P.rho_f * Vp;
-    if (MODE == 0) {
+    if (MODE != 1) {
       // pressure gradient + added mass together
       Fp = cvt<R>(Vp * gpx - ca * ai.x, Vp * gpy - ca * ai.y, Vp * gpz - ca * ai.z);
     } else {
@@ -327,12 +360,27 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
                                   (double)F.z * im + P.gz, 0.0);
   const double4 al = make_double4((double)T.x / II, (double)T.y / II, (double)T.z / II, 0.0);
   A.acc[i] = an;
+  if (MODE == 2) {
+    // second half kick, then the first half kick and drift of the next step
+    // (the arithmetic of the separate kick-drift kernel); alpha and the drag
+    // are consumed only by a separate kick-drift or a deposition, which never
+    // follow this mode directly
+    const double hdt = 0.5 * P.dt;
+    double4 v = half_kick(vi, an, hdt, mi);
+    double4 w = half_kick(wi, al, hdt, 0.0);
+    double4 x = pi;
+    kick_drift_one(P, A, i, x, v, w, an, al, A.rb_next);
+    A.pos_t[i] = x;
+    A.vel_t[i] = v;
+    A.omg_t[i] = w;
+    return;
+  }
   A.alp[i] = al;
   A.fdr[i] = make_double4((double)Fd.x, (double)Fd.y, (double)Fd.z, 0.0);
   if (MODE == 0) {
     const double hdt = 0.5 * P.dt;
-    A.vel_t[i] = make_double4(vi.x + hdt * an.x, vi.y + hdt * an.y, vi.z + hdt * an.z, mi);
-    A.omg_t[i] = make_double4(wi.x + hdt * al.x, wi.y + hdt * al.y, wi.z + hdt * al.z, 0.0);
+    A.vel_t[i] = half_kick(vi, an, hdt, mi);
+    A.omg_t[i] = half_kick(wi, al, hdt, 0.0);
   } else {
     double4* c = A.comp;
     c[(size_t)0 * N + i] = make_double4(Fc.x, Fc.y, Fc.z, 0.0);
@@ -363,11 +411,15 @@ void launch_forces(const DevParams& P, DevArrays& A, int mode, bool update_histo
   if (mixed) {
     if (mode == 0)
       hipLaunchKernelGGL((k_forces<float, 0>), dim3(g), dim3(kBlock), 0, s, P, A, u);
+    else if (mode == 2)
+      hipLaunchKernelGGL((k_forces<float, 2>), dim3(g), dim3(kBlock), 0, s, P, A, u);
     else
       hipLaunchKernelGGL((k_forces<float, 1>), dim3(g), dim3(kBlock), 0, s, P, A, u);
   } else {
     if (mode == 0)
       hipLaunchKernelGGL((k_forces<double, 0>), dim3(g), dim3(kBlock), 0, s, P, A, u);
+    else if (mode == 2)
+      hipLaunchKernelGGL((k_forces<double, 2>), dim3(g), dim3(kBlock), 0, s, P, A, u);
     else
       hipLaunchKernelGGL((k_forces<double, 1>), dim3(g), dim3(kBlock), 0, s, P, A, u);
   }

@@ -19,10 +19,10 @@ namespace sedimi {
 
 namespace {
 
-__device__ __forceinline__ bool gate(const Ctl* ctl) { return ctl->rebuild != 0; }
+__device__ __forceinline__ bool gate(const int* flag) { return *flag != 0; }
 
-__global__ void k_zero_ints(int* p, int64_t n, int gated, const Ctl* ctl) {
-  if (gated && !gate(ctl)) return;
+__global__ void k_zero_ints(int* p, int64_t n, int gated, const int* flag) {
+  if (gated && !gate(flag)) return;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
 }
@@ -33,43 +33,18 @@ __global__ void k_zero_ints(int* p, int64_t n, int gated, const Ctl* ctl) {
 __global__ void k_kick_drift(DevParams P, DevArrays A) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.n) return;
-  double hdt = 0.5 * P.dt;
   double4 x = A.pos[q], v = A.vel[q], w = A.omg[q];
-  double4 a = A.acc[q], al = A.alp[q];
-  v.x += hdt * a.x;
-  v.y += hdt * a.y;
-  v.z += hdt * a.z;
-  w.x += hdt * al.x;
-  w.y += hdt * al.y;
-  w.z += hdt * al.z;
-  x.x += P.dt * v.x;
-  x.y += P.dt * v.y;
-  x.z += P.dt * v.z;
-  if (x.x >= P.Lx) x.x -= P.Lx;
-  if (x.x < 0.0) x.x += P.Lx;
-  if (x.x >= P.Lx) x.x = 0.0;
-  if (x.y >= P.Ly) x.y -= P.Ly;
-  if (x.y < 0.0) x.y += P.Ly;
-  if (x.y >= P.Ly) x.y = 0.0;
+  const double4 a = A.acc[q], al = A.alp[q];
+  kick_drift_one(P, A, q, x, v, w, a, al, A.rb);
   A.pos[q] = x;
   A.vel[q] = v;
   A.omg[q] = w;
-  int fl = 0;
-  if (!(x.z >= 0.0 && x.z <= P.Lz)) fl |= 4;
-  if (!(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(v.x) && isfinite(v.y) &&
-        isfinite(v.z)))
-    fl |= 8;
-  if (fl) atomicOr(&A.ctl->flags, fl);
-  double4 b = A.xb[q];
-  double dx = min_image(x.x - b.x, P.Lx, P.hLx), dy = min_image(x.y - b.y, P.Ly, P.hLy),
-         dz = x.z - b.z;
-  if (dx * dx + dy * dy + dz * dz > P.half_skin2) atomicOr(&A.ctl->rebuild, 1);
 }
 
 // Active slot history -> (partner ID, xi) rows, before the re-sort.
 template <typename H>
 __global__ void k_compact(DevParams P, DevArrays A) {
-  if (!gate(A.ctl)) return;
+  if (!gate(A.rb)) return;
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P.n) return;
   const int N = P.n;
@@ -96,7 +71,7 @@ __global__ void k_compact(DevParams P, DevArrays A) {
 }
 
 __global__ void k_keys(DevParams P, DevArrays A) {
-  if (!gate(A.ctl)) return;
+  if (!gate(A.rb)) return;
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P.n) return;
   double4 x = A.pos[p];
@@ -106,7 +81,7 @@ __global__ void k_keys(DevParams P, DevArrays A) {
 }
 
 __global__ void k_scatter(DevParams P, DevArrays A) {
-  if (!gate(A.ctl)) return;
+  if (!gate(A.rb)) return;
   int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= P.n) return;
   A.perm[A.bin_start[A.key[p]] + A.rank[p]] = p;
@@ -114,7 +89,7 @@ __global__ void k_scatter(DevParams P, DevArrays A) {
 
 // Order each bin's members by particle ID (bins hold a handful of particles).
 __global__ void k_binsort(DevParams P, DevArrays A) {
-  if (!gate(A.ctl)) return;
+  if (!gate(A.rb)) return;
   int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= P.nbins) return;
   int s = A.bin_start[b], e = A.bin_start[b + 1];
@@ -131,7 +106,7 @@ __global__ void k_binsort(DevParams P, DevArrays A) {
 }
 
 __global__ void k_permute(DevParams P, DevArrays A) {
-  if (!gate(A.ctl)) return;
+  if (!gate(A.rb)) return;
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.n) return;
   int p = A.perm[q];
@@ -147,7 +122,7 @@ __global__ void k_permute(DevParams P, DevArrays A) {
 }
 
 __global__ void k_copyback(DevParams P, DevArrays A) {
-  if (!gate(A.ctl)) return;
+  if (!gate(A.rb)) return;
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.n) return;
   A.pos[q] = A.pos_t[q];
@@ -166,7 +141,7 @@ __global__ void k_copyback(DevParams P, DevArrays A) {
 // matched onto the new slots by partner ID.
 template <typename H>
 __global__ void k_build(DevParams P, DevArrays A) {
-  if (!gate(A.ctl)) return;
+  if (!gate(A.rb)) return;
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.n) return;
   const int N = P.n;
@@ -263,8 +238,8 @@ __device__ int block_exclusive(int v, int* lds, int* total) {
 }
 
 __global__ void k_scan_tiles(const int* cnt, int* start, int n, int* tile_sums, int gated,
-                             const Ctl* ctl) {
-  if (gated && !gate(ctl)) return;
+                             const int* flag) {
+  if (gated && !gate(flag)) return;
   __shared__ int lds[kBlock / 64];
   int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
   int v[kScanItems];
@@ -283,8 +258,8 @@ __global__ void k_scan_tiles(const int* cnt, int* start, int n, int* tile_sums, 
 }
 
 __global__ void k_scan_top(int* tile_sums, int ntiles, int* start, int n, int gated,
-                           const Ctl* ctl) {
-  if (gated && !gate(ctl)) return;
+                           const int* flag) {
+  if (gated && !gate(flag)) return;
   __shared__ int lds[kBlock / 64];
   int carry = 0;
   for (int base = 0; base < ntiles; base += kBlock) {
@@ -299,8 +274,8 @@ __global__ void k_scan_top(int* tile_sums, int ntiles, int* start, int n, int ga
 }
 
 __global__ void k_scan_add(int* start, int n, const int* tile_sums, int gated,
-                           const Ctl* ctl) {
-  if (gated && !gate(ctl)) return;
+                           const int* flag) {
+  if (gated && !gate(flag)) return;
   int base = blockIdx.x * kScanTile;
   int off = tile_sums[blockIdx.x];
   for (int k = threadIdx.x; k < kScanTile; k += kBlock)
@@ -357,21 +332,21 @@ void launch_pairmask(const DevParams& P, DevArrays& A, unsigned* out, hipStream_
   hipLaunchKernelGGL(k_pairmask, dim3(nblk(P.n)), dim3(kBlock), 0, s, P, A, out);
 }
 
-void launch_zero_ints(int* p, int64_t n, bool gated, const Ctl* ctl, hipStream_t s) {
+void launch_zero_ints(int* p, int64_t n, bool gated, const int* flag, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_zero_ints, dim3(nblk(n)), dim3(kBlock), 0, s, p, n, gated ? 1 : 0, ctl);
+  hipLaunchKernelGGL(k_zero_ints, dim3(nblk(n)), dim3(kBlock), 0, s, p, n, gated ? 1 : 0, flag);
 }
 
-void launch_exclusive_scan(int* cnt, int* start, int n, int* tmp, bool gated, const Ctl* ctl,
+void launch_exclusive_scan(int* cnt, int* start, int n, int* tmp, bool gated, const int* flag,
                            hipStream_t s) {
   int ntiles = (n + kScanTile - 1) / kScanTile;
   if (ntiles == 0) ntiles = 1;
   hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, s, cnt, start, n, tmp,
-                     gated ? 1 : 0, ctl);
+                     gated ? 1 : 0, flag);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, ntiles, start, n,
-                     gated ? 1 : 0, ctl);
+                     gated ? 1 : 0, flag);
   hipLaunchKernelGGL(k_scan_add, dim3(ntiles), dim3(kBlock), 0, s, start, n, tmp,
-                     gated ? 1 : 0, ctl);
+                     gated ? 1 : 0, flag);
 }
 
 void launch_kick_drift(const DevParams& P, DevArrays& A, hipStream_t s) {
@@ -383,7 +358,7 @@ void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixe
                     hipStream_t s) {
   if (P.n <= 0) return;
   unsigned g = nblk(P.n);
-  launch_zero_ints(A.bin_count, P.nbins, true, A.ctl, s);
+  launch_zero_ints(A.bin_count, P.nbins, true, A.rb, s);
   if (from_slots) {
     if (mixed)
       hipLaunchKernelGGL(k_compact<float>, dim3(g), dim3(kBlock), 0, s, P, A);
@@ -391,7 +366,7 @@ void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixe
       hipLaunchKernelGGL(k_compact<double>, dim3(g), dim3(kBlock), 0, s, P, A);
   }
   hipLaunchKernelGGL(k_keys, dim3(g), dim3(kBlock), 0, s, P, A);
-  launch_exclusive_scan(A.bin_count, A.bin_start, P.nbins, A.scan_tmp, true, A.ctl, s);
+  launch_exclusive_scan(A.bin_count, A.bin_start, P.nbins, A.scan_tmp, true, A.rb, s);
   hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_binsort, dim3(nblk(P.nbins)), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_permute, dim3(g), dim3(kBlock), 0, s, P, A);

@@ -65,6 +65,9 @@ struct sedimi_ctx {
   bool have_particles = false;
   int64_t last_iters = 0;
   double last_residual = 0.0;
+  bool direct = false;       // the implicit steps are solved by diagonalisation
+  bool last_direct = false;  // the last plain solve was the direct one
+  int check_blocks = 0;      // residual partials of the last direct solve
   std::string err;
   // phase timing
   bool prof = false;
@@ -99,6 +102,10 @@ int fail(sedimi_ctx* c, int code, const std::string& msg) {
   } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Largest axis of the direct diffusion solve (its transform tables grow as
+// n^2 and its work per cell as n).
+constexpr int kDirectMaxAxis = 2048;
 
 // Workspace carving: the same walk computes the size (base == nullptr) and
 // assigns the pointers.
@@ -167,12 +174,15 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
   a.sxf = w.take<double>(4 * nc);
   a.stmp = w.take<double>(4 * nc);
   a.ztab = w.take<double>(2 * (size_t)c->P.nz);
+  a.spec = w.take<double>(c->direct ? spectral_table_doubles(c->P) : 0);
   a.cell_count = w.take<int>(nc + 1);
   a.cell_start = w.take<int>(nc + 1);
   a.red = w.take<double>(smooth_red_doubles((int)nc, 4, std::max(1, c->prm.avg_ntau)));
   // kept across sedimi_set_particles (which clears everything before U)
   a.bin_rank = w.take<int>(nb);
   a.ctl = w.take<Ctl>(1);
+  a.rb = a.ctl ? &a.ctl->rebuild : nullptr;
+  a.rb_next = a.ctl ? &a.ctl->rebuild_alt : nullptr;
   if (A) *A = a;
   if (c->prm.nn_enable) {
     NNBufs b;
@@ -229,6 +239,10 @@ int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
     return fail(c, SEDIMI_EINVAL, "max_neighbors must be in 1..30");
   if (p.nn_enable && !(p.nn_alpha >= 0 && p.nn_bound > 0 && p.nn_sample > 0 && p.nn_sample <= 1))
     return fail(c, SEDIMI_EINVAL, "surrogate parameters out of range");
+  if (p.avg_solver < SEDIMI_SOLVE_AUTO || p.avg_solver > SEDIMI_SOLVE_ITERATIVE)
+    return fail(c, SEDIMI_EINVAL, "unknown averaging solver");
+  if (p.avg_solver == SEDIMI_SOLVE_DIRECT && std::max(p.nx, std::max(p.ny, p.nz)) > kDirectMaxAxis)
+    return fail(c, SEDIMI_EINVAL, "direct averaging solve needs <= 2048 cells per axis");
   return SEDIMI_OK;
 }
 
@@ -299,8 +313,7 @@ int flags_to_rc(sedimi_ctx* c, int flags) {
 
 int set_rebuild_flag(sedimi_ctx* c) {
   int one = 1;
-  HIPCHK(c, hipMemcpyAsync(&c->A.ctl->rebuild, &one, sizeof(int), hipMemcpyHostToDevice,
-                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->A.rb, &one, sizeof(int), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return SEDIMI_OK;
 }
@@ -341,10 +354,36 @@ void phase_end(sedimi_ctx* c) {
 void nn_run_forward(sedimi_ctx* c, bool keep);
 int nn_check_smooth(sedimi_ctx* c, double rel[4]);
 
-int64_t do_average_plain(sedimi_ctx* c) {
+// Plain solve of channels [0, nch) of RAW into SMOOTH.  Returns the solver
+// iterations (0 for the direct solve).  The direct solve is followed by the
+// full-field residual r = A^N_tau y - raw (A = I - Delta tau L_h) for
+// check_solve.
+int64_t plain_solve(sedimi_ctx* c, int nch) {
+  const int ntau = c->prm.avg_ntau;
   double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
+  c->last_direct = c->direct && ntau > 0;
+  if (c->last_direct) {
+    launch_spectral(c->P, c->A, nch, ntau, tau, c->stream);
+    c->check_blocks = launch_check(c->P, c->A, c->A.smooth, ntau, tau, 0, 1.0, c->stream);
+    return 0;
+  }
   const double rtol = c->mixed ? std::max(c->prm.avg_rtol, 1e-6) : c->prm.avg_rtol;
-  return launch_smooth(c->P, c->A, 4, c->prm.avg_ntau, tau, rtol, c->mixed, c->stream);
+  return launch_smooth(c->P, c->A, nch, ntau, tau, rtol, c->mixed, c->stream);
+}
+
+int64_t do_average_plain(sedimi_ctx* c) { return plain_solve(c, 4); }
+
+// Residual bound of the direct solve: a backward-stable y has
+// |A^N y - raw| <= c eps |A|^N |y| with |A| <= 1 + Delta tau lambda_max.
+double direct_tol(const sedimi_ctx* c) {
+  const DevParams& P = c->P;
+  const int ntau = std::max(1, c->prm.avg_ntau);
+  const double dtau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth / ntau;
+  double lam = 0.0;
+  if (P.nx > 1) lam += 4.0 / (P.hx * P.hx);
+  if (P.ny > 1) lam += 4.0 / (P.hy * P.hy);
+  if (P.nz > 1) lam += 4.0 / (P.hz * P.hz);
+  return std::max(c->prm.avg_rtol, 1e-13 * pow(1.0 + dtau * lam, (double)ntau));
 }
 
 // One averaging in the current mode.  Returns the solver iterations (0 when
@@ -380,6 +419,17 @@ int64_t do_average(sedimi_ctx* c, bool* used_plain) {
 }
 
 int check_solve(sedimi_ctx* c, int nch) {
+  if (c->last_direct) {
+    double rel[4];
+    if (read_check(c->A, c->check_blocks, rel, c->stream))
+      return fail(c, SEDIMI_EDEVICE, "reading the solver residual failed");
+    double res = 0.0;
+    for (int ch = 0; ch < nch; ++ch) res = std::max(res, rel[ch]);
+    c->last_residual = res;
+    if (!(res <= direct_tol(c) * 10.0))
+      return fail(c, SEDIMI_ENOCONV, "direct diffusion solve residual above its bound");
+    return SEDIMI_OK;
+  }
   double res = read_smooth_residual(c->P, c->A, nch, c->prm.avg_ntau, c->stream);
   if (res < 0) return fail(c, SEDIMI_EDEVICE, "reading the solver residual failed");
   c->last_residual = res;
@@ -403,6 +453,9 @@ int sedimi_create(const sedimi_params* p, int64_t max_particles, sedimi_ctx** ou
   c->prm = *p;
   c->cap = max_particles;
   c->mixed = p->precision == SEDIMI_MIXED;
+  c->direct = p->avg_solver == SEDIMI_SOLVE_DIRECT ||
+              (p->avg_solver == SEDIMI_SOLVE_AUTO &&
+               std::max(p->nx, std::max(p->ny, p->nz)) <= kDirectMaxAxis);
   if (rc == SEDIMI_OK) {
     fill_dev_params(c);
     if (c->P.nbx < 3 || c->P.nby < 3)
@@ -459,6 +512,13 @@ int sedimi_bind_workspace(sedimi_ctx* c, void* dev_ptr, size_t bytes) {
     smooth_ztab(P, std::max(1, c->prm.avg_ntau), tau, zt.data());
     HIPCHK(c, hipMemcpyAsync(c->A.ztab, zt.data(), sizeof(double) * zt.size(),
                              hipMemcpyHostToDevice, c->stream));
+    if (c->direct) {
+      std::vector<double> st(spectral_table_doubles(P));
+      spectral_tables(P, st.data());
+      HIPCHK(c, hipMemcpyAsync(c->A.spec, st.data(), sizeof(double) * st.size(),
+                               hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -500,6 +560,8 @@ int sedimi_set_particles(sedimi_ctx* c, int64_t n, const double* x, const double
   // layout) and the control block; mesh fields are kept
   HIPCHK(c, hipMemsetAsync(c->ws, 0, (size_t)((char*)c->A.U - c->ws), c->stream));
   HIPCHK(c, hipMemsetAsync(c->A.ctl, 0, sizeof(Ctl), c->stream));
+  c->A.rb = &c->A.ctl->rebuild;
+  c->A.rb_next = &c->A.ctl->rebuild_alt;
   if (n > 0) {
     HIPCHK(c, hipMemcpyAsync(c->A.pos, pos.data(), sizeof(double4) * n, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->A.vel, vel.data(), sizeof(double4) * n, hipMemcpyHostToDevice, c->stream));
@@ -608,20 +670,33 @@ int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
   if (rc) return rc;
   if (nsteps < 0) return fail(c, SEDIMI_EINVAL, "nsteps must be >= 0");
   bool averaged = false;
+  // A step whose successor is in this call and is not preceded by an
+  // averaging fuses the successor's half kick and drift into its force
+  // kernel; the state between calls is always the end of a whole step.
+  bool drifted = false;
   for (int s = 0; s < nsteps; ++s) {
-    phase_begin(c, 0);
-    launch_kick_drift(c->P, c->A, c->stream);
-    phase_end(c);
+    if (!drifted) {
+      phase_begin(c, 0);
+      launch_kick_drift(c->P, c->A, c->stream);
+      phase_end(c);
+    }
     phase_begin(c, 1);
     launch_rebuild(c->P, c->A, true, c->mixed, c->stream);
     phase_end(c);
+    const bool avg_now = average_every > 0 && (c->step + 1) % average_every == 0;
+    const bool fuse = s + 1 < nsteps && !avg_now;
     phase_begin(c, 2);
-    launch_forces(c->P, c->A, 0, true, c->mixed, c->stream);
+    launch_forces(c->P, c->A, fuse ? 2 : 0, true, c->mixed, c->stream);
     phase_end(c);
     std::swap(c->A.vel, c->A.vel_t);
     std::swap(c->A.omg, c->A.omg_t);
+    if (fuse) {
+      std::swap(c->A.pos, c->A.pos_t);
+      std::swap(c->A.rb, c->A.rb_next);
+    }
+    drifted = fuse;
     ++c->step;
-    if (average_every > 0 && c->step % average_every == 0) {
+    if (avg_now) {
       bool plain = true;
       int64_t it = do_average(c, &plain);
       if (it < 0) return (int)it;
@@ -667,10 +742,7 @@ int sedimi_smooth(sedimi_ctx* c, int nch) {
   int rc = need_ws(c);
   if (rc) return rc;
   if (nch < 1 || nch > 4) return fail(c, SEDIMI_EINVAL, "nch must be 1..4");
-  double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
-  const double rtol = c->mixed ? std::max(c->prm.avg_rtol, 1e-6) : c->prm.avg_rtol;
-  c->last_iters = launch_smooth(c->P, c->A, nch, c->prm.avg_ntau, tau, rtol, c->mixed,
-                                c->stream);
+  c->last_iters = plain_solve(c, nch);
   launch_pack_eps(c->P, c->A, c->stream);
   HIPCHK(c, hipGetLastError());
   return check_solve(c, nch);
@@ -846,13 +918,15 @@ int sedimi_set_history(sedimi_ctx* c, int64_t nrec, const void* records) {
   HIPCHK(c, hipMemcpyAsync(c->A.cxi, cxi.data(), sizeof(double) * cxi.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->A.ccnt, ccnt.data(), sizeof(int) * n, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipMemcpyAsync(c->A.wxi, wxi.data(), sizeof(double4) * 2 * n, hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, hipMemsetAsync(c->A.ctl, 0, sizeof(int) * 2, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->A.ctl, 0, sizeof(int) * 4, c->stream));
+  c->A.rb = &c->A.ctl->rebuild;
+  c->A.rb_next = &c->A.ctl->rebuild_alt;
   rc = set_rebuild_flag(c);
   if (rc) return rc;
   launch_rebuild(c->P, c->A, false, c->mixed, c->stream);
   // the next force kernel clears the rebuild flag; do it here for a clean state
   int zero = 0;
-  HIPCHK(c, hipMemcpyAsync(&c->A.ctl->rebuild, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->A.rb, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
   Ctl ctl;
   if ((rc = read_ctl(c, &ctl))) return rc;
   if (ctl.flags & 2) return fail(c, SEDIMI_EINVAL, "a history pair is not in the neighbour list");

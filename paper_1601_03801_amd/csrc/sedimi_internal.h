@@ -47,10 +47,10 @@ inline unsigned xcd_grid(int64_t nblocks) {
 
 // Flags and counters living in device memory.
 struct Ctl {
-  int rebuild;       // a rebuild is pending for this step
+  int rebuild;       // rebuild flags: DevArrays::rb points at the one of the
   int flags;         // bit 0 overflow, 1 lost contact, 2 escape, 3 non-finite
   int max_nbr;       // largest neighbour count at a build
-  int pad0;
+  int rebuild_alt;   // current step, rb_next at the other (see there)
   long long rebuilds;
   long long pad1[5];
 };
@@ -96,24 +96,33 @@ struct DevArrays {
   double *raw, *smooth, *sx, *sr, *sd0, *sd1;
   double *sxf, *stmp;  // solver: FP32 iterate (mixed mode), column-sweep scratch
   double* ztab;        // z-line preconditioner: reciprocal pivots, super-diagonal
+  double* spec;        // direct solve: H_x, H_y, C_z, C_z^-1, per-axis eigenvalues
   int *cell_count, *cell_start, *cperm;
   double* red;  // reduction partials
   Ctl* ctl;
+  // Rebuild flags.  *rb: a rebuild is due before this step's forces (set by
+  // the drift, read by every rebuild kernel, cleared by the force kernel).  A
+  // force kernel that also drifts to the next step sets *rb_next instead; the
+  // host then swaps the two pointers.
+  int* rb;
+  int* rb_next;
 };
 
 // ---- launchers (k_neighbors.hip) ----
-void launch_zero_ints(int* p, int64_t n, bool gated, const Ctl* ctl, hipStream_t s);
+void launch_zero_ints(int* p, int64_t n, bool gated, const int* flag, hipStream_t s);
 void launch_kick_drift(const DevParams& P, DevArrays& A, hipStream_t s);
 void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixed,
                     hipStream_t s);
 void launch_pairmask(const DevParams& P, DevArrays& A, unsigned* out, hipStream_t s);
 void launch_translate(const DevParams& P, DevArrays& A, double dx, double dy, hipStream_t s);
 void launch_exclusive_scan(int* in_out_count, int* start, int n, int* tmp, bool gated,
-                           const Ctl* ctl, hipStream_t s);
+                           const int* flag, hipStream_t s);
 
 // ---- launchers (k_forces.hip) ----
 // mode: 0 = step (second half kick, writes vel_t/omg_t), 1 = evaluation with
-// breakdown (writes comp, acc, alp); update_history as in sedimi_compute_forces.
+// breakdown (writes comp, acc, alp), 2 = step fused with the first half kick
+// and drift of the next step (writes pos_t/vel_t/omg_t/acc, sets *rb_next);
+// update_history as in sedimi_compute_forces.
 void launch_forces(const DevParams& P, DevArrays& A, int mode, bool update_history,
                    bool mixed, hipStream_t s);
 // Copy channel 0 of the smoothed field (solid fraction) into U.w.
@@ -140,5 +149,13 @@ void smooth_ztab(const DevParams& P, int ntau, double tau, double* host_tab);
 int launch_check(const DevParams& P, DevArrays& A, const double* y, int ntau, double tau,
                  uint64_t seed, double frac, hipStream_t s);
 int read_check(DevArrays& A, int nblocks, double rel[4], hipStream_t s);
+
+// ---- launchers (k_spectral.hip) ----
+// Direct solve of all N_tau implicit steps on the uniform mesh: channels
+// [0, nch) of raw into smooth (A.sr and A.stmp as scratch).
+void launch_spectral(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
+                     hipStream_t s);
+size_t spectral_table_doubles(const DevParams& P);
+void spectral_tables(const DevParams& P, double* host_tab);
 
 }  // namespace sedimi

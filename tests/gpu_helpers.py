@@ -28,13 +28,15 @@ def dense_bed(n, seed, poly=True, jitter=0.002, Lfac=1.0):
                 gradp=gradp, dudt=dudt)
 
 
-def gpu_context(case, precision="fp64", skin_frac=0.1, max_neighbors=24, cap=None):
+def gpu_context(case, precision="fp64", skin_frac=0.1, max_neighbors=24, cap=None,
+                solver="auto"):
     import paper_1601_03801_amd as sm
     prm = dict(case["params"])
     dmax = float(np.max(case["d"])) if len(case["d"]) else workloads.D50
     n = len(case["d"])
     g = sm.Sedimi(prm, cap if cap is not None else max(n, 1), precision=precision,
-                  d_max=dmax, skin=skin_frac * dmax, max_neighbors=max_neighbors)
+                  d_max=dmax, skin=skin_frac * dmax, max_neighbors=max_neighbors,
+                  solver=solver)
     g.set_fluid(case.get("U"), case.get("gradp"), case.get("dudt"))
     g.set_particles(case["x"], case["v"], case["d"], case["rho"], omega=case.get("w"))
     return g
