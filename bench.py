@@ -83,6 +83,8 @@ def main():
                     help="surrogate training snapshots (0 skips the surrogate section)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy used to scale the PMC byte counters")
+    ap.add_argument("--nn-alpha", type=float, default=0.1,
+                    help="leaky-ReLU slope of the surrogate (1 makes the network linear)")
     ap.add_argument("--nn-steps", type=int, default=10,
                     help="coupled steps (averaging every step) per averaging mode")
     args = ap.parse_args()
@@ -222,7 +224,7 @@ def surrogate_section(args):
     dmax = float(max(wtr["d"].max(), w4["d"].max()))
     n4 = len(w4["d"])
     g = sm.Sedimi(prm, n4, precision="mixed", d_max=dmax, skin=0.1 * dmax, max_neighbors=24,
-                  nn=True, nn_bound=1e-3, nn_sample=0.01)
+                  nn=True, nn_alpha=args.nn_alpha, nn_bound=1e-3, nn_sample=0.01)
     g.set_fluid(wtr["U"], wtr["gradp"], wtr["dudt"])
     g.set_particles(wtr["x"], wtr["v"], wtr["d"], wtr["rho"])
     g.compute_forces()
@@ -306,6 +308,7 @@ def surrogate_section(args):
     g.set_avg_mode(sm.AVG_PLAIN)
     return {
         "workload": "fine4m", "mesh": w4["meta"]["mesh"], "particles": n4,
+        "leaky_relu_alpha": args.nn_alpha,
         "train": {"snapshots": T, "bed": "fine2m, random periodic translations",
                   "seconds": round(train_s, 2), "ms_per_train_step": round(step_ms, 3),
                   "loss_first": float(np.mean(losses[:5])), "loss_last": float(np.mean(losses[-5:]))},

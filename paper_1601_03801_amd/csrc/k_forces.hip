@@ -165,6 +165,85 @@ __device__ __forceinline__ void wall(const DevParams& P, int side, double dist, 
   }
 }
 
+// One pair (i, slot k, partner j) already known to be in the pair set: its
+// lubrication and contact forces on i and the contact torque on i.  The
+// operands are put in lower-ID -> higher-ID order before any arithmetic, so
+// both sides of the pair compute the same bits; the result is added with the
+// sign of i's side.  Updates slot k's tangential history.
+template <typename R>
+__device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& A, int N, int i,
+                                           int k, int j, const double4& pi, const double4& vi,
+                                           const double4& wi, int idi, unsigned mask_old,
+                                           bool upd, V3<R>& Fc, V3<R>& Fl, V3<R>& T,
+                                           unsigned& mask_new) {
+  const double4 pj = A.pos[j];
+  double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
+  double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
+  double dz = pj.z - pi.z;
+  const double s = pair_s(dx, dy, dz);
+  const double ri = pi.w, mi = vi.w;
+  const double rs = ri + pj.w;
+  const R kn = (R)P.kn, kt = (R)P.kt, mu = (R)P.mu, dtR = (R)P.dt;
+  R* hx = (R*)A.hxi;
+  R* hy = hx + (size_t)P.maxn * N;
+  R* hz = hy + (size_t)P.maxn * N;
+  const int idj = A.id[j];
+  const double4 vj = A.vel[j], wj = A.omg[j];
+  const bool lo = idi < idj;
+  // canonical orientation: from the lower to the higher particle ID
+  const double sg = lo ? 1.0 : -1.0;
+  dx *= sg;
+  dy *= sg;
+  dz *= sg;
+  const double dist = sqrt(s);
+  const double inv = 1.0 / dist;
+  const V3<R> n = cvt<R>(dx * inv, dy * inv, dz * inv);
+  const double4 vlo = lo ? vi : vj, vhi = lo ? vj : vi;
+  const double4 wlo = lo ? wi : wj, whi = lo ? wj : wi;
+  const double rlo = lo ? ri : pj.w, rhi = lo ? pj.w : ri;
+  const V3<R> dv = cvt<R>(vlo.x - vhi.x, vlo.y - vhi.y, vlo.z - vhi.z);
+  const V3<R> rw = (R)rlo * cvt<R>(wlo.x, wlo.y, wlo.z) + (R)rhi * cvt<R>(whi.x, whi.y, whi.z);
+  const V3<R> vrel = dv + cross(rw, n);
+  const R un = dot(vrel, n);
+  V3<R> Fpl{0, 0, 0}, Fpc{0, 0, 0};
+  if (P.lubrication) {
+    const double h = dist - rs, hin = P.lub_in * rs;
+    const R hh = (R)(h > hin ? h : hin);
+    const R aeff = (R)(rlo * rhi / rs);
+    const R Flub = (R)(6.0 * kPi * P.mu_f) * aeff * aeff * un / hh;
+    Fpl = (-Flub) * n;
+  }
+  const double delta = rs - dist;
+  V3<R> Tp{0, 0, 0};
+  if (delta > 0.0) {
+    const double mlo = lo ? mi : vj.w, mhi = lo ? vj.w : mi;
+    const R meff = (R)(mlo * mhi / (mlo + mhi));
+    const R gn = (R)(2.0 * P.zeta) * sqrt(meff * kn);
+    const R gt = (R)P.gt_over_gn * gn;
+    const R Frep = kn * (R)delta + gn * un;
+    V3<R> xi{0, 0, 0};
+    const size_t o = (size_t)k * N + i;
+    if (mask_old & (1u << k)) xi = V3<R>{hx[o], hy[o], hz[o]};
+    const V3<R> ft = tangential<R>(kt, gt, mu, dtR, n, vrel, un, fabs(Frep), xi);
+    Fpc = ft - Frep * n;
+    Tp = (R)(lo ? rlo : rhi) * cross(n, ft);
+    if (upd) {
+      hx[o] = xi.x;
+      hy[o] = xi.y;
+      hz[o] = xi.z;
+      mask_new |= 1u << k;
+    }
+  }
+  if (lo) {
+    Fc = Fc + Fpc;
+    Fl = Fl + Fpl;
+  } else {
+    Fc = Fc - Fpc;
+    Fl = Fl - Fpl;
+  }
+  T = T + Tp;
+}
+
 #ifndef SEDIMI_FORCE_PF
 #define SEDIMI_FORCE_PF 0
 #endif
@@ -190,107 +269,49 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
   const unsigned mask_old = A.hmask[i];
   unsigned mask_new = 0;
   const int cnt = A.ncnt[i];
-  R* hx = (R*)A.hxi;
-  R* hy = hx + (size_t)P.maxn * N;
-  R* hz = hy + (size_t)P.maxn * N;
-  const R kn = (R)P.kn, kt = (R)P.kt, mu = (R)P.mu, dtR = (R)P.dt;
 
 #if SEDIMI_FORCE_PF == 0
   for (int k = 0; k < cnt; ++k) {
     const int j = A.nbr[(size_t)k * N + i];
     const double4 pj = A.pos[j];
+    const double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
+    const double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
+    const double s = pair_s(dx, dy, pj.z - pi.z);
+    if (!pair_in_range(s, ri + pj.w, P.lub_out)) continue;
+    pair_force<R>(P, A, N, i, k, j, pi, vi, wi, idi, mask_old, upd, Fc, Fl, T, mask_new);
+  }
 #else
-  // software pipeline: neighbour index two slots ahead, its state one ahead
-  int jn1 = cnt > 0 ? A.nbr[i] : i;
-  int jn2 = cnt > 1 ? A.nbr[(size_t)N + i] : i;
-  double4 pn = A.pos[jn1];
-#if SEDIMI_FORCE_PF == 2
-  double4 vn = A.vel[jn1], wn = A.omg[jn1];
-  int idn = A.id[jn1];
-#endif
+  // Classify the slots first (pair range; likely contact when s < (r_i+r_j)^2),
+  // then walk the likely contacts and the lubrication-only pairs in two
+  // separate loops, so that the lanes of a wave take the same path in each
+  // iteration instead of the contact path whenever any lane has a contact.
+  unsigned conm = 0, lubm = 0;
   for (int k = 0; k < cnt; ++k) {
-    const int j = jn1;
-    const double4 pj = pn;
-#if SEDIMI_FORCE_PF == 2
-    const double4 vj = vn, wj = wn;
-    const int idj = idn;
-#endif
-    jn1 = jn2;
-    if (k + 2 < cnt) jn2 = A.nbr[(size_t)(k + 2) * N + i];
-    if (k + 1 < cnt) {
-      pn = A.pos[jn1];
-#if SEDIMI_FORCE_PF == 2
-      vn = A.vel[jn1];
-      wn = A.omg[jn1];
-      idn = A.id[jn1];
-#endif
-    }
-#endif
-    double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
-    double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
-    double dz = pj.z - pi.z;
-    const double s = pair_s(dx, dy, dz);
+    const int j = A.nbr[(size_t)k * N + i];
+    const double4 pj = A.pos[j];
+    const double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
+    const double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
+    const double s = pair_s(dx, dy, pj.z - pi.z);
     const double rs = ri + pj.w;
     if (!pair_in_range(s, rs, P.lub_out)) continue;
-#if SEDIMI_FORCE_PF != 2
-    const int idj = A.id[j];
-    const double4 vj = A.vel[j], wj = A.omg[j];
-#endif
-    const bool lo = idi < idj;
-    // canonical orientation: from the lower to the higher particle ID
-    const double sg = lo ? 1.0 : -1.0;
-    dx *= sg;
-    dy *= sg;
-    dz *= sg;
-    const double dist = sqrt(s);
-    const double inv = 1.0 / dist;
-    const V3<R> n = cvt<R>(dx * inv, dy * inv, dz * inv);
-    const double4 vlo = lo ? vi : vj, vhi = lo ? vj : vi;
-    const double4 wlo = lo ? wi : wj, whi = lo ? wj : wi;
-    const double rlo = lo ? ri : pj.w, rhi = lo ? pj.w : ri;
-    const V3<R> dv = cvt<R>(vlo.x - vhi.x, vlo.y - vhi.y, vlo.z - vhi.z);
-    const V3<R> rw = (R)rlo * cvt<R>(wlo.x, wlo.y, wlo.z) + (R)rhi * cvt<R>(whi.x, whi.y, whi.z);
-    const V3<R> vrel = dv + cross(rw, n);
-    const R un = dot(vrel, n);
-    V3<R> Fpl{0, 0, 0}, Fpc{0, 0, 0};
-    if (P.lubrication) {
-      const double h = dist - rs, hin = P.lub_in * rs;
-      const R hh = (R)(h > hin ? h : hin);
-      const R aeff = (R)(rlo * rhi / rs);
-      const R Flub = (R)(6.0 * kPi * P.mu_f) * aeff * aeff * un / hh;
-      Fpl = (-Flub) * n;
-    }
-    const double delta = rs - dist;
-    V3<R> Tp{0, 0, 0};
-    if (delta > 0.0) {
-      const double mlo = lo ? mi : vj.w, mhi = lo ? vj.w : mi;
-      const R meff = (R)(mlo * mhi / (mlo + mhi));
-      const R gn = (R)(2.0 * P.zeta) * sqrt(meff * kn);
-      const R gt = (R)P.gt_over_gn * gn;
-      const R Frep = kn * (R)delta + gn * un;
-      V3<R> xi{0, 0, 0};
-      if (mask_old & (1u << k)) {
-        xi = V3<R>{hx[(size_t)k * N + i], hy[(size_t)k * N + i], hz[(size_t)k * N + i]};
-      }
-      const V3<R> ft = tangential<R>(kt, gt, mu, dtR, n, vrel, un, fabs(Frep), xi);
-      Fpc = ft - Frep * n;
-      Tp = (R)(lo ? rlo : rhi) * cross(n, ft);
-      if (upd) {
-        hx[(size_t)k * N + i] = xi.x;
-        hy[(size_t)k * N + i] = xi.y;
-        hz[(size_t)k * N + i] = xi.z;
-        mask_new |= 1u << k;
-      }
-    }
-    if (lo) {
-      Fc = Fc + Fpc;
-      Fl = Fl + Fpl;
-    } else {
-      Fc = Fc - Fpc;
-      Fl = Fl - Fpl;
-    }
-    T = T + Tp;
+    if (s < rs * rs)
+      conm |= 1u << k;
+    else
+      lubm |= 1u << k;
   }
+  while (conm) {
+    const int k = __builtin_ctz(conm);
+    conm &= conm - 1;
+    pair_force<R>(P, A, N, i, k, A.nbr[(size_t)k * N + i], pi, vi, wi, idi, mask_old, upd, Fc,
+                  Fl, T, mask_new);
+  }
+  while (lubm) {
+    const int k = __builtin_ctz(lubm);
+    lubm &= lubm - 1;
+    pair_force<R>(P, A, N, i, k, A.nbr[(size_t)k * N + i], pi, vi, wi, idi, mask_old, upd, Fc,
+                  Fl, T, mask_new);
+  }
+#endif
   // flat walls (history validity in mask bits 30 / 31)
   {
     const V3<R> v = cvt<R>(vi.x, vi.y, vi.z);

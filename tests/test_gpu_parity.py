@@ -199,7 +199,7 @@ def test_fused_drift_matches_separate_steps():
     case = dict(case, params=prm)
     gs = []
     for _ in range(2):
-        g = gpu_context(case, skin_frac=0.02)
+        g = gpu_context(case, skin_frac=0.0)  # zero skin: a rebuild every step
         g.average()
         g.compute_forces(update_history=False)
         gs.append(g)
@@ -220,7 +220,7 @@ def test_fused_drift_matches_separate_steps():
     errs["eps"] = np.abs(fa[0] - fb[0]).max()
     sa, sb = gs[0].stats(), gs[1].stats()
     print("fused vs separate", errs, "rebuilds", sa["rebuilds"], sb["rebuilds"])
-    assert sa["rebuilds"] == sb["rebuilds"] >= 2
+    assert sa["rebuilds"] == sb["rebuilds"] >= 10
     assert errs["x"] < 1e-14
     for k in ("v", "omega", "a", "history"):
         assert errs[k] < 1e-10, (k, errs[k])
