@@ -165,22 +165,19 @@ __device__ __forceinline__ void wall(const DevParams& P, int side, double dist, 
   }
 }
 
-// One pair (i, slot k, partner j) already known to be in the pair set: its
+// One pair (i, slot k, partner j at pj, minimum-image offset (dx, dy, dz),
+// squared distance s) already known to be in the pair set: its
 // lubrication and contact forces on i and the contact torque on i.  The
 // operands are put in lower-ID -> higher-ID order before any arithmetic, so
 // both sides of the pair compute the same bits; the result is added with the
 // sign of i's side.  Updates slot k's tangential history.
 template <typename R>
 __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& A, int N, int i,
-                                           int k, int j, const double4& pi, const double4& vi,
-                                           const double4& wi, int idi, unsigned mask_old,
-                                           bool upd, V3<R>& Fc, V3<R>& Fl, V3<R>& T,
-                                           unsigned& mask_new) {
-  const double4 pj = A.pos[j];
-  double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
-  double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
-  double dz = pj.z - pi.z;
-  const double s = pair_s(dx, dy, dz);
+                                           int k, int j, const double4& pi, const double4& pj,
+                                           double dx, double dy, double dz, double s,
+                                           const double4& vi, const double4& wi, int idi,
+                                           unsigned mask_old, bool upd, V3<R>& Fc, V3<R>& Fl,
+                                           V3<R>& T, unsigned& mask_new) {
   const double ri = pi.w, mi = vi.w;
   const double rs = ri + pj.w;
   const R kn = (R)P.kn, kt = (R)P.kt, mu = (R)P.mu, dtR = (R)P.dt;
@@ -244,9 +241,6 @@ __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& 
   T = T + Tp;
 }
 
-#ifndef SEDIMI_FORCE_PF
-#define SEDIMI_FORCE_PF 0
-#endif
 #ifndef SEDIMI_FORCE_WAVES
 #define SEDIMI_FORCE_WAVES 1
 #endif
@@ -270,48 +264,17 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
   unsigned mask_new = 0;
   const int cnt = A.ncnt[i];
 
-#if SEDIMI_FORCE_PF == 0
   for (int k = 0; k < cnt; ++k) {
     const int j = A.nbr[(size_t)k * N + i];
     const double4 pj = A.pos[j];
     const double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
     const double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
-    const double s = pair_s(dx, dy, pj.z - pi.z);
+    const double dz = pj.z - pi.z;
+    const double s = pair_s(dx, dy, dz);
     if (!pair_in_range(s, ri + pj.w, P.lub_out)) continue;
-    pair_force<R>(P, A, N, i, k, j, pi, vi, wi, idi, mask_old, upd, Fc, Fl, T, mask_new);
+    pair_force<R>(P, A, N, i, k, j, pi, pj, dx, dy, dz, s, vi, wi, idi, mask_old, upd, Fc, Fl,
+                  T, mask_new);
   }
-#else
-  // Classify the slots first (pair range; likely contact when s < (r_i+r_j)^2),
-  // then walk the likely contacts and the lubrication-only pairs in two
-  // separate loops, so that the lanes of a wave take the same path in each
-  // iteration instead of the contact path whenever any lane has a contact.
-  unsigned conm = 0, lubm = 0;
-  for (int k = 0; k < cnt; ++k) {
-    const int j = A.nbr[(size_t)k * N + i];
-    const double4 pj = A.pos[j];
-    const double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
-    const double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
-    const double s = pair_s(dx, dy, pj.z - pi.z);
-    const double rs = ri + pj.w;
-    if (!pair_in_range(s, rs, P.lub_out)) continue;
-    if (s < rs * rs)
-      conm |= 1u << k;
-    else
-      lubm |= 1u << k;
-  }
-  while (conm) {
-    const int k = __builtin_ctz(conm);
-    conm &= conm - 1;
-    pair_force<R>(P, A, N, i, k, A.nbr[(size_t)k * N + i], pi, vi, wi, idi, mask_old, upd, Fc,
-                  Fl, T, mask_new);
-  }
-  while (lubm) {
-    const int k = __builtin_ctz(lubm);
-    lubm &= lubm - 1;
-    pair_force<R>(P, A, N, i, k, A.nbr[(size_t)k * N + i], pi, vi, wi, idi, mask_old, upd, Fc,
-                  Fl, T, mask_new);
-  }
-#endif
   // flat walls (history validity in mask bits 30 / 31)
   {
     const V3<R> v = cvt<R>(vi.x, vi.y, vi.z);
