@@ -165,15 +165,17 @@ __device__ __forceinline__ void wall(const DevParams& P, int side, double dist, 
   }
 }
 
-// One pair (i, slot k, partner j at pj, minimum-image offset (dx, dy, dz),
-// squared distance s) already known to be in the pair set: its
+// One pair (i, slot k, partner state pj / vj / wj, partner ID idj,
+// minimum-image offset (dx, dy, dz), squared distance s) already known to be
+// in the pair set: its
 // lubrication and contact forces on i and the contact torque on i.  The
 // operands are put in lower-ID -> higher-ID order before any arithmetic, so
 // both sides of the pair compute the same bits; the result is added with the
 // sign of i's side.  Updates slot k's tangential history.
 template <typename R>
 __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& A, int N, int i,
-                                           int k, int j, const double4& pi, const double4& pj,
+                                           int k, const double4& pi, const double4& pj,
+                                           const double4& vj, const double4& wj, int idj,
                                            double dx, double dy, double dz, double s,
                                            const double4& vi, const double4& wi, int idi,
                                            unsigned mask_old, bool upd, V3<R>& Fc, V3<R>& Fl,
@@ -184,8 +186,6 @@ __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& 
   R* hx = (R*)A.hxi;
   R* hy = hx + (size_t)P.maxn * N;
   R* hz = hy + (size_t)P.maxn * N;
-  const int idj = A.id[j];
-  const double4 vj = A.vel[j], wj = A.omg[j];
   const bool lo = idi < idj;
   // canonical orientation: from the lower to the higher particle ID
   const double sg = lo ? 1.0 : -1.0;
@@ -241,6 +241,20 @@ __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& 
   T = T + Tp;
 }
 
+// Neighbours of a block's particles lie mostly near them in the sorted order
+// (bins in Morton order): the block stages the state of its own particles
+// (and of kWin particles on each side) in LDS and reads a neighbour's state
+// from there when it falls in that window, from global memory otherwise.  On
+// a deposited bed 73% of neighbour reads fall in the block itself; windows of
+// +-64 / +-128 (80% / 82%) measured no faster.
+constexpr int kWin = 0;
+constexpr int kStage = kBlock + 2 * kWin;
+struct Staged {
+  double4 pos[kStage];
+  double4 vel[kStage];
+  double4 omg[kStage];  // .w = particle ID
+};
+
 #ifndef SEDIMI_FORCE_WAVES
 #define SEDIMI_FORCE_WAVES 1
 #endif
@@ -248,16 +262,32 @@ __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& 
 template <typename R, int MODE>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SEDIMI_FORCE_WAVES)))
 void k_forces(DevParams P, DevArrays A, int update_history) {
-  int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  __shared__ Staged S;
+  const int base = xcd_block(blockIdx.x, gridDim.x) * kBlock;
+  const int i = base + threadIdx.x;
   if (i == 0 && *A.rb) {
     A.ctl->rebuilds += 1;
     *A.rb = 0;
   }
-  if (i >= P.n) return;
   const int N = P.n;
+  const int wlo = base - kWin;
+  for (int t = threadIdx.x; t < kStage; t += kBlock) {
+    const int g = wlo + t;
+    if (g >= 0 && g < N) {
+      S.pos[t] = A.pos[g];
+      S.vel[t] = A.vel[g];
+      double4 w = A.omg[g];
+      w.w = (double)A.id[g];
+      S.omg[t] = w;
+    }
+  }
+  __syncthreads();
+  if (i >= N) return;
   const bool upd = update_history != 0;
-  double4 pi = A.pos[i], vi = A.vel[i], wi = A.omg[i], ai = A.acc[i];
-  const int idi = A.id[i];
+  const int ti = kWin + threadIdx.x;
+  double4 pi = S.pos[ti], vi = S.vel[ti], wi = S.omg[ti], ai = A.acc[i];
+  const int idi = (int)wi.w;
+  wi.w = 0.0;
   const double ri = pi.w, mi = vi.w;
   V3<R> Fc{0, 0, 0}, Fl{0, 0, 0}, T{0, 0, 0};
   const unsigned mask_old = A.hmask[i];
@@ -266,14 +296,31 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
 
   for (int k = 0; k < cnt; ++k) {
     const int j = A.nbr[(size_t)k * N + i];
-    const double4 pj = A.pos[j];
+    const int t = j - wlo;
+    const bool staged = (unsigned)t < (unsigned)kStage;
+    double4 pj;
+    if (staged)
+      pj = S.pos[t];
+    else
+      pj = A.pos[j];
     const double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
     const double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
     const double dz = pj.z - pi.z;
     const double s = pair_s(dx, dy, dz);
     if (!pair_in_range(s, ri + pj.w, P.lub_out)) continue;
-    pair_force<R>(P, A, N, i, k, j, pi, pj, dx, dy, dz, s, vi, wi, idi, mask_old, upd, Fc, Fl,
-                  T, mask_new);
+    double4 vj, wj;
+    int idj;
+    if (staged) {
+      vj = S.vel[t];
+      wj = S.omg[t];
+      idj = (int)wj.w;
+    } else {
+      vj = A.vel[j];
+      wj = A.omg[j];
+      idj = A.id[j];
+    }
+    pair_force<R>(P, A, N, i, k, pi, pj, vj, wj, idj, dx, dy, dz, s, vi, wi, idi, mask_old, upd,
+                  Fc, Fl, T, mask_new);
   }
   // flat walls (history validity in mask bits 30 / 31)
   {
