@@ -81,11 +81,11 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--nn-train-steps", type=int, default=300,
+    ap.add_argument("--nn-train-steps", type=int, default=2000,
                     help="surrogate training snapshots (0 skips the surrogate section)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the 1 GiB copy used to scale the PMC byte counters")
-    ap.add_argument("--nn-alpha", type=float, default=0.1,
+    ap.add_argument("--nn-alpha", type=float, default=1.0,
                     help="leaky-ReLU slope of the surrogate (1 makes the network linear)")
     ap.add_argument("--nn-steps", type=int, default=10,
                     help="coupled steps (averaging every step) per averaging mode")

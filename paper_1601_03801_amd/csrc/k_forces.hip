@@ -1,10 +1,11 @@
 // k_forces.hip -- fused force evaluation and second half kick.
 //
 // One lane per particle (bin-sorted order) walks its full neighbour list.
-// Every pair is evaluated on both of its sides with the operands put in
-// lower-ID -> higher-ID order first, so both sides compute bit-identical pair
-// forces and tangential histories: the pair forces are exactly antisymmetric
-// and no atomics are needed.  Per pair (Sections 2.1, 2.5):
+// Every pair is evaluated on both of its sides in the frame of its lower-ID
+// particle, with operations whose IEEE results do not depend on which side
+// computes them, so both sides get bit-identical pair forces and tangential
+// histories: the pair forces are exactly antisymmetric and no atomics are
+// needed.  Per pair (Sections 2.1, 2.5):
 //   - pair set: s = |dx|^2 < ((r_i + r_j)(1 + f_out))^2, exact FP64 test;
 //   - lubrication (Ball & Melrose squeeze term) for every pair in the set:
 //     F = -6 pi mu a_eff^2 u_n / max(h, h_in) n;
@@ -75,24 +76,30 @@ __device__ __forceinline__ R drag_coef(const DevParams& P, R d, R eps_f, R wm) {
   return (R)0.5 * cd * (R)P.rho_f * area * pow(eps_f, (R)2 - chi) * wm;
 }
 
-struct Interp {
-  int idx[8];
-  double w[8];
+// Trilinear interpolation of the cell-centred mesh fields at (x, y, z):
+// periodic in x and y, clamped to the first / last cell centre in z.  The
+// eight corners are visited as four x-rows (y then z), two cells each, in a
+// loop that is not unrolled: unrolled, the sixteen in-flight double4 loads
+// set the kernel's register peak and halve its occupancy.
+struct FluidAt {
+  double Ux, Uy, Uz, es;  // fluid velocity, solid fraction
+  double gx, gy, gz;      // step modes: G; evaluation mode: grad p
+  double dx, dy, dz;      // evaluation mode: DU/Dt
 };
 
-__device__ __forceinline__ Interp interp_weights(const DevParams& P, double x, double y,
-                                                 double z) {
-  Interp I;
+template <int MODE>
+__device__ __forceinline__ FluidAt fluid_at(const DevParams& P, const DevArrays& A, double x,
+                                            double y, double z) {
   double sx = x / P.hx - 0.5, sy = y / P.hy - 0.5, sz = z / P.hz - 0.5;
   // keep indices in range even for non-finite positions (flagged elsewhere)
   if (!(sx >= -1.0 && sx <= (double)P.nx)) sx = 0.0;
   if (!(sy >= -1.0 && sy <= (double)P.ny)) sy = 0.0;
-  double fx0 = floor(sx), fy0 = floor(sy);
-  double fx = sx - fx0, fy = sy - fy0;
-  int i0 = (((int)fx0 % P.nx) + P.nx) % P.nx;
-  int i1 = i0 + 1 == P.nx ? 0 : i0 + 1;
-  int j0 = (((int)fy0 % P.ny) + P.ny) % P.ny;
-  int j1 = j0 + 1 == P.ny ? 0 : j0 + 1;
+  const double fx0 = floor(sx), fy0 = floor(sy);
+  const double fx = sx - fx0, fy = sy - fy0;
+  const int i0 = (((int)fx0 % P.nx) + P.nx) % P.nx;
+  const int i1 = i0 + 1 == P.nx ? 0 : i0 + 1;
+  const int j0 = (((int)fy0 % P.ny) + P.ny) % P.ny;
+  const int j1 = j0 + 1 == P.ny ? 0 : j0 + 1;
   int k0, k1;
   double fz;
   if (P.nz == 1) {
@@ -105,19 +112,40 @@ __device__ __forceinline__ Interp interp_weights(const DevParams& P, double x, d
     k1 = k0 + 1;
     fz = sz - (double)k0;
   }
-  int q = 0;
+  FluidAt f{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 1
+  for (int r = 0; r < 4; ++r) {
+    const int jj = (r & 1) ? j1 : j0, kk = (r & 2) ? k1 : k0;
+    const double wy = (r & 1) ? fy : 1.0 - fy, wz = (r & 2) ? fz : 1.0 - fz;
+    const int row = (kk * P.ny + jj) * P.nx;
 #pragma unroll
-  for (int c = 0; c < 2; ++c)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        int ii = a ? i1 : i0, jj = b ? j1 : j0, kk = c ? k1 : k0;
-        I.idx[q] = (kk * P.ny + jj) * P.nx + ii;
-        I.w[q] = (a ? fx : 1.0 - fx) * (b ? fy : 1.0 - fy) * (c ? fz : 1.0 - fz);
-        ++q;
+    for (int a = 0; a < 2; ++a) {
+      const int c = row + (a ? i1 : i0);
+      const double w = (a ? fx : 1.0 - fx) * wy * wz;
+      const double4 u = A.U[c];
+      f.Ux += w * u.x;
+      f.Uy += w * u.y;
+      f.Uz += w * u.z;
+      f.es += w * u.w;
+      if (P.fluid_forces) {
+        if (MODE != 1) {
+          const double4 g = A.G[c];
+          f.gx += w * g.x;
+          f.gy += w * g.y;
+          f.gz += w * g.z;
+        } else {
+          const double4 g = A.gp[c], m = A.du[c];
+          f.gx += w * g.x;
+          f.gy += w * g.y;
+          f.gz += w * g.z;
+          f.dx += w * m.x;
+          f.dy += w * m.y;
+          f.dz += w * m.z;
+        }
       }
-  return I;
+    }
+  }
+  return f;
 }
 
 // One wall of particle i: side -1 bottom (n = -z), +1 top (n = +z).  The
@@ -165,13 +193,34 @@ __device__ __forceinline__ void wall(const DevParams& P, int side, double dist, 
   }
 }
 
+// r_i w_i + r_j w_j with each product rounded on its own (no fused
+// multiply-add), so that both sides of a pair get the same bits.
+template <typename R>
+__device__ __forceinline__ V3<R> sym_rw(double ri, const double4& wi, double rj,
+                                        const double4& wj);
+template <>
+__device__ __forceinline__ V3<double> sym_rw<double>(double ri, const double4& wi, double rj,
+                                                     const double4& wj) {
+  return V3<double>{__dadd_rn(__dmul_rn(ri, wi.x), __dmul_rn(rj, wj.x)),
+                    __dadd_rn(__dmul_rn(ri, wi.y), __dmul_rn(rj, wj.y)),
+                    __dadd_rn(__dmul_rn(ri, wi.z), __dmul_rn(rj, wj.z))};
+}
+template <>
+__device__ __forceinline__ V3<float> sym_rw<float>(double ri, const double4& wi, double rj,
+                                                   const double4& wj) {
+  const float a = (float)ri, b = (float)rj;
+  return V3<float>{__fadd_rn(__fmul_rn(a, (float)wi.x), __fmul_rn(b, (float)wj.x)),
+                   __fadd_rn(__fmul_rn(a, (float)wi.y), __fmul_rn(b, (float)wj.y)),
+                   __fadd_rn(__fmul_rn(a, (float)wi.z), __fmul_rn(b, (float)wj.z))};
+}
+
 // One pair (i, slot k, partner state pj / vj / wj, partner ID idj,
 // minimum-image offset (dx, dy, dz), squared distance s) already known to be
-// in the pair set: its
-// lubrication and contact forces on i and the contact torque on i.  The
-// operands are put in lower-ID -> higher-ID order before any arithmetic, so
-// both sides of the pair compute the same bits; the result is added with the
-// sign of i's side.  Updates slot k's tangential history.
+// in the pair set: its lubrication and contact forces on i and the contact
+// torque on i.  The pair is computed in the frame of its lower-ID particle
+// (normal from lower to higher ID) using only sign-symmetric and commutative
+// steps, so both sides of the pair compute the same bits; the result is added
+// with the sign of i's side.  Updates slot k's tangential history.
 template <typename R>
 __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& A, int N, int i,
                                            int k, const double4& pi, const double4& pj,
@@ -195,26 +244,26 @@ __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& 
   const double dist = sqrt(s);
   const double inv = 1.0 / dist;
   const V3<R> n = cvt<R>(dx * inv, dy * inv, dz * inv);
-  const double4 vlo = lo ? vi : vj, vhi = lo ? vj : vi;
-  const double4 wlo = lo ? wi : wj, whi = lo ? wj : wi;
-  const double rlo = lo ? ri : pj.w, rhi = lo ? pj.w : ri;
-  const V3<R> dv = cvt<R>(vlo.x - vhi.x, vlo.y - vhi.y, vlo.z - vhi.z);
-  const V3<R> rw = (R)rlo * cvt<R>(wlo.x, wlo.y, wlo.z) + (R)rhi * cvt<R>(whi.x, whi.y, whi.z);
+  // Quantities of the lower-ID side computed without selecting operands:
+  // sg (v_i - v_j) is exactly v_lo - v_hi (IEEE subtraction is sign
+  // symmetric), and r_i w_i + r_j w_j with separately rounded products is the
+  // same on both sides (IEEE addition and multiplication commute).
+  const V3<R> dv = cvt<R>(sg * (vi.x - vj.x), sg * (vi.y - vj.y), sg * (vi.z - vj.z));
+  const V3<R> rw = sym_rw<R>(ri, wi, pj.w, wj);
   const V3<R> vrel = dv + cross(rw, n);
   const R un = dot(vrel, n);
   V3<R> Fpl{0, 0, 0}, Fpc{0, 0, 0};
   if (P.lubrication) {
     const double h = dist - rs, hin = P.lub_in * rs;
     const R hh = (R)(h > hin ? h : hin);
-    const R aeff = (R)(rlo * rhi / rs);
+    const R aeff = (R)(ri * pj.w / rs);
     const R Flub = (R)(6.0 * kPi * P.mu_f) * aeff * aeff * un / hh;
     Fpl = (-Flub) * n;
   }
   const double delta = rs - dist;
   V3<R> Tp{0, 0, 0};
   if (delta > 0.0) {
-    const double mlo = lo ? mi : vj.w, mhi = lo ? vj.w : mi;
-    const R meff = (R)(mlo * mhi / (mlo + mhi));
+    const R meff = (R)(mi * vj.w / (mi + vj.w));
     const R gn = (R)(2.0 * P.zeta) * sqrt(meff * kn);
     const R gt = (R)P.gt_over_gn * gn;
     const R Frep = kn * (R)delta + gn * un;
@@ -223,7 +272,7 @@ __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& 
     if (mask_old & (1u << k)) xi = V3<R>{hx[o], hy[o], hz[o]};
     const V3<R> ft = tangential<R>(kt, gt, mu, dtR, n, vrel, un, fabs(Frep), xi);
     Fpc = ft - Frep * n;
-    Tp = (R)(lo ? rlo : rhi) * cross(n, ft);
+    Tp = (R)ri * cross(n, ft);
     if (upd) {
       hx[o] = xi.x;
       hy[o] = xi.y;
@@ -231,13 +280,9 @@ __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& 
       mask_new |= 1u << k;
     }
   }
-  if (lo) {
-    Fc = Fc + Fpc;
-    Fl = Fl + Fpl;
-  } else {
-    Fc = Fc - Fpc;
-    Fl = Fl - Fpl;
-  }
+  // back to i's side (multiplying by +-1 is exact)
+  Fc = Fc + (R)sg * Fpc;
+  Fl = Fl + (R)sg * Fpl;
   T = T + Tp;
 }
 
@@ -285,11 +330,14 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
   if (i >= N) return;
   const bool upd = update_history != 0;
   const int ti = kWin + threadIdx.x;
-  double4 pi = S.pos[ti], vi = S.vel[ti], wi = S.omg[ti], ai = A.acc[i];
+  double4 pi = S.pos[ti], vi = S.vel[ti], wi = S.omg[ti];
   const int idi = (int)wi.w;
   wi.w = 0.0;
   const double ri = pi.w, mi = vi.w;
   V3<R> Fc{0, 0, 0}, Fl{0, 0, 0}, T{0, 0, 0};
+  // the step modes need only the sum of contact and lubrication forces:
+  // one accumulator for both saves registers
+  V3<R>& Flub = MODE == 1 ? Fl : Fc;
   const unsigned mask_old = A.hmask[i];
   unsigned mask_new = 0;
   const int cnt = A.ncnt[i];
@@ -320,18 +368,19 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
       idj = A.id[j];
     }
     pair_force<R>(P, A, N, i, k, pi, pj, vj, wj, idj, dx, dy, dz, s, vi, wi, idi, mask_old, upd,
-                  Fc, Fl, T, mask_new);
+                  Fc, Flub, T, mask_new);
   }
+  const double4 ai = A.acc[i];  // loaded after the pair loop: not live across it
   // flat walls (history validity in mask bits 30 / 31)
   {
     const V3<R> v = cvt<R>(vi.x, vi.y, vi.z);
     const V3<R> rw = (R)ri * cvt<R>(wi.x, wi.y, wi.z);
     if (P.bottom_wall)
       wall<R>(P, -1, pi.z, ri, mi, v, rw, A.wxi + i, (mask_old >> 30) & 1u, upd, 1u << 30,
-              mask_new, Fc, Fl, T);
+              mask_new, Fc, Flub, T);
     if (P.top_wall)
       wall<R>(P, 1, P.Lz - pi.z, ri, mi, v, rw, A.wxi + (size_t)N + i, (mask_old >> 31) & 1u,
-              upd, 1u << 31, mask_new, Fc, Fl, T);
+              upd, 1u << 31, mask_new, Fc, Flub, T);
   }
   if (upd) A.hmask[i] = mask_new;
 
@@ -341,34 +390,10 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
   // linearly with the particle volume).
   const double d = 2.0 * ri;
   const double Vp = (kPi / 6.0) * d * d * d;
-  const Interp I = interp_weights(P, pi.x, pi.y, pi.z);
-  double Ux = 0, Uy = 0, Uz = 0, es = 0;
-  double gpx = 0, gpy = 0, gpz = 0, dux = 0, duy = 0, duz = 0;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const double w = I.w[q];
-    const double4 u = A.U[I.idx[q]];
-    Ux += w * u.x;
-    Uy += w * u.y;
-    Uz += w * u.z;
-    es += w * u.w;
-    if (P.fluid_forces) {
-      if (MODE != 1) {
-        const double4 g = A.G[I.idx[q]];
-        gpx += w * g.x;
-        gpy += w * g.y;
-        gpz += w * g.z;
-      } else {
-        const double4 g = A.gp[I.idx[q]], m = A.du[I.idx[q]];
-        gpx += w * g.x;
-        gpy += w * g.y;
-        gpz += w * g.z;
-        dux += w * m.x;
-        duy += w * m.y;
-        duz += w * m.z;
-      }
-    }
-  }
+  const FluidAt fl = fluid_at<MODE>(P, A, pi.x, pi.y, pi.z);
+  const double Ux = fl.Ux, Uy = fl.Uy, Uz = fl.Uz;
+  const double gpx = fl.gx, gpy = fl.gy, gpz = fl.gz, dux = fl.dx, duy = fl.dy, duz = fl.dz;
+  double es = fl.es;
   es = es < 0.0 ? 0.0 : (es > P.eps_s_max ? P.eps_s_max : es);
   const V3<R> wrel = cvt<R>(Ux - vi.x, Uy - vi.y, Uz - vi.z);
   const R wm = sqrt(dot(wrel, wrel));
