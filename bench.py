@@ -33,8 +33,8 @@ HBM_PEAK_GBS = 8000.0
 # the same counters read for a 1 GiB device copy (--copy-calibration: the
 # copy's FETCH_SIZE reads 0.5x the bytes read, WRITE_SIZE 1.0x the bytes
 # written).  Valid only for the kernel sources it was measured on.
-FORCE_PMC = {"fetch_kib": 268358.6, "write_kib": 305006.4, "fetch_scale": 2.0, "write_scale": 1.0,
-             "sources_sha256": "e271bb7a38f0e32d41ab0928f35393c90416f031924520b2c75634d0cac03f0a",
+FORCE_PMC = {"fetch_kib": 308840.9, "write_kib": 305006.0, "fetch_scale": 2.0, "write_scale": 1.0,
+             "sources_sha256": "795d966d1c343acd0ebd7a6dfccbd18b08ccdb27ec823c335f5e9290b6f6c2c6",
              "profile": "profiles/k_forces_bed1m_fp64.md"}
 FORCE_SOURCES = ("k_forces.hip", "k_common.h", "sedimi_internal.h")
 
