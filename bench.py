@@ -157,6 +157,8 @@ def main():
     phases = {k: {"ms_per_launch": round(v[0] / max(v[1], 1), 5), "launches": v[1]}
               for k, v in prof.items()}
     avg_ms = (prof["deposit"][0] + prof["smooth"][0]) / max(prof["smooth"][1], 1)
+    # the particle step alone (drift, gated rebuild chain, forces), per step
+    dem_ms = (prof["drift"][0] + prof["rebuild"][0] + prof["forces"][0]) / max(prof["forces"][1], 1)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -197,6 +199,8 @@ def main():
                       "solver": "direct" if st["solve_iters"] == 0 else "iterative",
                       "solve_iters": st["solve_iters"], "residual": st["solve_residual"]},
         "phases": phases,
+        "particle_step_only": {"ms_per_step": round(dem_ms, 5),
+                               "particle_updates_per_s": round(n / (dem_ms * 1e-3), 1)},
         "surrogate": surrogate,
         "stats": {"mean_neighbors": round(st["mean_neighbors"], 3),
                   "mean_contacts": round(st["mean_contacts"], 3),
@@ -277,6 +281,30 @@ def surrogate_section(args):
         errs.append([float(np.abs(nn[0] - plain[0]).max())] + [float(r) for r in rel])
     errs = np.array(errs)
 
+    # network forward alone against the plain solve alone, HIP events per call
+    def timed(fn, reps=5):
+        tot = 0.0
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            tot += e0.elapsed_time(e1)
+        return tot / reps
+    g.nn_forward()
+    fwd_ms = timed(g.nn_forward)
+    solve_ms = timed(lambda: g.smooth(4))
+    ncell = prm["nx"] * prm["ny"] * prm["nz"]
+    C = 32
+    fwd_flop = 2 * 27 * ncell * (4 * C + 4 * C * C + C * 4)
+    mfma = {"forward_ms": round(fwd_ms, 4), "plain_solve_ms": round(solve_ms, 4),
+            "forward_tflops": round(fwd_flop / (fwd_ms * 1e-3) / 1e12, 2),
+            "peak_tflops_bf16": 2500.0,
+            "frac": round(fwd_flop / (fwd_ms * 1e-3) / 2.5e15, 4)}
+    print(f"bench: network forward {fwd_ms:.3f} ms ({mfma['forward_tflops']} TFLOP/s), "
+          f"plain solve {solve_ms:.3f} ms", file=sys.stderr, flush=True)
+
     # coupled 4M-sphere run, averaging every step, per averaging mode
     g.set_fluid(w4["U"], w4["gradp"], w4["dudt"])
     g.set_particles(w4["x"], w4["v"], w4["d"], w4["rho"])
@@ -317,6 +345,7 @@ def surrogate_section(args):
         "error_vs_plain": {"eps_s_maxabs": float(errs[:, 0].max()),
                            "rel_l2_per_channel": [float(v) for v in errs[:, 1:].max(axis=0)],
                            "sampled_residual": max(checks), "bound": 1e-3},
+        "mfma": mfma,
         "modes": modes,
     }
 

@@ -29,44 +29,65 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
+// Cell of each particle and its rank among the cell's members.  Sorted
+// particles that share a cell mostly sit in the same wave: each group of
+// lanes with one cell takes its ranks with a single atomic add.
 __global__ void k_cellkey(DevParams P, DevArrays A) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= P.n) return;
-  double4 x = A.pos[q];
-  int a = (int)floor(x.x / P.hx), b = (int)floor(x.y / P.hy), c = (int)floor(x.z / P.hz);
-  a = a < 0 ? 0 : (a >= P.nx ? P.nx - 1 : a);
-  b = b < 0 ? 0 : (b >= P.ny ? P.ny - 1 : b);
-  c = c < 0 ? 0 : (c >= P.nz ? P.nz - 1 : c);
-  int k = (c * P.ny + b) * P.nx + a;
-  A.key[q] = k;
-  A.rank[q] = atomicAdd(&A.cell_count[k], 1);
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = q < P.n;
+  int k = -1;
+  if (valid) {
+    const double4 x = A.pos[q];
+    int a = (int)floor(x.x / P.hx), b = (int)floor(x.y / P.hy), c = (int)floor(x.z / P.hz);
+    a = a < 0 ? 0 : (a >= P.nx ? P.nx - 1 : a);
+    b = b < 0 ? 0 : (b >= P.ny ? P.ny - 1 : b);
+    c = c < 0 ? 0 : (c >= P.nz ? P.nz - 1 : c);
+    k = (c * P.ny + b) * P.nx + a;
+    A.key[q] = k;
+  }
+  // every lane of the wave is still active here (no early return above)
+  unsigned long long active = __ballot(valid);
+  const int lane = __lane_id();
+  int rank = 0;
+  while (active) {
+    const int leader = __ffsll((long long)active) - 1;
+    const int kl = __shfl(k, leader);
+    const unsigned long long grp = __ballot(k == kl) & active;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&A.cell_count[kl], (int)__popcll(grp));
+    base = __shfl(base, leader);
+    if ((grp >> lane) & 1ull) rank = base + (int)__popcll(grp & ((1ull << lane) - 1ull));
+    active &= ~grp;
+  }
+  if (valid) A.rank[q] = rank;
 }
 
 __global__ void k_cellscatter(DevParams P, DevArrays A) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= P.n) return;
-  A.cperm[A.cell_start[A.key[q]] + A.rank[q]] = q;
+  A.cperm[A.cell_start[A.key[q]] + A.rank[q]] =
+      ((unsigned long long)(unsigned)A.id[q] << 32) | (unsigned)q;
 }
 
-// One lane per cell: order the members by particle ID, then sum.
+// One lane per cell: order the members by particle ID (the high half of each
+// (ID, index) key), then sum in that order.
 __global__ void k_cellsum(DevParams P, DevArrays A) {
 #pragma clang fp contract(off)
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P.ncell) return;
   int s = A.cell_start[c], e = A.cell_start[c + 1];
   for (int i = s + 1; i < e; ++i) {
-    int q = A.cperm[i];
-    int key = A.id[q];
+    const unsigned long long key = A.cperm[i];
     int j = i - 1;
-    while (j >= s && A.id[A.cperm[j]] > key) {
+    while (j >= s && A.cperm[j] > key) {
       A.cperm[j + 1] = A.cperm[j];
       --j;
     }
-    A.cperm[j + 1] = q;
+    A.cperm[j + 1] = key;
   }
   double v = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
   for (int i = s; i < e; ++i) {
-    int q = A.cperm[i];
+    const int q = (int)(unsigned)(A.cperm[i] & 0xffffffffull);
     double d = 2.0 * A.pos[q].w;
     double V = (kPi / 6.0) * d * d * d;
     v += V;

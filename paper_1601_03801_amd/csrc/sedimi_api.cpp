@@ -156,7 +156,7 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
   a.key = w.take<int>(N);
   a.rank = w.take<int>(N);
   a.perm = w.take<int>(N);
-  a.cperm = w.take<int>(N);
+  a.cperm = w.take<unsigned long long>(N);
   a.bin_count = w.take<int>(nb);
   a.bin_start = w.take<int>(nb);
   size_t tiles = (std::max(nb, nc + 1) + 1023) / 1024 + 2;

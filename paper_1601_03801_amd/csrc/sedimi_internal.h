@@ -97,7 +97,8 @@ struct DevArrays {
   double *sxf, *stmp;  // solver: FP32 iterate (mixed mode), column-sweep scratch
   double* ztab;        // z-line preconditioner: reciprocal pivots, super-diagonal
   double* spec;        // direct solve: H_x, H_y, C_z, C_z^-1, per-axis eigenvalues
-  int *cell_count, *cell_start, *cperm;
+  int *cell_count, *cell_start;
+  unsigned long long* cperm;  // deposition: (particle ID << 32 | sorted index), by cell
   double* red;  // reduction partials
   Ctl* ctl;
   // Rebuild flags.  *rb: a rebuild is due before this step's forces (set by

@@ -290,3 +290,30 @@ def test_smooth_direct_partial_channels_and_repeat(orc):
     g.smooth(4)
     want2, _ = orc.diffuse(prm, raw2)
     assert np.abs(g.get_field(1) - want2).max() < 1e-11 * raw2.max()
+
+
+def test_error_paths_forced_from_the_host():
+    """Device-side checks end in error codes, never in faults: a neighbour
+    list too short for the bed (slot overflow), a particle shot through the
+    open top (escape) and a non-finite velocity (unstable state)."""
+    import paper_1601_03801_amd as sm
+    case = dense_bed(2000, 3)
+    with pytest.raises(sm.SedimiError) as e:
+        gpu_context(case, max_neighbors=2)
+    assert e.value.code == sm.EOVERFLOW
+
+    w = workloads.workload("small")
+    prm = dict(w["params"], top_wall=0)
+    v = w["v"].copy()
+    v[17] = (0.0, 0.0, 1.0e3)
+    g = gpu_context(dict(w, params=prm, v=v))
+    with pytest.raises(sm.SedimiError) as e:
+        g.step(2)
+    assert e.value.code == sm.EESCAPE
+
+    v = w["v"].copy()
+    v[5, 0] = float("nan")
+    g = gpu_context(dict(w, v=v))
+    with pytest.raises(sm.SedimiError) as e:
+        g.step(1)
+    assert e.value.code == sm.EUNSTABLE
