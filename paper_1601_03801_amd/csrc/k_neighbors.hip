@@ -23,8 +23,9 @@ __device__ __forceinline__ bool gate(const int* flag) { return *flag != 0; }
 
 __global__ void k_zero_ints(int* p, int64_t n, int gated, const int* flag) {
   if (gated && !gate(flag)) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
 }
 
 // First half kick and drift of velocity Verlet; wrap on the periodic axes;
@@ -41,12 +42,9 @@ __global__ void k_kick_drift(DevParams P, DevArrays A) {
   A.omg[q] = w;
 }
 
-// Active slot history -> (partner ID, xi) rows, before the re-sort.
+// Active slot history -> (partner ID, xi) rows of particle p, before the re-sort.
 template <typename H>
-__global__ void k_compact(DevParams P, DevArrays A) {
-  if (!gate(A.rb)) return;
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P.n) return;
+__device__ __forceinline__ void compact_one(const DevParams& P, const DevArrays& A, int p) {
   const int N = P.n;
   unsigned m = A.hmask[p];
   int cnt = A.ncnt[p];
@@ -70,70 +68,88 @@ __global__ void k_compact(DevParams P, DevArrays A) {
   A.ccnt[p] = c;
 }
 
-__global__ void k_keys(DevParams P, DevArrays A) {
-  if (!gate(A.rb)) return;
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P.n) return;
+// Bin key of particle p (bins in Morton order) and its rank among the bin's
+// members.
+__device__ __forceinline__ void keys_one(const DevParams& P, const DevArrays& A, int p) {
   double4 x = A.pos[p];
   int b = A.bin_rank[bin_of(P, x.x, x.y, x.z)];
   A.key[p] = b;
   A.rank[p] = atomicAdd(&A.bin_count[b], 1);
 }
 
+// First kernel of a rebuild: history rows (when the list slots carry
+// history) and bin keys, one pass over the particles.
+template <typename H, bool SLOTS>
+__global__ void k_compact_keys(DevParams P, DevArrays A) {
+  if (!gate(A.rb)) return;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += gridDim.x * blockDim.x) {
+    if (SLOTS) compact_one<H>(P, A, p);
+    keys_one(P, A, p);
+  }
+}
+
+
 __global__ void k_scatter(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
-  int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= P.n) return;
-  A.perm[A.bin_start[A.key[p]] + A.rank[p]] = p;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P.n;
+       p += gridDim.x * blockDim.x) {
+    A.perm[A.bin_start[A.key[p]] + A.rank[p]] = p;
+  }
 }
 
 // Order each bin's members by particle ID (bins hold a handful of particles).
 __global__ void k_binsort(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
-  int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= P.nbins) return;
-  int s = A.bin_start[b], e = A.bin_start[b + 1];
-  for (int i = s + 1; i < e; ++i) {
-    int p = A.perm[i];
-    int key = A.id[p];
-    int j = i - 1;
-    while (j >= s && A.id[A.perm[j]] > key) {
-      A.perm[j + 1] = A.perm[j];
-      --j;
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < P.nbins;
+       b += gridDim.x * blockDim.x) {
+    int s = A.bin_start[b], e = A.bin_start[b + 1];
+    for (int i = s + 1; i < e; ++i) {
+      int p = A.perm[i];
+      int key = A.id[p];
+      int j = i - 1;
+      while (j >= s && A.id[A.perm[j]] > key) {
+        A.perm[j + 1] = A.perm[j];
+        --j;
+      }
+      A.perm[j + 1] = p;
     }
-    A.perm[j + 1] = p;
   }
 }
 
 __global__ void k_permute(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= P.n) return;
-  int p = A.perm[q];
-  A.pos_t[q] = A.pos[p];
-  A.vel_t[q] = A.vel[p];
-  A.omg_t[q] = A.omg[p];
-  A.acc_t[q] = A.acc[p];
-  A.alp_t[q] = A.alp[p];
-  A.fdr_t[q] = A.fdr[p];
-  A.wxi_t[q] = A.wxi[p];
-  A.wxi_t[(size_t)P.n + q] = A.wxi[(size_t)P.n + p];
-  A.id_t[q] = A.id[p];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < P.n;
+       q += gridDim.x * blockDim.x) {
+    int p = A.perm[q];
+    A.pos_t[q] = A.pos[p];
+    A.vel_t[q] = A.vel[p];
+    A.omg_t[q] = A.omg[p];
+    A.acc_t[q] = A.acc[p];
+    A.alp_t[q] = A.alp[p];
+    A.fdr_t[q] = A.fdr[p];
+    A.wxi_t[q] = A.wxi[p];
+    A.wxi_t[(size_t)P.n + q] = A.wxi[(size_t)P.n + p];
+    A.id_t[q] = A.id[p];
+  }
 }
 
 __global__ void k_copyback(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= P.n) return;
-  A.pos[q] = A.pos_t[q];
-  A.vel[q] = A.vel_t[q];
-  A.omg[q] = A.omg_t[q];
-  A.acc[q] = A.acc_t[q];
-  A.alp[q] = A.alp_t[q];
-  A.fdr[q] = A.fdr_t[q];
-  A.wxi[q] = A.wxi_t[q];
-  A.wxi[(size_t)P.n + q] = A.wxi_t[(size_t)P.n + q];
-  A.id[q] = A.id_t[q];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < P.n;
+       q += gridDim.x * blockDim.x) {
+    A.pos[q] = A.pos_t[q];
+    A.vel[q] = A.vel_t[q];
+    A.omg[q] = A.omg_t[q];
+    A.acc[q] = A.acc_t[q];
+    A.alp[q] = A.alp_t[q];
+    A.fdr[q] = A.fdr_t[q];
+    A.wxi[q] = A.wxi_t[q];
+    A.wxi[(size_t)P.n + q] = A.wxi_t[(size_t)P.n + q];
+    A.id[q] = A.id_t[q];
+  }
+  // the bin counts are no longer needed: clear them for the next rebuild
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < P.nbins; b += gridDim.x * blockDim.x)
+    A.bin_count[b] = 0;
 }
 
 // Neighbour list of particle q: every particle in the 27 surrounding bins
@@ -142,78 +158,79 @@ __global__ void k_copyback(DevParams P, DevArrays A) {
 template <typename H>
 __global__ void k_build(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= P.n) return;
-  const int N = P.n;
-  double4 xi = A.pos[q];
-  int bx = bin_coord(xi.x, P.hbx, P.nbx), by = bin_coord(xi.y, P.hby, P.nby),
-      bz = bin_coord(xi.z, P.hbz, P.nbz);
-  int cnt = 0;
-  for (int dz = -1; dz <= 1; ++dz) {
-    int cz = bz + dz;
-    if (cz < 0 || cz >= P.nbz) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      int cy = by + dy;
-      cy = cy < 0 ? cy + P.nby : (cy >= P.nby ? cy - P.nby : cy);
-      for (int dx = -1; dx <= 1; ++dx) {
-        int cx = bx + dx;
-        cx = cx < 0 ? cx + P.nbx : (cx >= P.nbx ? cx - P.nbx : cx);
-        int b = A.bin_rank[(cz * P.nby + cy) * P.nbx + cx];
-        int s = A.bin_start[b], e = A.bin_start[b + 1];
-        for (int j = s; j < e; ++j) {
-          if (j == q) continue;
-          double4 xj = A.pos[j];
-          double ddx = min_image(xj.x - xi.x, P.Lx, P.hLx);
-          double ddy = min_image(xj.y - xi.y, P.Ly, P.hLy);
-          double ddz = xj.z - xi.z;
-          double s2 = ddx * ddx + ddy * ddy + ddz * ddz;
-          double rs = xi.w + xj.w;
-          double Rl = rs + P.lub_out * rs + P.skin;
-          if (s2 < Rl * Rl * (1.0 + 1e-9)) {
-            if (cnt < P.maxn) A.nbr[(size_t)cnt * N + q] = j;
-            ++cnt;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < P.n;
+       q += gridDim.x * blockDim.x) {
+    const int N = P.n;
+    double4 xi = A.pos[q];
+    int bx = bin_coord(xi.x, P.hbx, P.nbx), by = bin_coord(xi.y, P.hby, P.nby),
+        bz = bin_coord(xi.z, P.hbz, P.nbz);
+    int cnt = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+      int cz = bz + dz;
+      if (cz < 0 || cz >= P.nbz) continue;
+      for (int dy = -1; dy <= 1; ++dy) {
+        int cy = by + dy;
+        cy = cy < 0 ? cy + P.nby : (cy >= P.nby ? cy - P.nby : cy);
+        for (int dx = -1; dx <= 1; ++dx) {
+          int cx = bx + dx;
+          cx = cx < 0 ? cx + P.nbx : (cx >= P.nbx ? cx - P.nbx : cx);
+          int b = A.bin_rank[(cz * P.nby + cy) * P.nbx + cx];
+          int s = A.bin_start[b], e = A.bin_start[b + 1];
+          for (int j = s; j < e; ++j) {
+            if (j == q) continue;
+            double4 xj = A.pos[j];
+            double ddx = min_image(xj.x - xi.x, P.Lx, P.hLx);
+            double ddy = min_image(xj.y - xi.y, P.Ly, P.hLy);
+            double ddz = xj.z - xi.z;
+            double s2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            double rs = xi.w + xj.w;
+            double Rl = rs + P.lub_out * rs + P.skin;
+            if (s2 < Rl * Rl * (1.0 + 1e-9)) {
+              if (cnt < P.maxn) A.nbr[(size_t)cnt * N + q] = j;
+              ++cnt;
+            }
           }
         }
       }
     }
-  }
-  if (cnt > P.maxn) {
-    atomicOr(&A.ctl->flags, 1);
-    cnt = P.maxn;
-  }
-  atomicMax(&A.ctl->max_nbr, cnt);
-  A.ncnt[q] = cnt;
-  A.xb[q] = xi;
-  // history: rows of the pre-sort position perm[q]
-  int p = A.perm[q];
-  int nc = A.ccnt[p];
-  unsigned mask = 0;
-  int matched = 0;
-  H* hx = (H*)A.hxi;
-  H* hy = hx + (size_t)P.maxn * N;
-  H* hz = hy + (size_t)P.maxn * N;
-  if (nc > 0) {
-    for (int k = 0; k < cnt; ++k) {
-      int pid = A.id[A.nbr[(size_t)k * N + q]];
-      for (int c = 0; c < nc; ++c) {
-        if (A.cid[(size_t)c * N + p] == pid) {
-          hx[(size_t)k * N + q] = (H)A.cxi[((size_t)0 * kMaxContacts + c) * N + p];
-          hy[(size_t)k * N + q] = (H)A.cxi[((size_t)1 * kMaxContacts + c) * N + p];
-          hz[(size_t)k * N + q] = (H)A.cxi[((size_t)2 * kMaxContacts + c) * N + p];
-          mask |= 1u << k;
-          ++matched;
-          break;
+    if (cnt > P.maxn) {
+      atomicOr(&A.ctl->flags, 1);
+      cnt = P.maxn;
+    }
+    atomicMax(&A.ctl->max_nbr, cnt);
+    A.ncnt[q] = cnt;
+    A.xb[q] = xi;
+    // history: rows of the pre-sort position perm[q]
+    int p = A.perm[q];
+    int nc = A.ccnt[p];
+    unsigned mask = 0;
+    int matched = 0;
+    H* hx = (H*)A.hxi;
+    H* hy = hx + (size_t)P.maxn * N;
+    H* hz = hy + (size_t)P.maxn * N;
+    if (nc > 0) {
+      for (int k = 0; k < cnt; ++k) {
+        int pid = A.id[A.nbr[(size_t)k * N + q]];
+        for (int c = 0; c < nc; ++c) {
+          if (A.cid[(size_t)c * N + p] == pid) {
+            hx[(size_t)k * N + q] = (H)A.cxi[((size_t)0 * kMaxContacts + c) * N + p];
+            hy[(size_t)k * N + q] = (H)A.cxi[((size_t)1 * kMaxContacts + c) * N + p];
+            hz[(size_t)k * N + q] = (H)A.cxi[((size_t)2 * kMaxContacts + c) * N + p];
+            mask |= 1u << k;
+            ++matched;
+            break;
+          }
         }
       }
     }
+    if (A.wxi[q].w != 0.0) mask |= 1u << 30;
+    if (A.wxi[(size_t)N + q].w != 0.0) mask |= 1u << 31;
+    A.hmask[q] = mask;
+    if (matched != nc) atomicOr(&A.ctl->flags, 2);
   }
-  if (A.wxi[q].w != 0.0) mask |= 1u << 30;
-  if (A.wxi[(size_t)N + q].w != 0.0) mask |= 1u << 31;
-  A.hmask[q] = mask;
-  if (matched != nc) atomicOr(&A.ctl->flags, 2);
 }
 
-// ---- exclusive scan of int counts (3 passes, 1024 items per block) ----
+// ---- exclusive scan of int counts (2 passes, 1024 items per block) ----
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kBlock * kScanItems;
 
@@ -257,29 +274,23 @@ __global__ void k_scan_tiles(const int* cnt, int* start, int n, int* tile_sums, 
   if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
 }
 
-__global__ void k_scan_top(int* tile_sums, int ntiles, int* start, int n, int gated,
+
+// Second pass: each tile adds the sum of all tiles before it (read and
+// reduced by the tile's own block, so no third pass is needed); the last
+// tile also writes the total to start[n].
+__global__ void k_scan_add(int* start, int n, const int* tile_sums, int ntiles, int gated,
                            const int* flag) {
   if (gated && !gate(flag)) return;
   __shared__ int lds[kBlock / 64];
-  int carry = 0;
-  for (int base = 0; base < ntiles; base += kBlock) {
-    int i = base + threadIdx.x;
-    int v = i < ntiles ? tile_sums[i] : 0;
-    int tot;
-    int ex = block_exclusive(v, lds, &tot);
-    if (i < ntiles) tile_sums[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) start[n] = carry;
-}
-
-__global__ void k_scan_add(int* start, int n, const int* tile_sums, int gated,
-                           const int* flag) {
-  if (gated && !gate(flag)) return;
-  int base = blockIdx.x * kScanTile;
-  int off = tile_sums[blockIdx.x];
+  const int b = blockIdx.x;
+  int part = 0;
+  for (int t = threadIdx.x; t < b; t += kBlock) part += tile_sums[t];
+  int off;
+  (void)block_exclusive(part, lds, &off);
+  const int base = b * kScanTile;
   for (int k = threadIdx.x; k < kScanTile; k += kBlock)
     if (base + k < n) start[base + k] += off;
+  if (b == ntiles - 1 && threadIdx.x == 0) start[n] = off + tile_sums[b];
 }
 
 // Which neighbour slots of each particle are in the pair set right now (the
@@ -319,6 +330,15 @@ __global__ void k_translate(DevParams P, DevArrays A, double dx, double dy) {
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+// Grid of the rebuild-chain kernels: they loop over their range, so a few
+// blocks per CU suffice when a rebuild runs, and when it does not (most
+// steps) each launch only dispatches these blocks, which read the flag and
+// return.
+constexpr unsigned kGatedBlocks = 1024;
+inline unsigned gated_grid(int64_t n) {
+  const unsigned b = nblk(n);
+  return b < kGatedBlocks ? (b > 0 ? b : 1) : kGatedBlocks;
+}
 
 }  // namespace
 
@@ -334,7 +354,8 @@ void launch_pairmask(const DevParams& P, DevArrays& A, unsigned* out, hipStream_
 
 void launch_zero_ints(int* p, int64_t n, bool gated, const int* flag, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_zero_ints, dim3(nblk(n)), dim3(kBlock), 0, s, p, n, gated ? 1 : 0, flag);
+  hipLaunchKernelGGL(k_zero_ints, dim3(gated_grid(n)), dim3(kBlock), 0, s, p, n, gated ? 1 : 0,
+                     flag);
 }
 
 void launch_exclusive_scan(int* cnt, int* start, int n, int* tmp, bool gated, const int* flag,
@@ -343,9 +364,7 @@ void launch_exclusive_scan(int* cnt, int* start, int n, int* tmp, bool gated, co
   if (ntiles == 0) ntiles = 1;
   hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, s, cnt, start, n, tmp,
                      gated ? 1 : 0, flag);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, ntiles, start, n,
-                     gated ? 1 : 0, flag);
-  hipLaunchKernelGGL(k_scan_add, dim3(ntiles), dim3(kBlock), 0, s, start, n, tmp,
+  hipLaunchKernelGGL(k_scan_add, dim3(ntiles), dim3(kBlock), 0, s, start, n, tmp, ntiles,
                      gated ? 1 : 0, flag);
 }
 
@@ -357,18 +376,18 @@ void launch_kick_drift(const DevParams& P, DevArrays& A, hipStream_t s) {
 void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixed,
                     hipStream_t s) {
   if (P.n <= 0) return;
-  unsigned g = nblk(P.n);
-  launch_zero_ints(A.bin_count, P.nbins, true, A.rb, s);
-  if (from_slots) {
-    if (mixed)
-      hipLaunchKernelGGL(k_compact<float>, dim3(g), dim3(kBlock), 0, s, P, A);
-    else
-      hipLaunchKernelGGL(k_compact<double>, dim3(g), dim3(kBlock), 0, s, P, A);
-  }
-  hipLaunchKernelGGL(k_keys, dim3(g), dim3(kBlock), 0, s, P, A);
+  unsigned g = gated_grid(P.n);
+  // the bin counts are zero here: set_particles clears them and every
+  // rebuild clears them again in k_copyback
+  if (!from_slots)
+    hipLaunchKernelGGL((k_compact_keys<double, false>), dim3(g), dim3(kBlock), 0, s, P, A);
+  else if (mixed)
+    hipLaunchKernelGGL((k_compact_keys<float, true>), dim3(g), dim3(kBlock), 0, s, P, A);
+  else
+    hipLaunchKernelGGL((k_compact_keys<double, true>), dim3(g), dim3(kBlock), 0, s, P, A);
   launch_exclusive_scan(A.bin_count, A.bin_start, P.nbins, A.scan_tmp, true, A.rb, s);
   hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, P, A);
-  hipLaunchKernelGGL(k_binsort, dim3(nblk(P.nbins)), dim3(kBlock), 0, s, P, A);
+  hipLaunchKernelGGL(k_binsort, dim3(gated_grid(P.nbins)), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_permute, dim3(g), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_copyback, dim3(g), dim3(kBlock), 0, s, P, A);
   if (mixed)
