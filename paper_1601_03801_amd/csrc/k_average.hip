@@ -300,12 +300,29 @@ __global__ void k_residual(Stencil S, const T* __restrict__ b, const T* __restri
   }
 }
 
-// out = A in for every channel (blockIdx.y).
+// out = A in for every channel (blockIdx.z), one x-row per block row: the
+// row's (j, k) is uniform across the block, so no lane divides its index.
 __global__ void k_applyA(Stencil S, const double* __restrict__ in, double* __restrict__ out) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= S.ncell) return;
-  size_t off = (size_t)blockIdx.y * S.ncell;
-  out[off + c] = apply_A<double>(S, in + off, c);
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.nx) return;
+  const size_t off = (size_t)blockIdx.z * S.ncell;
+  const double* x = in + off;
+  const int plane = S.nx * S.ny;
+  for (int jk = blockIdx.y; jk < S.ny * S.nz; jk += gridDim.y) {
+    const int j = jk % S.ny, k = jk / S.ny;
+    const int c = jk * S.nx + i;
+    const double xc = x[c];
+    const int ip = i + 1 == S.nx ? c - i : c + 1;
+    const int im = i == 0 ? c + S.nx - 1 : c - 1;
+    const int jp = j + 1 == S.ny ? c - j * S.nx : c + S.nx;
+    const int jm = j == 0 ? c + (S.ny - 1) * S.nx : c - S.nx;
+    const double lx = (x[ip] - xc) + (x[im] - xc);
+    const double ly = (x[jp] - xc) + (x[jm] - xc);
+    double lz = 0.0;
+    if (k + 1 < S.nz) lz += x[c + plane] - xc;
+    if (k > 0) lz += x[c - plane] - xc;
+    out[off + c] = xc - (S.cx * lx + S.cy * ly + S.cz * lz);
+  }
 }
 
 __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
@@ -355,7 +372,8 @@ int launch_check(const DevParams& P, DevArrays& A, const double* y, int ntau, do
   S.cx = dtau / (P.hx * P.hx);
   S.cy = dtau / (P.hy * P.hy);
   S.cz = dtau / (P.hz * P.hz);
-  dim3 grid(nblk(P.ncell), 4);
+  const int rows = P.ny * P.nz;
+  dim3 grid((unsigned)((P.nx + kBlock - 1) / kBlock), (unsigned)(rows < 65535 ? rows : 65535), 4);
   const double* cur = y;
   double* bufs[2] = {A.sd0, A.sd1};
   for (int m = 0; m < ntau; ++m) {

@@ -13,9 +13,15 @@
 //   smooth = T^-1 diag((1 + Delta tau lambda)^-N_tau) T raw,
 // with T = H_x (x) H_y (x) C_z applied one axis at a time.  Every axis
 // transform is a small dense real matrix product over the field, done here
-// as a tiled FP64 GEMM (LDS tiles, 4 x 4 outputs per lane); the spectral
-// factor is applied in the epilogue of the forward z pass.  Six passes over
+// as a tiled FP64 GEMM; the spectral factor is applied in the epilogue of the
+// forward z pass.  Six passes over
 // the field replace the tens of stencil sweeps of an iterative solve.
+//
+// The GEMM runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64): a block
+// computes a 64 x 64 tile of C with four waves of 32 x 32 (2 x 2 MFMA tiles);
+// K is staged through LDS 16 at a time.  Per MFMA a lane reads one double of
+// A and one of B, against eight LDS reads per 16 FMAs for a 4 x 4 outer
+// product on the vector units.
 #include "k_common.h"
 
 namespace sedimi {
@@ -42,63 +48,83 @@ struct Gemm {
   double dtau;
 };
 
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 template <bool SPECTRAL>
 __global__ __launch_bounds__(256) void k_gemm64(Gemm g) {
   __shared__ double As[kTK][kTM + 1];
   __shared__ double Bs[kTK][kTN];
   const int tid = threadIdx.x;
-  const int tm = tid >> 4, tn = tid & 15;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;  // the wave's 32 x 32 quarter of the tile
+  const int lr = lane & 15, lk = lane >> 4;
   const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
   const int64_t b = blockIdx.z;
   const double* A = g.A + b * g.sa;
   const double* B = g.B + b * g.sb;
   double* C = g.C + b * g.sc;
-  double acc[4][4];
+  v4d acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < g.K; k0 += kTK) {
-    // A tile: 64 rows x 16 k, read along k (contiguous), stored k-major
+  // The next K chunk is loaded into registers while the current one, already
+  // in LDS, feeds the matrix cores.
+  double ra[4], rb[4];
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
+      // A: 64 rows x 16 k, read along k (contiguous)
       const int r = (tid >> 4) + 16 * s, c = tid & 15;
       const int m = m0 + r, k = k0 + c;
-      As[c][r] = (m < g.M && k < g.K) ? A[(int64_t)m * g.lda + k] : 0.0;
+      ra[s] = (m < g.M && k < g.K) ? A[(int64_t)m * g.lda + k] : 0.0;
+      // B: 16 k x 64 columns, read along the columns (contiguous)
+      const int idx = tid + 256 * s;
+      const int rr = idx >> 6, cc = idx & 63;
+      const int kb = k0 + rr, n = n0 + cc;
+      rb[s] = (kb < g.K && n < g.N) ? B[(int64_t)kb * g.ldb + n] : 0.0;
     }
-    // B tile: 16 k x 64 columns, read along the columns (contiguous)
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < g.K; k0 += kTK) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
+      As[tid & 15][(tid >> 4) + 16 * s] = ra[s];  // stored k-major
       const int idx = tid + 256 * s;
-      const int r = idx >> 6, c = idx & 63;
-      const int k = k0 + r, n = n0 + c;
-      Bs[r][c] = (k < g.K && n < g.N) ? B[(int64_t)k * g.ldb + n] : 0.0;
+      Bs[idx >> 6][idx & 63] = rb[s];
     }
     __syncthreads();
+    if (k0 + kTK < g.K) fetch(k0 + kTK);
+    // MFMA operands: lane (lr, lk) holds A[m = lr][k = lk] and B[k = lk][n = lr]
+    // of each 16 x 4 / 4 x 16 fragment
 #pragma unroll
-    for (int kk = 0; kk < kTK; ++kk) {
-      double a[4], bb[4];
+    for (int kk = 0; kk < kTK; kk += 4) {
+      double a[2], bb[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm * 4 + i];
+      for (int i = 0; i < 2; ++i) a[i] = As[kk + lk][wm * 32 + i * 16 + lr];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tn + 16 * j];
+      for (int j = 0; j < 2; ++j) bb[j] = Bs[kk + lk][wn * 32 + j * 16 + lr];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fma(a[i], bb[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
+  // result layout (checked on the device): element r of lane (lr, lk) is row
+  // lk + 4 r, column lr of each 16 x 16 tile
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int m = m0 + tm * 4 + i;
-    if (m >= g.M) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + tn + 16 * j;
-      if (n >= g.N) continue;
-      double v = g.alpha * acc[i][j];
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + wm * 32 + i * 16 + lk + 4 * r;
+      const int n = n0 + wn * 32 + j * 16 + lr;
+      if (m >= g.M || n >= g.N) continue;
+      double v = g.alpha * acc[i][j][r];
       if (SPECTRAL) {
         const double lam = g.lam_m[m] + g.lam_x[n % g.nx] + g.lam_y[n / g.nx];
         const double f = 1.0 / (1.0 + g.dtau * lam);
@@ -108,7 +134,6 @@ __global__ __launch_bounds__(256) void k_gemm64(Gemm g) {
       }
       C[(int64_t)m * g.ldc + n] = v;
     }
-  }
 }
 
 void gemm(const Gemm& g, int batch, bool spectral, hipStream_t s) {
