@@ -16,6 +16,7 @@
 // offsets negated and the weights transposed; the weight gradient is a GEMM
 // over cells (K = cells) whose operands come from LDS through transpose
 // reads, with per-block partial sums reduced in a fixed order.
+#include <limits.h>
 #include <math.h>
 
 #include "k_nn.h"
@@ -92,21 +93,41 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(ConvGeom g, const __bf16*
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[m][nt] = v4f{0.f, 0.f, 0.f, 0.f};
     if (CIN == 32) {
+      // Neighbour offsets of each tile's cell, once: x-neighbours (wrapped),
+      // y-row offsets (wrapped) and z-plane offsets (negative when the plane
+      // is outside the mesh: zero padding); tap (dz, dy, dx) is then
+      // zo[dz] + yo[dy] + xo[dx].  Negated taps (data gradient) swap the ends.
+      int xo[TM][3], yo[TM][3], zo[TM][3];
+      const int plane = g.nx * g.ny;
+#pragma unroll
+      for (int m = 0; m < TM; ++m) {
+        const int im = ci[m] == 0 ? g.nx - 1 : ci[m] - 1, ip = ci[m] + 1 == g.nx ? 0 : ci[m] + 1;
+        const int jm = cj[m] == 0 ? g.ny - 1 : cj[m] - 1, jp = cj[m] + 1 == g.ny ? 0 : cj[m] + 1;
+        const int km = ck[m] - g.dil, kp = ck[m] + g.dil;
+        const int zm = km >= 0 ? km * plane : INT_MIN / 2, zp = kp < g.nz ? kp * plane : INT_MIN / 2;
+        const int zc = valid[m] ? ck[m] * plane : INT_MIN / 2;
+        xo[m][0] = g.neg ? ip : im, xo[m][1] = ci[m], xo[m][2] = g.neg ? im : ip;
+        yo[m][0] = (g.neg ? jp : jm) * g.nx, yo[m][1] = cj[m] * g.nx, yo[m][2] = (g.neg ? jm : jp) * g.nx;
+        zo[m][0] = valid[m] ? (g.neg ? zp : zm) : INT_MIN / 2, zo[m][1] = zc;
+        zo[m][2] = valid[m] ? (g.neg ? zm : zp) : INT_MIN / 2;
+      }
+      // t is uniform across the wave: the three choices are scalar selects
+      auto pick = [](const int (&v)[3], int sel) { return sel == 0 ? v[0] : (sel == 1 ? v[1] : v[2]); };
+      auto frag = [&](int m, int t) -> v8bf {
+        const int q = pick(zo[m], t / 9) + pick(yo[m], (t / 3) % 3) + pick(xo[m], t % 3);
+        return q >= 0 ? *reinterpret_cast<const v8bf*>(in + (size_t)q * 32 + grp * 8) : zero8;
+      };
       // software pipeline: the next tap's neighbour fragments are in flight
       // while the current tap's MFMAs run
       v8bf a[TM], an[TM];
 #pragma unroll
-      for (int m = 0; m < TM; ++m) {
-        const int q = valid[m] ? tap_cell(g, ci[m], cj[m], ck[m], 0) : -1;
-        a[m] = q >= 0 ? *reinterpret_cast<const v8bf*>(in + (size_t)q * 32 + grp * 8) : zero8;
-      }
+      for (int m = 0; m < TM; ++m) a[m] = frag(m, 0);
+      // kept rolled: unrolled, the hoisted loads of all taps spill registers
+#pragma unroll 1
       for (int t = 0; t < 27; ++t) {
         if (t + 1 < 27) {
 #pragma unroll
-          for (int m = 0; m < TM; ++m) {
-            const int q = valid[m] ? tap_cell(g, ci[m], cj[m], ck[m], t + 1) : -1;
-            an[m] = q >= 0 ? *reinterpret_cast<const v8bf*>(in + (size_t)q * 32 + grp * 8) : zero8;
-          }
+          for (int m = 0; m < TM; ++m) an[m] = frag(m, t + 1);
         }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
