@@ -44,7 +44,8 @@ extern "C" {
 #define SEDIMI_EINVAL (-1)    /* bad argument or parameter */
 #define SEDIMI_ENOMEM (-2)    /* workspace missing or too small, or host allocation failed */
 #define SEDIMI_EDEVICE (-3)   /* a HIP runtime call failed */
-#define SEDIMI_EOVERFLOW (-4) /* neighbour slots exceeded or a contact fell out of the list */
+#define SEDIMI_EOVERFLOW (-4) /* neighbour slots exceeded, a contact fell out of the list, or
+                                 a neighbour bin / mesh cell too crowded to sort */
 #define SEDIMI_EUNSTABLE (-5) /* non-finite state */
 #define SEDIMI_EESCAPE (-6)   /* a particle left [0, Lz] through a wall plane */
 #define SEDIMI_ENOCONV (-7)   /* diffusion solve above its residual tolerance */
@@ -132,7 +133,9 @@ typedef struct {
   int64_t steps;          /* steps taken since sedimi_set_particles */
   int64_t rebuilds;       /* neighbour-list rebuilds (re-sorts) */
   int32_t max_neighbors;  /* largest neighbour count seen at a rebuild */
-  int32_t flags;          /* bit 0 slot overflow, 1 lost contact, 2 escape, 3 non-finite */
+  int32_t flags;          /* bit 0 slot overflow, 1 lost contact, 2 escape, 3 non-finite,
+                             4 a neighbour bin (> 1024) or mesh cell (> 4096) too crowded
+                             to sort */
   int64_t solve_iters;    /* iterations of the last diffusion solve (all steps) */
   double solve_residual;  /* largest final relative residual of the last solve */
   double mean_neighbors;  /* mean neighbour-list length per particle (now) */
@@ -196,9 +199,11 @@ int sedimi_compute_forces(sedimi_ctx* ctx, int update_history);
 int sedimi_step(sedimi_ctx* ctx, int nsteps, int average_every);
 /* Deposition (Eq. 11) into the RAW field, then the diffusion solve (Eq. 12)
  * into the SMOOTH field.  Both use the particles' current positions and the
- * drag of the last force evaluation. */
+ * drag of the last force evaluation.  Like sedimi_step, returns the error of
+ * any state flag raised since sedimi_set_particles (EOVERFLOW when a mesh
+ * cell holds more than 4096 particles: its sum is then not in ID order). */
 int sedimi_average(sedimi_ctx* ctx);
-/* Deposition only (RAW field). */
+/* Deposition only (RAW field); flags as sedimi_average. */
 int sedimi_deposit(sedimi_ctx* ctx);
 /* Diffusion solve only: SMOOTH <- smoothed RAW, for channels [0, nch). */
 int sedimi_smooth(sedimi_ctx* ctx, int nch);

@@ -38,10 +38,8 @@ __global__ void k_cellkey(DevParams P, DevArrays A) {
   int k = -1;
   if (valid) {
     const double4 x = A.pos[q];
-    int a = (int)floor(x.x / P.hx), b = (int)floor(x.y / P.hy), c = (int)floor(x.z / P.hz);
-    a = a < 0 ? 0 : (a >= P.nx ? P.nx - 1 : a);
-    b = b < 0 ? 0 : (b >= P.ny ? P.ny - 1 : b);
-    c = c < 0 ? 0 : (c >= P.nz ? P.nz - 1 : c);
+    const int a = grid_coord(x.x, P.hx, P.nx), b = grid_coord(x.y, P.hy, P.ny),
+              c = grid_coord(x.z, P.hz, P.nz);
     k = (c * P.ny + b) * P.nx + a;
     A.key[q] = k;
   }
@@ -76,7 +74,10 @@ __global__ void k_cellsum(DevParams P, DevArrays A) {
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P.ncell) return;
   int s = A.cell_start[c], e = A.cell_start[c + 1];
-  for (int i = s + 1; i < e; ++i) {
+  // a crowded cell is summed unsorted (order not reproducible) and flagged
+  const bool sorted = e - s <= kMaxCellMembers;
+  if (!sorted) atomicOr(&A.ctl->flags, kFlagCrowded);
+  for (int i = s + 1; sorted && i < e; ++i) {
     const unsigned long long key = A.cperm[i];
     int j = i - 1;
     while (j >= s && A.cperm[j] > key) {

@@ -61,10 +61,10 @@ __device__ __forceinline__ void kick_drift_one(const DevParams& P, const DevArra
   if (x.y < 0.0) x.y += P.Ly;
   if (x.y >= P.Ly) x.y = 0.0;
   int fl = 0;
-  if (!(x.z >= 0.0 && x.z <= P.Lz)) fl |= 4;
+  if (!(x.z >= 0.0 && x.z <= P.Lz)) fl |= kFlagEscape;
   if (!(isfinite(x.x) && isfinite(x.y) && isfinite(x.z) && isfinite(v.x) && isfinite(v.y) &&
         isfinite(v.z)))
-    fl |= 8;
+    fl |= kFlagNonFinite;
   if (fl) atomicOr(&A.ctl->flags, fl);
   const double4 b = A.xb[q];
   const double dx = min_image(x.x - b.x, P.Lx, P.hLx), dy = min_image(x.y - b.y, P.Ly, P.hLy),
@@ -72,11 +72,16 @@ __device__ __forceinline__ void kick_drift_one(const DevParams& P, const DevArra
   if (dx * dx + dy * dy + dz * dz > P.half_skin2) atomicOr(rb, 1);
 }
 
-// Bin coordinate of a position (clamped into the grid).
-__device__ __forceinline__ int bin_coord(double x, double h, int n) {
-  int b = (int)floor(x / h);
-  return b < 0 ? 0 : (b >= n ? n - 1 : b);
+// Index of the grid interval of width h holding x, clamped into [0, n - 1]
+// before the conversion to int, so that huge and non-finite coordinates
+// (NaN goes to 0) give a valid index.
+__device__ __forceinline__ int grid_coord(double x, double h, int n) {
+  const double f = floor(x / h);
+  return f >= 0.0 ? (f < (double)n ? (int)f : n - 1) : 0;
 }
+
+// Bin coordinate of a position (clamped into the grid).
+__device__ __forceinline__ int bin_coord(double x, double h, int n) { return grid_coord(x, h, n); }
 
 __device__ __forceinline__ int bin_of(const DevParams& P, double x, double y, double z) {
   int bx = bin_coord(x, P.hbx, P.nbx), by = bin_coord(y, P.hby, P.nby),

@@ -55,7 +55,7 @@ __device__ __forceinline__ void compact_one(const DevParams& P, const DevArrays&
   for (int k = 0; k < cnt; ++k) {
     if (!(m & (1u << k))) continue;
     if (c >= kMaxContacts) {
-      atomicOr(&A.ctl->flags, 1);
+      atomicOr(&A.ctl->flags, kFlagOverflow);
       break;
     }
     int j = A.nbr[(size_t)k * N + p];
@@ -103,6 +103,10 @@ __global__ void k_binsort(DevParams P, DevArrays A) {
   for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < P.nbins;
        b += gridDim.x * blockDim.x) {
     int s = A.bin_start[b], e = A.bin_start[b + 1];
+    if (e - s > kMaxBinMembers) {
+      atomicOr(&A.ctl->flags, kFlagCrowded);
+      continue;
+    }
     for (int i = s + 1; i < e; ++i) {
       int p = A.perm[i];
       int key = A.id[p];
@@ -153,48 +157,79 @@ __global__ void k_copyback(DevParams P, DevArrays A) {
 }
 
 // Neighbour list of particle q: every particle in the 27 surrounding bins
-// within (pair range + skin); then the history rows of q's pre-sort slot are
-// matched onto the new slots by partner ID.
+// within (pair range + skin), ordered by class: overlapping (in contact)
+// first, then within the lubrication range, then the rest; in bin-scan order
+// within a class.  The force kernel walks the slots of a wave's particles in
+// lockstep and runs the contact and lubrication code for a slot when any lane
+// needs it, so putting each list's contacts first about halves the slots
+// that run the contact code (and touch the tangential history).  Two passes
+// over the bins: the first counts each class, the second places.  Then the
+// history rows of q's pre-sort slot are matched onto the new slots by
+// partner ID.
 template <typename H>
 __global__ void k_build(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < P.n;
        q += gridDim.x * blockDim.x) {
     const int N = P.n;
-    double4 xi = A.pos[q];
-    int bx = bin_coord(xi.x, P.hbx, P.nbx), by = bin_coord(xi.y, P.hby, P.nby),
-        bz = bin_coord(xi.z, P.hbz, P.nbz);
-    int cnt = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
-      int cz = bz + dz;
-      if (cz < 0 || cz >= P.nbz) continue;
-      for (int dy = -1; dy <= 1; ++dy) {
-        int cy = by + dy;
-        cy = cy < 0 ? cy + P.nby : (cy >= P.nby ? cy - P.nby : cy);
-        for (int dx = -1; dx <= 1; ++dx) {
-          int cx = bx + dx;
-          cx = cx < 0 ? cx + P.nbx : (cx >= P.nbx ? cx - P.nbx : cx);
-          int b = A.bin_rank[(cz * P.nby + cy) * P.nbx + cx];
-          int s = A.bin_start[b], e = A.bin_start[b + 1];
-          for (int j = s; j < e; ++j) {
-            if (j == q) continue;
-            double4 xj = A.pos[j];
-            double ddx = min_image(xj.x - xi.x, P.Lx, P.hLx);
-            double ddy = min_image(xj.y - xi.y, P.Ly, P.hLy);
-            double ddz = xj.z - xi.z;
-            double s2 = ddx * ddx + ddy * ddy + ddz * ddz;
-            double rs = xi.w + xj.w;
-            double Rl = rs + P.lub_out * rs + P.skin;
-            if (s2 < Rl * Rl * (1.0 + 1e-9)) {
-              if (cnt < P.maxn) A.nbr[(size_t)cnt * N + q] = j;
-              ++cnt;
+    const double4 xi = A.pos[q];
+    const int bx = bin_coord(xi.x, P.hbx, P.nbx), by = bin_coord(xi.y, P.hby, P.nby),
+              bz = bin_coord(xi.z, P.hbz, P.nbz);
+    // pass 0 counts the candidates of each class, pass 1 places them; a pass
+    // stops once more than maxn candidates have been seen (the list has
+    // overflowed), at the same candidate in both
+    int n0 = 0, n1 = 0, cnt = 0, w0 = 0, w1 = 0, w2 = 0;
+#pragma unroll 1
+    for (int pass = 0; pass < 2; ++pass) {
+      int seen = 0;
+#pragma unroll 1
+      for (int dz = -1; dz <= 1; ++dz) {
+        const int cz = bz + dz;
+        if (cz < 0 || cz >= P.nbz) continue;
+#pragma unroll 1
+        for (int dy = -1; dy <= 1; ++dy) {
+          int cy = by + dy;
+          cy = cy < 0 ? cy + P.nby : (cy >= P.nby ? cy - P.nby : cy);
+#pragma unroll 1
+          for (int dx = -1; dx <= 1; ++dx) {
+            int cx = bx + dx;
+            cx = cx < 0 ? cx + P.nbx : (cx >= P.nbx ? cx - P.nbx : cx);
+            const int b = A.bin_rank[(cz * P.nby + cy) * P.nbx + cx];
+            const int s = A.bin_start[b], e = A.bin_start[b + 1];
+            if (e - s > kMaxBinMembers) continue;  // flagged by k_binsort
+            for (int j = s; j < e && seen <= P.maxn; ++j) {
+              if (j == q) continue;
+              const double4 xj = A.pos[j];
+              const double ddx = min_image(xj.x - xi.x, P.Lx, P.hLx);
+              const double ddy = min_image(xj.y - xi.y, P.Ly, P.hLy);
+              const double ddz = xj.z - xi.z;
+              const double s2 = ddx * ddx + ddy * ddy + ddz * ddz;
+              const double rs = xi.w + xj.w;
+              const double Rl = rs + P.lub_out * rs + P.skin;
+              if (!(s2 < Rl * Rl * (1.0 + 1e-9))) continue;
+              const double Rp = rs + P.lub_out * rs;
+              const int c = s2 < rs * rs ? 0 : (s2 < Rp * Rp ? 1 : 2);
+              if (pass == 0) {
+                n0 += c == 0;
+                n1 += c == 1;
+                ++cnt;
+              } else {
+                const int w = c == 0 ? w0 : (c == 1 ? w1 : w2);
+                if (w < P.maxn) A.nbr[(size_t)w * N + q] = j;
+                w0 += c == 0;
+                w1 += c == 1;
+                w2 += c == 2;
+              }
+              ++seen;
             }
           }
         }
       }
+      w1 = n0;
+      w2 = n0 + n1;
     }
     if (cnt > P.maxn) {
-      atomicOr(&A.ctl->flags, 1);
+      atomicOr(&A.ctl->flags, kFlagOverflow);
       cnt = P.maxn;
     }
     atomicMax(&A.ctl->max_nbr, cnt);
@@ -226,7 +261,7 @@ __global__ void k_build(DevParams P, DevArrays A) {
     if (A.wxi[q].w != 0.0) mask |= 1u << 30;
     if (A.wxi[(size_t)N + q].w != 0.0) mask |= 1u << 31;
     A.hmask[q] = mask;
-    if (matched != nc) atomicOr(&A.ctl->flags, 2);
+    if (matched != nc) atomicOr(&A.ctl->flags, kFlagLost);
   }
 }
 

@@ -304,10 +304,13 @@ int read_ctl(sedimi_ctx* c, Ctl* out) {
 }
 
 int flags_to_rc(sedimi_ctx* c, int flags) {
-  if (flags & 8) return fail(c, SEDIMI_EUNSTABLE, "non-finite particle state");
-  if (flags & 4) return fail(c, SEDIMI_EESCAPE, "a particle left [0, Lz]");
-  if (flags & 1) return fail(c, SEDIMI_EOVERFLOW, "neighbour or contact slots exceeded");
-  if (flags & 2) return fail(c, SEDIMI_EOVERFLOW, "a contact fell out of the neighbour list");
+  if (flags & kFlagNonFinite) return fail(c, SEDIMI_EUNSTABLE, "non-finite particle state");
+  if (flags & kFlagEscape) return fail(c, SEDIMI_EESCAPE, "a particle left [0, Lz]");
+  if (flags & kFlagCrowded)
+    return fail(c, SEDIMI_EOVERFLOW,
+                "a neighbour bin or mesh cell holds more particles than its sort allows");
+  if (flags & kFlagOverflow) return fail(c, SEDIMI_EOVERFLOW, "neighbour or contact slots exceeded");
+  if (flags & kFlagLost) return fail(c, SEDIMI_EOVERFLOW, "a contact fell out of the neighbour list");
   return SEDIMI_OK;
 }
 
@@ -435,7 +438,7 @@ int check_solve(sedimi_ctx* c, int nch) {
   c->last_residual = res;
   // FP32 working vectors cannot go below ~1e-6 relative
   const double tol = c->mixed ? std::max(c->prm.avg_rtol, 1e-6) : c->prm.avg_rtol;
-  if (res > tol * 10.0 + 1e-300)
+  if (!(res <= tol * 10.0 + 1e-300))
     return fail(c, SEDIMI_ENOCONV, "diffusion solve residual above tolerance");
   return SEDIMI_OK;
 }
@@ -722,10 +725,10 @@ int sedimi_average(sedimi_ctx* c) {
   if (it < 0) return (int)it;
   c->last_iters = it;
   HIPCHK(c, hipGetLastError());
-  if (!plain) {
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return SEDIMI_OK;
-  }
+  Ctl ctl;
+  if ((rc = read_ctl(c, &ctl))) return rc;
+  if ((rc = flags_to_rc(c, ctl.flags))) return rc;
+  if (!plain) return SEDIMI_OK;
   return check_solve(c, 4);
 }
 
@@ -734,8 +737,9 @@ int sedimi_deposit(sedimi_ctx* c) {
   if (rc) return rc;
   launch_deposit(c->P, c->A, c->stream);
   HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipStreamSynchronize(c->stream));
-  return SEDIMI_OK;
+  Ctl ctl;
+  if ((rc = read_ctl(c, &ctl))) return rc;
+  return flags_to_rc(c, ctl.flags);
 }
 
 int sedimi_smooth(sedimi_ctx* c, int nch) {
@@ -929,7 +933,8 @@ int sedimi_set_history(sedimi_ctx* c, int64_t nrec, const void* records) {
   HIPCHK(c, hipMemcpyAsync(c->A.rb, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
   Ctl ctl;
   if ((rc = read_ctl(c, &ctl))) return rc;
-  if (ctl.flags & 2) return fail(c, SEDIMI_EINVAL, "a history pair is not in the neighbour list");
+  if (ctl.flags & kFlagLost)
+    return fail(c, SEDIMI_EINVAL, "a history pair is not in the neighbour list");
   return flags_to_rc(c, ctl.flags);
 }
 

@@ -33,6 +33,19 @@ namespace sedimi {
 
 constexpr int kBlock = 256;
 constexpr int kMaxContacts = 16;  // contacts per particle kept across a re-sort
+// Members a neighbour bin / a mesh cell may hold: each is ordered by one
+// thread (insertion sort), so a state that crowds many particles into one
+// (a non-finite or runaway position is clamped into the grid) would otherwise
+// cost that thread quadratic time.  Above the limit the bin or cell raises
+// kFlagCrowded instead; physical packings stay far below it.
+constexpr int kMaxBinMembers = 1024;
+constexpr int kMaxCellMembers = 4096;
+// Ctl::flags bits
+constexpr int kFlagOverflow = 1;   // neighbour or contact slots exceeded
+constexpr int kFlagLost = 2;       // a contact fell out of the neighbour list
+constexpr int kFlagEscape = 4;     // a particle left [0, Lz]
+constexpr int kFlagNonFinite = 8;  // non-finite position or velocity
+constexpr int kFlagCrowded = 16;   // a bin or mesh cell above its member limit
 
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
 // Renumber them so that every XCD works through one contiguous range of
@@ -46,11 +59,13 @@ inline unsigned xcd_grid(int64_t nblocks) {
 }
 
 // Flags and counters living in device memory.
+// rebuild / rebuild_alt are the two rebuild flags: DevArrays::rb points at
+// the one of the current step, rb_next at the other.
 struct Ctl {
-  int rebuild;       // rebuild flags: DevArrays::rb points at the one of the
-  int flags;         // bit 0 overflow, 1 lost contact, 2 escape, 3 non-finite
-  int max_nbr;       // largest neighbour count at a build
-  int rebuild_alt;   // current step, rb_next at the other (see there)
+  int rebuild;
+  int flags;        // kFlag* bits
+  int max_nbr;      // largest neighbour count at a build
+  int rebuild_alt;
   long long rebuilds;
   long long pad1[5];
 };

@@ -317,3 +317,43 @@ def test_error_paths_forced_from_the_host():
     with pytest.raises(sm.SedimiError) as e:
         g.step(1)
     assert e.value.code == sm.EUNSTABLE
+
+
+def test_crowded_and_runaway_states_end_in_error_codes():
+    """States that pile many particles into one neighbour bin or mesh cell
+    end in error codes in bounded time: each bin and cell is ordered by one
+    thread, so above its member limit (1024 per bin, 4096 per cell) it is
+    flagged instead of sorted.  Covers a finite pile-up set by the caller and
+    a run whose positions all turn non-finite (they are clamped into one mesh
+    cell) with averaging in the loop."""
+    import paper_1601_03801_amd as sm
+    w = workloads.workload("small")
+    prm = w["params"]
+    n = 5000
+    rng = np.random.default_rng(3)
+    centre = np.array([0.5 * prm["Lx"], 0.5 * prm["Ly"], 0.5 * prm["Lz"]])
+    x = centre + rng.uniform(-1e-7, 1e-7, size=(n, 3))
+    d = np.full(n, float(w["d"].max()))
+    g = sm.Sedimi(prm, n, precision="fp64", d_max=float(d.max()), skin=0.1 * float(d.max()),
+                  max_neighbors=24)
+    g.set_fluid(w["U"], w["gradp"], w["dudt"])
+    with pytest.raises(sm.SedimiError) as e:
+        g.set_particles(x, np.zeros((n, 3)), d, np.full(n, workloads.RHO_P))
+    assert e.value.code == sm.EOVERFLOW
+    assert "more particles than its sort allows" in str(e.value)
+    with pytest.raises(sm.SedimiError) as e:
+        g.deposit()
+    assert e.value.code == sm.EOVERFLOW
+    assert g.stats()["flags"] & 16
+
+    case = dense_bed(6000, 5)
+    case["v"] = np.full_like(case["v"], float("nan"))
+    g = gpu_context(case)
+    with pytest.raises(sm.SedimiError) as e:
+        g.step(4, average_every=2)
+    assert e.value.code == sm.EUNSTABLE
+    st = g.stats()
+    assert st["flags"] & 8 and st["flags"] & 16  # 6000 NaN positions in one cell
+    with pytest.raises(sm.SedimiError) as e:
+        g.average()
+    assert e.value.code == sm.EUNSTABLE
