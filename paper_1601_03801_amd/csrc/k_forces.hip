@@ -220,14 +220,16 @@ __device__ __forceinline__ V3<float> sym_rw<float>(double ri, const double4& wi,
 // torque on i.  The pair is computed in the frame of its lower-ID particle
 // (normal from lower to higher ID) using only sign-symmetric and commutative
 // steps, so both sides of the pair compute the same bits; the result is added
-// with the sign of i's side.  Updates slot k's tangential history.
+// with the sign of i's side.  xi is slot k's tangential history at the start
+// of the step (zero if the slot held no contact); the updated history is
+// stored back into slot k.
 template <typename R>
 __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& A, int N, int i,
                                            int k, const double4& pi, const double4& pj,
                                            const double4& vj, const double4& wj, int idj,
                                            double dx, double dy, double dz, double s,
                                            const double4& vi, const double4& wi, int idi,
-                                           unsigned mask_old, bool upd, V3<R>& Fc, V3<R>& Fl,
+                                           V3<R> xi, bool upd, V3<R>& Fc, V3<R>& Fl,
                                            V3<R>& T, unsigned& mask_new) {
   const double ri = pi.w, mi = vi.w;
   const double rs = ri + pj.w;
@@ -267,9 +269,7 @@ __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& 
     const R gn = (R)(2.0 * P.zeta) * sqrt(meff * kn);
     const R gt = (R)P.gt_over_gn * gn;
     const R Frep = kn * (R)delta + gn * un;
-    V3<R> xi{0, 0, 0};
     const size_t o = (size_t)k * N + i;
-    if (mask_old & (1u << k)) xi = V3<R>{hx[o], hy[o], hz[o]};
     const V3<R> ft = tangential<R>(kt, gt, mu, dtR, n, vrel, un, fabs(Frep), xi);
     Fpc = ft - Frep * n;
     Tp = (R)ri * cross(n, ft);
@@ -342,32 +342,41 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
   unsigned mask_new = 0;
   const int cnt = A.ncnt[i];
 
+  const R* hx = (const R*)A.hxi;
+  const R* hy = hx + (size_t)P.maxn * N;
+  const R* hz = hy + (size_t)P.maxn * N;
   for (int k = 0; k < cnt; ++k) {
     const int j = A.nbr[(size_t)k * N + i];
+    // The slot's tangential history and the partner's whole state are
+    // loaded together, before the range test: a wait for a load also waits
+    // for every earlier store (the previous slot's history), so fewer,
+    // larger groups of loads per slot pay that wait fewer times.
+    V3<R> xi{0, 0, 0};
+    if (mask_old & (1u << k)) {
+      const size_t o = (size_t)k * N + i;
+      xi = V3<R>{hx[o], hy[o], hz[o]};
+    }
     const int t = j - wlo;
     const bool staged = (unsigned)t < (unsigned)kStage;
-    double4 pj;
-    if (staged)
+    double4 pj, vj, wj;
+    int idj;
+    if (staged) {
       pj = S.pos[t];
-    else
+      vj = S.vel[t];
+      wj = S.omg[t];
+      idj = (int)wj.w;
+    } else {
       pj = A.pos[j];
+      vj = A.vel[j];
+      wj = A.omg[j];
+      idj = A.id[j];
+    }
     const double dx = min_image(pj.x - pi.x, P.Lx, P.hLx);
     const double dy = min_image(pj.y - pi.y, P.Ly, P.hLy);
     const double dz = pj.z - pi.z;
     const double s = pair_s(dx, dy, dz);
     if (!pair_in_range(s, ri + pj.w, P.lub_out)) continue;
-    double4 vj, wj;
-    int idj;
-    if (staged) {
-      vj = S.vel[t];
-      wj = S.omg[t];
-      idj = (int)wj.w;
-    } else {
-      vj = A.vel[j];
-      wj = A.omg[j];
-      idj = A.id[j];
-    }
-    pair_force<R>(P, A, N, i, k, pi, pj, vj, wj, idj, dx, dy, dz, s, vi, wi, idi, mask_old, upd,
+    pair_force<R>(P, A, N, i, k, pi, pj, vj, wj, idj, dx, dy, dz, s, vi, wi, idi, xi, upd,
                   Fc, Flub, T, mask_new);
   }
   const double4 ai = A.acc[i];  // loaded after the pair loop: not live across it
