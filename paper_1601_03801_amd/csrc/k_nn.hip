@@ -47,6 +47,63 @@ __device__ __forceinline__ int tap_cell(const ConvGeom& g, int i, int j, int k, 
   return (kk * g.ny + jj) * g.nx + ii;
 }
 
+// Output element o = cell * COUT + n (channel n) of the layer from its
+// accumulated convolution v.
+template <int EPI>
+__device__ __forceinline__ void epilogue(const EpiArgs& e, const float* __restrict__ bias,
+                                         size_t o, int n, float v) {
+  if (EPI == EPI_FIRST || EPI == EPI_RES) {
+    const float zb = bf(v + bias[n]);
+    if (e.zout) e.zout[o] = (__bf16)zb;
+    float h = leaky(zb, e.alpha);
+    if (EPI == EPI_RES) h += (float)e.hin[o];
+    e.hout[o] = (__bf16)h;
+  } else if (EPI == EPI_LAST) {
+    e.yout[o] = e.xres[o] + v + bias[n];
+  } else {  // EPI_BWD: dh = acc (+ dh of the layer above); dz = dh * phi'(z)
+    float gsum = v + (e.hin ? (float)e.hin[o] : 0.0f);
+    const float gb = bf(gsum);
+    if (e.hout) e.hout[o] = (__bf16)gb;
+    if (e.zout) e.zout[o] = (__bf16)(gb * dleaky((float)e.zin[o], e.alpha));
+  }
+}
+
+// The same for channels n0 .. n0+3 of one cell (o = cell * 32 + n0): 8-byte
+// loads and stores, the same roundings as epilogue().
+template <int EPI>
+__device__ __forceinline__ void epilogue4(const EpiArgs& e, const float* __restrict__ bias,
+                                          size_t o, int n0, const float4& v4) {
+  const float v[4] = {v4.x, v4.y, v4.z, v4.w};
+  if (EPI == EPI_FIRST || EPI == EPI_RES) {
+    v4bf hin4 = {};
+    if (EPI == EPI_RES) hin4 = *reinterpret_cast<const v4bf*>(e.hin + o);
+    v4bf zb4, h4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float zb = bf(v[q] + bias[n0 + q]);
+      zb4[q] = (__bf16)zb;
+      float h = leaky(zb, e.alpha);
+      if (EPI == EPI_RES) h += (float)hin4[q];
+      h4[q] = (__bf16)h;
+    }
+    if (e.zout) *reinterpret_cast<v4bf*>(e.zout + o) = zb4;
+    *reinterpret_cast<v4bf*>(e.hout + o) = h4;
+  } else if (EPI == EPI_BWD) {
+    v4bf hin4 = {}, zin4 = {};
+    if (e.hin) hin4 = *reinterpret_cast<const v4bf*>(e.hin + o);
+    if (e.zout) zin4 = *reinterpret_cast<const v4bf*>(e.zin + o);
+    v4bf gb4, dz4;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float gb = bf(v[q] + (e.hin ? (float)hin4[q] : 0.0f));
+      gb4[q] = (__bf16)gb;
+      dz4[q] = (__bf16)(gb * dleaky((float)zin4[q], e.alpha));
+    }
+    if (e.hout) *reinterpret_cast<v4bf*>(e.hout + o) = gb4;
+    if (e.zout) *reinterpret_cast<v4bf*>(e.zout + o) = dz4;
+  }
+}
+
 // Weights in LDS, layout for CIN = 32: [27][NT*16][32]; for CIN = 4:
 // [NT*16][128] with k = tap*4 + channel (zero beyond 108).
 template <int CIN, int COUT>
@@ -65,9 +122,12 @@ template <int CIN, int COUT, int EPI>
 __global__ __launch_bounds__(kConvThreads) void k_conv(ConvGeom g, const __bf16* __restrict__ in,
                                               const __bf16* __restrict__ wpk,
                                               const float* __restrict__ bias, EpiArgs e) {
+  static_assert(CIN == 4 && COUT == 32, "k_conv serves the 4 -> 32 channel convolutions");
   constexpr int NT = WShape<CIN, COUT>::NT;
   constexpr int WE = WShape<CIN, COUT>::elems;
+  constexpr int kOS = 36;  // epilogue staging: cell stride in floats
   __shared__ __attribute__((aligned(16))) __bf16 sw[WE];
+  __shared__ __attribute__((aligned(16))) float ep[kConvThreads / 64][32 * kOS];
   for (int q = threadIdx.x; q < WE / 8; q += blockDim.x)
     reinterpret_cast<uint4*>(sw)[q] = reinterpret_cast<const uint4*>(wpk)[q];
   __syncthreads();
@@ -75,7 +135,7 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(ConvGeom g, const __bf16*
   const int row = lane & 15, grp = lane >> 4;
   const int ngroups = (g.ncell + 16 * TM - 1) / (16 * TM);
   const int wpb = blockDim.x / 64;
-  const v8bf zero8 = {};
+  float* wreg = &ep[wave][0];
   for (int tg = blockIdx.x * wpb + wave; tg < ngroups; tg += gridDim.x * wpb) {
     int ci[TM], cj[TM], ck[TM];
     bool valid[TM];
@@ -92,43 +152,164 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(ConvGeom g, const __bf16*
     for (int m = 0; m < TM; ++m)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[m][nt] = v4f{0.f, 0.f, 0.f, 0.f};
-    if (CIN == 32) {
-      // Neighbour offsets of each tile's cell, once: x-neighbours (wrapped),
-      // y-row offsets (wrapped) and z-plane offsets (negative when the plane
-      // is outside the mesh: zero padding); tap (dz, dy, dx) is then
-      // zo[dz] + yo[dy] + xo[dx].  Negated taps (data gradient) swap the ends.
-      int xo[TM][3], yo[TM][3], zo[TM][3];
-      const int plane = g.nx * g.ny;
+    // 4 input channels: two taps share a lane group, K padded from 108 to 128
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int t0 = 8 * s + 2 * grp, t1 = t0 + 1;
+      v8bf a[TM];
 #pragma unroll
       for (int m = 0; m < TM; ++m) {
-        const int im = ci[m] == 0 ? g.nx - 1 : ci[m] - 1, ip = ci[m] + 1 == g.nx ? 0 : ci[m] + 1;
-        const int jm = cj[m] == 0 ? g.ny - 1 : cj[m] - 1, jp = cj[m] + 1 == g.ny ? 0 : cj[m] + 1;
-        const int km = ck[m] - g.dil, kp = ck[m] + g.dil;
-        const int zm = km >= 0 ? km * plane : INT_MIN / 2, zp = kp < g.nz ? kp * plane : INT_MIN / 2;
-        const int zc = valid[m] ? ck[m] * plane : INT_MIN / 2;
-        xo[m][0] = g.neg ? ip : im, xo[m][1] = ci[m], xo[m][2] = g.neg ? im : ip;
-        yo[m][0] = (g.neg ? jp : jm) * g.nx, yo[m][1] = cj[m] * g.nx, yo[m][2] = (g.neg ? jm : jp) * g.nx;
-        zo[m][0] = valid[m] ? (g.neg ? zp : zm) : INT_MIN / 2, zo[m][1] = zc;
-        zo[m][2] = valid[m] ? (g.neg ? zm : zp) : INT_MIN / 2;
-      }
-      // t is uniform across the wave: the three choices are scalar selects
-      auto pick = [](const int (&v)[3], int sel) { return sel == 0 ? v[0] : (sel == 1 ? v[1] : v[2]); };
-      auto frag = [&](int m, int t) -> v8bf {
-        const int q = pick(zo[m], t / 9) + pick(yo[m], (t / 3) % 3) + pick(xo[m], t % 3);
-        return q >= 0 ? *reinterpret_cast<const v8bf*>(in + (size_t)q * 32 + grp * 8) : zero8;
-      };
-      // software pipeline: the next tap's neighbour fragments are in flight
-      // while the current tap's MFMAs run
-      v8bf a[TM], an[TM];
-#pragma unroll
-      for (int m = 0; m < TM; ++m) a[m] = frag(m, 0);
-      // kept rolled: unrolled, the hoisted loads of all taps spill registers
-#pragma unroll 1
-      for (int t = 0; t < 27; ++t) {
-        if (t + 1 < 27) {
-#pragma unroll
-          for (int m = 0; m < TM; ++m) an[m] = frag(m, t + 1);
+        v4bf lo = {}, hi = {};
+        if (valid[m] && t0 < 27) {
+          const int q = tap_cell(g, ci[m], cj[m], ck[m], t0);
+          if (q >= 0) lo = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
         }
+        if (valid[m] && t1 < 27) {
+          const int q = tap_cell(g, ci[m], cj[m], ck[m], t1);
+          if (q >= 0) hi = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
+        }
+        a[m] = v8bf{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const v8bf b = *reinterpret_cast<const v8bf*>(sw + (nt * 16 + row) * 128 + 32 * s + grp * 8);
+#pragma unroll
+        for (int m = 0; m < TM; ++m)
+          acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][nt], 0, 0, 0);
+      }
+    }
+    // acc[m][nt][r] = output (cell (tg*TM + m)*16 + 4*grp + r, channel nt*16 + row).
+    // Through the wave's own LDS region, 32 cells at a time, so that each
+    // lane then handles 4 consecutive channels of a cell (as in
+    // k_conv_tiled).  Only this wave touches its region; the fences keep the
+    // compiler from moving the lanes' reads above the other lanes' writes
+    // (the LDS executes one wave's accesses in order).
+    const int c0 = tg * TM * 16;
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            wreg[(16 * mm + 4 * grp + r) * kOS + nt * 16 + row] = acc[2 * ps + mm][nt][r];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int id = lane + 64 * j;
+        const int cl = id >> 3, n0 = 4 * (id & 7);
+        const int co = c0 + 32 * ps + cl;
+        if (co >= g.ncell) continue;
+        const float4 v4 = *reinterpret_cast<const float4*>(wreg + cl * kOS + n0);
+        epilogue4<EPI>(e, bias, (size_t)co * 32 + n0, n0, v4);
+      }
+    }
+  }
+}
+
+// Convolutions with 32 input channels, tiled through LDS.  A block of 16
+// waves owns an output tile of 64 (x) by 16 (y) cells in one z-plane; wave w
+// computes row w of it as 4 MFMA tiles of 16 cells.  The taps are taken one
+// z-plane at a time: the block copies the input plane (the tile plus a
+// one-cell halo in x and y, periodic; zeros outside the mesh in z) into LDS
+// with coalesced 16-byte loads, then every wave reads the A fragments of the
+// plane's 9 taps from LDS, where 16 consecutive cells of one row are 1 KB of
+// contiguous LDS (no bank conflicts).  Each input cell is thus read from
+// memory about 1.3 times per plane (halo) instead of once per tap through
+// L1.  The next plane is loaded into registers while the current one feeds
+// the matrix cores.  Tap order and accumulation are those of k_conv.
+constexpr int kTileX = 64, kTileY = 16;
+constexpr int kTiledThreads = 64 * kTileY;
+constexpr int kHaloX = kTileX + 2, kHaloY = kTileY + 2;
+constexpr int kPlaneUnits = kHaloY * kHaloX * 4;  // 16-byte units of a staged plane
+constexpr int kUnitsPerThread = (kPlaneUnits + kTiledThreads - 1) / kTiledThreads;
+
+template <int COUT, int EPI>
+__global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
+                                                              const __bf16* __restrict__ in,
+                                                              const __bf16* __restrict__ wpk,
+                                                              const float* __restrict__ bias,
+                                                              EpiArgs e) {
+  constexpr int NT = WShape<32, COUT>::NT;
+  constexpr int WE = WShape<32, COUT>::elems;
+  __shared__ __attribute__((aligned(16))) __bf16 sw[WE];
+  __shared__ __attribute__((aligned(16))) __bf16 sp[kHaloY][kHaloX][32];
+  for (int q = threadIdx.x; q < WE / 8; q += blockDim.x)
+    reinterpret_cast<uint4*>(sw)[q] = reinterpret_cast<const uint4*>(wpk)[q];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 15, grp = lane >> 4;
+  const int ntx = (g.nx + kTileX - 1) / kTileX, nty = (g.ny + kTileY - 1) / kTileY;
+  const int ntiles = ntx * nty * g.nz;
+  const int sgn = g.neg ? -1 : 1;
+  // Plane (tile, phase) -> registers: phase p stages plane z + sgn dil (p - 1).
+  // The loads are unconditional (clamped to valid addresses) and the zero
+  // padding outside the mesh is applied when the registers are written to
+  // LDS: conditional loads would make the compiler merge and copy the
+  // registers, which waits for the loads right away.
+  uint4 st[kUnitsPerThread];
+  bool live = false;  // the staged plane lies inside the mesh (uniform)
+  auto fetch = [&](int tile, int p) {
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    const int kk = tz + sgn * g.dil * (p - 1);
+    live = kk >= 0 && kk < g.nz;
+    const int kc = live ? kk : 0;
+#pragma unroll
+    for (int q = 0; q < kUnitsPerThread; ++q) {
+      int u = threadIdx.x + q * kTiledThreads;
+      u = u < kPlaneUnits ? u : kPlaneUnits - 1;
+      const int ry = u / (kHaloX * 4), rem = u % (kHaloX * 4);
+      const int px = rem / 4, part = rem % 4;
+      int ii = (tx * kTileX - 1 + px) % g.nx;
+      ii = ii < 0 ? ii + g.nx : ii;
+      int jj = (ty * kTileY - 1 + ry) % g.ny;
+      jj = jj < 0 ? jj + g.ny : jj;
+      const size_t c = ((size_t)kc * g.ny + jj) * g.nx + ii;
+      st[q] = *reinterpret_cast<const uint4*>(in + c * 32 + part * 8);
+    }
+  };
+  int tile = blockIdx.x;
+  if (tile < ntiles) fetch(tile, 0);
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    v4f acc[TM][NT];
+#pragma unroll
+    for (int m = 0; m < TM; ++m)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) acc[m][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int p = 0; p < 3; ++p) {
+      __syncthreads();  // every wave is done with the previous plane
+      const unsigned keep = live ? ~0u : 0u;  // a mask, not a select of arrays
+#pragma unroll
+      for (int q = 0; q < kUnitsPerThread; ++q) {
+        const int u = threadIdx.x + q * kTiledThreads;
+        if (u < kPlaneUnits)
+          reinterpret_cast<uint4*>(&sp[0][0][0])[u] =
+              make_uint4(st[q].x & keep, st[q].y & keep, st[q].z & keep, st[q].w & keep);
+      }
+      __syncthreads();
+      // the next plane (of this tile, else of the next tile; the last tile
+      // refetches its own first plane) is in flight during the MFMAs
+      int ft = tile, fp = p + 1;
+      if (p == 2) {
+        ft = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : tile;
+        fp = 0;
+      }
+      fetch(ft, fp);
+#pragma unroll 1
+      for (int t9 = 0; t9 < 9; ++t9) {
+        const int t = p * 9 + t9;
+        const int ly = wave + 1 + sgn * (t9 / 3 - 1);
+        const int lx = row + 1 + sgn * (t9 % 3 - 1);
+        v8bf a[TM];
+#pragma unroll
+        for (int m = 0; m < TM; ++m)
+          a[m] = *reinterpret_cast<const v8bf*>(&sp[ly][lx + 16 * m][grp * 8]);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
           const v8bf b = *reinterpret_cast<const v8bf*>(sw + ((t * NT + nt) * 16 + row) * 32 + grp * 8);
@@ -136,65 +317,59 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(ConvGeom g, const __bf16*
           for (int m = 0; m < TM; ++m)
             acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][nt], 0, 0, 0);
         }
-#pragma unroll
-        for (int m = 0; m < TM; ++m) a[m] = an[m];
-      }
-    } else {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int t0 = 8 * s + 2 * grp, t1 = t0 + 1;
-        v8bf a[TM];
-#pragma unroll
-        for (int m = 0; m < TM; ++m) {
-          v4bf lo = {}, hi = {};
-          if (valid[m] && t0 < 27) {
-            const int q = tap_cell(g, ci[m], cj[m], ck[m], t0);
-            if (q >= 0) lo = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
-          }
-          if (valid[m] && t1 < 27) {
-            const int q = tap_cell(g, ci[m], cj[m], ck[m], t1);
-            if (q >= 0) hi = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
-          }
-          a[m] = v8bf{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-        }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-          const v8bf b = *reinterpret_cast<const v8bf*>(sw + (nt * 16 + row) * 128 + 32 * s + grp * 8);
-#pragma unroll
-          for (int m = 0; m < TM; ++m)
-            acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][nt], 0, 0, 0);
-        }
       }
     }
-    // epilogue: acc[m][nt][r] = output (cell (tg*TM + m)*16 + 4*grp + r, channel nt*16 + row)
+    // acc[m][nt][r] = output (x = tile x0 + 16 m + 4 grp + r, y = y0 + wave, channel nt*16 + row)
+    const int cy = ty * kTileY + wave;
+    if (COUT == 32) {
+      // Through LDS, half a row (32 cells x 32 channels, FP32) per wave and
+      // pass, into the wave's own region of the plane buffer (cell stride 36
+      // floats: the 64 lanes of a write hit 64 different banks).  Then each
+      // lane takes 4 consecutive channels of a cell, so consecutive lanes
+      // cover consecutive 8-byte pieces of the channel-last outputs.
+      constexpr int kOS = 36;
+      static_assert(kTileY * 32 * kOS * 4 <= (int)sizeof(sp), "epilogue staging exceeds the plane buffer");
+      float* wreg = reinterpret_cast<float*>(&sp[0][0][0]) + wave * 32 * kOS;
 #pragma unroll
-    for (int m = 0; m < TM; ++m)
+      for (int ps = 0; ps < 2; ++ps) {
+        __syncthreads();  // the plane (or the previous pass) is no longer read
 #pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const int n = nt * 16 + row;
-        if (n >= COUT) continue;
+        for (int mm = 0; mm < 2; ++mm)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int co = (tg * TM + m) * 16 + 4 * grp + r;
-          if (co >= g.ncell) continue;
-          const size_t o = (size_t)co * COUT + n;
-          float v = acc[m][nt][r];
-          if (EPI == EPI_FIRST || EPI == EPI_RES) {
-            const float zb = bf(v + bias[n]);
-            if (e.zout) e.zout[o] = (__bf16)zb;
-            float h = leaky(zb, e.alpha);
-            if (EPI == EPI_RES) h += (float)e.hin[o];
-            e.hout[o] = (__bf16)h;
-          } else if (EPI == EPI_LAST) {
-            e.yout[o] = e.xres[o] + v + bias[n];
-          } else {  // EPI_BWD: dh = acc (+ dh of the layer above); dz = dh * phi'(z)
-            float gsum = v + (e.hin ? (float)e.hin[o] : 0.0f);
-            const float gb = bf(gsum);
-            if (e.hout) e.hout[o] = (__bf16)gb;
-            if (e.zout) e.zout[o] = (__bf16)(gb * dleaky((float)e.zin[o], e.alpha));
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              wreg[(16 * mm + 4 * grp + r) * kOS + nt * 16 + row] = acc[2 * ps + mm][nt][r];
+        __syncthreads();
+        if (cy < g.ny) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int id = lane + 64 * j;
+            const int cl = id >> 3, n0 = 4 * (id & 7);
+            const int cx = tx * kTileX + 32 * ps + cl;
+            if (cx >= g.nx) continue;
+            const float4 v4 = *reinterpret_cast<const float4*>(wreg + cl * kOS + n0);
+            const size_t co = ((size_t)tz * g.ny + cy) * g.nx + cx;
+            epilogue4<EPI>(e, bias, co * 32 + n0, n0, v4);
           }
         }
       }
+    } else if (cy < g.ny) {
+#pragma unroll
+      for (int m = 0; m < TM; ++m)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const int n = nt * 16 + row;
+          if (n >= COUT) continue;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int cx = tx * kTileX + 16 * m + 4 * grp + r;
+            if (cx >= g.nx) continue;
+            const size_t co = ((size_t)tz * g.ny + cy) * g.nx + cx;
+            epilogue<EPI>(e, bias, co * COUT + n, n, acc[m][nt][r]);
+          }
+        }
+    }
   }
 }
 
@@ -335,14 +510,31 @@ __global__ __launch_bounds__(256) void k_conv_dw(ConvGeom g, const __bf16* __res
   }
 }
 
-// out[k] = sum over blocks of part[b][k], in block order.
-__global__ void k_reduce_parts(const float* __restrict__ part, int nblocks, int len,
-                               float* __restrict__ out) {
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= len) return;
-  float s = 0.0f;
-  for (int b = 0; b < nblocks; ++b) s += part[(size_t)b * len + k];
-  out[k] = s;
+// out[k] = sum over blocks of part[b][k] in a fixed order: the blocks in four
+// contiguous segments (one wave each, 64 outputs per workgroup), each summed
+// with four interleaved accumulators so that four loads are in flight, then
+// the partial sums added pairwise.
+__global__ __launch_bounds__(256) void k_reduce_parts(const float* __restrict__ part,
+                                                      int nblocks, int len,
+                                                      float* __restrict__ out) {
+  __shared__ float seg[4][64];
+  const int kk = threadIdx.x & 63, sgi = threadIdx.x >> 6;
+  const int k = blockIdx.x * 64 + kk;
+  float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, a3 = 0.0f;
+  if (k < len) {
+    const int b1 = (int)((int64_t)(sgi + 1) * nblocks / 4);
+    int b = (int)((int64_t)sgi * nblocks / 4);
+    for (; b + 3 < b1; b += 4) {
+      a0 += part[(size_t)b * len + k];
+      a1 += part[(size_t)(b + 1) * len + k];
+      a2 += part[(size_t)(b + 2) * len + k];
+      a3 += part[(size_t)(b + 3) * len + k];
+    }
+    for (; b < b1; ++b) a0 += part[(size_t)b * len + k];
+  }
+  seg[sgi][kk] = (a0 + a1) + (a2 + a3);
+  __syncthreads();
+  if (sgi == 0 && k < len) out[k] = (seg[0][kk] + seg[1][kk]) + (seg[2][kk] + seg[3][kk]);
 }
 
 // Normalised input: xf [c][4] = (raw[ch][c] - mean) / std, and its BF16 copy.
@@ -444,6 +636,24 @@ size_t nn_packed_elems(int cin, int cout) {
 
 void launch_conv(int cin, int cout, int epi, const ConvGeom& g, const __bf16* in,
                  const __bf16* wpk, const float* bias, const EpiArgs& e, hipStream_t s) {
+  if (cin == 32) {
+    const int64_t ntiles = (int64_t)((g.nx + kTileX - 1) / kTileX) *
+                           ((g.ny + kTileY - 1) / kTileY) * g.nz;
+    if (ntiles == 0) return;
+    // one block of 16 waves per CU, persistent over the tiles
+    const unsigned grid = (unsigned)(ntiles < 256 ? ntiles : 256);
+#define SEDIMI_CONV_T(CO, EP)                                                           \
+    if (cout == CO && epi == EP) {                                                      \
+      hipLaunchKernelGGL((k_conv_tiled<CO, EP>), dim3(grid), dim3(kTiledThreads), 0, s, g, in, \
+                         wpk, bias, e);                                                 \
+      return;                                                                           \
+    }
+    SEDIMI_CONV_T(32, EPI_RES)
+    SEDIMI_CONV_T(4, EPI_LAST)
+    SEDIMI_CONV_T(32, EPI_BWD)
+#undef SEDIMI_CONV_T
+    return;
+  }
   int ngroups = (g.ncell + 16 * TM - 1) / (16 * TM);
   const int wpb = kConvThreads / 64;
   unsigned grid = (unsigned)((ngroups + wpb - 1) / wpb);
@@ -455,10 +665,7 @@ void launch_conv(int cin, int cout, int epi, const ConvGeom& g, const __bf16* in
     return;                                                                               \
   }
   SEDIMI_CONV(4, 32, EPI_FIRST)
-  SEDIMI_CONV(32, 32, EPI_RES)
-  SEDIMI_CONV(32, 4, EPI_LAST)
   SEDIMI_CONV(4, 32, EPI_BWD)
-  SEDIMI_CONV(32, 32, EPI_BWD)
 #undef SEDIMI_CONV
 }
 
@@ -474,8 +681,9 @@ int launch_conv_dw(int cin, int cout, const ConvGeom& g, const __bf16* x, const 
   else
     return -1;
   int len = 27 * cin * cout;
-  hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(len)), dim3(256), 0, s, part, nblocks, len, dw);
-  hipLaunchKernelGGL(k_reduce_parts, dim3(1), dim3(256), 0, s, part_b, nblocks, cout, db);
+  hipLaunchKernelGGL(k_reduce_parts, dim3((len + 63) / 64), dim3(256), 0, s, part, nblocks, len, dw);
+  hipLaunchKernelGGL(k_reduce_parts, dim3((cout + 63) / 64), dim3(256), 0, s, part_b, nblocks, cout,
+                     db);
   return 0;
 }
 

@@ -43,7 +43,9 @@ def setup(orc, shape, seed, scale=0.08):
     return g, params.astype(np.float64), raw, mean, std, xh
 
 
-@pytest.mark.parametrize("shape", [(16, 8, 12), (10, 7, 9)])
+# (70, 20, 5): two ragged tiles of 64 x 16 cells in x and y, and z-taps of
+# dilation 4 that mostly fall outside the mesh
+@pytest.mark.parametrize("shape", [(16, 8, 12), (10, 7, 9), (70, 20, 5)])
 def test_forward_matches_oracle(orc, shape):
     g, params, raw, mean, std, xh = setup(orc, shape, 1)
     g.nn_forward()
@@ -155,9 +157,10 @@ def test_residual_check_and_fallback():
     assert g2.stats()["nn_calls"] == 3
 
 
-def test_gradients_ragged_mesh(orc):
-    """x-rows shorter than and not a multiple of the 32-cell weight-gradient chunk."""
-    shape = (10, 7, 9)
+@pytest.mark.parametrize("shape", [(10, 7, 9), (70, 20, 5)])
+def test_gradients_ragged_mesh(orc, shape):
+    """x-rows shorter than, or not a multiple of, the 32-cell weight-gradient
+    chunk; several ragged 64 x 16 convolution tiles."""
     g, params, raw, mean, std, xh = setup(orc, shape, 8)
     target = raw * 0.8 + 0.05
     g.set_field(1, target)
