@@ -376,14 +376,17 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
 // Weight and bias gradients of one convolution: dW[t][i][o] = sum_cells
 // x[nb(c,t)][i] dy[c][o], as per-block partials.  K of the GEMM runs over
 // cells, so both MFMA operands need 8 consecutive cells of one channel per
-// lane while the activations are channel-last.  The chunk (32 consecutive
-// cells of one x-row) and the 9 input row segments it touches (34 cells
-// each, shared by the three x-taps) are copied into LDS unchanged, and the
-// operands are read with the LDS transpose read (ds_read_b64_tr_b16): within
-// each 16-lane group, lane 4b+a receives element a of the 4-element rows
-// addressed by lanes b, b+4, b+8, b+12.  If lane r addresses cell
-// base + r/4, channels 4(r%4) .. 4(r%4)+3, lane t receives cells base..base+3
-// of channel t.  Wave w owns taps w, w+4, ...
+// lane while the activations are channel-last.  A chunk is 32 consecutive
+// cells of kDwRows consecutive x-rows of one z-plane; its dy and the input
+// row segments it touches (3 z-planes x (kDwRows + 2) rows, 34 cells each,
+// shared by the x-taps and by neighbouring rows) are copied into LDS
+// unchanged, and the operands are read with the LDS transpose read
+// (ds_read_b64_tr_b16): within each 16-lane group, lane 4b+a receives element
+// a of the 4-element rows addressed by lanes b, b+4, b+8, b+12.  If lane r
+// addresses cell base + r/4, channels 4(r%4) .. 4(r%4)+3, lane t receives
+// cells base..base+3 of channel t.  Wave w owns taps w, w+8, ...; each row of
+// the chunk is one K step.  The next chunk is loaded into registers while the
+// current one feeds the matrix cores.
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) v4s lds_v4s;
 
@@ -396,24 +399,35 @@ __device__ __forceinline__ v8bf tr_pair(const __bf16* p0, const __bf16* p1) {
   return r;
 }
 
+constexpr int kDwThreads = 512;
+constexpr int kDwRows = 4;
+
 template <int CIN, int COUT>
-__global__ __launch_bounds__(256) void k_conv_dw(ConvGeom g, const __bf16* __restrict__ x,
-                                                 const __bf16* __restrict__ dy,
-                                                 float* __restrict__ part,
-                                                 float* __restrict__ part_b) {
+__global__ __launch_bounds__(kDwThreads) void k_conv_dw(ConvGeom g, const __bf16* __restrict__ x,
+                                                        const __bf16* __restrict__ dy,
+                                                        float* __restrict__ part,
+                                                        float* __restrict__ part_b) {
   constexpr int CP = CIN < 16 ? 16 : CIN;    // padded input channels (M)
   constexpr int OP = COUT < 16 ? 16 : COUT;  // padded output channels (N)
   constexpr int MT = CP / 16, NT = OP / 16;
-  constexpr int SLOTS = 7;  // taps per wave: ceil(27 / 4)
-  constexpr int SEG = 34;   // row segment: cells x0-1 .. x0+32
-  __shared__ __attribute__((aligned(16))) __bf16 xs[9][SEG][CP];
-  __shared__ __attribute__((aligned(16))) __bf16 dys[32][OP];
-  __shared__ float bsum[256][8];
+  constexpr int NW = kDwThreads / 64;
+  constexpr int SLOTS = (27 + NW - 1) / NW;  // taps per wave
+  constexpr int SEG = 34;                    // row segment: cells x0-1 .. x0+32
+  constexpr int XR = kDwRows + 2;            // staged rows per z-plane
+  constexpr int XU = CIN / 4;                // 8-byte units per cell of x
+  constexpr int YU = COUT / 4;               // 8-byte units per cell of dy
+  constexpr int XUNITS = 3 * XR * SEG * XU, YUNITS = kDwRows * 32 * YU;
+  constexpr int XPT = (XUNITS + kDwThreads - 1) / kDwThreads;
+  constexpr int YPT = (YUNITS + kDwThreads - 1) / kDwThreads;
+  static_assert(kDwThreads % YU == 0, "each thread must keep one dy channel block");
+  __shared__ __attribute__((aligned(16))) __bf16 xs[3][XR][SEG][CP];
+  __shared__ __attribute__((aligned(16))) __bf16 dys[kDwRows][32][OP];
+  __shared__ float bsum[kDwThreads][4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int t16 = lane & 15, grp = lane >> 4;
   // zero the padding channels once (never overwritten)
-  for (int q = threadIdx.x; q < 9 * SEG * CP; q += 256) (&xs[0][0][0])[q] = (__bf16)0.0f;
-  for (int q = threadIdx.x; q < 32 * OP; q += 256) (&dys[0][0])[q] = (__bf16)0.0f;
+  for (int q = threadIdx.x; q < 3 * XR * SEG * CP; q += kDwThreads) (&xs[0][0][0][0])[q] = (__bf16)0.0f;
+  for (int q = threadIdx.x; q < kDwRows * 32 * OP; q += kDwThreads) (&dys[0][0][0])[q] = (__bf16)0.0f;
   v4f acc[SLOTS][MT][NT];
 #pragma unroll
   for (int s = 0; s < SLOTS; ++s)
@@ -421,62 +435,97 @@ __global__ __launch_bounds__(256) void k_conv_dw(ConvGeom g, const __bf16* __res
     for (int a = 0; a < MT; ++a)
 #pragma unroll
       for (int b = 0; b < NT; ++b) acc[s][a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  float bacc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  const int nseg = (g.nx + 31) / 32;
-  const int nchunks = g.ny * g.nz * nseg;
-  constexpr int XU = CIN / 4;   // 8-byte units per cell of x
-  constexpr int YU = COUT / 4;  // 8-byte units per cell of dy
-  __syncthreads();
-  for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-    const int seg = ch % nseg, row = ch / nseg;
-    const int cj = row % g.ny, ck = row / g.ny;
-    const int x0 = seg * 32;
-    const int len = min(32, g.nx - x0);
-    // dy chunk (cells beyond the row end are zero) + bias partial sums
-    for (int u = threadIdx.x; u < 32 * YU; u += 256) {
-      const int cl = u / YU, blk = u % YU;
-      uint2 v = make_uint2(0u, 0u);
-      if (cl < len) {
-        const size_t c = ((size_t)ck * g.ny + cj) * g.nx + x0 + cl;
-        v = *reinterpret_cast<const uint2*>(dy + c * COUT + blk * 4);
-        const __bf16* e = reinterpret_cast<const __bf16*>(&v);
-        for (int q = 0; q < 4; ++q) bacc[q] += (float)e[q];
-      }
-      *reinterpret_cast<uint2*>(&dys[cl][blk * 4]) = v;
+  float bacc[4] = {0, 0, 0, 0};
+  const int nseg = (g.nx + 31) / 32, nrow = (g.ny + kDwRows - 1) / kDwRows;
+  const int nchunks = nseg * nrow * g.nz;
+  // Chunk -> registers.  Loads are unconditional (clamped to valid cells) and
+  // the zeros outside the mesh are applied when the registers are written
+  // to LDS, from the bit masks: conditional loads would make the compiler
+  // copy the registers and wait for the loads at once.
+  uint2 rx[XPT], ry[YPT];
+  unsigned mx = 0, my = 0;  // bit q: unit q holds data
+  auto fetch = [&](int ch) {
+    const int seg = ch % nseg, rb = (ch / nseg) % nrow, ck = ch / (nseg * nrow);
+    const int x0 = seg * 32, y0 = rb * kDwRows;
+    mx = 0;
+    my = 0;
+#pragma unroll
+    for (int q = 0; q < YPT; ++q) {
+      const int u = threadIdx.x + q * kDwThreads;
+      const int rr = u / (32 * YU), rem = u % (32 * YU);
+      const int cl = rem / YU, blk = rem % YU;
+      const int yy = y0 + rr, xx = x0 + cl;
+      const bool ok = u < YUNITS && yy < g.ny && xx < g.nx;
+      const size_t c = ok ? ((size_t)ck * g.ny + yy) * g.nx + xx : 0;
+      ry[q] = *reinterpret_cast<const uint2*>(dy + c * COUT + blk * 4);
+      my |= (ok ? 1u : 0u) << q;
     }
-    // 9 input row segments (dz, dy), periodic in x and y, zero outside z
-    for (int u = threadIdx.x; u < 9 * SEG * XU; u += 256) {
-      const int r = u / (SEG * XU), rem = u % (SEG * XU);
-      const int p = rem / XU, blk = rem % XU;
-      const int dz = r / 3 - 1, dyy = r % 3 - 1;
-      const int kk = ck + g.dil * dz;
-      uint2 v = make_uint2(0u, 0u);
-      if (kk >= 0 && kk < g.nz) {
-        int jj = cj + dyy;
-        jj = jj < 0 ? jj + g.ny : (jj >= g.ny ? jj - g.ny : jj);
-        int ii = x0 - 1 + p;
-        ii = ii < 0 ? ii + g.nx : (ii >= g.nx ? ii - g.nx : ii);
-        const size_t c = ((size_t)kk * g.ny + jj) * g.nx + ii;
-        v = *reinterpret_cast<const uint2*>(x + c * CIN + blk * 4);
-      }
-      *reinterpret_cast<uint2*>(&xs[r][p][blk * 4]) = v;
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int u = threadIdx.x + q * kDwThreads;
+      const int pz = u / (XR * SEG * XU), rem = u % (XR * SEG * XU);
+      const int pr = rem / (SEG * XU), rem2 = rem % (SEG * XU);
+      const int pc = rem2 / XU, blk = rem2 % XU;
+      const int kk = ck + g.dil * (pz - 1);
+      const bool ok = u < XUNITS && kk >= 0 && kk < g.nz;
+      int jj = (y0 - 1 + pr) % g.ny;
+      jj = jj < 0 ? jj + g.ny : jj;
+      int ii = (x0 - 1 + pc) % g.nx;
+      ii = ii < 0 ? ii + g.nx : ii;
+      const size_t c = ok ? ((size_t)kk * g.ny + jj) * g.nx + ii : 0;
+      rx[q] = *reinterpret_cast<const uint2*>(x + c * CIN + blk * 4);
+      mx |= (ok ? 1u : 0u) << q;
+    }
+  };
+  int ch = blockIdx.x;
+  if (ch < nchunks) fetch(ch);
+  __syncthreads();
+  for (; ch < nchunks; ch += gridDim.x) {
+#pragma unroll
+    for (int q = 0; q < YPT; ++q) {
+      const int u = threadIdx.x + q * kDwThreads;
+      if (u >= YUNITS) continue;
+      const unsigned keep = ((my >> q) & 1u) ? ~0u : 0u;
+      const uint2 v = make_uint2(ry[q].x & keep, ry[q].y & keep);
+      const int rr = u / (32 * YU), rem = u % (32 * YU);
+      const int cl = rem / YU, blk = rem % YU;
+      *reinterpret_cast<uint2*>(&dys[rr][cl][blk * 4]) = v;
+      const __bf16* e = reinterpret_cast<const __bf16*>(&v);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) bacc[k] += (float)e[k];
+    }
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int u = threadIdx.x + q * kDwThreads;
+      if (u >= XUNITS) continue;
+      const unsigned keep = ((mx >> q) & 1u) ? ~0u : 0u;
+      const int pz = u / (XR * SEG * XU), rem = u % (XR * SEG * XU);
+      const int pr = rem / (SEG * XU), rem2 = rem % (SEG * XU);
+      const int pc = rem2 / XU, blk = rem2 % XU;
+      *reinterpret_cast<uint2*>(&xs[pz][pr][pc][blk * 4]) =
+          make_uint2(rx[q].x & keep, rx[q].y & keep);
     }
     __syncthreads();
+    // the next chunk (the last one refetches itself) is in flight meanwhile
+    fetch(ch + (int)gridDim.x < nchunks ? ch + (int)gridDim.x : ch);
 #pragma unroll
     for (int slot = 0; slot < SLOTS; ++slot) {
-      const int t = wave + 4 * slot;
+      const int t = wave + NW * slot;
       if (t < 27) {
-        const int r = t / 3, dxi = t % 3;  // row (dz, dy) and x shift + 1
+        const int pz = t / 9, dyi = (t / 3) % 3, dxi = t % 3;  // z-plane, row and x shift + 1
+#pragma unroll 1
+        for (int rr = 0; rr < kDwRows; ++rr) {
 #pragma unroll
-        for (int a = 0; a < MT; ++a) {
-          const __bf16* pa = &xs[r][8 * grp + (t16 >> 2) + dxi][16 * a + 4 * (t16 & 3)];
-          const v8bf A = tr_pair(pa, pa + 4 * CP);
+          for (int a = 0; a < MT; ++a) {
+            const __bf16* pa = &xs[pz][rr + dyi][8 * grp + (t16 >> 2) + dxi][16 * a + 4 * (t16 & 3)];
+            const v8bf A = tr_pair(pa, pa + 4 * CP);
 #pragma unroll
-          for (int b = 0; b < NT; ++b) {
-            const __bf16* pb = &dys[8 * grp + (t16 >> 2)][16 * b + 4 * (t16 & 3)];
-            const v8bf B = tr_pair(pb, pb + 4 * OP);
-            acc[slot][a][b] =
-                __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[slot][a][b], 0, 0, 0);
+            for (int b = 0; b < NT; ++b) {
+              const __bf16* pb = &dys[rr][8 * grp + (t16 >> 2)][16 * b + 4 * (t16 & 3)];
+              const v8bf B = tr_pair(pb, pb + 4 * OP);
+              acc[slot][a][b] =
+                  __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[slot][a][b], 0, 0, 0);
+            }
           }
         }
       }
@@ -487,7 +536,7 @@ __global__ __launch_bounds__(256) void k_conv_dw(ConvGeom g, const __bf16* __res
   float* pb = part + (size_t)blockIdx.x * 27 * CIN * COUT;
 #pragma unroll
   for (int slot = 0; slot < SLOTS; ++slot) {
-    const int t = wave + 4 * slot;
+    const int t = wave + NW * slot;
     if (t >= 27) continue;
 #pragma unroll
     for (int a = 0; a < MT; ++a)
@@ -499,13 +548,13 @@ __global__ __launch_bounds__(256) void k_conv_dw(ConvGeom g, const __bf16* __res
           if (m < CIN && n < COUT) pb[((size_t)t * CIN + m) * COUT + n] = acc[slot][a][b][q];
         }
   }
-  // bias: thread u (< 32 * YU) always loaded channel block u % YU
+  // bias: thread u always loaded dy channel block u % YU (kDwThreads % YU == 0)
   for (int q = 0; q < 4; ++q) bsum[threadIdx.x][q] = bacc[q];
   __syncthreads();
   if ((int)threadIdx.x < COUT) {
     const int blk = threadIdx.x / 4, q = threadIdx.x % 4;
     float s2 = 0.0f;
-    for (int u = blk; u < 256 && u < 32 * YU; u += YU) s2 += bsum[u][q];
+    for (int u = blk; u < kDwThreads; u += YU) s2 += bsum[u][q];
     part_b[(size_t)blockIdx.x * COUT + threadIdx.x] = s2;
   }
 }
@@ -673,11 +722,11 @@ int launch_conv_dw(int cin, int cout, const ConvGeom& g, const __bf16* x, const 
                    float* part, float* part_b, float* dw, float* db, int nblocks,
                    hipStream_t s) {
   if (cin == 32 && cout == 32)
-    hipLaunchKernelGGL((k_conv_dw<32, 32>), dim3(nblocks), dim3(256), 0, s, g, x, dy, part, part_b);
+    hipLaunchKernelGGL((k_conv_dw<32, 32>), dim3(nblocks), dim3(kDwThreads), 0, s, g, x, dy, part, part_b);
   else if (cin == 4 && cout == 32)
-    hipLaunchKernelGGL((k_conv_dw<4, 32>), dim3(nblocks), dim3(256), 0, s, g, x, dy, part, part_b);
+    hipLaunchKernelGGL((k_conv_dw<4, 32>), dim3(nblocks), dim3(kDwThreads), 0, s, g, x, dy, part, part_b);
   else if (cin == 32 && cout == 4)
-    hipLaunchKernelGGL((k_conv_dw<32, 4>), dim3(nblocks), dim3(256), 0, s, g, x, dy, part, part_b);
+    hipLaunchKernelGGL((k_conv_dw<32, 4>), dim3(nblocks), dim3(kDwThreads), 0, s, g, x, dy, part, part_b);
   else
     return -1;
   int len = 27 * cin * cout;
