@@ -300,12 +300,13 @@ struct Staged {
   double4 omg[kStage];  // .w = particle ID
 };
 
-#ifndef SEDIMI_FORCE_WAVES
-#define SEDIMI_FORCE_WAVES 1
-#endif
-
+// Occupancy: the kernel is bound by the memory latency each SIMD can hide,
+// so waves count.  With FP32 pair arithmetic the step kernel fits 5 waves per
+// SIMD (95 VGPRs, a 20 B/lane spill outside the pair loop; 3% faster than 4
+// waves on the 10M-sphere bed); the FP64 kernels keep the compiler's choice
+// (4 waves: forcing 5 spills inside the loop).
 template <typename R, int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(SEDIMI_FORCE_WAVES)))
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1)))
 void k_forces(DevParams P, DevArrays A, int update_history) {
   __shared__ Staged S;
   const int base = xcd_block(blockIdx.x, gridDim.x) * kBlock;
