@@ -69,14 +69,16 @@ __device__ __forceinline__ void epilogue(const EpiArgs& e, const float* __restri
 }
 
 // The same for channels n0 .. n0+3 of one cell (o = cell * 32 + n0): 8-byte
-// loads and stores, the same roundings as epilogue().
+// loads and stores, the same roundings as epilogue().  hres, when given, is
+// the residual input of these channels (EPI_RES), already loaded.
 template <int EPI>
 __device__ __forceinline__ void epilogue4(const EpiArgs& e, const float* __restrict__ bias,
-                                          size_t o, int n0, const float4& v4) {
+                                          size_t o, int n0, const float4& v4,
+                                          const v4bf* hres = nullptr) {
   const float v[4] = {v4.x, v4.y, v4.z, v4.w};
   if (EPI == EPI_FIRST || EPI == EPI_RES) {
     v4bf hin4 = {};
-    if (EPI == EPI_RES) hin4 = *reinterpret_cast<const v4bf*>(e.hin + o);
+    if (EPI == EPI_RES) hin4 = hres ? *hres : *reinterpret_cast<const v4bf*>(e.hin + o);
     v4bf zb4, h4;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -281,8 +283,14 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
     for (int m = 0; m < TM; ++m)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[m][nt] = v4f{0.f, 0.f, 0.f, 0.f};
+    // Residual layers take the centre plane last: it then stays in LDS for
+    // the epilogue, which reads the residual input h_in (the layer's own
+    // input) from there instead of from memory.  Planes: p -> z + sgn dil (p - 1).
+    constexpr bool kCentreLast = EPI == EPI_RES;
+    auto phase = [](int i) { return kCentreLast ? (i == 0 ? 0 : (i == 1 ? 2 : 1)) : i; };
 #pragma unroll 1
-    for (int p = 0; p < 3; ++p) {
+    for (int pi = 0; pi < 3; ++pi) {
+      const int p = phase(pi);
       __syncthreads();  // every wave is done with the previous plane
       const unsigned keep = live ? ~0u : 0u;  // a mask, not a select of arrays
 #pragma unroll
@@ -295,11 +303,8 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
       __syncthreads();
       // the next plane (of this tile, else of the next tile; the last tile
       // refetches its own first plane) is in flight during the MFMAs
-      int ft = tile, fp = p + 1;
-      if (p == 2) {
-        ft = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : tile;
-        fp = 0;
-      }
+      int ft = tile, fp = phase(pi + 1 < 3 ? pi + 1 : 0);
+      if (pi == 2) ft = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : tile;
       fetch(ft, fp);
 #pragma unroll 1
       for (int t9 = 0; t9 < 9; ++t9) {
@@ -329,6 +334,18 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
       // cover consecutive 8-byte pieces of the channel-last outputs.
       constexpr int kOS = 36;
       static_assert(kTileY * 32 * kOS * 4 <= (int)sizeof(sp), "epilogue staging exceeds the plane buffer");
+      // h_in of this lane's output pieces, from the centre plane still in LDS
+      v4bf hres[2][4];
+      if (kCentreLast) {
+#pragma unroll
+        for (int ps = 0; ps < 2; ++ps)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int id = lane + 64 * j;
+            const int cl = id >> 3, n0 = 4 * (id & 7);
+            hres[ps][j] = *reinterpret_cast<const v4bf*>(&sp[wave + 1][32 * ps + cl + 1][n0]);
+          }
+      }
       float* wreg = reinterpret_cast<float*>(&sp[0][0][0]) + wave * 32 * kOS;
 #pragma unroll
       for (int ps = 0; ps < 2; ++ps) {
@@ -350,7 +367,7 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
             if (cx >= g.nx) continue;
             const float4 v4 = *reinterpret_cast<const float4*>(wreg + cl * kOS + n0);
             const size_t co = ((size_t)tz * g.ny + cy) * g.nx + cx;
-            epilogue4<EPI>(e, bias, co * 32 + n0, n0, v4);
+            epilogue4<EPI>(e, bias, co * 32 + n0, n0, v4, kCentreLast ? &hres[ps][j] : nullptr);
           }
         }
       }
