@@ -25,6 +25,30 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-updates/s at 1M/10M particles; averaging ms plain vs surrogate"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6
+
+
+def averaging_rooflines(n, ncell, dep_ms, smooth_ms, direct, mesh):
+    """Deposition against HBM: algorithmic bytes 88 B per particle (cell key
+    32 B read + 8 B written, 8 B scatter, 40 B read by the per-cell sums)
+    plus 32 B per cell written.  Direct solve against the FP64 matrix cores:
+    four channels, a forward and an inverse transform along each axis, so
+    4 (nx + ny + nz) FLOP per cell and channel; its algorithmic HBM minimum
+    (read raw + write smooth, 16 B per cell and channel) is given beside it.
+    The solve time includes its full-field residual check."""
+    dep_bytes = 88 * n + 32 * ncell
+    dep = {"ms": round(dep_ms, 5), "bytes": int(dep_bytes), "bound": "hbm",
+           "achieved_GBps": round(dep_bytes / (dep_ms * 1e-3) / 1e9, 1),
+           "frac": round(dep_bytes / (dep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    min_bytes = 16 * ncell * 4
+    sol = {"ms": round(smooth_ms, 5), "hbm_minimum_ms": round(min_bytes / HBM_PEAK_GBS / 1e6, 5)}
+    if direct:
+        flop = 4 * (mesh[0] + mesh[1] + mesh[2]) * ncell * 4
+        tf = flop / (smooth_ms * 1e-3) / 1e12
+        sol.update({"bound": "mfma_fp64", "gflop": round(flop / 1e9, 3),
+                    "achieved_tflops": round(tf, 2), "peak_tflops": FP64_MFMA_PEAK_TFLOPS,
+                    "frac": round(tf / FP64_MFMA_PEAK_TFLOPS, 4)})
+    return dep, sol
 
 
 # HBM traffic of the step-mode force kernel on the 1M-sphere bed (FP64), from
@@ -157,6 +181,10 @@ def main():
     phases = {k: {"ms_per_launch": round(v[0] / max(v[1], 1), 5), "launches": v[1]}
               for k, v in prof.items()}
     avg_ms = (prof["deposit"][0] + prof["smooth"][0]) / max(prof["smooth"][1], 1)
+    dep_r, sol_r = averaging_rooflines(
+        n, ncell, prof["deposit"][0] / max(prof["deposit"][1], 1),
+        prof["smooth"][0] / max(prof["smooth"][1], 1), st["solve_iters"] == 0,
+        w["meta"]["mesh"])
     # the particle step alone (drift, gated rebuild chain, forces), per step
     dem_ms = (prof["drift"][0] + prof["rebuild"][0] + prof["forces"][0]) / max(prof["forces"][1], 1)
 
@@ -197,7 +225,8 @@ def main():
         "cpu_baseline": cpu,
         "averaging": {"plain_ms": round(avg_ms, 4),
                       "solver": "direct" if st["solve_iters"] == 0 else "iterative",
-                      "solve_iters": st["solve_iters"], "residual": st["solve_residual"]},
+                      "solve_iters": st["solve_iters"], "residual": st["solve_residual"],
+                      "deposit": dep_r, "solve": sol_r},
         "phases": phases,
         "particle_step_only": {"ms_per_step": round(dem_ms, 5),
                                "particle_updates_per_s": round(n / (dem_ms * 1e-3), 1)},
