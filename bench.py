@@ -58,16 +58,22 @@ def averaging_rooflines(n, ncell, dep_ms, smooth_ms, direct, mesh):
 # copy's FETCH_SIZE reads 0.5x the bytes read, WRITE_SIZE 1.0x the bytes
 # written).  Valid only for the kernel sources it was measured on.
 FORCE_PMC = {"fetch_kib": 315436.3, "write_kib": 280999.8, "fetch_scale": 2.0, "write_scale": 1.0,
-             "sources_sha256": "5172d6a0379d0563e191366dba634c356c4c484c548ee343e3df8d61ec776012",
+             "sources_sha256": "31f6d7805e0f5d04c8732f2ae2065cd3db42cb85b125dba1a872ece07c8d7fe7",
              "profile": "profiles/k_forces_bed1m_fp64.md"}
 FORCE_SOURCES = ("k_forces.hip", "k_common.h", "sedimi_internal.h")
 
 
 def force_sources_sha():
+    """Hash of the force kernel's sources with comments and blank lines
+    removed: the stored HBM counters stay valid across comment edits and
+    lapse with any change to the code."""
     h = hashlib.sha256()
     for f in FORCE_SOURCES:
-        with open(os.path.join(ROOT, "paper_1601_03801_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1601_03801_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 

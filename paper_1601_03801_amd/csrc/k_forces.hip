@@ -7,7 +7,8 @@
 // histories: the pair forces are exactly antisymmetric and no atomics are
 // needed.  Per pair (Sections 2.1, 2.5):
 //   - pair set: s = |dx|^2 < ((r_i + r_j)(1 + f_out))^2, exact FP64 test;
-//   - lubrication (Ball & Melrose squeeze term) for every pair in the set:
+//   - lubrication (the force of the fluid squeezed out of the gap) for every
+//     pair in the set:
 //     F = -6 pi mu a_eff^2 u_n / max(h, h_in) n;
 //   - contact when the overlap delta > 0: linear spring-dashpot normal force
 //     -(k_n delta + gamma_n u_n) n, tangential history spring with Coulomb

@@ -5,18 +5,21 @@
 //
 // Convolution as an implicit GEMM on v_mfma_f32_16x16x32_bf16: each MFMA
 // computes 16 consecutive cells (M) by 16 output channels (N); K runs over
-// (tap, input channel); a wave works on 4 such cell tiles at once.  Activations are stored
-// channel-last, so the A fragment of a tap (8 consecutive input channels of
-// one neighbour cell per lane) is a single 16-byte load; the layer's weights
-// sit in LDS in the order the B fragments are read.  With 32 input channels
-// one tap is exactly one K step; with 4 input channels two taps share a lane
-// group and K is padded from 108 to 128.
+// (tap, input channel); a wave works on 4 such cell tiles at once.
+// Activations are stored channel-last, so the A fragment of a tap (8
+// consecutive input channels of one neighbour cell per lane) is 16 contiguous
+// bytes; the layer's weights sit in LDS in the order the B fragments are read.
+//   - 32 input channels (k_conv_tiled): one tap is one K step; the input is
+//     staged through LDS one z-plane of a 64 x 16-cell tile at a time.
+//   - 4 input channels (k_conv): two taps share a lane group, K is padded
+//     from 108 to 128, and the fragments are gathered directly.
+// Both write their outputs through LDS so that the epilogue's loads and
+// stores are 8-byte pieces of consecutive channels.
 //
 // The data gradient of a convolution is the same kernel run with the tap
 // offsets negated and the weights transposed; the weight gradient is a GEMM
 // over cells (K = cells) whose operands come from LDS through transpose
 // reads, with per-block partial sums reduced in a fixed order.
-#include <limits.h>
 #include <math.h>
 
 #include "k_nn.h"
