@@ -20,7 +20,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liborc.so")
 _SOURCES = ["orc_pairs.c", "orc_forces.c", "orc_average.c", "orc_cnn.c"]
 
-DRAG = {"none": 0, "difelice": 1, "stokes": 2}
+DRAG = {"none": 0, "difelice": 1, "stokes": 2, "syamlal": 3}
 WALL_BOTTOM = -1
 WALL_TOP = -2
 

@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-enum { ORC_DRAG_NONE = 0, ORC_DRAG_DIFELICE = 1, ORC_DRAG_STOKES = 2 };
+enum { ORC_DRAG_NONE = 0, ORC_DRAG_DIFELICE = 1, ORC_DRAG_STOKES = 2, ORC_DRAG_SYAMLAL = 3 };
 enum { ORC_WALL_BOTTOM = -1, ORC_WALL_TOP = -2 };
 
 typedef struct {

@@ -303,3 +303,51 @@ def test_pair_forces_are_antisymmetric(orc):
     scale = np.abs(comps["contact"]).sum() + np.abs(comps["lub"]).sum()
     assert scale > 0
     assert np.all(np.abs(s) < 1e-13 * scale)
+
+
+def _one_particle_drag(orc, law, U, eps_s, d=D):
+    """Drag on one particle at rest in a uniform flow U on a one-cell mesh
+    whose smoothed solid fraction is eps_s."""
+    prm = workloads.base_params(nx=1, ny=1, nz=1, drag_law=law, lubrication=0,
+                                fluid_forces=0, bottom_wall=0, top_wall=0, eps_s_max=0.7)
+    x = np.array([[1e-3, 1e-3, 1e-3]])
+    comps, _ = orc.forces(prm, x, np.zeros((1, 3)), np.zeros((1, 3)), np.full(1, d),
+                          np.full(1, RHO), U=np.array([U]), eps_s=np.array([eps_s]))
+    return comps["drag"][0]
+
+
+def test_syamlal_single_sphere_is_dalla_valle(orc):
+    """At eps_f = 1, A1 = A2 = 1 and V_r = 1: the correlation reduces to the
+    single-sphere drag 1/2 C_d rho_f (pi d^2/4) |w| w, C_d = (0.63 + 4.8/sqrt(Re))^2."""
+    rf, mu = workloads.RHO_F, workloads.MU_F
+    for Re in (0.01, 1.0, 50.0, 2000.0):
+        wm = Re * mu / (rf * D)
+        f = _one_particle_drag(orc, "syamlal", [wm, 0.0, 0.0], 0.0)
+        cd = (0.63 + 4.8 / math.sqrt(Re)) ** 2
+        want = 0.5 * cd * rf * math.pi * D * D / 4 * wm * wm
+        assert f[0] > 0 and f[1] == 0 and f[2] == 0
+        assert abs(f[0] - want) < 1e-13 * want, Re
+
+
+@pytest.mark.parametrize("eps_f", [0.5, 0.8, 0.95])
+def test_syamlal_low_re_is_hindered_stokes(orc, eps_f):
+    """Re -> 0: V_r -> A1 = eps_f^4.14 and C_d -> 23.04 V_r/Re, so the drag
+    tends to 0.96 x Stokes / eps_f^4.14 (Richardson-Zaki hindering)."""
+    rf, mu = workloads.RHO_F, workloads.MU_F
+    wm = 1e-8 * mu / (rf * D)
+    f = _one_particle_drag(orc, "syamlal", [0.0, wm, 0.0], 1.0 - eps_f)
+    ratio = f[1] / (3 * math.pi * mu * D * wm)
+    assert abs(ratio - 0.96 / eps_f ** 4.14) < 1e-3 * ratio
+
+
+@pytest.mark.parametrize("eps_f", [0.5, 0.8, 0.9])
+def test_syamlal_high_re_is_hindered_newton(orc, eps_f):
+    """Re -> infinity: V_r -> A2 (0.8 eps_f^1.28 up to 0.85, eps_f^2.65 above)
+    and C_d -> 0.63^2, so the drag tends to the Newton-regime drag / A2^2."""
+    rf, mu = workloads.RHO_F, workloads.MU_F
+    wm = 1e9 * mu / (rf * D)
+    f = _one_particle_drag(orc, "syamlal", [0.0, 0.0, -wm], 1.0 - eps_f)
+    A2 = 0.8 * eps_f ** 1.28 if eps_f <= 0.85 else eps_f ** 2.65
+    newton = 0.5 * 0.63 ** 2 * rf * math.pi * D * D / 4 * wm * wm
+    assert f[2] < 0
+    assert abs(-f[2] / newton - 1.0 / A2 ** 2) < 2e-3 / A2 ** 2
