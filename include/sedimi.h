@@ -51,10 +51,14 @@ extern "C" {
 #define SEDIMI_ENOCONV (-7)   /* diffusion solve above its residual tolerance */
 #define SEDIMI_ESTATE (-8)    /* call out of order (e.g. no particles yet) */
 
-/* drag laws (Section 2.3) */
+/* drag laws (Section 2.3); w = U_f - u_p at the particle centre */
 #define SEDIMI_DRAG_NONE 0
-#define SEDIMI_DRAG_DIFELICE 1
-#define SEDIMI_DRAG_STOKES 2
+#define SEDIMI_DRAG_DIFELICE 1 /* 1/2 C_d rho_f (pi d^2/4) eps_f^(2-chi) |w| w */
+#define SEDIMI_DRAG_STOKES 2   /* 3 pi mu d w */
+#define SEDIMI_DRAG_SYAMLAL 3  /* Syamlal-O'Brien, Eqs. (beta-i)-(drag-A):
+                                  (3/4) V_p C_d rho_f |w| w / (V_r^2 d),
+                                  C_d = (0.63 + 4.8 sqrt(V_r/Re))^2,
+                                  Re = rho_f d |w| / mu */
 
 /* arithmetic of the force evaluation */
 #define SEDIMI_FP64 0  /* everything in FP64 */

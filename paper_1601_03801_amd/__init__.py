@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsedimi.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW, EUNSTABLE, EESCAPE, ENOCONV, ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7, -8
-DRAG = {"none": 0, "difelice": 1, "stokes": 2}
+DRAG = {"none": 0, "difelice": 1, "stokes": 2, "syamlal": 3}
 FP64, MIXED = 0, 1
 SOLVERS = {"auto": 0, "direct": 1, "iterative": 2}
 FORCE = {"contact": 0, "lub": 1, "drag": 2, "pressure": 3, "added": 4, "total": 5,

@@ -63,9 +63,23 @@ __device__ __forceinline__ V3<R> tangential(R kt, R gt, R mu, R dt, V3<R> n, V3<
   return ft;
 }
 
+// Drag force per unit slip velocity w (F = drag_coef * w) for the selected
+// law (Section 2.3).
 template <typename R>
 __device__ __forceinline__ R drag_coef(const DevParams& P, R d, R eps_f, R wm) {
   if (P.drag_law == SEDIMI_DRAG_STOKES) return (R)(3.0 * kPi * P.mu_f) * d;
+  if (P.drag_law == SEDIMI_DRAG_SYAMLAL) {
+    // (3/4) V_p C_d rho_f |w| / (V_r^2 d) = (pi/8) d^2 C_d rho_f |w| / V_r^2
+    const R Re = (R)P.rho_f * d * wm / (R)P.mu_f;
+    if (!(Re >= (R)1e-12)) return (R)0;
+    const R A1 = pow(eps_f, (R)4.14);
+    const R A2 = eps_f <= (R)0.85 ? (R)0.8 * pow(eps_f, (R)1.28) : pow(eps_f, (R)2.65);
+    const R a = (R)0.06 * Re;
+    const R Vr = (R)0.5 * (A1 - a + sqrt(a * a + (R)0.12 * Re * ((R)2 * A2 - A1) + A1 * A1));
+    R cd = (R)0.63 + (R)4.8 * sqrt(Vr / Re);
+    cd = cd * cd;
+    return (R)(0.125 * kPi) * d * d * cd * (R)P.rho_f * wm / (Vr * Vr);
+  }
   if (P.drag_law != SEDIMI_DRAG_DIFELICE) return (R)0;
   R Re = (R)P.rho_f * d * eps_f * wm / (R)P.mu_f;
   if (!(Re >= (R)1e-12)) return (R)0;

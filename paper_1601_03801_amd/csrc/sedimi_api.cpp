@@ -227,7 +227,8 @@ int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
   if (!(p.rho_f >= 0 && p.mu_f > 0 && p.c_add >= 0))
     return fail(c, SEDIMI_EINVAL, "fluid properties out of range");
   if (!(p.dt > 0)) return fail(c, SEDIMI_EINVAL, "dt must be positive");
-  if (p.drag_law < 0 || p.drag_law > 2) return fail(c, SEDIMI_EINVAL, "unknown drag law");
+  if (p.drag_law < SEDIMI_DRAG_NONE || p.drag_law > SEDIMI_DRAG_SYAMLAL)
+    return fail(c, SEDIMI_EINVAL, "unknown drag law");
   if (!(p.eps_s_max >= 0 && p.eps_s_max < 1)) return fail(c, SEDIMI_EINVAL, "eps_s_max in [0,1)");
   if (!(p.avg_bandwidth >= 0) || p.avg_ntau < 0 || !(p.avg_rtol > 0))
     return fail(c, SEDIMI_EINVAL, "averaging parameters out of range");

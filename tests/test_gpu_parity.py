@@ -115,6 +115,16 @@ def test_forces_mixed_fp32(orc, seed):
     _force_parity(orc, case, "mixed", 1e-5, seed)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_forces_syamlal_drag(orc, precision, tol):
+    """The Syamlal-O'Brien drag law; the bed's smoothed solid fraction puts
+    particles on both branches of A2 (eps_f below and above 0.85)."""
+    case = dense_bed(3000, 8)
+    case["params"] = dict(case["params"], drag_law="syamlal")
+    worst = _force_parity(orc, case, precision, tol, 8)
+    assert worst["drag"] < tol
+
+
 def test_deposit_bit_exact_and_smooth(orc):
     case = dense_bed(4000, 8)
     prm = case["params"]
