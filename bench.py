@@ -57,8 +57,8 @@ def averaging_rooflines(n, ncell, dep_ms, smooth_ms, direct, mesh):
 # the same counters read for a 1 GiB device copy (--copy-calibration: the
 # copy's FETCH_SIZE reads 0.5x the bytes read, WRITE_SIZE 1.0x the bytes
 # written).  Valid only for the kernel sources it was measured on.
-FORCE_PMC = {"fetch_kib": 315436.3, "write_kib": 280999.8, "fetch_scale": 2.0, "write_scale": 1.0,
-             "sources_sha256": "31f6d7805e0f5d04c8732f2ae2065cd3db42cb85b125dba1a872ece07c8d7fe7",
+FORCE_PMC = {"fetch_kib": 315496.9, "write_kib": 280999.8, "fetch_scale": 2.0, "write_scale": 1.0,
+             "sources_sha256": "9acc6a076691eb2c93144aad71411306770bc86c1da621275188818ea42efb0a",
              "profile": "profiles/k_forces_bed1m_fp64.md"}
 FORCE_SOURCES = ("k_forces.hip", "k_common.h", "sedimi_internal.h")
 
@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--workload", default="bed1m")
     ap.add_argument("--substeps", type=int, default=10)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--drag", default="difelice", choices=["difelice", "syamlal", "stokes"],
+                    help="drag law of the particle step")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nn-train-steps", type=int, default=2000,
@@ -136,7 +138,7 @@ def main():
 
     t0 = time.time()
     w = workloads.workload(args.workload)
-    prm = dict(w["params"])
+    prm = dict(w["params"], drag_law=args.drag)
     n = len(w["d"])
     print(f"bench: workload {args.workload}: {n} spheres, mesh {w['meta']['mesh']}, "
           f"generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -176,7 +178,7 @@ def main():
     achieved = bytes_launch / (f_avg * 1e-3) / 1e9
     traffic = None
     if (FORCE_PMC is not None and args.workload == "bed1m" and not mixed
-            and FORCE_PMC["sources_sha256"] == force_sources_sha()):
+            and args.drag == "difelice" and FORCE_PMC["sources_sha256"] == force_sources_sha()):
         traffic = int(1024 * (FORCE_PMC["fetch_kib"] * FORCE_PMC["fetch_scale"]
                               + FORCE_PMC["write_kib"] * FORCE_PMC["write_scale"]))
     roofline = {"bound": "hbm", "kernel": "k_forces (step)", "achieved": round(achieved, 1),
@@ -225,7 +227,8 @@ def main():
         "dtype": "f64" if not mixed else "f64-state/f32-forces", "data": "synthetic",
         "config": {"workload": args.workload, "particles": n, "mesh": w["meta"]["mesh"],
                    "substeps_per_step": S, "average_every": S, "dt": prm["dt"],
-                   "precision": args.precision, "bed_seed": w["meta"].get("bed_seed"),
+                   "precision": args.precision, "drag": args.drag,
+                   "bed_seed": w["meta"].get("bed_seed"),
                    "field_seed": w["meta"].get("field_seed")},
         "roofline": roofline,
         "cpu_baseline": cpu,
