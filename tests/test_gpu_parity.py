@@ -367,3 +367,61 @@ def test_crowded_and_runaway_states_end_in_error_codes():
     with pytest.raises(sm.SedimiError) as e:
         g.average()
     assert e.value.code == sm.EUNSTABLE
+
+
+def test_translate_shifts_bed_keeps_pairs_and_history(orc):
+    """sedimi_translate: positions become fmod(x + shift, L) wrapped into
+    [0, L), bit for bit; the pair set and the contact history are those of
+    the unshifted bed; the forces equal the oracle's on the shifted bed (the
+    mesh fields stay put)."""
+    case = dense_bed(3000, 9)
+    prm = case["params"]
+    hist, a_prev, sm = _oracle_inputs(orc, case, 9)
+    g = gpu_context(case)
+    g.set_field(1, sm)
+    g.set_accel(a_prev)
+    g.set_history(hist)
+    pairs0 = g.get_pairs()
+    h0 = g.get_history()
+    sx, sy = 0.37 * prm["Lx"], -0.61 * prm["Ly"]
+    g.translate(sx, sy)
+    want = case["x"].copy()
+    for a, (s, L) in enumerate(((sx, prm["Lx"]), (sy, prm["Ly"]))):
+        c = np.fmod(want[:, a] + s, L)
+        c = np.where(c < 0.0, c + L, c)
+        want[:, a] = np.where(c >= L, 0.0, c)
+    assert np.array_equal(g.get_particles()["x"], want)
+    assert np.array_equal(g.get_pairs(), pairs0)
+    assert np.array_equal(g.get_pairs(), orc.pairs_cells(prm, want, case["d"]))
+    h1 = g.get_history()
+    assert np.array_equal(h1["i"], h0["i"]) and np.array_equal(h1["j"], h0["j"])
+    assert np.array_equal(h1["xi"], h0["xi"])
+    comps, _ = orc.forces(prm, want, case["v"], case["w"], case["d"], case["rho"],
+                          a_prev=a_prev, U=case["U"], gradp=case["gradp"], dudt=case["dudt"],
+                          eps_s=sm[0], hist=hist)
+    g.compute_forces(update_history=False)
+    m = case["rho"] * math.pi / 6 * case["d"] ** 3
+    scale = sum(np.linalg.norm(comps[k], axis=1) for k in
+                ("contact", "lub", "drag", "pressure", "added")) + m * 9.81
+    assert rel_err(g.get_forces("total"), comps["total"], scale).max() < 1e-12
+
+
+def test_profiling_counts_phase_launches():
+    """Phase timing: launches per phase for a known step sequence; turning
+    profiling on again clears the totals."""
+    w = workloads.workload("small")
+    g = gpu_context(w)
+    g.average()
+    g.compute_forces()
+    g.set_profiling(True)
+    g.step(5, average_every=5)
+    p = g.profile()
+    assert p["forces"][1] == 5 and p["rebuild"][1] == 5
+    assert p["deposit"][1] == 1 and p["smooth"][1] == 1
+    assert p["drift"][1] == 1  # later drifts are fused into the force kernel
+    assert all(ms >= 0.0 for ms, _ in p.values())
+    assert p["forces"][0] > 0.0
+    g.set_profiling(False)
+    g.set_profiling(True)
+    assert all(v == (0.0, 0) for v in g.profile().values())
+    g.set_profiling(False)
