@@ -52,6 +52,7 @@ class orc_params(C.Structure):
         ("bottom_wall", C.c_int), ("top_wall", C.c_int),
         ("eps_s_max", C.c_double),
         ("avg_bandwidth", C.c_double), ("avg_ntau", C.c_int), ("cg_rtol", C.c_double),
+        ("avg_bandwidth_z", C.c_double),
     ]
 
 

@@ -54,6 +54,7 @@ typedef struct {
   double avg_bandwidth;      /* diffusion-averaging bandwidth b (m) */
   int avg_ntau;              /* number of implicit pseudo-time steps */
   double cg_rtol;            /* CG relative residual tolerance */
+  double avg_bandwidth_z;    /* bandwidth along z (m); 0: avg_bandwidth */
 } orc_params;
 
 /* One tangential-history record.  Particle pairs carry i < j (IDs); a wall

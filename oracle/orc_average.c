@@ -12,7 +12,10 @@
  *    mesh are clamped into the first/last cell.
  *  - Eq. (12): the deposited field then diffuses with unit diffusivity up to
  *    pseudo-time tau = b^2/4 (b = bandwidth; the paper states the equivalence
- *    to Gaussian averaging with bandwidth sqrt(4 tau)).  Space: the
+ *    to Gaussian averaging with bandwidth sqrt(4 tau)).  The application
+ *    cases of Section 4 use a smaller bandwidth b_z across the bed than along
+ *    it; the diffusivity along z is then (b_z/b)^2, so that each axis has
+ *    its own Gaussian width sqrt(4 tau D_a) = b_a.  Space: the
  *    second-order central finite-volume Laplacian on the CFD mesh (Section
  *    2.5), periodic in x and y, zero flux through the walls at z = 0 and Lz
  *    (the no-flux wall condition of Section 2.4).  Time: avg_ntau implicit
@@ -64,6 +67,10 @@ void orc_apply_A(const orc_params* p, double dtau, const double* x, double* y) {
   double ix2 = 1.0 / ((p->Lx / nx) * (p->Lx / nx));
   double iy2 = 1.0 / ((p->Ly / ny) * (p->Ly / ny));
   double iz2 = 1.0 / ((p->Lz / nz) * (p->Lz / nz));
+  if (p->avg_bandwidth_z > 0.0 && p->avg_bandwidth > 0.0) {
+    const double r = p->avg_bandwidth_z / p->avg_bandwidth;
+    iz2 *= r * r;  /* diffusivity along z */
+  }
   for (int k = 0; k < nz; ++k) {
     for (int j = 0; j < ny; ++j) {
       for (int i = 0; i < nx; ++i) {

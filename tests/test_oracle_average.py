@@ -30,12 +30,14 @@ def spectral_solve(prm, raw, exact_time=False):
     nx, ny, nz = prm["nx"], prm["ny"], prm["nz"]
     hx, hy, hz = prm["Lx"] / nx, prm["Ly"] / ny, prm["Lz"] / nz
     tau = prm["avg_bandwidth"] ** 2 / 4
+    bz = prm.get("avg_bandwidth_z", 0.0)
+    kz = (bz / prm["avg_bandwidth"]) ** 2 if bz > 0 else 1.0  # diffusivity along z
     f = raw.reshape(nz, ny, nx)
     F = sfft.dct(np.fft.fft2(f, axes=(1, 2)), type=2, axis=0, norm="ortho")
     kx = 2 * np.pi * np.arange(nx) / nx
     ky = 2 * np.pi * np.arange(ny) / ny
-    kz = np.pi * np.arange(nz) / nz
-    lam = ((2 - 2 * np.cos(kz))[:, None, None] / hz ** 2 +
+    kzw = np.pi * np.arange(nz) / nz
+    lam = (kz * (2 - 2 * np.cos(kzw))[:, None, None] / hz ** 2 +
            (2 - 2 * np.cos(ky))[None, :, None] / hy ** 2 +
            (2 - 2 * np.cos(kx))[None, None, :] / hx ** 2)
     if exact_time:
@@ -69,9 +71,10 @@ def test_pcm_single_particle_and_faces(orc):
         assert raw[1:, cell] == pytest.approx(np.array([1.0, 2.0, 3.0]) / Vc, rel=1e-14)
 
 
-@pytest.mark.parametrize("shape,ntau", [((8, 6, 5), 4), ((16, 12, 10), 1), ((10, 10, 24), 8)])
-def test_diffusion_equals_spectral_solution(orc, shape, ntau):
-    prm = mesh_prm(*shape, ntau=ntau)
+@pytest.mark.parametrize("shape,ntau,bz", [((8, 6, 5), 4, 0.0), ((16, 12, 10), 1, 0.0),
+                                           ((10, 10, 24), 8, 0.0), ((12, 10, 16), 4, 0.6e-3)])
+def test_diffusion_equals_spectral_solution(orc, shape, ntau, bz):
+    prm = dict(mesh_prm(*shape, ntau=ntau), avg_bandwidth_z=bz)
     rng = np.random.default_rng(sum(shape))
     raw = rng.random((2, np.prod(shape))) ** 4
     out, iters = orc.diffuse(prm, raw)
@@ -172,3 +175,32 @@ def test_diffusion_apply_matches_stencil_definition(orc):
     dtau = 1e-7
     y = orc.apply_A(prm, dtau, mode)
     assert np.max(np.abs(y - (1 + dtau * lam) * mode)) < 1e-13
+
+
+@pytest.mark.parametrize("bz_over_b", [1.0, 0.5])
+def test_point_source_variance_grows_by_b2_over_2_per_axis(orc, bz_over_b):
+    """Backward Euler with the discrete Laplacian raises the second moment of
+    a point source by exactly 2 D_a dtau per step along each axis (sum by
+    parts: the 3-point Laplacian of i^2 is 2), whatever the number of steps.
+    So the variance after tau = b^2/4 is b^2/2 along x and y and, with the
+    bandwidth b_z across the bed (diffusivity (b_z/b)^2), b_z^2/2 along z,
+    up to the solver tolerance while the walls are far away."""
+    n = 64
+    b = 1.0e-3
+    h = b / 4
+    prm = dict(mesh_prm(n, n, n, L=(n * h, n * h, n * h), b=b, ntau=4),
+               avg_bandwidth_z=(bz_over_b * b if bz_over_b != 1.0 else 0.0))
+    src = np.zeros(n ** 3)
+    src[((n // 2) * n + n // 2) * n + n // 2] = 1.0
+    out, _ = orc.diffuse(prm, src[None])
+    u = out[0].reshape(n, n, n)
+    r = (np.arange(n) - n // 2) * h
+    m0 = u.sum()
+    assert abs(m0 - 1.0) < 1e-13
+    var_x = (u.sum(axis=(0, 1)) * r ** 2).sum() / m0
+    var_y = (u.sum(axis=(0, 2)) * r ** 2).sum() / m0
+    var_z = (u.sum(axis=(1, 2)) * r ** 2).sum() / m0
+    assert abs(var_x - b * b / 2) < 1e-9 * b * b
+    assert abs(var_y - b * b / 2) < 1e-9 * b * b
+    bz = bz_over_b * b
+    assert abs(var_z - bz * bz / 2) < 1e-9 * b * b
