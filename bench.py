@@ -111,6 +111,9 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--drag", default="difelice", choices=["difelice", "syamlal", "stokes"],
                     help="drag law of the particle step")
+    ap.add_argument("--bandwidth-z", type=float, default=0.0,
+                    help="averaging bandwidth across the bed in particle diameters "
+                         "(0: the same as along it)")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nn-train-steps", type=int, default=2000,
@@ -138,7 +141,8 @@ def main():
 
     t0 = time.time()
     w = workloads.workload(args.workload)
-    prm = dict(w["params"], drag_law=args.drag)
+    prm = dict(w["params"], drag_law=args.drag,
+               avg_bandwidth_z=args.bandwidth_z * workloads.D50)
     n = len(w["d"])
     print(f"bench: workload {args.workload}: {n} spheres, mesh {w['meta']['mesh']}, "
           f"generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -228,6 +232,8 @@ def main():
         "config": {"workload": args.workload, "particles": n, "mesh": w["meta"]["mesh"],
                    "substeps_per_step": S, "average_every": S, "dt": prm["dt"],
                    "precision": args.precision, "drag": args.drag,
+                   "avg_bandwidth_m": prm["avg_bandwidth"],
+                   "avg_bandwidth_z_m": prm["avg_bandwidth_z"] or prm["avg_bandwidth"],
                    "bed_seed": w["meta"].get("bed_seed"),
                    "field_seed": w["meta"].get("field_seed")},
         "roofline": roofline,

@@ -117,6 +117,10 @@ typedef struct {
   double nn_sample;          /* fraction of cells in the residual sample */
   uint64_t nn_seed;          /* seed of the residual sample */
   int avg_solver;            /* SEDIMI_SOLVE_*: how the implicit steps are solved */
+  double avg_bandwidth_z;    /* averaging bandwidth across the bed, along z (m); 0: the
+                                same as avg_bandwidth.  The z diffusivity is then
+                                (avg_bandwidth_z / avg_bandwidth)^2, so each axis has
+                                its own Gaussian width (Section 4's cases use 2d / d) */
 } sedimi_params;
 
 /* solvers of the implicit diffusion steps (Eq. 12) */

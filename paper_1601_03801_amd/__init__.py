@@ -53,6 +53,7 @@ class sedimi_params(C.Structure):
         ("nn_enable", C.c_int), ("nn_alpha", C.c_double), ("nn_bound", C.c_double),
         ("nn_sample", C.c_double), ("nn_seed", C.c_uint64),
         ("avg_solver", C.c_int),
+        ("avg_bandwidth_z", C.c_double),
     ]
 
 

@@ -372,7 +372,7 @@ int launch_check(const DevParams& P, DevArrays& A, const double* y, int ntau, do
   double dtau = tau / (ntau > 0 ? ntau : 1);
   S.cx = dtau / (P.hx * P.hx);
   S.cy = dtau / (P.hy * P.hy);
-  S.cz = dtau / (P.hz * P.hz);
+  S.cz = dtau * P.kz_diff / (P.hz * P.hz);
   const int rows = P.ny * P.nz;
   dim3 grid((unsigned)((P.nx + kBlock - 1) / kBlock), (unsigned)(rows < 65535 ? rows : 65535), 4);
   const double* cur = y;
@@ -423,7 +423,7 @@ size_t smooth_red_doubles(int ncell, int nch, int ntau) {
 
 void smooth_ztab(const DevParams& P, int ntau, double tau, double* host_tab) {
   double dtau = tau / (ntau > 0 ? ntau : 1);
-  double cz = dtau / (P.hz * P.hz);
+  double cz = dtau * P.kz_diff / (P.hz * P.hz);
   double prev_cp = 0.0;
   for (int k = 0; k < P.nz; ++k) {
     int nb = (k > 0) + (k + 1 < P.nz);
@@ -452,7 +452,7 @@ static int64_t smooth_impl(const DevParams& P, DevArrays& A, int nch, int ntau, 
   double dtau = tau / ntau;
   S.cx = dtau / (P.hx * P.hx);
   S.cy = dtau / (P.hy * P.hy);
-  S.cz = dtau / (P.hz * P.hz);
+  S.cz = dtau * P.kz_diff / (P.hz * P.hz);
   const double axy = 4.0 * ((P.nx > 1 ? S.cx : 0.0) + (P.ny > 1 ? S.cy : 0.0));
   const double az = 4.0 * (P.nz > 1 ? S.cz : 0.0);
   const double kappaA = 1.0 + axy + az;

@@ -187,7 +187,7 @@ void spectral_tables(const DevParams& P, double* t) {
   for (int p = 0; p < ny; ++p)
     ly[p] = (2.0 - 2.0 * cos(2.0 * pi * p / ny)) / (P.hy * P.hy);
   for (int m = 0; m < nz; ++m)
-    lz[m] = (2.0 - 2.0 * cos(pi * m / nz)) / (P.hz * P.hz);
+    lz[m] = P.kz_diff * (2.0 - 2.0 * cos(pi * m / nz)) / (P.hz * P.hz);  // z diffusivity
 }
 
 // raw (nch channels) -> smooth, through A.sr / A.stmp.

@@ -240,6 +240,8 @@ int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
     return fail(c, SEDIMI_EINVAL, "max_neighbors must be in 1..30");
   if (p.nn_enable && !(p.nn_alpha >= 0 && p.nn_bound > 0 && p.nn_sample > 0 && p.nn_sample <= 1))
     return fail(c, SEDIMI_EINVAL, "surrogate parameters out of range");
+  if (!(p.avg_bandwidth_z >= 0 && std::isfinite(p.avg_bandwidth_z)))
+    return fail(c, SEDIMI_EINVAL, "avg_bandwidth_z must be finite and >= 0");
   if (p.avg_solver < SEDIMI_SOLVE_AUTO || p.avg_solver > SEDIMI_SOLVE_ITERATIVE)
     return fail(c, SEDIMI_EINVAL, "unknown averaging solver");
   if (p.avg_solver == SEDIMI_SOLVE_DIRECT && std::max(p.nx, std::max(p.ny, p.nz)) > kDirectMaxAxis)
@@ -273,6 +275,11 @@ void fill_dev_params(sedimi_ctx* c) {
   P.fluid_forces = p.fluid_forces ? 1 : 0;
   P.bottom_wall = p.bottom_wall ? 1 : 0, P.top_wall = p.top_wall ? 1 : 0;
   P.eps_s_max = p.eps_s_max;
+  P.kz_diff = 1.0;
+  if (p.avg_bandwidth_z > 0 && p.avg_bandwidth > 0) {
+    const double r = p.avg_bandwidth_z / p.avg_bandwidth;
+    P.kz_diff = r * r;
+  }
   // neighbour bins: no smaller than the largest pair range plus the skin
   double hb = p.d_max * (1.0 + p.lub_out_frac) + p.skin;
   P.nbx = std::max(1, (int)floor(p.Lx / hb));
@@ -386,7 +393,7 @@ double direct_tol(const sedimi_ctx* c) {
   double lam = 0.0;
   if (P.nx > 1) lam += 4.0 / (P.hx * P.hx);
   if (P.ny > 1) lam += 4.0 / (P.hy * P.hy);
-  if (P.nz > 1) lam += 4.0 / (P.hz * P.hz);
+  if (P.nz > 1) lam += 4.0 * P.kz_diff / (P.hz * P.hz);
   return std::max(c->prm.avg_rtol, 1e-13 * pow(1.0 + dtau * lam, (double)ntau));
 }
 

@@ -81,6 +81,7 @@ struct DevParams {
   double gx, gy, gz, dt;
   int drag_law, lubrication, fluid_forces, bottom_wall, top_wall;
   double eps_s_max;
+  double kz_diff;  // diffusivity of the averaging along z (1: isotropic)
   // neighbour bins
   int nbx, nby, nbz, nbins;
   double hbx, hby, hbz;

@@ -148,13 +148,18 @@ def test_deposit_bit_exact_and_smooth(orc):
 
 
 @pytest.mark.parametrize("solver", ["direct", "iterative"])
-@pytest.mark.parametrize("shape,ntau", [((16, 16, 8), 4), ((33, 20, 17), 3), ((64, 32, 48), 4),
-                                        ((1, 5, 70), 2), ((130, 2, 1), 5)])
-def test_smooth_matches_oracle(orc, shape, ntau, solver):
+@pytest.mark.parametrize("shape,ntau,bz", [((16, 16, 8), 4, 0.0), ((33, 20, 17), 3, 0.0),
+                                           ((64, 32, 48), 4, 0.0), ((1, 5, 70), 2, 0.0),
+                                           ((130, 2, 1), 5, 0.0),
+                                           ((33, 20, 17), 4, 0.5e-3), ((24, 16, 40), 2, 3.0e-3)])
+def test_smooth_matches_oracle(orc, shape, ntau, bz, solver):
+    """bz > 0: a different bandwidth across the bed (smaller and larger than
+    the horizontal 1.5 mm)."""
     # the context needs >= 3 neighbour bins across x and y: thin meshes get wide cells
     prm = workloads.base_params(Lx=max(shape[0] * 0.3e-3, 5e-3), Ly=max(shape[1] * 0.3e-3, 5e-3),
                                 Lz=shape[2] * 0.2e-3,
-                                nx=shape[0], ny=shape[1], nz=shape[2], avg_ntau=ntau)
+                                nx=shape[0], ny=shape[1], nz=shape[2], avg_ntau=ntau,
+                                avg_bandwidth_z=bz)
     rng = np.random.default_rng(sum(shape))
     raw = rng.random((4, np.prod(shape))) ** 3
     want, _ = orc.diffuse(prm, raw)
