@@ -52,7 +52,7 @@ class orc_params(C.Structure):
         ("bottom_wall", C.c_int), ("top_wall", C.c_int),
         ("eps_s_max", C.c_double),
         ("avg_bandwidth", C.c_double), ("avg_ntau", C.c_int), ("cg_rtol", C.c_double),
-        ("avg_bandwidth_z", C.c_double),
+        ("avg_bandwidth_z", C.c_double), ("c_lift", C.c_double),
     ]
 
 
@@ -67,7 +67,7 @@ class orc_fields(C.Structure):
 
 class orc_forces_out(C.Structure):
     _fields_ = [(k, C.c_void_p) for k in
-                ("contact", "lub", "drag", "pressure", "added", "total", "torque")]
+                ("contact", "lub", "drag", "pressure", "added", "total", "torque", "lift")]
 
 
 CONTACT_DTYPE = np.dtype([("i", np.int64), ("j", np.int64), ("xi", np.float64, (3,))])
@@ -195,7 +195,7 @@ def forces(prm, x, v, w, d, rho, a_prev=None, U=None, gradp=None, dudt=None, eps
     hout = np.zeros(cap, CONTACT_DTYPE)
     nh = C.c_int64(0)
     comps = {k: np.zeros((n, 3)) for k in
-             ("contact", "lub", "drag", "pressure", "added", "total", "torque")}
+             ("contact", "lub", "drag", "pressure", "added", "total", "torque", "lift")}
     o = orc_forces_out(*[_ptr(comps[k]) for k, _ in orc_forces_out._fields_])
     _check(lib().orc_forces(C.byref(p), n, _ptr(x), _ptr(v), _ptr(w), _ptr(d), _ptr(rho),
                             _ptr(ap), C.byref(fl), _ptr(hin) if len(hin) else None, len(hin),

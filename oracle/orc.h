@@ -55,6 +55,7 @@ typedef struct {
   int avg_ntau;              /* number of implicit pseudo-time steps */
   double cg_rtol;            /* CG relative residual tolerance */
   double avg_bandwidth_z;    /* bandwidth along z (m); 0: avg_bandwidth */
+  double c_lift;             /* lift coefficient C_l of Eq. (particleLift); 0: no lift */
 } orc_params;
 
 /* One tangential-history record.  Particle pairs carry i < j (IDs); a wall
@@ -83,6 +84,7 @@ typedef struct {
   double* added;    /* added mass [n][3] */
   double* total;    /* sum of the above + m g [n][3] */
   double* torque;   /* [n][3] */
+  double* lift;     /* shear lift [n][3] */
 } orc_forces_out;
 
 /* ---- pair search (Section 2.5: neighbour lists + link-cell binning) ---- */

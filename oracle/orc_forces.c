@@ -43,6 +43,14 @@
  *    as in the correlation's source.)
  *    Eq. (4) prints the fluid-side orientation (u_p - U_f); on the particle the
  *    force points towards the fluid velocity.
+ *  - Lift (Eq. particleLift, Saffman): f = C_l rho_f nu^(1/2) d^2 |omega|^(-1/2)
+ *    (U_f - u_p) x omega with omega = curl U_f at the particle (0 when
+ *    omega = 0).  The printed form lacks the |omega|^(-1/2) that makes it a
+ *    force and orients the slip as u_p - U_f, which would push a particle
+ *    lagging a shear flow towards the slower fluid; this is Saffman's form,
+ *    whose coefficient 6.46/4 = 1.615 the paper rounds to C_l = 1.6.  The
+ *    curl is taken at cell centres by central differences (periodic in x, y;
+ *    one-sided at the first and last cell in z) and interpolated like U_f.
  *  - Pressure gradient: f = -V_p grad p (Eq. 2b's -grad p seen by a particle;
  *    it carries the buoyancy of the hydrostatic part).
  *  - Added mass, Eq. (10): f = C_add rho_f V_p (DU_f/Dt - a_prev), where
@@ -178,6 +186,40 @@ static double interp_scalar(const double* f, const int64_t idx[8], const double 
   if (!f) return 0.0;
   for (int q = 0; q < 8; ++q) s += wt[q] * f[idx[q]];
   return s;
+}
+
+/* ---------------- vorticity ---------------- */
+/* omega = curl U at every cell centre [ncell][3]: central differences,
+ * periodic in x and y; in z central inside, one-sided in the first and last
+ * cell, zero when nz = 1. */
+static void curl_cells(const orc_params* p, const double* U, double* om) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const double hx = p->Lx / nx, hy = p->Ly / ny, hz = p->Lz / nz;
+  for (int k = 0; k < nz; ++k)
+    for (int j = 0; j < ny; ++j)
+      for (int i = 0; i < nx; ++i) {
+        const int64_t c = ((int64_t)k * ny + j) * nx + i;
+        const int64_t xp = ((int64_t)k * ny + j) * nx + (i + 1) % nx;
+        const int64_t xm = ((int64_t)k * ny + j) * nx + (i + nx - 1) % nx;
+        const int64_t yp = ((int64_t)k * ny + (j + 1) % ny) * nx + i;
+        const int64_t ym = ((int64_t)k * ny + (j + ny - 1) % ny) * nx + i;
+        double dUdx[3], dUdy[3], dUdz[3];
+        for (int a = 0; a < 3; ++a) {
+          dUdx[a] = (U[3 * xp + a] - U[3 * xm + a]) / (2.0 * hx);
+          dUdy[a] = (U[3 * yp + a] - U[3 * ym + a]) / (2.0 * hy);
+          if (nz == 1) {
+            dUdz[a] = 0.0;
+          } else {
+            const int kp = k + 1 < nz ? k + 1 : k, km = k > 0 ? k - 1 : k;
+            const int64_t zp = ((int64_t)kp * ny + j) * nx + i;
+            const int64_t zm = ((int64_t)km * ny + j) * nx + i;
+            dUdz[a] = (U[3 * zp + a] - U[3 * zm + a]) / ((double)(kp - km) * hz);
+          }
+        }
+        om[3 * c + 0] = dUdy[2] - dUdz[1];
+        om[3 * c + 1] = dUdz[0] - dUdx[2];
+        om[3 * c + 2] = dUdx[1] - dUdy[0];
+      }
 }
 
 /* ---------------- drag laws ---------------- */
@@ -317,18 +359,19 @@ int orc_forces(const orc_params* p, int64_t n, const double* x, const double* v,
                const double* w, const double* d, const double* rho, const double* a_prev,
                const orc_fields* fl, const orc_contact* hin, int64_t nhin,
                orc_contact* hout, int64_t cap_hout, int64_t* nhout, orc_forces_out* out) {
-  double* arrs[7] = {out->contact, out->lub, out->drag, out->pressure,
-                     out->added, out->total, out->torque};
-  for (int k = 0; k < 7; ++k)
+  double* arrs[8] = {out->contact, out->lub, out->drag, out->pressure,
+                     out->added, out->total, out->torque, out->lift};
+  for (int k = 0; k < 8; ++k)
     if (arrs[k]) memset(arrs[k], 0, sizeof(double) * 3 * (size_t)n);
   *nhout = 0;
   if (n == 0) return 0;
 
   /* scratch breakdown arrays if the caller did not ask for some */
-  double* own[7] = {0};
+  double* own[8] = {0};
   orc_forces_out o = *out;
-  double** slots[7] = {&o.contact, &o.lub, &o.drag, &o.pressure, &o.added, &o.total, &o.torque};
-  for (int k = 0; k < 7; ++k) {
+  double** slots[8] = {&o.contact, &o.lub, &o.drag, &o.pressure, &o.added, &o.total, &o.torque,
+                       &o.lift};
+  for (int k = 0; k < 8; ++k) {
     if (!*slots[k]) {
       own[k] = (double*)calloc(3 * (size_t)n, sizeof(double));
       if (!own[k]) {
@@ -342,6 +385,15 @@ int orc_forces(const orc_params* p, int64_t n, const double* x, const double* v,
   int rc = 0;
   hmap hm;
   int64_t* ij = NULL;
+  double* omega = NULL; /* vorticity at cell centres, when the lift is on */
+  if (p->c_lift > 0.0 && fl && fl->U) {
+    omega = (double*)malloc(sizeof(double) * 3 * (size_t)p->nx * p->ny * p->nz);
+    if (!omega) {
+      for (int k = 0; k < 8; ++k) free(own[k]);
+      return -2;
+    }
+    curl_cells(p, fl->U, omega);
+  }
   if (hmap_build(&hm, n, hin, nhin) != 0) {
     rc = -2;
     goto done;
@@ -466,10 +518,23 @@ int orc_forces(const orc_params* p, int64_t n, const double* x, const double* v,
                       ca * (du[2] - (ap ? ap[2] : 0.0))};
       add3(o.added, i, fa, 1.0);
     }
+    if (omega) {
+      double om[3];
+      interp_vec(omega, idx, wt, om);
+      double on = sqrt(dot3(om, om));
+      if (on > 0.0) {
+        double c = p->c_lift * p->rho_f * sqrt(p->mu_f / p->rho_f) * d[i] * d[i] / sqrt(on);
+        double fl3[3] = {c * (wrel[1] * om[2] - wrel[2] * om[1]),
+                         c * (wrel[2] * om[0] - wrel[0] * om[2]),
+                         c * (wrel[0] * om[1] - wrel[1] * om[0])};
+        add3(o.lift, i, fl3, 1.0);
+      }
+    }
     for (int c = 0; c < 3; ++c) {
       double g = c == 0 ? p->gx : (c == 1 ? p->gy : p->gz);
       o.total[3 * i + c] = o.contact[3 * i + c] + o.lub[3 * i + c] + o.drag[3 * i + c] +
-                           o.pressure[3 * i + c] + o.added[3 * i + c] + m * g;
+                           o.pressure[3 * i + c] + o.added[3 * i + c] + o.lift[3 * i + c] +
+                           m * g;
     }
   }
   qsort(hout, (size_t)*nhout, sizeof(orc_contact), cmp_contact);
@@ -479,7 +544,8 @@ done_pairs:
 done_map:
   hmap_free(&hm);
 done:
-  for (int k = 0; k < 7; ++k) free(own[k]);
+  for (int k = 0; k < 8; ++k) free(own[k]);
+  free(omega);
   return rc;
 }
 
@@ -491,7 +557,7 @@ static int eval_accel(const orc_params* p, int64_t n, const double* x, const dou
                       int64_t nhin, orc_contact* hout, int64_t cap_hout, int64_t* nhout,
                       double* a, double* alpha, double* fdrag) {
   size_t sz = sizeof(double) * 3 * (size_t)n;
-  double* buf = (double*)malloc(5 * sz + 1);
+  double* buf = (double*)malloc(6 * sz + 1);
   if (!buf) return -2;
   orc_forces_out o;
   memset(&o, 0, sizeof(o));
@@ -500,6 +566,7 @@ static int eval_accel(const orc_params* p, int64_t n, const double* x, const dou
   o.pressure = buf + 6 * n;
   o.added = buf + 9 * n;
   o.torque = buf + 12 * n;
+  o.lift = buf + 15 * n;
   o.drag = fdrag;
   int rc = orc_forces(p, n, x, v, w, d, rho, a_prev, fl, hin, nhin, hout, cap_hout, nhout, &o);
   if (rc == 0) {
@@ -511,7 +578,7 @@ static int eval_accel(const orc_params* p, int64_t n, const double* x, const dou
       double I = 0.4 * m * r * r;
       for (int c = 0; c < 3; ++c) {
         int64_t k = 3 * i + c;
-        double F = o.contact[k] + o.lub[k] + o.drag[k] + o.pressure[k] + o.added[k];
+        double F = o.contact[k] + o.lub[k] + o.drag[k] + o.pressure[k] + o.added[k] + o.lift[k];
         a[k] = F / m + g[c];
         alpha[k] = o.torque[k] / I;
       }

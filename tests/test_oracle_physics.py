@@ -351,3 +351,64 @@ def test_syamlal_high_re_is_hindered_newton(orc, eps_f):
     newton = 0.5 * 0.63 ** 2 * rf * math.pi * D * D / 4 * wm * wm
     assert f[2] < 0
     assert abs(-f[2] / newton - 1.0 / A2 ** 2) < 2e-3 / A2 ** 2
+
+
+def _lift_case(orc, Ufun, v=(0.0, 0.0, 0.0), zp=0.37e-3, c_lift=1.6):
+    """One particle in a frozen field U(x, y, z) sampled at cell centres of a
+    4 x 4 x 8 mesh (walls at z = 0 and 2 mm); only the lift is on."""
+    prm = workloads.base_params(nx=4, ny=4, nz=8, Lx=2e-3, Ly=2e-3, Lz=2e-3, drag_law="none",
+                                lubrication=0, fluid_forces=0, bottom_wall=0, top_wall=0,
+                                c_lift=c_lift)
+    h = 2e-3 / np.array([4, 4, 8])
+    k, j, i = np.meshgrid(np.arange(8), np.arange(4), np.arange(4), indexing="ij")
+    cx, cy, cz = (i + 0.5) * h[0], (j + 0.5) * h[1], (k + 0.5) * h[2]
+    U = np.stack(Ufun(cx.ravel(), cy.ravel(), cz.ravel()), axis=1)
+    x = np.array([[0.71e-3, 1.13e-3, 1e-3 + zp]])
+    comps, _ = orc.forces(prm, x, np.array([v]), np.zeros((1, 3)), np.full(1, D), np.full(1, RHO),
+                          U=U)
+    return comps, x[0]
+
+
+def test_lift_in_linear_shear_is_saffman(orc):
+    """U = (g z, 0, 0): the discrete curl is exact, omega = (0, g, 0); a particle
+    at rest lags the flow by s = g z and is lifted towards the faster fluid with
+    Saffman's 6.46 mu a^2 s (g/nu)^(1/2) (C_l = 1.6 is its 1.615, rounded)."""
+    g = 40.0
+    comps, xp = _lift_case(orc, lambda x, y, z: (g * z, 0 * z, 0 * z))
+    f = comps["lift"][0]
+    s = g * xp[2]
+    nu = workloads.MU_F / workloads.RHO_F
+    saffman = 6.46 * workloads.MU_F * (D / 2) ** 2 * s * math.sqrt(g / nu)
+    assert f[0] == 0 and f[1] == 0 and f[2] > 0
+    assert abs(f[2] / saffman - 1.0) < 0.01
+    assert abs(f[2] - 1.6 * workloads.RHO_F * math.sqrt(nu) * D * D * s * math.sqrt(g)) < 1e-12 * f[2]
+    mg = RHO * math.pi / 6 * D ** 3 * 9.81
+    assert np.allclose(comps["total"][0], f - np.array([0, 0, mg]), rtol=0, atol=1e-15 * mg)
+
+
+def test_lift_is_perpendicular_to_slip_and_vorticity(orc):
+    """U = (g1 z, g2 z, 0): omega = (-g2, g1, 0) exactly, perpendicular to the
+    slip; the lift is perpendicular to both with magnitude
+    C_l rho_f nu^(1/2) d^2 |w| |omega|^(1/2)."""
+    g1, g2 = 30.0, -55.0
+    comps, xp = _lift_case(orc, lambda x, y, z: (g1 * z, g2 * z, 0 * z))
+    f = comps["lift"][0]
+    w = np.array([g1, g2, 0.0]) * xp[2]
+    om = np.array([-g2, g1, 0.0])
+    nu = workloads.MU_F / workloads.RHO_F
+    want = 1.6 * workloads.RHO_F * math.sqrt(nu) * D * D * np.linalg.norm(w) * math.sqrt(np.linalg.norm(om))
+    assert abs(np.linalg.norm(f) - want) < 1e-12 * want
+    assert abs(f @ w) < 1e-12 * want * np.linalg.norm(w)
+    assert abs(f @ om) < 1e-12 * want * np.linalg.norm(om)
+
+
+def test_lift_vanishes_without_vorticity_or_slip(orc):
+    comps, _ = _lift_case(orc, lambda x, y, z: (0 * z + 0.3, 0 * z - 0.1, 0 * z))
+    assert not comps["lift"].any()  # uniform flow: no vorticity
+    g = 40.0
+    zp = 0.37e-3
+    comps, xp = _lift_case(orc, lambda x, y, z: (g * z, 0 * z, 0 * z), v=(g * (1e-3 + zp), 0, 0),
+                           zp=zp)
+    assert np.abs(comps["lift"]).max() < 1e-12 * RHO * D ** 3  # moving with the fluid
+    comps, _ = _lift_case(orc, lambda x, y, z: (g * z, 0 * z, 0 * z), c_lift=0.0)
+    assert not comps["lift"].any()
