@@ -72,8 +72,9 @@ extern "C" {
 #define SEDIMI_F_DRAG 2     /* drag */
 #define SEDIMI_F_PRESSURE 3 /* -V_p grad p */
 #define SEDIMI_F_ADDED 4    /* added mass */
-#define SEDIMI_F_TOTAL 5    /* sum of the above + m g */
+#define SEDIMI_F_TOTAL 5    /* sum of the forces (lift included) + m g */
 #define SEDIMI_F_TORQUE 6   /* contact torque */
+#define SEDIMI_F_LIFT 7     /* shear lift (zero unless c_lift > 0) */
 
 /* mesh fields for sedimi_get_field / sedimi_set_field, each [4][ncell] */
 #define SEDIMI_FIELD_RAW 0    /* deposited, before smoothing (Eq. 11) */
@@ -121,6 +122,14 @@ typedef struct {
                                 same as avg_bandwidth.  The z diffusivity is then
                                 (avg_bandwidth_z / avg_bandwidth)^2, so each axis has
                                 its own Gaussian width (Section 4's cases use 2d / d) */
+  double c_lift;             /* lift coefficient C_l of Eq. (particleLift); 0: no lift.
+                                Read as Saffman's shear lift
+                                C_l rho_f nu^(1/2) d^2 |w|^(-1/2) (U_f - u_p) x w with
+                                w = curl U_f, nu = mu_f / rho_f, the curl taken by
+                                central differences at cell centres (periodic in x and
+                                y, one-sided in the first and last z cell, zero with one
+                                z cell) and interpolated like U_f; 1.6 approximates
+                                Saffman's 1.615 */
 } sedimi_params;
 
 /* solvers of the implicit diffusion steps (Eq. 12) */

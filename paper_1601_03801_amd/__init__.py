@@ -23,7 +23,7 @@ DRAG = {"none": 0, "difelice": 1, "stokes": 2, "syamlal": 3}
 FP64, MIXED = 0, 1
 SOLVERS = {"auto": 0, "direct": 1, "iterative": 2}
 FORCE = {"contact": 0, "lub": 1, "drag": 2, "pressure": 3, "added": 4, "total": 5,
-         "torque": 6}
+         "torque": 6, "lift": 7}
 FIELD_RAW, FIELD_SMOOTH = 0, 1
 
 HISTORY_DTYPE = np.dtype([("i", np.int64), ("j", np.int64), ("xi", np.float64, (3,))])
@@ -53,7 +53,7 @@ class sedimi_params(C.Structure):
         ("nn_enable", C.c_int), ("nn_alpha", C.c_double), ("nn_bound", C.c_double),
         ("nn_sample", C.c_double), ("nn_seed", C.c_uint64),
         ("avg_solver", C.c_int),
-        ("avg_bandwidth_z", C.c_double),
+        ("avg_bandwidth_z", C.c_double), ("c_lift", C.c_double),
     ]
 
 

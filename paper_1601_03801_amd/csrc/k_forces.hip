@@ -102,31 +102,44 @@ struct FluidAt {
   double dx, dy, dz;      // evaluation mode: DU/Dt
 };
 
-template <int MODE>
-__device__ __forceinline__ FluidAt fluid_at(const DevParams& P, const DevArrays& A, double x,
-                                            double y, double z) {
+// The cell-centre corners around (x, y, z) and the fractional offsets.
+struct Corners {
+  int i0, i1, j0, j1, k0, k1;
+  double fx, fy, fz;
+};
+
+__device__ __forceinline__ Corners corners_at(const DevParams& P, double x, double y, double z) {
   double sx = x / P.hx - 0.5, sy = y / P.hy - 0.5, sz = z / P.hz - 0.5;
   // keep indices in range even for non-finite positions (flagged elsewhere)
   if (!(sx >= -1.0 && sx <= (double)P.nx)) sx = 0.0;
   if (!(sy >= -1.0 && sy <= (double)P.ny)) sy = 0.0;
   const double fx0 = floor(sx), fy0 = floor(sy);
-  const double fx = sx - fx0, fy = sy - fy0;
-  const int i0 = (((int)fx0 % P.nx) + P.nx) % P.nx;
-  const int i1 = i0 + 1 == P.nx ? 0 : i0 + 1;
-  const int j0 = (((int)fy0 % P.ny) + P.ny) % P.ny;
-  const int j1 = j0 + 1 == P.ny ? 0 : j0 + 1;
-  int k0, k1;
-  double fz;
+  Corners q;
+  q.fx = sx - fx0;
+  q.fy = sy - fy0;
+  q.i0 = (((int)fx0 % P.nx) + P.nx) % P.nx;
+  q.i1 = q.i0 + 1 == P.nx ? 0 : q.i0 + 1;
+  q.j0 = (((int)fy0 % P.ny) + P.ny) % P.ny;
+  q.j1 = q.j0 + 1 == P.ny ? 0 : q.j0 + 1;
   if (P.nz == 1) {
-    k0 = k1 = 0;
-    fz = 0.0;
+    q.k0 = q.k1 = 0;
+    q.fz = 0.0;
   } else {
     sz = sz >= 0.0 ? (sz > P.nz - 1 ? (double)(P.nz - 1) : sz) : 0.0;
-    k0 = (int)floor(sz);
-    if (k0 > P.nz - 2) k0 = P.nz - 2;
-    k1 = k0 + 1;
-    fz = sz - (double)k0;
+    q.k0 = (int)floor(sz);
+    if (q.k0 > P.nz - 2) q.k0 = P.nz - 2;
+    q.k1 = q.k0 + 1;
+    q.fz = sz - (double)q.k0;
   }
+  return q;
+}
+
+template <int MODE>
+__device__ __forceinline__ FluidAt fluid_at(const DevParams& P, const DevArrays& A, double x,
+                                            double y, double z) {
+  const Corners q = corners_at(P, x, y, z);
+  const int i0 = q.i0, i1 = q.i1, j0 = q.j0, j1 = q.j1, k0 = q.k0, k1 = q.k1;
+  const double fx = q.fx, fy = q.fy, fz = q.fz;
   FluidAt f{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll 1
   for (int r = 0; r < 4; ++r) {
@@ -161,6 +174,24 @@ __device__ __forceinline__ FluidAt fluid_at(const DevParams& P, const DevArrays&
     }
   }
   return f;
+}
+
+// Trilinear interpolation of the cell-centred vorticity W (the lift only).
+__device__ __forceinline__ double3 vorticity_at(const DevParams& P, const DevArrays& A, double x,
+                                             double y, double z) {
+  const Corners q = corners_at(P, x, y, z);
+  double3 o = make_double3(0.0, 0.0, 0.0);
+#pragma unroll 1
+  for (int r = 0; r < 8; ++r) {
+    const int ii = (r & 1) ? q.i1 : q.i0, jj = (r & 2) ? q.j1 : q.j0, kk = (r & 4) ? q.k1 : q.k0;
+    const double w = ((r & 1) ? q.fx : 1.0 - q.fx) * ((r & 2) ? q.fy : 1.0 - q.fy) *
+                     ((r & 4) ? q.fz : 1.0 - q.fz);
+    const double4 v = A.W[(kk * P.ny + jj) * P.nx + ii];
+    o.x += w * v.x;
+    o.y += w * v.y;
+    o.z += w * v.z;
+  }
+  return o;
 }
 
 // One wall of particle i: side -1 bottom (n = -z), +1 top (n = +z).  The
@@ -434,7 +465,19 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
       Fa = cvt<R>(ca * (dux - ai.x), ca * (duy - ai.y), ca * (duz - ai.z));
     }
   }
-  const V3<R> F = Fc + Fl + Fd + Fp + Fa;
+  // shear lift C_l rho_f nu^(1/2) d^2 |omega|^(-1/2) (U_f - u_p) x omega
+  V3<R> Fy{0, 0, 0};
+  if (P.lift_c > 0.0) {
+    const double3 om = vorticity_at(P, A, pi.x, pi.y, pi.z);
+    const double on = sqrt(om.x * om.x + om.y * om.y + om.z * om.z);
+    if (on > 0.0) {
+      const double cl = P.lift_c * d * d / sqrt(on);
+      const double sx = Ux - vi.x, sy = Uy - vi.y, sz = Uz - vi.z;
+      Fy = cvt<R>(cl * (sy * om.z - sz * om.y), cl * (sz * om.x - sx * om.z),
+                  cl * (sx * om.y - sy * om.x));
+    }
+  }
+  const V3<R> F = Fc + Fl + Fd + Fp + Fa + Fy;
   const double im = 1.0 / mi;
   const double II = 0.4 * mi * ri * ri;
   const double4 an = make_double4((double)F.x * im + P.gx, (double)F.y * im + P.gy,
@@ -472,6 +515,7 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
     c[(size_t)5 * N + i] = make_double4((double)F.x + mi * P.gx, (double)F.y + mi * P.gy,
                                         (double)F.z + mi * P.gz, 0.0);
     c[(size_t)6 * N + i] = make_double4(T.x, T.y, T.z, 0.0);
+    c[(size_t)7 * N + i] = make_double4(Fy.x, Fy.y, Fy.z, 0.0);
   }
 }
 

@@ -152,7 +152,7 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
   a.cid = w.take<int>((size_t)kMaxContacts * N);
   a.cxi = w.take<double>(3 * (size_t)kMaxContacts * N);
   a.ccnt = w.take<int>(N);
-  a.comp = w.take<double4>(7 * N);
+  a.comp = w.take<double4>(8 * N);
   a.key = w.take<int>(N);
   a.rank = w.take<int>(N);
   a.perm = w.take<int>(N);
@@ -165,6 +165,7 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
   a.gp = w.take<double4>(nc);
   a.du = w.take<double4>(nc);
   a.G = w.take<double4>(nc);
+  a.W = w.take<double4>(c->prm.c_lift > 0 ? nc : 0);
   a.raw = w.take<double>(4 * nc);
   a.smooth = w.take<double>(4 * nc);
   a.sx = w.take<double>(4 * nc);
@@ -240,6 +241,8 @@ int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
     return fail(c, SEDIMI_EINVAL, "max_neighbors must be in 1..30");
   if (p.nn_enable && !(p.nn_alpha >= 0 && p.nn_bound > 0 && p.nn_sample > 0 && p.nn_sample <= 1))
     return fail(c, SEDIMI_EINVAL, "surrogate parameters out of range");
+  if (!(p.c_lift >= 0 && std::isfinite(p.c_lift)))
+    return fail(c, SEDIMI_EINVAL, "c_lift must be finite and >= 0");
   if (!(p.avg_bandwidth_z >= 0 && std::isfinite(p.avg_bandwidth_z)))
     return fail(c, SEDIMI_EINVAL, "avg_bandwidth_z must be finite and >= 0");
   if (p.avg_solver < SEDIMI_SOLVE_AUTO || p.avg_solver > SEDIMI_SOLVE_ITERATIVE)
@@ -275,6 +278,7 @@ void fill_dev_params(sedimi_ctx* c) {
   P.fluid_forces = p.fluid_forces ? 1 : 0;
   P.bottom_wall = p.bottom_wall ? 1 : 0, P.top_wall = p.top_wall ? 1 : 0;
   P.eps_s_max = p.eps_s_max;
+  P.lift_c = p.c_lift > 0 ? p.c_lift * p.rho_f * sqrt(p.mu_f / p.rho_f) : 0.0;
   P.kz_diff = 1.0;
   if (p.avg_bandwidth_z > 0 && p.avg_bandwidth > 0) {
     const double r = p.avg_bandwidth_z / p.avg_bandwidth;
@@ -614,6 +618,33 @@ int sedimi_set_fluid(sedimi_ctx* c, const double* U, const double* gp, const dou
     h[k] = make_double4(-g[0] + ca * m[0], -g[1] + ca * m[1], -g[2] + ca * m[2], 0.0);
   }
   HIPCHK(c, hipMemcpyAsync(c->A.G, h.data(), sizeof(double4) * nc, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->prm.c_lift > 0) {
+    // vorticity of the frozen flow at cell centres (central differences,
+    // periodic in x and y, one-sided in the first and last z cell), read by
+    // the shear lift
+    const DevParams& P = c->P;
+    const int nx = P.nx, ny = P.ny, nz = P.nz;
+    auto u = [&](int i, int j, int k, int a) {
+      return U ? U[3 * (((size_t)k * ny + j) * nx + i) + a] : 0.0;
+    };
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+          const int ip = (i + 1) % nx, im = (i + nx - 1) % nx;
+          const int jp = (j + 1) % ny, jm = (j + ny - 1) % ny;
+          const int kp = std::min(k + 1, nz - 1), km = std::max(k - 1, 0);
+          double gx[3], gy[3], gz[3];
+          for (int a = 0; a < 3; ++a) {
+            gx[a] = (u(ip, j, k, a) - u(im, j, k, a)) / (2.0 * P.hx);
+            gy[a] = (u(i, jp, k, a) - u(i, jm, k, a)) / (2.0 * P.hy);
+            gz[a] = kp > km ? (u(i, j, kp, a) - u(i, j, km, a)) / ((kp - km) * P.hz) : 0.0;
+          }
+          h[((size_t)k * ny + j) * nx + i] =
+              make_double4(gy[2] - gz[1], gz[0] - gx[2], gx[1] - gy[0], 0.0);
+        }
+    HIPCHK(c, hipMemcpyAsync(c->A.W, h.data(), sizeof(double4) * nc, hipMemcpyHostToDevice, c->stream));
+  }
   launch_pack_eps(c->P, c->A, c->stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -785,7 +816,7 @@ int sedimi_get_particles(sedimi_ctx* c, double* x, double* v, double* w, double*
 int sedimi_get_forces(sedimi_ctx* c, int comp, double* f) {
   int rc = need_particles(c);
   if (rc) return rc;
-  if (comp < 0 || comp > 6 || !f) return fail(c, SEDIMI_EINVAL, "bad force component");
+  if (comp < 0 || comp > SEDIMI_F_LIFT || !f) return fail(c, SEDIMI_EINVAL, "bad force component");
   const size_t n = (size_t)c->n;
   std::vector<int> id;
   rc = download(c, id, c->A.id, n);

@@ -82,6 +82,7 @@ struct DevParams {
   int drag_law, lubrication, fluid_forces, bottom_wall, top_wall;
   double eps_s_max;
   double kz_diff;  // diffusivity of the averaging along z (1: isotropic)
+  double lift_c;   // C_l rho_f nu^(1/2) of the shear lift (0: no lift)
   // neighbour bins
   int nbx, nby, nbz, nbins;
   double hbx, hby, hbz;
@@ -109,6 +110,7 @@ struct DevArrays {
   // mesh
   double4 *U, *gp, *du;  // U.w = averaged solid fraction
   double4* G;            // -grad p + C_add rho_f DU/Dt (step kernel)
+  double4* W;            // curl U_f at cell centres (only with the lift)
   double *raw, *smooth, *sx, *sr, *sd0, *sd1;
   double *sxf, *stmp;  // solver: FP32 iterate (mixed mode), column-sweep scratch
   double* ztab;        // z-line preconditioner: reciprocal pivots, super-diagonal

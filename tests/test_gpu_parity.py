@@ -84,9 +84,9 @@ def _force_parity(orc, case, precision, tol, seed):
     g.compute_forces(update_history=True)
     m = case["rho"] * math.pi / 6 * case["d"] ** 3
     scale = sum(np.linalg.norm(comps[k], axis=1) for k in
-                ("contact", "lub", "drag", "pressure", "added")) + m * 9.81
+                ("contact", "lub", "drag", "pressure", "added", "lift")) + m * 9.81
     worst = {}
-    for k in ("contact", "lub", "drag", "pressure", "added", "total"):
+    for k in ("contact", "lub", "drag", "pressure", "added", "lift", "total"):
         e = rel_err(g.get_forces(k), comps[k], scale)
         worst[k] = float(e.max())
     r = 0.5 * case["d"]
@@ -123,6 +123,23 @@ def test_forces_syamlal_drag(orc, precision, tol):
     case["params"] = dict(case["params"], drag_law="syamlal")
     worst = _force_parity(orc, case, precision, tol, 8)
     assert worst["drag"] < tol
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 1e-5)])
+def test_forces_shear_lift(orc, precision, tol):
+    """Saffman's shear lift with C_l = 1.6: the log-law flow over the bed
+    with fluctuations has vorticity in every direction, so the discrete curl,
+    its interpolation and the cross product are all exercised."""
+    case = dense_bed(3000, 9)
+    case["params"] = dict(case["params"], c_lift=1.6)
+    worst = _force_parity(orc, case, precision, tol, 9)
+    g = gpu_context(case, precision=precision)
+    g.compute_forces()
+    lift = g.get_forces("lift")
+    drag = g.get_forces("drag")
+    # the lift is on and not negligible next to the drag
+    assert np.linalg.norm(lift, axis=1).max() > 1e-3 * np.linalg.norm(drag, axis=1).max()
+    assert worst["lift"] < tol
 
 
 def test_deposit_bit_exact_and_smooth(orc):
