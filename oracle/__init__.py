@@ -93,6 +93,9 @@ def lib():
         L.orc_init_accel.argtypes = [pp, i64, P, P, P, P, P, P, P, P, P, P, P, P, P, i64]
         L.orc_deposit.argtypes = [pp, i64, P, P, P, P]
         L.orc_diffuse.argtypes = [pp, C.c_int, P, P, C.POINTER(i64)]
+        L.orc_deposit_flux.argtypes = [pp, i64, P, P, P, P]
+        L.orc_solid_velocity.argtypes = [i64, P, P, P]
+        L.orc_solid_velocity.restype = None
         L.orc_apply_A.argtypes = [pp, C.c_double, P, P]
         L.orc_apply_A.restype = None
         if hasattr(L, "orc_conv3d_fwd"):
@@ -268,6 +271,31 @@ def deposit(prm, x, d, fdrag=None):
     _check(lib().orc_deposit(C.byref(p), x.shape[0], _ptr(x), _ptr(d), _ptr(fd), _ptr(raw)),
            "deposit")
     return raw
+
+
+def deposit_flux(prm, x, d, v):
+    """Solid volume flux [3, ncell]: sum V_p u_p / V_c per cell."""
+    p = make_params(prm)
+    x = _f64(x, (-1, 3))
+    d = _f64(d)
+    v = _f64(v, (-1, 3))
+    ncell = prm["nx"] * prm["ny"] * prm["nz"]
+    flux = np.zeros((3, ncell))
+    _check(lib().orc_deposit_flux(C.byref(p), x.shape[0], _ptr(x), _ptr(d), _ptr(v),
+                                  _ptr(flux)), "deposit_flux")
+    return flux
+
+
+US_EPS_MIN = 1e-9
+
+
+def solid_velocity(eps_s, flux):
+    """U_s [3, ncell] = flux / eps_s where eps_s > US_EPS_MIN, else 0."""
+    eps_s = _f64(eps_s)
+    flux = _f64(flux).reshape(3, -1)
+    us = np.zeros_like(flux)
+    lib().orc_solid_velocity(eps_s.size, _ptr(eps_s), _ptr(flux), _ptr(us))
+    return us
 
 
 def diffuse(prm, raw):

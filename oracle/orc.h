@@ -128,6 +128,15 @@ int orc_init_accel(const orc_params* p, int64_t n, const double* x, const double
 /* raw [4][ncell]: channel 0 = sum V_p / V_c, channels 1..3 = sum f_drag / V_c */
 int orc_deposit(const orc_params* p, int64_t n, const double* x, const double* d,
                 const double* fdrag, double* raw);
+/* flux [3][ncell]: sum V_p u_p / V_c, the solid volume flux eps_s U_s of the
+ * continuity equation, deposited like the solid fraction (same cells, ID
+ * order). */
+int orc_deposit_flux(const orc_params* p, int64_t n, const double* x, const double* d,
+                     const double* v, double* flux);
+/* U_s [3][ncell] = flux / eps_s from the smoothed fields, where eps_s exceeds
+ * ORC_US_EPS_MIN; 0 elsewhere (no solid there to carry a velocity). */
+#define ORC_US_EPS_MIN 1e-9
+void orc_solid_velocity(int64_t ncell, const double* eps_s, const double* flux, double* us);
 /* Smooth nch channels [nch][ncell] by avg_ntau backward-Euler steps of the
  * diffusion equation up to pseudo-time b^2/4.  iters (may be NULL) receives the
  * total CG iteration count.  Returns 0, or -3 if CG failed to converge. */

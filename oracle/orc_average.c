@@ -10,6 +10,13 @@
  *    stored is the force on the particles.  Sums run in particle-ID order.
  *    A centre on a cell face belongs to the upper cell; centres outside the
  *    mesh are clamped into the first/last cell.
+ *  - The solid velocity U_s (Section 2.4 smooths it with the same procedure):
+ *    the continuity equation carries the product eps_s U_s, so the particle
+ *    volume flux sum V_p u_p / V_c is deposited like the solid fraction and
+ *    smoothed like it, and U_s is the ratio of the two smoothed fields.  The
+ *    weights are particle volumes (equal to mass weights for one particle
+ *    density).  Where the smoothed eps_s is at rounding level the ratio
+ *    means nothing and U_s is set to 0.
  *  - Eq. (12): the deposited field then diffuses with unit diffusivity up to
  *    pseudo-time tau = b^2/4 (b = bandwidth; the paper states the equivalence
  *    to Gaussian averaging with bandwidth sqrt(4 tau)).  The application
@@ -57,6 +64,33 @@ int orc_deposit(const orc_params* p, int64_t n, const double* x, const double* d
   }
   for (int64_t k = 0; k < 4 * ncell; ++k) raw[k] /= Vc;
   return 0;
+}
+
+int orc_deposit_flux(const orc_params* p, int64_t n, const double* x, const double* d,
+                     const double* v, double* flux) {
+  int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
+  double hx = p->Lx / p->nx, hy = p->Ly / p->ny, hz = p->Lz / p->nz;
+  double Vc = hx * hy * hz;
+  memset(flux, 0, sizeof(double) * 3 * (size_t)ncell);
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t a = (int64_t)floor(x[3 * i] / hx);
+    int64_t b = (int64_t)floor(x[3 * i + 1] / hy);
+    int64_t c = (int64_t)floor(x[3 * i + 2] / hz);
+    a = a < 0 ? 0 : (a >= p->nx ? p->nx - 1 : a);
+    b = b < 0 ? 0 : (b >= p->ny ? p->ny - 1 : b);
+    c = c < 0 ? 0 : (c >= p->nz ? p->nz - 1 : c);
+    int64_t k = (c * p->ny + b) * p->nx + a;
+    double V = (M_PI / 6.0) * d[i] * d[i] * d[i];
+    for (int e = 0; e < 3; ++e) flux[e * ncell + k] += V * v[3 * i + e];
+  }
+  for (int64_t k = 0; k < 3 * ncell; ++k) flux[k] /= Vc;
+  return 0;
+}
+
+void orc_solid_velocity(int64_t ncell, const double* eps_s, const double* flux, double* us) {
+  for (int64_t k = 0; k < ncell; ++k)
+    for (int e = 0; e < 3; ++e)
+      us[e * ncell + k] = eps_s[k] > ORC_US_EPS_MIN ? flux[e * ncell + k] / eps_s[k] : 0.0;
 }
 
 /* y = (I - dtau L_h) x.  L_h sums, over the six faces of a cell, the

@@ -204,3 +204,74 @@ def test_point_source_variance_grows_by_b2_over_2_per_axis(orc, bz_over_b):
     assert abs(var_y - b * b / 2) < 1e-9 * b * b
     bz = bz_over_b * b
     assert abs(var_z - bz * bz / 2) < 1e-9 * b * b
+
+
+def _us_case(seed, n=400, uniform=None):
+    """A small bed of spheres in the lower half of a 12 x 10 x 16 mesh with
+    random (or uniform) velocities."""
+    prm = mesh_prm(12, 10, 16)
+    rng = np.random.default_rng(seed)
+    x = rng.random((n, 3)) * [prm["Lx"], prm["Ly"], 0.5 * prm["Lz"]]
+    d = rng.uniform(0.3e-3, 0.8e-3, n)
+    v = np.tile(uniform, (n, 1)) if uniform is not None else rng.normal(size=(n, 3))
+    return prm, x, d, v
+
+
+def _smoothed_us(orc, prm, x, d, v):
+    raw = np.concatenate([orc.deposit(prm, x, d)[:1], orc.deposit_flux(prm, x, d, v)])
+    sm, _ = orc.diffuse(prm, raw)
+    return raw, sm, orc.solid_velocity(sm[0], sm[1:])
+
+
+def test_solid_velocity_of_a_uniform_motion_is_that_velocity(orc):
+    """All particles moving with one velocity: the flux is that velocity
+    times the solid fraction in every cell before and after the (linear)
+    smoothing, so U_s equals it wherever there is solid; a transposed
+    component or a wrong weight breaks the equality."""
+    u0 = np.array([0.31, -0.07, 0.0123])
+    prm, x, d, v = _us_case(5, uniform=u0)
+    raw, sm, us = _smoothed_us(orc, prm, x, d, v)
+    for e in range(3):
+        assert np.max(np.abs(raw[1 + e] - u0[e] * raw[0])) < 1e-14 * raw[0].max()
+    solid = sm[0] > 1e-6
+    assert solid.sum() > 0.5 * solid.size
+    for e in range(3):
+        assert np.max(np.abs(us[e][solid] - u0[e])) < 1e-10 * abs(u0).max()
+    assert np.all(us[:, sm[0] <= orc.US_EPS_MIN] == 0.0)
+
+
+def test_solid_flux_conserves_momentum_and_stays_within_particle_velocities(orc):
+    """sum over cells of flux V_c is the total particle volume flux, before
+    and after the smoothing (zero-flux walls, periodic sides); the smoothing
+    operator is a nonnegative matrix with unit column sums, so each cell's
+    U_s is a convex combination of particle velocities."""
+    prm, x, d, v = _us_case(6)
+    raw, sm, us = _smoothed_us(orc, prm, x, d, v)
+    Vc = prm["Lx"] / prm["nx"] * prm["Ly"] / prm["ny"] * prm["Lz"] / prm["nz"]
+    Vp = math.pi / 6 * d ** 3
+    total = (Vp[:, None] * v).sum(axis=0)
+    scale = (Vp[:, None] * np.abs(v)).sum(axis=0)
+    for e in range(3):
+        assert abs(raw[1 + e].sum() * Vc - total[e]) < 1e-13 * scale[e]
+        assert abs(sm[1 + e].sum() * Vc - total[e]) < 1e-12 * scale[e]
+    solid = sm[0] > 1e-6
+    for e in range(3):
+        lo, hi = v[:, e].min(), v[:, e].max()
+        assert np.all(us[e][solid] >= lo - 1e-9) and np.all(us[e][solid] <= hi + 1e-9)
+
+
+def test_solid_velocity_single_particle_and_cell_sums(orc):
+    """One sphere: the flux sits in its cell only, equal to V_p u / V_c; two
+    spheres in one cell with opposite velocities and equal sizes cancel."""
+    prm = mesh_prm(4, 4, 4, L=(4e-3, 4e-3, 4e-3))
+    Vc = 1e-9
+    d = np.array([0.5e-3])
+    u = np.array([[0.2, -0.4, 1.5]])
+    f = orc.deposit_flux(prm, np.array([[1.5e-3, 2.0e-3, 3.0e-3]]), d, u)
+    cell = (3 * 4 + 2) * 4 + 1
+    assert list(np.flatnonzero(f[0])) == [cell]
+    Vp = math.pi / 6 * 0.5e-3 ** 3
+    assert f[:, cell] == pytest.approx(Vp * u[0] / Vc, rel=1e-14)
+    f2 = orc.deposit_flux(prm, np.array([[0.2e-3, 0.3e-3, 0.4e-3], [0.7e-3, 0.6e-3, 0.5e-3]]),
+                          np.array([0.5e-3, 0.5e-3]), np.array([[1.0, 2.0, 3.0], [-1.0, -2.0, -3.0]]))
+    assert np.all(f2 == 0.0)
