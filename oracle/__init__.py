@@ -53,6 +53,7 @@ class orc_params(C.Structure):
         ("eps_s_max", C.c_double),
         ("avg_bandwidth", C.c_double), ("avg_ntau", C.c_int), ("cg_rtol", C.c_double),
         ("avg_bandwidth_z", C.c_double), ("c_lift", C.c_double),
+        ("avg_scheme", C.c_int),
     ]
 
 

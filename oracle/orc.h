@@ -56,6 +56,7 @@ typedef struct {
   double cg_rtol;            /* CG relative residual tolerance */
   double avg_bandwidth_z;    /* bandwidth along z (m); 0: avg_bandwidth */
   double c_lift;             /* lift coefficient C_l of Eq. (particleLift); 0: no lift */
+  int avg_scheme;            /* pseudo-time scheme: ORC_SCHEME_EULER or ORC_SCHEME_BDF2 */
 } orc_params;
 
 /* One tangential-history record.  Particle pairs carry i < j (IDs); a wall
@@ -137,6 +138,8 @@ int orc_deposit_flux(const orc_params* p, int64_t n, const double* x, const doub
  * ORC_US_EPS_MIN; 0 elsewhere (no solid there to carry a velocity). */
 #define ORC_US_EPS_MIN 1e-9
 void orc_solid_velocity(int64_t ncell, const double* eps_s, const double* flux, double* us);
+#define ORC_SCHEME_EULER 0 /* backward Euler steps */
+#define ORC_SCHEME_BDF2 1  /* second-order backward differences (first step Euler) */
 /* Smooth nch channels [nch][ncell] by avg_ntau backward-Euler steps of the
  * diffusion equation up to pseudo-time b^2/4.  iters (may be NULL) receives the
  * total CG iteration count.  Returns 0, or -3 if CG failed to converge. */

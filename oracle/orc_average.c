@@ -26,9 +26,14 @@
  *    second-order central finite-volume Laplacian on the CFD mesh (Section
  *    2.5), periodic in x and y, zero flux through the walls at z = 0 and Lz
  *    (the no-flux wall condition of Section 2.4).  Time: avg_ntau implicit
- *    (backward Euler) steps of dtau = tau/avg_ntau, each solved by plain
- *    conjugate gradients from the previous field to a relative residual of
- *    cg_rtol.
+ *    steps of dtau = tau/avg_ntau, each solved by plain conjugate gradients
+ *    from its right-hand side to a relative residual of cg_rtol.  Backward
+ *    Euler by default: (I - dtau L) phi^{m+1} = phi^m.  The paper names a
+ *    second-order implicit scheme without giving it; avg_scheme = BDF2 takes
+ *    the two-step backward difference formula
+ *    (3 phi^{m+1} - 4 phi^m + phi^{m-1}) / (2 dtau) = L phi^{m+1},
+ *    i.e. (I - (2/3) dtau L) phi^{m+1} = (4 phi^m - phi^{m-1}) / 3, started
+ *    by one backward-Euler step.
  */
 #include "orc.h"
 
@@ -170,9 +175,11 @@ int orc_diffuse(const orc_params* p, int nch, const double* in, double* out, int
   double* r = (double*)malloc(sizeof(double) * (size_t)n);
   double* pv = (double*)malloc(sizeof(double) * (size_t)n);
   double* Ap = (double*)malloc(sizeof(double) * (size_t)n);
+  double* prev = (double*)malloc(sizeof(double) * (size_t)n);
+  const int bdf2 = p->avg_scheme == ORC_SCHEME_BDF2;
   int rc = 0;
   if (iters) *iters = 0;
-  if (!cur || !r || !pv || !Ap) {
+  if (!cur || !r || !pv || !Ap || !prev) {
     rc = -2;
     goto out;
   }
@@ -181,13 +188,20 @@ int orc_diffuse(const orc_params* p, int nch, const double* in, double* out, int
     double* dst = out + (size_t)ch * n;
     memcpy(cur, src, sizeof(double) * (size_t)n);
     for (int m = 0; m < ntau; ++m) {
-      rc = cg_solve(p, dtau, cur, dst, iters, r, pv, Ap);
+      if (bdf2 && m > 0) {
+        /* right-hand side (4 phi^m - phi^{m-1}) / 3 into prev, then solve */
+        for (int64_t k = 0; k < n; ++k) prev[k] = (4.0 * cur[k] - prev[k]) / 3.0;
+        rc = cg_solve(p, (2.0 / 3.0) * dtau, prev, dst, iters, r, pv, Ap);
+      } else {
+        rc = cg_solve(p, dtau, cur, dst, iters, r, pv, Ap);
+      }
       if (rc) goto out;
+      memcpy(prev, cur, sizeof(double) * (size_t)n);
       memcpy(cur, dst, sizeof(double) * (size_t)n);
     }
     if (ntau == 0) memcpy(dst, cur, sizeof(double) * (size_t)n);
   }
 out:
-  free(cur), free(r), free(pv), free(Ap);
+  free(cur), free(r), free(pv), free(Ap), free(prev);
   return rc;
 }

@@ -88,7 +88,7 @@ def base_params(**kw):
         rho_f=RHO_F, mu_f=MU_F, c_add=0.5, gx=0.0, gy=0.0, gz=-9.81, dt=1.0e-5,
         drag_law="difelice", lubrication=1, fluid_forces=1, bottom_wall=1, top_wall=1,
         eps_s_max=0.7, avg_bandwidth=3 * D50, avg_ntau=4, cg_rtol=1e-14,
-        avg_bandwidth_z=0.0, c_lift=0.0,
+        avg_bandwidth_z=0.0, c_lift=0.0, avg_scheme=0,
     )
     p.update(kw)
     return p
