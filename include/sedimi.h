@@ -76,10 +76,16 @@ extern "C" {
 #define SEDIMI_F_TORQUE 6   /* contact torque */
 #define SEDIMI_F_LIFT 7     /* shear lift (zero unless c_lift > 0) */
 
-/* mesh fields for sedimi_get_field / sedimi_set_field, each [4][ncell] */
+/* mesh fields for sedimi_get_field / sedimi_set_field.  RAW and SMOOTH are
+ * [nch][ncell] with nch = 4 (solid fraction, drag density x, y, z), or 7 when
+ * avg_solid_velocity is set (channels 4..6: the solid volume flux
+ * eps_s U_s = sum V_p u_p / V_c). */
 #define SEDIMI_FIELD_RAW 0    /* deposited, before smoothing (Eq. 11) */
 #define SEDIMI_FIELD_SMOOTH 1 /* after the diffusion solve (Eq. 12); channel 0
                                  is the solid fraction the drag reads */
+#define SEDIMI_FIELD_US 2     /* get only, [3][ncell]: the solid velocity U_s,
+                                 smoothed flux / smoothed eps_s where eps_s
+                                 > 1e-9, else 0 (avg_solid_velocity only) */
 
 typedef struct sedimi_ctx sedimi_ctx;
 
@@ -130,6 +136,11 @@ typedef struct {
                                 y, one-sided in the first and last z cell, zero with one
                                 z cell) and interpolated like U_f; 1.6 approximates
                                 Saffman's 1.615 */
+  int avg_solid_velocity;    /* nonzero: the averaging also deposits and smooths
+                                the particle volume flux and forms the solid
+                                velocity U_s (Section 2.4); the SMOOTH field
+                                then has 7 channels.  Not with nn_enable (the
+                                network covers the 4 standard channels) */
 } sedimi_params;
 
 /* solvers of the implicit diffusion steps (Eq. 12) */
@@ -194,7 +205,7 @@ int sedimi_set_particles(sedimi_ctx* ctx, int64_t n, const double* x, const doub
 /* Upload the frozen fluid fields (host, [ncell][3] each; NULL = zero). */
 int sedimi_set_fluid(sedimi_ctx* ctx, const double* U, const double* gradp,
                      const double* dudt);
-/* Overwrite a mesh field (host [4][ncell]). */
+/* Overwrite the RAW or SMOOTH mesh field (host [nch][ncell]). */
 int sedimi_set_field(sedimi_ctx* ctx, int field, const double* in);
 /* Translate every particle by (dx, dy) on the periodic axes (positions
  * wrapped into [0, L)); relative positions, neighbour lists and contact
@@ -222,7 +233,8 @@ int sedimi_step(sedimi_ctx* ctx, int nsteps, int average_every);
 int sedimi_average(sedimi_ctx* ctx);
 /* Deposition only (RAW field); flags as sedimi_average. */
 int sedimi_deposit(sedimi_ctx* ctx);
-/* Diffusion solve only: SMOOTH <- smoothed RAW, for channels [0, nch). */
+/* Diffusion solve only: SMOOTH <- smoothed RAW, for channels [0, nch), nch at
+ * most the field's channel count; with all 7 channels U_s is formed too. */
 int sedimi_smooth(sedimi_ctx* ctx, int nch);
 
 /* Read back, in ID order.  Any output pointer may be NULL. */

@@ -24,7 +24,7 @@ FP64, MIXED = 0, 1
 SOLVERS = {"auto": 0, "direct": 1, "iterative": 2}
 FORCE = {"contact": 0, "lub": 1, "drag": 2, "pressure": 3, "added": 4, "total": 5,
          "torque": 6, "lift": 7}
-FIELD_RAW, FIELD_SMOOTH = 0, 1
+FIELD_RAW, FIELD_SMOOTH, FIELD_US = 0, 1, 2
 
 HISTORY_DTYPE = np.dtype([("i", np.int64), ("j", np.int64), ("xi", np.float64, (3,))])
 
@@ -54,6 +54,7 @@ class sedimi_params(C.Structure):
         ("nn_sample", C.c_double), ("nn_seed", C.c_uint64),
         ("avg_solver", C.c_int),
         ("avg_bandwidth_z", C.c_double), ("c_lift", C.c_double),
+        ("avg_solid_velocity", C.c_int),
     ]
 
 
@@ -190,6 +191,7 @@ class Sedimi:
         self._chk(self._L.sedimi_set_stream(self._ctx, C.c_void_p(self.stream.cuda_stream)))
         self._chk(self._L.sedimi_bind_workspace(self._ctx, C.c_void_p(aligned), nbytes))
         self.ncell = prm["nx"] * prm["ny"] * prm["nz"]
+        self.nch = 7 if self.params.avg_solid_velocity else 4  # averaged channels
         self.n = 0
 
     # -- plumbing --
@@ -228,7 +230,7 @@ class Sedimi:
         self._chk(self._L.sedimi_set_fluid(self._ctx, _ptr(U), _ptr(gradp), _ptr(dudt)))
 
     def set_field(self, which, arr):
-        arr = _f64(arr).reshape(4, self.ncell)
+        arr = _f64(arr).reshape(self.nch, self.ncell)
         self._chk(self._L.sedimi_set_field(self._ctx, which, _ptr(arr)))
 
     def translate(self, dx, dy):
@@ -250,8 +252,8 @@ class Sedimi:
     def deposit(self):
         self._chk(self._L.sedimi_deposit(self._ctx))
 
-    def smooth(self, nch=4):
-        self._chk(self._L.sedimi_smooth(self._ctx, int(nch)))
+    def smooth(self, nch=None):
+        self._chk(self._L.sedimi_smooth(self._ctx, int(self.nch if nch is None else nch)))
 
     def get_particles(self):
         out = [np.zeros((self.n, 3)) for _ in range(4)]
@@ -265,7 +267,7 @@ class Sedimi:
         return f
 
     def get_field(self, which):
-        out = np.zeros((4, self.ncell))
+        out = np.zeros((3 if which == FIELD_US else self.nch, self.ncell))
         self._chk(self._L.sedimi_get_field(self._ctx, which, _ptr(out)))
         return out
 

@@ -86,7 +86,8 @@ __global__ void k_cellsum(DevParams P, DevArrays A) {
     }
     A.cperm[j + 1] = key;
   }
-  double v = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+  const bool flux = P.nch_avg == 7;
+  double v = 0.0, fx = 0.0, fy = 0.0, fz = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
   for (int i = s; i < e; ++i) {
     const int q = (int)(unsigned)(A.cperm[i] & 0xffffffffull);
     double d = 2.0 * A.pos[q].w;
@@ -96,12 +97,35 @@ __global__ void k_cellsum(DevParams P, DevArrays A) {
     fx += f.x;
     fy += f.y;
     fz += f.z;
+    if (flux) {
+      const double4 u = A.vel[q];
+      qx += V * u.x;
+      qy += V * u.y;
+      qz += V * u.z;
+    }
   }
   const size_t nc = (size_t)P.ncell;
   A.raw[c] = v / P.Vc;
   A.raw[nc + c] = fx / P.Vc;
   A.raw[2 * nc + c] = fy / P.Vc;
   A.raw[3 * nc + c] = fz / P.Vc;
+  if (flux) {
+    A.raw[4 * nc + c] = qx / P.Vc;
+    A.raw[5 * nc + c] = qy / P.Vc;
+    A.raw[6 * nc + c] = qz / P.Vc;
+  }
+}
+
+// Solid velocity: the smoothed volume flux over the smoothed solid fraction,
+// 0 where the fraction is at rounding level.
+__global__ void k_solid_velocity(DevParams P, DevArrays A) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= P.ncell) return;
+  const size_t nc = (size_t)P.ncell;
+  const double es = A.smooth[c];
+  const bool solid = es > kSolidEpsMin;
+#pragma unroll
+  for (int e = 0; e < 3; ++e) A.us[e * nc + c] = solid ? A.smooth[(4 + e) * nc + c] / es : 0.0;
 }
 
 struct Stencil {
@@ -335,38 +359,48 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
 
 // Residual of a smoothed field y against the deposited field on a seeded
 // sample of cells: r = Ay - raw with Ay = A^ntau y.  Per-block FP64 sums of
-// r^2 and y^2 for each of the 4 channels (8 values per block).
-__global__ void k_check(int ncell, const double* __restrict__ Ay, const double* __restrict__ raw,
-                        const double* __restrict__ y, uint64_t seed, uint64_t thresh,
-                        double* __restrict__ part) {
-  __shared__ double s[8][kBlock];
+// r^2 (first nch values) and y^2 (next nch) for each of the nch <= 7
+// channels.
+constexpr int kMaxCh = 7;
+__global__ void k_check(int ncell, int nch, const double* __restrict__ Ay,
+                        const double* __restrict__ raw, const double* __restrict__ y,
+                        uint64_t seed, uint64_t thresh, double* __restrict__ part) {
+  __shared__ double s[2 * kMaxCh][kBlock];
   int c = blockIdx.x * blockDim.x + threadIdx.x;
-  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double v[2 * kMaxCh];
+#pragma unroll
+  for (int q = 0; q < 2 * kMaxCh; ++q) v[q] = 0.0;
   if (c < ncell && splitmix64(seed ^ (uint64_t)c) < thresh) {
-    for (int ch = 0; ch < 4; ++ch) {
+#pragma unroll
+    for (int ch = 0; ch < kMaxCh; ++ch) {
+      if (ch >= nch) break;
       size_t o = (size_t)ch * ncell + c;
       double r = Ay[o] - raw[o];
       v[ch] = r * r;
-      v[4 + ch] = y[o] * y[o];
+      v[kMaxCh + ch] = y[o] * y[o];
     }
   }
-  for (int q = 0; q < 8; ++q) s[q][threadIdx.x] = v[q];
+#pragma unroll
+  for (int q = 0; q < 2 * kMaxCh; ++q) s[q][threadIdx.x] = v[q];
   __syncthreads();
   for (int w = kBlock / 2; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w)
-      for (int q = 0; q < 8; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
+      for (int q = 0; q < 2 * kMaxCh; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0)
-    for (int q = 0; q < 8; ++q) part[(size_t)blockIdx.x * 8 + q] = s[q][0];
+    for (int ch = 0; ch < nch; ++ch) {
+      part[(size_t)blockIdx.x * 2 * nch + ch] = s[ch][0];
+      part[(size_t)blockIdx.x * 2 * nch + nch + ch] = s[kMaxCh + ch][0];
+    }
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
 
-int launch_check(const DevParams& P, DevArrays& A, const double* y, int ntau, double tau,
-                 uint64_t seed, double frac, hipStream_t s) {
+int launch_check(const DevParams& P, DevArrays& A, const double* y, int nch, int ntau,
+                 double tau, uint64_t seed, double frac, hipStream_t s) {
   Stencil S;
   S.nx = P.nx, S.ny = P.ny, S.nz = P.nz, S.ncell = P.ncell;
   double dtau = tau / (ntau > 0 ? ntau : 1);
@@ -374,7 +408,7 @@ int launch_check(const DevParams& P, DevArrays& A, const double* y, int ntau, do
   S.cy = dtau / (P.hy * P.hy);
   S.cz = dtau * P.kz_diff / (P.hz * P.hz);
   const int rows = P.ny * P.nz;
-  dim3 grid((unsigned)((P.nx + kBlock - 1) / kBlock), (unsigned)(rows < 65535 ? rows : 65535), 4);
+  dim3 grid((unsigned)((P.nx + kBlock - 1) / kBlock), (unsigned)(rows < 65535 ? rows : 65535), nch);
   const double* cur = y;
   double* bufs[2] = {A.sd0, A.sd1};
   for (int m = 0; m < ntau; ++m) {
@@ -383,26 +417,30 @@ int launch_check(const DevParams& P, DevArrays& A, const double* y, int ntau, do
   }
   double f = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
   uint64_t thresh = f >= 1.0 ? ~0ull : (uint64_t)(f * 18446744073709551616.0);
-  hipLaunchKernelGGL(k_check, dim3(nblk(P.ncell)), dim3(kBlock), 0, s, P.ncell, cur, A.raw, y,
-                     seed, thresh, A.red);
+  hipLaunchKernelGGL(k_check, dim3(nblk(P.ncell)), dim3(kBlock), 0, s, P.ncell, nch, cur, A.raw,
+                     y, seed, thresh, A.red);
   return (int)nblk(P.ncell);
 }
 
-int read_check(DevArrays& A, int nblocks, double rel[4], hipStream_t s) {
-  std::vector<double> h((size_t)nblocks * 8);
+int read_check(DevArrays& A, int nblocks, int nch, double* rel, hipStream_t s) {
+  std::vector<double> h((size_t)nblocks * 2 * nch);
   if (hipMemcpyAsync(h.data(), A.red, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s) !=
       hipSuccess)
     return -1;
   if (hipStreamSynchronize(s) != hipSuccess) return -1;
-  for (int ch = 0; ch < 4; ++ch) {
+  for (int ch = 0; ch < nch; ++ch) {
     double rr = 0.0, yy = 0.0;
     for (int b = 0; b < nblocks; ++b) {
-      rr += h[(size_t)b * 8 + ch];
-      yy += h[(size_t)b * 8 + 4 + ch];
+      rr += h[(size_t)b * 2 * nch + ch];
+      yy += h[(size_t)b * 2 * nch + nch + ch];
     }
     rel[ch] = yy > 0.0 ? sqrt(rr / yy) : sqrt(rr);
   }
   return 0;
+}
+
+void launch_solid_velocity(const DevParams& P, DevArrays& A, hipStream_t s) {
+  hipLaunchKernelGGL(k_solid_velocity, dim3(nblk(P.ncell)), dim3(kBlock), 0, s, P, A);
 }
 
 void launch_deposit(const DevParams& P, DevArrays& A, hipStream_t s) {

@@ -166,19 +166,21 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
   a.du = w.take<double4>(nc);
   a.G = w.take<double4>(nc);
   a.W = w.take<double4>(c->prm.c_lift > 0 ? nc : 0);
-  a.raw = w.take<double>(4 * nc);
-  a.smooth = w.take<double>(4 * nc);
-  a.sx = w.take<double>(4 * nc);
-  a.sr = w.take<double>(4 * nc);
-  a.sd0 = w.take<double>(4 * nc);
-  a.sd1 = w.take<double>(4 * nc);
-  a.sxf = w.take<double>(4 * nc);
-  a.stmp = w.take<double>(4 * nc);
+  const size_t nch = c->prm.avg_solid_velocity ? 7 : 4;
+  a.raw = w.take<double>(nch * nc);
+  a.smooth = w.take<double>(nch * nc);
+  a.sx = w.take<double>(nch * nc);
+  a.sr = w.take<double>(nch * nc);
+  a.sd0 = w.take<double>(nch * nc);
+  a.sd1 = w.take<double>(nch * nc);
+  a.sxf = w.take<double>(nch * nc);
+  a.stmp = w.take<double>(nch * nc);
+  a.us = w.take<double>(nch == 7 ? 3 * nc : 0);
   a.ztab = w.take<double>(2 * (size_t)c->P.nz);
   a.spec = w.take<double>(c->direct ? spectral_table_doubles(c->P) : 0);
   a.cell_count = w.take<int>(nc + 1);
   a.cell_start = w.take<int>(nc + 1);
-  a.red = w.take<double>(smooth_red_doubles((int)nc, 4, std::max(1, c->prm.avg_ntau)));
+  a.red = w.take<double>(smooth_red_doubles((int)nc, (int)nch, std::max(1, c->prm.avg_ntau)));
   // kept across sedimi_set_particles (which clears everything before U)
   a.bin_rank = w.take<int>(nb);
   a.ctl = w.take<Ctl>(1);
@@ -241,6 +243,8 @@ int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
     return fail(c, SEDIMI_EINVAL, "max_neighbors must be in 1..30");
   if (p.nn_enable && !(p.nn_alpha >= 0 && p.nn_bound > 0 && p.nn_sample > 0 && p.nn_sample <= 1))
     return fail(c, SEDIMI_EINVAL, "surrogate parameters out of range");
+  if (p.avg_solid_velocity && p.nn_enable)
+    return fail(c, SEDIMI_EINVAL, "avg_solid_velocity needs the plain solve (nn_enable off)");
   if (!(p.c_lift >= 0 && std::isfinite(p.c_lift)))
     return fail(c, SEDIMI_EINVAL, "c_lift must be finite and >= 0");
   if (!(p.avg_bandwidth_z >= 0 && std::isfinite(p.avg_bandwidth_z)))
@@ -279,6 +283,7 @@ void fill_dev_params(sedimi_ctx* c) {
   P.bottom_wall = p.bottom_wall ? 1 : 0, P.top_wall = p.top_wall ? 1 : 0;
   P.eps_s_max = p.eps_s_max;
   P.lift_c = p.c_lift > 0 ? p.c_lift * p.rho_f * sqrt(p.mu_f / p.rho_f) : 0.0;
+  P.nch_avg = p.avg_solid_velocity ? 7 : 4;
   P.kz_diff = 1.0;
   if (p.avg_bandwidth_z > 0 && p.avg_bandwidth > 0) {
     const double r = p.avg_bandwidth_z / p.avg_bandwidth;
@@ -377,16 +382,20 @@ int64_t plain_solve(sedimi_ctx* c, int nch) {
   const int ntau = c->prm.avg_ntau;
   double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
   c->last_direct = c->direct && ntau > 0;
+  int64_t it = 0;
   if (c->last_direct) {
     launch_spectral(c->P, c->A, nch, ntau, tau, c->stream);
-    c->check_blocks = launch_check(c->P, c->A, c->A.smooth, ntau, tau, 0, 1.0, c->stream);
-    return 0;
+    c->check_blocks = launch_check(c->P, c->A, c->A.smooth, nch, ntau, tau, 0, 1.0, c->stream);
+  } else {
+    const double rtol = c->mixed ? std::max(c->prm.avg_rtol, 1e-6) : c->prm.avg_rtol;
+    it = launch_smooth(c->P, c->A, nch, ntau, tau, rtol, c->mixed, c->stream);
   }
-  const double rtol = c->mixed ? std::max(c->prm.avg_rtol, 1e-6) : c->prm.avg_rtol;
-  return launch_smooth(c->P, c->A, nch, ntau, tau, rtol, c->mixed, c->stream);
+  // all channels smoothed: the solid velocity follows from the flux
+  if (nch == 7) launch_solid_velocity(c->P, c->A, c->stream);
+  return it;
 }
 
-int64_t do_average_plain(sedimi_ctx* c) { return plain_solve(c, 4); }
+int64_t do_average_plain(sedimi_ctx* c) { return plain_solve(c, c->P.nch_avg); }
 
 // Residual bound of the direct solve: a backward-stable y has
 // |A^N y - raw| <= c eps |A|^N |y| with |A| <= 1 + Delta tau lambda_max.
@@ -415,7 +424,7 @@ int64_t do_average(sedimi_ctx* c, bool* used_plain) {
     ++c->nn_calls;
     plain = false;
     if (c->avg_mode == SEDIMI_AVG_SURROGATE_CHECKED) {
-      double rel[4];
+      double rel[4];  // the network's 4 channels
       int rc = nn_check_smooth(c, rel);
       if (rc) return rc;
       double worst = std::max(std::max(rel[0], rel[1]), std::max(rel[2], rel[3]));
@@ -435,8 +444,8 @@ int64_t do_average(sedimi_ctx* c, bool* used_plain) {
 
 int check_solve(sedimi_ctx* c, int nch) {
   if (c->last_direct) {
-    double rel[4];
-    if (read_check(c->A, c->check_blocks, rel, c->stream))
+    double rel[7];
+    if (read_check(c->A, c->check_blocks, nch, rel, c->stream))
       return fail(c, SEDIMI_EDEVICE, "reading the solver residual failed");
     double res = 0.0;
     for (int ch = 0; ch < nch; ++ch) res = std::max(res, rel[ch]);
@@ -657,7 +666,8 @@ int sedimi_set_field(sedimi_ctx* c, int field, const double* in) {
   if (!in || (field != SEDIMI_FIELD_RAW && field != SEDIMI_FIELD_SMOOTH))
     return fail(c, SEDIMI_EINVAL, "bad field");
   double* dst = field == SEDIMI_FIELD_RAW ? c->A.raw : c->A.smooth;
-  HIPCHK(c, hipMemcpyAsync(dst, in, sizeof(double) * 4 * c->P.ncell, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dst, in, sizeof(double) * c->P.nch_avg * c->P.ncell,
+                           hipMemcpyHostToDevice, c->stream));
   if (field == SEDIMI_FIELD_SMOOTH) launch_pack_eps(c->P, c->A, c->stream);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -752,7 +762,7 @@ int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
   if (rc) return rc;
   rc = flags_to_rc(c, ctl.flags);
   if (rc) return rc;
-  if (averaged) return check_solve(c, 4);
+  if (averaged) return check_solve(c, c->P.nch_avg);
   return SEDIMI_OK;
 }
 
@@ -768,7 +778,7 @@ int sedimi_average(sedimi_ctx* c) {
   if ((rc = read_ctl(c, &ctl))) return rc;
   if ((rc = flags_to_rc(c, ctl.flags))) return rc;
   if (!plain) return SEDIMI_OK;
-  return check_solve(c, 4);
+  return check_solve(c, c->P.nch_avg);
 }
 
 int sedimi_deposit(sedimi_ctx* c) {
@@ -784,7 +794,8 @@ int sedimi_deposit(sedimi_ctx* c) {
 int sedimi_smooth(sedimi_ctx* c, int nch) {
   int rc = need_ws(c);
   if (rc) return rc;
-  if (nch < 1 || nch > 4) return fail(c, SEDIMI_EINVAL, "nch must be 1..4");
+  if (nch < 1 || nch > c->P.nch_avg)
+    return fail(c, SEDIMI_EINVAL, "nch must be 1..4 (1..7 with avg_solid_velocity)");
   c->last_iters = plain_solve(c, nch);
   launch_pack_eps(c->P, c->A, c->stream);
   HIPCHK(c, hipGetLastError());
@@ -834,10 +845,15 @@ int sedimi_get_forces(sedimi_ctx* c, int comp, double* f) {
 int sedimi_get_field(sedimi_ctx* c, int field, double* out) {
   int rc = need_ws(c);
   if (rc) return rc;
-  if (!out || (field != SEDIMI_FIELD_RAW && field != SEDIMI_FIELD_SMOOTH))
+  if (!out || field < SEDIMI_FIELD_RAW || field > SEDIMI_FIELD_US)
     return fail(c, SEDIMI_EINVAL, "bad field");
-  const double* src = field == SEDIMI_FIELD_RAW ? c->A.raw : c->A.smooth;
-  HIPCHK(c, hipMemcpyAsync(out, src, sizeof(double) * 4 * c->P.ncell, hipMemcpyDeviceToHost, c->stream));
+  if (field == SEDIMI_FIELD_US && c->P.nch_avg != 7)
+    return fail(c, SEDIMI_EINVAL, "the solid velocity needs avg_solid_velocity");
+  const double* src = field == SEDIMI_FIELD_RAW ? c->A.raw
+                      : field == SEDIMI_FIELD_SMOOTH ? c->A.smooth : c->A.us;
+  const size_t nch = field == SEDIMI_FIELD_US ? 3 : (size_t)c->P.nch_avg;
+  HIPCHK(c, hipMemcpyAsync(out, src, sizeof(double) * nch * c->P.ncell, hipMemcpyDeviceToHost,
+                           c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return SEDIMI_OK;
 }
@@ -1086,9 +1102,9 @@ void nn_run_forward(sedimi_ctx* c, bool keep) {
 
 int nn_check_smooth(sedimi_ctx* c, double rel[4]) {
   double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
-  int nb = launch_check(c->P, c->A, c->A.smooth, std::max(1, c->prm.avg_ntau), tau,
+  int nb = launch_check(c->P, c->A, c->A.smooth, 4, std::max(1, c->prm.avg_ntau), tau,
                         c->prm.nn_seed, c->prm.nn_sample, c->stream);
-  if (read_check(c->A, nb, rel, c->stream) != 0)
+  if (read_check(c->A, nb, 4, rel, c->stream) != 0)
     return fail(c, SEDIMI_EDEVICE, "reading the residual check failed");
   return SEDIMI_OK;
 }

@@ -32,6 +32,8 @@
 namespace sedimi {
 
 constexpr int kBlock = 256;
+// smoothed solid fraction below which the solid velocity is set to 0
+constexpr double kSolidEpsMin = 1e-9;
 constexpr int kMaxContacts = 16;  // contacts per particle kept across a re-sort
 // Members a neighbour bin / a mesh cell may hold: each is ordered by one
 // thread (insertion sort), so a state that crowds many particles into one
@@ -83,6 +85,7 @@ struct DevParams {
   double eps_s_max;
   double kz_diff;  // diffusivity of the averaging along z (1: isotropic)
   double lift_c;   // C_l rho_f nu^(1/2) of the shear lift (0: no lift)
+  int nch_avg;     // averaged channels: 4, or 7 with the solid volume flux
   // neighbour bins
   int nbx, nby, nbz, nbins;
   double hbx, hby, hbz;
@@ -111,7 +114,8 @@ struct DevArrays {
   double4 *U, *gp, *du;  // U.w = averaged solid fraction
   double4* G;            // -grad p + C_add rho_f DU/Dt (step kernel)
   double4* W;            // curl U_f at cell centres (only with the lift)
-  double *raw, *smooth, *sx, *sr, *sd0, *sd1;
+  double *raw, *smooth, *sx, *sr, *sd0, *sd1;  // [nch_avg][ncell] each
+  double* us;  // solid velocity [3][ncell] (only with the solid flux)
   double *sxf, *stmp;  // solver: FP32 iterate (mixed mode), column-sweep scratch
   double* ztab;        // z-line preconditioner: reciprocal pivots, super-diagonal
   double* spec;        // direct solve: H_x, H_y, C_z, C_z^-1, per-axis eigenvalues
@@ -161,13 +165,15 @@ double read_smooth_residual(const DevParams& P, DevArrays& A, int nch, int ntau,
 size_t smooth_red_doubles(int ncell, int nch, int ntau);
 // Thomas-algorithm table of the z-line preconditioner (2 * nz doubles).
 void smooth_ztab(const DevParams& P, int ntau, double tau, double* host_tab);
-// Residual check of a smoothed field y (4 channels) against raw on a seeded
+// Residual check of a smoothed field y (nch channels) against raw on a seeded
 // sample of cells (fraction frac): r = A^ntau y - raw.  Enqueues the work
 // (partials in A.red, A.sd0/A.sd1 as scratch) and returns the block count;
 // read_check then gives |r|/|y| per channel over the sample (synchronises).
-int launch_check(const DevParams& P, DevArrays& A, const double* y, int ntau, double tau,
-                 uint64_t seed, double frac, hipStream_t s);
-int read_check(DevArrays& A, int nblocks, double rel[4], hipStream_t s);
+int launch_check(const DevParams& P, DevArrays& A, const double* y, int nch, int ntau,
+                 double tau, uint64_t seed, double frac, hipStream_t s);
+int read_check(DevArrays& A, int nblocks, int nch, double* rel, hipStream_t s);
+// U_s = smoothed flux / smoothed solid fraction (channels 4..6 over 0) into A.us.
+void launch_solid_velocity(const DevParams& P, DevArrays& A, hipStream_t s);
 
 // ---- launchers (k_spectral.hip) ----
 // Direct solve of all N_tau implicit steps on the uniform mesh: channels

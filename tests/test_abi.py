@@ -78,6 +78,14 @@ def test_create_checks_parameters(L):
         assert rc == sm.EINVAL and not ctx.value, b
     rc, ctx = create(L, prm, max_neighbors=0)
     assert rc == sm.EINVAL
+    # the network covers the 4 standard channels only
+    rc, ctx = create(L, dict(prm, avg_solid_velocity=1), nn=True)
+    assert rc == sm.EINVAL and not ctx.value
+    rc, ctx = create(L, dict(prm, avg_solid_velocity=1))
+    assert rc == sm.OK
+    n3 = L.sedimi_workspace_bytes(ctx)
+    L.sedimi_destroy(ctx)
+    assert n3 > n1  # three more averaged channels and the solid velocity
     rc, ctx = create(L, prm, cap=-1)
     assert rc == sm.EINVAL
 

@@ -165,6 +165,55 @@ def test_deposit_bit_exact_and_smooth(orc):
 
 
 @pytest.mark.parametrize("solver", ["direct", "iterative"])
+def test_solid_velocity_matches_oracle(orc, solver):
+    """Solid volume flux deposited bit-exactly (same per-cell ID-order sums),
+    the 7 smoothed channels and U_s = flux / eps_s against the oracle."""
+    case = dense_bed(4000, 12)
+    prm = dict(case["params"], avg_solid_velocity=1)
+    case["params"] = prm
+    comps, _ = orc.forces(prm, case["x"], case["v"], case["w"], case["d"], case["rho"],
+                          U=case["U"], gradp=case["gradp"], dudt=case["dudt"])
+    raw_o = np.concatenate([orc.deposit(prm, case["x"], case["d"], comps["drag"]),
+                            orc.deposit_flux(prm, case["x"], case["d"], case["v"])])
+    sm_o, _ = orc.diffuse(prm, raw_o)
+    us_o = orc.solid_velocity(sm_o[0], sm_o[4:])
+    g = gpu_context(case, solver=solver)
+    g.compute_forces()
+    g.average()
+    raw_g, sm_g, us_g = g.get_field(0), g.get_field(1), g.get_field(2)
+    assert raw_g.shape == (7, g.ncell) and us_g.shape == (3, g.ncell)
+    assert np.array_equal(raw_g[0], raw_o[0]) and np.array_equal(raw_g[4:], raw_o[4:])
+    qscale = np.abs(raw_o[4:]).max()
+    assert np.abs(sm_g[4:] - sm_o[4:]).max() < 1e-10 * qscale
+    solid = sm_o[0] > 1e-6
+    vmax = np.abs(case["v"]).max()
+    assert solid.sum() > 100
+    assert np.abs(us_g[:, solid] - us_o[:, solid]).max() < 1e-8 * vmax
+    assert np.all(np.isfinite(us_g)) and np.abs(us_g).max() <= 1.001 * vmax
+    assert np.all(us_g[:, sm_g[0] <= 1e-9] == 0.0)
+    # channel count checks of the boundary
+    import paper_1601_03801_amd as sm
+    with pytest.raises(sm.SedimiError):
+        g.smooth(8)
+
+
+def test_solid_velocity_inside_steps_reads_the_current_velocities(orc):
+    """The averaging inside sedimi_step deposits the velocities at the end of
+    the step: its flux equals the oracle's deposit of the state read back."""
+    case = dense_bed(3000, 13)
+    case["params"] = dict(case["params"], avg_solid_velocity=1)
+    g = gpu_context(case)
+    g.step(4, 2)
+    st = g.get_particles()
+    raw_g, sm_g, us_g = g.get_field(0), g.get_field(1), g.get_field(2)
+    flux_o = orc.deposit_flux(case["params"], st["x"], case["d"], st["v"])
+    assert np.array_equal(raw_g[4:], flux_o)
+    assert not np.array_equal(st["v"], case["v"])  # the velocities did change
+    solid = sm_g[0] > 1e-6
+    assert np.allclose(us_g[:, solid] * sm_g[0, solid], sm_g[4:, solid], rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("solver", ["direct", "iterative"])
 @pytest.mark.parametrize("shape,ntau,bz", [((16, 16, 8), 4, 0.0), ((33, 20, 17), 3, 0.0),
                                            ((64, 32, 48), 4, 0.0), ((1, 5, 70), 2, 0.0),
                                            ((130, 2, 1), 5, 0.0),
