@@ -141,7 +141,17 @@ typedef struct {
                                 velocity U_s (Section 2.4); the SMOOTH field
                                 then has 7 channels.  Not with nn_enable (the
                                 network covers the 4 standard channels) */
+  int avg_scheme;            /* pseudo-time scheme of the averaging (Section 2.4):
+                                SEDIMI_SCHEME_EULER, or SEDIMI_SCHEME_BDF2 (direct
+                                solve only; not with nn_enable) */
 } sedimi_params;
+
+/* avg_scheme: backward Euler, (I - dtau L) phi^{m+1} = phi^m; or the two-step
+ * backward difference formula (I - 2/3 dtau L) phi^{m+1} = (4 phi^m - phi^{m-1})/3,
+ * started by one backward-Euler step (the paper's second-order implicit
+ * scheme) */
+#define SEDIMI_SCHEME_EULER 0
+#define SEDIMI_SCHEME_BDF2 1
 
 /* solvers of the implicit diffusion steps (Eq. 12) */
 #define SEDIMI_SOLVE_AUTO 0      /* direct when every axis has <= 2048 cells */

@@ -327,7 +327,11 @@ __global__ void k_residual(Stencil S, const T* __restrict__ b, const T* __restri
 
 // out = A in for every channel (blockIdx.z), one x-row per block row: the
 // row's (j, k) is uniform across the block, so no lane divides its index.
-__global__ void k_applyA(Stencil S, const double* __restrict__ in, double* __restrict__ out) {
+// COMB: out = alpha A in + beta in + gamma other instead.
+template <bool COMB>
+__global__ void k_applyA(Stencil S, const double* __restrict__ in, double* __restrict__ out,
+                         double alpha, double beta, double gamma,
+                         const double* __restrict__ other) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.nx) return;
   const size_t off = (size_t)blockIdx.z * S.ncell;
@@ -346,7 +350,14 @@ __global__ void k_applyA(Stencil S, const double* __restrict__ in, double* __res
     double lz = 0.0;
     if (k + 1 < S.nz) lz += x[c + plane] - xc;
     if (k > 0) lz += x[c - plane] - xc;
-    out[off + c] = xc - (S.cx * lx + S.cy * ly + S.cz * lz);
+    const double ax = xc - (S.cx * lx + S.cy * ly + S.cz * lz);
+    if (COMB) {
+      double v = alpha * ax + beta * xc;
+      if (other) v += gamma * other[off + c];
+      out[off + c] = v;
+    } else {
+      out[off + c] = ax;
+    }
   }
 }
 
@@ -412,7 +423,8 @@ int launch_check(const DevParams& P, DevArrays& A, const double* y, int nch, int
   const double* cur = y;
   double* bufs[2] = {A.sd0, A.sd1};
   for (int m = 0; m < ntau; ++m) {
-    hipLaunchKernelGGL(k_applyA, grid, dim3(kBlock), 0, s, S, cur, bufs[m & 1]);
+    hipLaunchKernelGGL(k_applyA<false>, grid, dim3(kBlock), 0, s, S, cur, bufs[m & 1], 1.0,
+                       0.0, 0.0, nullptr);
     cur = bufs[m & 1];
   }
   double f = frac < 0.0 ? 0.0 : (frac > 1.0 ? 1.0 : frac);
@@ -437,6 +449,51 @@ int read_check(DevArrays& A, int nblocks, int nch, double* rel, hipStream_t s) {
     rel[ch] = yy > 0.0 ? sqrt(rr / yy) : sqrt(rr);
   }
   return 0;
+}
+
+int launch_check_bdf2(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
+                      hipStream_t s) {
+  Stencil S;
+  S.nx = P.nx, S.ny = P.ny, S.nz = P.nz, S.ncell = P.ncell;
+  const int N = ntau > 0 ? ntau : 1;
+  const double dtau = tau / N;
+  S.cx = dtau / (P.hx * P.hx);
+  S.cy = dtau / (P.hy * P.hy);
+  S.cz = dtau * P.kz_diff / (P.hz * P.hz);
+  const int rows = P.ny * P.nz;
+  dim3 grid((unsigned)((P.nx + kBlock - 1) / kBlock), (unsigned)(rows < 65535 ? rows : 65535), nch);
+  // A = I + M, so (3 + 2M) x = 2 A x + x
+  auto comb = [&](const double* in, double* out, double al, double be, double ga,
+                  const double* other) {
+    hipLaunchKernelGGL(k_applyA<true>, grid, dim3(kBlock), 0, s, S, in, out, al, be, ga, other);
+  };
+  // q_N(M) y: N - 1 factors (3 + 2M), then (1 + M)
+  const double* qy = A.smooth;
+  double* qb[2] = {A.sd0, A.sd1};
+  for (int m = 0; m < N; ++m) {
+    if (m + 1 < N)
+      comb(qy, qb[m & 1], 2.0, 1.0, 0.0, nullptr);
+    else
+      comb(qy, qb[m & 1], 1.0, 0.0, 0.0, nullptr);
+    qy = qb[m & 1];
+  }
+  // p_N(M) raw: p_1 = raw, p_2 = 3 raw - M raw = 4 raw - A raw,
+  // p_{n+1} = 4 p_n - (2 A p_{n-1} + p_{n-1})
+  const double* prev = A.raw;
+  const double* cur = A.raw;
+  double* pool[3] = {A.sx, A.sr, A.stmp};
+  for (int n = 1; n < N; ++n) {
+    double* next = pool[n % 3];
+    if (n == 1)
+      comb(A.raw, next, -1.0, 0.0, 4.0, A.raw);
+    else
+      comb(prev, next, -2.0, -1.0, 4.0, cur);
+    prev = cur;
+    cur = next;
+  }
+  hipLaunchKernelGGL(k_check, dim3(nblk(P.ncell)), dim3(kBlock), 0, s, P.ncell, nch, qy, cur,
+                     (const double*)A.smooth, (uint64_t)0, ~0ull, A.red);
+  return (int)nblk(P.ncell);
 }
 
 void launch_solid_velocity(const DevParams& P, DevArrays& A, hipStream_t s) {

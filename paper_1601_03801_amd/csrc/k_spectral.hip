@@ -31,7 +31,9 @@ namespace {
 constexpr int kTM = 64, kTN = 64, kTK = 16;
 
 // C[b] = alpha * A[b] * B[b] (row-major, FP64), optional spectral epilogue:
-// C[m][j] *= (1 + dtau (lam_m[m] + lam_x[j % nx] + lam_y[j / nx]))^-ntau.
+// with a = dtau (lam_m[m] + lam_x[j % nx] + lam_y[j / nx]), C[m][j] is scaled
+// by (1 + a)^-ntau (backward Euler) or by the BDF2 factor g_ntau(a) of the
+// recurrence g_0 = 1, g_1 = 1 / (1 + a), g_{n+1} = (4 g_n - g_{n-1}) / (3 + 2a).
 struct Gemm {
   const double* A;
   const double* B;
@@ -46,6 +48,7 @@ struct Gemm {
   int nx;
   int ntau;
   double dtau;
+  int bdf2;
 };
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -129,7 +132,18 @@ __global__ __launch_bounds__(256) void k_gemm64(Gemm g) {
         const double lam = g.lam_m[m] + g.lam_x[n % g.nx] + g.lam_y[n / g.nx];
         const double f = 1.0 / (1.0 + g.dtau * lam);
         double p = 1.0;
-        for (int q = 0; q < g.ntau; ++q) p *= f;
+        if (g.bdf2) {
+          const double r = 1.0 / (3.0 + 2.0 * g.dtau * lam);
+          double g0 = 1.0;
+          p = f;
+          for (int q = 1; q < g.ntau; ++q) {
+            const double g2 = (4.0 * p - g0) * r;
+            g0 = p;
+            p = g2;
+          }
+        } else {
+          for (int q = 0; q < g.ntau; ++q) p *= f;
+        }
         v *= p;
       }
       C[(int64_t)m * g.ldc + n] = v;
@@ -192,7 +206,7 @@ void spectral_tables(const DevParams& P, double* t) {
 
 // raw (nch channels) -> smooth, through A.sr / A.stmp.
 void launch_spectral(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
-                     hipStream_t s) {
+                     bool bdf2, hipStream_t s) {
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   const int64_t nc = P.ncell, plane = (int64_t)nx * ny;
   const double* hx = A.spec;
@@ -231,6 +245,7 @@ void launch_spectral(const DevParams& P, DevArrays& A, int nch, int ntau, double
     g.alpha = 1.0;
     g.lam_m = lz, g.lam_x = lx, g.lam_y = ly, g.nx = nx;
     g.ntau = ntau, g.dtau = tau / ntau;
+    g.bdf2 = bdf2 ? 1 : 0;
     gemm(g, nch, spectral, s);
   };
   xpass(A.raw, t0, 1.0);

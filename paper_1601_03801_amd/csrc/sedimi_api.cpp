@@ -243,6 +243,12 @@ int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
     return fail(c, SEDIMI_EINVAL, "max_neighbors must be in 1..30");
   if (p.nn_enable && !(p.nn_alpha >= 0 && p.nn_bound > 0 && p.nn_sample > 0 && p.nn_sample <= 1))
     return fail(c, SEDIMI_EINVAL, "surrogate parameters out of range");
+  if (p.avg_scheme != SEDIMI_SCHEME_EULER && p.avg_scheme != SEDIMI_SCHEME_BDF2)
+    return fail(c, SEDIMI_EINVAL, "unknown averaging scheme");
+  if (p.avg_scheme == SEDIMI_SCHEME_BDF2 &&
+      (p.nn_enable || p.avg_solver == SEDIMI_SOLVE_ITERATIVE ||
+       std::max(p.nx, std::max(p.ny, p.nz)) > kDirectMaxAxis))
+    return fail(c, SEDIMI_EINVAL, "BDF2 averaging needs the direct solve (no nn_enable)");
   if (p.avg_solid_velocity && p.nn_enable)
     return fail(c, SEDIMI_EINVAL, "avg_solid_velocity needs the plain solve (nn_enable off)");
   if (!(p.c_lift >= 0 && std::isfinite(p.c_lift)))
@@ -384,8 +390,11 @@ int64_t plain_solve(sedimi_ctx* c, int nch) {
   c->last_direct = c->direct && ntau > 0;
   int64_t it = 0;
   if (c->last_direct) {
-    launch_spectral(c->P, c->A, nch, ntau, tau, c->stream);
-    c->check_blocks = launch_check(c->P, c->A, c->A.smooth, nch, ntau, tau, 0, 1.0, c->stream);
+    const bool bdf2 = c->prm.avg_scheme == SEDIMI_SCHEME_BDF2;
+    launch_spectral(c->P, c->A, nch, ntau, tau, bdf2, c->stream);
+    c->check_blocks = bdf2 ? launch_check_bdf2(c->P, c->A, nch, ntau, tau, c->stream)
+                           : launch_check(c->P, c->A, c->A.smooth, nch, ntau, tau, 0, 1.0,
+                                          c->stream);
   } else {
     const double rtol = c->mixed ? std::max(c->prm.avg_rtol, 1e-6) : c->prm.avg_rtol;
     it = launch_smooth(c->P, c->A, nch, ntau, tau, rtol, c->mixed, c->stream);
@@ -407,7 +416,12 @@ double direct_tol(const sedimi_ctx* c) {
   if (P.nx > 1) lam += 4.0 / (P.hx * P.hx);
   if (P.ny > 1) lam += 4.0 / (P.hy * P.hy);
   if (P.nz > 1) lam += 4.0 * P.kz_diff / (P.hz * P.hz);
-  return std::max(c->prm.avg_rtol, 1e-13 * pow(1.0 + dtau * lam, (double)ntau));
+  const double a = dtau * lam;
+  // BDF2: the check multiplies y by (I + M)(3 I + 2 M)^(N-1), M = -dtau L
+  const double amp = c->prm.avg_scheme == SEDIMI_SCHEME_BDF2
+                         ? (1.0 + a) * pow(3.0 + 2.0 * a, (double)(ntau - 1))
+                         : pow(1.0 + a, (double)ntau);
+  return std::max(c->prm.avg_rtol, 1e-13 * amp);
 }
 
 // One averaging in the current mode.  Returns the solver iterations (0 when

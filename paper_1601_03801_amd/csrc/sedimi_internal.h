@@ -172,6 +172,13 @@ void smooth_ztab(const DevParams& P, int ntau, double tau, double* host_tab);
 int launch_check(const DevParams& P, DevArrays& A, const double* y, int nch, int ntau,
                  double tau, uint64_t seed, double frac, hipStream_t s);
 int read_check(DevArrays& A, int nblocks, int nch, double* rel, hipStream_t s);
+// The same check for BDF2 steps: y = g_N(M) raw with M = -dtau L and the
+// per-mode BDF2 factor g_N = p_N / q_N, q_N = (1 + M)(3 + 2M)^(N-1),
+// p_1 = 1, p_2 = 3 - M, p_{n+1} = 4 p_n - (3 + 2M) p_{n-1}; the residual is
+// r = q_N(M) y - p_N(M) raw, from stencil products only (A.sx, A.sr, A.stmp,
+// A.sd0, A.sd1 as scratch).
+int launch_check_bdf2(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
+                      hipStream_t s);
 // U_s = smoothed flux / smoothed solid fraction (channels 4..6 over 0) into A.us.
 void launch_solid_velocity(const DevParams& P, DevArrays& A, hipStream_t s);
 
@@ -179,7 +186,7 @@ void launch_solid_velocity(const DevParams& P, DevArrays& A, hipStream_t s);
 // Direct solve of all N_tau implicit steps on the uniform mesh: channels
 // [0, nch) of raw into smooth (A.sr and A.stmp as scratch).
 void launch_spectral(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
-                     hipStream_t s);
+                     bool bdf2, hipStream_t s);
 size_t spectral_table_doubles(const DevParams& P);
 void spectral_tables(const DevParams& P, double* host_tab);
 
