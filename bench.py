@@ -28,22 +28,24 @@ HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
-def averaging_rooflines(n, ncell, dep_ms, smooth_ms, direct, mesh):
+def averaging_rooflines(n, ncell, dep_ms, smooth_ms, direct, mesh, nch=4):
     """Deposition against HBM: algorithmic bytes 88 B per particle (cell key
     32 B read + 8 B written, 8 B scatter, 40 B read by the per-cell sums)
-    plus 32 B per cell written.  Direct solve against the FP64 matrix cores:
-    four channels, a forward and an inverse transform along each axis, so
-    4 (nx + ny + nz) FLOP per cell and channel; its algorithmic HBM minimum
-    (read raw + write smooth, 16 B per cell and channel) is given beside it.
-    The solve time includes its full-field residual check."""
-    dep_bytes = 88 * n + 32 * ncell
+    plus 8 B per cell and channel written; with the solid volume flux (7
+    channels) the per-cell sums also read the velocity, 32 B per particle.
+    Direct solve against the FP64 matrix cores: a forward and an inverse
+    transform along each axis, so 4 (nx + ny + nz) FLOP per cell and channel;
+    its algorithmic HBM minimum (read raw + write smooth, 16 B per cell and
+    channel) is given beside it.  The solve time includes its full-field
+    residual check."""
+    dep_bytes = (88 + (32 if nch == 7 else 0)) * n + 8 * nch * ncell
     dep = {"ms": round(dep_ms, 5), "bytes": int(dep_bytes), "bound": "hbm",
            "achieved_GBps": round(dep_bytes / (dep_ms * 1e-3) / 1e9, 1),
            "frac": round(dep_bytes / (dep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-    min_bytes = 16 * ncell * 4
+    min_bytes = 16 * ncell * nch
     sol = {"ms": round(smooth_ms, 5), "hbm_minimum_ms": round(min_bytes / HBM_PEAK_GBS / 1e6, 5)}
     if direct:
-        flop = 4 * (mesh[0] + mesh[1] + mesh[2]) * ncell * 4
+        flop = 4 * (mesh[0] + mesh[1] + mesh[2]) * ncell * nch
         tf = flop / (smooth_ms * 1e-3) / 1e12
         sol.update({"bound": "mfma_fp64", "gflop": round(flop / 1e9, 3),
                     "achieved_tflops": round(tf, 2), "peak_tflops": FP64_MFMA_PEAK_TFLOPS,
@@ -114,6 +116,12 @@ def main():
     ap.add_argument("--bandwidth-z", type=float, default=0.0,
                     help="averaging bandwidth across the bed in particle diameters "
                          "(0: the same as along it)")
+    ap.add_argument("--lift", type=float, default=0.0,
+                    help="shear-lift coefficient C_l (0: no lift; the paper's value is 1.6)")
+    ap.add_argument("--solid-velocity", action="store_true",
+                    help="also average the solid velocity U_s (7 averaged channels)")
+    ap.add_argument("--scheme", default="euler", choices=["euler", "bdf2"],
+                    help="pseudo-time scheme of the averaging")
     ap.add_argument("--cpu-steps", type=int, default=3, help="oracle steps for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--nn-train-steps", type=int, default=2000,
@@ -142,7 +150,9 @@ def main():
     t0 = time.time()
     w = workloads.workload(args.workload)
     prm = dict(w["params"], drag_law=args.drag,
-               avg_bandwidth_z=args.bandwidth_z * workloads.D50)
+               avg_bandwidth_z=args.bandwidth_z * workloads.D50, c_lift=args.lift,
+               avg_solid_velocity=1 if args.solid_velocity else 0,
+               avg_scheme=1 if args.scheme == "bdf2" else 0)
     n = len(w["d"])
     print(f"bench: workload {args.workload}: {n} spheres, mesh {w['meta']['mesh']}, "
           f"generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
@@ -178,11 +188,12 @@ def main():
     mixed = args.precision == "mixed"
     bpp = force_bytes_per_particle(st["mean_neighbors"], st["mean_contacts"], mixed)
     ncell = prm["nx"] * prm["ny"] * prm["nz"]
-    bytes_launch = n * bpp + ncell * (3 * 32 + 8)
+    bytes_launch = n * bpp + ncell * ((4 if args.lift > 0 else 3) * 32 + 8)
     achieved = bytes_launch / (f_avg * 1e-3) / 1e9
     traffic = None
     if (FORCE_PMC is not None and args.workload == "bed1m" and not mixed
-            and args.drag == "difelice" and FORCE_PMC["sources_sha256"] == force_sources_sha()):
+            and args.drag == "difelice" and args.lift == 0
+            and FORCE_PMC["sources_sha256"] == force_sources_sha()):
         traffic = int(1024 * (FORCE_PMC["fetch_kib"] * FORCE_PMC["fetch_scale"]
                               + FORCE_PMC["write_kib"] * FORCE_PMC["write_scale"]))
     roofline = {"bound": "hbm", "kernel": "k_forces (step)", "achieved": round(achieved, 1),
@@ -196,7 +207,7 @@ def main():
     dep_r, sol_r = averaging_rooflines(
         n, ncell, prof["deposit"][0] / max(prof["deposit"][1], 1),
         prof["smooth"][0] / max(prof["smooth"][1], 1), st["solve_iters"] == 0,
-        w["meta"]["mesh"])
+        w["meta"]["mesh"], g.nch)
     # the particle step alone (drift, gated rebuild chain, forces), per step
     dem_ms = (prof["drift"][0] + prof["rebuild"][0] + prof["forces"][0]) / max(prof["forces"][1], 1)
 
@@ -231,7 +242,8 @@ def main():
         "dtype": "f64" if not mixed else "f64-state/f32-forces", "data": "synthetic",
         "config": {"workload": args.workload, "particles": n, "mesh": w["meta"]["mesh"],
                    "substeps_per_step": S, "average_every": S, "dt": prm["dt"],
-                   "precision": args.precision, "drag": args.drag,
+                   "precision": args.precision, "drag": args.drag, "lift_c": args.lift,
+                   "solid_velocity": args.solid_velocity, "scheme": args.scheme,
                    "avg_bandwidth_m": prm["avg_bandwidth"],
                    "avg_bandwidth_z_m": prm["avg_bandwidth_z"] or prm["avg_bandwidth"],
                    "bed_seed": w["meta"].get("bed_seed"),
