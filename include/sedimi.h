@@ -142,8 +142,8 @@ typedef struct {
                                 then has 7 channels.  Not with nn_enable (the
                                 network covers the 4 standard channels) */
   int avg_scheme;            /* pseudo-time scheme of the averaging (Section 2.4):
-                                SEDIMI_SCHEME_EULER, or SEDIMI_SCHEME_BDF2 (direct
-                                solve only; not with nn_enable) */
+                                SEDIMI_SCHEME_EULER, or SEDIMI_SCHEME_BDF2 (either
+                                solver; not with nn_enable) */
 } sedimi_params;
 
 /* avg_scheme: backward Euler, (I - dtau L) phi^{m+1} = phi^m; or the two-step

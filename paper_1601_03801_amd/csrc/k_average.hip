@@ -539,15 +539,31 @@ static int cheb_iters(double kappa, double pre, double rtol) {
   return k < 1 ? 1 : k;
 }
 
+// BDF2 right-hand side in place: x <- (4 x - prev) / 3, prev <- old x.
 template <typename T>
-static int64_t smooth_impl(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
-                           double rtol, hipStream_t s) {
+__global__ void k_bdf2_rhs(size_t n, T* __restrict__ x, T* __restrict__ prev) {
+  size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double t = (double)x[k];
+  x[k] = (T)((4.0 * t - (double)prev[k]) / 3.0);
+  prev[k] = (T)t;
+}
+
+// Chebyshev set-up for (I - dt L_h) at one pseudo-time step size dt.
+struct ChebPlan {
   Stencil S;
+  bool line;
+  int kiter;
+  double theta, delta;
+};
+
+static ChebPlan cheb_plan(const DevParams& P, int nch, double dt, double rtol) {
+  ChebPlan p;
+  Stencil& S = p.S;
   S.nx = P.nx, S.ny = P.ny, S.nz = P.nz, S.ncell = P.ncell;
-  double dtau = tau / ntau;
-  S.cx = dtau / (P.hx * P.hx);
-  S.cy = dtau / (P.hy * P.hy);
-  S.cz = dtau * P.kz_diff / (P.hz * P.hz);
+  S.cx = dt / (P.hx * P.hx);
+  S.cy = dt / (P.hy * P.hy);
+  S.cz = dt * P.kz_diff / (P.hz * P.hz);
   const double axy = 4.0 * ((P.nx > 1 ? S.cx : 0.0) + (P.ny > 1 ? S.cy : 0.0));
   const double az = 4.0 * (P.nz > 1 ? S.cz : 0.0);
   const double kappaA = 1.0 + axy + az;
@@ -562,27 +578,55 @@ static int64_t smooth_impl(const DevParams& P, DevArrays& A, int nch, int ntau, 
   const double lanes = (double)P.nx * P.ny * nch;
   const double t_plain = k_plain * 6.0 / 5.0;
   const double t_line = k_line * 9.0 / (lanes >= 131072.0 ? 3.6 : 2.0);
-  const bool line = t_line < t_plain;
-  const double lmin = 1.0, lmax = line ? 1.0 + axy : kappaA;
-  const int kiter = line ? k_line : k_plain;
-  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+  p.line = t_line < t_plain;
+  const double lmin = 1.0, lmax = p.line ? 1.0 + axy : kappaA;
+  p.kiter = p.line ? k_line : k_plain;
+  p.theta = 0.5 * (lmax + lmin);
+  p.delta = 0.5 * (lmax - lmin);
+  return p;
+}
+
+template <typename T>
+static int64_t smooth_impl(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
+                           double rtol, bool bdf2, hipStream_t s) {
+  const double dtau = tau / ntau;
+  // backward Euler (and BDF2's first step) at dtau; later BDF2 steps solve
+  // (I - 2/3 dtau L_h) with the second z-line table
+  const ChebPlan plans[2] = {cheb_plan(P, nch, dtau, rtol),
+                             cheb_plan(P, nch, (2.0 / 3.0) * dtau, rtol)};
   const size_t nall = (size_t)nch * P.ncell;
+  const unsigned gall = (unsigned)((nall + kBlock - 1) / kBlock);
   T* x = std::is_same<T, double>::value ? (T*)A.smooth : (T*)A.sxf;
   T* r = (T*)A.sr;
   T* d0 = (T*)A.sd0;
   T* d1 = (T*)A.sd1;
   T* tmp = (T*)A.stmp;
   T* bsave = (T*)A.sx;
-  hipLaunchKernelGGL((k_convert<double, T>), dim3((unsigned)((nall + kBlock - 1) / kBlock)),
-                     dim3(kBlock), 0, s, nall, (const double*)A.raw, x);
+  T* prev = (T*)A.sprev;
+  hipLaunchKernelGGL((k_convert<double, T>), dim3(gall), dim3(kBlock), 0, s, nall,
+                     (const double*)A.raw, x);
   dim3 cgrid(nblk((int64_t)P.nx * P.ny), nch);
   dim3 grid(nblk(P.ncell), nch);
   const size_t nred = (size_t)grid.x * 2 * nch;
+  int64_t total = 0;
   for (int m = 0; m < ntau; ++m) {
+    const bool second = bdf2 && m > 0;
+    if (bdf2) {
+      // the step's right-hand side becomes x (and its starting guess)
+      if (m == 0)
+        hipLaunchKernelGGL((k_convert<T, T>), dim3(gall), dim3(kBlock), 0, s, nall,
+                           (const T*)x, prev);
+      else
+        hipLaunchKernelGGL(k_bdf2_rhs<T>, dim3(gall), dim3(kBlock), 0, s, nall, x, prev);
+    }
+    const ChebPlan& pl = plans[second ? 1 : 0];
+    const Stencil& S = pl.S;
+    const double* ztab = A.ztab + (second ? 2 * (size_t)P.nz : 0);
+    const double theta = pl.theta, delta = pl.delta;
     const double inv_theta = delta > 0.0 ? 1.0 / theta : 1.0;
-    if (line)
+    if (pl.line)
       hipLaunchKernelGGL((k_pcheb_init<T>), cgrid, dim3(kBlock), 0, s, S, x, r, d0, bsave, tmp,
-                         A.ztab, inv_theta);
+                         ztab, inv_theta);
     else
       hipLaunchKernelGGL((k_cheb_init<T>), grid, dim3(kBlock), 0, s, S, x, r, d0, bsave,
                          inv_theta);
@@ -590,7 +634,7 @@ static int64_t smooth_impl(const DevParams& P, DevArrays& A, int nch, int ntau, 
     double rho_k = 1.0 / sigma1;
     T* dcur = d0;
     T* dnext = d1;
-    for (int it = 0; it < kiter; ++it) {
+    for (int it = 0; it < pl.kiter; ++it) {
       double c1 = 0.0, c2 = 0.0;
       if (delta > 0.0) {
         double rho_n = 1.0 / (2.0 * sigma1 - rho_k);
@@ -598,9 +642,9 @@ static int64_t smooth_impl(const DevParams& P, DevArrays& A, int nch, int ntau, 
         c2 = 2.0 * rho_n / delta;
         rho_k = rho_n;
       }
-      if (line)
+      if (pl.line)
         hipLaunchKernelGGL((k_pcheb_iter<T>), cgrid, dim3(kBlock), 0, s, S, dcur, x, r, dnext,
-                           tmp, A.ztab, c1, c2);
+                           tmp, ztab, c1, c2);
       else
         hipLaunchKernelGGL((k_cheb_iter<T>), grid, dim3(kBlock), 0, s, S, dcur, x, r, dnext,
                            c1, c2);
@@ -610,22 +654,23 @@ static int64_t smooth_impl(const DevParams& P, DevArrays& A, int nch, int ntau, 
     }
     hipLaunchKernelGGL(k_residual<T>, grid, dim3(kBlock), 0, s, S, bsave, x,
                        A.red + (size_t)m * nred);
+    total += pl.kiter;
   }
   if (!std::is_same<T, double>::value)
-    hipLaunchKernelGGL((k_convert<T, double>), dim3((unsigned)((nall + kBlock - 1) / kBlock)),
-                       dim3(kBlock), 0, s, nall, x, A.smooth);
-  return (int64_t)kiter * ntau;
+    hipLaunchKernelGGL((k_convert<T, double>), dim3(gall), dim3(kBlock), 0, s, nall, x,
+                       A.smooth);
+  return total;
 }
 
 int64_t launch_smooth(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
-                      double rtol, bool mixed, hipStream_t s) {
+                      double rtol, bool mixed, bool bdf2, hipStream_t s) {
   if (ntau <= 0) {
     (void)hipMemcpyAsync(A.smooth, A.raw, sizeof(double) * nch * P.ncell,
                          hipMemcpyDeviceToDevice, s);
     return 0;
   }
-  if (mixed) return smooth_impl<float>(P, A, nch, ntau, tau, rtol, s);
-  return smooth_impl<double>(P, A, nch, ntau, tau, rtol, s);
+  if (mixed) return smooth_impl<float>(P, A, nch, ntau, tau, rtol, bdf2, s);
+  return smooth_impl<double>(P, A, nch, ntau, tau, rtol, bdf2, s);
 }
 
 double read_smooth_residual(const DevParams& P, DevArrays& A, int nch, int ntau,

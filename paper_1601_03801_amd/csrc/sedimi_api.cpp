@@ -176,7 +176,8 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
   a.sxf = w.take<double>(nch * nc);
   a.stmp = w.take<double>(nch * nc);
   a.us = w.take<double>(nch == 7 ? 3 * nc : 0);
-  a.ztab = w.take<double>(2 * (size_t)c->P.nz);
+  a.ztab = w.take<double>(4 * (size_t)c->P.nz);
+  a.sprev = w.take<double>(c->prm.avg_scheme == SEDIMI_SCHEME_BDF2 && !c->direct ? nch * nc : 0);
   a.spec = w.take<double>(c->direct ? spectral_table_doubles(c->P) : 0);
   a.cell_count = w.take<int>(nc + 1);
   a.cell_start = w.take<int>(nc + 1);
@@ -245,10 +246,8 @@ int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
     return fail(c, SEDIMI_EINVAL, "surrogate parameters out of range");
   if (p.avg_scheme != SEDIMI_SCHEME_EULER && p.avg_scheme != SEDIMI_SCHEME_BDF2)
     return fail(c, SEDIMI_EINVAL, "unknown averaging scheme");
-  if (p.avg_scheme == SEDIMI_SCHEME_BDF2 &&
-      (p.nn_enable || p.avg_solver == SEDIMI_SOLVE_ITERATIVE ||
-       std::max(p.nx, std::max(p.ny, p.nz)) > kDirectMaxAxis))
-    return fail(c, SEDIMI_EINVAL, "BDF2 averaging needs the direct solve (no nn_enable)");
+  if (p.avg_scheme == SEDIMI_SCHEME_BDF2 && p.nn_enable)
+    return fail(c, SEDIMI_EINVAL, "BDF2 averaging needs the plain solve (nn_enable off)");
   if (p.avg_solid_velocity && p.nn_enable)
     return fail(c, SEDIMI_EINVAL, "avg_solid_velocity needs the plain solve (nn_enable off)");
   if (!(p.c_lift >= 0 && std::isfinite(p.c_lift)))
@@ -397,7 +396,8 @@ int64_t plain_solve(sedimi_ctx* c, int nch) {
                                           c->stream);
   } else {
     const double rtol = c->mixed ? std::max(c->prm.avg_rtol, 1e-6) : c->prm.avg_rtol;
-    it = launch_smooth(c->P, c->A, nch, ntau, tau, rtol, c->mixed, c->stream);
+    it = launch_smooth(c->P, c->A, nch, ntau, tau, rtol, c->mixed,
+                       c->prm.avg_scheme == SEDIMI_SCHEME_BDF2, c->stream);
   }
   // all channels smoothed: the solid velocity follows from the flux
   if (nch == 7) launch_solid_velocity(c->P, c->A, c->stream);
@@ -545,9 +545,10 @@ int sedimi_bind_workspace(sedimi_ctx* c, void* dev_ptr, size_t bytes) {
     for (int r = 0; r < P.nbins; ++r) rank[code[r].second] = r;
     HIPCHK(c, hipMemcpyAsync(c->A.bin_rank, rank.data(), sizeof(int) * rank.size(),
                              hipMemcpyHostToDevice, c->stream));
-    std::vector<double> zt(2 * (size_t)P.nz);
+    std::vector<double> zt(4 * (size_t)P.nz);
     double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
     smooth_ztab(P, std::max(1, c->prm.avg_ntau), tau, zt.data());
+    smooth_ztab(P, std::max(1, c->prm.avg_ntau), (2.0 / 3.0) * tau, zt.data() + 2 * P.nz);
     HIPCHK(c, hipMemcpyAsync(c->A.ztab, zt.data(), sizeof(double) * zt.size(),
                              hipMemcpyHostToDevice, c->stream));
     if (c->direct) {

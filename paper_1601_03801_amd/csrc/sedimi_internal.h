@@ -117,7 +117,9 @@ struct DevArrays {
   double *raw, *smooth, *sx, *sr, *sd0, *sd1;  // [nch_avg][ncell] each
   double* us;  // solid velocity [3][ncell] (only with the solid flux)
   double *sxf, *stmp;  // solver: FP32 iterate (mixed mode), column-sweep scratch
-  double* ztab;        // z-line preconditioner: reciprocal pivots, super-diagonal
+  double* ztab;        // z-line preconditioner: reciprocal pivots, super-diagonal, for
+                       // dtau and (BDF2) for 2/3 dtau
+  double* sprev;       // BDF2 iterative solve: the previous pseudo-time step
   double* spec;        // direct solve: H_x, H_y, C_z, C_z^-1, per-axis eigenvalues
   int *cell_count, *cell_start;
   unsigned long long* cperm;  // deposition: (particle ID << 32 | sorted index), by cell
@@ -153,11 +155,12 @@ void launch_pack_eps(const DevParams& P, DevArrays& A, hipStream_t s);
 
 // ---- launchers (k_average.hip) ----
 void launch_deposit(const DevParams& P, DevArrays& A, hipStream_t s);
-// Enqueue the smoothing of channels [0, nch) of raw into smooth; returns the
-// total number of solver iterations.  Each pseudo-time step's final residual
+// Enqueue the smoothing of channels [0, nch) of raw into smooth (backward
+// Euler, or BDF2 with A.sprev holding the previous step); returns the total
+// number of solver iterations.  Each pseudo-time step's final residual
 // partials are left in A.red for read_smooth_residual.
 int64_t launch_smooth(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
-                      double rtol, bool mixed, hipStream_t s);
+                      double rtol, bool mixed, bool bdf2, hipStream_t s);
 // Largest relative residual over channels and pseudo-time steps of the last
 // launch_smooth (synchronises the stream); negative on a HIP error.
 double read_smooth_residual(const DevParams& P, DevArrays& A, int nch, int ntau,

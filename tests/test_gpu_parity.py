@@ -197,6 +197,30 @@ def test_solid_velocity_matches_oracle(orc, solver):
         g.smooth(8)
 
 
+def test_solid_velocity_mixed_fp32_vectors(orc):
+    """Mixed precision: the flux is still deposited in FP64 (bit-identical),
+    the 7 channels are smoothed with FP32 working vectors, and U_s follows
+    where the solid fraction is well above the FP32 rounding of the solve."""
+    case = dense_bed(4000, 14)
+    prm = dict(case["params"], avg_solid_velocity=1)
+    case["params"] = prm
+    flux_o = orc.deposit_flux(prm, case["x"], case["d"], case["v"])
+    raw_o = np.concatenate([orc.deposit(prm, case["x"], case["d"]), flux_o])
+    g = gpu_context(case, precision="mixed", solver="iterative")
+    g.compute_forces()
+    g.average()
+    raw_g, sm_g, us_g = g.get_field(0), g.get_field(1), g.get_field(2)
+    assert np.array_equal(raw_g[0], raw_o[0]) and np.array_equal(raw_g[4:], flux_o)
+    sm_o, _ = orc.diffuse(prm, raw_g)  # the oracle smooths the GPU's own deposit
+    us_o = orc.solid_velocity(sm_o[0], sm_o[4:])
+    qscale = np.abs(raw_o[4:]).max()
+    assert np.abs(sm_g[4:] - sm_o[4:]).max() < 1e-5 * qscale
+    solid = sm_o[0] > 0.05
+    vmax = np.abs(case["v"]).max()
+    assert solid.sum() > 100
+    assert np.abs(us_g[:, solid] - us_o[:, solid]).max() < 1e-4 * vmax
+
+
 def test_solid_velocity_inside_steps_reads_the_current_velocities(orc):
     """The averaging inside sedimi_step deposits the velocities at the end of
     the step: its flux equals the oracle's deposit of the state read back."""
@@ -243,13 +267,16 @@ def test_smooth_matches_oracle(orc, shape, ntau, bz, solver):
         assert st["solve_iters"] == 0
 
 
+@pytest.mark.parametrize("solver", ["direct", "iterative"])
 @pytest.mark.parametrize("shape,ntau,bz", [((16, 16, 8), 1, 0.0), ((33, 20, 17), 4, 0.0),
                                            ((64, 32, 48), 6, 0.0), ((1, 5, 70), 2, 0.0),
                                            ((130, 2, 1), 5, 0.0), ((24, 16, 40), 3, 3.0e-3)])
-def test_smooth_bdf2_matches_oracle(orc, shape, ntau, bz):
-    """BDF2 pseudo-time by the direct solve (the BDF2 factor per mode)
-    against the oracle's step-by-step CG solves, with the BDF2 residual check
-    (q_N(M) y = p_N(M) raw) inside its bound."""
+def test_smooth_bdf2_matches_oracle(orc, shape, ntau, bz, solver):
+    """BDF2 pseudo-time against the oracle's step-by-step CG solves: by the
+    direct solve (the BDF2 factor per mode, with the BDF2 residual check
+    q_N(M) y = p_N(M) raw inside its bound) and by the iterative solver (the
+    right-hand side (4 x - x_prev)/3 formed before each later step, which is
+    solved with 2/3 dtau)."""
     prm = workloads.base_params(Lx=max(shape[0] * 0.3e-3, 5e-3), Ly=max(shape[1] * 0.3e-3, 5e-3),
                                 Lz=shape[2] * 0.2e-3,
                                 nx=shape[0], ny=shape[1], nz=shape[2], avg_ntau=ntau,
@@ -260,7 +287,7 @@ def test_smooth_bdf2_matches_oracle(orc, shape, ntau, bz):
     euler, _ = orc.diffuse(dict(prm, avg_scheme=0), raw)
     case = dict(params=prm, x=np.zeros((0, 3)), v=np.zeros((0, 3)), w=np.zeros((0, 3)),
                 d=np.zeros(0), rho=np.zeros(0))
-    g = gpu_context(case, cap=1, solver="direct")
+    g = gpu_context(case, cap=1, solver=solver)
     g.set_field(0, raw)
     g.smooth(4)
     got = g.get_field(1)
@@ -269,9 +296,12 @@ def test_smooth_bdf2_matches_oracle(orc, shape, ntau, bz):
     if ntau > 1:  # the schemes differ from the second step on
         assert np.abs(euler - want).max() > 1e3 * np.abs(got - want).max()
     st = g.stats()
-    print("bdf2", shape, "residual", st["solve_residual"])
-    # (smooth() itself fails with ENOCONV above the bound 1e-12 (1 + a)(3 + 2a)^(N-1))
-    assert st["solve_iters"] == 0 and np.isfinite(st["solve_residual"])
+    print("bdf2", solver, shape, "iterations", st["solve_iters"], "residual",
+          st["solve_residual"])
+    # (smooth() itself fails with ENOCONV above its bound: for the direct solve
+    # 1e-12 (1 + a)(3 + 2a)^(N-1), for the iterative one 10 avg_rtol per step)
+    assert np.isfinite(st["solve_residual"])
+    assert (st["solve_iters"] == 0) == (solver == "direct")
 
 
 def test_short_trajectory(orc):
@@ -359,12 +389,13 @@ def test_history_survives_resort(orc):
     assert np.abs(gh["xi"] - oh["xi"]).max() < 1e-9 * np.abs(oh["xi"]).max()
 
 
-@pytest.mark.parametrize("shape", [(32, 16, 24), (40, 20, 64)])
-def test_smooth_mixed_fp32_vectors(orc, shape):
+@pytest.mark.parametrize("shape,scheme", [((32, 16, 24), 0), ((40, 20, 64), 0),
+                                          ((40, 20, 64), 1)])
+def test_smooth_mixed_fp32_vectors(orc, shape, scheme):
     """FP32 working vectors, FP64 residual: the solid fraction stays within
-    1e-6 of the oracle's FP64 solve."""
+    1e-6 of the oracle's FP64 solve (backward Euler and BDF2)."""
     prm = workloads.base_params(Lx=shape[0] * 1.5e-3, Ly=shape[1] * 1.5e-3, Lz=shape[2] * 0.25e-3,
-                                nx=shape[0], ny=shape[1], nz=shape[2])
+                                nx=shape[0], ny=shape[1], nz=shape[2], avg_scheme=scheme)
     rng = np.random.default_rng(7)
     raw = 0.6 * rng.random((4, np.prod(shape))) ** 3
     want, _ = orc.diffuse(prm, raw)
