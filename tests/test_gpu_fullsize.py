@@ -91,23 +91,27 @@ def _patch(w, samples, reach):
     return np.unique(np.concatenate(keep))
 
 
-def _context(w, precision):
+def _context(w, precision, prm=None):
     import paper_1601_03801_amd as sm
     dmax = float(w["d"].max())
-    g = sm.Sedimi(w["params"], len(w["d"]), precision=precision, d_max=dmax, skin=0.1 * dmax,
-                  max_neighbors=24)
+    g = sm.Sedimi(prm or w["params"], len(w["d"]), precision=precision, d_max=dmax,
+                  skin=0.1 * dmax, max_neighbors=24)
     g.set_fluid(w["U"], w["gradp"], w["dudt"])
     g.set_particles(w["x"], w["v"], w["d"], w["rho"], omega=w["w"])
     return g
 
 
-@pytest.mark.parametrize("name,precision,tol", [("bed1m", "fp64", 1e-12),
-                                                 ("bed10m", "mixed", 1e-5)])
-def test_fullsize_forces_on_sampled_particles(orc, name, precision, tol):
+@pytest.mark.parametrize("name,precision,tol,opts", [
+    ("bed1m", "fp64", 1e-12, {}),
+    ("bed10m", "mixed", 1e-5, {}),
+    ("bed1m", "fp64", 1e-12, {"c_lift": 1.6, "drag_law": "syamlal"})])
+def test_fullsize_forces_on_sampled_particles(orc, name, precision, tol, opts):
+    """opts: the shear lift and the Syamlal-O'Brien drag (bench.py --lift 1.6
+    --drag syamlal)."""
     w = _bed(name)
-    prm = w["params"]
-    print(f"{name}: {len(w['d'])} spheres, context ({precision})", flush=True)
-    g = _context(w, precision)
+    prm = dict(w["params"], **opts)
+    print(f"{name}: {len(w['d'])} spheres, context ({precision}, {opts})", flush=True)
+    g = _context(w, precision, prm)
     g.set_field(1, w["smooth"])
     g.set_accel(w["a_prev"])
     g.compute_forces(update_history=True)
@@ -122,9 +126,11 @@ def test_fullsize_forces_on_sampled_particles(orc, name, precision, tol):
     loc = np.searchsorted(patch, samples)
     m = w["rho"][samples] * math.pi / 6 * w["d"][samples] ** 3
     scale = sum(np.linalg.norm(comps[k][loc], axis=1) for k in
-                ("contact", "lub", "drag", "pressure", "added")) + m * 9.81
+                ("contact", "lub", "drag", "pressure", "added", "lift")) + m * 9.81
+    if opts.get("c_lift"):
+        assert np.abs(comps["lift"][loc]).max() > 0.0
     table = {}
-    for k in ("contact", "lub", "drag", "pressure", "added", "total"):
+    for k in ("contact", "lub", "drag", "pressure", "added", "lift", "total"):
         e = rel_err(g.get_forces(k)[samples], comps[k][loc], scale)
         table[k] = (float(e.max()), float(np.quantile(e, 0.99)))
     r = 0.5 * w["d"][samples]
@@ -174,3 +180,31 @@ def test_fullsize_deposit_bit_exact_and_smooth(orc, name):
     print(f"{name}: smoothed solid fraction max abs error {err:.3e}", flush=True)
     assert err < 1e-11 * raw_o[0].max()
     assert not sm_g[1:].any()
+
+
+def test_fullsize_solid_velocity_and_bdf2(orc):
+    """The 1M bed with the solid volume flux and BDF2 pseudo-time, both
+    solvers' default for this mesh (direct): flux deposited bit-identically,
+    smoothed solid fraction and flux against the oracle's BDF2 CG solves,
+    and U_s on every solid cell."""
+    w = _bed("bed1m")
+    prm = dict(w["params"], avg_solid_velocity=1, avg_scheme=1)
+    g = _context(w, "fp64", prm)
+    g.average()
+    raw_g, sm_g, us_g = g.get_field(0), g.get_field(1), g.get_field(2)
+    raw_o = orc.deposit(prm, w["x"], w["d"])
+    flux_o = orc.deposit_flux(prm, w["x"], w["d"], w["v"])
+    assert np.array_equal(raw_g[0], raw_o[0]) and np.array_equal(raw_g[4:], flux_o)
+    print("bed1m: oracle BDF2 diffusion of the solid fraction and flux", flush=True)
+    sm_o, _ = orc.diffuse(prm, np.concatenate([raw_o[:1], flux_o]))
+    err = np.abs(sm_g[0] - sm_o[0]).max()
+    qscale = np.abs(flux_o).max()
+    qerr = np.abs(sm_g[4:] - sm_o[1:]).max()
+    print(f"bed1m: eps_s max abs error {err:.3e}, flux max error {qerr / qscale:.3e}", flush=True)
+    assert err < 1e-11 * raw_o[0].max()
+    assert qerr < 1e-10 * qscale
+    us_o = orc.solid_velocity(sm_o[0], sm_o[1:])
+    solid = sm_o[0] > 1e-6
+    vmax = np.abs(w["v"]).max()
+    assert solid.sum() > 1000
+    assert np.abs(us_g[:, solid] - us_o[:, solid]).max() < 1e-8 * vmax
