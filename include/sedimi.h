@@ -109,7 +109,7 @@ typedef struct {
   int bottom_wall, top_wall; /* 0/1 */
   double eps_s_max;          /* clamp of the interpolated solid fraction in the drag */
   double avg_bandwidth;      /* averaging bandwidth b (m); pseudo-time b^2/4 */
-  int avg_ntau;              /* implicit pseudo-time steps */
+  int avg_ntau;              /* implicit pseudo-time steps (0: no smoothing, SMOOTH = RAW) */
   double avg_rtol;           /* relative residual tolerance of each implicit step */
   int precision;             /* SEDIMI_FP64 or SEDIMI_MIXED */
   double d_max;              /* largest particle diameter the context will hold (m);

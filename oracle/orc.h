@@ -52,7 +52,7 @@ typedef struct {
   int bottom_wall, top_wall; /* 0/1 */
   double eps_s_max;          /* clamp for the interpolated solid fraction in drag */
   double avg_bandwidth;      /* diffusion-averaging bandwidth b (m) */
-  int avg_ntau;              /* number of implicit pseudo-time steps */
+  int avg_ntau;              /* number of implicit pseudo-time steps (0: no smoothing) */
   double cg_rtol;            /* CG relative residual tolerance */
   double avg_bandwidth_z;    /* bandwidth along z (m); 0: avg_bandwidth */
   double c_lift;             /* lift coefficient C_l of Eq. (particleLift); 0: no lift */

@@ -169,8 +169,9 @@ static int cg_solve(const orc_params* p, double dtau, const double* b, double* x
 int orc_diffuse(const orc_params* p, int nch, const double* in, double* out, int64_t* iters) {
   int64_t n = (int64_t)p->nx * p->ny * p->nz;
   double tau = 0.25 * p->avg_bandwidth * p->avg_bandwidth;
-  int ntau = p->avg_ntau > 0 ? p->avg_ntau : 1;
-  double dtau = tau / ntau;
+  /* no pseudo-time steps: the deposited field itself (no smoothing) */
+  int ntau = p->avg_ntau > 0 ? p->avg_ntau : 0;
+  double dtau = ntau > 0 ? tau / ntau : 0.0;
   double* cur = (double*)malloc(sizeof(double) * (size_t)n);
   double* r = (double*)malloc(sizeof(double) * (size_t)n);
   double* pv = (double*)malloc(sizeof(double) * (size_t)n);

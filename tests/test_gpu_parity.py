@@ -302,6 +302,26 @@ def test_smooth_bdf2_matches_oracle(orc, shape, ntau, bz, solver):
     # 1e-12 (1 + a)(3 + 2a)^(N-1), for the iterative one 10 avg_rtol per step)
     assert np.isfinite(st["solve_residual"])
     assert (st["solve_iters"] == 0) == (solver == "direct")
+    import paper_1601_03801_amd as sm
+    with pytest.raises(sm.SedimiError):
+        g.get_field(2)  # no solid velocity without avg_solid_velocity
+
+
+@pytest.mark.parametrize("solver", ["direct", "iterative"])
+def test_smooth_zero_steps_returns_the_deposit(orc, solver):
+    """avg_ntau = 0 takes no pseudo-time step: SMOOTH equals RAW, as in the
+    oracle."""
+    shape = (12, 10, 8)
+    prm = workloads.base_params(Lx=5e-3, Ly=5e-3, Lz=shape[2] * 0.2e-3, nx=shape[0],
+                                ny=shape[1], nz=shape[2], avg_ntau=0)
+    raw = np.random.default_rng(3).random((4, np.prod(shape)))
+    want, _ = orc.diffuse(prm, raw)
+    case = dict(params=prm, x=np.zeros((0, 3)), v=np.zeros((0, 3)), w=np.zeros((0, 3)),
+                d=np.zeros(0), rho=np.zeros(0))
+    g = gpu_context(case, cap=1, solver=solver)
+    g.set_field(0, raw)
+    g.smooth(4)
+    assert np.array_equal(g.get_field(1), want) and np.array_equal(want, raw)
 
 
 def test_short_trajectory(orc):

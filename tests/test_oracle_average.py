@@ -330,3 +330,13 @@ def test_bdf2_is_second_order_and_euler_first_order(orc):
     assert errs[1, 16] < 0.05 * errs[0, 16]
     uni, _ = orc.diffuse(dict(mesh_prm(*shape, ntau=5), avg_scheme=1), np.full((1, n), 0.37))
     assert np.max(np.abs(uni - 0.37)) < 1e-14
+
+
+def test_zero_pseudo_time_steps_leave_the_field(orc):
+    """avg_ntau = 0: no diffusion step is taken, the deposited field is
+    returned unchanged (either scheme)."""
+    prm = mesh_prm(6, 5, 4, ntau=0)
+    raw = np.random.default_rng(2).random((2, 120))
+    for scheme in (0, 1):
+        out, iters = orc.diffuse(dict(prm, avg_scheme=scheme), raw)
+        assert np.array_equal(out, raw) and iters == 0
