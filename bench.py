@@ -59,8 +59,8 @@ def averaging_rooflines(n, ncell, dep_ms, smooth_ms, direct, mesh, nch=4):
 # the same counters read for a 1 GiB device copy (--copy-calibration: the
 # copy's FETCH_SIZE reads 0.5x the bytes read, WRITE_SIZE 1.0x the bytes
 # written).  Valid only for the kernel sources it was measured on.
-FORCE_PMC = {"fetch_kib": 315355.2, "write_kib": 281002.5, "fetch_scale": 2.0, "write_scale": 1.0,
-             "sources_sha256": "463ec7ef85ec4c449365ada4be5311260ae09b2df3b41b44f22182881e88a96e",
+FORCE_PMC = {"fetch_kib": 315359.3, "write_kib": 281002.4, "fetch_scale": 2.0, "write_scale": 1.0,
+             "sources_sha256": "901ce0a353829f77b4c70bc03f82b7afdf7191770ed62079b28290157fb1f419",
              "profile": "profiles/k_forces_bed1m_fp64.md"}
 FORCE_SOURCES = ("k_forces.hip", "k_common.h", "sedimi_internal.h")
 

@@ -249,6 +249,13 @@ int sedimi_smooth(sedimi_ctx* ctx, int nch);
 
 /* Read back, in ID order.  Any output pointer may be NULL. */
 int sedimi_get_particles(sedimi_ctx* ctx, double* x, double* v, double* omega, double* a);
+/* The accelerations a^n and angular accelerations alpha^n of the last force
+ * evaluation (host [n][3], ID order), the counterpart of sedimi_set_accel: with
+ * sedimi_get_particles, sedimi_get_history and the SMOOTH field they make a
+ * checkpoint from which set_particles, set_field, set_accel and set_history
+ * resume the run (Section 2.5's velocity Verlet needs a^n and alpha^n for the
+ * next half kick). */
+int sedimi_get_accel(sedimi_ctx* ctx, double* a, double* alpha);
 int sedimi_get_forces(sedimi_ctx* ctx, int component, double* f);
 int sedimi_get_field(sedimi_ctx* ctx, int field, double* out);
 /* Current contact-pair set (centre distance below contact distance plus the

@@ -108,6 +108,7 @@ def lib():
         L.sedimi_deposit.argtypes = [P]
         L.sedimi_smooth.argtypes = [P, I]
         L.sedimi_get_particles.argtypes = [P, P, P, P, P]
+        L.sedimi_get_accel.argtypes = [P, P, P]
         L.sedimi_get_forces.argtypes = [P, I, P]
         L.sedimi_get_field.argtypes = [P, I, P]
         L.sedimi_get_pairs.argtypes = [P, i64, P, C.POINTER(i64)]
@@ -259,6 +260,11 @@ class Sedimi:
         out = [np.zeros((self.n, 3)) for _ in range(4)]
         self._chk(self._L.sedimi_get_particles(self._ctx, *[_ptr(o) for o in out]))
         return dict(zip(("x", "v", "omega", "a"), out))
+
+    def get_accel(self):
+        out = [np.zeros((self.n, 3)) for _ in range(2)]
+        self._chk(self._L.sedimi_get_accel(self._ctx, *[_ptr(o) for o in out]))
+        return dict(zip(("a", "alpha"), out))
 
     def get_forces(self, component):
         f = np.zeros((self.n, 3))

@@ -839,6 +839,28 @@ int sedimi_get_particles(sedimi_ctx* c, double* x, double* v, double* w, double*
   return SEDIMI_OK;
 }
 
+int sedimi_get_accel(sedimi_ctx* c, double* a, double* alpha) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  const size_t n = (size_t)c->n;
+  std::vector<int> id;
+  rc = download(c, id, c->A.id, n);
+  if (rc) return rc;
+  double* outs[2] = {a, alpha};
+  const double4* srcs[2] = {c->A.acc, c->A.alp};
+  std::vector<double4> h;
+  for (int f = 0; f < 2; ++f) {
+    if (!outs[f]) continue;
+    rc = download(c, h, srcs[f], n);
+    if (rc) return rc;
+    for (size_t q = 0; q < n; ++q) {
+      double* o = outs[f] + 3 * (size_t)id[q];
+      o[0] = h[q].x, o[1] = h[q].y, o[2] = h[q].z;
+    }
+  }
+  return SEDIMI_OK;
+}
+
 int sedimi_get_forces(sedimi_ctx* c, int comp, double* f) {
   int rc = need_particles(c);
   if (rc) return rc;

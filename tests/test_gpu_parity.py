@@ -324,6 +324,53 @@ def test_smooth_zero_steps_returns_the_deposit(orc, solver):
     assert np.array_equal(g.get_field(1), want) and np.array_equal(want, raw)
 
 
+def test_checkpoint_resume_continues_the_run():
+    """A run stopped after 10 steps and restored into a new context (particles,
+    accelerations, contact history, smoothed field) continues as the
+    uninterrupted run.  The resumed neighbour lists are built from the
+    checkpointed positions, so their order, and with it each particle's
+    summation order, may differ: agreement to rounding, same contacts."""
+    case = dense_bed(3000, 15)
+    a = gpu_context(case)
+    a.average()
+    a.compute_forces(update_history=True)
+    a.step(10, 5)
+    ck = a.get_particles()
+    acc = a.get_accel()
+    hist = a.get_history()
+    smooth = a.get_field(1)
+    assert len(hist) > 1000 and np.abs(acc["alpha"]).max() > 0
+    a.step(10, 5)
+    want = a.get_particles()
+    want_hist = a.get_history()
+    b = gpu_context(dict(case, x=ck["x"], v=ck["v"], w=ck["omega"]))
+    b.set_field(1, smooth)
+    b.set_accel(acc["a"], acc["alpha"])
+    b.set_history(hist)
+    got_acc = b.get_accel()
+    assert np.array_equal(got_acc["a"], acc["a"]) and np.array_equal(got_acc["alpha"], acc["alpha"])
+    b.step(10, 5)
+    got = b.get_particles()
+    got_hist = b.get_history()
+    dx = np.abs(got["x"] - want["x"]).max() / case["d"].max()
+    dv = np.abs(got["v"] - want["v"]).max() / np.abs(want["v"]).max()
+    dw = np.abs(got["omega"] - want["omega"]).max() / np.abs(want["omega"]).max()
+    print(f"resume: max |dx|/d {dx:.2e}, |dv| {dv:.2e}, |dw| {dw:.2e}")
+    assert dx < 1e-12 and dv < 1e-9 and dw < 1e-9
+    assert np.array_equal(got_hist["i"], want_hist["i"])
+    assert np.array_equal(got_hist["j"], want_hist["j"])
+    xs = np.abs(want_hist["xi"]).max()
+    assert np.abs(got_hist["xi"] - want_hist["xi"]).max() < 1e-9 * xs
+    # without the angular accelerations the first half kick differs
+    c = gpu_context(dict(case, x=ck["x"], v=ck["v"], w=ck["omega"]))
+    c.set_field(1, smooth)
+    c.set_accel(acc["a"], None)
+    c.set_history(hist)
+    c.step(10, 5)
+    assert np.abs(c.get_particles()["omega"] - want["omega"]).max() > 1e3 * dw * np.abs(
+        want["omega"]).max()
+
+
 def test_short_trajectory(orc):
     w = workloads.workload("small")
     prm = w["params"]
