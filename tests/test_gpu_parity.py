@@ -142,6 +142,32 @@ def test_forces_shear_lift(orc, precision, tol):
     assert worst["lift"] < tol
 
 
+@pytest.mark.parametrize("nz,with_fluid", [(1, True), (2, True), (11, False)])
+def test_forces_shear_lift_edge_meshes(orc, nz, with_fluid):
+    """The lift's curl on a single z cell (no z derivatives) and on two z
+    cells (one-sided differences only), on a random flow; and with no fluid
+    velocity at all (no vorticity, no lift)."""
+    case = dense_bed(2000, 16)
+    prm = dict(case["params"], nz=nz, c_lift=1.6)
+    ncell = prm["nx"] * prm["ny"] * nz
+    rng = np.random.default_rng(31 + nz)
+    U = rng.normal(scale=0.05, size=(ncell, 3)) if with_fluid else None
+    comps, _ = orc.forces(prm, case["x"], case["v"], case["w"], case["d"], case["rho"], U=U)
+    c2 = dict(case, params=prm, U=U, gradp=None, dudt=None)
+    g = gpu_context(c2)
+    g.compute_forces()
+    lift = g.get_forces("lift")
+    m = case["rho"] * math.pi / 6 * case["d"] ** 3
+    scale = np.linalg.norm(comps["drag"], axis=1) + np.linalg.norm(comps["lift"], axis=1) + m * 9.81
+    err = rel_err(lift, comps["lift"], scale).max()
+    print(f"nz {nz} fluid {with_fluid}: lift max rel error {err:.2e}")
+    assert err < 1e-12
+    if with_fluid:
+        assert np.abs(comps["lift"]).max() > 0.0
+    else:
+        assert not lift.any() and not comps["lift"].any()
+
+
 def test_deposit_bit_exact_and_smooth(orc):
     case = dense_bed(4000, 8)
     prm = case["params"]
