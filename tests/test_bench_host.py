@@ -1,0 +1,41 @@
+"""bench.py's host-side contract, without a GPU: more than one GPU is
+refused with a message, the averaging rooflines count what the docstring
+states, and the stored force-kernel counters are tied to the current kernel
+sources."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_averaging_roofline_bytes_and_flops():
+    n, ncell, mesh = 1000, 64, (4, 4, 4)
+    dep, sol = bench.averaging_rooflines(n, ncell, 1.0, 1.0, True, mesh)
+    assert dep["bytes"] == 88 * n + 32 * ncell
+    assert sol["gflop"] == round(4 * 12 * ncell * 4 / 1e9, 3)
+    dep7, sol7 = bench.averaging_rooflines(n, ncell, 1.0, 1.0, True, mesh, nch=7)
+    assert dep7["bytes"] == 120 * n + 56 * ncell
+    assert sol7["gflop"] == round(4 * 12 * ncell * 7 / 1e9, 3)
+    big = 10 ** 8  # large enough for the rounded HBM minimum
+    _, s4 = bench.averaging_rooflines(n, big, 1.0, 1.0, True, mesh)
+    _, s7 = bench.averaging_rooflines(n, big, 1.0, 1.0, True, mesh, nch=7)
+    assert s4["hbm_minimum_ms"] == round(16 * big * 4 / bench.HBM_PEAK_GBS / 1e6, 5)
+    assert s7["hbm_minimum_ms"] == round(16 * big * 7 / bench.HBM_PEAK_GBS / 1e6, 5)
+
+
+def test_stored_force_counters_match_the_kernel_sources():
+    """The HBM traffic in the bench line is reported only while the hash of
+    the force kernel's sources equals the one the counters were taken on."""
+    assert bench.FORCE_PMC is not None
+    assert bench.FORCE_PMC["sources_sha256"] == bench.force_sources_sha()
+    assert os.path.exists(os.path.join(ROOT, bench.FORCE_PMC["profile"]))
