@@ -182,6 +182,7 @@ typedef struct {
   int64_t nn_calls;       /* averagings answered by the network (checked or not) */
   int64_t nn_fallbacks;   /* checked averagings that fell back to the plain solve */
   double nn_last_check;   /* largest per-channel relative residual of the last check */
+  int64_t particles;      /* particles in the context */
 } sedimi_stats;
 
 /* Device time per phase of sedimi_step / sedimi_average, measured with HIP
@@ -256,6 +257,18 @@ int sedimi_get_particles(sedimi_ctx* ctx, double* x, double* v, double* omega, d
  * resume the run (Section 2.5's velocity Verlet needs a^n and alpha^n for the
  * next half kick). */
 int sedimi_get_accel(sedimi_ctx* ctx, double* a, double* alpha);
+/* Checkpoint of the whole context as one opaque blob: the device workspace
+ * (particles in their sorted order, neighbour lists, contact history, mesh
+ * fields, network) and the host-side counters.  A context with the same mesh,
+ * capacity and options restores it with sedimi_set_state and continues the
+ * run bit for bit (physical parameters are those of the restoring context).
+ * get: *size_out receives the blob size (about the workspace size); the blob
+ * is written only if buf is non-NULL and cap >= that size, else ENOMEM when
+ * buf is non-NULL.  set: EINVAL if the blob is malformed or from a context of
+ * another layout.  Both synchronise the stream; host buffers are the
+ * caller's. */
+int sedimi_get_state(sedimi_ctx* ctx, void* buf, size_t cap, size_t* size_out);
+int sedimi_set_state(sedimi_ctx* ctx, const void* buf, size_t size);
 int sedimi_get_forces(sedimi_ctx* ctx, int component, double* f);
 int sedimi_get_field(sedimi_ctx* ctx, int field, double* out);
 /* Current contact-pair set (centre distance below contact distance plus the

@@ -63,7 +63,8 @@ class sedimi_stats(C.Structure):
                 ("flags", C.c_int32), ("solve_iters", C.c_int64),
                 ("solve_residual", C.c_double), ("mean_neighbors", C.c_double),
                 ("mean_contacts", C.c_double), ("nn_calls", C.c_int64),
-                ("nn_fallbacks", C.c_int64), ("nn_last_check", C.c_double)]
+                ("nn_fallbacks", C.c_int64), ("nn_last_check", C.c_double),
+                ("particles", C.c_int64)]
 
 
 NPHASES = 6
@@ -109,6 +110,8 @@ def lib():
         L.sedimi_smooth.argtypes = [P, I]
         L.sedimi_get_particles.argtypes = [P, P, P, P, P]
         L.sedimi_get_accel.argtypes = [P, P, P]
+        L.sedimi_get_state.argtypes = [P, P, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.sedimi_set_state.argtypes = [P, P, C.c_size_t]
         L.sedimi_get_forces.argtypes = [P, I, P]
         L.sedimi_get_field.argtypes = [P, I, P]
         L.sedimi_get_pairs.argtypes = [P, i64, P, C.POINTER(i64)]
@@ -260,6 +263,19 @@ class Sedimi:
         out = [np.zeros((self.n, 3)) for _ in range(4)]
         self._chk(self._L.sedimi_get_particles(self._ctx, *[_ptr(o) for o in out]))
         return dict(zip(("x", "v", "omega", "a"), out))
+
+    def get_state(self):
+        """Opaque checkpoint blob (numpy uint8) of the whole context."""
+        size = C.c_size_t(0)
+        self._chk(self._L.sedimi_get_state(self._ctx, None, 0, C.byref(size)))
+        blob = np.empty(size.value, np.uint8)
+        self._chk(self._L.sedimi_get_state(self._ctx, _ptr(blob), blob.size, C.byref(size)))
+        return blob
+
+    def set_state(self, blob):
+        blob = np.ascontiguousarray(blob, np.uint8)
+        self._chk(self._L.sedimi_set_state(self._ctx, _ptr(blob), blob.size))
+        self.n = int(self.stats()["particles"])
 
     def get_accel(self):
         out = [np.zeros((self.n, 3)) for _ in range(2)]

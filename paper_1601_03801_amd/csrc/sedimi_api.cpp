@@ -1030,6 +1030,105 @@ int sedimi_set_history(sedimi_ctx* c, int64_t nrec, const void* records) {
   return flags_to_rc(c, ctl.flags);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Header of a state blob; the workspace bytes follow it.
+struct StateHeader {
+  char magic[8];
+  uint64_t header_bytes, ws_bytes;
+  // layout: a restoring context must carve its workspace the same way
+  int64_t cap;
+  int32_t maxn, nbins, ncell, nch_avg, mixed, direct, nn_enable, pad0;
+  // host-side state
+  int64_t n, step, adam_t, nn_calls, nn_fallbacks, last_iters;
+  double nn_last_check, last_residual;
+  int32_t avg_mode, have_particles, last_direct, check_blocks;
+  uint32_t swapped;  // double buffers in their second position: vel, omg, pos, rb
+  int32_t pad1;
+  NNNorm norm;
+};
+constexpr char kStateMagic[8] = {'S', 'E', 'D', 'I', 'M', 'I', 'S', '1'};
+
+void state_layout(const sedimi_ctx* c, StateHeader* h) {
+  h->ws_bytes = c->ws_bytes;
+  h->cap = c->cap;
+  h->maxn = c->P.maxn;
+  h->nbins = c->P.nbins;
+  h->ncell = c->P.ncell;
+  h->nch_avg = c->P.nch_avg;
+  h->mixed = c->mixed ? 1 : 0;
+  h->direct = c->direct ? 1 : 0;
+  h->nn_enable = c->prm.nn_enable ? 1 : 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sedimi_get_state(sedimi_ctx* c, void* buf, size_t cap, size_t* size_out) {
+  int rc = need_ws(c);
+  if (rc) return rc;
+  const size_t total = sizeof(StateHeader) + c->ws_bytes;
+  if (size_out) *size_out = total;
+  if (!buf) return SEDIMI_OK;
+  if (cap < total) return fail(c, SEDIMI_ENOMEM, "state buffer too small");
+  StateHeader h{};
+  memcpy(h.magic, kStateMagic, sizeof(kStateMagic));
+  h.header_bytes = sizeof(StateHeader);
+  state_layout(c, &h);
+  h.n = c->n, h.step = c->step, h.adam_t = c->adam_t;
+  h.nn_calls = c->nn_calls, h.nn_fallbacks = c->nn_fallbacks, h.last_iters = c->last_iters;
+  h.nn_last_check = c->nn_last_check, h.last_residual = c->last_residual;
+  h.avg_mode = c->avg_mode, h.have_particles = c->have_particles ? 1 : 0;
+  h.last_direct = c->last_direct ? 1 : 0, h.check_blocks = c->check_blocks;
+  h.norm = c->norm;
+  DevArrays canon{};
+  layout(c, c->ws, &canon);
+  h.swapped = (c->A.vel != canon.vel ? 1u : 0u) | (c->A.omg != canon.omg ? 2u : 0u) |
+              (c->A.pos != canon.pos ? 4u : 0u) | (c->A.rb != canon.rb ? 8u : 0u);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  memcpy(buf, &h, sizeof(h));
+  HIPCHK(c, hipMemcpy((char*)buf + sizeof(h), c->ws, c->ws_bytes, hipMemcpyDeviceToHost));
+  return SEDIMI_OK;
+}
+
+int sedimi_set_state(sedimi_ctx* c, const void* buf, size_t size) {
+  int rc = need_ws(c);
+  if (rc) return rc;
+  if (!buf || size < sizeof(StateHeader)) return fail(c, SEDIMI_EINVAL, "state blob too short");
+  StateHeader h;
+  memcpy(&h, buf, sizeof(h));
+  if (memcmp(h.magic, kStateMagic, sizeof(kStateMagic)) != 0 ||
+      h.header_bytes != sizeof(StateHeader) || size != sizeof(StateHeader) + h.ws_bytes)
+    return fail(c, SEDIMI_EINVAL, "not a state blob of this library");
+  StateHeader mine{};
+  state_layout(c, &mine);
+  if (h.ws_bytes != mine.ws_bytes || h.cap != mine.cap || h.maxn != mine.maxn ||
+      h.nbins != mine.nbins || h.ncell != mine.ncell || h.nch_avg != mine.nch_avg ||
+      h.mixed != mine.mixed || h.direct != mine.direct || h.nn_enable != mine.nn_enable)
+    return fail(c, SEDIMI_EINVAL, "state blob from a context of another layout");
+  if (h.n < 0 || h.n > c->cap || h.swapped > 15u)
+    return fail(c, SEDIMI_EINVAL, "state blob out of range");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(c->ws, (const char*)buf + sizeof(h), c->ws_bytes, hipMemcpyHostToDevice));
+  layout(c, c->ws, &c->A);
+  if (h.swapped & 1u) std::swap(c->A.vel, c->A.vel_t);
+  if (h.swapped & 2u) std::swap(c->A.omg, c->A.omg_t);
+  if (h.swapped & 4u) std::swap(c->A.pos, c->A.pos_t);
+  if (h.swapped & 8u) std::swap(c->A.rb, c->A.rb_next);
+  c->n = h.n;
+  c->P.n = (int)h.n;
+  c->step = h.step, c->adam_t = h.adam_t;
+  c->nn_calls = h.nn_calls, c->nn_fallbacks = h.nn_fallbacks, c->last_iters = h.last_iters;
+  c->nn_last_check = h.nn_last_check, c->last_residual = h.last_residual;
+  c->avg_mode = h.avg_mode, c->have_particles = h.have_particles != 0;
+  c->last_direct = h.last_direct != 0, c->check_blocks = h.check_blocks;
+  c->norm = h.norm;
+  return SEDIMI_OK;
+}
+
 int sedimi_get_stats(sedimi_ctx* c, sedimi_stats* out) {
   int rc = need_ws(c);
   if (rc) return rc;
@@ -1047,6 +1146,7 @@ int sedimi_get_stats(sedimi_ctx* c, sedimi_stats* out) {
   out->nn_calls = c->nn_calls;
   out->nn_fallbacks = c->nn_fallbacks;
   out->nn_last_check = c->nn_last_check;
+  out->particles = c->n;
   if (c->have_particles && c->n > 0) {
     const size_t n = (size_t)c->n;
     std::vector<int> cnt;

@@ -109,6 +109,9 @@ def test_calls_before_a_workspace_fail_cleanly(L):
         assert b"workspace" in L.sedimi_last_error(ctx)
         assert L.sedimi_average(ctx) == sm.ENOMEM
         assert L.sedimi_smooth(ctx, 1) == sm.ENOMEM
+        size = C.c_size_t(0)
+        assert L.sedimi_get_state(ctx, None, 0, C.byref(size)) == sm.ENOMEM
+        assert L.sedimi_set_state(ctx, None, 0) == sm.ENOMEM
         # a misaligned workspace is refused before any device call
         assert L.sedimi_bind_workspace(ctx, C.c_void_p(0x1001), 1 << 30) == sm.EINVAL
         assert b"aligned" in L.sedimi_last_error(ctx)

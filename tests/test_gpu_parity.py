@@ -397,6 +397,42 @@ def test_checkpoint_resume_continues_the_run():
         want["omega"]).max()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_state_blob_resume_is_bit_exact(precision):
+    """N + N steps through sedimi_get_state / sedimi_set_state equal 2N steps
+    bit for bit: particles, accelerations, contact history and the averaged
+    fields; a blob from another layout is refused."""
+    import paper_1601_03801_amd as sm
+    case = dense_bed(3000, 17)
+    a = gpu_context(case, precision=precision)
+    a.average()
+    a.compute_forces(update_history=True)
+    a.step(7, 5)  # odd: the double buffers end in their second position
+    blob = a.get_state()
+    a.step(13, 5)
+    want = (a.get_particles(), a.get_accel(), a.get_history(), a.get_field(1), a.stats())
+    b = sm.Sedimi(dict(case["params"]), len(case["d"]), precision=precision,
+                  d_max=float(case["d"].max()), skin=0.1 * float(case["d"].max()),
+                  max_neighbors=24)
+    b.set_state(blob)
+    assert b.n == len(case["d"])
+    b.step(13, 5)
+    got = (b.get_particles(), b.get_accel(), b.get_history(), b.get_field(1), b.stats())
+    for k in ("x", "v", "omega", "a"):
+        assert np.array_equal(got[0][k], want[0][k]), k
+    assert np.array_equal(got[1]["alpha"], want[1]["alpha"])
+    assert np.array_equal(got[2], want[2])
+    assert np.array_equal(got[3], want[3])
+    assert got[4]["steps"] == want[4]["steps"] == 20
+    assert got[4]["rebuilds"] == want[4]["rebuilds"]
+    # another mesh: refused, and the context keeps working
+    other = dict(case["params"], nz=case["params"]["nz"] + 1)
+    c = gpu_context(dict(case, params=other), precision=precision)
+    with pytest.raises(sm.SedimiError):
+        c.set_state(blob)
+    c.step(1, 0)
+
+
 def test_short_trajectory(orc):
     w = workloads.workload("small")
     prm = w["params"]
