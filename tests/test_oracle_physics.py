@@ -412,3 +412,35 @@ def test_lift_vanishes_without_vorticity_or_slip(orc):
     assert np.abs(comps["lift"]).max() < 1e-12 * RHO * D ** 3  # moving with the fluid
     comps, _ = _lift_case(orc, lambda x, y, z: (g * z, 0 * z, 0 * z), c_lift=0.0)
     assert not comps["lift"].any()
+
+
+def test_lift_curl_wraps_periodically_and_takes_the_discrete_derivative(orc):
+    """U = (A sin(2 pi y / Ly), 0, 0) on the 4-cell periodic y axis: at the
+    cell centre next to the seam (j = 0) the central difference reaches
+    across it, and the discrete curl is omega_z = -A sin(k h)/h cos(k y_c)
+    (k = 2 pi / Ly), not the continuous -A k cos(k y_c).  A particle at rest
+    at that centre lags the flow by s = A sin(k y_c), and the lift is
+    C_l rho_f nu^(1/2) d^2 |omega_z|^(1/2) s along -sign(omega_z) y."""
+    A, L, ny = 0.08, 2e-3, 4
+    kk, h = 2 * math.pi / L, L / ny
+    yc = 0.5 * h
+    prm = workloads.base_params(nx=4, ny=ny, nz=8, Lx=L, Ly=L, Lz=2e-3, drag_law="none",
+                                lubrication=0, fluid_forces=0, bottom_wall=0, top_wall=0,
+                                c_lift=1.6)
+    k, j, i = np.meshgrid(np.arange(8), np.arange(ny), np.arange(4), indexing="ij")
+    cy = (j + 0.5) * h
+    U = np.stack([A * np.sin(kk * cy.ravel()), 0 * cy.ravel(), 0 * cy.ravel()], axis=1)
+    x = np.array([[2.5 * (L / 4), yc, 4.5 * (2e-3 / 8)]])  # a cell centre, j = 0
+    comps, _ = orc.forces(prm, x, np.zeros((1, 3)), np.zeros((1, 3)), np.full(1, D),
+                          np.full(1, RHO), U=U)
+    f = comps["lift"][0]
+    om = -A * math.sin(kk * h) / h * math.cos(kk * yc)
+    s = A * math.sin(kk * yc)
+    nu = workloads.MU_F / workloads.RHO_F
+    want = 1.6 * workloads.RHO_F * math.sqrt(nu) * D * D / math.sqrt(abs(om)) * (-s * om)
+    assert f[0] == 0 and f[2] == 0
+    assert abs(f[1] - want) < 1e-12 * abs(want)
+    # the continuous derivative would give a different value: the pin is sharp
+    om_c = -A * kk * math.cos(kk * yc)
+    want_c = 1.6 * workloads.RHO_F * math.sqrt(nu) * D * D / math.sqrt(abs(om_c)) * (-s * om_c)
+    assert abs(want_c - want) > 1e-3 * abs(want)
