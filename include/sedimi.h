@@ -259,14 +259,14 @@ int sedimi_get_particles(sedimi_ctx* ctx, double* x, double* v, double* omega, d
 int sedimi_get_accel(sedimi_ctx* ctx, double* a, double* alpha);
 /* Checkpoint of the whole context as one opaque blob: the device workspace
  * (particles in their sorted order, neighbour lists, contact history, mesh
- * fields, network) and the host-side counters.  A context with the same mesh,
- * capacity and options restores it with sedimi_set_state and continues the
- * run bit for bit (physical parameters are those of the restoring context).
+ * fields, network) and the host-side counters.  A context created with the
+ * same parameters and capacity restores it with sedimi_set_state and
+ * continues the run bit for bit.
  * get: *size_out receives the blob size (about the workspace size); the blob
  * is written only if buf is non-NULL and cap >= that size, else ENOMEM when
- * buf is non-NULL.  set: EINVAL if the blob is malformed or from a context of
- * another layout.  Both synchronise the stream; host buffers are the
- * caller's. */
+ * buf is non-NULL.  set: EINVAL if the blob is malformed or from a context
+ * with other parameters or capacity.  Both synchronise the stream; host
+ * buffers are the caller's. */
 int sedimi_get_state(sedimi_ctx* ctx, void* buf, size_t cap, size_t* size_out);
 int sedimi_set_state(sedimi_ctx* ctx, const void* buf, size_t size);
 int sedimi_get_forces(sedimi_ctx* ctx, int component, double* f);

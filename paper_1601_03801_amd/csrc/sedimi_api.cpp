@@ -1048,6 +1048,9 @@ struct StateHeader {
   uint32_t swapped;  // double buffers in their second position: vel, omg, pos, rb
   int32_t pad1;
   NNNorm norm;
+  // the device parameters (every physical parameter the kernels and the
+  // workspace's derived tables and fields depend on), particle count zeroed
+  DevParams P;
 };
 constexpr char kStateMagic[8] = {'S', 'E', 'D', 'I', 'M', 'I', 'S', '1'};
 
@@ -1084,6 +1087,8 @@ int sedimi_get_state(sedimi_ctx* c, void* buf, size_t cap, size_t* size_out) {
   h.avg_mode = c->avg_mode, h.have_particles = c->have_particles ? 1 : 0;
   h.last_direct = c->last_direct ? 1 : 0, h.check_blocks = c->check_blocks;
   h.norm = c->norm;
+  memcpy(&h.P, &c->P, sizeof(DevParams));  // bytes, padding included
+  h.P.n = 0;
   DevArrays canon{};
   layout(c, c->ws, &canon);
   h.swapped = (c->A.vel != canon.vel ? 1u : 0u) | (c->A.omg != canon.omg ? 2u : 0u) |
@@ -1111,6 +1116,12 @@ int sedimi_set_state(sedimi_ctx* c, const void* buf, size_t size) {
     return fail(c, SEDIMI_EINVAL, "state blob from a context of another layout");
   if (h.n < 0 || h.n > c->cap || h.swapped > 15u)
     return fail(c, SEDIMI_EINVAL, "state blob out of range");
+  // c->P is value-initialised (zero padding) and both sides are copied as bytes
+  DevParams here;
+  memcpy(&here, &c->P, sizeof(DevParams));
+  here.n = 0;
+  if (memcmp(&here, &h.P, sizeof(DevParams)) != 0)
+    return fail(c, SEDIMI_EINVAL, "state blob from a context with other parameters");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(c->ws, (const char*)buf + sizeof(h), c->ws_bytes, hipMemcpyHostToDevice));
   layout(c, c->ws, &c->A);

@@ -425,9 +425,14 @@ def test_state_blob_resume_is_bit_exact(precision):
     assert np.array_equal(got[3], want[3])
     assert got[4]["steps"] == want[4]["steps"] == 20
     assert got[4]["rebuilds"] == want[4]["rebuilds"]
-    # another mesh: refused, and the context keeps working
+    # another mesh, or the same layout with another physical parameter:
+    # refused, and the context keeps working
     other = dict(case["params"], nz=case["params"]["nz"] + 1)
     c = gpu_context(dict(case, params=other), precision=precision)
+    with pytest.raises(sm.SedimiError):
+        c.set_state(blob)
+    c.step(1, 0)
+    c = gpu_context(dict(case, params=dict(case["params"], c_add=0.25)), precision=precision)
     with pytest.raises(sm.SedimiError):
         c.set_state(blob)
     c.step(1, 0)
