@@ -7,8 +7,9 @@
  * Newton's equations (Eq. 1a-1b) with contact, lubrication and fluid-particle
  * forces (Sections 2.1, 2.3, 2.5); the fluid is given on an Eulerian mesh
  * (Section 2.2; frozen here: velocity, pressure gradient and material
- * derivative per cell); the particles' volume and drag are averaged back onto
- * the mesh by deposition (Eq. 11) and implicit diffusion (Eq. 12).
+ * derivative per cell); the particles' volume, drag and (optionally) volume
+ * flux are averaged back onto the mesh by deposition (Eq. 11) and implicit
+ * diffusion (Eq. 12).
  *
  * Conventions (SI units throughout):
  *   - axes: x streamwise and y spanwise, both periodic on [0, L); z
@@ -17,7 +18,8 @@
  *     sedimi_set_particles), vectors [n][3] row-major, scalars [n];
  *   - mesh cell (i, j, k) has index (k*ny + j)*nx + i; vector fields are
  *     [ncell][3], averaged fields are [4][ncell] (channel 0 = solid volume
- *     fraction, channels 1..3 = drag force density on the particles);
+ *     fraction, channels 1..3 = drag force density on the particles), or
+ *     [7][ncell] with avg_solid_velocity (channels 4..6 = solid volume flux);
  *   - host arrays passed in are copied, never retained; host arrays passed
  *     out are filled before the call returns (those calls synchronise the
  *     bound stream);
