@@ -18,7 +18,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liborc.so")
-_SOURCES = ["orc_pairs.c", "orc_forces.c", "orc_average.c", "orc_cnn.c"]
+_SOURCES = ["orc_pairs.c", "orc_forces.c", "orc_average.c", "orc_cnn.c", "orc_mesh.c"]
 
 DRAG = {"none": 0, "difelice": 1, "stokes": 2, "syamlal": 3}
 WALL_BOTTOM = -1
@@ -53,7 +53,7 @@ class orc_params(C.Structure):
         ("eps_s_max", C.c_double),
         ("avg_bandwidth", C.c_double), ("avg_ntau", C.c_int), ("cg_rtol", C.c_double),
         ("avg_bandwidth_z", C.c_double), ("c_lift", C.c_double),
-        ("avg_scheme", C.c_int),
+        ("avg_scheme", C.c_int), ("z_grading", C.c_double),
     ]
 
 

@@ -57,7 +57,16 @@ typedef struct {
   double avg_bandwidth_z;    /* bandwidth along z (m); 0: avg_bandwidth */
   double c_lift;             /* lift coefficient C_l of Eq. (particleLift); 0: no lift */
   int avg_scheme;            /* pseudo-time scheme: ORC_SCHEME_EULER or ORC_SCHEME_BDF2 */
+  double z_grading;          /* top / bottom cell height ratio of a geometrically graded
+                                z mesh; <= 0 or 1: uniform */
 } orc_params;
+
+/* ---- mesh geometry along z (orc_mesh.c) ---- */
+int orc_graded(const orc_params* p);
+/* faces zf[0..nz]: 0 = zf[0] < ... < zf[nz] = Lz */
+void orc_z_faces(const orc_params* p, double* zf);
+/* cell k with zf[k] <= z < zf[k+1], clamped to [0, nz - 1] */
+int orc_z_cell(const double* zf, int nz, double z);
 
 /* One tangential-history record.  Particle pairs carry i < j (IDs); a wall
  * contact carries j = ORC_WALL_BOTTOM or ORC_WALL_TOP.  xi is the tangential

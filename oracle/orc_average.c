@@ -45,20 +45,48 @@
 #define M_PI 3.14159265358979323846
 #endif
 
+/* Mesh cell of a position and the volumes of the cells, uniform or graded
+ * along z (faces from orc_z_faces). */
+typedef struct {
+  double hx, hy, hz;
+  double* zf; /* graded meshes only: faces [nz + 1] */
+} orc_cells;
+
+static int cells_open(const orc_params* p, orc_cells* m) {
+  m->hx = p->Lx / p->nx, m->hy = p->Ly / p->ny, m->hz = p->Lz / p->nz;
+  m->zf = NULL;
+  if (orc_graded(p)) {
+    m->zf = (double*)malloc(sizeof(double) * (size_t)(p->nz + 1));
+    if (!m->zf) return -2;
+    orc_z_faces(p, m->zf);
+  }
+  return 0;
+}
+
+static int64_t cell_of(const orc_params* p, const orc_cells* m, const double* xp) {
+  int64_t a = (int64_t)floor(xp[0] / m->hx);
+  int64_t b = (int64_t)floor(xp[1] / m->hy);
+  int64_t c = m->zf ? (int64_t)orc_z_cell(m->zf, p->nz, xp[2]) : (int64_t)floor(xp[2] / m->hz);
+  a = a < 0 ? 0 : (a >= p->nx ? p->nx - 1 : a);
+  b = b < 0 ? 0 : (b >= p->ny ? p->ny - 1 : b);
+  c = c < 0 ? 0 : (c >= p->nz ? p->nz - 1 : c);
+  return (c * p->ny + b) * p->nx + a;
+}
+
+static double cell_volume(const orc_params* p, const orc_cells* m, int64_t k) {
+  if (!m->zf) return m->hx * m->hy * m->hz;
+  const int64_t c = k / ((int64_t)p->nx * p->ny);
+  return m->hx * m->hy * (m->zf[c + 1] - m->zf[c]);
+}
+
 int orc_deposit(const orc_params* p, int64_t n, const double* x, const double* d,
                 const double* fdrag, double* raw) {
   int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
-  double hx = p->Lx / p->nx, hy = p->Ly / p->ny, hz = p->Lz / p->nz;
-  double Vc = hx * hy * hz;
+  orc_cells m;
+  if (cells_open(p, &m)) return -2;
   memset(raw, 0, sizeof(double) * 4 * (size_t)ncell);
   for (int64_t i = 0; i < n; ++i) {
-    int64_t a = (int64_t)floor(x[3 * i] / hx);
-    int64_t b = (int64_t)floor(x[3 * i + 1] / hy);
-    int64_t c = (int64_t)floor(x[3 * i + 2] / hz);
-    a = a < 0 ? 0 : (a >= p->nx ? p->nx - 1 : a);
-    b = b < 0 ? 0 : (b >= p->ny ? p->ny - 1 : b);
-    c = c < 0 ? 0 : (c >= p->nz ? p->nz - 1 : c);
-    int64_t k = (c * p->ny + b) * p->nx + a;
+    int64_t k = cell_of(p, &m, x + 3 * i);
     double V = (M_PI / 6.0) * d[i] * d[i] * d[i];
     raw[k] += V;
     if (fdrag) {
@@ -67,28 +95,30 @@ int orc_deposit(const orc_params* p, int64_t n, const double* x, const double* d
       raw[3 * ncell + k] += fdrag[3 * i + 2];
     }
   }
-  for (int64_t k = 0; k < 4 * ncell; ++k) raw[k] /= Vc;
+  for (int64_t k = 0; k < ncell; ++k) {
+    const double Vc = cell_volume(p, &m, k);
+    for (int ch = 0; ch < 4; ++ch) raw[ch * ncell + k] /= Vc;
+  }
+  free(m.zf);
   return 0;
 }
 
 int orc_deposit_flux(const orc_params* p, int64_t n, const double* x, const double* d,
                      const double* v, double* flux) {
   int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
-  double hx = p->Lx / p->nx, hy = p->Ly / p->ny, hz = p->Lz / p->nz;
-  double Vc = hx * hy * hz;
+  orc_cells m;
+  if (cells_open(p, &m)) return -2;
   memset(flux, 0, sizeof(double) * 3 * (size_t)ncell);
   for (int64_t i = 0; i < n; ++i) {
-    int64_t a = (int64_t)floor(x[3 * i] / hx);
-    int64_t b = (int64_t)floor(x[3 * i + 1] / hy);
-    int64_t c = (int64_t)floor(x[3 * i + 2] / hz);
-    a = a < 0 ? 0 : (a >= p->nx ? p->nx - 1 : a);
-    b = b < 0 ? 0 : (b >= p->ny ? p->ny - 1 : b);
-    c = c < 0 ? 0 : (c >= p->nz ? p->nz - 1 : c);
-    int64_t k = (c * p->ny + b) * p->nx + a;
+    int64_t k = cell_of(p, &m, x + 3 * i);
     double V = (M_PI / 6.0) * d[i] * d[i] * d[i];
     for (int e = 0; e < 3; ++e) flux[e * ncell + k] += V * v[3 * i + e];
   }
-  for (int64_t k = 0; k < 3 * ncell; ++k) flux[k] /= Vc;
+  for (int64_t k = 0; k < ncell; ++k) {
+    const double Vc = cell_volume(p, &m, k);
+    for (int e = 0; e < 3; ++e) flux[e * ncell + k] /= Vc;
+  }
+  free(m.zf);
   return 0;
 }
 
@@ -106,9 +136,17 @@ void orc_apply_A(const orc_params* p, double dtau, const double* x, double* y) {
   double ix2 = 1.0 / ((p->Lx / nx) * (p->Lx / nx));
   double iy2 = 1.0 / ((p->Ly / ny) * (p->Ly / ny));
   double iz2 = 1.0 / ((p->Lz / nz) * (p->Lz / nz));
+  double kz = 1.0; /* diffusivity along z */
   if (p->avg_bandwidth_z > 0.0 && p->avg_bandwidth > 0.0) {
     const double r = p->avg_bandwidth_z / p->avg_bandwidth;
-    iz2 *= r * r;  /* diffusivity along z */
+    iz2 *= r * r;
+    kz = r * r;
+  }
+  double* zf = NULL;
+  if (orc_graded(p)) {
+    zf = (double*)malloc(sizeof(double) * (size_t)(nz + 1));
+    if (!zf) abort();
+    orc_z_faces(p, zf);
   }
   for (int k = 0; k < nz; ++k) {
     for (int j = 0; j < ny; ++j) {
@@ -122,12 +160,25 @@ void orc_apply_A(const orc_params* p, double dtau, const double* x, double* y) {
         lap += (x[((int64_t)k * ny + j) * nx + im] - xc) * ix2;
         lap += (x[((int64_t)k * ny + jp) * nx + i] - xc) * iy2;
         lap += (x[((int64_t)k * ny + jm) * nx + i] - xc) * iy2;
-        if (k + 1 < nz) lap += (x[((int64_t)(k + 1) * ny + j) * nx + i] - xc) * iz2;
-        if (k > 0) lap += (x[((int64_t)(k - 1) * ny + j) * nx + i] - xc) * iz2;
+        if (zf) {
+          /* graded: flux through each face over the centre distance, per
+           * unit cell height */
+          const double hk = zf[k + 1] - zf[k], zc = 0.5 * (zf[k] + zf[k + 1]);
+          if (k + 1 < nz)
+            lap += (x[((int64_t)(k + 1) * ny + j) * nx + i] - xc) * kz /
+                   (hk * (0.5 * (zf[k + 1] + zf[k + 2]) - zc));
+          if (k > 0)
+            lap += (x[((int64_t)(k - 1) * ny + j) * nx + i] - xc) * kz /
+                   (hk * (zc - 0.5 * (zf[k - 1] + zf[k])));
+        } else {
+          if (k + 1 < nz) lap += (x[((int64_t)(k + 1) * ny + j) * nx + i] - xc) * iz2;
+          if (k > 0) lap += (x[((int64_t)(k - 1) * ny + j) * nx + i] - xc) * iz2;
+        }
         y[c] = xc - dtau * lap;
       }
     }
   }
+  free(zf);
 }
 
 static double dotn(int64_t n, const double* a, const double* b) {
@@ -136,21 +187,61 @@ static double dotn(int64_t n, const double* a, const double* b) {
   return s;
 }
 
-/* Solve (I - dtau L_h) x = b by conjugate gradients, starting from x = b. */
-static int cg_solve(const orc_params* p, double dtau, const double* b, double* x,
+/* y = H (I - dtau L_h) x with H the cell heights of a graded mesh: the
+ * finite-volume operator scaled by the cell volumes, symmetric where
+ * I - dtau L_h itself is not. */
+static void apply_S(const orc_params* p, double dtau, const double* hcell, const double* x,
+                    double* y) {
+  const int64_t n = (int64_t)p->nx * p->ny * p->nz, plane = (int64_t)p->nx * p->ny;
+  orc_apply_A(p, dtau, x, y);
+  for (int64_t c = 0; c < n; ++c) y[c] *= hcell[c / plane];
+}
+
+static void apply_op(const orc_params* p, double dtau, const double* hcell, const double* x,
+                     double* y) {
+  if (hcell)
+    apply_S(p, dtau, hcell, x, y);
+  else
+    orc_apply_A(p, dtau, x, y);
+}
+
+/* Solve (I - dtau L_h) x = b by conjugate gradients, starting from x = b; on
+ * a graded mesh the system multiplied by the cell heights, which makes it
+ * symmetric positive definite. */
+static int cg_solve(const orc_params* p, double dtau, const double* b_in, double* x,
                     int64_t* iters, double* r, double* pv, double* Ap) {
   int64_t n = (int64_t)p->nx * p->ny * p->nz;
-  memcpy(x, b, sizeof(double) * (size_t)n);
+  memcpy(x, b_in, sizeof(double) * (size_t)n);
+  double* hcell = NULL;
+  double* bw = NULL;
+  const double* b = b_in;
+  if (orc_graded(p)) {
+    const int64_t plane = (int64_t)p->nx * p->ny;
+    hcell = (double*)malloc(sizeof(double) * (size_t)(p->nz + 1));
+    bw = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!hcell || !bw) {
+      free(hcell), free(bw);
+      return -2;
+    }
+    orc_z_faces(p, hcell);
+    for (int k = 0; k < p->nz; ++k) hcell[k] = hcell[k + 1] - hcell[k];
+    for (int64_t c = 0; c < n; ++c) bw[c] = b_in[c] * hcell[c / plane];
+    b = bw;
+  }
+  int rc = 0;
   double bn = sqrt(dotn(n, b, b));
-  if (bn == 0.0) return 0;
-  orc_apply_A(p, dtau, x, Ap);
+  if (bn == 0.0) goto done;
+  apply_op(p, dtau, hcell, x, Ap);
   for (int64_t k = 0; k < n; ++k) r[k] = b[k] - Ap[k];
   memcpy(pv, r, sizeof(double) * (size_t)n);
   double rr = dotn(n, r, r);
   int64_t it = 0;
   while (sqrt(rr) > p->cg_rtol * bn) {
-    if (it > 10000) return -3;
-    orc_apply_A(p, dtau, pv, Ap);
+    if (it > 10000) {
+      rc = -3;
+      goto done;
+    }
+    apply_op(p, dtau, hcell, pv, Ap);
     double alpha = rr / dotn(n, pv, Ap);
     for (int64_t k = 0; k < n; ++k) {
       x[k] += alpha * pv[k];
@@ -163,7 +254,9 @@ static int cg_solve(const orc_params* p, double dtau, const double* b, double* x
     ++it;
   }
   if (iters) *iters += it;
-  return 0;
+done:
+  free(hcell), free(bw);
+  return rc;
 }
 
 int orc_diffuse(const orc_params* p, int nch, const double* in, double* out, int64_t* iters) {

@@ -155,6 +155,24 @@ static void interp_weights(const orc_params* p, const double* xp, int64_t idx[8]
   if (p->nz == 1) {
     k0 = k1 = 0;
     fz = 0.0;
+  } else if (orc_graded(p)) {
+    /* graded: linear between the two cell centres around z, clamped to the
+     * first / last centre */
+    double zf[p->nz + 1];
+    orc_z_faces(p, zf);
+    const double z = xp[2];
+    const double zlo = 0.5 * (zf[0] + zf[1]), zhi = 0.5 * (zf[p->nz - 1] + zf[p->nz]);
+    if (!(z > zlo)) {
+      k0 = 0, fz = 0.0;
+    } else if (z >= zhi) {
+      k0 = p->nz - 2, fz = 1.0;
+    } else {
+      k0 = 0;
+      while (k0 + 1 < p->nz - 1 && 0.5 * (zf[k0 + 1] + zf[k0 + 2]) <= z) ++k0;
+      const double c0 = 0.5 * (zf[k0] + zf[k0 + 1]), c1 = 0.5 * (zf[k0 + 1] + zf[k0 + 2]);
+      fz = (z - c0) / (c1 - c0);
+    }
+    k1 = k0 + 1;
   } else {
     if (sz < 0.0) sz = 0.0;
     if (sz > p->nz - 1) sz = p->nz - 1;
@@ -195,6 +213,15 @@ static double interp_scalar(const double* f, const int64_t idx[8], const double 
 static void curl_cells(const orc_params* p, const double* U, double* om) {
   const int nx = p->nx, ny = p->ny, nz = p->nz;
   const double hx = p->Lx / nx, hy = p->Ly / ny, hz = p->Lz / nz;
+  /* graded meshes: cell-centre heights for the z differences */
+  double zcv[nz > 0 ? nz : 1];
+  const double* zc = NULL;
+  if (orc_graded(p)) {
+    double zf[nz + 1];
+    orc_z_faces(p, zf);
+    for (int k = 0; k < nz; ++k) zcv[k] = 0.5 * (zf[k] + zf[k + 1]);
+    zc = zcv;
+  }
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
@@ -213,7 +240,8 @@ static void curl_cells(const orc_params* p, const double* U, double* om) {
             const int kp = k + 1 < nz ? k + 1 : k, km = k > 0 ? k - 1 : k;
             const int64_t zp = ((int64_t)kp * ny + j) * nx + i;
             const int64_t zm = ((int64_t)km * ny + j) * nx + i;
-            dUdz[a] = (U[3 * zp + a] - U[3 * zm + a]) / ((double)(kp - km) * hz);
+            dUdz[a] = (U[3 * zp + a] - U[3 * zm + a]) /
+                      (zc ? zc[kp] - zc[km] : (double)(kp - km) * hz);
           }
         }
         om[3 * c + 0] = dUdy[2] - dUdz[1];

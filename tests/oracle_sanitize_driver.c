@@ -131,6 +131,14 @@ int main(void) {
   p.avg_ntau = 0;
   CHECK(orc_diffuse(&p, 1, raw, sm, &iters));
 
+  /* the same on a z mesh graded towards the bottom */
+  p.z_grading = 5.0, p.avg_ntau = 3, p.avg_scheme = ORC_SCHEME_EULER;
+  CHECK(orc_deposit(&p, n, x, d, fd, raw));
+  CHECK(orc_deposit_flux(&p, n, x, d, v, raw + 4 * ncell));
+  CHECK(orc_diffuse(&p, 7, raw, sm, &iters));
+  nh = 0;
+  CHECK(orc_forces(&p, n, x, v, w, d, rho, NULL, &fl, NULL, 0, hist, 16 * n + 64, &nh, &out));
+
   /* network: one conv forward / backward, the loss gradient, an Adam step */
   const int mx = 5, my = 4, mz = 6, C = 4;
   const int64_t m = (int64_t)mx * my * mz;

@@ -12,7 +12,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 ORACLE = os.path.join(ROOT, "oracle")
-SOURCES = ["orc_pairs.c", "orc_forces.c", "orc_average.c", "orc_cnn.c"]
+SOURCES = ["orc_pairs.c", "orc_forces.c", "orc_average.c", "orc_cnn.c", "orc_mesh.c"]
 
 
 def test_oracle_clean_under_address_and_undefined_sanitizers(tmp_path):

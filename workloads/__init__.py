@@ -89,6 +89,7 @@ def base_params(**kw):
         drag_law="difelice", lubrication=1, fluid_forces=1, bottom_wall=1, top_wall=1,
         eps_s_max=0.7, avg_bandwidth=3 * D50, avg_ntau=4, cg_rtol=1e-14,
         avg_bandwidth_z=0.0, c_lift=0.0, avg_scheme=0,
+        z_grading=0.0,
     )
     p.update(kw)
     return p
