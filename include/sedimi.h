@@ -146,6 +146,10 @@ typedef struct {
   int avg_scheme;            /* pseudo-time scheme of the averaging (Section 2.4):
                                 SEDIMI_SCHEME_EULER, or SEDIMI_SCHEME_BDF2 (either
                                 solver; not with nn_enable) */
+  double z_grading;          /* top / bottom cell height ratio of a z mesh graded
+                                towards the bottom wall (Section 4's channel case);
+                                0 or 1: uniform.  Graded meshes are not built on the
+                                GPU yet: any other value is refused (EINVAL) */
 } sedimi_params;
 
 /* avg_scheme: backward Euler, (I - dtau L) phi^{m+1} = phi^m; or the two-step

@@ -54,7 +54,7 @@ class sedimi_params(C.Structure):
         ("nn_sample", C.c_double), ("nn_seed", C.c_uint64),
         ("avg_solver", C.c_int),
         ("avg_bandwidth_z", C.c_double), ("c_lift", C.c_double),
-        ("avg_solid_velocity", C.c_int), ("avg_scheme", C.c_int),
+        ("avg_solid_velocity", C.c_int), ("avg_scheme", C.c_int), ("z_grading", C.c_double),
     ]
 
 

@@ -244,6 +244,8 @@ int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
     return fail(c, SEDIMI_EINVAL, "max_neighbors must be in 1..30");
   if (p.nn_enable && !(p.nn_alpha >= 0 && p.nn_bound > 0 && p.nn_sample > 0 && p.nn_sample <= 1))
     return fail(c, SEDIMI_EINVAL, "surrogate parameters out of range");
+  if (!(p.z_grading == 0.0 || p.z_grading == 1.0))
+    return fail(c, SEDIMI_EINVAL, "graded z meshes are not supported on the GPU (z_grading 0 or 1)");
   if (p.avg_scheme != SEDIMI_SCHEME_EULER && p.avg_scheme != SEDIMI_SCHEME_BDF2)
     return fail(c, SEDIMI_EINVAL, "unknown averaging scheme");
   if (p.avg_scheme == SEDIMI_SCHEME_BDF2 && p.nn_enable)

@@ -68,6 +68,7 @@ int main() {
       {"us+nn", [](sedimi_params& q) { q.avg_solid_velocity = 1; q.nn_enable = 1; }},
       {"slots", [](sedimi_params& q) { q.max_neighbors = 0; }},
       {"narrow", [](sedimi_params& q) { q.Lx = 2 * q.d_max; }},
+      {"graded", [](sedimi_params& q) { q.z_grading = 4.0; }},
   };
   for (const Bad& b : bad) {
     sedimi_params q = base();

@@ -97,6 +97,13 @@ def test_create_checks_parameters(L):
     assert rc == sm.EINVAL and not ctx.value
     rc, ctx = create(L, dict(prm, avg_scheme=2))
     assert rc == sm.EINVAL
+    # graded z meshes: the oracle has them, the GPU path refuses them for now
+    for g in (0.0, 1.0):
+        rc, ctx = create(L, dict(prm, z_grading=g))
+        assert rc == sm.OK
+        L.sedimi_destroy(ctx)
+    rc, ctx = create(L, dict(prm, z_grading=4.0))
+    assert rc == sm.EINVAL and not ctx.value
     rc, ctx = create(L, prm, cap=-1)
     assert rc == sm.EINVAL
 
@@ -119,3 +126,33 @@ def test_calls_before_a_workspace_fail_cleanly(L):
         L.sedimi_destroy(ctx)
     assert L.sedimi_step(None, 1, 0) == sm.EINVAL
     assert L.sedimi_last_error(None) == b"null context"
+
+
+STRUCTS = (("sedimi_params", sm.sedimi_params), ("sedimi_stats", sm.sedimi_stats),
+           ("sedimi_profile", sm.sedimi_profile))
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """The ctypes mirrors of sedimi_params, sedimi_stats and sedimi_profile have the C
+    header's size and field offsets (a drift would pass garbage across the
+    boundary)."""
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc is not available")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sedimi.h"', 'int main(void) {']
+    for struct, cls in STRUCTS:
+        lines.append(f'  printf("{struct} %zu\\n", sizeof({struct}));')
+        for name, _ in cls._fields_:
+            lines.append(f'  printf("{struct}.{name} %zu\\n", offsetof({struct}, {name}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = str(tmp_path / "layout")
+    subprocess.run([gcc, "-I", os.path.dirname(HEADER), str(src), "-o", exe], check=True,
+                   capture_output=True, timeout=120)
+    got = dict(ln.split() for ln in subprocess.run([exe], capture_output=True, text=True,
+                                                    check=True).stdout.splitlines())
+    for struct, cls in STRUCTS:
+        assert int(got[struct]) == C.sizeof(cls), struct
+        for name, _ in cls._fields_:
+            assert int(got[f"{struct}.{name}"]) == getattr(cls, name).offset, (struct, name)
