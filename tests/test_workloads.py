@@ -88,3 +88,30 @@ def test_time_step_is_one_fiftieth_of_the_shortest_contact():
     wn = math.sqrt(k / me)
     tc = math.pi / (wn * math.sqrt(1 - zeta ** 2))
     assert abs(workloads.dt_rule(prm, dmin) - tc / 50) < 1e-15 * tc
+
+
+def test_graded_mesh_geometry_and_fields():
+    """z_grading: geometric faces with the requested top/bottom height
+    ratio; the log law is sampled at the graded centres, and the convective
+    derivative of a field linear in z is exact on them."""
+    prm = workloads.base_params(nx=4, ny=3, nz=16, Lz=8e-3, z_grading=5.0)
+    zf = workloads.z_faces(prm)
+    h = np.diff(zf)
+    assert zf[0] == 0 and zf[-1] == prm["Lz"] and np.all(h > 0)
+    assert abs(h[-1] / h[0] - 5.0) < 1e-12
+    assert np.allclose(h[1:] / h[:-1], 5.0 ** (1 / 15), rtol=1e-12)
+    _, _, zc = workloads.cell_centres(prm)
+    assert np.allclose(np.unique(zc), 0.5 * (zf[1:] + zf[:-1]), rtol=1e-15)
+    U, _, _ = workloads.fluid_fields(prm, z_bed=1e-3)
+    z0 = workloads.D50 / 30
+    above = zc - 1e-3 > z0
+    assert np.allclose(U[above, 0], workloads.U_STAR / workloads.KAPPA *
+                       np.log((zc[above] - 1e-3) / z0), rtol=1e-14)
+    V = np.zeros((zc.size, 3))
+    V[:, 0] = 0.3
+    V[:, 2] = 0.01 + 2.0 * zc  # w grows linearly with z: w dw/dz = w * 2
+    got = workloads.convective_derivative(prm, V)
+    assert np.allclose(got[:, 2], V[:, 2] * 2.0, rtol=1e-12)
+    # uniform meshes are unchanged by the option's default
+    assert np.array_equal(workloads.z_faces(workloads.base_params()),
+                          workloads.base_params()["Lz"] * np.arange(9) / 8)

@@ -145,11 +145,33 @@ def bed_top(x, d, Lx, Ly, nbins=16):
 # frozen fluid fields (stand-in for the CFD solution)
 # ----------------------------------------------------------------------------
 
+def z_faces(prm):
+    """Cell faces along z: uniform, or graded geometrically towards the
+    bottom with z_grading = top / bottom cell height (0 or 1: uniform)."""
+    nz, Lz, g = prm["nz"], prm["Lz"], prm.get("z_grading", 0.0)
+    if not _graded(prm):
+        return Lz * np.arange(nz + 1) / nz
+    h = g ** (np.arange(nz) / (nz - 1))
+    zf = np.concatenate([[0.0], np.cumsum(h * (Lz / h.sum()))])
+    zf[-1] = Lz
+    return zf
+
+
 def cell_centres(prm):
     nx, ny, nz = prm["nx"], prm["ny"], prm["nz"]
     hx, hy, hz = prm["Lx"] / nx, prm["Ly"] / ny, prm["Lz"] / nz
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    return ((i + 0.5) * hx).ravel(), ((j + 0.5) * hy).ravel(), ((k + 0.5) * hz).ravel()
+    if _graded(prm):
+        zf = z_faces(prm)
+        zc = (0.5 * (zf[1:] + zf[:-1]))[k]
+    else:
+        zc = (k + 0.5) * hz
+    return ((i + 0.5) * hx).ravel(), ((j + 0.5) * hy).ravel(), zc.ravel()
+
+
+def _graded(prm):
+    g = prm.get("z_grading", 0.0)
+    return prm["nz"] > 1 and g > 0.0 and g != 1.0
 
 
 def fluid_fields(prm, z_bed=0.0, d=D50, u_star=U_STAR, fluct=0.0, seed=0):
@@ -186,7 +208,11 @@ def convective_derivative(prm, U):
     dfx = (np.roll(F, -1, axis=2) - np.roll(F, 1, axis=2)) / (2 * hx)
     dfy = (np.roll(F, -1, axis=1) - np.roll(F, 1, axis=1)) / (2 * hy)
     if nz > 1:
-        dfz = np.gradient(F, hz, axis=0)
+        if _graded(prm):
+            zf = z_faces(prm)
+            dfz = np.gradient(F, 0.5 * (zf[1:] + zf[:-1]), axis=0)
+        else:
+            dfz = np.gradient(F, hz, axis=0)
     else:
         dfz = np.zeros_like(F)
     out = F[..., 0:1] * dfx + F[..., 1:2] * dfy + F[..., 2:3] * dfz
