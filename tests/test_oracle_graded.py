@@ -156,3 +156,20 @@ def test_grading_one_is_the_uniform_mesh(orc):
     s0, _ = orc.diffuse(base, r0[:1])
     s1, _ = orc.diffuse(one, r1[:1])
     assert np.array_equal(s0, s1)
+
+
+def test_graded_run_with_averaging_conserves_the_solid_volume(orc):
+    """A short velocity-Verlet run of a small bed on the graded mesh with
+    averaging inside: the state stays finite and every averaging keeps the
+    total solid volume sum(eps_s V_k) equal to the particles' volume."""
+    w = workloads.workload("small")
+    prm = dict(w["params"], z_grading=4.0, avg_ntau=2)
+    st = orc.State(prm, w["x"], w["v"], w["w"], w["d"], w["rho"], U=w["U"], gradp=w["gradp"],
+                   dudt=w["dudt"])
+    st.average()
+    st.init_accel()
+    st.run(20, average_every=10)
+    assert np.all(np.isfinite(st.x)) and np.all(np.isfinite(st.v))
+    V = cell_volumes(prm)
+    Vp = (math.pi / 6 * w["d"] ** 3).sum()
+    assert abs((st.eps_s * V).sum() - Vp) < 1e-11 * Vp
