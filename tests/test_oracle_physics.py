@@ -444,3 +444,36 @@ def test_lift_curl_wraps_periodically_and_takes_the_discrete_derivative(orc):
     om_c = -A * kk * math.cos(kk * yc)
     want_c = 1.6 * workloads.RHO_F * math.sqrt(nu) * D * D / math.sqrt(abs(om_c)) * (-s * om_c)
     assert abs(want_c - want) > 1e-3 * abs(want)
+
+
+def _difelice_force(orc, d, w, eps_f):
+    prm = workloads.base_params(nx=1, ny=1, nz=1, drag_law="difelice", lubrication=0,
+                                fluid_forces=0, bottom_wall=0, top_wall=0)
+    comps, _ = orc.forces(prm, np.array([[1e-3, 1e-3, 1e-3]]), np.zeros((1, 3)), np.zeros((1, 3)),
+                          np.full(1, d), np.full(1, RHO), U=np.array([[w, 0.0, 0.0]]),
+                          eps_s=np.array([1.0 - eps_f]))
+    return comps["drag"][0, 0]
+
+
+def test_difelice_in_a_suspension_low_re_limit(orc):
+    """eps_f < 1 as Re -> 0: chi -> 3.7 and C_d -> 23.04/Re with Re carrying
+    eps_f, so the force tends to 0.96 eps_f^(-2.7) times the Stokes drag."""
+    d, w = 10e-6, 1e-6
+    for eps_f in (0.9, 0.6, 0.45):
+        f = _difelice_force(orc, d, w, eps_f)
+        ratio = f / (3 * math.pi * workloads.MU_F * d * w)
+        assert abs(ratio / (0.96 * eps_f ** -2.7) - 1) < 2e-3, (eps_f, ratio)
+
+
+def test_difelice_voidage_factor_at_fixed_reynolds_number(orc):
+    """At a fixed particle Reynolds number (Re carries eps_f, so the slip is
+    w = Re mu / (rho_f d eps_f)) C_d and chi are fixed and the force scales
+    as eps_f^(2 - chi) w^2 ~ eps_f^(-chi); at log10 Re = 1.5 the exponent is
+    exactly chi = 3.7 - 0.65 = 3.05."""
+    d = D
+    Re = 10 ** 1.5
+    f = {}
+    for eps_f in (0.9, 0.5):
+        w = Re * workloads.MU_F / (workloads.RHO_F * d * eps_f)
+        f[eps_f] = _difelice_force(orc, d, w, eps_f)
+    assert abs(f[0.5] / f[0.9] / (0.5 / 0.9) ** -3.05 - 1) < 1e-12
