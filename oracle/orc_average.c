@@ -17,6 +17,11 @@
  *    weights are particle volumes (equal to mass weights for one particle
  *    density).  Where the smoothed eps_s is at rounding level the ratio
  *    means nothing and U_s is set to 0.
+ *  - On a z mesh graded towards the bottom (orc_mesh.c) a particle's cell is
+ *    found from the faces and each cell divides by its own volume; the
+ *    diffusion is the finite-volume operator (face flux over the centre
+ *    distance, per unit cell height), and CG solves it multiplied by the
+ *    cell heights, which makes it symmetric positive definite.
  *  - Eq. (12): the deposited field then diffuses with unit diffusivity up to
  *    pseudo-time tau = b^2/4 (b = bandwidth; the paper states the equivalence
  *    to Gaussian averaging with bandwidth sqrt(4 tau)).  The application

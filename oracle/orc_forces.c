@@ -43,6 +43,9 @@
  *    as in the correlation's source.)
  *    Eq. (4) prints the fluid-side orientation (u_p - U_f); on the particle the
  *    force points towards the fluid velocity.
+ *  - Graded z meshes (orc_mesh.c): fields are interpolated linearly between
+ *    the graded cell centres, and the curl's z differences divide by the
+ *    centre distances.
  *  - Lift (Eq. particleLift, Saffman): f = C_l rho_f nu^(1/2) d^2 |omega|^(-1/2)
  *    (U_f - u_p) x omega with omega = curl U_f at the particle (0 when
  *    omega = 0).  The printed form lacks the |omega|^(-1/2) that makes it a
