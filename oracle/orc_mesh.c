@@ -24,14 +24,14 @@ void orc_z_faces(const orc_params* p, double* zf) {
     for (int k = 1; k <= nz; ++k) zf[k] = p->Lz * k / nz;
     return;
   }
-  const double q = pow(p->z_grading, 1.0 / (nz - 1));
-  /* h_0 (1 + q + ... + q^(nz-1)) = Lz */
-  const double h0 = p->Lz * (q - 1.0) / (pow(q, nz) - 1.0);
-  double h = h0;
-  for (int k = 1; k <= nz; ++k) {
-    zf[k] = zf[k - 1] + h;
-    h *= q;
-  }
+  /* relative heights q^k = z_grading^(k/(nz-1)), summed in order and scaled
+   * to Lz (the closed form of the geometric sum, (q^nz - 1)/(q - 1), cancels
+   * as the grading tends to 1) */
+  double sum = 0.0;
+  for (int k = 0; k < nz; ++k) sum += pow(p->z_grading, (double)k / (nz - 1));
+  const double scale = p->Lz / sum;
+  for (int k = 1; k <= nz; ++k)
+    zf[k] = zf[k - 1] + pow(p->z_grading, (double)(k - 1) / (nz - 1)) * scale;
   zf[nz] = p->Lz;
 }
 

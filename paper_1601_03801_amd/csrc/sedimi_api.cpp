@@ -1053,8 +1053,33 @@ struct StateHeader {
   // the device parameters (every physical parameter the kernels and the
   // workspace's derived tables and fields depend on), particle count zeroed
   DevParams P;
+  // the averaging and network parameters that DevParams does not carry (the
+  // z-line and spectral tables in the workspace derive from the bandwidths
+  // and N_tau)
+  struct AvgParams {
+    double avg_bandwidth, avg_bandwidth_z, avg_rtol, nn_alpha, nn_bound, nn_sample;
+    uint64_t nn_seed;
+    int32_t avg_ntau, avg_scheme, avg_solver, avg_solid_velocity;
+  } avg;
 };
 constexpr char kStateMagic[8] = {'S', 'E', 'D', 'I', 'M', 'I', 'S', '1'};
+
+// Field by field into a zeroed struct (no padding bytes are compared).
+void state_avg_params(const sedimi_ctx* c, StateHeader::AvgParams* a) {
+  memset(a, 0, sizeof(*a));
+  const sedimi_params& p = c->prm;
+  a->avg_bandwidth = p.avg_bandwidth;
+  a->avg_bandwidth_z = p.avg_bandwidth_z;
+  a->avg_rtol = p.avg_rtol;
+  a->nn_alpha = p.nn_alpha;
+  a->nn_bound = p.nn_bound;
+  a->nn_sample = p.nn_sample;
+  a->nn_seed = p.nn_seed;
+  a->avg_ntau = p.avg_ntau;
+  a->avg_scheme = p.avg_scheme;
+  a->avg_solver = p.avg_solver;
+  a->avg_solid_velocity = p.avg_solid_velocity;
+}
 
 void state_layout(const sedimi_ctx* c, StateHeader* h) {
   h->ws_bytes = c->ws_bytes;
@@ -1091,6 +1116,7 @@ int sedimi_get_state(sedimi_ctx* c, void* buf, size_t cap, size_t* size_out) {
   h.norm = c->norm;
   memcpy(&h.P, &c->P, sizeof(DevParams));  // bytes, padding included
   h.P.n = 0;
+  state_avg_params(c, &h.avg);
   DevArrays canon{};
   layout(c, c->ws, &canon);
   h.swapped = (c->A.vel != canon.vel ? 1u : 0u) | (c->A.omg != canon.omg ? 2u : 0u) |
@@ -1122,8 +1148,15 @@ int sedimi_set_state(sedimi_ctx* c, const void* buf, size_t size) {
   DevParams here;
   memcpy(&here, &c->P, sizeof(DevParams));
   here.n = 0;
-  if (memcmp(&here, &h.P, sizeof(DevParams)) != 0)
+  StateHeader::AvgParams avg_here;
+  state_avg_params(c, &avg_here);
+  if (memcmp(&here, &h.P, sizeof(DevParams)) != 0 ||
+      memcmp(&avg_here, &h.avg, sizeof(avg_here)) != 0)
     return fail(c, SEDIMI_EINVAL, "state blob from a context with other parameters");
+  if (h.avg_mode < SEDIMI_AVG_PLAIN || h.avg_mode > SEDIMI_AVG_SURROGATE ||
+      (h.avg_mode != SEDIMI_AVG_PLAIN && !c->prm.nn_enable) || h.check_blocks < 0 ||
+      h.step < 0 || h.adam_t < 0)
+    return fail(c, SEDIMI_EINVAL, "state blob out of range");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(c->ws, (const char*)buf + sizeof(h), c->ws_bytes, hipMemcpyHostToDevice));
   layout(c, c->ws, &c->A);

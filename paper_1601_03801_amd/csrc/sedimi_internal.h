@@ -105,7 +105,7 @@ struct DevArrays {
   int* cid;
   double* cxi;
   int* ccnt;
-  // force breakdown (diagnostic evaluation): 7 x double4 [N]
+  // force breakdown (diagnostic evaluation): 8 x double4 [N], SEDIMI_F_* order (lift last)
   double4* comp;
   // sort scratch
   int *key, *rank, *perm, *bin_count, *bin_start, *scan_tmp;

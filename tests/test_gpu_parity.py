@@ -438,6 +438,32 @@ def test_state_blob_resume_is_bit_exact(precision):
     c.step(1, 0)
 
 
+def test_state_blob_refused_with_other_averaging_parameters():
+    """The workspace holds the z-line preconditioner and spectral tables built
+    from the averaging bandwidths and N_tau: a blob from a context that differs
+    only there is refused (iterative solver, whose layout is otherwise the same)."""
+    import paper_1601_03801_amd as sm
+    case = dense_bed(2000, 19)
+    a = gpu_context(case, solver="iterative")
+    a.average()
+    a.step(3, 0)
+    blob = a.get_state()
+    prm = case["params"]
+    for change in (dict(avg_bandwidth=1.2 * prm["avg_bandwidth"]),
+                   dict(avg_bandwidth_z=0.5 * prm["avg_bandwidth"]), dict(avg_ntau=5),
+                   dict(avg_rtol=1e-10)):
+        c = gpu_context(dict(case, params=dict(prm, **change)), solver="iterative")
+        with pytest.raises(sm.SedimiError):
+            c.set_state(blob)
+        c.average()
+    b = gpu_context(case, solver="iterative")
+    b.set_state(blob)
+    b.step(2, 1)
+    a.step(2, 1)
+    assert np.array_equal(a.get_particles()["x"], b.get_particles()["x"])
+    assert np.array_equal(a.get_field(1), b.get_field(1))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_two_runs_are_bit_identical(precision):
     """No floating-point atomics on the step path: two runs from the same

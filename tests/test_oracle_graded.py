@@ -158,6 +158,30 @@ def test_grading_one_is_the_uniform_mesh(orc):
     assert np.array_equal(s0, s1)
 
 
+@pytest.mark.parametrize("eps", [1e-6, 1e-9])
+def test_grading_near_one_tends_to_the_uniform_mesh(orc, eps):
+    """A grading of 1 + eps runs the graded branches (faces, per-cell
+    volumes, the height-weighted operator) and must approach the uniform mesh
+    as eps -> 0: faces within eps Lz, the bottom cell no taller than the top
+    one, deposition and smoothing within a few eps."""
+    base = graded_prm(g=0.0)
+    near = dict(base, z_grading=1.0 + eps)
+    zf = faces(near)
+    nz = base["nz"]
+    h = np.diff(zf)
+    assert np.all(h[1:] >= h[:-1] * (1 - 1e-15)) and h[-1] / h[0] <= 1 + 2 * eps
+    assert np.all(np.abs(zf - base["Lz"] * np.arange(nz + 1) / nz) < eps * base["Lz"])
+    rng = np.random.default_rng(4)
+    n = 500
+    d = rng.uniform(0.3e-3, 0.8e-3, n)
+    x = rng.random((n, 3)) * [base["Lx"], base["Ly"], base["Lz"]]
+    r0, r1 = orc.deposit(base, x, d), orc.deposit(near, x, d)
+    assert np.all(np.abs(r1 - r0) <= 4 * eps * np.abs(r0).max())
+    s0, _ = orc.diffuse(base, r0[:1])
+    s1, _ = orc.diffuse(near, r1[:1])
+    assert np.all(np.abs(s1 - s0) <= 20 * eps * np.abs(s0).max())
+
+
 def test_graded_run_with_averaging_conserves_the_solid_volume(orc):
     """A short velocity-Verlet run of a small bed on the graded mesh with
     averaging inside: the state stays finite and every averaging keeps the
