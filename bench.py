@@ -59,9 +59,12 @@ def averaging_rooflines(n, ncell, dep_ms, smooth_ms, direct, mesh, nch=4):
 # the same counters read for a 1 GiB device copy (--copy-calibration: the
 # copy's FETCH_SIZE reads 0.5x the bytes read, WRITE_SIZE 1.0x the bytes
 # written).  Valid only for the kernel sources it was measured on.
-FORCE_PMC = {"fetch_kib": 315359.3, "write_kib": 281002.4, "fetch_scale": 2.0, "write_scale": 1.0,
-             "sources_sha256": "901ce0a353829f77b4c70bc03f82b7afdf7191770ed62079b28290157fb1f419",
-             "profile": "profiles/k_forces_bed1m_fp64.md"}
+FORCE_PMC = {
+    ("bed1m", "fp64"): {
+        "fetch_kib": 315359.3, "write_kib": 281002.4, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sources_sha256": "901ce0a353829f77b4c70bc03f82b7afdf7191770ed62079b28290157fb1f419",
+        "profile": "profiles/k_forces_bed1m_fp64.md"},
+}
 FORCE_SOURCES = ("k_forces.hip", "k_common.h", "sedimi_internal.h")
 
 
@@ -130,6 +133,11 @@ def main():
                     help="only run the 1 GiB copy used to scale the PMC byte counters")
     ap.add_argument("--nn-alpha", type=float, default=1.0,
                     help="leaky-ReLU slope of the surrogate (1 makes the network linear)")
+    ap.add_argument("--rebuilds", type=int, default=5,
+                    help="forced neighbour-list rebuilds timed on the main bed")
+    ap.add_argument("--bed10m-steps", type=int, default=20,
+                    help="timed bench steps of the 10M-sphere mixed-precision bed "
+                         "(0 skips it)")
     ap.add_argument("--nn-steps", type=int, default=10,
                     help="coupled steps (averaging every step) per averaging mode")
     args = ap.parse_args()
@@ -141,29 +149,103 @@ def main():
         copy_calibration()
         return
 
-    import numpy as np
+    import torch
+
+    main_run = particle_bench(args, args.workload, args.precision, args.steps, args.warmup,
+                              rebuilds=args.rebuilds, cpu_steps=0 if args.no_cpu_baseline
+                              else args.cpu_steps)
+    value, elapsed, n = main_run["value"], main_run["elapsed"], main_run["n"]
+    K, W, S, prm = args.steps, args.warmup, args.substeps, main_run["prm"]
+    mixed = args.precision == "mixed"
+    torch.cuda.empty_cache()
+
+    bed10m = None
+    if args.workload == "bed1m" and args.bed10m_steps > 0:
+        r = particle_bench(args, "bed10m", "mixed", args.bed10m_steps, 2, rebuilds=0,
+                           cpu_steps=0)
+        bed10m = {"workload": "bed10m", "particles": r["n"], "mesh": r["mesh"],
+                  "precision": "mixed", "dtype": "f64-state/f32-forces",
+                  "value": round(r["value"], 1), "unit": "particle-updates/s",
+                  "steps": r["steps"], "particle_steps": r["steps"] * S,
+                  "ms_per_step": round(1000 * r["elapsed"] / r["steps"], 4),
+                  "roofline": r["roofline"], "averaging_ms": r["averaging"]["plain_ms"],
+                  "averaging": r["averaging"], "particle_step_only": r["particle_step_only"],
+                  "stats": r["stats"]}
+        print(f"bench: bed10m mixed {bed10m['value']:.4e} particle-updates/s", file=sys.stderr,
+              flush=True)
+        torch.cuda.empty_cache()
+
+    surrogate = None
+    if args.nn_train_steps > 0:
+        surrogate = surrogate_section(args)
+
+    out = {
+        "metric": METRIC, "value": round(value, 1), "unit": "particle-updates/s",
+        "n_gpus": 1, "steps": K, "warmup": W,
+        "ms_per_step": round(1000 * elapsed / K, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if not mixed else "f64-state/f32-forces", "data": "synthetic",
+        "config": {"workload": args.workload, "particles": n, "mesh": main_run["mesh"],
+                   "substeps_per_step": S, "average_every": S, "dt": prm["dt"],
+                   "precision": args.precision, "drag": args.drag, "lift_c": args.lift,
+                   "solid_velocity": args.solid_velocity, "scheme": args.scheme,
+                   "avg_bandwidth_m": prm["avg_bandwidth"],
+                   "avg_bandwidth_z_m": prm["avg_bandwidth_z"] or prm["avg_bandwidth"],
+                   "bed_seed": main_run["meta"].get("bed_seed"),
+                   "field_seed": main_run["meta"].get("field_seed")},
+        "roofline": main_run["roofline"],
+        "cpu_baseline": main_run["cpu"],
+        "averaging": main_run["averaging"],
+        "phases": main_run["phases"],
+        "particle_step_only": main_run["particle_step_only"],
+        "rebuild": main_run["rebuild"],
+        "bed10m_mixed": bed10m,
+        "surrogate": surrogate,
+        "stats": main_run["stats"],
+    }
+    print(json.dumps(out))
+
+
+def rebuild_bytes_per_particle(mean_nbr, mean_contacts, mixed):
+    """Algorithmic HBM bytes of one neighbour-list rebuild per particle:
+    bin key from the position (32 B read, key + rank 8 B written), the
+    scatter (8 B read, 4 B written), the re-sort of the particle state (pos,
+    vel, omg, acc, alpha, drag, two wall-history rows and the ID: 260 B read
+    and 260 B written once), the list build (own position 32 B, the
+    neighbour indices 4 B each, count, history mask and build position
+    40 B) and the carry-over of the tangential history (slot history read,
+    (partner ID, xi) rows written and read back, slot history written:
+    per active contact 2 h + 2 x 28 B with h = 24 B, 12 B in mixed mode)."""
+    h = 12 if mixed else 24
+    return 40 + 12 + 520 + 72 + 4 * mean_nbr + mean_contacts * (2 * h + 56)
+
+
+def particle_bench(args, name, precision, K, W, rebuilds=0, cpu_steps=0):
+    """Time K bench steps (each args.substeps particle steps + one averaging)
+    of one workload after W warm-up bench steps; then per-phase device times,
+    the force-kernel roofline, forced rebuilds and the oracle CPU baseline."""
     import torch
 
     import paper_1601_03801_amd as sm
     import workloads
 
     t0 = time.time()
-    w = workloads.workload(args.workload)
+    w = workloads.workload(name)
     prm = dict(w["params"], drag_law=args.drag,
                avg_bandwidth_z=args.bandwidth_z * workloads.D50, c_lift=args.lift,
                avg_solid_velocity=1 if args.solid_velocity else 0,
                avg_scheme=1 if args.scheme == "bdf2" else 0)
     n = len(w["d"])
-    print(f"bench: workload {args.workload}: {n} spheres, mesh {w['meta']['mesh']}, "
+    print(f"bench: workload {name}: {n} spheres, mesh {w['meta']['mesh']}, "
           f"generated in {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
     dmax = float(w["d"].max())
-    g = sm.Sedimi(prm, n, precision=args.precision, d_max=dmax, skin=0.1 * dmax,
+    g = sm.Sedimi(prm, n, precision=precision, d_max=dmax, skin=0.1 * dmax,
                   max_neighbors=24)
     g.set_fluid(w["U"], w["gradp"], w["dudt"])
     g.set_particles(w["x"], w["v"], w["d"], w["rho"], omega=w["w"])
     g.average()
     g.compute_forces(update_history=False)
-    K, W, S = args.steps, args.warmup, args.substeps
+    S = args.substeps
     for _ in range(W):
         g.step(S, average_every=S)
     torch.cuda.synchronize()
@@ -174,7 +256,8 @@ def main():
     t2 = time.perf_counter()
     elapsed = t2 - t1
     value = n * S * K / elapsed
-    print(f"bench: timed {K} bench steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+    print(f"bench: {name} timed {K} bench steps in {elapsed:.3f} s", file=sys.stderr,
+          flush=True)
 
     # per-phase device times (HIP events on the library's stream)
     g.set_profiling(True)
@@ -185,17 +268,17 @@ def main():
     st = g.stats()
     f_ms, f_cnt = prof["forces"]
     f_avg = f_ms / max(f_cnt, 1)
-    mixed = args.precision == "mixed"
+    mixed = precision == "mixed"
     bpp = force_bytes_per_particle(st["mean_neighbors"], st["mean_contacts"], mixed)
     ncell = prm["nx"] * prm["ny"] * prm["nz"]
     bytes_launch = n * bpp + ncell * ((4 if args.lift > 0 else 3) * 32 + 8)
     achieved = bytes_launch / (f_avg * 1e-3) / 1e9
     traffic = None
-    if (FORCE_PMC is not None and args.workload == "bed1m" and not mixed
-            and args.drag == "difelice" and args.lift == 0
-            and FORCE_PMC["sources_sha256"] == force_sources_sha()):
-        traffic = int(1024 * (FORCE_PMC["fetch_kib"] * FORCE_PMC["fetch_scale"]
-                              + FORCE_PMC["write_kib"] * FORCE_PMC["write_scale"]))
+    pmc = FORCE_PMC.get((name, precision))
+    if (pmc is not None and args.drag == "difelice" and args.lift == 0
+            and pmc["sources_sha256"] == force_sources_sha()):
+        traffic = int(1024 * (pmc["fetch_kib"] * pmc["fetch_scale"]
+                              + pmc["write_kib"] * pmc["write_scale"]))
     roofline = {"bound": "hbm", "kernel": "k_forces (step)", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "avg_launch_ms": round(f_avg, 5),
@@ -211,58 +294,67 @@ def main():
     # the particle step alone (drift, gated rebuild chain, forces), per step
     dem_ms = (prof["drift"][0] + prof["rebuild"][0] + prof["forces"][0]) / max(prof["forces"][1], 1)
 
+    # forced neighbour-list rebuilds (binning, re-sort, pair search, history
+    # carry-over) on the same bed: the timed run above rebuilds only when a
+    # particle has moved half the skin
+    rebuild = None
+    if rebuilds > 0:
+        g.rebuild()
+        g.set_profiling(True)
+        for _ in range(rebuilds):
+            g.step(1, average_every=0)
+            g.rebuild()
+        prof_r = g.profile()
+        g.set_profiling(False)
+        st_r = g.stats()
+        # phase 1 holds the forced rebuilds and the gated (idle) chains of the steps
+        idle_ms = prof["rebuild"][0] / max(prof["rebuild"][1], 1)
+        r_ms = (prof_r["rebuild"][0] - rebuilds * idle_ms) / rebuilds
+        rb_bpp = rebuild_bytes_per_particle(st_r["mean_neighbors"], st_r["mean_contacts"], mixed)
+        r_bytes = n * rb_bpp + 8 * n  # + bin counts and starts (about one bin per particle)
+        rebuild = {"ms": round(r_ms, 5), "forced": rebuilds, "bytes": int(r_bytes),
+                   "bytes_per_particle": round(rb_bpp, 1), "bound": "hbm",
+                   "achieved_GBps": round(r_bytes / (r_ms * 1e-3) / 1e9, 1),
+                   "frac": round(r_bytes / (r_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "gated_idle_ms_per_step": round(idle_ms, 5)}
+        print(f"bench: {name} forced rebuild {r_ms:.3f} ms", file=sys.stderr, flush=True)
+
     cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        ost = oracle.State(prm, w["x"], w["v"], w["w"], w["d"], w["rho"], U=w["U"],
-                           gradp=w["gradp"], dudt=w["dudt"])
-        ost.average()
-        ost.init_accel()
-        c0 = time.perf_counter()
-        ost.run(args.cpu_steps)
-        c1 = time.perf_counter()
-        cpu = {"value": round(n * args.cpu_steps / (c1 - c0), 1), "unit": "particle-updates/s",
-               "cores": 1, "kind": "oracle",
-               "sample": f"{args.cpu_steps} particle steps of the same {n}-sphere bed "
-                         f"({c1 - c0:.1f} s), no averaging"}
-        print(f"bench: oracle {args.cpu_steps} steps in {c1 - c0:.1f} s", file=sys.stderr,
-              flush=True)
+    if cpu_steps > 0:
+        cpu = cpu_baseline(w, prm, cpu_steps)
+    stats = {"mean_neighbors": round(st["mean_neighbors"], 3),
+             "mean_contacts": round(st["mean_contacts"], 3),
+             "rebuilds": st["rebuilds"], "steps": st["steps"]}
+    g.close()
+    del g
+    return {"value": value, "elapsed": elapsed, "n": n, "prm": prm, "steps": K,
+            "mesh": w["meta"]["mesh"], "meta": w["meta"], "roofline": roofline,
+            "phases": phases,
+            "averaging": {"plain_ms": round(avg_ms, 4),
+                          "solver": "direct" if st["solve_iters"] == 0 else "iterative",
+                          "solve_iters": st["solve_iters"], "residual": st["solve_residual"],
+                          "deposit": dep_r, "solve": sol_r},
+            "particle_step_only": {"ms_per_step": round(dem_ms, 5),
+                                   "particle_updates_per_s": round(n / (dem_ms * 1e-3), 1)},
+            "rebuild": rebuild, "cpu": cpu, "stats": stats}
 
-    surrogate = None
-    if args.nn_train_steps > 0:
-        del g
-        torch.cuda.empty_cache()
-        surrogate = surrogate_section(args)
 
-    out = {
-        "metric": METRIC, "value": round(value, 1), "unit": "particle-updates/s",
-        "n_gpus": 1, "steps": K, "warmup": W,
-        "ms_per_step": round(1000 * elapsed / K, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if not mixed else "f64-state/f32-forces", "data": "synthetic",
-        "config": {"workload": args.workload, "particles": n, "mesh": w["meta"]["mesh"],
-                   "substeps_per_step": S, "average_every": S, "dt": prm["dt"],
-                   "precision": args.precision, "drag": args.drag, "lift_c": args.lift,
-                   "solid_velocity": args.solid_velocity, "scheme": args.scheme,
-                   "avg_bandwidth_m": prm["avg_bandwidth"],
-                   "avg_bandwidth_z_m": prm["avg_bandwidth_z"] or prm["avg_bandwidth"],
-                   "bed_seed": w["meta"].get("bed_seed"),
-                   "field_seed": w["meta"].get("field_seed")},
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "averaging": {"plain_ms": round(avg_ms, 4),
-                      "solver": "direct" if st["solve_iters"] == 0 else "iterative",
-                      "solve_iters": st["solve_iters"], "residual": st["solve_residual"],
-                      "deposit": dep_r, "solve": sol_r},
-        "phases": phases,
-        "particle_step_only": {"ms_per_step": round(dem_ms, 5),
-                               "particle_updates_per_s": round(n / (dem_ms * 1e-3), 1)},
-        "surrogate": surrogate,
-        "stats": {"mean_neighbors": round(st["mean_neighbors"], 3),
-                  "mean_contacts": round(st["mean_contacts"], 3),
-                  "rebuilds": st["rebuilds"], "steps": st["steps"]},
-    }
-    print(json.dumps(out))
+def cpu_baseline(w, prm, steps):
+    """The FP64 oracle on the host: a few particle steps of the same bed."""
+    import oracle
+    n = len(w["d"])
+    ost = oracle.State(prm, w["x"], w["v"], w["w"], w["d"], w["rho"], U=w["U"],
+                       gradp=w["gradp"], dudt=w["dudt"])
+    ost.average()
+    ost.init_accel()
+    c0 = time.perf_counter()
+    ost.run(steps)
+    c1 = time.perf_counter()
+    print(f"bench: oracle {steps} steps in {c1 - c0:.1f} s", file=sys.stderr, flush=True)
+    return {"value": round(n * steps / (c1 - c0), 1), "unit": "particle-updates/s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"{steps} particle steps of the same {n}-sphere bed "
+                      f"({c1 - c0:.1f} s), no averaging"}
 
 
 def surrogate_section(args):

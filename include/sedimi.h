@@ -242,6 +242,13 @@ int sedimi_compute_forces(sedimi_ctx* ctx, int update_history);
  * every step whose global index is a multiple of average_every, and its
  * solid fraction feeds the drag of the following steps. */
 int sedimi_step(sedimi_ctx* ctx, int nsteps, int average_every);
+/* Rebuild the neighbour lists now, as sedimi_step does when a particle has
+ * moved half the skin (Section 2.5's link-cell search): binning, the stable
+ * re-sort by (bin, ID), the pair search and the carry-over of the tangential
+ * history.  Positions, velocities and history are unchanged; later steps may
+ * differ from an unforced run by the order of each particle's force sum only.
+ * Errors: ESTATE before particles, EOVERFLOW as sedimi_step. */
+int sedimi_rebuild(sedimi_ctx* ctx);
 /* Deposition (Eq. 11) into the RAW field, then the diffusion solve (Eq. 12)
  * into the SMOOTH field.  Both use the particles' current positions and the
  * drag of the last force evaluation.  Like sedimi_step, returns the error of
@@ -297,8 +304,10 @@ int sedimi_set_avg_mode(sedimi_ctx* ctx, int mode);
  * A 6-layer 3-D CNN (3x3x3 taps; z dilations 1, 2, 4, 4, 2, 1; 32 channels;
  * layer 1: 4 -> 32, layers 2-5: 32 -> 32 with identity skips, layer 6: 32 -> 4;
  * leaky ReLU; output = input + network) mapping the deposited fields to the
- * smoothed ones in per-channel normalised units; periodic in x, y and zero
- * padded in z.  BF16 weights and activations, FP32 accumulation and output.
+ * smoothed ones in per-channel normalised units; periodic in x, y and mirror
+ * padded in z (the field extended by reflection about the wall faces, as the
+ * zero-flux walls of Eq. 12 reflect the diffusion).  BF16 weights and
+ * activations, FP32 accumulation and output.
  * Parameters are a flat FP32 vector: per layer w[27][cin][cout] then b[cout],
  * tap t = (dz+1)*9 + (dy+1)*3 + (dx+1).  The plain solve stays the fallback:
  * a checked averaging accepts the network's field y only if, on the seeded

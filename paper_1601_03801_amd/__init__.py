@@ -105,6 +105,7 @@ def lib():
         L.sedimi_translate.argtypes = [P, C.c_double, C.c_double]
         L.sedimi_compute_forces.argtypes = [P, I]
         L.sedimi_step.argtypes = [P, I, I]
+        L.sedimi_rebuild.argtypes = [P]
         L.sedimi_average.argtypes = [P]
         L.sedimi_deposit.argtypes = [P]
         L.sedimi_smooth.argtypes = [P, I]
@@ -249,6 +250,9 @@ class Sedimi:
 
     def step(self, nsteps, average_every=0):
         self._chk(self._L.sedimi_step(self._ctx, int(nsteps), int(average_every)))
+
+    def rebuild(self):
+        self._chk(self._L.sedimi_rebuild(self._ctx))
 
     def average(self):
         self._chk(self._L.sedimi_average(self._ctx))

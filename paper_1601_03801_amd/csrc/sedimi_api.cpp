@@ -734,6 +734,26 @@ int sedimi_compute_forces(sedimi_ctx* c, int update_history) {
   return flags_to_rc(c, ctl.flags);
 }
 
+int sedimi_rebuild(sedimi_ctx* c) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  if ((rc = set_rebuild_flag(c))) return rc;
+  phase_begin(c, 1);
+  launch_rebuild(c->P, c->A, true, c->mixed, c->stream);
+  phase_end(c);
+  HIPCHK(c, hipGetLastError());
+  // the force kernel clears the flag and counts the rebuild; with no force
+  // evaluation in this call, do both here so the next step does not rebuild
+  // again
+  Ctl ctl;
+  if ((rc = read_ctl(c, &ctl))) return rc;
+  ctl.rebuilds += 1;
+  ctl.rebuild = ctl.rebuild_alt = 0;
+  HIPCHK(c, hipMemcpyAsync(c->A.ctl, &ctl, sizeof(Ctl), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return flags_to_rc(c, ctl.flags);
+}
+
 int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
   int rc = need_particles(c);
   if (rc) return rc;

@@ -37,7 +37,15 @@ def test_stored_force_counters_name_their_sources_and_profile():
     """The HBM traffic in the bench line is reported only while the hash of
     the force kernel's sources equals the one the counters were taken on
     (otherwise it is null); the counters' profile summary is committed."""
-    assert bench.FORCE_PMC is not None
-    assert len(bench.FORCE_PMC["sources_sha256"]) == 64
+    assert bench.FORCE_PMC
     assert len(bench.force_sources_sha()) == 64
-    assert os.path.exists(os.path.join(ROOT, bench.FORCE_PMC["profile"]))
+    for (workload, precision), pmc in bench.FORCE_PMC.items():
+        assert workload in ("bed1m", "bed10m") and precision in ("fp64", "mixed")
+        assert len(pmc["sources_sha256"]) == 64
+        assert os.path.exists(os.path.join(ROOT, pmc["profile"]))
+
+
+def test_rebuild_bytes_count_what_the_docstring_states():
+    b = bench.rebuild_bytes_per_particle(8.0, 4.0, False)
+    assert b == 40 + 12 + 520 + 72 + 32 + 4 * (48 + 56)
+    assert bench.rebuild_bytes_per_particle(8.0, 4.0, True) == b - 4 * 24

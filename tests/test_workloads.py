@@ -115,3 +115,20 @@ def test_graded_mesh_geometry_and_fields():
     # uniform meshes are unchanged by the option's default
     assert np.array_equal(workloads.z_faces(workloads.base_params()),
                           workloads.base_params()["Lz"] * np.arange(9) / 8)
+
+
+def test_tiled_bed_copies_meet_without_overlap():
+    """The 10M bed is an array of copies of one periodic deposited tile: the
+    copies must meet at the seams without overlaps, keep the tile's size
+    distribution and fill the whole domain."""
+    n = 700
+    d = workloads.lognormal_diameters(n, 9)
+    tx, ty = 12 * workloads.D50, 9 * workloads.D50
+    x = workloads.rsd_bed(n, d, tx, ty, 9)
+    xt, dt = workloads.tile_bed(x, d, 3 * tx, 2 * ty, (3, 2))
+    assert len(xt) == 6 * n and np.array_equal(dt[:n], d) and np.array_equal(dt[5 * n:], d)
+    assert np.all((xt[:, 0] >= 0) & (xt[:, 0] < 3 * tx) & (xt[:, 1] >= 0) & (xt[:, 1] < 2 * ty))
+    assert _min_gap(xt, dt, 3 * tx, 2 * ty) > -1e-12 * workloads.D50
+    # copy (a, b) is the tile shifted by (a tx, b ty)
+    k = (1 * 3 + 2) * n
+    assert np.allclose(xt[k:k + n] - x, [2 * tx, ty, 0.0], rtol=0, atol=1e-15)

@@ -14,7 +14,11 @@ Workloads (sizes of the paper's cases, Table 1 and Section 5.2):
   bed1m       1,000,000 log-normal spheres (median 0.5 mm, sigma 0.2, truncated
               to [0.3, 0.8] mm) deposited in a 400d x 200d x 60d channel,
               128 x 64 x 48 mesh, log-law + 5% rms fluctuations
-  bed10m      10,000,000 spheres in 1200d x 600d x 60d, 384 x 192 x 48 mesh
+  bed10m      10,000,000 spheres in 1200d x 600d x 60d, 384 x 192 x 48 mesh: a
+              5 x 2 array of copies of one seeded 1M-sphere deposited tile of
+              240d x 300d (the tile is periodic, so its copies meet without
+              overlaps; same size distribution, packing and depth as one
+              deposition of 10M spheres, generated in a tenth of the time)
   fine2m/4m   2M / 4M spheres, 256 x 128 x 128 mesh with cells of
               (3.125d, 3.125d, 0.5d) in an 800d x 400d x 64d channel
 """
@@ -128,6 +132,18 @@ def rsd_bed(n, d, Lx, Ly, seed):
     x = np.zeros((n, 3))
     _bedlib().bedgen_rsd(n, r.ctypes.data, Lx, Ly, seed, x.ctypes.data)
     return x
+
+
+def tile_bed(x, d, Lx, Ly, tiles):
+    """Copies of a bed that is periodic on [0, Lx/tiles[0]) x [0, Ly/tiles[1])
+    laid side by side over [0, Lx) x [0, Ly); copy (a, b) holds IDs
+    (b * tiles[0] + a) * n + i."""
+    tx, ty = Lx / tiles[0], Ly / tiles[1]
+    x = np.concatenate([x + [a * tx, b * ty, 0.0]
+                        for b in range(tiles[1]) for a in range(tiles[0])])
+    x[:, 0] = np.where(x[:, 0] >= Lx, x[:, 0] - Lx, x[:, 0])
+    x[:, 1] = np.where(x[:, 1] >= Ly, x[:, 1] - Ly, x[:, 1])
+    return x, np.tile(d, tiles[0] * tiles[1])
 
 
 def bed_top(x, d, Lx, Ly, nbins=16):
@@ -255,13 +271,17 @@ def workload(name, seed=None, n=None):
         prm = base_params(Lx=lx * D50 * scale, Ly=ly * D50 * scale, Lz=lz * D50,
                           nx=max(2, int(round(mesh[0] * scale))),
                           ny=max(2, int(round(mesh[1] * scale))), nz=mesh[2])
-        d = lognormal_diameters(N, bseed)
-        x = rsd_bed(N, d, prm["Lx"], prm["Ly"], seed=bseed)
+        tiles = (5, 2) if name == "bed10m" and n is None else (1, 1)
+        nt = tiles[0] * tiles[1]
+        d = lognormal_diameters(N // nt, bseed)
+        x = rsd_bed(N // nt, d, prm["Lx"] / tiles[0], prm["Ly"] / tiles[1], seed=bseed)
+        if nt > 1:
+            x, d = tile_bed(x, d, prm["Lx"], prm["Ly"], tiles)
         prm["dt"] = dt_rule(prm, float(d.min()))
         zb = bed_top(x, d, prm["Lx"], prm["Ly"])
         U, gradp, dudt = fluid_fields(prm, z_bed=zb, fluct=0.05, seed=fseed)
         meta = dict(workload=name, n=N, mesh=[prm["nx"], prm["ny"], prm["nz"]],
-                    bed_seed=bseed, field_seed=fseed, bed_top=zb)
+                    bed_seed=bseed, field_seed=fseed, bed_top=zb, tiles=list(tiles))
     else:
         raise KeyError(name)
     n = len(d)
