@@ -7,8 +7,11 @@
  *
  *   conv(x)[c][o] = b[o] + sum_t sum_i x[nb(c, t)][i] * w[t][i][o]
  *     taps t = (dz + 1)*9 + (dy + 1)*3 + (dx + 1), dz, dy, dx in {-1, 0, 1};
- *     nb(c, t) = cell (i + dx, j + dy, k + dil*dz), periodic in x and y, and
- *     no contribution when k + dil*dz falls outside [0, nz) (zero padding);
+ *     nb(c, t) = cell (i + dx, j + dy, R(k + dil*dz)), periodic in x and y;
+ *     in z the field is extended by reflection about the wall faces (mirror
+ *     padding: plane -1 is plane 0, plane nz is plane nz-1, repeated with
+ *     period 2 nz), the even extension that matches the zero-flux walls of
+ *     the diffusion it stands in for;
  *   layer 1: h1 = phi(conv1(x))                        (4 -> C channels)
  *   layers 2..5: h_l = h_{l-1} + phi(conv_l(h_{l-1}))  (C -> C)
  *   layer 6: y = x + conv6(h5)                         (C -> 4)
@@ -47,8 +50,10 @@ static int64_t nbr(int nx, int ny, int nz, int64_t c, int t, int dil) {
   int j = (int)((c / nx) % ny);
   int k = (int)(c / ((int64_t)nx * ny));
   int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-  int kk = k + dil * dz;
-  if (kk < 0 || kk >= nz) return -1;
+  /* reflection into [0, nz): the even extension about both wall faces */
+  int kk = (k + dil * dz) % (2 * nz);
+  if (kk < 0) kk += 2 * nz;
+  if (kk >= nz) kk = 2 * nz - 1 - kk;
   int ii = ((i + dx) % nx + nx) % nx;
   int jj = ((j + dy) % ny + ny) % ny;
   return ((int64_t)kk * ny + jj) * nx + ii;
@@ -61,8 +66,7 @@ void orc_conv3d_fwd(int nx, int ny, int nz, int cin, int cout, int dil, const do
   for (int64_t c = 0; c < n; ++c) {
     for (int o = 0; o < cout; ++o) y[c * cout + o] = b ? b[o] : 0.0;
     for (int t = 0; t < 27; ++t) {
-      int64_t q = nbr(nx, ny, nz, c, t, dil);
-      if (q < 0) continue;
+      const int64_t q = nbr(nx, ny, nz, c, t, dil);
       for (int i = 0; i < cin; ++i) {
         double xv = x[q * cin + i];
         for (int o = 0; o < cout; ++o) y[c * cout + o] += xv * w[((int64_t)t * cin + i) * cout + o];
@@ -80,8 +84,7 @@ void orc_conv3d_bwd(int nx, int ny, int nz, int cin, int cout, int dil, const do
   for (int64_t c = 0; c < n; ++c) {
     for (int o = 0; o < cout; ++o) db[o] += dy[c * cout + o];
     for (int t = 0; t < 27; ++t) {
-      int64_t q = nbr(nx, ny, nz, c, t, dil);
-      if (q < 0) continue;
+      const int64_t q = nbr(nx, ny, nz, c, t, dil);
       for (int i = 0; i < cin; ++i) {
         double acc = 0.0;
         for (int o = 0; o < cout; ++o) {

@@ -36,13 +36,36 @@ __device__ __forceinline__ float leaky(float z, float a) { return z > 0.0f ? z :
 __device__ __forceinline__ float dleaky(float z, float a) { return z > 0.0f ? 1.0f : a; }
 __device__ __forceinline__ float bf(float v) { return (float)(__bf16)v; }
 
-// Neighbour cell of (i, j, k) for tap t (offsets negated when neg != 0);
-// -1 when the z index leaves the mesh (zero padding); periodic in x and y.
-__device__ __forceinline__ int tap_cell(const ConvGeom& g, int i, int j, int k, int t) {
-  int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-  if (g.neg) dz = -dz, dy = -dy, dx = -dx;
-  int kk = k + g.dil * dz;
-  if (kk < 0 || kk >= g.nz) return -1;
+// z source planes of output plane k for the z-tap offset dz (in taps, not
+// scaled by the dilation).  The field is extended along z by reflection about
+// the wall faces (mirror padding, period 2 nz).  The forward convolution
+// (neg = 0) reads the one plane R(k + dil dz): `which` 0.  Its adjoint
+// (neg = 1) gathers every plane k' with R(k' + dil dz) = k: the direct one,
+// k' = k - dil dz (`which` 0), and the mirror image, k' = -k - 1 - dil dz
+// below the bottom face or 2 nz - 1 - k - dil dz above the top one (`which`
+// 1); each exists only when it lies inside the mesh.  -1: no such plane.
+__device__ __forceinline__ int zsrc(const ConvGeom& g, int k, int dz, int which) {
+  const int nz2 = 2 * g.nz, lo = g.dil * dz;
+  if (!g.neg) {
+    if (which) return -1;
+    int j = (k + lo) % nz2;
+    j = j < 0 ? j + nz2 : j;
+    return j < g.nz ? j : nz2 - 1 - j;
+  }
+  int m = (which ? -k - 1 - lo : k - lo) % nz2;
+  m = m < 0 ? m + nz2 : m;
+  return m < g.nz ? m : -1;
+}
+
+// Neighbour cell of (i, j, k) for tap t and z source `which` (x and y offsets
+// negated when neg != 0); -1 when that z source does not exist; periodic in x
+// and y.
+__device__ __forceinline__ int tap_cell(const ConvGeom& g, int i, int j, int k, int t,
+                                        int which) {
+  int dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+  if (g.neg) dy = -dy, dx = -dx;
+  const int kk = zsrc(g, k, t / 9 - 1, which);
+  if (kk < 0) return -1;
   int ii = i + dx;
   ii = ii < 0 ? ii + g.nx : (ii >= g.nx ? ii - g.nx : ii);
   int jj = j + dy;
@@ -157,30 +180,45 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(ConvGeom g, const __bf16*
     for (int m = 0; m < TM; ++m)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[m][nt] = v4f{0.f, 0.f, 0.f, 0.f};
-    // 4 input channels: two taps share a lane group, K padded from 108 to 128
+    // 4 input channels: two taps share a lane group, K padded from 108 to 128.
+    // Pass 0 takes each tap's direct z source; the adjoint then takes a
+    // second pass over the mirror-image sources, needed only by waves with a
+    // cell within one dilation of a wall (each product accumulates in FP32,
+    // as for any other tap).
+    int npass = 1;
+    if (g.neg) {
+      bool near = false;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int t0 = 8 * s + 2 * grp, t1 = t0 + 1;
-      v8bf a[TM];
+      for (int m = 0; m < TM; ++m)
+        near |= valid[m] && (ck[m] < g.dil || ck[m] >= g.nz - g.dil);
+      npass = __ballot(near) ? 2 : 1;
+    }
+#pragma unroll 1
+    for (int which = 0; which < npass; ++which) {
 #pragma unroll
-      for (int m = 0; m < TM; ++m) {
-        v4bf lo = {}, hi = {};
-        if (valid[m] && t0 < 27) {
-          const int q = tap_cell(g, ci[m], cj[m], ck[m], t0);
-          if (q >= 0) lo = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
+      for (int s = 0; s < 4; ++s) {
+        const int t0 = 8 * s + 2 * grp, t1 = t0 + 1;
+        v8bf a[TM];
+#pragma unroll
+        for (int m = 0; m < TM; ++m) {
+          v4bf lo = {}, hi = {};
+          if (valid[m] && t0 < 27) {
+            const int q = tap_cell(g, ci[m], cj[m], ck[m], t0, which);
+            if (q >= 0) lo = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
+          }
+          if (valid[m] && t1 < 27) {
+            const int q = tap_cell(g, ci[m], cj[m], ck[m], t1, which);
+            if (q >= 0) hi = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
+          }
+          a[m] = v8bf{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
         }
-        if (valid[m] && t1 < 27) {
-          const int q = tap_cell(g, ci[m], cj[m], ck[m], t1);
-          if (q >= 0) hi = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          const v8bf b = *reinterpret_cast<const v8bf*>(sw + (nt * 16 + row) * 128 + 32 * s + grp * 8);
+#pragma unroll
+          for (int m = 0; m < TM; ++m)
+            acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][nt], 0, 0, 0);
         }
-        a[m] = v8bf{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-      }
-#pragma unroll
-      for (int nt = 0; nt < NT; ++nt) {
-        const v8bf b = *reinterpret_cast<const v8bf*>(sw + (nt * 16 + row) * 128 + 32 * s + grp * 8);
-#pragma unroll
-        for (int m = 0; m < TM; ++m)
-          acc[m][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m], b, acc[m][nt], 0, 0, 0);
       }
     }
     // acc[m][nt][r] = output (cell (tg*TM + m)*16 + 4*grp + r, channel nt*16 + row).
@@ -221,13 +259,17 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(ConvGeom g, const __bf16*
 // waves owns an output tile of 64 (x) by 16 (y) cells in one z-plane; wave w
 // computes row w of it as 4 MFMA tiles of 16 cells.  The taps are taken one
 // z-plane at a time: the block copies the input plane (the tile plus a
-// one-cell halo in x and y, periodic; zeros outside the mesh in z) into LDS
-// with coalesced 16-byte loads, then every wave reads the A fragments of the
-// plane's 9 taps from LDS, where 16 consecutive cells of one row are 1 KB of
-// contiguous LDS (no bank conflicts).  Each input cell is thus read from
-// memory about 1.3 times per plane (halo) instead of once per tap through
-// L1.  The next plane is loaded into registers while the current one feeds
-// the matrix cores.  Tap order and accumulation are those of k_conv.
+// one-cell halo in x and y, periodic) into LDS with coalesced 16-byte loads,
+// then every wave reads the A fragments of the plane's 9 taps from LDS,
+// where 16 consecutive cells of one row are 1 KB of contiguous LDS (no bank
+// conflicts).  Each input cell is thus read from memory about 1.3 times per
+// plane (halo) instead of once per tap through L1.  The next plane is loaded
+// into registers while the current one feeds the matrix cores.
+//
+// The planes of a tile are jobs (z-tap p, source plane): the forward takes
+// one source per z-tap (mirror padding, zsrc), the adjoint one or two (a
+// direct plane and a mirror image), and some z-taps of its planes next to a
+// wall have none.  Job j = 2 pi + which for pi = 0..2 in the tap order below.
 constexpr int kTileX = 64, kTileY = 16;
 constexpr int kTiledThreads = 64 * kTileY;
 constexpr int kHaloX = kTileX + 2, kHaloY = kTileY + 2;
@@ -251,18 +293,25 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
   const int ntx = (g.nx + kTileX - 1) / kTileX, nty = (g.ny + kTileY - 1) / kTileY;
   const int ntiles = ntx * nty * g.nz;
   const int sgn = g.neg ? -1 : 1;
-  // Plane (tile, phase) -> registers: phase p stages plane z + sgn dil (p - 1).
-  // The loads are unconditional (clamped to valid addresses) and the zero
-  // padding outside the mesh is applied when the registers are written to
-  // LDS: conditional loads would make the compiler merge and copy the
-  // registers, which waits for the loads right away.
+  // Residual layers take the centre z-tap last: it then stays in LDS for the
+  // epilogue, which reads the residual input h_in (the layer's own input,
+  // plane z itself) from there instead of from memory.
+  constexpr bool kCentreLast = EPI == EPI_RES;
+  auto phase = [](int i) { return kCentreLast ? (i == 0 ? 0 : (i == 1 ? 2 : 1)) : i; };
+  // source plane of job j of output plane tz (-1: none); z-tap p covers the
+  // forward offset dz = p - 1
+  auto job_src = [&](int tz, int j) { return zsrc(g, tz, phase(j >> 1) - 1, j & 1); };
+  auto first_job = [&](int tz, int j) {
+    while (j < 6 && job_src(tz, j) < 0) ++j;
+    return j;
+  };
+  // Plane of (tile, job) -> registers.  The loads are unconditional (clamped
+  // to valid addresses): conditional loads would make the compiler merge and
+  // copy the registers, which waits for the loads right away.
   uint4 st[kUnitsPerThread];
-  bool live = false;  // the staged plane lies inside the mesh (uniform)
-  auto fetch = [&](int tile, int p) {
+  auto fetch = [&](int tile, int j) {
     const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-    const int kk = tz + sgn * g.dil * (p - 1);
-    live = kk >= 0 && kk < g.nz;
-    const int kc = live ? kk : 0;
+    const int kc = job_src(tz, j);
 #pragma unroll
     for (int q = 0; q < kUnitsPerThread; ++q) {
       int u = threadIdx.x + q * kTiledThreads;
@@ -278,7 +327,8 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
     }
   };
   int tile = blockIdx.x;
-  if (tile < ntiles) fetch(tile, 0);
+  // every plane has at least one job: the centre z-tap's direct source
+  if (tile < ntiles) fetch(tile, first_job(tile / (ntx * nty), 0));
   for (; tile < ntiles; tile += gridDim.x) {
     const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
     v4f acc[TM][NT];
@@ -286,29 +336,24 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
     for (int m = 0; m < TM; ++m)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[m][nt] = v4f{0.f, 0.f, 0.f, 0.f};
-    // Residual layers take the centre plane last: it then stays in LDS for
-    // the epilogue, which reads the residual input h_in (the layer's own
-    // input) from there instead of from memory.  Planes: p -> z + sgn dil (p - 1).
-    constexpr bool kCentreLast = EPI == EPI_RES;
-    auto phase = [](int i) { return kCentreLast ? (i == 0 ? 0 : (i == 1 ? 2 : 1)) : i; };
 #pragma unroll 1
-    for (int pi = 0; pi < 3; ++pi) {
-      const int p = phase(pi);
+    for (int j = first_job(tz, 0); j < 6; j = first_job(tz, j + 1)) {
+      const int p = phase(j >> 1);
       __syncthreads();  // every wave is done with the previous plane
-      const unsigned keep = live ? ~0u : 0u;  // a mask, not a select of arrays
 #pragma unroll
       for (int q = 0; q < kUnitsPerThread; ++q) {
         const int u = threadIdx.x + q * kTiledThreads;
-        if (u < kPlaneUnits)
-          reinterpret_cast<uint4*>(&sp[0][0][0])[u] =
-              make_uint4(st[q].x & keep, st[q].y & keep, st[q].z & keep, st[q].w & keep);
+        if (u < kPlaneUnits) reinterpret_cast<uint4*>(&sp[0][0][0])[u] = st[q];
       }
       __syncthreads();
-      // the next plane (of this tile, else of the next tile; the last tile
-      // refetches its own first plane) is in flight during the MFMAs
-      int ft = tile, fp = phase(pi + 1 < 3 ? pi + 1 : 0);
-      if (pi == 2) ft = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : tile;
-      fetch(ft, fp);
+      // the next plane (of this tile, else the first of the next tile; the
+      // last tile refetches its own first plane) is in flight during the MFMAs
+      int ft = tile, fj = first_job(tz, j + 1);
+      if (fj >= 6) {
+        ft = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : tile;
+        fj = first_job(ft / (ntx * nty), 0);
+      }
+      fetch(ft, fj);
 #pragma unroll 1
       for (int t9 = 0; t9 < 9; ++t9) {
         const int t = p * 9 + t9;
@@ -458,10 +503,11 @@ __global__ __launch_bounds__(kDwThreads) void k_conv_dw(ConvGeom g, const __bf16
   float bacc[4] = {0, 0, 0, 0};
   const int nseg = (g.nx + 31) / 32, nrow = (g.ny + kDwRows - 1) / kDwRows;
   const int nchunks = nseg * nrow * g.nz;
-  // Chunk -> registers.  Loads are unconditional (clamped to valid cells) and
-  // the zeros outside the mesh are applied when the registers are written
-  // to LDS, from the bit masks: conditional loads would make the compiler
-  // copy the registers and wait for the loads at once.
+  // Chunk -> registers.  Loads are unconditional (clamped to valid cells);
+  // the x planes are mirrored into the mesh along z, and the dy cells beyond
+  // a ragged row end are zeroed when the registers are written to LDS, from
+  // the bit masks: conditional loads would make the compiler copy the
+  // registers and wait for the loads at once.
   uint2 rx[XPT], ry[YPT];
   unsigned mx = 0, my = 0;  // bit q: unit q holds data
   auto fetch = [&](int ch) {
@@ -486,8 +532,10 @@ __global__ __launch_bounds__(kDwThreads) void k_conv_dw(ConvGeom g, const __bf16
       const int pz = u / (XR * SEG * XU), rem = u % (XR * SEG * XU);
       const int pr = rem / (SEG * XU), rem2 = rem % (SEG * XU);
       const int pc = rem2 / XU, blk = rem2 % XU;
-      const int kk = ck + g.dil * (pz - 1);
-      const bool ok = u < XUNITS && kk >= 0 && kk < g.nz;
+      int kk = (ck + g.dil * (pz - 1)) % (2 * g.nz);  // mirror padding in z
+      kk = kk < 0 ? kk + 2 * g.nz : kk;
+      kk = kk < g.nz ? kk : 2 * g.nz - 1 - kk;
+      const bool ok = u < XUNITS;
       int jj = (y0 - 1 + pr) % g.ny;
       jj = jj < 0 ? jj + g.ny : jj;
       int ii = (x0 - 1 + pc) % g.nx;

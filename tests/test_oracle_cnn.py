@@ -13,37 +13,103 @@ def cell(i, j, k):
     return (k * SHAPE[1] + j) * SHAPE[0] + i
 
 
+def mirror_extended_conv(shape, x, w, dil):
+    """The convolution written as the textbook recipe: extend the field along
+    z by reflection about the wall faces (numpy's 'symmetric' padding, the
+    even extension), wrap it periodically in x and y, then take the plain
+    correlation over the extended array."""
+    nx, ny, nz = shape
+    cin, cout = w.shape[1], w.shape[2]
+    f = x.reshape(nz, ny, nx, cin)
+    pad = dil
+    while True:  # numpy reflects once per call: repeat for thin meshes
+        reps = min(pad, f.shape[0])
+        f = np.pad(f, ((reps, reps), (0, 0), (0, 0), (0, 0)), mode="symmetric")
+        pad -= reps
+        if pad == 0:
+            break
+    f = np.pad(f, ((0, 0), (1, 1), (1, 1), (0, 0)), mode="wrap")
+    y = np.zeros((nz, ny, nx, cout))
+    for t in range(27):
+        dz, dy, dx = t // 9 - 1, (t // 3) % 3 - 1, t % 3 - 1
+        sl = f[dil + dil * dz: dil + dil * dz + nz, 1 + dy: 1 + dy + ny, 1 + dx: 1 + dx + nx]
+        y += sl @ w[t]
+    return y.reshape(-1, cout)
+
+
+@pytest.mark.parametrize("dil", [1, 2, 4])
+@pytest.mark.parametrize("shape", [SHAPE, (4, 3, 3), (3, 4, 1)])
+def test_conv_is_the_mirror_extended_correlation(orc, dil, shape):
+    """conv3d equals the correlation over the field extended by reflection
+    in z (several reflections on meshes thinner than the dilation) and
+    periodically in x and y."""
+    rng = np.random.default_rng(dil)
+    cin, cout = 3, 2
+    n = shape[0] * shape[1] * shape[2]
+    w = rng.normal(size=(27, cin, cout))
+    x = rng.normal(size=(n, cin))
+    y = orc.conv3d_fwd(shape, x, w, None, dil)
+    assert np.allclose(y, mirror_extended_conv(shape, x, w, dil), rtol=0, atol=1e-12)
+
+
 @pytest.mark.parametrize("dil", [1, 2, 4])
 def test_conv_impulse_response(orc, dil):
     """A unit impulse at (i0, j0, k0) in channel 1 makes output cell
-    (i0 - dx, j0 - dy, k0 - dil*dz) equal to w[t][1][:], wrapped in x and y,
-    and nothing where k0 - dil*dz leaves the mesh."""
+    (i0 - dx, j0 - dy, k) equal to w[t][1][:] for every k whose tap
+    k + dil*dz lands on k0 or on its mirror image about a wall face."""
     rng = np.random.default_rng(dil)
     cin, cout = 3, 2
+    nz = SHAPE[2]
     w = rng.normal(size=(27, cin, cout))
-    for (i0, j0, k0) in ((0, 4, 0), (5, 0, 8), (2, 2, 4)):
+    for (i0, j0, k0) in ((0, 4, 0), (5, 0, 8), (2, 2, 4), (1, 1, 1)):
         x = np.zeros((N, cin))
         x[cell(i0, j0, k0), 1] = 1.0
         y = orc.conv3d_fwd(SHAPE, x, w, None, dil)
         want = np.zeros((N, cout))
         for t in range(27):
             dz, dy, dx = t // 9 - 1, (t // 3) % 3 - 1, t % 3 - 1
-            k = k0 - dil * dz
-            if not 0 <= k < SHAPE[2]:
-                continue
-            want[cell((i0 - dx) % SHAPE[0], (j0 - dy) % SHAPE[1], k)] += w[t, 1]
+            for k in range(nz):
+                src = k + dil * dz
+                img = -src - 1 if src < 0 else (2 * nz - 1 - src if src >= nz else src)
+                if img == k0:
+                    want[cell((i0 - dx) % SHAPE[0], (j0 - dy) % SHAPE[1], k)] += w[t, 1]
         assert np.allclose(y, want, rtol=0, atol=1e-15)
 
 
-def test_conv_adjoint_identity(orc):
+@pytest.mark.parametrize("dil,shape", [(2, SHAPE), (4, SHAPE), (4, (5, 4, 3)), (1, (4, 4, 1))])
+def test_conv_adjoint_identity(orc, dil, shape):
     rng = np.random.default_rng(3)
     cin, cout = 4, 3
+    n = shape[0] * shape[1] * shape[2]
     w = rng.normal(size=(27, cin, cout))
-    x = rng.normal(size=(N, cin))
-    g = rng.normal(size=(N, cout))
-    y = orc.conv3d_fwd(SHAPE, x, w, None, 2)
-    dx, _, _ = orc.conv3d_bwd(SHAPE, x, w, g, 2)
+    x = rng.normal(size=(n, cin))
+    g = rng.normal(size=(n, cout))
+    y = orc.conv3d_fwd(shape, x, w, None, dil)
+    dx, _, _ = orc.conv3d_bwd(shape, x, w, g, dil)
     assert abs((y * g).sum() - (x * dx).sum()) < 1e-11 * np.abs(y * g).sum()
+
+
+def test_network_keeps_a_field_even_about_the_walls(orc):
+    """With taps symmetric in z, mirror padding makes each layer commute with
+    the reflection of the column about its centre: a field symmetric in z
+    stays symmetric through the whole network (zero padding would not keep
+    the planes next to the walls equal to their mirror images' values)."""
+    C = 4
+    rng = np.random.default_rng(8)
+    params = rng.normal(scale=0.3, size=orc.nn_param_count(C))
+    off = 0
+    for l in range(6):
+        cin = 4 if l == 0 else C
+        cout = 4 if l == 5 else C
+        w = params[off:off + 27 * cin * cout].reshape(3, 9, cin, cout)
+        w[2] = w[0]  # taps dz = +1 equal taps dz = -1
+        params[off:off + 27 * cin * cout] = w.ravel()
+        off += 27 * cin * cout + cout
+    nx, ny, nz = SHAPE
+    x = rng.normal(size=(nz, ny, nx, 4))
+    x = 0.5 * (x + x[::-1])
+    y = orc.nn_forward(SHAPE, params, x.reshape(-1, 4), C=C, alpha=0.1).reshape(nz, ny, nx, 4)
+    assert np.allclose(y, y[::-1], rtol=0, atol=1e-12)
 
 
 def test_conv_gradients_finite_difference(orc):
