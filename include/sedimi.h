@@ -206,6 +206,8 @@ typedef struct {
  * (EINVAL with a message on failure).  No device memory is touched yet. */
 int sedimi_create(const sedimi_params* p, int64_t max_particles, sedimi_ctx** out);
 void sedimi_destroy(sedimi_ctx* ctx);
+/* Message of the context's last failure; with NULL, of the calling thread's
+ * last failed context-free call ("null context" before any). */
 const char* sedimi_last_error(const sedimi_ctx* ctx);
 
 /* Device bytes the context needs; bind a device allocation of at least that
@@ -331,6 +333,33 @@ int sedimi_nn_forward(sedimi_ctx* ctx);
 int sedimi_nn_train_step(sedimi_ctx* ctx, double lr, double* loss);
 /* Sampled relative residual of SMOOTH against RAW, per channel (rel4[4]). */
 int sedimi_nn_check(sedimi_ctx* ctx, double* rel4);
+
+/* ---- the direct solve without an allocation ----
+ * For callers that cannot allocate device memory or bind a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The same direct solve as sedimi_smooth (all avg_ntau implicit
+ * steps, backward Euler or BDF2, uniform mesh) of channels [0, nch) of a
+ * caller's device field raw_dev [nch][ncell] into smooth_dev [nch][ncell]
+ * (caller-owned device memory on the current device, not overlapping),
+ * enqueued on hip_stream (NULL: the null stream), with no context.
+ * It reads the mesh (Lx, Ly, Lz, nx, ny, nz), avg_bandwidth, avg_bandwidth_z,
+ * avg_ntau and avg_scheme of p and ignores the rest; every axis <= 2048 cells,
+ * nch 1..7.
+ * Memory: the transform tables and one intermediate field live in a static
+ * device array of SEDIMI_STATIC_SCRATCH_BYTES that each GPU the library runs
+ * on holds until the process ends.  The call needs
+ * 8 (nx^2 + ny^2 + 2 nz^2 + nx + ny + nz) bytes (rounded up to 256) plus
+ * 8 nch nx ny nz bytes of it and refuses larger problems (ENOMEM).  Every
+ * call on one GPU shares that array, so calls that overlap on one GPU (on
+ * other streams or threads) race; calls on one stream are ordered.  It calls
+ * no allocator: the first call on each device looks up the array's address
+ * (not a stream operation).
+ * Asynchronous: no residual check (sedimi_smooth's needs a read back) and no
+ * synchronisation.  Errors (EINVAL, ENOMEM, EDEVICE) leave nothing enqueued;
+ * sedimi_last_error(NULL) gives the calling thread's last message. */
+#define SEDIMI_STATIC_SCRATCH_BYTES (64u << 20)
+int sedimi_smooth_static(const sedimi_params* p, int nch, const double* raw_dev,
+                         double* smooth_dev, void* hip_stream);
 
 /* Turn phase timing on (1) or off (0); turning it on clears the totals. */
 int sedimi_set_profiling(sedimi_ctx* ctx, int on);

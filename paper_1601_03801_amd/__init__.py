@@ -106,6 +106,7 @@ def lib():
         L.sedimi_compute_forces.argtypes = [P, I]
         L.sedimi_step.argtypes = [P, I, I]
         L.sedimi_rebuild.argtypes = [P]
+        L.sedimi_smooth_static.argtypes = [C.POINTER(sedimi_params), I, P, P, P]
         L.sedimi_average.argtypes = [P]
         L.sedimi_deposit.argtypes = [P]
         L.sedimi_smooth.argtypes = [P, I]
@@ -381,6 +382,24 @@ class Sedimi:
         s = sedimi_stats()
         self._chk(self._L.sedimi_get_stats(self._ctx, C.byref(s)))
         return {k: getattr(s, k) for k, _ in sedimi_stats._fields_}
+
+
+def smooth_static(prm: dict, raw, smooth, nch=None, stream=None, **opts):
+    """sedimi_smooth_static on torch float64 device tensors raw and smooth
+    ([nch, ncell], contiguous); enqueued on `stream` (default: the current
+    torch stream)."""
+    import torch
+    L = lib()
+    p = make_params(prm, d_max=opts.pop("d_max", 1.0), **opts)
+    for t in (raw, smooth):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("raw and smooth must be contiguous float64 device tensors")
+    nch = raw.shape[0] if nch is None else nch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    rc = L.sedimi_smooth_static(C.byref(p), int(nch), C.c_void_p(raw.data_ptr()),
+                                C.c_void_p(smooth.data_ptr()), C.c_void_p(s.cuda_stream))
+    if rc != OK:
+        raise SedimiError(rc, L.sedimi_last_error(None).decode())
 
 
 def exported_symbols():

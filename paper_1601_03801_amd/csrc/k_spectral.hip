@@ -22,6 +22,9 @@
 // K is staged through LDS 16 at a time.  Per MFMA a lane reads one double of
 // A and one of B, against eight LDS reads per 16 FMAs for a 4 x 4 outer
 // product on the vector units.
+#include <mutex>
+#include <string>
+
 #include "k_common.h"
 
 namespace sedimi {
@@ -204,41 +207,42 @@ void spectral_tables(const DevParams& P, double* t) {
     lz[m] = P.kz_diff * (2.0 - 2.0 * cos(pi * m / nz)) / (P.hz * P.hz);  // z diffusivity
 }
 
-// raw (nch channels) -> smooth, through A.sr / A.stmp.
-void launch_spectral(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
-                     bool bdf2, hipStream_t s) {
-  const int nx = P.nx, ny = P.ny, nz = P.nz;
-  const int64_t nc = P.ncell, plane = (int64_t)nx * ny;
-  const double* hx = A.spec;
+namespace {
+
+// The six axis passes of the direct solve: in -> t -> out -> t -> out -> t ->
+// out (t is scratch; in, t and out must not overlap).  tab holds the tables
+// in spectral_tables' order.
+void spectral_passes(int nx, int ny, int nz, const double* tab, const double* in, double* t,
+                     double* out, int nch, int ntau, double tau, bool bdf2, hipStream_t s) {
+  const int64_t plane = (int64_t)nx * ny, nc = plane * nz;
+  const double* hx = tab;
   const double* hy = hx + (size_t)nx * nx;
   const double* cz = hy + (size_t)ny * ny;
   const double* czi = cz + (size_t)nz * nz;
   const double* lx = czi + (size_t)nz * nz;
   const double* ly = lx + nx;
   const double* lz = ly + ny;
-  double* t0 = A.sr;
-  double* t1 = A.stmp;
-  auto xpass = [&](const double* in, double* out, double alpha) {
-    // lines along x: out[l][p] = alpha sum_q in[l][q] H_x[q][p]
+  auto xpass = [&](const double* a, double* c, double alpha) {
+    // lines along x: c[l][p] = alpha sum_q a[l][q] H_x[q][p]
     Gemm g{};
-    g.A = in, g.B = hx, g.C = out;
+    g.A = a, g.B = hx, g.C = c;
     g.M = (int)((int64_t)nch * nz * ny), g.N = nx, g.K = nx;
     g.lda = nx, g.ldb = nx, g.ldc = nx;
     g.alpha = alpha;
     gemm(g, 1, false, s);
   };
-  auto ypass = [&](const double* in, double* out, double alpha) {
+  auto ypass = [&](const double* a, double* c, double alpha) {
     Gemm g{};
-    g.A = hy, g.B = in, g.C = out;
+    g.A = hy, g.B = a, g.C = c;
     g.M = ny, g.N = nx, g.K = ny;
     g.lda = ny, g.ldb = nx, g.ldc = nx;
     g.sa = 0, g.sb = plane, g.sc = plane;
     g.alpha = alpha;
     gemm(g, nch * nz, false, s);
   };
-  auto zpass = [&](const double* in, double* out, const double* mat, bool spectral) {
+  auto zpass = [&](const double* a, double* c, const double* mat, bool spectral) {
     Gemm g{};
-    g.A = mat, g.B = in, g.C = out;
+    g.A = mat, g.B = a, g.C = c;
     g.M = nz, g.N = (int)plane, g.K = nz;
     g.lda = nz, g.ldb = plane, g.ldc = plane;
     g.sa = 0, g.sb = nc, g.sc = nc;
@@ -248,12 +252,135 @@ void launch_spectral(const DevParams& P, DevArrays& A, int nch, int ntau, double
     g.bdf2 = bdf2 ? 1 : 0;
     gemm(g, nch, spectral, s);
   };
-  xpass(A.raw, t0, 1.0);
-  ypass(t0, t1, 1.0);
-  zpass(t1, t0, cz, true);
-  zpass(t0, t1, czi, false);
-  ypass(t1, t0, 1.0 / ny);
-  xpass(t0, A.smooth, 1.0 / nx);
+  xpass(in, t, 1.0);
+  ypass(t, out, 1.0);
+  zpass(out, t, cz, true);
+  zpass(t, out, czi, false);
+  ypass(out, t, 1.0 / ny);
+  xpass(t, out, 1.0 / nx);
+}
+
+// ---- the direct solve without a workspace ----
+// Its tables and intermediate field live in this static device array; each
+// GPU the library runs on holds its own copy until the process ends.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in): it uses the device address looked up once per device.
+static __device__ __align__(256) unsigned char scratch[SEDIMI_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up at the first
+// call on each device, with that device current).
+hipError_t scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// The tables of spectral_tables, computed on the device (the same integer
+// angle reduction; cosines and sines from the device's FP64 library).
+__global__ void k_spectral_tables(int nx, int ny, int nz, double hx, double hy, double hz,
+                                  double kz_diff, double* __restrict__ t) {
+  const double pi = 3.14159265358979323846;
+  const int64_t sx = (int64_t)nx * nx, sy = (int64_t)ny * ny, sz = (int64_t)nz * nz;
+  const int64_t total = sx + sy + 2 * sz + nx + ny + nz;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    double v;
+    if (q < sx + sy) {
+      const int n = q < sx ? nx : ny;
+      const int64_t r = q < sx ? q : q - sx;
+      const int64_t p = r / n, k = r % n;
+      const double a = 2.0 * pi * (double)((p * k) % n) / n;
+      v = cos(a) + sin(a);
+    } else if (q < sx + sy + 2 * sz) {
+      // C_z[m][k] = cos(pi m (2k + 1) / (2 nz)); C_z^-1[k][m] = (1 or 2)/nz C_z[m][k]
+      const int64_t r = q - sx - sy;
+      const bool inv = r >= sz;
+      const int64_t rr = inv ? r - sz : r;
+      const int64_t m = inv ? rr % nz : rr / nz, k = inv ? rr / nz : rr % nz;
+      const int64_t ang = (m * (2 * k + 1)) % (4 * (int64_t)nz);
+      const double c = cos(pi * (double)ang / (2.0 * nz));
+      v = inv ? (m == 0 ? 1.0 : 2.0) / nz * c : c;
+    } else {
+      const int64_t r = q - sx - sy - 2 * sz;
+      if (r < nx) {
+        v = (2.0 - 2.0 * cos(2.0 * pi * r / nx)) / (hx * hx);
+      } else if (r < nx + ny) {
+        v = (2.0 - 2.0 * cos(2.0 * pi * (r - nx) / ny)) / (hy * hy);
+      } else {
+        v = kz_diff * (2.0 - 2.0 * cos(pi * (r - nx - ny) / nz)) / (hz * hz);
+      }
+    }
+    t[q] = v;
+  }
+}
+
+__global__ void k_copy_field(int64_t n, const double* __restrict__ a, double* __restrict__ b) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x)
+    b[q] = a[q];
+}
+
+}  // namespace
+
+// raw (nch channels) -> smooth, through A.sr.
+void launch_spectral(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
+                     bool bdf2, hipStream_t s) {
+  spectral_passes(P.nx, P.ny, P.nz, A.spec, A.raw, A.sr, A.smooth, nch, ntau, tau, bdf2, s);
+}
+
+size_t spectral_static_bytes(int nx, int ny, int nz, int nch) {
+  const size_t tab = (size_t)nx * nx + (size_t)ny * ny + 2 * (size_t)nz * nz + nx + ny + nz;
+  return ((tab * sizeof(double) + 255) & ~(size_t)255) +
+         (size_t)nch * nx * ny * nz * sizeof(double);
+}
+
+int spectral_static(int nx, int ny, int nz, double hx, double hy, double hz, double kz_diff,
+                    int nch, int ntau, double tau, bool bdf2, const double* raw, double* out,
+                    hipStream_t s, std::string* err) {
+  const size_t need = spectral_static_bytes(nx, ny, nz, nch);
+  if (need > (size_t)SEDIMI_STATIC_SCRATCH_BYTES) {
+    *err = "problem needs " + std::to_string(need) + " bytes of static scratch, more than the " +
+           std::to_string((size_t)SEDIMI_STATIC_SCRATCH_BYTES) + " available";
+    return SEDIMI_ENOMEM;
+  }
+  void* base = nullptr;
+  hipError_t e = scratch_address(&base);
+  if (e != hipSuccess) {
+    *err = std::string("looking up the static scratch: ") + hipGetErrorString(e);
+    return SEDIMI_EDEVICE;
+  }
+  const int64_t n = (int64_t)nch * nx * ny * nz;
+  if (ntau == 0) {  // no pseudo-time step: the field unchanged
+    hipLaunchKernelGGL(k_copy_field, dim3(1024), dim3(256), 0, s, n, raw, out);
+  } else {
+    double* tab = (double*)base;
+    const size_t ntab = (size_t)nx * nx + (size_t)ny * ny + 2 * (size_t)nz * nz + nx + ny + nz;
+    double* t = (double*)((char*)base + ((ntab * sizeof(double) + 255) & ~(size_t)255));
+    hipLaunchKernelGGL(k_spectral_tables, dim3(1024), dim3(256), 0, s, nx, ny, nz, hx, hy, hz,
+                       kz_diff, tab);
+    spectral_passes(nx, ny, nz, tab, raw, t, out, nch, ntau, tau, bdf2, s);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    *err = std::string("launching the direct solve: ") + hipGetErrorString(e);
+    return SEDIMI_EDEVICE;
+  }
+  return SEDIMI_OK;
 }
 
 }  // namespace sedimi

@@ -89,6 +89,9 @@ namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
+// last failure of a context-free call, per thread
+thread_local std::string g_noctx_err = "null context";
+
 int fail(sedimi_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
   return code;
@@ -516,7 +519,45 @@ int sedimi_create(const sedimi_params* p, int64_t max_particles, sedimi_ctx** ou
 
 void sedimi_destroy(sedimi_ctx* c) { delete c; }
 
-const char* sedimi_last_error(const sedimi_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* sedimi_last_error(const sedimi_ctx* c) {
+  return c ? c->err.c_str() : g_noctx_err.c_str();
+}
+
+int sedimi_smooth_static(const sedimi_params* p, int nch, const double* raw, double* out,
+                         void* stream) {
+  auto bad = [](int code, const std::string& msg) {
+    g_noctx_err = msg;
+    return code;
+  };
+  if (!p) return bad(SEDIMI_EINVAL, "null parameters");
+  if (!(p->Lx > 0 && p->Ly > 0 && p->Lz > 0) || p->nx < 1 || p->ny < 1 || p->nz < 1)
+    return bad(SEDIMI_EINVAL, "domain and mesh must be positive");
+  if (std::max(p->nx, std::max(p->ny, p->nz)) > kDirectMaxAxis)
+    return bad(SEDIMI_EINVAL, "direct averaging solve needs <= 2048 cells per axis");
+  if (!(p->avg_bandwidth >= 0 && std::isfinite(p->avg_bandwidth)) ||
+      !(p->avg_bandwidth_z >= 0 && std::isfinite(p->avg_bandwidth_z)) || p->avg_ntau < 0)
+    return bad(SEDIMI_EINVAL, "averaging parameters out of range");
+  if (p->avg_scheme != SEDIMI_SCHEME_EULER && p->avg_scheme != SEDIMI_SCHEME_BDF2)
+    return bad(SEDIMI_EINVAL, "unknown averaging scheme");
+  if (nch < 1 || nch > 7) return bad(SEDIMI_EINVAL, "nch must be 1..7");
+  if (!raw || !out) return bad(SEDIMI_EINVAL, "null field");
+  const size_t bytes = sizeof(double) * (size_t)nch * p->nx * p->ny * p->nz;
+  if ((const char*)raw < (const char*)out + bytes && (const char*)out < (const char*)raw + bytes)
+    return bad(SEDIMI_EINVAL, "raw and smooth fields overlap");
+  double kz = 1.0;
+  if (p->avg_bandwidth_z > 0 && p->avg_bandwidth > 0) {
+    const double r = p->avg_bandwidth_z / p->avg_bandwidth;
+    kz = r * r;
+  }
+  std::string err;
+  const int rc = spectral_static(p->nx, p->ny, p->nz, p->Lx / p->nx, p->Ly / p->ny,
+                                 p->Lz / p->nz, kz, nch, p->avg_ntau,
+                                 0.25 * p->avg_bandwidth * p->avg_bandwidth,
+                                 p->avg_scheme == SEDIMI_SCHEME_BDF2, raw, out,
+                                 (hipStream_t)stream, &err);
+  if (rc) return bad(rc, err);
+  return SEDIMI_OK;
+}
 
 size_t sedimi_workspace_bytes(const sedimi_ctx* c) { return c ? c->ws_bytes : 0; }
 

@@ -192,5 +192,12 @@ void launch_spectral(const DevParams& P, DevArrays& A, int nch, int ntau, double
                      bool bdf2, hipStream_t s);
 size_t spectral_table_doubles(const DevParams& P);
 void spectral_tables(const DevParams& P, double* host_tab);
+// The same solve of a caller's device field without a workspace: tables and
+// the intermediate field in the library's static device scratch (see
+// sedimi_smooth_static).  Enqueue only; SEDIMI_OK or an error code with *err.
+size_t spectral_static_bytes(int nx, int ny, int nz, int nch);
+int spectral_static(int nx, int ny, int nz, double hx, double hy, double hz, double kz_diff,
+                    int nch, int ntau, double tau, bool bdf2, const double* raw, double* out,
+                    hipStream_t s, std::string* err);
 
 }  // namespace sedimi
