@@ -122,8 +122,9 @@ typedef struct {
   /* learned stand-in for the diffusion averaging (not part of the paper) */
   int nn_enable;             /* 1: allocate the 6-layer, 32-channel 3-D CNN */
   double nn_alpha;           /* leaky-ReLU slope for negative arguments */
-  double nn_bound;           /* fallback when the sampled relative residual exceeds this */
-  double nn_sample;          /* fraction of cells in the residual sample */
+  double nn_bound;           /* fallback when the check's estimated relative error of the
+                                solid fraction exceeds this */
+  double nn_sample;          /* share of z-columns (so of cells) the check samples */
   uint64_t nn_seed;          /* seed of the residual sample */
   int avg_solver;            /* SEDIMI_SOLVE_*: how the implicit steps are solved */
   double avg_bandwidth_z;    /* averaging bandwidth across the bed, along z (m); 0: the
@@ -169,7 +170,7 @@ typedef struct {
 
 /* averaging modes (sedimi_set_avg_mode) */
 #define SEDIMI_AVG_PLAIN 0             /* deposition + implicit diffusion solve */
-#define SEDIMI_AVG_SURROGATE_CHECKED 1 /* network, sampled residual check, plain
+#define SEDIMI_AVG_SURROGATE_CHECKED 1 /* network, sampled error check, plain
                                           solve when the check fails */
 #define SEDIMI_AVG_SURROGATE 2         /* network only */
 
@@ -187,8 +188,12 @@ typedef struct {
                              walls included (now) */
   int64_t nn_calls;       /* averagings answered by the network (checked or not) */
   int64_t nn_fallbacks;   /* checked averagings that fell back to the plain solve */
-  double nn_last_check;   /* largest per-channel relative residual of the last check */
+  double nn_last_check;   /* estimated relative error of the solid fraction at the last
+                             check */
   int64_t particles;      /* particles in the context */
+  double nn_check_trunc;  /* mass of the check's Green's function outside its window */
+  int32_t nn_check_window[3]; /* the window's half widths in cells (x, y, z) */
+  int32_t nn_check_columns;   /* z-columns the check samples */
 } sedimi_stats;
 
 /* Device time per phase of sedimi_step / sedimi_average, measured with HIP
@@ -305,17 +310,33 @@ int sedimi_set_avg_mode(sedimi_ctx* ctx, int mode);
 /* ---- learned stand-in for the diffusion averaging ----
  * A 6-layer 3-D CNN (3x3x3 taps; z dilations 1, 2, 4, 4, 2, 1; 32 channels;
  * layer 1: 4 -> 32, layers 2-5: 32 -> 32 with identity skips, layer 6: 32 -> 4;
- * leaky ReLU; output = input + network) mapping the deposited fields to the
- * smoothed ones in per-channel normalised units; periodic in x, y and mirror
+ * leaky ReLU) mapping the deposited fields x to the smoothed ones in
+ * per-channel normalised units as y = S x + network(x - S x).  The skip S is
+ * the diffusion of Eq. 12 split by axis: each implicit step replaced by the
+ * product of the exact one-dimensional implicit steps along x, y and z
+ * (FP32, computed from the mesh, the bandwidths and avg_ntau); it leaves only
+ * the steps' small non-separable cross terms to the network, which reads the
+ * part of the field S smooths away.  Periodic in x, y and mirror
  * padded in z (the field extended by reflection about the wall faces, as the
  * zero-flux walls of Eq. 12 reflect the diffusion).  BF16 weights and
  * activations, FP32 accumulation and output.
  * Parameters are a flat FP32 vector: per layer w[27][cin][cout] then b[cout],
- * tap t = (dz+1)*9 + (dy+1)*3 + (dx+1).  The plain solve stays the fallback:
- * a checked averaging accepts the network's field y only if, on the seeded
- * sample of cells, |A^ntau y - raw| / |y| <= nn_bound for every channel
- * (A = I - dtau L_h, the implicit step's operator; its inverse has norm <= 1,
- * so the residual bounds the error against the plain solve). */
+ * tap t = (dz+1)*9 + (dy+1)*3 + (dx+1).  The plain solve stays the fallback
+ * and the judge: a checked averaging estimates the network's error on a
+ * seeded sample of whole z-columns (the nn_sample share of the columns, so of
+ * the cells), where the plain solution is the Green's function G of all ntau
+ * implicit steps of Eq. 12, (I - dtau L_h)^-ntau, applied to RAW: over a
+ * window of at most 9 x 9 x 65 cells (periodic in x, y; the walls' mirror
+ * images in z) that holds all but 1e-4 of G's mass where the mesh allows
+ * (chosen at sedimi_bind_workspace; sedimi_get_stats reports it and the mass
+ * outside, which bounds the estimate's own error by that share of the
+ * field's largest value).  It accepts the network's field y if
+ * |y - G*RAW| / |G*RAW| over the sample is <= nn_bound for the solid fraction
+ * (channel 0, the field the particle step reads back); otherwise the plain
+ * solve runs.  On meshes where G reaches beyond the window (cells coarse
+ * against the bandwidth) the estimate cannot resolve small errors and the
+ * check falls back.  Backward Euler only (the network is refused with
+ * BDF2). */
 int sedimi_nn_param_count(const sedimi_ctx* ctx, int64_t* n);
 /* He-normal initial weights (seeded), zero last layer and biases, zero Adam moments. */
 int sedimi_nn_init(sedimi_ctx* ctx, uint64_t seed);
@@ -325,13 +346,35 @@ int sedimi_nn_get_params(sedimi_ctx* ctx, float* p, int64_t n);
 int sedimi_nn_get_grads(sedimi_ctx* ctx, float* g, int64_t n);
 /* Per-channel normalisation x_n = (x - mean) / std of inputs and targets. */
 int sedimi_nn_set_norm(sedimi_ctx* ctx, const double* mean4, const double* std4);
+/* Per-channel weights w of the training loss (default 1 each): the loss is
+ * sum_ch w_ch mean over cells of (y - target)^2 / 4.  Weights that equalise
+ * the channels' errors let a channel with a small error (the solid fraction)
+ * be learned beside noisier ones. */
+int sedimi_nn_set_loss_weights(sedimi_ctx* ctx, const double* w4);
 /* SMOOTH <- network(RAW) (no check). */
 int sedimi_nn_forward(sedimi_ctx* ctx);
-/* One Adam step (lr; beta 0.9 / 0.999; eps 1e-8) on the mean-squared error
- * between network(RAW) and SMOOTH in normalised units; *loss (may be NULL)
- * receives the loss before the step.  RAW and SMOOTH are not modified. */
+/* One Adam step (lr; beta 0.9 / 0.999; eps 1e-8) on the weighted
+ * mean-squared error between network(RAW) and SMOOTH in normalised units;
+ * *loss (may be NULL) receives the loss before the step.  RAW and SMOOTH are
+ * not modified. */
 int sedimi_nn_train_step(sedimi_ctx* ctx, double lr, double* loss);
-/* Sampled relative residual of SMOOTH against RAW, per channel (rel4[4]). */
+/* The network's tensors of the last sedimi_nn_train_step (its forward
+ * keeps them all; sedimi_nn_forward refreshes X, XB, SX, H and Y only), for
+ * inspection and element-wise tests, as FP32 (BF16 values are exact in FP32)
+ * channel-last [ncell][channels]: n must be 4 ncell, or 32 ncell for the
+ * per-layer tensors, layer 0..4 (the outputs of layers 1..5). */
+#define SEDIMI_NN_X 0   /* normalised input, FP32 [ncell][4] */
+#define SEDIMI_NN_XB 1  /* its BF16 copy, the first layer's input [ncell][4] */
+#define SEDIMI_NN_SX 2  /* the skip S x, FP32 [ncell][4] */
+#define SEDIMI_NN_Z 3   /* pre-activation z_l, BF16 [ncell][32] */
+#define SEDIMI_NN_H 4   /* activation h_l, BF16 [ncell][32] */
+#define SEDIMI_NN_Y 5   /* output S x + conv6(h_5) + b, FP32 [ncell][4] (normalised) */
+#define SEDIMI_NN_DY 6  /* loss gradient at the output, BF16 [ncell][4] */
+#define SEDIMI_NN_DH 7  /* loss gradient at h_l, BF16 [ncell][32] */
+#define SEDIMI_NN_DZ 8  /* loss gradient at z_l, BF16 [ncell][32] */
+int sedimi_nn_get_tensor(sedimi_ctx* ctx, int which, int layer, float* out, int64_t n);
+/* The check's error estimate for SMOOTH, per channel (rel4[4]):
+ * |SMOOTH - G*RAW| / |G*RAW| over the sampled columns. */
 int sedimi_nn_check(sedimi_ctx* ctx, double* rel4);
 
 /* ---- the direct solve without an allocation ----

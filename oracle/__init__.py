@@ -113,10 +113,12 @@ def _declare_cnn(L):
     L.orc_conv3d_bwd.restype = None
     L.orc_nn_param_count.argtypes = [i]
     L.orc_nn_param_count.restype = i64
-    L.orc_nn_forward.argtypes = [i, i, i, i, d, i, P, P, P, P]
+    L.orc_nn_forward.argtypes = [i, i, i, i, d, i, P, P, P, P, P]
     L.orc_nn_forward.restype = None
-    L.orc_nn_loss_grad.argtypes = [i, i, i, i, d, i, P, P, P, P]
+    L.orc_nn_loss_grad.argtypes = [i, i, i, i, d, i, P, P, P, P, P, P]
     L.orc_nn_loss_grad.restype = d
+    L.orc_split_smooth.argtypes = [i, i, i, i, P, P, P]
+    L.orc_split_smooth.restype = None
     L.orc_adam.argtypes = [i64, P, P, P, P, d, d, d, d, i64]
     L.orc_adam.restype = None
 
@@ -353,21 +355,47 @@ def nn_param_count(C=32):
     return int(lib().orc_nn_param_count(C))
 
 
-def nn_forward(shape, params, x, C=32, alpha=0.1, bf16=False):
+def split_coefficients(prm):
+    """{c_x, c_y, c_z, N} of the network's skip S for a parameter dict:
+    c_a = dtau D_a / h_a^2 with dtau = b^2 / (4 N) and D_z = (b_z / b)^2."""
+    N = max(1, int(prm["avg_ntau"]))
+    b = prm["avg_bandwidth"]
+    bz = prm.get("avg_bandwidth_z", 0.0) or b
+    dtau = 0.25 * b * b / N
+    hx, hy, hz = prm["Lx"] / prm["nx"], prm["Ly"] / prm["ny"], prm["Lz"] / prm["nz"]
+    kz = (bz / b) ** 2 if b > 0 else 1.0
+    return np.array([dtau / hx ** 2, dtau / hy ** 2, dtau * kz / hz ** 2, float(N)])
+
+
+def split_smooth(shape, split, x):
+    """S x for channel-last x [n, nchan] (the network's skip)."""
+    nx, ny, nz = shape
+    x = _f64(x)
+    nchan = x.shape[1] if x.ndim == 2 else 1
+    out = np.zeros_like(x)
+    lib().orc_split_smooth(nx, ny, nz, nchan, _ptr(_f64(split)), _ptr(x), _ptr(out))
+    return out
+
+
+def nn_forward(shape, params, x, C=32, alpha=0.1, bf16=False, split=None):
     nx, ny, nz = shape
     params, x = _f64(params), _f64(x)
+    sp = None if split is None else _f64(split)
     y = np.zeros((nx * ny * nz, 4))
-    lib().orc_nn_forward(nx, ny, nz, C, alpha, 1 if bf16 else 0, _ptr(params), _ptr(x),
-                         _ptr(y), None)
+    lib().orc_nn_forward(nx, ny, nz, C, alpha, 1 if bf16 else 0, _ptr(params), _ptr(sp),
+                         _ptr(x), _ptr(y), None)
     return y
 
 
-def nn_loss_grad(shape, params, x, target, C=32, alpha=0.1, bf16=False):
+def nn_loss_grad(shape, params, x, target, C=32, alpha=0.1, bf16=False, split=None,
+                 loss_weights=None):
     nx, ny, nz = shape
     params, x, target = _f64(params), _f64(x), _f64(target)
+    sp = None if split is None else _f64(split)
+    lw = None if loss_weights is None else _f64(loss_weights)
     g = np.zeros_like(params)
     loss = lib().orc_nn_loss_grad(nx, ny, nz, C, alpha, 1 if bf16 else 0, _ptr(params),
-                                  _ptr(x), _ptr(target), _ptr(g))
+                                  _ptr(sp), _ptr(lw), _ptr(x), _ptr(target), _ptr(g))
     return loss, g
 
 

@@ -64,12 +64,14 @@ class sedimi_stats(C.Structure):
                 ("solve_residual", C.c_double), ("mean_neighbors", C.c_double),
                 ("mean_contacts", C.c_double), ("nn_calls", C.c_int64),
                 ("nn_fallbacks", C.c_int64), ("nn_last_check", C.c_double),
-                ("particles", C.c_int64)]
+                ("particles", C.c_int64), ("nn_check_trunc", C.c_double),
+                ("nn_check_window", C.c_int32 * 3), ("nn_check_columns", C.c_int32)]
 
 
 NPHASES = 6
 PHASES = ("drift", "rebuild", "forces", "deposit", "smooth", "nn_train")
 AVG_PLAIN, AVG_SURROGATE_CHECKED, AVG_SURROGATE = 0, 1, 2
+NN_TENSORS = {"x": 0, "xb": 1, "sx": 2, "z": 3, "h": 4, "y": 5, "dy": 6, "dh": 7, "dz": 8}
 
 
 class sedimi_profile(C.Structure):
@@ -129,8 +131,10 @@ def lib():
         L.sedimi_nn_get_grads.argtypes = [P, P, i64]
         L.sedimi_nn_set_norm.argtypes = [P, P, P]
         L.sedimi_nn_forward.argtypes = [P]
+        L.sedimi_nn_set_loss_weights.argtypes = [P, P]
         L.sedimi_nn_train_step.argtypes = [P, C.c_double, C.POINTER(C.c_double)]
         L.sedimi_nn_check.argtypes = [P, P]
+        L.sedimi_nn_get_tensor.argtypes = [P, I, I, P, i64]
         L.sedimi_get_profile.argtypes = [P, C.POINTER(sedimi_profile)]
         _lib = L
     return _lib
@@ -356,6 +360,10 @@ class Sedimi:
         mean, std = _f64(mean), _f64(std)
         self._chk(self._L.sedimi_nn_set_norm(self._ctx, _ptr(mean), _ptr(std)))
 
+    def nn_set_loss_weights(self, w):
+        w = _f64(w)
+        self._chk(self._L.sedimi_nn_set_loss_weights(self._ctx, _ptr(w)))
+
     def nn_forward(self):
         self._chk(self._L.sedimi_nn_forward(self._ctx))
 
@@ -363,6 +371,16 @@ class Sedimi:
         loss = C.c_double(0.0)
         self._chk(self._L.sedimi_nn_train_step(self._ctx, float(lr), C.byref(loss)))
         return loss.value
+
+    def nn_tensor(self, which, layer=0):
+        """A stored network tensor (NN_* names) as float32 [ncell, channels]."""
+        which = NN_TENSORS[which] if isinstance(which, str) else which
+        ch = 32 if which in (NN_TENSORS["z"], NN_TENSORS["h"], NN_TENSORS["dh"],
+                             NN_TENSORS["dz"]) else 4
+        out = np.zeros((self.ncell, ch), np.float32)
+        self._chk(self._L.sedimi_nn_get_tensor(self._ctx, int(which), int(layer), _ptr(out),
+                                               out.size))
+        return out
 
     def nn_check(self):
         rel = np.zeros(4)
@@ -381,7 +399,9 @@ class Sedimi:
     def stats(self):
         s = sedimi_stats()
         self._chk(self._L.sedimi_get_stats(self._ctx, C.byref(s)))
-        return {k: getattr(s, k) for k, _ in sedimi_stats._fields_}
+        out = {k: getattr(s, k) for k, _ in sedimi_stats._fields_}
+        out["nn_check_window"] = list(s.nn_check_window)
+        return out
 
 
 def smooth_static(prm: dict, raw, smooth, nch=None, stream=None, **opts):

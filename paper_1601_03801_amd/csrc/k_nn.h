@@ -32,6 +32,19 @@ struct EpiArgs {
 
 struct NNNorm {
   double mean[4], std[4];
+  double lw[4];  // per-channel weights of the training loss
+};
+
+// The network's skip S (the diffusion split by axis): circulant taps of the
+// periodic one-dimensional steps in x and y (device FP64 arrays; tap t at
+// offset off0 + t), and the z-line Thomas table (reciprocal pivots [nz],
+// back-substitution multipliers [nz]) with the z coefficient c_z.
+struct SplitTabs {
+  const double* tapx;
+  const double* tapy;
+  const double* ztab;
+  int off0x, ntapx, off0y, ntapy;
+  double cz;
 };
 
 size_t nn_packed_elems(int cin, int cout);
@@ -44,6 +57,13 @@ int launch_conv_dw(int cin, int cout, const ConvGeom& g, const __bf16* x, const 
                    hipStream_t s);
 void launch_nn_prep(int ncell, const double* raw, const NNNorm& nm, float* xf, __bf16* xb,
                     hipStream_t s);
+// out = S in on channel-last FP32 [ncell][4] fields (tmp: scratch of the same
+// size); needs split_lds_bytes(nz) bytes of LDS per block (nz <= 150).
+size_t split_lds_bytes(int nz);
+void launch_split(int nx, int ny, int nz, int ntau, const SplitTabs& st, const float* in,
+                  float* tmp, float* out, hipStream_t s);
+// The network's input x - S x in BF16 (over the copy launch_nn_prep wrote).
+void launch_nn_highpass(int ncell, const float* xf, const float* xs, __bf16* xb, hipStream_t s);
 void launch_nn_out(int ncell, const float* y, const NNNorm& nm, double* smooth, hipStream_t s);
 unsigned launch_nn_loss(int ncell, const float* y, const double* smooth, const NNNorm& nm,
                         __bf16* dy, double* part, hipStream_t s);

@@ -22,6 +22,8 @@
 // reads, with per-block partial sums reduced in a fixed order.
 #include <math.h>
 
+#include <algorithm>
+
 #include "k_nn.h"
 
 namespace sedimi {
@@ -44,27 +46,36 @@ __device__ __forceinline__ float bf(float v) { return (float)(__bf16)v; }
 // k' = k - dil dz (`which` 0), and the mirror image, k' = -k - 1 - dil dz
 // below the bottom face or 2 nz - 1 - k - dil dz above the top one (`which`
 // 1); each exists only when it lies inside the mesh.  -1: no such plane.
+template <bool ADJ>
 __device__ __forceinline__ int zsrc(const ConvGeom& g, int k, int dz, int which) {
-  const int nz2 = 2 * g.nz, lo = g.dil * dz;
-  if (!g.neg) {
+  const int nz = g.nz, nz2 = 2 * nz, lo = g.dil * dz;
+  if (!ADJ) {
     if (which) return -1;
-    int j = (k + lo) % nz2;
+    int j = k + lo;
+    if (nz >= g.dil) return j < 0 ? -j - 1 : (j >= nz ? nz2 - 1 - j : j);  // one reflection
+    j %= nz2;
     j = j < 0 ? j + nz2 : j;
-    return j < g.nz ? j : nz2 - 1 - j;
+    return j < nz ? j : nz2 - 1 - j;
   }
-  int m = (which ? -k - 1 - lo : k - lo) % nz2;
+  int m = which ? -k - 1 - lo : k - lo;
+  if (nz >= g.dil) {  // m lies in [-nz - dil, nz + dil): at most one period away
+    m = m < 0 ? m + nz2 : (m >= nz2 ? m - nz2 : m);
+    return m < nz ? m : -1;
+  }
+  m %= nz2;
   m = m < 0 ? m + nz2 : m;
-  return m < g.nz ? m : -1;
+  return m < nz ? m : -1;
 }
 
 // Neighbour cell of (i, j, k) for tap t and z source `which` (x and y offsets
 // negated when neg != 0); -1 when that z source does not exist; periodic in x
 // and y.
+template <bool ADJ>
 __device__ __forceinline__ int tap_cell(const ConvGeom& g, int i, int j, int k, int t,
                                         int which) {
   int dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-  if (g.neg) dy = -dy, dx = -dx;
-  const int kk = zsrc(g, k, t / 9 - 1, which);
+  if (ADJ) dy = -dy, dx = -dx;
+  const int kk = zsrc<ADJ>(g, k, t / 9 - 1, which);
   if (kk < 0) return -1;
   int ii = i + dx;
   ii = ii < 0 ? ii + g.nx : (ii >= g.nx ? ii - g.nx : ii);
@@ -185,8 +196,9 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(ConvGeom g, const __bf16*
     // second pass over the mirror-image sources, needed only by waves with a
     // cell within one dilation of a wall (each product accumulates in FP32,
     // as for any other tap).
+    constexpr bool kAdj = EPI == EPI_BWD;  // the data gradient: negated offsets
     int npass = 1;
-    if (g.neg) {
+    if (kAdj) {
       bool near = false;
 #pragma unroll
       for (int m = 0; m < TM; ++m)
@@ -203,11 +215,11 @@ __global__ __launch_bounds__(kConvThreads) void k_conv(ConvGeom g, const __bf16*
         for (int m = 0; m < TM; ++m) {
           v4bf lo = {}, hi = {};
           if (valid[m] && t0 < 27) {
-            const int q = tap_cell(g, ci[m], cj[m], ck[m], t0, which);
+            const int q = tap_cell<kAdj>(g, ci[m], cj[m], ck[m], t0, which);
             if (q >= 0) lo = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
           }
           if (valid[m] && t1 < 27) {
-            const int q = tap_cell(g, ci[m], cj[m], ck[m], t1, which);
+            const int q = tap_cell<kAdj>(g, ci[m], cj[m], ck[m], t1, which);
             if (q >= 0) hi = *reinterpret_cast<const v4bf*>(in + (size_t)q * 4);
           }
           a[m] = v8bf{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
@@ -292,7 +304,8 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
   const int row = lane & 15, grp = lane >> 4;
   const int ntx = (g.nx + kTileX - 1) / kTileX, nty = (g.ny + kTileY - 1) / kTileY;
   const int ntiles = ntx * nty * g.nz;
-  const int sgn = g.neg ? -1 : 1;
+  constexpr bool kAdj = EPI == EPI_BWD;  // the data gradient: negated offsets
+  const int sgn = kAdj ? -1 : 1;
   // Residual layers take the centre z-tap last: it then stays in LDS for the
   // epilogue, which reads the residual input h_in (the layer's own input,
   // plane z itself) from there instead of from memory.
@@ -300,18 +313,23 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
   auto phase = [](int i) { return kCentreLast ? (i == 0 ? 0 : (i == 1 ? 2 : 1)) : i; };
   // source plane of job j of output plane tz (-1: none); z-tap p covers the
   // forward offset dz = p - 1
-  auto job_src = [&](int tz, int j) { return zsrc(g, tz, phase(j >> 1) - 1, j & 1); };
-  auto first_job = [&](int tz, int j) {
-    while (j < 6 && job_src(tz, j) < 0) ++j;
-    return j;
+  auto job_src = [&](int tz, int j) { return zsrc<kAdj>(g, tz, phase(j >> 1) - 1, j & 1); };
+  // the tile's jobs as a bit mask (bit j: job j has a source plane)
+  auto jobs_of = [&](int tz) {
+    unsigned m = 0;
+    for (int j = 0; j < 6; ++j)
+      if (!(j & 1) || kAdj) m |= (job_src(tz, j) >= 0 ? 1u : 0u) << j;
+    return m;
   };
+  auto lowest = [](unsigned m) { return __builtin_ctz(m); };
   // Plane of (tile, job) -> registers.  The loads are unconditional (clamped
   // to valid addresses): conditional loads would make the compiler merge and
   // copy the registers, which waits for the loads right away.
   uint4 st[kUnitsPerThread];
-  auto fetch = [&](int tile, int j) {
-    const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
-    const int kc = job_src(tz, j);
+  // (kc is computed at the call sites, so that the lambda stays small, is
+  // inlined, and st stays in registers)
+  auto fetch = [&](int tile, int kc) __attribute__((always_inline)) {
+    const int tx = tile % ntx, ty = (tile / ntx) % nty;
 #pragma unroll
     for (int q = 0; q < kUnitsPerThread; ++q) {
       int u = threadIdx.x + q * kTiledThreads;
@@ -328,32 +346,37 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
   };
   int tile = blockIdx.x;
   // every plane has at least one job: the centre z-tap's direct source
-  if (tile < ntiles) fetch(tile, first_job(tile / (ntx * nty), 0));
+  unsigned jobs = tile < ntiles ? jobs_of(tile / (ntx * nty)) : 0u;
+  if (tile < ntiles) fetch(tile, job_src(tile / (ntx * nty), lowest(jobs)));
   for (; tile < ntiles; tile += gridDim.x) {
     const int tx = tile % ntx, ty = (tile / ntx) % nty, tz = tile / (ntx * nty);
+    const int next = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : tile;
+    const unsigned next_jobs = jobs_of(next / (ntx * nty));
     v4f acc[TM][NT];
 #pragma unroll
     for (int m = 0; m < TM; ++m)
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) acc[m][nt] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 1
-    for (int j = first_job(tz, 0); j < 6; j = first_job(tz, j + 1)) {
+    for (unsigned left = jobs; left; left &= left - 1) {
+      const int j = lowest(left);
       const int p = phase(j >> 1);
       __syncthreads();  // every wave is done with the previous plane
 #pragma unroll
       for (int q = 0; q < kUnitsPerThread; ++q) {
         const int u = threadIdx.x + q * kTiledThreads;
-        if (u < kPlaneUnits) reinterpret_cast<uint4*>(&sp[0][0][0])[u] = st[q];
+        // member by member: a whole-struct copy of the vector type keeps st
+        // out of registers (it is then spilled to scratch between loads)
+        if (u < kPlaneUnits)
+          reinterpret_cast<uint4*>(&sp[0][0][0])[u] = make_uint4(st[q].x, st[q].y, st[q].z, st[q].w);
       }
       __syncthreads();
       // the next plane (of this tile, else the first of the next tile; the
       // last tile refetches its own first plane) is in flight during the MFMAs
-      int ft = tile, fj = first_job(tz, j + 1);
-      if (fj >= 6) {
-        ft = tile + (int)gridDim.x < ntiles ? tile + (int)gridDim.x : tile;
-        fj = first_job(ft / (ntx * nty), 0);
-      }
-      fetch(ft, fj);
+      // (one call site: loads in two branches would be waited for at the join)
+      const unsigned rest = left & (left - 1);
+      const int ft = rest ? tile : next;
+      fetch(ft, job_src(ft / (ntx * nty), rest ? lowest(rest) : lowest(next_jobs)));
 #pragma unroll 1
       for (int t9 = 0; t9 < 9; ++t9) {
         const int t = p * 9 + t9;
@@ -435,6 +458,7 @@ __global__ __launch_bounds__(kTiledThreads) void k_conv_tiled(ConvGeom g,
           }
         }
     }
+    jobs = next_jobs;
   }
 }
 
@@ -666,6 +690,14 @@ __global__ void k_nn_prep(int ncell, const double* __restrict__ raw, NNNorm nm,
   }
 }
 
+// The network's input: what the skip leaves behind, x - S x, in BF16.
+__global__ void k_nn_highpass(int64_t n4, const float* __restrict__ xf,
+                              const float* __restrict__ xs, __bf16* __restrict__ xb) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4;
+       q += (int64_t)gridDim.x * blockDim.x)
+    xb[q] = (__bf16)(xf[q] - xs[q]);
+}
+
 // Network output back to the smoothed field: smooth[ch][c] = y*std + mean.
 __global__ void k_nn_out(int ncell, const float* __restrict__ y, NNNorm nm,
                          double* __restrict__ smooth) {
@@ -675,8 +707,9 @@ __global__ void k_nn_out(int ncell, const float* __restrict__ y, NNNorm nm,
     smooth[(size_t)ch * ncell + c] = (double)y[(size_t)c * 4 + ch] * nm.std[ch] + nm.mean[ch];
 }
 
-// Loss gradient: target t = (smooth - mean)/std; dy = 2 (y - t) / (4 n) in
-// BF16; per-block FP64 partial sums of (y - t)^2.
+// Loss gradient: target t = (smooth - mean)/std; with the channel weight w,
+// dy = (2 w / (4 n)) (y - t) in BF16 (the factor 2 w / (4 n) formed in FP32);
+// per-block FP64 partial sums of w (y - t)^2.
 __global__ void k_nn_loss(int ncell, const float* __restrict__ y,
                           const double* __restrict__ smooth, NNNorm nm,
                           __bf16* __restrict__ dy, double* __restrict__ part) {
@@ -688,8 +721,9 @@ __global__ void k_nn_loss(int ncell, const float* __restrict__ y,
     for (int ch = 0; ch < 4; ++ch) {
       float t = (float)((smooth[(size_t)ch * ncell + c] - nm.mean[ch]) / nm.std[ch]);
       float d = y[(size_t)c * 4 + ch] - t;
-      acc += (double)d * (double)d;
-      dy[(size_t)c * 4 + ch] = (__bf16)(scale * d);
+      acc += nm.lw[ch] * ((double)d * (double)d);
+      const float sw = scale * (float)nm.lw[ch];
+      dy[(size_t)c * 4 + ch] = (__bf16)(sw * d);
     }
   }
   s[threadIdx.x] = acc;
@@ -742,9 +776,100 @@ __global__ void k_pack(const float* __restrict__ w, int cin, int cout,
   }
 }
 
+// ---- the network's skip S: the diffusion split by axis ----
+// out = S_a in along one periodic axis (a = x: stride 1, length nx; a = y:
+// stride nx, length ny) as a circulant: out[i] = sum_t tap[t] in[i + off0 + t]
+// (wrapped), FP64 sums of the FP32 channel-last cells.
+__global__ void k_split_line(int nx, int ny, int nz, int axis, int off0, int ntap,
+                             const double* __restrict__ tap, const float4* __restrict__ in,
+                             float4* __restrict__ out) {
+  const int64_t ncell = (int64_t)nx * ny * nz;
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < ncell;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(c % nx), j = (int)((c / nx) % ny);
+    const int n = axis == 0 ? nx : ny;
+    const int pos = axis == 0 ? i : j;
+    const int64_t stride = axis == 0 ? 1 : nx;
+    const int64_t base = c - (int64_t)pos * stride;
+    int q = (pos + off0) % n;
+    q = q < 0 ? q + n : q;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (int t = 0; t < ntap; ++t) {
+      const float4 v = in[base + (int64_t)q * stride];
+      const double w = tap[t];
+      a0 += w * v.x, a1 += w * v.y, a2 += w * v.z, a3 += w * v.w;
+      q = q + 1 == n ? 0 : q + 1;
+    }
+    out[c] = make_float4((float)a0, (float)a1, (float)a2, (float)a3);
+  }
+}
+
+// S_z: ntau backward-Euler steps along z with zero-flux walls, in place, for
+// kSplitCols consecutive columns per block held in LDS (FP64 sums, FP32
+// storage).  tab: reciprocal pivots [nz] then the Thomas multipliers [nz] of
+// the tridiagonal (1 + c n_k) u_k - c u_{k-1} - c u_{k+1}, n_k the number of
+// neighbours of plane k.
+constexpr int kSplitCols = 64;
+__global__ __launch_bounds__(kSplitCols) void k_split_z(int nx, int ny, int nz, int ntau,
+                                                        double c, const double* __restrict__ tab,
+                                                        float4* __restrict__ f) {
+  extern __shared__ float4 col[];  // [nz][kSplitCols]
+  const int64_t plane = (int64_t)nx * ny;
+  const int64_t c0 = (int64_t)blockIdx.x * kSplitCols;
+  const int t = threadIdx.x;
+  const bool live = c0 + t < plane;
+  for (int k = 0; k < nz; ++k)
+    if (live) col[k * kSplitCols + t] = f[k * plane + c0 + t];
+  if (live && nz > 1) {
+    const double* ib = tab;       // 1 / pivot
+    const double* gm = tab + nz;  // multiplier of the back substitution
+    for (int s = 0; s < ntau; ++s) {
+      // forward sweep: u_k = (f_k + c u_{k-1}) / pivot_k
+      float4 v = col[t];
+      double p0 = v.x * ib[0], p1 = v.y * ib[0], p2 = v.z * ib[0], p3 = v.w * ib[0];
+      col[t] = make_float4((float)p0, (float)p1, (float)p2, (float)p3);
+      for (int k = 1; k < nz; ++k) {
+        v = col[k * kSplitCols + t];
+        p0 = (v.x + c * p0) * ib[k];
+        p1 = (v.y + c * p1) * ib[k];
+        p2 = (v.z + c * p2) * ib[k];
+        p3 = (v.w + c * p3) * ib[k];
+        col[k * kSplitCols + t] = make_float4((float)p0, (float)p1, (float)p2, (float)p3);
+      }
+      // back substitution: u_k -= gamma_{k+1} u_{k+1}, carried in FP64
+      for (int k = nz - 2; k >= 0; --k) {
+        v = col[k * kSplitCols + t];
+        p0 = v.x - gm[k + 1] * p0;
+        p1 = v.y - gm[k + 1] * p1;
+        p2 = v.z - gm[k + 1] * p2;
+        p3 = v.w - gm[k + 1] * p3;
+        col[k * kSplitCols + t] = make_float4((float)p0, (float)p1, (float)p2, (float)p3);
+      }
+    }
+  }
+  for (int k = 0; k < nz; ++k)
+    if (live) f[k * plane + c0 + t] = col[k * kSplitCols + t];
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
+
+size_t split_lds_bytes(int nz) { return (size_t)nz * kSplitCols * sizeof(float4); }
+
+void launch_split(int nx, int ny, int nz, int ntau, const SplitTabs& st, const float* in,
+                  float* tmp, float* out, hipStream_t s) {
+  const int64_t ncell = (int64_t)nx * ny * nz;
+  const unsigned g = (unsigned)std::min<int64_t>((ncell + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_split_line, dim3(g), dim3(256), 0, s, nx, ny, nz, 0, st.off0x, st.ntapx,
+                     st.tapx, (const float4*)in, (float4*)tmp);
+  hipLaunchKernelGGL(k_split_line, dim3(g), dim3(256), 0, s, nx, ny, nz, 1, st.off0y, st.ntapy,
+                     st.tapy, (const float4*)tmp, (float4*)out);
+  const int64_t plane = (int64_t)nx * ny;
+  hipLaunchKernelGGL(k_split_z, dim3((unsigned)((plane + kSplitCols - 1) / kSplitCols)),
+                     dim3(kSplitCols), split_lds_bytes(nz), s, nx, ny, nz, ntau, st.cz, st.ztab,
+                     (float4*)out);
+}
 
 size_t nn_packed_elems(int cin, int cout) {
   int nt = (cout + 15) / 16;
@@ -807,6 +932,9 @@ int launch_conv_dw(int cin, int cout, const ConvGeom& g, const __bf16* x, const 
 void launch_nn_prep(int ncell, const double* raw, const NNNorm& nm, float* xf, __bf16* xb,
                     hipStream_t s) {
   hipLaunchKernelGGL(k_nn_prep, dim3(nblk(ncell)), dim3(256), 0, s, ncell, raw, nm, xf, xb);
+}
+void launch_nn_highpass(int ncell, const float* xf, const float* xs, __bf16* xb, hipStream_t s) {
+  hipLaunchKernelGGL(k_nn_highpass, dim3(2048), dim3(256), 0, s, (int64_t)ncell * 4, xf, xs, xb);
 }
 void launch_nn_out(int ncell, const float* y, const NNNorm& nm, double* smooth, hipStream_t s) {
   hipLaunchKernelGGL(k_nn_out, dim3(nblk(ncell)), dim3(256), 0, s, ncell, y, nm, smooth);

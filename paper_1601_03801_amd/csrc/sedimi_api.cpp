@@ -30,10 +30,35 @@ struct NNBufs {
   __bf16 *xb = nullptr, *dy6 = nullptr;
   __bf16* z[5] = {};
   __bf16* h[5] = {};
-  __bf16* dh[2] = {};
-  __bf16* dz[2] = {};
+  __bf16* dh[5] = {};  // gradient of the loss at h_l, z_l of layers 1..5 (kept for reading)
+  __bf16* dz[5] = {};
   float *part = nullptr, *part_b = nullptr;
+  // the check: Green's function window of the plain solve, sampled columns,
+  // per-column partials
+  double* gtab = nullptr;
+  int* cols = nullptr;
+  double* gpart = nullptr;
+  // the skip S (the diffusion split by axis): S x and scratch, FP32 [ncell][4];
+  // taps in x and y and the z-line table, FP64
+  float *xs = nullptr, *xt = nullptr;
+  double* stab = nullptr;
 };
+
+constexpr int kSplitMaxTaps = 129;  // circulant taps per periodic axis
+constexpr int kSplitMaxNz = 150;    // z-column held in LDS by the split's z solve
+
+// Window of the check's Green's function (host side).
+struct GreenWindow {
+  int rx = 0, ry = 0, rz = 0;
+  double trunc = 1.0;  // mass of the Green's function outside the window
+  std::vector<double> tab;  // [2ry+1][2rx+1][2rz+1]
+};
+constexpr int kGreenRxy = 4, kGreenRz = 32;
+int nn_check_columns(const sedimi_params& p) {
+  const int64_t ncol = (int64_t)p.nx * p.ny;
+  const int64_t m = (int64_t)ceil(p.nn_sample * (double)ncol);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(ncol, m));
+}
 
 int nn_cin(int l) { return l == 0 ? 4 : kNNC; }
 int nn_cout(int l) { return l == 5 ? 4 : kNNC; }
@@ -49,7 +74,7 @@ struct sedimi_ctx {
   sedimi_params prm;
   int avg_mode = SEDIMI_AVG_PLAIN;
   NNBufs nn;
-  NNNorm norm{{0, 0, 0, 0}, {1, 1, 1, 1}};
+  NNNorm norm{{0, 0, 0, 0}, {1, 1, 1, 1}, {1, 1, 1, 1}};
   int64_t adam_t = 0;
   int64_t nn_calls = 0, nn_fallbacks = 0;
   double nn_last_check = 0.0;
@@ -68,6 +93,9 @@ struct sedimi_ctx {
   bool direct = false;       // the implicit steps are solved by diagonalisation
   bool last_direct = false;  // the last plain solve was the direct one
   int check_blocks = 0;      // residual partials of the last direct solve
+  GreenWindow green;         // the network check's Green's function window
+  SplitTabs split{};         // the network's skip S (device tables)
+  int green_cols = 0;        // sampled columns of the network check
   std::string err;
   // phase timing
   bool prof = false;
@@ -88,6 +116,14 @@ struct sedimi_ctx {
 namespace {
 
 constexpr double kPi = 3.14159265358979323846;
+
+// splitmix64 (Steele, Lea & Flood): seeded weights and check samples
+uint64_t mix64(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
 
 // last failure of a context-free call, per thread
 thread_local std::string g_noctx_err = "null context";
@@ -208,13 +244,140 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
     b.dy6 = w.take<__bf16>(4 * nc);
     for (int l = 0; l < 5; ++l) b.z[l] = w.take<__bf16>(kNNC * nc);
     for (int l = 0; l < 5; ++l) b.h[l] = w.take<__bf16>(kNNC * nc);
-    for (int l = 0; l < 2; ++l) b.dh[l] = w.take<__bf16>(kNNC * nc);
-    for (int l = 0; l < 2; ++l) b.dz[l] = w.take<__bf16>(kNNC * nc);
+    for (int l = 0; l < 5; ++l) b.dh[l] = w.take<__bf16>(kNNC * nc);
+    for (int l = 0; l < 5; ++l) b.dz[l] = w.take<__bf16>(kNNC * nc);
     b.part = w.take<float>((size_t)kDwBlocks * 27 * kNNC * kNNC);
     b.part_b = w.take<float>((size_t)kDwBlocks * kNNC);
+    b.xs = w.take<float>(4 * nc);
+    b.xt = w.take<float>(4 * nc);
+    b.stab = w.take<double>(2 * kSplitMaxTaps + 2 * (size_t)c->P.nz);
+    b.gtab = w.take<double>((size_t)(2 * kGreenRxy + 1) * (2 * kGreenRxy + 1) * (2 * kGreenRz + 1));
+    b.cols = w.take<int>((size_t)nn_check_columns(c->prm));
+    b.gpart = w.take<double>(8 * (size_t)nn_check_columns(c->prm));
     if (base) const_cast<sedimi_ctx*>(c)->nn = b;
   }
   return align256(w.off);
+}
+
+// Green's function of all N_tau backward-Euler steps, (I - dtau L)^-N_tau
+// delta, on the unbounded mesh with this mesh's spacings: the inverse cosine
+// transform of (1 + sum_a c_a (2 - 2 cos k_a))^-N_tau (c_a = dtau D_a / h_a^2)
+// over a periodic grid of 64 x 64 x 256 cells, far wider than the function
+// (it decays exponentially), evaluated one axis at a time on the offsets
+// |dx|, |dy| <= 4, |dz| <= 32.  The window is the smallest box whose mass
+// (the function sums to 1) is within 1e-4 of 1, else the largest; the mass
+// outside bounds the estimate's error by that share of the field's largest
+// value.
+GreenWindow green_window(const DevParams& P, int ntau, double tau) {
+  constexpr int Mx = 64, My = 64, Mz = 256;
+  constexpr int R = kGreenRz, Q = kGreenRxy;
+  GreenWindow gw;
+  const int N = ntau > 0 ? ntau : 1;
+  const double dtau = tau / N;
+  const double cx = dtau / (P.hx * P.hx), cy = dtau / (P.hy * P.hy);
+  const double cz = dtau * P.kz_diff / (P.hz * P.hz);
+  std::vector<double> ex(Mx), ey(My), ez(Mz), cosx(Mx * (Q + 1)), cosy(My * (Q + 1)),
+      cosz(Mz * (R + 1));
+  for (int k = 0; k < Mx; ++k) {
+    ex[k] = cx * (2.0 - 2.0 * cos(2.0 * kPi * k / Mx));
+    for (int d = 0; d <= Q; ++d) cosx[k * (Q + 1) + d] = cos(2.0 * kPi * (double)((k * d) % Mx) / Mx);
+  }
+  for (int k = 0; k < My; ++k) {
+    ey[k] = cy * (2.0 - 2.0 * cos(2.0 * kPi * k / My));
+    for (int d = 0; d <= Q; ++d) cosy[k * (Q + 1) + d] = cos(2.0 * kPi * (double)((k * d) % My) / My);
+  }
+  for (int k = 0; k < Mz; ++k) {
+    ez[k] = cz * (2.0 - 2.0 * cos(2.0 * kPi * k / Mz));
+    for (int d = 0; d <= R; ++d) cosz[k * (R + 1) + d] = cos(2.0 * kPi * (double)((k * d) % Mz) / Mz);
+  }
+  // T[kx][ky][dz] = sum_kz S cos(kz dz); U[kx][dy][dz] = sum_ky T cos(ky dy)
+  std::vector<double> U((size_t)Mx * (Q + 1) * (R + 1), 0.0), T(R + 1);
+  for (int kx = 0; kx < Mx; ++kx)
+    for (int ky = 0; ky < My; ++ky) {
+      std::fill(T.begin(), T.end(), 0.0);
+      for (int kz = 0; kz < Mz; ++kz) {
+        const double S = pow(1.0 + ex[kx] + ey[ky] + ez[kz], -(double)N);
+        const double* cz_ = &cosz[kz * (R + 1)];
+        for (int d = 0; d <= R; ++d) T[d] += S * cz_[d];
+      }
+      for (int dy = 0; dy <= Q; ++dy) {
+        const double c = cosy[ky * (Q + 1) + dy];
+        double* u = &U[((size_t)kx * (Q + 1) + dy) * (R + 1)];
+        for (int d = 0; d <= R; ++d) u[d] += c * T[d];
+      }
+    }
+  // G[|dx|][|dy|][|dz|]
+  std::vector<double> G((size_t)(Q + 1) * (Q + 1) * (R + 1), 0.0);
+  const double norm = 1.0 / ((double)Mx * My * Mz);
+  for (int dx = 0; dx <= Q; ++dx)
+    for (int kx = 0; kx < Mx; ++kx) {
+      const double c = cosx[kx * (Q + 1) + dx] * norm;
+      for (int dy = 0; dy <= Q; ++dy)
+        for (int d = 0; d <= R; ++d)
+          G[((size_t)dx * (Q + 1) + dy) * (R + 1) + d] += c * U[((size_t)kx * (Q + 1) + dy) * (R + 1) + d];
+    }
+  auto g = [&](int dx, int dy, int dz) {
+    return G[((size_t)std::abs(dx) * (Q + 1) + std::abs(dy)) * (R + 1) + std::abs(dz)];
+  };
+  auto mass = [&](int rx, int ry, int rz) {
+    double m = 0.0;
+    for (int dz = -rz; dz <= rz; ++dz)
+      for (int dy = -ry; dy <= ry; ++dy)
+        for (int dx = -rx; dx <= rx; ++dx) m += g(dx, dy, dz);
+    return m;
+  };
+  int best = -1;
+  for (int rx = 0; rx <= Q; ++rx)
+    for (int ry = 0; ry <= Q; ++ry)
+      for (int rz = 0; rz <= R; ++rz) {
+        const int vol = (2 * rx + 1) * (2 * ry + 1) * (2 * rz + 1);
+        if (best >= 0 && vol >= best) continue;
+        if (1.0 - mass(rx, ry, rz) <= 1e-4) {
+          best = vol;
+          gw.rx = rx, gw.ry = ry, gw.rz = rz;
+        }
+      }
+  if (best < 0) gw.rx = Q, gw.ry = Q, gw.rz = R;
+  gw.trunc = 1.0 - mass(gw.rx, gw.ry, gw.rz);
+  gw.tab.clear();  // [dy][dx][dz]: one z-run per window column
+  for (int dy = -gw.ry; dy <= gw.ry; ++dy)
+    for (int dx = -gw.rx; dx <= gw.rx; ++dx)
+      for (int dz = -gw.rz; dz <= gw.rz; ++dz) gw.tab.push_back(g(dx, dy, dz));
+  return gw;
+}
+
+// Circulant taps of N periodic one-dimensional implicit steps
+// (1 - c D)^-N on n cells: g[m] = (1/n) sum_k cos(2 pi k m / n)
+// (1 + c (2 - 2 cos(2 pi k / n)))^-N.  The offsets |m| <= R for the smallest
+// R <= 64 whose tail sums below 1e-13, or all n offsets when those do not
+// leave out any (2R + 1 >= n, n <= 129).
+void split_taps(int n, double c, int N, std::vector<double>* taps, int* off0) {
+  std::vector<double> g((size_t)n, 0.0);
+  for (int m = 0; m < n; ++m) {
+    double acc = 0.0;
+    for (int k = 0; k < n; ++k) {
+      const double lam = c * (2.0 - 2.0 * cos(2.0 * kPi * k / n));
+      acc += cos(2.0 * kPi * (double)(((int64_t)k * m) % n) / n) * pow(1.0 + lam, -(double)N);
+    }
+    g[m] = acc / n;
+  }
+  taps->clear();
+  int R = 64;
+  for (int r = 0; r < 64 && 2 * r + 1 < n; ++r) {
+    double tail = 0.0;
+    for (int m = r + 1; m <= n - 1 - r; ++m) tail += fabs(g[m]);
+    if (tail <= 1e-13) {
+      R = r;
+      break;
+    }
+  }
+  if (2 * R + 1 >= n && n <= kSplitMaxTaps) {
+    *taps = g;
+    *off0 = 0;
+    return;
+  }
+  for (int t = -R; t <= R; ++t) taps->push_back(g[(size_t)((t + n) % n)]);
+  *off0 = -R;
 }
 
 int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
@@ -247,6 +410,8 @@ int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
     return fail(c, SEDIMI_EINVAL, "max_neighbors must be in 1..30");
   if (p.nn_enable && !(p.nn_alpha >= 0 && p.nn_bound > 0 && p.nn_sample > 0 && p.nn_sample <= 1))
     return fail(c, SEDIMI_EINVAL, "surrogate parameters out of range");
+  if (p.nn_enable && p.nz > kSplitMaxNz)
+    return fail(c, SEDIMI_EINVAL, "the network needs nz <= 150 (its skip holds a z-column in LDS)");
   if (!(p.z_grading == 0.0 || p.z_grading == 1.0))
     return fail(c, SEDIMI_EINVAL, "graded z meshes are not supported on the GPU (z_grading 0 or 1)");
   if (p.avg_scheme != SEDIMI_SCHEME_EULER && p.avg_scheme != SEDIMI_SCHEME_BDF2)
@@ -446,7 +611,8 @@ int64_t do_average(sedimi_ctx* c, bool* used_plain) {
       double rel[4];  // the network's 4 channels
       int rc = nn_check_smooth(c, rel);
       if (rc) return rc;
-      double worst = std::max(std::max(rel[0], rel[1]), std::max(rel[2], rel[3]));
+      // the solid fraction decides: it is the field the particle step reads back
+      const double worst = rel[0];
       c->nn_last_check = worst;
       if (!(worst <= c->prm.nn_bound)) {
         ++c->nn_fallbacks;
@@ -598,6 +764,60 @@ int sedimi_bind_workspace(sedimi_ctx* c, void* dev_ptr, size_t bytes) {
       std::vector<double> st(spectral_table_doubles(P));
       spectral_tables(P, st.data());
       HIPCHK(c, hipMemcpyAsync(c->A.spec, st.data(), sizeof(double) * st.size(),
+                               hipMemcpyHostToDevice, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    if (c->prm.nn_enable) {
+      // the network's skip S: taps in x and y, the z-line Thomas table
+      const int N = std::max(1, c->prm.avg_ntau);
+      const double dtau = tau / N;
+      std::vector<double> tx, ty;
+      int ox = 0, oy = 0;
+      split_taps(P.nx, dtau / (P.hx * P.hx), N, &tx, &ox);
+      split_taps(P.ny, dtau / (P.hy * P.hy), N, &ty, &oy);
+      const double cz = dtau * P.kz_diff / (P.hz * P.hz);
+      std::vector<double> stab(2 * kSplitMaxTaps + 2 * (size_t)P.nz, 0.0);
+      std::copy(tx.begin(), tx.end(), stab.begin());
+      std::copy(ty.begin(), ty.end(), stab.begin() + kSplitMaxTaps);
+      double* ib = stab.data() + 2 * kSplitMaxTaps;
+      double* gm = ib + P.nz;
+      // Thomas factors of (1 + c n_k) u_k - c u_{k-1} - c u_{k+1}: pivots and
+      // the back-substitution multipliers
+      double bet = 1.0 + cz * ((P.nz > 1) ? 1 : 0);
+      ib[0] = 1.0 / bet;
+      for (int k = 1; k < P.nz; ++k) {
+        gm[k] = -cz / bet;
+        const double diag = 1.0 + cz * (k == P.nz - 1 ? 1 : 2);
+        bet = diag + cz * gm[k];
+        ib[k] = 1.0 / bet;
+      }
+      HIPCHK(c, hipMemcpyAsync(c->nn.stab, stab.data(), sizeof(double) * stab.size(),
+                               hipMemcpyHostToDevice, c->stream));
+      c->split.tapx = c->nn.stab;
+      c->split.tapy = c->nn.stab + kSplitMaxTaps;
+      c->split.ztab = c->nn.stab + 2 * kSplitMaxTaps;
+      c->split.off0x = ox, c->split.ntapx = (int)tx.size();
+      c->split.off0y = oy, c->split.ntapy = (int)ty.size();
+      c->split.cz = cz;
+      // the network check: Green's function window and the sampled columns
+      // (the nn_sample share of the columns with the smallest seeded hashes)
+      c->green = green_window(P, c->prm.avg_ntau, tau);
+      HIPCHK(c, hipMemcpyAsync(c->nn.gtab, c->green.tab.data(),
+                               sizeof(double) * c->green.tab.size(), hipMemcpyHostToDevice,
+                               c->stream));
+      const int ncol = P.nx * P.ny;
+      std::vector<std::pair<uint64_t, int>> h((size_t)ncol);
+      uint64_t st = c->prm.nn_seed;
+      for (int q = 0; q < ncol; ++q) {
+        uint64_t s2 = st ^ (uint64_t)q;
+        h[q] = {mix64(s2), q};
+      }
+      c->green_cols = nn_check_columns(c->prm);
+      std::partial_sort(h.begin(), h.begin() + c->green_cols, h.end());
+      std::vector<int> cols((size_t)c->green_cols);
+      for (int q = 0; q < c->green_cols; ++q) cols[q] = h[q].second;
+      std::sort(cols.begin(), cols.end());
+      HIPCHK(c, hipMemcpyAsync(c->nn.cols, cols.data(), sizeof(int) * cols.size(),
                                hipMemcpyHostToDevice, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
     }
@@ -1253,6 +1473,11 @@ int sedimi_get_stats(sedimi_ctx* c, sedimi_stats* out) {
   out->nn_calls = c->nn_calls;
   out->nn_fallbacks = c->nn_fallbacks;
   out->nn_last_check = c->nn_last_check;
+  out->nn_check_trunc = c->prm.nn_enable ? c->green.trunc : 0.0;
+  out->nn_check_window[0] = c->green.rx;
+  out->nn_check_window[1] = c->green.ry;
+  out->nn_check_window[2] = c->green.rz;
+  out->nn_check_columns = c->green_cols;
   out->particles = c->n;
   if (c->have_particles && c->n > 0) {
     const size_t n = (size_t)c->n;
@@ -1324,6 +1549,9 @@ void nn_run_forward(sedimi_ctx* c, bool keep) {
   NNBufs& b = c->nn;
   const int n = c->P.ncell;
   launch_nn_prep(n, c->A.raw, c->norm, b.xf, b.xb, c->stream);
+  launch_split(c->P.nx, c->P.ny, c->P.nz, std::max(1, c->prm.avg_ntau), c->split, b.xf, b.xt,
+               b.xs, c->stream);
+  launch_nn_highpass(n, b.xf, b.xs, b.xb, c->stream);
   const float alpha = (float)c->prm.nn_alpha;
   for (int l = 0; l < 5; ++l) {
     EpiArgs e{};
@@ -1337,7 +1565,7 @@ void nn_run_forward(sedimi_ctx* c, bool keep) {
   }
   EpiArgs e{};
   e.alpha = alpha;
-  e.xres = b.xf;
+  e.xres = b.xs;
   e.yout = b.y;
   launch_conv(kNNC, 4, EPI_LAST, geom(c, 5, 0), b.h[4], b.fwd[5],
               b.w + nn_woff(5) + 27LL * kNNC * 4, e, c->stream);
@@ -1345,11 +1573,11 @@ void nn_run_forward(sedimi_ctx* c, bool keep) {
 }
 
 int nn_check_smooth(sedimi_ctx* c, double rel[4]) {
-  double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
-  int nb = launch_check(c->P, c->A, c->A.smooth, 4, std::max(1, c->prm.avg_ntau), tau,
-                        c->prm.nn_seed, c->prm.nn_sample, c->stream);
-  if (read_check(c->A, nb, 4, rel, c->stream) != 0)
-    return fail(c, SEDIMI_EDEVICE, "reading the residual check failed");
+  const GreenWindow& gw = c->green;
+  int nb = launch_green_check(c->P, c->A.raw, c->A.smooth, c->nn.cols, c->green_cols,
+                              c->nn.gtab, gw.rx, gw.ry, gw.rz, c->nn.gpart, c->stream);
+  if (nb <= 0 || read_partials(c->nn.gpart, nb, 4, rel, c->stream) != 0)
+    return fail(c, SEDIMI_EDEVICE, "reading the network check failed");
   return SEDIMI_OK;
 }
 
@@ -1360,12 +1588,6 @@ int need_nn(sedimi_ctx* c) {
   return SEDIMI_OK;
 }
 
-uint64_t mix64(uint64_t& s) {
-  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
 
 }  // namespace
 
@@ -1457,6 +1679,16 @@ int sedimi_nn_set_norm(sedimi_ctx* c, const double* mean4, const double* std4) {
   return SEDIMI_OK;
 }
 
+int sedimi_nn_set_loss_weights(sedimi_ctx* c, const double* w4) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  if (!w4) return fail(c, SEDIMI_EINVAL, "null loss weights");
+  for (int k = 0; k < 4; ++k)
+    if (!(w4[k] >= 0 && std::isfinite(w4[k]))) return fail(c, SEDIMI_EINVAL, "loss weights must be finite and >= 0");
+  for (int k = 0; k < 4; ++k) c->norm.lw[k] = w4[k];
+  return SEDIMI_OK;
+}
+
 int sedimi_nn_forward(sedimi_ctx* c) {
   int rc = need_nn(c);
   if (rc) return rc;
@@ -1480,6 +1712,9 @@ int sedimi_nn_train_step(sedimi_ctx* c, double lr, double* loss) {
   // forward keeping activations; the network output goes to nn.y only (the
   // SMOOTH field holds the target and is not touched)
   launch_nn_prep(n, c->A.raw, c->norm, b.xf, b.xb, c->stream);
+  launch_split(c->P.nx, c->P.ny, c->P.nz, std::max(1, c->prm.avg_ntau), c->split, b.xf, b.xt,
+               b.xs, c->stream);
+  launch_nn_highpass(n, b.xf, b.xs, b.xb, c->stream);
   for (int l = 0; l < 5; ++l) {
     EpiArgs e{};
     e.alpha = alpha;
@@ -1493,7 +1728,7 @@ int sedimi_nn_train_step(sedimi_ctx* c, double lr, double* loss) {
   {
     EpiArgs e{};
     e.alpha = alpha;
-    e.xres = b.xf;
+    e.xres = b.xs;
     e.yout = b.y;
     launch_conv(kNNC, 4, EPI_LAST, geom(c, 5, 0), b.h[4], b.fwd[5],
                 b.w + nn_woff(5) + 27LL * kNNC * 4, e, c->stream);
@@ -1507,24 +1742,22 @@ int sedimi_nn_train_step(sedimi_ctx* c, double lr, double* loss) {
     EpiArgs e{};
     e.alpha = alpha;
     e.zin = b.z[4];
-    e.hout = b.dh[0];
-    e.zout = b.dz[0];
+    e.hout = b.dh[4];
+    e.zout = b.dz[4];
     launch_conv(4, kNNC, EPI_BWD, geom(c, 5, 1), b.dy6, b.adj[5], nullptr, e, c->stream);
   }
-  int cur = 0;
   for (int l = 4; l >= 1; --l) {
-    launch_conv_dw(kNNC, kNNC, geom(c, l, 0), b.h[l - 1], b.dz[cur], b.part, b.part_b,
+    launch_conv_dw(kNNC, kNNC, geom(c, l, 0), b.h[l - 1], b.dz[l], b.part, b.part_b,
                    b.g + nn_woff(l), b.g + nn_woff(l) + 27LL * kNNC * kNNC, dwb, c->stream);
     EpiArgs e{};
     e.alpha = alpha;
-    e.hin = b.dh[cur];
+    e.hin = b.dh[l];
     e.zin = b.z[l - 1];
-    e.hout = b.dh[1 - cur];
-    e.zout = b.dz[1 - cur];
-    launch_conv(kNNC, kNNC, EPI_BWD, geom(c, l, 1), b.dz[cur], b.adj[l], nullptr, e, c->stream);
-    cur = 1 - cur;
+    e.hout = b.dh[l - 1];
+    e.zout = b.dz[l - 1];
+    launch_conv(kNNC, kNNC, EPI_BWD, geom(c, l, 1), b.dz[l], b.adj[l], nullptr, e, c->stream);
   }
-  launch_conv_dw(4, kNNC, geom(c, 0, 0), b.xb, b.dz[cur], b.part, b.part_b, b.g + nn_woff(0),
+  launch_conv_dw(4, kNNC, geom(c, 0, 0), b.xb, b.dz[0], b.part, b.part_b, b.g + nn_woff(0),
                  b.g + nn_woff(0) + 27LL * 4 * kNNC, dwb, c->stream);
   const int64_t P = nn_count();
   c->adam_t += 1;
@@ -1541,6 +1774,37 @@ int sedimi_nn_train_step(sedimi_ctx* c, double lr, double* loss) {
     *loss = sum / (4.0 * n);
   } else {
     HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return SEDIMI_OK;
+}
+
+int sedimi_nn_get_tensor(sedimi_ctx* c, int which, int layer, float* out, int64_t n) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  const NNBufs& b = c->nn;
+  const int64_t nc = c->P.ncell;
+  const bool layered = which == SEDIMI_NN_Z || which == SEDIMI_NN_H || which == SEDIMI_NN_DH ||
+                       which == SEDIMI_NN_DZ;
+  if (which < SEDIMI_NN_X || which > SEDIMI_NN_DZ || (layered && (layer < 0 || layer > 4)) || !out)
+    return fail(c, SEDIMI_EINVAL, "bad network tensor");
+  const int64_t want = (layered ? kNNC : 4) * nc;
+  if (n != want) return fail(c, SEDIMI_EINVAL, "network tensor has the wrong length");
+  const float* f32 = which == SEDIMI_NN_X ? b.xf : which == SEDIMI_NN_SX ? b.xs
+                     : which == SEDIMI_NN_Y ? b.y : nullptr;
+  if (f32) {
+    HIPCHK(c, hipMemcpyAsync(out, f32, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SEDIMI_OK;
+  }
+  const __bf16* h16 = which == SEDIMI_NN_XB ? b.xb : which == SEDIMI_NN_DY ? b.dy6
+                      : which == SEDIMI_NN_Z ? b.z[layer] : which == SEDIMI_NN_H ? b.h[layer]
+                      : which == SEDIMI_NN_DH ? b.dh[layer] : b.dz[layer];
+  std::vector<uint16_t> h((size_t)n);
+  HIPCHK(c, hipMemcpyAsync(h.data(), h16, sizeof(uint16_t) * n, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int64_t q = 0; q < n; ++q) {
+    const uint32_t u = (uint32_t)h[q] << 16;  // a BF16 is the upper half of an FP32
+    memcpy(out + q, &u, 4);
   }
   return SEDIMI_OK;
 }

@@ -175,6 +175,21 @@ void smooth_ztab(const DevParams& P, int ntau, double tau, double* host_tab);
 int launch_check(const DevParams& P, DevArrays& A, const double* y, int nch, int ntau,
                  double tau, uint64_t seed, double frac, hipStream_t s);
 int read_check(DevArrays& A, int nblocks, int nch, double* rel, hipStream_t s);
+// The same from per-block partials part[b][2 nch] of any check kernel.
+int read_partials(const double* part, int nblocks, int nch, double* rel, hipStream_t s);
+// A^ntau y (A = I - dtau L_h) for channels [0, nch) into A.sd0 / A.sd1;
+// returns the buffer holding it (y itself when ntau = 0).
+const double* apply_An(const DevParams& P, DevArrays& A, const double* y, int nch, int ntau,
+                       double tau, hipStream_t s);
+// Error estimate of a smoothed 4-channel field y on whole sampled z-columns
+// (cols: x + nx y): the plain solution there is taken as the Green's function
+// of the ntau implicit steps (gtab [2ry+1][2rx+1][2rz+1], rx, ry <= 4,
+// rz <= 32) applied to raw, with periodic x, y and mirror images about the
+// walls.  Per-column partials part[col][8] = sum (y - G*raw)^2, sum (G*raw)^2
+// per channel, in read_check's layout; returns the block count.
+int launch_green_check(const DevParams& P, const double* raw, const double* y, const int* cols,
+                       int ncols, const double* gtab, int rx, int ry, int rz, double* part,
+                       hipStream_t s);
 // The same check for BDF2 steps: y = g_N(M) raw with M = -dtau L and the
 // per-mode BDF2 factor g_N = p_N / q_N, q_N = (1 + M)(3 + 2M)^(N-1),
 // p_1 = 1, p_2 = 3 - M, p_{n+1} = 4 p_n - (3 + 2M) p_{n-1}; the residual is

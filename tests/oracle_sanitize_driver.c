@@ -20,8 +20,8 @@ void orc_conv3d_bwd(int nx, int ny, int nz, int cin, int cout, int dil, const do
                     const double* w, const double* dy, double* dx, double* dw, double* db);
 int64_t orc_nn_param_count(int C);
 double orc_nn_loss_grad(int nx, int ny, int nz, int C, double alpha, int bf16,
-                        const double* params, const double* x, const double* target,
-                        double* grads);
+                        const double* params, const double* split, const double* lw,
+                        const double* x, const double* target, double* grads);
 void orc_adam(int64_t n, double* w, double* m, double* v, const double* g, double lr,
               double b1, double b2, double eps, int64_t t);
 
@@ -152,7 +152,9 @@ int main(void) {
   double *prm = vec(np), *g = vec(np), *mm = vec(np), *vv = vec(np), *tgt = vec(m * 4);
   for (int64_t k = 0; k < np; ++k) prm[k] = 0.05 * (uniform() - 0.5);
   for (int64_t k = 0; k < m * 4; ++k) tgt[k] = uniform();
-  double loss = orc_nn_loss_grad(mx, my, mz, 8, 0.1, 1, prm, cx, tgt, g);
+  const double split[4] = {0.06, 0.05, 2.25, 4.0};
+  const double lw[4] = {1.0, 0.5, 2.0, 1.0};
+  double loss = orc_nn_loss_grad(mx, my, mz, 8, 0.1, 1, prm, split, lw, cx, tgt, g);
   orc_adam(np, prm, mm, vv, g, 1e-3, 0.9, 0.999, 1e-8, 1);
   if (!isfinite(loss)) {
     fprintf(stderr, "non-finite loss\n");

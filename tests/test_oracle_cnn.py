@@ -149,8 +149,9 @@ def test_network_gradient_finite_difference(orc):
     params = rng.normal(scale=0.3, size=npar)
     x = rng.normal(size=(N, 4))
     target = rng.normal(size=(N, 4))
-    loss, grad = orc.nn_loss_grad(SHAPE, params, x, target, C=C, alpha=0.1)
-    y = orc.nn_forward(SHAPE, params, x, C=C, alpha=0.1)
+    split = np.array([0.1, 0.2, 1.5, 3.0])
+    loss, grad = orc.nn_loss_grad(SHAPE, params, x, target, C=C, alpha=0.1, split=split)
+    y = orc.nn_forward(SHAPE, params, x, C=C, alpha=0.1, split=split)
     assert abs(loss - ((y - target) ** 2).mean()) < 1e-12 * loss
     h = 1e-6
     picks = rng.choice(npar, 25, replace=False)
@@ -158,10 +159,32 @@ def test_network_gradient_finite_difference(orc):
         pp, pm = params.copy(), params.copy()
         pp[k] += h
         pm[k] -= h
-        lp, _ = orc.nn_loss_grad(SHAPE, pp, x, target, C=C, alpha=0.1)
-        lm, _ = orc.nn_loss_grad(SHAPE, pm, x, target, C=C, alpha=0.1)
+        lp, _ = orc.nn_loss_grad(SHAPE, pp, x, target, C=C, alpha=0.1, split=split)
+        lm, _ = orc.nn_loss_grad(SHAPE, pm, x, target, C=C, alpha=0.1, split=split)
         fd = (lp - lm) / (2 * h)
         assert abs(fd - grad[k]) < 2e-6 * (abs(grad[k]) + 1e-3), (k, fd, grad[k])
+
+
+def test_weighted_loss_gradient_finite_difference(orc):
+    C = 4
+    rng = np.random.default_rng(15)
+    npar = orc.nn_param_count(C)
+    params = rng.normal(scale=0.3, size=npar)
+    x = rng.normal(size=(N, 4))
+    target = rng.normal(size=(N, 4))
+    lw = np.array([2.0, 0.5, 0.0, 1.5])
+    split = np.array([0.1, 0.2, 1.5, 3.0])
+    loss, grad = orc.nn_loss_grad(SHAPE, params, x, target, C=C, split=split, loss_weights=lw)
+    y = orc.nn_forward(SHAPE, params, x, C=C, split=split)
+    assert abs(loss - (lw * (y - target) ** 2).mean()) < 1e-12 * loss
+    h = 1e-6
+    for k in rng.choice(npar, 12, replace=False):
+        pp, pm = params.copy(), params.copy()
+        pp[k] += h
+        pm[k] -= h
+        lp, _ = orc.nn_loss_grad(SHAPE, pp, x, target, C=C, split=split, loss_weights=lw)
+        lm, _ = orc.nn_loss_grad(SHAPE, pm, x, target, C=C, split=split, loss_weights=lw)
+        assert abs((lp - lm) / (2 * h) - grad[k]) < 2e-6 * (abs(grad[k]) + 1e-3)
 
 
 def test_network_identity_at_zero_weights(orc):
@@ -184,3 +207,62 @@ def test_adam_first_steps_closed_form(orc):
     orc.adam(w, m, v, g, lr, 2, eps=eps)
     # same gradient twice: bias-corrected moments are again g and g^2
     assert np.allclose(w, w2 - lr * g / (np.abs(g) + eps), rtol=0, atol=1e-14)
+
+
+def split_symbol_apply(shape, c, x):
+    """The split skip S through its Fourier / cosine symbol: periodic FFT in x
+    and y, the even extension about the wall faces in z (DCT-II), each axis
+    multiplied by (1 + c_a (2 - 2 cos k_a))^-N."""
+    nx, ny, nz = shape
+    N = int(c[3])
+    f = x.reshape(nz, ny, nx, -1)
+    f = np.concatenate([f, f[::-1]], axis=0)
+    F = np.fft.fftn(f, axes=(0, 1, 2))
+    kz = 2 * np.pi * np.fft.fftfreq(2 * nz)
+    ky = 2 * np.pi * np.fft.fftfreq(ny)
+    kx = 2 * np.pi * np.fft.fftfreq(nx)
+    sym = ((1 + c[2] * (2 - 2 * np.cos(kz)))[:, None, None] *
+           (1 + c[1] * (2 - 2 * np.cos(ky)))[None, :, None] *
+           (1 + c[0] * (2 - 2 * np.cos(kx)))[None, None, :]) ** (-N)
+    out = np.real(np.fft.ifftn(F * sym[..., None], axes=(0, 1, 2)))[:nz]
+    return out.reshape(-1, x.shape[1])
+
+
+@pytest.mark.parametrize("shape,c", [
+    ((6, 5, 9), (0.06, 0.3, 2.25, 4)), ((3, 4, 1), (1.5, 0.2, 0.7, 2)),
+    ((2, 7, 5), (0.5, 0.05, 3.0, 3)), ((1, 3, 4), (0.4, 0.9, 0.1, 1)),
+    ((16, 8, 32), (0.0576, 0.0576, 2.25, 4))])
+def test_split_skip_is_the_product_of_one_dimensional_implicit_steps(orc, shape, c):
+    """S from the exact per-line solves (cyclic tridiagonal in x and y,
+    Thomas with zero-flux ends in z) equals the separable symbol applied in
+    Fourier / cosine space; it conserves each channel's sum."""
+    n = shape[0] * shape[1] * shape[2]
+    x = np.random.default_rng(len(shape) + shape[0]).random((n, 3))
+    got = orc.split_smooth(shape, np.array(c, float), x)
+    want = split_symbol_apply(shape, c, x)
+    assert np.allclose(got, want, rtol=0, atol=1e-13)
+    assert np.allclose(got.sum(axis=0), x.sum(axis=0), rtol=1e-13)
+
+
+def test_split_skip_is_close_to_the_exact_steps_on_a_fine_mesh(orc):
+    """On cells small along z against the bandwidth (3.125d x 3.125d x 0.5d,
+    b = 3d) the split differs from the exact backward-Euler steps only by
+    their cross terms: well under 1% of a deposited bed's smoothed field."""
+    import workloads
+    w = workloads.workload("fine2m", n=12000)
+    prm = w["params"]
+    shape = (prm["nx"], prm["ny"], prm["nz"])
+    raw = orc.deposit(prm, w["x"], w["d"])[:1]
+    exact, _ = orc.diffuse(prm, raw)
+    s = orc.split_smooth(shape, orc.split_coefficients(prm), raw.T)[:, 0]
+    rel = np.linalg.norm(s - exact[0]) / np.linalg.norm(exact[0])
+    assert rel < 1e-2
+    # and it carries most of the smoothing: the deposited field is far off
+    assert np.linalg.norm(raw[0] - exact[0]) / np.linalg.norm(exact[0]) > 0.2
+
+
+def test_network_with_split_skip_at_zero_weights_is_the_split(orc):
+    x = np.random.default_rng(7).normal(size=(N, 4))
+    c = np.array([0.1, 0.2, 1.5, 3.0])
+    y = orc.nn_forward(SHAPE, np.zeros(orc.nn_param_count(8)), x, C=8, split=c)
+    assert np.allclose(y, orc.split_smooth(SHAPE, c, x), rtol=0, atol=1e-15)

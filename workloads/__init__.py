@@ -20,7 +20,8 @@ Workloads (sizes of the paper's cases, Table 1 and Section 5.2):
               overlaps; same size distribution, packing and depth as one
               deposition of 10M spheres, generated in a tenth of the time)
   fine2m/4m   2M / 4M spheres, 256 x 128 x 128 mesh with cells of
-              (3.125d, 3.125d, 0.5d) in an 800d x 400d x 64d channel
+              (3.125d, 3.125d, 0.5d) in an 800d x 400d x 64d channel; 4 x 4
+              copies of a 125k-sphere tile (2M) and 2 x 2 of a 1M tile (4M)
 """
 from __future__ import annotations
 
@@ -245,9 +246,13 @@ def dt_rule(prm, dmin, rho=RHO_P):
     return contact_time(prm["kn"], prm["restitution"], 0.5 * m) / 50.0
 
 
-def workload(name, seed=None, n=None):
+DEFAULT_TILES = {"bed10m": (5, 2), "fine2m": (4, 4), "fine4m": (2, 2)}
+
+
+def workload(name, seed=None, n=None, tiles=None):
     """Build a named workload.  Returns dict(params, x, v, w, d, rho, U, gradp,
-    dudt, meta)."""
+    dudt, meta).  tiles = (a, b): the bed is an a x b array of copies of one
+    seeded deposited tile (default DEFAULT_TILES, (1, 1) when n is given)."""
     if name == "small":
         s = 0 if seed is None else seed
         n = 2000 if n is None else n
@@ -271,7 +276,8 @@ def workload(name, seed=None, n=None):
         prm = base_params(Lx=lx * D50 * scale, Ly=ly * D50 * scale, Lz=lz * D50,
                           nx=max(2, int(round(mesh[0] * scale))),
                           ny=max(2, int(round(mesh[1] * scale))), nz=mesh[2])
-        tiles = (5, 2) if name == "bed10m" and n is None else (1, 1)
+        if tiles is None:
+            tiles = DEFAULT_TILES.get(name, (1, 1)) if n is None else (1, 1)
         nt = tiles[0] * tiles[1]
         d = lognormal_diameters(N // nt, bseed)
         x = rsd_bed(N // nt, d, prm["Lx"] / tiles[0], prm["Ly"] / tiles[1], seed=bseed)
