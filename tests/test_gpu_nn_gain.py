@@ -1,0 +1,137 @@
+"""What the learned stand-in gains and costs against the plain averaging, on a
+half-size fine-mesh bed (500k spheres, 2 x 2 copies of a seeded tile, 128 x
+64 x 128 cells of 3.125d x 3.125d x 0.5d): train on snapshots of 4 seeded
+beds, then on a held-out seed state, per channel, the relative L2 error
+against the plain solve of
+
+  - the raw PCM field (no smoothing at all),
+  - the skip alone (S x, the axis-split backward-Euler steps),
+  - the network (S x + net(x - S x)),
+
+and the time of the network's forward pass, of the check, of the direct
+plain solve and of the iterative plain solve (Chebyshev, the route of meshes
+the direct solve does not diagonalise), each from HIP events.
+
+What must hold: the network is at least as close to the plain solve as its
+skip on every channel (its last layer starts at zero, so training can only
+have moved it from S x by descending the loss), both are far closer than the
+raw field, the check's estimate stays within a factor of the measured error,
+checked mode falls back exactly when that estimate exceeds the bound, and
+the forward pass is faster than the iterative solve.  Whether it beats the
+direct solve is stated, not asserted: on this mesh it does not."""
+import json
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TRAIN, HELD = (2000, 2001, 2002, 2003), 2010
+N = 500_000
+STEPS = 400
+
+
+def _timed(torch, fn, reps=5):
+    tot = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        tot += e0.elapsed_time(e1)
+    return tot / reps
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b, axis=1) / (np.linalg.norm(b, axis=1) + 1e-300)
+
+
+def test_network_error_and_time_against_the_plain_solve():
+    import torch
+
+    import paper_1601_03801_amd as sm
+    beds = {s: workloads.workload("fine2m", seed=s, n=N, tiles=(2, 2)) for s in TRAIN + (HELD,)}
+    prm = dict(beds[HELD]["params"])
+    nx, ny, nz = prm["nx"], prm["ny"], prm["nz"]
+    print(f"gain: mesh {nx}x{ny}x{nz}, {N} spheres, {STEPS} training steps", flush=True)
+    dmax = float(max(b["d"].max() for b in beds.values()))
+    bound = 1e-3
+    g = sm.Sedimi(prm, N, precision="mixed", d_max=dmax, skin=0.1 * dmax, max_neighbors=24,
+                  nn=True, nn_alpha=1.0, nn_bound=bound, nn_sample=0.01)
+    rng = np.random.default_rng(77)
+
+    def load(seed):
+        b = beds[seed]
+        g.set_fluid(b["U"], b["gradp"], b["dudt"])
+        g.set_particles(b["x"], b["v"], b["d"], b["rho"])
+
+    def snapshot():
+        g.translate(rng.uniform(0, prm["Lx"]), rng.uniform(0, prm["Ly"]))
+        g.compute_forces()
+        g.deposit()
+
+    raws = []
+    for s in TRAIN:
+        load(s)
+        snapshot()
+        raws.append(g.get_field(0))
+    rms = np.sqrt((np.stack(raws) ** 2).mean(axis=(0, 2))) + 1e-30
+    g.nn_set_norm(np.zeros(4), rms)
+    g.nn_init(3)
+    losses = []
+    for it in range(STEPS):
+        if it % 10 == 0:
+            load(TRAIN[(it // 10) % len(TRAIN)])
+        snapshot()
+        g.smooth(4)
+        lr = 1e-6 + 0.5 * (1e-4 - 1e-6) * (1 + math.cos(math.pi * it / STEPS))
+        losses.append(g.nn_train_step(lr))
+    print(f"gain: loss {np.mean(losses[:5]):.3e} -> {np.mean(losses[-5:]):.3e}", flush=True)
+
+    load(HELD)
+    snapshot()
+    g.smooth(4)
+    plain = g.get_field(1)
+    raw = g.get_field(0)
+    g.nn_forward()
+    net = g.get_field(1)
+    skip = (g.nn_tensor("sx").astype(np.float64) * rms).T
+    est = g.nn_check()
+    err = {"raw": _rel(raw, plain), "skip": _rel(skip, plain), "network": _rel(net, plain)}
+
+    fwd_ms = _timed(torch, g.nn_forward)
+    check_ms = _timed(torch, g.nn_check)
+    direct_ms = _timed(torch, lambda: g.smooth(4))
+    g.set_avg_mode(sm.AVG_SURROGATE_CHECKED)
+    g.average()
+    st = g.stats()
+    g.close()
+    gi = sm.Sedimi(prm, N, precision="fp64", d_max=dmax, skin=0.1 * dmax, max_neighbors=24,
+                   solver="iterative")
+    b = beds[HELD]
+    gi.set_fluid(b["U"], b["gradp"], b["dudt"])
+    gi.set_particles(b["x"], b["v"], b["d"], b["rho"])
+    gi.compute_forces()
+    gi.deposit()
+    gi.smooth(4)
+    iter_ms = _timed(torch, lambda: gi.smooth(4), reps=3)
+    gi.close()
+
+    report = {"rel_l2_vs_plain": {k: [float(x) for x in v] for k, v in err.items()},
+              "check_estimate": [float(x) for x in est], "bound": bound,
+              "forward_ms": round(fwd_ms, 3), "check_ms": round(check_ms, 3),
+              "direct_plain_ms": round(direct_ms, 3), "iterative_plain_ms": round(iter_ms, 3),
+              "checked_mode_fell_back": bool(st["nn_fallbacks"] > 0)}
+    print("gain: " + json.dumps(report), flush=True)
+
+    for c in range(4):
+        assert err["network"][c] <= err["skip"][c] * 1.001, (c, report)
+        assert err["skip"][c] < 0.5 * err["raw"][c], (c, report)
+    # the decision is taken on the solid fraction
+    assert 0.5 * err["network"][0] - 1e-4 < est[0] < 2.0 * err["network"][0] + 1e-4, report
+    assert report["checked_mode_fell_back"] == bool(est[0] > bound), report
+    assert fwd_ms < iter_ms, report
