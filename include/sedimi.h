@@ -148,9 +148,20 @@ typedef struct {
                                 SEDIMI_SCHEME_EULER, or SEDIMI_SCHEME_BDF2 (either
                                 solver; not with nn_enable) */
   double z_grading;          /* top / bottom cell height ratio of a z mesh graded
-                                towards the bottom wall (Section 4's channel case);
-                                0 or 1: uniform.  Graded meshes are not built on the
-                                GPU yet: any other value is refused (EINVAL) */
+                                towards the bottom wall (Section 4's channel case):
+                                cell heights grow geometrically from the bottom,
+                                h_k = h_0 q^k with q^(nz-1) = z_grading, summed in
+                                order and scaled to Lz.  0 or 1: uniform; finite
+                                and >= 0, else EINVAL.  On a graded mesh the
+                                deposition finds each particle's cell from the faces
+                                and divides by that cell's volume, the diffusion is
+                                the finite-volume operator (face flux over the
+                                centre distance, per unit cell height), the fluid
+                                fields and their curl are interpolated between the
+                                centres' own heights.  The direct solve handles
+                                nz <= 512 (its z transform is an eigen-decomposition
+                                at sedimi_create); the network (nn_enable) and
+                                sedimi_smooth_static need a uniform mesh (EINVAL) */
 } sedimi_params;
 
 /* avg_scheme: backward Euler, (I - dtau L) phi^{m+1} = phi^m; or the two-step
@@ -161,9 +172,11 @@ typedef struct {
 #define SEDIMI_SCHEME_BDF2 1
 
 /* solvers of the implicit diffusion steps (Eq. 12) */
-#define SEDIMI_SOLVE_AUTO 0      /* direct when every axis has <= 2048 cells */
-#define SEDIMI_SOLVE_DIRECT 1    /* exact diagonalisation on the uniform mesh:
-                                    Hartley transforms in x and y, DCT-II in z;
+#define SEDIMI_SOLVE_AUTO 0      /* direct when every axis has <= 2048 cells
+                                    (graded z meshes: and nz <= 512) */
+#define SEDIMI_SOLVE_DIRECT 1    /* exact diagonalisation: Hartley transforms
+                                    in x and y, DCT-II in z (graded z meshes:
+                                    the eigenvectors of the graded z operator);
                                     all N_tau steps in one pass; FP64 always */
 #define SEDIMI_SOLVE_ITERATIVE 2 /* Chebyshev iteration per step to avg_rtol
                                     (FP32 vectors with FP64 residuals in mixed mode) */
@@ -385,9 +398,9 @@ int sedimi_nn_check(sedimi_ctx* ctx, double* rel4);
  * caller's device field raw_dev [nch][ncell] into smooth_dev [nch][ncell]
  * (caller-owned device memory on the current device, not overlapping),
  * enqueued on hip_stream (NULL: the null stream), with no context.
- * It reads the mesh (Lx, Ly, Lz, nx, ny, nz), avg_bandwidth, avg_bandwidth_z,
- * avg_ntau and avg_scheme of p and ignores the rest; every axis <= 2048 cells,
- * nch 1..7.
+ * It reads the mesh (Lx, Ly, Lz, nx, ny, nz, z_grading), avg_bandwidth,
+ * avg_bandwidth_z, avg_ntau and avg_scheme of p and ignores the rest; every
+ * axis <= 2048 cells, a uniform z mesh (z_grading 0 or 1), nch 1..7.
  * Memory: the transform tables and one intermediate field live in a static
  * device array of SEDIMI_STATIC_SCRATCH_BYTES that each GPU the library runs
  * on holds until the process ends.  The call needs

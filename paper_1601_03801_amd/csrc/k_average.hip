@@ -39,7 +39,8 @@ __global__ void k_cellkey(DevParams P, DevArrays A) {
   if (valid) {
     const double4 x = A.pos[q];
     const int a = grid_coord(x.x, P.hx, P.nx), b = grid_coord(x.y, P.hy, P.ny),
-              c = grid_coord(x.z, P.hz, P.nz);
+              c = P.graded ? z_cell(A.zgeo + zgeo_faces(P.nz), P.nz, x.z)
+                           : grid_coord(x.z, P.hz, P.nz);
     k = (c * P.ny + b) * P.nx + a;
     A.key[q] = k;
   }
@@ -105,14 +106,16 @@ __global__ void k_cellsum(DevParams P, DevArrays A) {
     }
   }
   const size_t nc = (size_t)P.ncell;
-  A.raw[c] = v / P.Vc;
-  A.raw[nc + c] = fx / P.Vc;
-  A.raw[2 * nc + c] = fy / P.Vc;
-  A.raw[3 * nc + c] = fz / P.Vc;
+  // each cell divides by its own volume (one per plane on a graded mesh)
+  const double Vc = P.graded ? A.zgeo[zgeo_volumes(P.nz) + c / (P.nx * P.ny)] : P.Vc;
+  A.raw[c] = v / Vc;
+  A.raw[nc + c] = fx / Vc;
+  A.raw[2 * nc + c] = fy / Vc;
+  A.raw[3 * nc + c] = fz / Vc;
   if (flux) {
-    A.raw[4 * nc + c] = qx / P.Vc;
-    A.raw[5 * nc + c] = qy / P.Vc;
-    A.raw[6 * nc + c] = qz / P.Vc;
+    A.raw[4 * nc + c] = qx / Vc;
+    A.raw[5 * nc + c] = qy / Vc;
+    A.raw[6 * nc + c] = qz / Vc;
   }
 }
 
@@ -128,10 +131,38 @@ __global__ void k_solid_velocity(DevParams P, DevArrays A) {
   for (int e = 0; e < 3; ++e) A.us[e * nc + c] = solid ? A.smooth[(4 + e) * nc + c] / es : 0.0;
 }
 
+// The operator I - dtau L_h.  Along z, a uniform mesh couples a plane to its
+// neighbours with cz = dtau kz / hz^2; a graded mesh (gz set) with
+// cz gz[2k] to the plane above and cz gz[2k + 1] to the one below (cz =
+// dtau there): the flux through each face over the centre distance, per
+// unit cell height.
 struct Stencil {
   int nx, ny, nz, ncell;
-  double cx, cy, cz;  // dtau / h^2 per axis
+  double cx, cy, cz;
+  const double* gz;
 };
+
+// dtau L_z contribution at plane k from up = x_{k+1} - x_k and dn =
+// x_{k-1} - x_k (each 0 where the plane has no such neighbour).
+__device__ __forceinline__ double z_term(const Stencil& S, int k, double up, double dn) {
+  if (S.gz) return S.cz * (S.gz[2 * k] * up + S.gz[2 * k + 1] * dn);
+  return S.cz * (up + dn);
+}
+// dtau times the coupling of plane k to the plane below (the negated
+// sub-diagonal of I - dtau L_z in row k).
+__device__ __forceinline__ double z_down(const Stencil& S, int k) {
+  return S.gz ? S.cz * S.gz[2 * k + 1] : S.cz;
+}
+
+Stencil make_stencil(const DevParams& P, const DevArrays& A, double dt) {
+  Stencil S;
+  S.nx = P.nx, S.ny = P.ny, S.nz = P.nz, S.ncell = P.ncell;
+  S.cx = dt / (P.hx * P.hx);
+  S.cy = dt / (P.hy * P.hy);
+  S.cz = P.graded ? dt : dt * P.kz_diff / (P.hz * P.hz);
+  S.gz = P.graded ? A.zgeo + zgeo_coupling(P.nz) : nullptr;
+  return S;
+}
 
 // y = (I - dtau L_h) x at cell c (channel offset already applied to x).
 template <typename T>
@@ -148,11 +179,10 @@ __device__ __forceinline__ double apply_A(const Stencil& S, const T* __restrict_
   int jm = j == 0 ? c + (S.ny - 1) * rowy : c - rowy;
   double lx = ((double)x[ip] - xc) + ((double)x[im] - xc);
   double ly = ((double)x[jp] - xc) + ((double)x[jm] - xc);
-  double lz = 0.0;
   int plane = S.nx * S.ny;
-  if (k + 1 < S.nz) lz += (double)x[c + plane] - xc;
-  if (k > 0) lz += (double)x[c - plane] - xc;
-  return xc - (S.cx * lx + S.cy * ly + S.cz * lz);
+  const double up = k + 1 < S.nz ? (double)x[c + plane] - xc : 0.0;
+  const double dn = k > 0 ? (double)x[c - plane] - xc : 0.0;
+  return xc - (S.cx * lx + S.cy * ly + z_term(S, k, up, dn));
 }
 
 // Preconditioned Chebyshev iteration for (I - dtau L_h) x = b, preconditioner
@@ -182,10 +212,9 @@ __device__ __forceinline__ double A_col(const Stencil& S, const T* __restrict__ 
   size_t jm = j == 0 ? c + (size_t)(S.ny - 1) * row : c - row;
   double lx = (ld(v, ip) - v0) + (ld(v, im) - v0);
   double ly = (ld(v, jp) - v0) + (ld(v, jm) - v0);
-  double lz = 0.0;
-  if (k + 1 < S.nz) lz += vp - v0;
-  if (k > 0) lz += vm - v0;
-  return v0 - (S.cx * lx + S.cy * ly + S.cz * lz);
+  const double up = k + 1 < S.nz ? vp - v0 : 0.0;
+  const double dn = k > 0 ? vm - v0 : 0.0;
+  return v0 - (S.cx * lx + S.cy * ly + z_term(S, k, up, dn));
 }
 
 // Start of a pseudo-time step with b = x (x unchanged): r = b - A b,
@@ -210,7 +239,7 @@ __global__ void k_pcheb_init(Stencil S, const T* __restrict__ x, T* __restrict__
     const double rr = v0 - Ab;
     r[off + c] = (T)rr;
     bsave[off + c] = (T)v0;
-    yp = (rr + S.cz * yp) * inv_m[k];
+    yp = (rr + z_down(S, k) * yp) * inv_m[k];
     tmp[off + c] = (T)yp;
     vm = v0;
     v0 = vp;
@@ -245,7 +274,7 @@ __global__ void k_pcheb_iter(Stencil S, const T* __restrict__ d, T* __restrict__
     x[off + c] = (T)(ld(x, off + c) + v0);
     const double rr = ld(r, off + c) - Ad;
     r[off + c] = (T)rr;
-    yp = (rr + S.cz * yp) * inv_m[k];
+    yp = (rr + z_down(S, k) * yp) * inv_m[k];
     tmp[off + c] = (T)yp;
     vm = v0;
     v0 = vp;
@@ -347,10 +376,9 @@ __global__ void k_applyA(Stencil S, const double* __restrict__ in, double* __res
     const int jm = j == 0 ? c + (S.ny - 1) * S.nx : c - S.nx;
     const double lx = (x[ip] - xc) + (x[im] - xc);
     const double ly = (x[jp] - xc) + (x[jm] - xc);
-    double lz = 0.0;
-    if (k + 1 < S.nz) lz += x[c + plane] - xc;
-    if (k > 0) lz += x[c - plane] - xc;
-    const double ax = xc - (S.cx * lx + S.cy * ly + S.cz * lz);
+    const double up = k + 1 < S.nz ? x[c + plane] - xc : 0.0;
+    const double dn = k > 0 ? x[c - plane] - xc : 0.0;
+    const double ax = xc - (S.cx * lx + S.cy * ly + z_term(S, k, up, dn));
     if (COMB) {
       double v = alpha * ax + beta * xc;
       if (other) v += gamma * other[off + c];
@@ -508,12 +536,8 @@ int launch_green_check(const DevParams& P, const double* raw, const double* y, c
 
 const double* apply_An(const DevParams& P, DevArrays& A, const double* y, int nch, int ntau,
                        double tau, hipStream_t s) {
-  Stencil S;
-  S.nx = P.nx, S.ny = P.ny, S.nz = P.nz, S.ncell = P.ncell;
   double dtau = tau / (ntau > 0 ? ntau : 1);
-  S.cx = dtau / (P.hx * P.hx);
-  S.cy = dtau / (P.hy * P.hy);
-  S.cz = dtau * P.kz_diff / (P.hz * P.hz);
+  const Stencil S = make_stencil(P, A, dtau);
   const int rows = P.ny * P.nz;
   dim3 grid((unsigned)((P.nx + kBlock - 1) / kBlock), (unsigned)(rows < 65535 ? rows : 65535), nch);
   const double* cur = y;
@@ -559,13 +583,9 @@ int read_partials(const double* part, int nblocks, int nch, double* rel, hipStre
 
 int launch_check_bdf2(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
                       hipStream_t s) {
-  Stencil S;
-  S.nx = P.nx, S.ny = P.ny, S.nz = P.nz, S.ncell = P.ncell;
   const int N = ntau > 0 ? ntau : 1;
   const double dtau = tau / N;
-  S.cx = dtau / (P.hx * P.hx);
-  S.cy = dtau / (P.hy * P.hy);
-  S.cz = dtau * P.kz_diff / (P.hz * P.hz);
+  const Stencil S = make_stencil(P, A, dtau);
   const int rows = P.ny * P.nz;
   dim3 grid((unsigned)((P.nx + kBlock - 1) / kBlock), (unsigned)(rows < 65535 ? rows : 65535), nch);
   // A = I + M, so (3 + 2M) x = 2 A x + x
@@ -622,15 +642,25 @@ size_t smooth_red_doubles(int ncell, int nch, int ntau) {
   return (size_t)((ncell + kBlock - 1) / kBlock) * 2 * nch * (ntau > 0 ? ntau : 1);
 }
 
-void smooth_ztab(const DevParams& P, int ntau, double tau, double* host_tab) {
+void smooth_ztab(const DevParams& P, const double* zcoup, int ntau, double tau,
+                 double* host_tab) {
+  // Thomas factors of I - dtau L_z: row k has diagonal 1 + up_k + dn_k,
+  // -dn_k below it and -up_k above it (uniform: up = dn = cz inside)
   double dtau = tau / (ntau > 0 ? ntau : 1);
   double cz = dtau * P.kz_diff / (P.hz * P.hz);
   double prev_cp = 0.0;
   for (int k = 0; k < P.nz; ++k) {
-    int nb = (k > 0) + (k + 1 < P.nz);
-    double diag = 1.0 + cz * nb;
-    double m = k == 0 ? diag : diag + cz * prev_cp;
-    double cp = -cz / m;
+    double up, dn;
+    if (P.graded) {
+      up = dtau * zcoup[2 * k];
+      dn = dtau * zcoup[2 * k + 1];
+    } else {
+      up = k + 1 < P.nz ? cz : 0.0;
+      dn = k > 0 ? cz : 0.0;
+    }
+    double diag = 1.0 + up + dn;
+    double m = k == 0 ? diag : diag + dn * prev_cp;
+    double cp = -up / m;
     host_tab[k] = 1.0 / m;
     host_tab[P.nz + k] = cp;
     prev_cp = cp;
@@ -663,21 +693,23 @@ struct ChebPlan {
   double theta, delta;
 };
 
-static ChebPlan cheb_plan(const DevParams& P, int nch, double dt, double rtol) {
+static ChebPlan cheb_plan(const DevParams& P, const DevArrays& A, int nch, double dt,
+                          double rtol) {
   ChebPlan p;
-  Stencil& S = p.S;
-  S.nx = P.nx, S.ny = P.ny, S.nz = P.nz, S.ncell = P.ncell;
-  S.cx = dt / (P.hx * P.hx);
-  S.cy = dt / (P.hy * P.hy);
-  S.cz = dt * P.kz_diff / (P.hz * P.hz);
+  p.S = make_stencil(P, A, dt);
+  const Stencil& S = p.S;
   const double axy = 4.0 * ((P.nx > 1 ? S.cx : 0.0) + (P.ny > 1 ? S.cy : 0.0));
-  const double az = 4.0 * (P.nz > 1 ? S.cz : 0.0);
+  const double az = P.nz > 1 ? dt * P.zlam : 0.0;
   const double kappaA = 1.0 + axy + az;
+  // A graded mesh's operator is not symmetric but similar to a symmetric one
+  // through the square roots of the cell heights: its residual norms carry
+  // that similarity's condition number, zskew, on top of the bounds below.
   // plain Chebyshev on A: spectrum [1, kappaA], |r_0| <= (kappaA - 1) |b|
-  const int k_plain = cheb_iters(kappaA, kappaA - 1.0, rtol);
-  // z-line preconditioned: spectrum of M^-1 A in [1, 1 + axy]; the bound
-  // picks up sqrt(cond M) = sqrt(1 + az)
-  const int k_line = cheb_iters(1.0 + axy, sqrt(1.0 + az) * (kappaA - 1.0), rtol);
+  const int k_plain = cheb_iters(kappaA, P.zskew * (kappaA - 1.0), rtol);
+  // z-line preconditioned: L_xy and L_z commute (the z coupling is the same
+  // in every column), so the spectrum of M^-1 A lies in [1, 1 + axy]; the
+  // bound picks up sqrt(cond M) = sqrt(1 + az)
+  const int k_line = cheb_iters(1.0 + axy, P.zskew * sqrt(1.0 + az) * (kappaA - 1.0), rtol);
   // cost model from measurements on MI355X: the per-cell sweep moves 6
   // vectors at ~5 TB/s; the column sweep moves 9 and reaches ~3.6 TB/s with
   // >= 128k column lanes, ~2 TB/s with fewer (latency bound)
@@ -698,8 +730,8 @@ static int64_t smooth_impl(const DevParams& P, DevArrays& A, int nch, int ntau, 
   const double dtau = tau / ntau;
   // backward Euler (and BDF2's first step) at dtau; later BDF2 steps solve
   // (I - 2/3 dtau L_h) with the second z-line table
-  const ChebPlan plans[2] = {cheb_plan(P, nch, dtau, rtol),
-                             cheb_plan(P, nch, (2.0 / 3.0) * dtau, rtol)};
+  const ChebPlan plans[2] = {cheb_plan(P, A, nch, dtau, rtol),
+                             cheb_plan(P, A, nch, (2.0 / 3.0) * dtau, rtol)};
   const size_t nall = (size_t)nch * P.ncell;
   const unsigned gall = (unsigned)((nall + kBlock - 1) / kBlock);
   T* x = std::is_same<T, double>::value ? (T*)A.smooth : (T*)A.sxf;

@@ -7,13 +7,10 @@
 
 namespace sedimi {
 
+// Nearest periodic image of a coordinate difference (selects, no branches).
 __device__ __forceinline__ double min_image(double d, double L, double hL) {
-  if (d > hL) {
-    d -= L;
-  } else if (d < -hL) {
-    d += L;
-  }
-  return d;
+  const double lo = d - L, hi = d + L;
+  return d > hL ? lo : (d < -hL ? hi : d);
 }
 
 // Squared centre distance and pair range in the exact FP64 association that
@@ -70,6 +67,23 @@ __device__ __forceinline__ void kick_drift_one(const DevParams& P, const DevArra
   const double dx = min_image(x.x - b.x, P.Lx, P.hLx), dy = min_image(x.y - b.y, P.Ly, P.hLy),
                dz = x.z - b.z;
   if (dx * dx + dy * dy + dz * dz > P.half_skin2) atomicOr(rb, 1);
+}
+
+// Cell of height z on a graded mesh with faces zf[0..nz]: the k with
+// zf[k] <= z < zf[k + 1] (a point on a face belongs to the upper cell);
+// below the mesh (or NaN) the first cell, at or above the top the last.
+__device__ __forceinline__ int z_cell(const double* __restrict__ zf, int nz, double z) {
+  if (!(z >= zf[0])) return 0;
+  if (z >= zf[nz]) return nz - 1;
+  int lo = 0, hi = nz;  // zf[lo] <= z < zf[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (zf[mid] <= z)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
 }
 
 // Index of the grid interval of width h holding x, clamped into [0, n - 1]

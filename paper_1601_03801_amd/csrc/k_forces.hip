@@ -92,7 +92,8 @@ __device__ __forceinline__ R drag_coef(const DevParams& P, R d, R eps_f, R wm) {
 }
 
 // Trilinear interpolation of the cell-centred mesh fields at (x, y, z):
-// periodic in x and y, clamped to the first / last cell centre in z.  The
+// periodic in x and y, clamped to the first / last cell centre in z (on a
+// graded mesh, between the centres' own heights).  The
 // eight corners are visited as four x-rows (y then z), two cells each, in a
 // loop that is not unrolled: unrolled, the sixteen in-flight double4 loads
 // set the kernel's register peak and halve its occupancy.
@@ -108,7 +109,8 @@ struct Corners {
   double fx, fy, fz;
 };
 
-__device__ __forceinline__ Corners corners_at(const DevParams& P, double x, double y, double z) {
+__device__ __forceinline__ Corners corners_at(const DevParams& P, const double* __restrict__ zc,
+                                              double x, double y, double z) {
   double sx = x / P.hx - 0.5, sy = y / P.hy - 0.5, sz = z / P.hz - 0.5;
   // keep indices in range even for non-finite positions (flagged elsewhere)
   if (!(sx >= -1.0 && sx <= (double)P.nx)) sx = 0.0;
@@ -124,6 +126,28 @@ __device__ __forceinline__ Corners corners_at(const DevParams& P, double x, doub
   if (P.nz == 1) {
     q.k0 = q.k1 = 0;
     q.fz = 0.0;
+  } else if (P.graded) {
+    // linear between the two cell centres around z (zc: the centres'
+    // heights), clamped to the first / last centre
+    if (!(z > zc[0])) {
+      q.k0 = 0;
+      q.fz = 0.0;
+    } else if (z >= zc[P.nz - 1]) {
+      q.k0 = P.nz - 2;
+      q.fz = 1.0;
+    } else {
+      int lo = 0, hi = P.nz - 1;  // zc[lo] <= z < zc[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (zc[mid] <= z)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      q.k0 = lo;
+      q.fz = (z - zc[lo]) / (zc[lo + 1] - zc[lo]);
+    }
+    q.k1 = q.k0 + 1;
   } else {
     sz = sz >= 0.0 ? (sz > P.nz - 1 ? (double)(P.nz - 1) : sz) : 0.0;
     q.k0 = (int)floor(sz);
@@ -137,7 +161,7 @@ __device__ __forceinline__ Corners corners_at(const DevParams& P, double x, doub
 template <int MODE>
 __device__ __forceinline__ FluidAt fluid_at(const DevParams& P, const DevArrays& A, double x,
                                             double y, double z) {
-  const Corners q = corners_at(P, x, y, z);
+  const Corners q = corners_at(P, A.zgeo + zgeo_centres(P.nz), x, y, z);
   const int i0 = q.i0, i1 = q.i1, j0 = q.j0, j1 = q.j1, k0 = q.k0, k1 = q.k1;
   const double fx = q.fx, fy = q.fy, fz = q.fz;
   FluidAt f{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
@@ -179,7 +203,7 @@ __device__ __forceinline__ FluidAt fluid_at(const DevParams& P, const DevArrays&
 // Trilinear interpolation of the cell-centred vorticity W (the lift only).
 __device__ __forceinline__ double3 vorticity_at(const DevParams& P, const DevArrays& A, double x,
                                              double y, double z) {
-  const Corners q = corners_at(P, x, y, z);
+  const Corners q = corners_at(P, A.zgeo + zgeo_centres(P.nz), x, y, z);
   double3 o = make_double3(0.0, 0.0, 0.0);
 #pragma unroll 1
   for (int r = 0; r < 8; ++r) {

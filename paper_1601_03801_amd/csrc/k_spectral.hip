@@ -1,5 +1,4 @@
-// k_spectral.hip -- direct solve of the implicit diffusion averaging on the
-// uniform mesh.
+// k_spectral.hip -- direct solve of the implicit diffusion averaging.
 //
 // Each pseudo-time step of the averaging (Eq. 12, backward Euler with
 // Delta tau = tau / N_tau) solves (I - Delta tau L_h) e_{m+1} = e_m with L_h
@@ -17,12 +16,21 @@
 // forward z pass.  Six passes over
 // the field replace the tens of stencil sweeps of an iterative solve.
 //
+// On a z mesh graded towards the bottom wall (Section 4's channel case) the
+// z operator is the finite-volume one (face flux over the centre distance,
+// per unit cell height), not a DCT-diagonal matrix; it is similar to a
+// symmetric tridiagonal matrix through the square roots of the cell
+// heights, whose eigenvectors (computed once on the host) replace C_z and
+// its inverse.  The x and y transforms and the passes are unchanged.
+//
 // The GEMM runs on the FP64 matrix cores (v_mfma_f64_16x16x4f64): a block
 // computes a 64 x 64 tile of C with four waves of 32 x 32 (2 x 2 MFMA tiles);
 // K is staged through LDS 16 at a time.  Per MFMA a lane reads one double of
 // A and one of B, against eight LDS reads per 16 FMAs for a 4 x 4 outer
 // product on the vector units.
+#include <algorithm>
 #include <mutex>
+#include <vector>
 #include <string>
 
 #include "k_common.h"
@@ -169,10 +177,105 @@ size_t spectral_table_doubles(const DevParams& P) {
   return nx * nx + ny * ny + 2 * nz * nz + nx + ny + nz;
 }
 
+// Eigen-decomposition of a real symmetric tridiagonal matrix (diagonal d,
+// off-diagonal e[i] = T[i][i + 1], e[n - 1] unused) by the implicit QL
+// iteration with Wilkinson's shift: each sweep chases a bulge up from the
+// first negligible off-diagonal element below l with plane rotations, which
+// are accumulated into the columns of z (row-major n x n, identity on entry).
+// On return d holds the eigenvalues and column j of z the unit eigenvector
+// of d[j].  Returns false if an eigenvalue needs more than 64 sweeps.
+static bool tridiagonal_eigen(int n, double* d, double* e, double* z) {
+  const double eps = 2.220446049250313e-16;
+  e[n - 1] = 0.0;
+  for (int l = 0; l < n; ++l) {
+    for (int sweep = 0;; ++sweep) {
+      int m = l;
+      while (m < n - 1 && fabs(e[m]) > eps * (fabs(d[m]) + fabs(d[m + 1]))) ++m;
+      if (m == l) break;
+      if (sweep == 64) return false;
+      // shift: the eigenvalue of the leading 2 x 2 block nearer to d[l]
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0.0 ? r : -r));
+      double sn = 1.0, cs = 1.0, shift = 0.0;
+      bool split = false;
+      for (int i = m - 1; i >= l; --i) {
+        const double f = sn * e[i], b = cs * e[i];
+        r = hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {  // the matrix splits here: restart on the smaller block
+          d[i + 1] -= shift;
+          e[m] = 0.0;
+          split = true;
+          break;
+        }
+        sn = f / r;
+        cs = g / r;
+        g = d[i + 1] - shift;
+        r = (d[i] - g) * sn + 2.0 * cs * b;
+        shift = sn * r;
+        d[i + 1] = g + shift;
+        g = cs * r - b;
+        for (int k = 0; k < n; ++k) {
+          const double a = z[(size_t)k * n + i], c = z[(size_t)k * n + i + 1];
+          z[(size_t)k * n + i + 1] = sn * a + cs * c;
+          z[(size_t)k * n + i] = cs * a - sn * c;
+        }
+      }
+      if (split) continue;
+      d[l] -= shift;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  return true;
+}
+
+// The graded z operator: -L_z = H^-1 S with H the cell heights and S
+// symmetric tridiagonal (S_kk = u_k + d_k, S_k,k+1 = -u_k in units of the
+// coupling times the height of cell k).  B = H^-1/2 S H^-1/2 = Q diag(lam) Q^T
+// is symmetric, so -L_z = (H^-1/2 Q) diag(lam) (Q^T H^1/2): the forward
+// transform is Q^T H^1/2, the inverse H^-1/2 Q.
+int graded_z_transform(int nz, const double* zgeo, double* out) {
+  const double* zf = zgeo + zgeo_faces(nz);
+  const double* cp = zgeo + zgeo_coupling(nz);
+  std::vector<double> h(nz), d(nz), e(nz, 0.0), q((size_t)nz * nz, 0.0);
+  for (int k = 0; k < nz; ++k) h[k] = zf[k + 1] - zf[k];
+  for (int k = 0; k < nz; ++k) {
+    d[k] = cp[2 * k] + cp[2 * k + 1];  // (H^-1 S)_kk = S_kk / h_k
+    // S_k,k+1 = -h_k u_k (= -h_{k+1} d_{k+1}); B_k,k+1 = S_k,k+1 / sqrt(h_k h_k+1)
+    if (k + 1 < nz) e[k] = -h[k] * cp[2 * k] / sqrt(h[k] * h[k + 1]);
+  }
+  for (int k = 0; k < nz; ++k) q[(size_t)k * nz + k] = 1.0;
+  if (!tridiagonal_eigen(nz, d.data(), e.data(), q.data())) return -1;
+  // the columns must be orthonormal to rounding
+  double worst = 0.0;
+  for (int a = 0; a < nz; ++a)
+    for (int b = a; b < nz; ++b) {
+      double dot = 0.0;
+      for (int k = 0; k < nz; ++k) dot += q[(size_t)k * nz + a] * q[(size_t)k * nz + b];
+      worst = std::max(worst, fabs(dot - (a == b ? 1.0 : 0.0)));
+    }
+  if (!(worst <= 1e-13 * nz)) return -1;
+  double* fwd = out;
+  double* inv = out + (size_t)nz * nz;
+  double* lam = inv + (size_t)nz * nz;
+  for (int m = 0; m < nz; ++m) {
+    lam[m] = d[m] > 0.0 ? d[m] : 0.0;  // -L_z is positive semi-definite
+    for (int k = 0; k < nz; ++k) {
+      const double v = q[(size_t)k * nz + m];
+      fwd[(size_t)m * nz + k] = v * sqrt(h[k]);
+      inv[(size_t)k * nz + m] = v / sqrt(h[k]);
+    }
+  }
+  return 0;
+}
+
 // Host tables: H_x, H_y (symmetric, H H = n I), C_z, its inverse, and the
 // eigenvalues of -L_h per axis.  Angles are reduced exactly in integers
-// before the cosine so that large p q stay accurate.
-void spectral_tables(const DevParams& P, double* t) {
+// before the cosine so that large p q stay accurate.  On a graded mesh the
+// z transform, its inverse and eigenvalues are zdiag's.
+void spectral_tables(const DevParams& P, const double* zdiag, double* t) {
   const double pi = 3.14159265358979323846;
   const int nx = P.nx, ny = P.ny, nz = P.nz;
   double* hx = t;
@@ -191,7 +294,7 @@ void spectral_tables(const DevParams& P, double* t) {
   };
   cas_table(hx, nx);
   cas_table(hy, ny);
-  for (int m = 0; m < nz; ++m)
+  for (int m = 0; zdiag == nullptr && m < nz; ++m)
     for (int k = 0; k < nz; ++k) {
       // cos(pi m (2k + 1) / (2 nz)), angle reduced modulo 4 nz
       const int64_t r = ((int64_t)m * (2 * k + 1)) % (4 * (int64_t)nz);
@@ -203,8 +306,12 @@ void spectral_tables(const DevParams& P, double* t) {
     lx[p] = (2.0 - 2.0 * cos(2.0 * pi * p / nx)) / (P.hx * P.hx);
   for (int p = 0; p < ny; ++p)
     ly[p] = (2.0 - 2.0 * cos(2.0 * pi * p / ny)) / (P.hy * P.hy);
-  for (int m = 0; m < nz; ++m)
+  for (int m = 0; zdiag == nullptr && m < nz; ++m)
     lz[m] = P.kz_diff * (2.0 - 2.0 * cos(pi * m / nz)) / (P.hz * P.hz);  // z diffusivity
+  if (zdiag) {
+    std::copy(zdiag, zdiag + 2 * (size_t)nz * nz, cz);  // forward, then inverse
+    std::copy(zdiag + 2 * (size_t)nz * nz, zdiag + 2 * (size_t)nz * nz + nz, lz);
+  }
 }
 
 namespace {

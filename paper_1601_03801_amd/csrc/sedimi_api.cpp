@@ -90,6 +90,8 @@ struct sedimi_ctx {
   bool have_particles = false;
   int64_t last_iters = 0;
   double last_residual = 0.0;
+  std::vector<double> zgeo;  // z geometry (zgeo_* layout), uploaded at bind
+  std::vector<double> zdiag; // graded direct solve: z transform, inverse, eigenvalues
   bool direct = false;       // the implicit steps are solved by diagonalisation
   bool last_direct = false;  // the last plain solve was the direct one
   int check_blocks = 0;      // residual partials of the last direct solve
@@ -145,6 +147,51 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // Largest axis of the direct diffusion solve (its transform tables grow as
 // n^2 and its work per cell as n).
 constexpr int kDirectMaxAxis = 2048;
+// On a graded mesh the z transform comes from an eigen-decomposition on the
+// host at context creation (cubic in nz): larger graded meshes are solved by
+// the iterative solver.
+constexpr int kGradedDirectMaxNz = 512;
+
+bool graded_mesh(const sedimi_params& p) {
+  return p.nz > 1 && p.z_grading > 0.0 && p.z_grading != 1.0;
+}
+
+// Faces, centres, cell volumes and z coupling of the diffusion operator in
+// the zgeo_* layout.  Section 4's channel mesh is refined towards the bottom
+// wall; the grading is read as cell heights growing geometrically, h_k =
+// h_0 q^k with q^(nz - 1) = z_grading (the top cell's height over the bottom
+// cell's), summed from the bottom in order and scaled to Lz.  The coupling
+// of plane k to a neighbour is the flux through the shared face over the
+// centre distance, per unit height of cell k: kz / (h_k dc).
+std::vector<double> z_geometry(const sedimi_params& p, const DevParams& P) {
+  const int nz = P.nz;
+  std::vector<double> g(zgeo_doubles(nz), 0.0);
+  double* zf = g.data() + zgeo_faces(nz);
+  double* zc = g.data() + zgeo_centres(nz);
+  double* vol = g.data() + zgeo_volumes(nz);
+  double* cp = g.data() + zgeo_coupling(nz);
+  zf[0] = 0.0;
+  if (P.graded) {
+    double sum = 0.0;
+    for (int k = 0; k < nz; ++k) sum += pow(p.z_grading, (double)k / (nz - 1));
+    const double scale = p.Lz / sum;
+    for (int k = 1; k <= nz; ++k)
+      zf[k] = zf[k - 1] + pow(p.z_grading, (double)(k - 1) / (nz - 1)) * scale;
+    zf[nz] = p.Lz;
+  } else {
+    for (int k = 1; k <= nz; ++k) zf[k] = p.Lz * k / nz;
+  }
+  for (int k = 0; k < nz; ++k) {
+    zc[k] = 0.5 * (zf[k] + zf[k + 1]);
+    vol[k] = P.hx * P.hy * (zf[k + 1] - zf[k]);
+  }
+  for (int k = 0; k < nz; ++k) {
+    const double h = zf[k + 1] - zf[k];
+    cp[2 * k] = k + 1 < nz ? P.kz_diff / (h * (zc[k + 1] - zc[k])) : 0.0;
+    cp[2 * k + 1] = k > 0 ? P.kz_diff / (h * (zc[k] - zc[k - 1])) : 0.0;
+  }
+  return g;
+}
 
 // Workspace carving: the same walk computes the size (base == nullptr) and
 // assigns the pointers.
@@ -216,6 +263,7 @@ size_t layout(const sedimi_ctx* c, char* base, DevArrays* A) {
   a.stmp = w.take<double>(nch * nc);
   a.us = w.take<double>(nch == 7 ? 3 * nc : 0);
   a.ztab = w.take<double>(4 * (size_t)c->P.nz);
+  a.zgeo = w.take<double>(zgeo_doubles(c->P.nz));
   a.sprev = w.take<double>(c->prm.avg_scheme == SEDIMI_SCHEME_BDF2 && !c->direct ? nch * nc : 0);
   a.spec = w.take<double>(c->direct ? spectral_table_doubles(c->P) : 0);
   a.cell_count = w.take<int>(nc + 1);
@@ -412,8 +460,12 @@ int check_params(sedimi_ctx* c, const sedimi_params& p, int64_t cap) {
     return fail(c, SEDIMI_EINVAL, "surrogate parameters out of range");
   if (p.nn_enable && p.nz > kSplitMaxNz)
     return fail(c, SEDIMI_EINVAL, "the network needs nz <= 150 (its skip holds a z-column in LDS)");
-  if (!(p.z_grading == 0.0 || p.z_grading == 1.0))
-    return fail(c, SEDIMI_EINVAL, "graded z meshes are not supported on the GPU (z_grading 0 or 1)");
+  if (!(p.z_grading >= 0.0 && std::isfinite(p.z_grading)))
+    return fail(c, SEDIMI_EINVAL, "z_grading must be finite and >= 0 (0 or 1: uniform)");
+  if (graded_mesh(p) && p.nn_enable)
+    return fail(c, SEDIMI_EINVAL, "the network needs a uniform z mesh (z_grading 0 or 1)");
+  if (graded_mesh(p) && p.avg_solver == SEDIMI_SOLVE_DIRECT && p.nz > kGradedDirectMaxNz)
+    return fail(c, SEDIMI_EINVAL, "direct averaging solve on a graded mesh needs nz <= 512");
   if (p.avg_scheme != SEDIMI_SCHEME_EULER && p.avg_scheme != SEDIMI_SCHEME_BDF2)
     return fail(c, SEDIMI_EINVAL, "unknown averaging scheme");
   if (p.avg_scheme == SEDIMI_SCHEME_BDF2 && p.nn_enable)
@@ -463,6 +515,23 @@ void fill_dev_params(sedimi_ctx* c) {
   if (p.avg_bandwidth_z > 0 && p.avg_bandwidth > 0) {
     const double r = p.avg_bandwidth_z / p.avg_bandwidth;
     P.kz_diff = r * r;
+  }
+  P.graded = graded_mesh(p) ? 1 : 0;
+  P.zlam = p.nz > 1 ? 4.0 * P.kz_diff / (P.hz * P.hz) : 0.0;
+  P.zskew = 1.0;
+  c->zgeo = z_geometry(p, P);
+  if (P.graded) {
+    // Gershgorin bound of -L_z, and the cell heights' spread
+    const double* zf = c->zgeo.data() + zgeo_faces(p.nz);
+    const double* cp = c->zgeo.data() + zgeo_coupling(p.nz);
+    double lam = 0.0, hmin = INFINITY, hmax = 0.0;
+    for (int k = 0; k < p.nz; ++k) {
+      lam = std::max(lam, 2.0 * (cp[2 * k] + cp[2 * k + 1]));
+      hmin = std::min(hmin, zf[k + 1] - zf[k]);
+      hmax = std::max(hmax, zf[k + 1] - zf[k]);
+    }
+    P.zlam = lam;
+    P.zskew = sqrt(hmax / hmin);
   }
   // neighbour bins: no smaller than the largest pair range plus the skin
   double hb = p.d_max * (1.0 + p.lub_out_frac) + p.skin;
@@ -585,7 +654,7 @@ double direct_tol(const sedimi_ctx* c) {
   double lam = 0.0;
   if (P.nx > 1) lam += 4.0 / (P.hx * P.hx);
   if (P.ny > 1) lam += 4.0 / (P.hy * P.hy);
-  if (P.nz > 1) lam += 4.0 * P.kz_diff / (P.hz * P.hz);
+  if (P.nz > 1) lam += P.zlam;
   const double a = dtau * lam;
   // BDF2: the check multiplies y by (I + M)(3 I + 2 M)^(N-1), M = -dtau L
   const double amp = c->prm.avg_scheme == SEDIMI_SCHEME_BDF2
@@ -664,9 +733,22 @@ int sedimi_create(const sedimi_params* p, int64_t max_particles, sedimi_ctx** ou
   c->mixed = p->precision == SEDIMI_MIXED;
   c->direct = p->avg_solver == SEDIMI_SOLVE_DIRECT ||
               (p->avg_solver == SEDIMI_SOLVE_AUTO &&
-               std::max(p->nx, std::max(p->ny, p->nz)) <= kDirectMaxAxis);
+               std::max(p->nx, std::max(p->ny, p->nz)) <= kDirectMaxAxis &&
+               (!graded_mesh(*p) || p->nz <= kGradedDirectMaxNz));
   if (rc == SEDIMI_OK) {
     fill_dev_params(c);
+    if (c->direct && c->P.graded) {
+      // the z transform of the graded operator (host eigen-decomposition)
+      c->zdiag.assign(2 * (size_t)p->nz * p->nz + p->nz, 0.0);
+      if (graded_z_transform(p->nz, c->zgeo.data(), c->zdiag.data()) != 0) {
+        if (p->avg_solver == SEDIMI_SOLVE_DIRECT)
+          rc = fail(c, SEDIMI_ENOCONV, "eigen-decomposition of the graded z operator failed");
+        c->direct = false;
+        c->zdiag.clear();
+      }
+    }
+  }
+  if (rc == SEDIMI_OK) {
     if (c->P.nbx < 3 || c->P.nby < 3)
       rc = fail(c, SEDIMI_EINVAL, "domain must span at least 3 neighbour bins in x and y");
     else if ((int64_t)c->P.nbins > (int64_t)INT32_MAX / 8)
@@ -700,6 +782,8 @@ int sedimi_smooth_static(const sedimi_params* p, int nch, const double* raw, dou
     return bad(SEDIMI_EINVAL, "domain and mesh must be positive");
   if (std::max(p->nx, std::max(p->ny, p->nz)) > kDirectMaxAxis)
     return bad(SEDIMI_EINVAL, "direct averaging solve needs <= 2048 cells per axis");
+  if (graded_mesh(*p))
+    return bad(SEDIMI_EINVAL, "the static solve needs a uniform z mesh (z_grading 0 or 1)");
   if (!(p->avg_bandwidth >= 0 && std::isfinite(p->avg_bandwidth)) ||
       !(p->avg_bandwidth_z >= 0 && std::isfinite(p->avg_bandwidth_z)) || p->avg_ntau < 0)
     return bad(SEDIMI_EINVAL, "averaging parameters out of range");
@@ -754,15 +838,19 @@ int sedimi_bind_workspace(sedimi_ctx* c, void* dev_ptr, size_t bytes) {
     for (int r = 0; r < P.nbins; ++r) rank[code[r].second] = r;
     HIPCHK(c, hipMemcpyAsync(c->A.bin_rank, rank.data(), sizeof(int) * rank.size(),
                              hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->A.zgeo, c->zgeo.data(), sizeof(double) * c->zgeo.size(),
+                             hipMemcpyHostToDevice, c->stream));
     std::vector<double> zt(4 * (size_t)P.nz);
     double tau = 0.25 * c->prm.avg_bandwidth * c->prm.avg_bandwidth;
-    smooth_ztab(P, std::max(1, c->prm.avg_ntau), tau, zt.data());
-    smooth_ztab(P, std::max(1, c->prm.avg_ntau), (2.0 / 3.0) * tau, zt.data() + 2 * P.nz);
+    const double* zcoup = c->zgeo.data() + zgeo_coupling(P.nz);
+    smooth_ztab(P, zcoup, std::max(1, c->prm.avg_ntau), tau, zt.data());
+    smooth_ztab(P, zcoup, std::max(1, c->prm.avg_ntau), (2.0 / 3.0) * tau,
+                zt.data() + 2 * P.nz);
     HIPCHK(c, hipMemcpyAsync(c->A.ztab, zt.data(), sizeof(double) * zt.size(),
                              hipMemcpyHostToDevice, c->stream));
     if (c->direct) {
       std::vector<double> st(spectral_table_doubles(P));
-      spectral_tables(P, st.data());
+      spectral_tables(P, c->zdiag.empty() ? nullptr : c->zdiag.data(), st.data());
       HIPCHK(c, hipMemcpyAsync(c->A.spec, st.data(), sizeof(double) * st.size(),
                                hipMemcpyHostToDevice, c->stream));
       HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -925,7 +1013,11 @@ int sedimi_set_fluid(sedimi_ctx* c, const double* U, const double* gp, const dou
           for (int a = 0; a < 3; ++a) {
             gx[a] = (u(ip, j, k, a) - u(im, j, k, a)) / (2.0 * P.hx);
             gy[a] = (u(i, jp, k, a) - u(i, jm, k, a)) / (2.0 * P.hy);
-            gz[a] = kp > km ? (u(i, j, kp, a) - u(i, j, km, a)) / ((kp - km) * P.hz) : 0.0;
+            // z differences over the centre distance (graded meshes: the
+            // centres' own heights)
+            const double dzc = P.graded ? c->zgeo[zgeo_centres(nz) + kp] - c->zgeo[zgeo_centres(nz) + km]
+                                        : (kp - km) * P.hz;
+            gz[a] = kp > km ? (u(i, j, kp, a) - u(i, j, km, a)) / dzc : 0.0;
           }
           h[((size_t)k * ny + j) * nx + i] =
               make_double4(gy[2] - gz[1], gz[0] - gx[2], gx[1] - gy[0], 0.0);
@@ -1338,7 +1430,7 @@ struct StateHeader {
   // z-line and spectral tables in the workspace derive from the bandwidths
   // and N_tau)
   struct AvgParams {
-    double avg_bandwidth, avg_bandwidth_z, avg_rtol, nn_alpha, nn_bound, nn_sample;
+    double avg_bandwidth, avg_bandwidth_z, avg_rtol, nn_alpha, nn_bound, nn_sample, z_grading;
     uint64_t nn_seed;
     int32_t avg_ntau, avg_scheme, avg_solver, avg_solid_velocity;
   } avg;
@@ -1355,6 +1447,7 @@ void state_avg_params(const sedimi_ctx* c, StateHeader::AvgParams* a) {
   a->nn_alpha = p.nn_alpha;
   a->nn_bound = p.nn_bound;
   a->nn_sample = p.nn_sample;
+  a->z_grading = p.z_grading;
   a->nn_seed = p.nn_seed;
   a->avg_ntau = p.avg_ntau;
   a->avg_scheme = p.avg_scheme;

@@ -72,6 +72,13 @@ struct Ctl {
   long long pad1[5];
 };
 
+// Offsets into DevArrays::zgeo for a mesh of nz planes.
+__host__ __device__ inline size_t zgeo_faces(int) { return 0; }
+__host__ __device__ inline size_t zgeo_centres(int nz) { return (size_t)nz + 1; }
+__host__ __device__ inline size_t zgeo_volumes(int nz) { return 2 * (size_t)nz + 1; }
+__host__ __device__ inline size_t zgeo_coupling(int nz) { return 3 * (size_t)nz + 1; }
+__host__ __device__ inline size_t zgeo_doubles(int nz) { return 5 * (size_t)nz + 1; }
+
 // Parameters copied by value into the kernels.
 struct DevParams {
   double Lx, Ly, Lz, hLx, hLy;
@@ -84,6 +91,11 @@ struct DevParams {
   int drag_law, lubrication, fluid_forces, bottom_wall, top_wall;
   double eps_s_max;
   double kz_diff;  // diffusivity of the averaging along z (1: isotropic)
+  // z mesh: graded (geometric cell heights towards the bottom wall) or
+  // uniform.  zlam bounds the eigenvalues of -L_z (z diffusivity included);
+  // zskew = sqrt(largest / smallest cell height) (1 on a uniform mesh).
+  double zlam, zskew;
+  int graded, graded_pad;
   double lift_c;   // C_l rho_f nu^(1/2) of the shear lift (0: no lift)
   int nch_avg;     // averaged channels: 4, or 7 with the solid volume flux
   // neighbour bins
@@ -114,6 +126,10 @@ struct DevArrays {
   double4 *U, *gp, *du;  // U.w = averaged solid fraction
   double4* G;            // -grad p + C_add rho_f DU/Dt (step kernel)
   double4* W;            // curl U_f at cell centres (only with the lift)
+  // z geometry (ZGEO_* offsets): faces [nz + 1], centres [nz], cell volumes
+  // [nz], and per plane the z coupling of the diffusion operator to the plane
+  // above and below ([nz][2], z diffusivity included, zero at the walls)
+  double* zgeo;
   double *raw, *smooth, *sx, *sr, *sd0, *sd1;  // [nch_avg][ncell] each
   double* us;  // solid velocity [3][ncell] (only with the solid flux)
   double *sxf, *stmp;  // solver: FP32 iterate (mixed mode), column-sweep scratch
@@ -167,7 +183,10 @@ double read_smooth_residual(const DevParams& P, DevArrays& A, int nch, int ntau,
                             hipStream_t s);
 size_t smooth_red_doubles(int ncell, int nch, int ntau);
 // Thomas-algorithm table of the z-line preconditioner (2 * nz doubles).
-void smooth_ztab(const DevParams& P, int ntau, double tau, double* host_tab);
+// zcoup: the host copy of the z coupling table (graded meshes; may be null
+// on a uniform mesh).
+void smooth_ztab(const DevParams& P, const double* zcoup, int ntau, double tau,
+                 double* host_tab);
 // Residual check of a smoothed field y (nch channels) against raw on a seeded
 // sample of cells (fraction frac): r = A^ntau y - raw.  Enqueues the work
 // (partials in A.red, A.sd0/A.sd1 as scratch) and returns the block count;
@@ -206,7 +225,14 @@ void launch_solid_velocity(const DevParams& P, DevArrays& A, hipStream_t s);
 void launch_spectral(const DevParams& P, DevArrays& A, int nch, int ntau, double tau,
                      bool bdf2, hipStream_t s);
 size_t spectral_table_doubles(const DevParams& P);
-void spectral_tables(const DevParams& P, double* host_tab);
+// zdiag: on a graded mesh the z transform of graded_z_transform (null on a
+// uniform mesh, which uses the DCT-II).
+void spectral_tables(const DevParams& P, const double* zdiag, double* host_tab);
+// The z transform that diagonalises -L_z on a graded mesh (zgeo: the z
+// geometry in the zgeo_* layout): out = forward [nz][nz], inverse [nz][nz],
+// eigenvalues [nz].  Returns 0, or -1 if the eigen-decomposition did not
+// converge or its result fails the orthogonality check.
+int graded_z_transform(int nz, const double* zgeo, double* out);
 // The same solve of a caller's device field without a workspace: tables and
 // the intermediate field in the library's static device scratch (see
 // sedimi_smooth_static).  Enqueue only; SEDIMI_OK or an error code with *err.

@@ -68,7 +68,8 @@ int main() {
       {"us+nn", [](sedimi_params& q) { q.avg_solid_velocity = 1; q.nn_enable = 1; }},
       {"slots", [](sedimi_params& q) { q.max_neighbors = 0; }},
       {"narrow", [](sedimi_params& q) { q.Lx = 2 * q.d_max; }},
-      {"graded", [](sedimi_params& q) { q.z_grading = 4.0; }},
+      {"grading<0", [](sedimi_params& q) { q.z_grading = -1.0; }},
+      {"graded+nn", [](sedimi_params& q) { q.z_grading = 4.0; q.nn_enable = 1; }},
   };
   for (const Bad& b : bad) {
     sedimi_params q = base();
@@ -89,6 +90,14 @@ int main() {
   EXPECT(sedimi_workspace_bytes(c) > ws);
   sedimi_destroy(c);
   c = nullptr;
+  // graded z meshes: the direct solve's eigen-decomposition runs at creation
+  for (int nz : {2, 8, 64}) {
+    sedimi_params g = base();
+    g.z_grading = 5.0, g.nz = nz, g.avg_solver = SEDIMI_SOLVE_DIRECT;
+    EXPECT(sedimi_create(&g, 1000, &c) == SEDIMI_OK && c);
+    sedimi_destroy(c);
+    c = nullptr;
+  }
   EXPECT(sedimi_create(&p, -1, &c) == SEDIMI_EINVAL);
   if (c) sedimi_destroy(c);
   EXPECT(sedimi_step(nullptr, 1, 0) == SEDIMI_EINVAL);

@@ -97,12 +97,18 @@ def test_create_checks_parameters(L):
     assert rc == sm.EINVAL and not ctx.value
     rc, ctx = create(L, dict(prm, avg_scheme=2))
     assert rc == sm.EINVAL
-    # graded z meshes: the oracle has them, the GPU path refuses them for now
-    for g in (0.0, 1.0):
+    # graded z meshes: any finite grading >= 0; not with the network
+    for g in (0.0, 1.0, 4.0, 0.25):
         rc, ctx = create(L, dict(prm, z_grading=g))
         assert rc == sm.OK
         L.sedimi_destroy(ctx)
-    rc, ctx = create(L, dict(prm, z_grading=4.0))
+    for g in (-1.0, float("inf"), float("nan")):
+        rc, ctx = create(L, dict(prm, z_grading=g))
+        assert rc == sm.EINVAL and not ctx.value
+    rc, ctx = create(L, dict(prm, z_grading=4.0), nn=True)
+    assert rc == sm.EINVAL and not ctx.value
+    # the direct solve on a graded mesh: nz <= 512
+    rc, ctx = create(L, dict(prm, z_grading=4.0, nz=600, Lz=600 * 1e-4, solver="direct"))
     assert rc == sm.EINVAL and not ctx.value
     rc, ctx = create(L, prm, cap=-1)
     assert rc == sm.EINVAL
