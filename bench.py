@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -339,22 +341,54 @@ def particle_bench(args, name, precision, K, W, rebuilds=0, cpu_steps=0):
             "rebuild": rebuild, "cpu": cpu, "stats": stats}
 
 
+def host_cpu():
+    """The host CPU's model name (from /proc/cpuinfo), its logical CPU count
+    and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(w, prm, steps):
-    """The FP64 oracle on the host: a few particle steps of the same bed."""
+    """The FP64 oracle on the host: a few particle steps of the same bed, on
+    one thread and on all the threads this process may use (its OpenMP loops
+    keep every sum in order, so both runs give the same bits)."""
     import oracle
     n = len(w["d"])
-    ost = oracle.State(prm, w["x"], w["v"], w["w"], w["d"], w["rho"], U=w["U"],
-                       gradp=w["gradp"], dudt=w["dudt"])
-    ost.average()
-    ost.init_accel()
-    c0 = time.perf_counter()
-    ost.run(steps)
-    c1 = time.perf_counter()
-    print(f"bench: oracle {steps} steps in {c1 - c0:.1f} s", file=sys.stderr, flush=True)
-    return {"value": round(n * steps / (c1 - c0), 1), "unit": "particle-updates/s",
-            "cores": 1, "kind": "oracle",
+    host = host_cpu()
+    all_threads = int(os.environ.get("OMP_NUM_THREADS") or host["affinity"])
+    runs = {}
+    for threads in (1, all_threads):
+        oracle.set_threads(threads)
+        ost = oracle.State(prm, w["x"], w["v"], w["w"], w["d"], w["rho"], U=w["U"],
+                           gradp=w["gradp"], dudt=w["dudt"])
+        ost.average()
+        ost.init_accel()
+        c0 = time.perf_counter()
+        ost.run(steps)
+        c1 = time.perf_counter()
+        runs[threads] = (c1 - c0, ost.x.copy())
+        print(f"bench: oracle {steps} steps on {threads} threads in {c1 - c0:.1f} s",
+              file=sys.stderr, flush=True)
+    oracle.set_threads(1)
+    el_all, x_all = runs[all_threads]
+    el_one, x_one = runs[1]
+    return {"value": round(n * steps / el_all, 1), "unit": "particle-updates/s",
+            "cores": all_threads, "kind": "oracle",
             "sample": f"{steps} particle steps of the same {n}-sphere bed "
-                      f"({c1 - c0:.1f} s), no averaging"}
+                      f"({el_all:.1f} s on {all_threads} threads), no averaging",
+            "single_thread": {"value": round(n * steps / el_one, 1), "cores": 1,
+                              "seconds": round(el_one, 2)},
+            "bit_identical_across_threads": bool(np.array_equal(x_all, x_one)),
+            **host}
 
 
 def surrogate_section(args):

@@ -99,10 +99,26 @@ def lib():
         L.orc_solid_velocity.restype = None
         L.orc_apply_A.argtypes = [pp, C.c_double, P, P]
         L.orc_apply_A.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
+        L.orc_get_threads.argtypes = []
+        L.orc_get_threads.restype = C.c_int
+        # one thread unless a caller asks for more (set_threads)
+        L.orc_set_threads(1)
         if hasattr(L, "orc_conv3d_fwd"):
             _declare_cnn(L)
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops (results do not depend
+    on it: every sum keeps its order)."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 def _declare_cnn(L):

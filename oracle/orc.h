@@ -7,7 +7,9 @@
  * baseline leg use it.  It shares no code, header, table or constant with the
  * GPU path.  Every routine is written for clarity, not speed: pairs are
  * handled once each in ascending (i, j) order, sums run in particle-ID order,
- * and the linear solves are textbook conjugate gradients.
+ * and the linear solves are textbook conjugate gradients.  Loops whose
+ * iterations are independent may run on OpenMP threads; the sums after
+ * them keep that order.
  *
  * Conventions (all SI):
  *   axes x streamwise (periodic, [0, Lx)), y spanwise (periodic, [0, Ly)),
@@ -60,6 +62,13 @@ typedef struct {
   double z_grading;          /* top / bottom cell height ratio of a geometrically graded
                                 z mesh; <= 0 or 1: uniform */
 } orc_params;
+
+/* ---- threads (orc_pairs.c) ----
+ * The pair search, the per-pair and per-particle force evaluations and the
+ * kick-drift loops run on OpenMP threads; every sum still runs in the order
+ * written above, so the results are bit-identical for any thread count. */
+void orc_set_threads(int nthreads);
+int orc_get_threads(void);
 
 /* ---- mesh geometry along z (orc_mesh.c) ---- */
 int orc_graded(const orc_params* p);

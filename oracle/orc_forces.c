@@ -225,6 +225,7 @@ static void curl_cells(const orc_params* p, const double* U, double* om) {
     for (int k = 0; k < nz; ++k) zcv[k] = 0.5 * (zf[k] + zf[k + 1]);
     zc = zcv;
   }
+#pragma omp parallel for schedule(static)
   for (int k = 0; k < nz; ++k)
     for (int j = 0; j < ny; ++j)
       for (int i = 0; i < nx; ++i) {
@@ -386,6 +387,65 @@ static int wall_interaction(const orc_params* p, int64_t i, int side, const doub
   return 0;
 }
 
+/* One pair's lubrication, contact force and torque (Sections 2.1, 2.5), on
+ * i (j gets the opposite forces); kind 0: coincident centres (skipped),
+ * 1: no contact, 2: contact (xi: its updated tangential history). */
+typedef struct {
+  double flub[3], fnv[3], ft[3], tq[3], xi[3];
+  int kind;
+} pair_val;
+
+static void pair_eval(const orc_params* p, double zeta, double kt, int64_t i, int64_t j,
+                      const double* x, const double* v, const double* w, const double* d,
+                      const double* rho, const hmap* hm, const orc_contact* hin, pair_val* out) {
+  out->kind = 0;
+  double dx[3] = {min_image(x[3 * j] - x[3 * i], p->Lx), min_image(x[3 * j + 1] - x[3 * i + 1], p->Ly),
+                  x[3 * j + 2] - x[3 * i + 2]};
+  double s = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2];
+  double dist = sqrt(s);
+  if (!(dist > 0.0)) return; /* coincident centres: direction undefined */
+  out->kind = 1;
+  double nv[3] = {dx[0] / dist, dx[1] / dist, dx[2] / dist};
+  double ri = 0.5 * d[i], rj = 0.5 * d[j];
+  double rs = ri + rj;
+  double rw[3] = {ri * w[3 * i] + rj * w[3 * j], ri * w[3 * i + 1] + rj * w[3 * j + 1],
+                  ri * w[3 * i + 2] + rj * w[3 * j + 2]};
+  double rot[3];
+  cross3(rw, nv, rot);
+  double vrel[3] = {v[3 * i] - v[3 * j] + rot[0], v[3 * i + 1] - v[3 * j + 1] + rot[1],
+                    v[3 * i + 2] - v[3 * j + 2] + rot[2]};
+  double un = dot3(vrel, nv);
+  if (p->lubrication) {
+    double h = dist - rs;
+    double h_in = p->lub_in_frac * rs;
+    double hh = h > h_in ? h : h_in;
+    double aeff = ri * rj / rs;
+    double Fl = 6.0 * M_PI * p->mu_f * aeff * aeff * un / hh;
+    out->flub[0] = -Fl * nv[0];
+    out->flub[1] = -Fl * nv[1];
+    out->flub[2] = -Fl * nv[2];
+  }
+  double delta = rs - dist;
+  if (delta > 0.0) {
+    double mi = rho[i] * (M_PI / 6.0) * d[i] * d[i] * d[i];
+    double mj = rho[j] * (M_PI / 6.0) * d[j] * d[j] * d[j];
+    double meff = mi * mj / (mi + mj);
+    double gn = 2.0 * zeta * sqrt(meff * p->kn);
+    double gt = p->gammat_over_gamman * gn;
+    double Frep = p->kn * delta + gn * un;
+    out->fnv[0] = -Frep * nv[0];
+    out->fnv[1] = -Frep * nv[1];
+    out->fnv[2] = -Frep * nv[2];
+    double xi[3] = {0.0, 0.0, 0.0};
+    int64_t hq = hmap_find(hm, i, j);
+    if (hq >= 0) memcpy(xi, hin[hq].xi, sizeof(xi));
+    tangential(p, kt, gt, nv, vrel, fabs(Frep), xi, out->ft);
+    cross3(nv, out->ft, out->tq);
+    memcpy(out->xi, xi, sizeof(xi));
+    out->kind = 2;
+  }
+}
+
 int orc_forces(const orc_params* p, int64_t n, const double* x, const double* v,
                const double* w, const double* d, const double* rho, const double* a_prev,
                const orc_fields* fl, const orc_contact* hin, int64_t nhin,
@@ -448,68 +508,53 @@ int orc_forces(const orc_params* p, int64_t n, const double* x, const double* v,
     cap = np + 64;
   }
 
+  /* Each pair's forces depend on that pair alone: they are evaluated for a
+   * chunk of pairs at a time (in parallel when OpenMP threads are on), then
+   * added to the two particles in ascending pair order, so every sum is the
+   * same whatever the number of threads. */
   double zeta = damping_ratio(p->restitution);
   double kt = p->kt_over_kn * p->kn;
-  for (int64_t q = 0; q < np; ++q) {
-    int64_t i = ij[2 * q], j = ij[2 * q + 1];
-    double dx[3] = {min_image(x[3 * j] - x[3 * i], p->Lx), min_image(x[3 * j + 1] - x[3 * i + 1], p->Ly),
-                    x[3 * j + 2] - x[3 * i + 2]};
-    double s = (dx[0] * dx[0] + dx[1] * dx[1]) + dx[2] * dx[2];
-    double dist = sqrt(s);
-    if (!(dist > 0.0)) continue; /* coincident centres: direction undefined */
-    double nv[3] = {dx[0] / dist, dx[1] / dist, dx[2] / dist};
-    double ri = 0.5 * d[i], rj = 0.5 * d[j];
-    double rs = ri + rj;
-    double rw[3] = {ri * w[3 * i] + rj * w[3 * j], ri * w[3 * i + 1] + rj * w[3 * j + 1],
-                    ri * w[3 * i + 2] + rj * w[3 * j + 2]};
-    double rot[3];
-    cross3(rw, nv, rot);
-    double vrel[3] = {v[3 * i] - v[3 * j] + rot[0], v[3 * i + 1] - v[3 * j + 1] + rot[1],
-                      v[3 * i + 2] - v[3 * j + 2] + rot[2]};
-    double un = dot3(vrel, nv);
-    if (p->lubrication) {
-      double h = dist - rs;
-      double h_in = p->lub_in_frac * rs;
-      double hh = h > h_in ? h : h_in;
-      double aeff = ri * rj / rs;
-      double Fl = 6.0 * M_PI * p->mu_f * aeff * aeff * un / hh;
-      double f[3] = {-Fl * nv[0], -Fl * nv[1], -Fl * nv[2]};
-      add3(o.lub, i, f, 1.0);
-      add3(o.lub, j, f, -1.0);
-    }
-    double delta = rs - dist;
-    if (delta > 0.0) {
-      double mi = rho[i] * (M_PI / 6.0) * d[i] * d[i] * d[i];
-      double mj = rho[j] * (M_PI / 6.0) * d[j] * d[j] * d[j];
-      double meff = mi * mj / (mi + mj);
-      double gn = 2.0 * zeta * sqrt(meff * p->kn);
-      double gt = p->gammat_over_gamman * gn;
-      double Frep = p->kn * delta + gn * un;
-      double fnv[3] = {-Frep * nv[0], -Frep * nv[1], -Frep * nv[2]};
-      double xi[3] = {0.0, 0.0, 0.0};
-      int64_t hq = hmap_find(&hm, i, j);
-      if (hq >= 0) memcpy(xi, hin[hq].xi, sizeof(xi));
-      double ft[3];
-      tangential(p, kt, gt, nv, vrel, fabs(Frep), xi, ft);
-      add3(o.contact, i, fnv, 1.0);
-      add3(o.contact, j, fnv, -1.0);
-      add3(o.contact, i, ft, 1.0);
-      add3(o.contact, j, ft, -1.0);
-      double tq[3];
-      cross3(nv, ft, tq);
-      add3(o.torque, i, tq, ri);
-      add3(o.torque, j, tq, rj);
-      if (*nhout >= cap_hout) {
-        rc = -1;
-        goto done_pairs;
+  const int64_t chunk = (int64_t)1 << 20;
+  pair_val* pv = (pair_val*)malloc(sizeof(pair_val) * (size_t)(np < chunk ? (np > 0 ? np : 1) : chunk));
+  if (!pv) {
+    rc = -2;
+    goto done_pairs;
+  }
+  for (int64_t q0 = 0; q0 < np; q0 += chunk) {
+    const int64_t q1 = np - q0 < chunk ? np : q0 + chunk;
+#pragma omp parallel for schedule(static)
+    for (int64_t q = q0; q < q1; ++q)
+      pair_eval(p, zeta, kt, ij[2 * q], ij[2 * q + 1], x, v, w, d, rho, &hm, hin, &pv[q - q0]);
+    for (int64_t q = q0; q < q1; ++q) {
+      const pair_val* r = &pv[q - q0];
+      if (r->kind == 0) continue;
+      const int64_t i = ij[2 * q], j = ij[2 * q + 1];
+      if (p->lubrication) {
+        add3(o.lub, i, r->flub, 1.0);
+        add3(o.lub, j, r->flub, -1.0);
       }
-      hout[*nhout].i = i;
-      hout[*nhout].j = j;
-      memcpy(hout[*nhout].xi, xi, sizeof(xi));
-      ++*nhout;
+      if (r->kind == 2) {
+        add3(o.contact, i, r->fnv, 1.0);
+        add3(o.contact, j, r->fnv, -1.0);
+        add3(o.contact, i, r->ft, 1.0);
+        add3(o.contact, j, r->ft, -1.0);
+        add3(o.torque, i, r->tq, 0.5 * d[i]);
+        add3(o.torque, j, r->tq, 0.5 * d[j]);
+        if (*nhout >= cap_hout) {
+          rc = -1;
+          free(pv);
+          goto done_pairs;
+        }
+        hout[*nhout].i = i;
+        hout[*nhout].j = j;
+        memcpy(hout[*nhout].xi, r->xi, sizeof(r->xi));
+        ++*nhout;
+      }
     }
   }
+  free(pv);
 
+  /* walls, in particle order (their contacts join the history list) */
   for (int64_t i = 0; i < n; ++i) {
     double r = 0.5 * d[i];
     double V = (M_PI / 6.0) * d[i] * d[i] * d[i];
@@ -524,7 +569,13 @@ int orc_forces(const orc_params* p, int64_t n, const double* x, const double* v,
       rc = -1;
       goto done_pairs;
     }
-    /* fluid-particle forces (Section 2.3) */
+  }
+
+  /* fluid-particle forces (Section 2.3) and the totals: each particle's own */
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    double V = (M_PI / 6.0) * d[i] * d[i] * d[i];
+    double m = rho[i] * V;
     int64_t idx[8];
     double wt[8];
     interp_weights(p, x + 3 * i, idx, wt);
@@ -602,6 +653,7 @@ static int eval_accel(const orc_params* p, int64_t n, const double* x, const dou
   int rc = orc_forces(p, n, x, v, w, d, rho, a_prev, fl, hin, nhin, hout, cap_hout, nhout, &o);
   if (rc == 0) {
     double g[3] = {p->gx, p->gy, p->gz};
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
       double V = (M_PI / 6.0) * d[i] * d[i] * d[i];
       double m = rho[i] * V;
@@ -656,18 +708,22 @@ int orc_run(const orc_params* p, int64_t n, double* x, double* v, double* w, dou
   }
   double dt = p->dt;
   for (int s = 0; s < nsteps; ++s) {
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < 3 * n; ++k) {
       v[k] += 0.5 * dt * a[k];
       w[k] += 0.5 * dt * alpha[k];
     }
+    int escaped = 0;
+#pragma omp parallel for schedule(static) reduction(| : escaped)
     for (int64_t i = 0; i < n; ++i) {
       x[3 * i] = wrap(x[3 * i] + dt * v[3 * i], p->Lx);
       x[3 * i + 1] = wrap(x[3 * i + 1] + dt * v[3 * i + 1], p->Ly);
       x[3 * i + 2] = x[3 * i + 2] + dt * v[3 * i + 2];
-      if (!(x[3 * i + 2] >= 0.0 && x[3 * i + 2] <= p->Lz)) {
-        rc = -4; /* particle left the domain through a wall */
-        goto out;
-      }
+      escaped |= !(x[3 * i + 2] >= 0.0 && x[3 * i + 2] <= p->Lz);
+    }
+    if (escaped) {
+      rc = -4; /* a particle left the domain through a wall */
+      goto out;
     }
     memcpy(aprev, a, sizeof(double) * 3 * (size_t)n);
     int64_t nh = 0;
@@ -676,6 +732,7 @@ int orc_run(const orc_params* p, int64_t n, double* x, double* v, double* w, dou
     if (rc) goto out;
     memcpy(hist, hnew, sizeof(orc_contact) * (size_t)nh);
     *nhist = nh;
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < 3 * n; ++k) {
       v[k] += 0.5 * dt * a[k];
       w[k] += 0.5 * dt * alpha[k];

@@ -19,6 +19,9 @@
 #include "orc.h"
 
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
@@ -66,6 +69,49 @@ static int cmp_i64(const void* a, const void* b) {
   return (x > y) - (x < y);
 }
 
+/* The partners j > i of particle i in range, from the distinct cells around
+ * i's cell, into *cand (grown as needed); returns -2 when out of memory. */
+static int partners(const orc_params* p, const double* x, const double* d, int cx, int cy, int cz,
+                    const int64_t* cell_of, const int64_t* start, const int64_t* members,
+                    int64_t i, int64_t** cand, int64_t* cand_cap, int64_t* ncand) {
+  int64_t ci = cell_of[i];
+  int a0 = (int)(ci % cx), b0 = (int)((ci / cx) % cy), c0 = (int)(ci / ((int64_t)cx * cy));
+  /* distinct neighbour cells (small grids would otherwise repeat a cell) */
+  int64_t nb[27];
+  int nnb = 0;
+  for (int dc = -1; dc <= 1; ++dc) {
+    int c = c0 + dc;
+    if (c < 0 || c >= cz) continue;
+    for (int db = -1; db <= 1; ++db) {
+      int b = ((b0 + db) % cy + cy) % cy;
+      for (int da = -1; da <= 1; ++da) {
+        int a = ((a0 + da) % cx + cx) % cx;
+        int64_t k = ((int64_t)c * cy + b) * cx + a;
+        int seen = 0;
+        for (int q = 0; q < nnb; ++q) seen |= (nb[q] == k);
+        if (!seen) nb[nnb++] = k;
+      }
+    }
+  }
+  *ncand = 0;
+  for (int q = 0; q < nnb; ++q) {
+    for (int64_t m = start[nb[q]]; m < start[nb[q] + 1]; ++m) {
+      int64_t j = members[m];
+      if (j <= i) continue;
+      if (!in_range(p, x + 3 * i, x + 3 * j, 0.5 * d[i], 0.5 * d[j])) continue;
+      if (*ncand == *cand_cap) {
+        int64_t nc = *cand_cap ? 2 * *cand_cap : 64;
+        int64_t* t = (int64_t*)realloc(*cand, sizeof(int64_t) * nc);
+        if (!t) return -2;
+        *cand = t;
+        *cand_cap = nc;
+      }
+      (*cand)[(*ncand)++] = j;
+    }
+  }
+  return 0;
+}
+
 /* Link-cell search: a uniform grid whose cells are no smaller than the
  * largest possible pair range, so every partner of i lies in the 3x3x3 block
  * of cells around i's cell (wrapped on x, y; clipped on z). */
@@ -92,8 +138,6 @@ int orc_pairs_cells(const orc_params* p, int64_t n, const double* x, const doubl
   int64_t* start = (int64_t*)calloc(ncell + 1, sizeof(int64_t));
   int64_t* members = (int64_t*)malloc(sizeof(int64_t) * n);
   int64_t* fill = (int64_t*)calloc(ncell, sizeof(int64_t));
-  int64_t* cand = NULL;
-  int64_t cand_cap = 0;
   if (!cell_of || !start || !members || !fill) {
     free(cell_of), free(start), free(members), free(fill);
     return -2;
@@ -110,55 +154,86 @@ int orc_pairs_cells(const orc_params* p, int64_t n, const double* x, const doubl
   for (int64_t k = 0; k < ncell; ++k) start[k + 1] += start[k];
   for (int64_t i = 0; i < n; ++i) members[start[cell_of[i]] + fill[cell_of[i]]++] = i;
 
-  int64_t cnt = 0;
-  for (int64_t i = 0; i < n; ++i) {
-    int64_t ci = cell_of[i];
-    int a0 = (int)(ci % cx), b0 = (int)((ci / cx) % cy), c0 = (int)(ci / ((int64_t)cx * cy));
-    /* distinct neighbour cells (small grids would otherwise repeat a cell) */
-    int64_t nb[27];
-    int nnb = 0;
-    for (int dc = -1; dc <= 1; ++dc) {
-      int c = c0 + dc;
-      if (c < 0 || c >= cz) continue;
-      for (int db = -1; db <= 1; ++db) {
-        int b = ((b0 + db) % cy + cy) % cy;
-        for (int da = -1; da <= 1; ++da) {
-          int a = ((a0 + da) % cx + cx) % cx;
-          int64_t k = ((int64_t)c * cy + b) * cx + a;
-          int seen = 0;
-          for (int q = 0; q < nnb; ++q) seen |= (nb[q] == k);
-          if (!seen) nb[nnb++] = k;
+  /* Each thread takes one contiguous block of particles (static schedule)
+   * and lists its pairs, i ascending and each i's partners in ascending j,
+   * in a buffer of its own; the buffers are then joined in thread order,
+   * which is the order of a single pass over all particles. */
+  int nth = 1;
+#ifdef _OPENMP
+  nth = omp_get_max_threads();
+#endif
+  int64_t** buf = (int64_t**)calloc((size_t)nth, sizeof(int64_t*));
+  int64_t* len = (int64_t*)calloc((size_t)nth, sizeof(int64_t));
+  int oom = !buf || !len;
+  if (!oom) {
+#pragma omp parallel num_threads(nth) reduction(| : oom)
+    {
+      int t = 0;
+#ifdef _OPENMP
+      t = omp_get_thread_num();
+#endif
+      int64_t *cand = NULL, *out = NULL;
+      int64_t cand_cap = 0, out_cap = 0, nout = 0;
+#pragma omp for schedule(static)
+      for (int64_t i = 0; i < n; ++i) {
+        if (oom) continue;
+        int64_t ncand = 0;
+        if (partners(p, x, d, cx, cy, cz, cell_of, start, members, i, &cand, &cand_cap, &ncand)) {
+          oom = 1;
+          continue;
         }
-      }
-    }
-    int64_t ncand = 0;
-    for (int q = 0; q < nnb; ++q) {
-      for (int64_t m = start[nb[q]]; m < start[nb[q] + 1]; ++m) {
-        int64_t j = members[m];
-        if (j <= i) continue;
-        if (!in_range(p, x + 3 * i, x + 3 * j, 0.5 * d[i], 0.5 * d[j])) continue;
-        if (ncand == cand_cap) {
-          cand_cap = cand_cap ? 2 * cand_cap : 64;
-          int64_t* t = (int64_t*)realloc(cand, sizeof(int64_t) * cand_cap);
-          if (!t) {
-            free(cand), free(cell_of), free(start), free(members), free(fill);
-            return -2;
+        qsort(cand, (size_t)ncand, sizeof(int64_t), cmp_i64);
+        if (nout + 2 * ncand > out_cap) {
+          int64_t nc = out_cap ? 2 * out_cap : 1024;
+          while (nc < nout + 2 * ncand) nc *= 2;
+          int64_t* tmp = (int64_t*)realloc(out, sizeof(int64_t) * nc);
+          if (!tmp) {
+            oom = 1;
+            continue;
           }
-          cand = t;
+          out = tmp;
+          out_cap = nc;
         }
-        cand[ncand++] = j;
+        for (int64_t q = 0; q < ncand; ++q) {
+          out[nout++] = i;
+          out[nout++] = cand[q];
+        }
       }
-    }
-    qsort(cand, (size_t)ncand, sizeof(int64_t), cmp_i64);
-    for (int64_t q = 0; q < ncand; ++q) {
-      if (cnt < cap) {
-        ij[2 * cnt] = i;
-        ij[2 * cnt + 1] = cand[q];
-      }
-      ++cnt;
+      free(cand);
+      buf[t] = out;
+      len[t] = nout / 2;
     }
   }
-  free(cand), free(cell_of), free(start), free(members), free(fill);
+  int64_t cnt = 0;
+  for (int t = 0; !oom && t < nth; ++t) {
+    for (int64_t q = 0; q < len[t]; ++q, ++cnt)
+      if (cnt < cap) {
+        ij[2 * cnt] = buf[t][2 * q];
+        ij[2 * cnt + 1] = buf[t][2 * q + 1];
+      }
+  }
+  for (int t = 0; buf && t < nth; ++t) free(buf[t]);
+  free(buf), free(len);
+  if (oom) {
+    free(cell_of), free(start), free(members), free(fill);
+    return -2;
+  }
+  free(cell_of), free(start), free(members), free(fill);
   *n_out = cnt;
   return cnt <= cap ? 0 : -1;
+}
+
+void orc_set_threads(int nthreads) {
+#ifdef _OPENMP
+  omp_set_num_threads(nthreads > 0 ? nthreads : 1);
+#else
+  (void)nthreads;
+#endif
+}
+int orc_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

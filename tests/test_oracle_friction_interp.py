@@ -244,7 +244,7 @@ PLANTED = {
         [(F, "cross3(rw, nv, rot);", "rot[0] = rot[1] = rot[2] = 0.0;")],
         [check_rigid_rotation]),
     "r_i used for the torque on j": (
-        [(F, "add3(o.torque, j, tq, rj);", "add3(o.torque, j, tq, ri);")],
+        [(F, "add3(o.torque, j, r->tq, 0.5 * d[j]);", "add3(o.torque, j, r->tq, 0.5 * d[i]);")],
         [check_rigid_rotation, check_oblique_impact]),
     "history not rotated into the current tangent plane": (
         [(F, "xi[k] = xp[k] + vt[k] * p->dt;", "xi[k] = xi[k] + vt[k] * p->dt;")],
@@ -254,7 +254,7 @@ PLANTED = {
     "no Coulomb cap": (
         [(F, "if (fm > cap) {", "if (0 && fm > cap) {")], [check_oblique_impact]),
     "opposite torque sense on j": (
-        [(F, "add3(o.torque, j, tq, rj);", "add3(o.torque, j, tq, -rj);")],
+        [(F, "add3(o.torque, j, r->tq, 0.5 * d[j]);", "add3(o.torque, j, r->tq, -0.5 * d[j]);")],
         [check_rigid_rotation, check_oblique_impact]),
     "x cell-centre offset dropped": (
         [(F, "double sx = xp[0] / hx - 0.5,", "double sx = xp[0] / hx,")],
