@@ -304,17 +304,25 @@ int sedimi_get_state(sedimi_ctx* ctx, void* buf, size_t cap, size_t* size_out);
 int sedimi_set_state(sedimi_ctx* ctx, const void* buf, size_t size);
 int sedimi_get_forces(sedimi_ctx* ctx, int component, double* f);
 int sedimi_get_field(sedimi_ctx* ctx, int field, double* out);
-/* Current contact-pair set (centre distance below contact distance plus the
- * lubrication cut-off), as (i, j) ID pairs with i < j in ascending order.
- * *n_out receives the count; returns EOVERFLOW if it exceeds cap. */
+/* Current pair set (Section 2.5: particles interact, by contact or by
+ * lubrication, when the centre distance is below the contact distance plus
+ * the lubrication cut-off), as (i, j) ID pairs with i < j in ascending order,
+ * host int64 [cap][2].  *n_out receives the count; returns EOVERFLOW if it
+ * exceeds cap (nothing beyond cap is written). */
 int sedimi_get_pairs(sedimi_ctx* ctx, int64_t cap, int64_t* ij, int64_t* n_out);
-/* Tangential contact history as records {int64 i, int64 j, double xi[3]}:
+/* Tangential contact history (the tangential spring of the soft-sphere
+ * contact model, Section 2.1) as records {int64 i, int64 j, double xi[3]}:
  * i < j particle IDs, or j = -1 (wall z = 0) / -2 (wall z = Lz); xi is the
- * spring displacement of i relative to j.  get: sorted by (i, j); set:
- * replaces the whole history (any order; pairs must be in the current
- * neighbour list). */
+ * spring displacement of i relative to j.  get: sorted by (i, j), host
+ * records [cap], *n_out the count, EOVERFLOW beyond cap; set: replaces the
+ * whole history (any order; pairs must be in the current neighbour list,
+ * else EINVAL).  Both synchronise the stream. */
 int sedimi_get_history(sedimi_ctx* ctx, int64_t cap, void* records, int64_t* n_out);
 int sedimi_set_history(sedimi_ctx* ctx, int64_t n, const void* records);
+/* Counters of the run (host struct, filled whole): steps, neighbour-list
+ * rebuilds and the list statistics of the link-cell search (Section 2.5), the
+ * iterations and residual of the last diffusion solve (Eq. 12, Section 2.4),
+ * and the network's calls, fallbacks and check window.  Synchronises. */
 int sedimi_get_stats(sedimi_ctx* ctx, sedimi_stats* out);
 /* Averaging mode used by sedimi_average and by the averaging inside
  * sedimi_step (SEDIMI_AVG_*; the surrogate modes need nn_enable). */
@@ -355,6 +363,17 @@ int sedimi_nn_param_count(const sedimi_ctx* ctx, int64_t* n);
 int sedimi_nn_init(sedimi_ctx* ctx, uint64_t seed);
 int sedimi_nn_set_params(sedimi_ctx* ctx, const float* p, int64_t n);
 int sedimi_nn_get_params(sedimi_ctx* ctx, float* p, int64_t n);
+/* The trained network as one host blob, so that training resumes exactly: a
+ * header (magic, parameter count, leaky-ReLU slope, Adam step count, the
+ * per-channel standardisation and loss weights) followed by the FP32
+ * parameters and Adam's first and second moments (3 x count floats).
+ * save: *size_out receives the blob size; the blob is written only if buf is
+ * non-NULL and cap >= that size, else ENOMEM when buf is non-NULL.
+ * load: EINVAL if the blob is malformed, its parameter count differs or its
+ * slope differs from the context's nn_alpha.  Both synchronise the stream;
+ * the buffer is the caller's. */
+int sedimi_nn_save(sedimi_ctx* ctx, void* buf, size_t cap, size_t* size_out);
+int sedimi_nn_load(sedimi_ctx* ctx, const void* buf, size_t size);
 /* Gradient of the loss from the last sedimi_nn_train_step (same layout). */
 int sedimi_nn_get_grads(sedimi_ctx* ctx, float* g, int64_t n);
 /* Per-channel normalisation x_n = (x - mean) / std of inputs and targets. */

@@ -132,6 +132,8 @@ def lib():
         L.sedimi_nn_set_norm.argtypes = [P, P, P]
         L.sedimi_nn_forward.argtypes = [P]
         L.sedimi_nn_set_loss_weights.argtypes = [P, P]
+        L.sedimi_nn_save.argtypes = [P, P, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.sedimi_nn_load.argtypes = [P, P, C.c_size_t]
         L.sedimi_nn_train_step.argtypes = [P, C.c_double, C.POINTER(C.c_double)]
         L.sedimi_nn_check.argtypes = [P, P]
         L.sedimi_nn_get_tensor.argtypes = [P, I, I, P, i64]
@@ -350,6 +352,18 @@ class Sedimi:
         p = np.zeros(self.nn_param_count(), np.float32)
         self._chk(self._L.sedimi_nn_get_params(self._ctx, _ptr(p), len(p)))
         return p
+
+    def nn_save(self):
+        """The trained network (parameters, Adam moments and step, standardisation,
+        loss weights) as bytes."""
+        size = C.c_size_t(0)
+        self._chk(self._L.sedimi_nn_save(self._ctx, None, 0, C.byref(size)))
+        buf = C.create_string_buffer(size.value)
+        self._chk(self._L.sedimi_nn_save(self._ctx, buf, size.value, C.byref(size)))
+        return buf.raw
+
+    def nn_load(self, blob):
+        self._chk(self._L.sedimi_nn_load(self._ctx, blob, len(blob)))
 
     def nn_get_grads(self):
         g = np.zeros(self.nn_param_count(), np.float32)

@@ -69,42 +69,80 @@ __global__ void k_cellscatter(DevParams P, DevArrays A) {
 }
 
 // One lane per cell: order the members by particle ID (the high half of each
-// (ID, index) key), then sum in that order.
+// (ID, index) key), then sum in that order.  A cell of up to kSortRegs
+// members is sorted in registers by a bitonic network (padded with keys above
+// every real one) and written back; a larger one by insertion in place.
+constexpr int kSortRegs = 32;
+
+__device__ __forceinline__ void cell_add(const DevArrays& A, int q, bool flux, double& v,
+                                         double& fx, double& fy, double& fz, double& qx,
+                                         double& qy, double& qz) {
+#pragma clang fp contract(off)
+  const double d = 2.0 * A.pos[q].w;
+  const double V = (kPi / 6.0) * d * d * d;
+  v += V;
+  const double4 f = A.fdr[q];
+  fx += f.x;
+  fy += f.y;
+  fz += f.z;
+  if (flux) {
+    const double4 u = A.vel[q];
+    qx += V * u.x;
+    qy += V * u.y;
+    qz += V * u.z;
+  }
+}
+
 __global__ void k_cellsum(DevParams P, DevArrays A) {
 #pragma clang fp contract(off)
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= P.ncell) return;
-  int s = A.cell_start[c], e = A.cell_start[c + 1];
-  // a crowded cell is summed unsorted (order not reproducible) and flagged
-  const bool sorted = e - s <= kMaxCellMembers;
-  if (!sorted) atomicOr(&A.ctl->flags, kFlagCrowded);
-  for (int i = s + 1; sorted && i < e; ++i) {
-    const unsigned long long key = A.cperm[i];
-    int j = i - 1;
-    while (j >= s && A.cperm[j] > key) {
-      A.cperm[j + 1] = A.cperm[j];
-      --j;
-    }
-    A.cperm[j + 1] = key;
-  }
+  const int s = A.cell_start[c], e = A.cell_start[c + 1], m = e - s;
   const bool flux = P.nch_avg == 7;
   double v = 0.0, fx = 0.0, fy = 0.0, fz = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
-  for (int i = s; i < e; ++i) {
-    const int q = (int)(unsigned)(A.cperm[i] & 0xffffffffull);
-    double d = 2.0 * A.pos[q].w;
-    double V = (kPi / 6.0) * d * d * d;
-    v += V;
-    double4 f = A.fdr[q];
-    fx += f.x;
-    fy += f.y;
-    fz += f.z;
-    if (flux) {
-      const double4 u = A.vel[q];
-      qx += V * u.x;
-      qy += V * u.y;
-      qz += V * u.z;
+  if (m > 0 && m <= kSortRegs) {
+    // unconditional loads (clamped to the last member), padded after it
+    unsigned long long key[kSortRegs];
+#pragma unroll
+    for (int t = 0; t < kSortRegs; ++t) {
+      const unsigned long long k = A.cperm[s + (t < m ? t : m - 1)];
+      key[t] = t < m ? k : ~0ull;
+    }
+#pragma unroll
+    for (int k = 2; k <= kSortRegs; k <<= 1)
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+        for (int i = 0; i < kSortRegs; ++i) {
+          const int l = i ^ j;
+          if (l > i) {
+            const unsigned long long a = key[i], b = key[l];
+            const bool swap = (i & k) == 0 ? a > b : a < b;
+            key[i] = swap ? b : a;
+            key[l] = swap ? a : b;
+          }
+        }
+#pragma unroll
+    for (int t = 0; t < kSortRegs; ++t)
+      if (t < m) A.cperm[s + t] = key[t];
+  } else if (m > kSortRegs) {
+    // a crowded cell is summed unsorted (order not reproducible) and flagged
+    const bool sorted = m <= kMaxCellMembers;
+    if (!sorted) atomicOr(&A.ctl->flags, kFlagCrowded);
+    for (int i = s + 1; sorted && i < e; ++i) {
+      const unsigned long long key = A.cperm[i];
+      int j = i - 1;
+      while (j >= s && A.cperm[j] > key) {
+        A.cperm[j + 1] = A.cperm[j];
+        --j;
+      }
+      A.cperm[j + 1] = key;
     }
   }
+  // the members in ID order
+#pragma unroll 4
+  for (int i = s; i < e; ++i)
+    cell_add(A, (int)(unsigned)(A.cperm[i] & 0xffffffffull), flux, v, fx, fy, fz, qx, qy, qz);
   const size_t nc = (size_t)P.ncell;
   // each cell divides by its own volume (one per plane on a graded mesh)
   const double Vc = P.graded ? A.zgeo[zgeo_volumes(P.nz) + c / (P.nx * P.ny)] : P.Vc;

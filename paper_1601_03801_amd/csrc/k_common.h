@@ -66,7 +66,9 @@ __device__ __forceinline__ void kick_drift_one(const DevParams& P, const DevArra
   const double4 b = A.xb[q];
   const double dx = min_image(x.x - b.x, P.Lx, P.hLx), dy = min_image(x.y - b.y, P.Ly, P.hLy),
                dz = x.z - b.z;
-  if (dx * dx + dy * dy + dz * dz > P.half_skin2) atomicOr(rb, 1);
+  // many particles can cross the half skin in one step: one atomic per wave
+  const unsigned long long over = __ballot(dx * dx + dy * dy + dz * dz > P.half_skin2);
+  if (over && __lane_id() == __ffsll((long long)over) - 1) atomicOr(rb, 1);
 }
 
 // Cell of height z on a graded mesh with faces zf[0..nz]: the k with

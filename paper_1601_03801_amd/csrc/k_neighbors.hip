@@ -69,22 +69,46 @@ __device__ __forceinline__ void compact_one(const DevParams& P, const DevArrays&
 }
 
 // Bin key of particle p (bins in Morton order) and its rank among the bin's
-// members.
-__device__ __forceinline__ void keys_one(const DevParams& P, const DevArrays& A, int p) {
-  double4 x = A.pos[p];
-  int b = A.bin_rank[bin_of(P, x.x, x.y, x.z)];
-  A.key[p] = b;
-  A.rank[p] = atomicAdd(&A.bin_count[b], 1);
+// members (any order: k_binsort orders each bin by ID).  Particles still in
+// the last sorted order mostly share a bin with their wave neighbours: each
+// group of lanes with one bin takes its ranks with a single atomic add.
+// Every lane of the wave calls this (valid says whether p is a particle).
+__device__ __forceinline__ void keys_one(const DevParams& P, const DevArrays& A, int p,
+                                         bool valid) {
+  int b = -1;
+  if (valid) {
+    const double4 x = A.pos[p];
+    b = A.bin_rank[bin_of(P, x.x, x.y, x.z)];
+    A.key[p] = b;
+  }
+  unsigned long long active = __ballot(valid);
+  const int lane = __lane_id();
+  int rank = 0;
+  while (active) {
+    const int leader = __ffsll((long long)active) - 1;
+    const int bl = __shfl(b, leader);
+    const unsigned long long grp = __ballot(b == bl) & active;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&A.bin_count[bl], (int)__popcll(grp));
+    base = __shfl(base, leader);
+    if ((grp >> lane) & 1ull) rank = base + (int)__popcll(grp & ((1ull << lane) - 1ull));
+    active &= ~grp;
+  }
+  if (valid) A.rank[p] = rank;
 }
 
 // First kernel of a rebuild: history rows (when the list slots carry
-// history) and bin keys, one pass over the particles.
+// history) and bin keys, one pass over the particles.  The loop runs while
+// any lane of the block has a particle, so whole waves reach keys_one.
 template <typename H, bool SLOTS>
 __global__ void k_compact_keys(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P.n; p += gridDim.x * blockDim.x) {
-    if (SLOTS) compact_one<H>(P, A, p);
-    keys_one(P, A, p);
+  const int stride = gridDim.x * blockDim.x;
+  for (int p0 = blockIdx.x * blockDim.x; p0 < P.n; p0 += stride) {
+    const int p = p0 + threadIdx.x;
+    const bool valid = p < P.n;
+    if (SLOTS && valid) compact_one<H>(P, A, p);
+    keys_one(P, A, p, valid);
   }
 }
 
@@ -162,99 +186,114 @@ __global__ void k_copyback(DevParams P, DevArrays A) {
 // within a class.  The force kernel walks the slots of a wave's particles in
 // lockstep and runs the contact and lubrication code for a slot when any lane
 // needs it, so putting each list's contacts first about halves the slots
-// that run the contact code (and touch the tangential history).  Two passes
-// over the bins: the first counts each class, the second places.  Then the
-// history rows of q's pre-sort slot are matched onto the new slots by
-// partner ID.
+// that run the contact code (and touch the tangential history).
+// One pass over the bins, a row of three (consecutive x) at a time: a row's
+// member ranges are loaded together (two memory round trips per row, not per
+// bin), then its candidates are tested in bin-scan order and parked with
+// their class in the lane's row of LDS.  The list is then written class by
+// class, and each slot's tangential history is matched by partner ID against
+// the contact rows of q's pre-sort position, whose IDs are held in
+// registers.
+constexpr int kBuildStride = 31;  // LDS row of a lane: >= max_neighbors, odd (no bank conflicts)
+static_assert(kBuildStride >= 30, "a lane's LDS row must hold max_neighbors (<= 30) slots");
 template <typename H>
-__global__ void k_build(DevParams P, DevArrays A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_build(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
+  __shared__ int park[kBlock * kBuildStride];
+  int* row = park + threadIdx.x * kBuildStride;
+  int most = 0;  // the lane's largest list
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < P.n;
        q += gridDim.x * blockDim.x) {
     const int N = P.n;
     const double4 xi = A.pos[q];
     const int bx = bin_coord(xi.x, P.hbx, P.nbx), by = bin_coord(xi.y, P.hby, P.nby),
               bz = bin_coord(xi.z, P.hbz, P.nbz);
-    // pass 0 counts the candidates of each class, pass 1 places them; a pass
-    // stops once more than maxn candidates have been seen (the list has
-    // overflowed), at the same candidate in both
-    int n0 = 0, n1 = 0, cnt = 0, w0 = 0, w1 = 0, w2 = 0;
+    const int cxm = bx == 0 ? P.nbx - 1 : bx - 1, cxp = bx + 1 == P.nbx ? 0 : bx + 1;
+    // the scan tests every candidate (no early stop, so consecutive
+    // candidates' loads do not wait on each other); the first maxn are kept
+    // and more than maxn overflow the list
+    int seen = 0;
+    unsigned long long cls = 0;  // 2 bits of class per kept candidate
 #pragma unroll 1
-    for (int pass = 0; pass < 2; ++pass) {
-      int seen = 0;
-#pragma unroll 1
-      for (int dz = -1; dz <= 1; ++dz) {
-        const int cz = bz + dz;
-        if (cz < 0 || cz >= P.nbz) continue;
-#pragma unroll 1
-        for (int dy = -1; dy <= 1; ++dy) {
-          int cy = by + dy;
-          cy = cy < 0 ? cy + P.nby : (cy >= P.nby ? cy - P.nby : cy);
-#pragma unroll 1
-          for (int dx = -1; dx <= 1; ++dx) {
-            int cx = bx + dx;
-            cx = cx < 0 ? cx + P.nbx : (cx >= P.nbx ? cx - P.nbx : cx);
-            const int b = A.bin_rank[(cz * P.nby + cy) * P.nbx + cx];
-            const int s = A.bin_start[b], e = A.bin_start[b + 1];
-            if (e - s > kMaxBinMembers) continue;  // flagged by k_binsort
-            for (int j = s; j < e && seen <= P.maxn; ++j) {
-              if (j == q) continue;
-              const double4 xj = A.pos[j];
-              const double ddx = min_image(xj.x - xi.x, P.Lx, P.hLx);
-              const double ddy = min_image(xj.y - xi.y, P.Ly, P.hLy);
-              const double ddz = xj.z - xi.z;
-              const double s2 = ddx * ddx + ddy * ddy + ddz * ddz;
-              const double rs = xi.w + xj.w;
-              const double Rl = rs + P.lub_out * rs + P.skin;
-              if (!(s2 < Rl * Rl * (1.0 + 1e-9))) continue;
-              const double Rp = rs + P.lub_out * rs;
-              const int c = s2 < rs * rs ? 0 : (s2 < Rp * Rp ? 1 : 2);
-              if (pass == 0) {
-                n0 += c == 0;
-                n1 += c == 1;
-                ++cnt;
-              } else {
-                const int w = c == 0 ? w0 : (c == 1 ? w1 : w2);
-                if (w < P.maxn) A.nbr[(size_t)w * N + q] = j;
-                w0 += c == 0;
-                w1 += c == 1;
-                w2 += c == 2;
-              }
-              ++seen;
-            }
+    for (int r = 0; r < 9; ++r) {
+      const int cz = bz + r / 3 - 1;
+      if (cz < 0 || cz >= P.nbz) continue;
+      int cy = by + r % 3 - 1;
+      cy = cy < 0 ? cy + P.nby : (cy >= P.nby ? cy - P.nby : cy);
+      const int base = (cz * P.nby + cy) * P.nbx;
+      int bs[3], be[3];
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int bin = A.bin_rank[base + (t == 0 ? cxm : (t == 1 ? bx : cxp))];
+        bs[t] = A.bin_start[bin];
+        be[t] = A.bin_start[bin + 1];
+        if (be[t] - bs[t] > kMaxBinMembers) be[t] = bs[t];  // flagged by k_binsort
+      }
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+#pragma unroll 4
+        for (int j = bs[t]; j < be[t]; ++j) {
+          if (j == q) continue;
+          const double4 xj = A.pos[j];
+          const double ddx = min_image(xj.x - xi.x, P.Lx, P.hLx);
+          const double ddy = min_image(xj.y - xi.y, P.Ly, P.hLy);
+          const double ddz = xj.z - xi.z;
+          const double s2 = ddx * ddx + ddy * ddy + ddz * ddz;
+          const double rs = xi.w + xj.w;
+          const double Rl = rs + P.lub_out * rs + P.skin;
+          if (!(s2 < Rl * Rl * (1.0 + 1e-9))) continue;
+          const double Rp = rs + P.lub_out * rs;
+          const unsigned long long c = s2 < rs * rs ? 0 : (s2 < Rp * Rp ? 1 : 2);
+          if (seen < P.maxn) {
+            row[seen] = j;
+            cls |= c << (2 * seen);
           }
+          ++seen;
         }
       }
-      w1 = n0;
-      w2 = n0 + n1;
     }
+    int cnt = seen;
     if (cnt > P.maxn) {
       atomicOr(&A.ctl->flags, kFlagOverflow);
       cnt = P.maxn;
     }
-    atomicMax(&A.ctl->max_nbr, cnt);
+    most = cnt > most ? cnt : most;
     A.ncnt[q] = cnt;
     A.xb[q] = xi;
-    // history: rows of the pre-sort position perm[q]
-    int p = A.perm[q];
-    int nc = A.ccnt[p];
-    unsigned mask = 0;
-    int matched = 0;
+    // contact rows of the pre-sort position perm[q]: partner IDs in registers
+    const int p = A.perm[q];
+    const int nc = A.ccnt[p];
+    int cid[kMaxContacts];
+#pragma unroll
+    for (int c = 0; c < kMaxContacts; ++c) cid[c] = c < nc ? A.cid[(size_t)c * N + p] : -1;
     H* hx = (H*)A.hxi;
     H* hy = hx + (size_t)P.maxn * N;
     H* hz = hy + (size_t)P.maxn * N;
-    if (nc > 0) {
-      for (int k = 0; k < cnt; ++k) {
-        int pid = A.id[A.nbr[(size_t)k * N + q]];
-        for (int c = 0; c < nc; ++c) {
-          if (A.cid[(size_t)c * N + p] == pid) {
-            hx[(size_t)k * N + q] = (H)A.cxi[((size_t)0 * kMaxContacts + c) * N + p];
-            hy[(size_t)k * N + q] = (H)A.cxi[((size_t)1 * kMaxContacts + c) * N + p];
-            hz[(size_t)k * N + q] = (H)A.cxi[((size_t)2 * kMaxContacts + c) * N + p];
-            mask |= 1u << k;
-            ++matched;
-            break;
-          }
+    unsigned mask = 0;
+    int matched = 0;
+    int w0 = 0, w1 = 0, w2 = 0;
+    for (int k = 0; k < cnt; ++k) {
+      const int c = (int)((cls >> (2 * k)) & 3ull);
+      w1 += c == 0;
+      w2 += c != 2;
+    }
+#pragma unroll 2
+    for (int k = 0; k < cnt; ++k) {
+      const int c = (int)((cls >> (2 * k)) & 3ull);
+      const int w = c == 0 ? w0++ : (c == 1 ? w1++ : w2++);
+      const int j = row[k];
+      A.nbr[(size_t)w * N + q] = j;
+      if (nc > 0) {
+        const int pid = A.id[j];
+        int hit = -1;  // partner IDs in a list are distinct: at most one row matches
+#pragma unroll
+        for (int r = 0; r < kMaxContacts; ++r) hit = cid[r] == pid ? r : hit;
+        if (hit >= 0) {
+          hx[(size_t)w * N + q] = (H)A.cxi[((size_t)0 * kMaxContacts + hit) * N + p];
+          hy[(size_t)w * N + q] = (H)A.cxi[((size_t)1 * kMaxContacts + hit) * N + p];
+          hz[(size_t)w * N + q] = (H)A.cxi[((size_t)2 * kMaxContacts + hit) * N + p];
+          mask |= 1u << w;
+          ++matched;
         }
       }
     }
@@ -263,6 +302,13 @@ __global__ void k_build(DevParams P, DevArrays A) {
     A.hmask[q] = mask;
     if (matched != nc) atomicOr(&A.ctl->flags, kFlagLost);
   }
+  // the largest list: one atomic per wave, not per particle (all lanes of
+  // the wave are back together here)
+  for (int o = 32; o > 0; o >>= 1) {
+    const int other = __shfl_xor(most, o, 64);
+    most = other > most ? other : most;
+  }
+  if ((threadIdx.x & 63) == 0 && most > 0) atomicMax(&A.ctl->max_nbr, most);
 }
 
 // ---- exclusive scan of int counts (2 passes, 1024 items per block) ----
@@ -425,10 +471,12 @@ void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixe
   hipLaunchKernelGGL(k_binsort, dim3(gated_grid(P.nbins)), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_permute, dim3(g), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_copyback, dim3(g), dim3(kBlock), 0, s, P, A);
+  // the list build is latency bound: every particle gets its own lane
+  const unsigned gb = nblk(P.n) < 8192 ? nblk(P.n) : 8192;
   if (mixed)
-    hipLaunchKernelGGL(k_build<float>, dim3(g), dim3(kBlock), 0, s, P, A);
+    hipLaunchKernelGGL(k_build<float>, dim3(gb), dim3(kBlock), 0, s, P, A);
   else
-    hipLaunchKernelGGL(k_build<double>, dim3(g), dim3(kBlock), 0, s, P, A);
+    hipLaunchKernelGGL(k_build<double>, dim3(gb), dim3(kBlock), 0, s, P, A);
 }
 
 }  // namespace sedimi

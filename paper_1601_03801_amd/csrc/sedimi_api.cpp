@@ -1751,6 +1751,67 @@ int sedimi_nn_get_params(sedimi_ctx* c, float* p, int64_t n) {
   return SEDIMI_OK;
 }
 
+struct NNSaveHeader {
+  char magic[8];
+  int64_t count, adam_t;
+  double alpha;
+  double mean[4], std[4], lw[4];
+};
+constexpr char kNNMagic[8] = {'S', 'E', 'D', 'I', 'N', 'N', '0', '1'};
+
+int sedimi_nn_save(sedimi_ctx* c, void* buf, size_t cap, size_t* size_out) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  const int64_t P = nn_count();
+  const size_t total = sizeof(NNSaveHeader) + 3 * sizeof(float) * (size_t)P;
+  if (size_out) *size_out = total;
+  if (!buf) return SEDIMI_OK;
+  if (cap < total) return fail(c, SEDIMI_ENOMEM, "network blob buffer too small");
+  NNSaveHeader h;
+  memset(&h, 0, sizeof(h));
+  memcpy(h.magic, kNNMagic, sizeof(h.magic));
+  h.count = P, h.adam_t = c->adam_t, h.alpha = c->prm.nn_alpha;
+  for (int k = 0; k < 4; ++k)
+    h.mean[k] = c->norm.mean[k], h.std[k] = c->norm.std[k], h.lw[k] = c->norm.lw[k];
+  memcpy(buf, &h, sizeof(h));
+  float* body = reinterpret_cast<float*>(static_cast<char*>(buf) + sizeof(h));
+  const float* src[3] = {c->nn.w, c->nn.m, c->nn.v};
+  for (int a = 0; a < 3; ++a)
+    HIPCHK(c, hipMemcpyAsync(body + (size_t)a * P, src[a], sizeof(float) * P,
+                             hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
+int sedimi_nn_load(sedimi_ctx* c, const void* buf, size_t size) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  const int64_t P = nn_count();
+  NNSaveHeader h;
+  if (!buf || size < sizeof(h)) return fail(c, SEDIMI_EINVAL, "network blob too short");
+  memcpy(&h, buf, sizeof(h));
+  if (memcmp(h.magic, kNNMagic, sizeof(h.magic)) != 0 || h.count != P ||
+      size != sizeof(h) + 3 * sizeof(float) * (size_t)P || h.adam_t < 0)
+    return fail(c, SEDIMI_EINVAL, "not a network blob of this architecture");
+  if (h.alpha != c->prm.nn_alpha)
+    return fail(c, SEDIMI_EINVAL, "network blob trained with another leaky-ReLU slope");
+  for (int k = 0; k < 4; ++k)
+    if (!(h.std[k] > 0) || !std::isfinite(h.mean[k]) || !(h.lw[k] >= 0))
+      return fail(c, SEDIMI_EINVAL, "network blob with an invalid standardisation");
+  const float* body = reinterpret_cast<const float*>(static_cast<const char*>(buf) + sizeof(h));
+  rc = sedimi_nn_set_params(c, body, P);  // parameters, packed copies; zeroes the moments
+  if (rc) return rc;
+  HIPCHK(c, hipMemcpyAsync(c->nn.m, body + (size_t)P, sizeof(float) * P, hipMemcpyHostToDevice,
+                           c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->nn.v, body + 2 * (size_t)P, sizeof(float) * P,
+                           hipMemcpyHostToDevice, c->stream));
+  c->adam_t = h.adam_t;
+  for (int k = 0; k < 4; ++k)
+    c->norm.mean[k] = h.mean[k], c->norm.std[k] = h.std[k], c->norm.lw[k] = h.lw[k];
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return SEDIMI_OK;
+}
+
 int sedimi_nn_get_grads(sedimi_ctx* c, float* g, int64_t n) {
   int rc = need_nn(c);
   if (rc) return rc;

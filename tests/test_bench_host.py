@@ -22,10 +22,15 @@ def test_averaging_roofline_bytes_and_flops():
     n, ncell, mesh = 1000, 64, (4, 4, 4)
     dep, sol = bench.averaging_rooflines(n, ncell, 1.0, 1.0, True, mesh)
     assert dep["bytes"] == 88 * n + 32 * ncell
-    assert sol["gflop"] == round(4 * 12 * ncell * 4 / 1e9, 3)
+    # the solve against its algorithmic minimum (read raw, write smooth)
+    assert sol["bound"] == "hbm" and sol["bytes"] == 16 * ncell * 4
+    assert sol["frac"] == round(16 * ncell * 4 / 1e-3 / 1e9 / bench.HBM_PEAK_GBS, 4)
+    assert sol["transforms"]["gflop"] == round(4 * 12 * ncell * 4 / 1e9, 3)
     dep7, sol7 = bench.averaging_rooflines(n, ncell, 1.0, 1.0, True, mesh, nch=7)
     assert dep7["bytes"] == 120 * n + 56 * ncell
-    assert sol7["gflop"] == round(4 * 12 * ncell * 7 / 1e9, 3)
+    assert sol7["transforms"]["gflop"] == round(4 * 12 * ncell * 7 / 1e9, 3)
+    _, it = bench.averaging_rooflines(n, ncell, 1.0, 1.0, False, mesh)
+    assert "transforms" not in it and it["bound"] == "hbm"
     big = 10 ** 8  # large enough for the rounded HBM minimum
     _, s4 = bench.averaging_rooflines(n, big, 1.0, 1.0, True, mesh)
     _, s7 = bench.averaging_rooflines(n, big, 1.0, 1.0, True, mesh, nch=7)

@@ -158,3 +158,40 @@ def test_check_estimates_the_error_against_the_plain_solve(bz):
         full = np.linalg.norm(y - plain, axis=1) / np.linalg.norm(plain, axis=1)
         print("check estimate", est, "full-field error", full)
         assert np.all(np.abs(est - full) < 0.2 * full + floor), (est, full)
+
+
+def test_save_load_resumes_training_exactly():
+    """sedimi_nn_save / sedimi_nn_load carry the parameters, Adam's moments
+    and step, the standardisation and the loss weights: a context loaded
+    from a blob takes the same next training step, bit for bit, as the one
+    that saved it; blobs of another slope or truncated ones are refused."""
+    shape = (16, 12, 10)
+    n = int(np.prod(shape))
+    rng = np.random.default_rng(8)
+    raws = [rng.random((4, n)) ** 3 for _ in range(3)]
+    a, _ = mesh_ctx(shape)
+    a.nn_init(5)
+    a.nn_set_norm(np.zeros(4), np.array([0.3, 0.2, 0.25, 0.1]))
+    a.nn_set_loss_weights(np.array([1.0, 0.5, 2.0, 1.5]))
+    for r in raws[:2]:
+        a.set_field(0, r)
+        a.smooth(4)
+        a.nn_train_step(1e-3)
+    blob = a.nn_save()
+    b, _ = mesh_ctx(shape)
+    b.nn_load(blob)
+    for g in (a, b):
+        g.set_field(0, raws[2])
+        g.smooth(4)
+        g.nn_train_step(1e-3)
+    assert np.array_equal(a.nn_get_params(), b.nn_get_params())
+    assert np.array_equal(a.nn_save(), b.nn_save())
+    import paper_1601_03801_amd as sm
+    c, _ = mesh_ctx(shape)
+    with pytest.raises(sm.SedimiError):
+        c.nn_load(blob[:-4])
+    nx, ny, nz = shape
+    prm = workloads.base_params(Lx=nx * 1e-3, Ly=ny * 1e-3, Lz=nz * 0.4e-3, nx=nx, ny=ny, nz=nz)
+    other = sm.Sedimi(prm, 1, d_max=0.5e-3, nn=True, nn_alpha=0.5)
+    with pytest.raises(sm.SedimiError):
+        other.nn_load(blob)
