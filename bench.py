@@ -31,16 +31,16 @@ FP64_MFMA_PEAK_TFLOPS = 78.6
 
 
 def averaging_rooflines(n, ncell, dep_ms, smooth_ms, direct, mesh, nch=4):
-    """Deposition against HBM: algorithmic bytes 88 B per particle (cell key
-    32 B read + 8 B written, 8 B scatter, 40 B read by the per-cell sums)
-    plus 8 B per cell and channel written; with the solid volume flux (7
-    channels) the per-cell sums also read the velocity, 32 B per particle.
+    """Deposition against HBM: the method's algorithmic bytes, 60 B per
+    particle (position and radius 32 B, drag 24 B, ID 4 B) plus 8 B per cell
+    and channel written; with the solid volume flux (7 channels) also the
+    velocity, 24 B per particle.
     The plain solve against the method's algorithmic minimum: read raw and
     write smooth, 16 B per cell and channel, at HBM peak.  The direct solve's
     own work, a forward and an inverse transform along each axis (4 (nx + ny
     + nz) FLOP per cell and channel on the FP64 matrix cores), is given
     beside it.  The solve time includes its full-field residual check."""
-    dep_bytes = (88 + (32 if nch == 7 else 0)) * n + 8 * nch * ncell
+    dep_bytes = (60 + (24 if nch == 7 else 0)) * n + 8 * nch * ncell
     dep = {"ms": round(dep_ms, 5), "bytes": int(dep_bytes), "bound": "hbm",
            "achieved_GBps": round(dep_bytes / (dep_ms * 1e-3) / 1e9, 1),
            "frac": round(dep_bytes / (dep_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -67,8 +67,8 @@ def averaging_rooflines(n, ncell, dep_ms, smooth_ms, direct, mesh, nch=4):
 # written).  Valid only for the kernel sources it was measured on.
 FORCE_PMC = {
     ("bed1m", "fp64"): {
-        "fetch_kib": 315359.3, "write_kib": 281002.4, "fetch_scale": 2.0, "write_scale": 1.0,
-        "sources_sha256": "901ce0a353829f77b4c70bc03f82b7afdf7191770ed62079b28290157fb1f419",
+        "fetch_kib": 314508.6, "write_kib": 277639.0, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sources_sha256": "a333f234bd7a78cf649bca53c781997721c48ab3f736a7af29c66519eab03a78",
         "profile": "profiles/k_forces_bed1m_fp64.md"},
 }
 FORCE_SOURCES = ("k_forces.hip", "k_common.h", "sedimi_internal.h")

@@ -202,7 +202,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   __shared__ int park[kBlock * kBuildStride];
   int* row = park + threadIdx.x * kBuildStride;
   int most = 0;  // the lane's largest list
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < P.n;
+  // each XCD works through one contiguous range of particles, whose
+  // neighbours' positions then stay in that XCD's L2
+  for (int q = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; q < P.n;
        q += gridDim.x * blockDim.x) {
     const int N = P.n;
     const double4 xi = A.pos[q];
@@ -471,8 +473,9 @@ void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixe
   hipLaunchKernelGGL(k_binsort, dim3(gated_grid(P.nbins)), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_permute, dim3(g), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_copyback, dim3(g), dim3(kBlock), 0, s, P, A);
-  // the list build is latency bound: every particle gets its own lane
-  const unsigned gb = nblk(P.n) < 8192 ? nblk(P.n) : 8192;
+  // the list build is latency bound: every particle gets its own lane (the
+  // grid a multiple of the XCD count for the block renumbering)
+  const unsigned gb = xcd_grid(nblk(P.n) < 8192 ? nblk(P.n) : 8192);
   if (mixed)
     hipLaunchKernelGGL(k_build<float>, dim3(gb), dim3(kBlock), 0, s, P, A);
   else

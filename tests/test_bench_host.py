@@ -21,13 +21,13 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_averaging_roofline_bytes_and_flops():
     n, ncell, mesh = 1000, 64, (4, 4, 4)
     dep, sol = bench.averaging_rooflines(n, ncell, 1.0, 1.0, True, mesh)
-    assert dep["bytes"] == 88 * n + 32 * ncell
+    assert dep["bytes"] == 60 * n + 32 * ncell
     # the solve against its algorithmic minimum (read raw, write smooth)
     assert sol["bound"] == "hbm" and sol["bytes"] == 16 * ncell * 4
     assert sol["frac"] == round(16 * ncell * 4 / 1e-3 / 1e9 / bench.HBM_PEAK_GBS, 4)
     assert sol["transforms"]["gflop"] == round(4 * 12 * ncell * 4 / 1e9, 3)
     dep7, sol7 = bench.averaging_rooflines(n, ncell, 1.0, 1.0, True, mesh, nch=7)
-    assert dep7["bytes"] == 120 * n + 56 * ncell
+    assert dep7["bytes"] == 84 * n + 56 * ncell
     assert sol7["transforms"]["gflop"] == round(4 * 12 * ncell * 7 / 1e9, 3)
     _, it = bench.averaging_rooflines(n, ncell, 1.0, 1.0, False, mesh)
     assert "transforms" not in it and it["bound"] == "hbm"
