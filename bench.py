@@ -139,6 +139,10 @@ def main():
                     help="only run the 1 GiB copy used to scale the PMC byte counters")
     ap.add_argument("--nn-alpha", type=float, default=1.0,
                     help="leaky-ReLU slope of the surrogate (1 makes the network linear)")
+    ap.add_argument("--nn-groups", type=int, default=4, choices=[1, 4],
+                    help="channel groups of the surrogate (4: one group of 8 per field)")
+    ap.add_argument("--nn-lr", type=float, default=3e-4,
+                    help="peak of the surrogate's cosine learning-rate schedule")
     ap.add_argument("--rebuilds", type=int, default=5,
                     help="forced neighbour-list rebuilds timed on the main bed")
     ap.add_argument("--bed10m-steps", type=int, default=20,
@@ -431,7 +435,10 @@ def surrogate_section(args):
         g.compute_forces()
 
     def snapshot():
+        # the drag law reads the smoothed solid fraction of this snapshot, as
+        # in a coupled step (not the one of the previous, translated snapshot)
         g.translate(rng.uniform(0, Lx), rng.uniform(0, Ly))
+        g.average()
         g.compute_forces()
         g.deposit()
 
@@ -445,6 +452,10 @@ def surrogate_section(args):
     raws = np.stack(raws)
     rms = np.sqrt((raws ** 2).mean(axis=(0, 2))) + 1e-30
     g.nn_set_norm(np.zeros(4), rms)
+    # one channel group per field: the averaging smooths each field alone, so
+    # the solid fraction's output must not depend on the drag inputs (which
+    # change once particles move)
+    g.nn_set_groups(args.nn_groups)
     g.nn_init(11)
     T = args.nn_train_steps
     switch = max(1, T // 40)
@@ -457,7 +468,7 @@ def surrogate_section(args):
             load(train_seeds[(it // switch) % len(train_seeds)])
         snapshot()
         g.smooth(4)
-        lr = 1e-6 + 0.5 * (1e-4 - 1e-6) * (1 + math.cos(math.pi * it / max(T, 1)))
+        lr = 1e-6 + 0.5 * (args.nn_lr - 1e-6) * (1 + math.cos(math.pi * it / max(T, 1)))
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         losses.append(g.nn_train_step(lr))
@@ -466,8 +477,9 @@ def surrogate_section(args):
         train_ms += e0.elapsed_time(e1)
     train_s = time.perf_counter() - t1
     step_ms = train_ms / max(T, 1)
-    print(f"bench: trained {T} steps on {len(train_seeds)} beds in {train_s:.1f} s, loss "
-          f"{np.mean(losses[:5]):.3e} -> {np.mean(losses[-5:]):.3e}", file=sys.stderr, flush=True)
+    print(f"bench: trained {T} steps on {len(train_seeds)} beds in {train_s:.1f} s, median loss "
+          f"{np.median(losses[:100]):.3e} -> {np.median(losses[-100:]):.3e}", file=sys.stderr,
+          flush=True)
 
     # held-out beds: network error against the plain solve, and the check's estimate
     errs, checks = [], []
@@ -567,11 +579,12 @@ def surrogate_section(args):
           flush=True)
     return {
         "workload": "fine4m", "mesh": w4["meta"]["mesh"], "particles": n4,
-        "leaky_relu_alpha": args.nn_alpha,
-        "train": {"snapshots": T, "beds": f"fine2m seeds {train_seeds[0]}-{train_seeds[-1]}, "
+        "leaky_relu_alpha": args.nn_alpha, "channel_groups": args.nn_groups,
+        "train": {"snapshots": T, "lr": f"cosine {args.nn_lr:g} -> 1e-06", "beds": f"fine2m seeds {train_seeds[0]}-{train_seeds[-1]}, "
                                           "random periodic translations",
                   "seconds": round(train_s, 2), "ms_per_train_step": round(step_ms, 3),
-                  "loss_first": float(np.mean(losses[:5])), "loss_last": float(np.mean(losses[-5:]))},
+                  "loss_median_first_100": float(np.median(losses[:100])),
+                  "loss_median_last_100": float(np.median(losses[-100:]))},
         "error_vs_plain": {"held_out_seeds": held_seeds,
                            "eps_s_maxabs": float(errs[:, 0].max()),
                            "rel_l2_per_channel": [float(v) for v in errs[:, 1:5].max(axis=0)],

@@ -359,7 +359,10 @@ int sedimi_set_avg_mode(sedimi_ctx* ctx, int mode);
  * check falls back.  Backward Euler only (the network is refused with
  * BDF2). */
 int sedimi_nn_param_count(const sedimi_ctx* ctx, int64_t* n);
-/* He-normal initial weights (seeded), zero last layer and biases, zero Adam moments. */
+/* Seeded normal initial weights: standard deviation sqrt(2 / ((1 + a^2) fan_in))
+ * for leaky-ReLU slope a (fan_in = 27 x input channels), halved on the four
+ * residual layers; the last layer and all biases zero (the network starts as
+ * its skip); Adam moments zero. */
 int sedimi_nn_init(sedimi_ctx* ctx, uint64_t seed);
 int sedimi_nn_set_params(sedimi_ctx* ctx, const float* p, int64_t n);
 int sedimi_nn_get_params(sedimi_ctx* ctx, float* p, int64_t n);
@@ -376,8 +379,22 @@ int sedimi_nn_save(sedimi_ctx* ctx, void* buf, size_t cap, size_t* size_out);
 int sedimi_nn_load(sedimi_ctx* ctx, const void* buf, size_t size);
 /* Gradient of the loss from the last sedimi_nn_train_step (same layout). */
 int sedimi_nn_get_grads(sedimi_ctx* ctx, float* g, int64_t n);
-/* Per-channel normalisation x_n = (x - mean) / std of inputs and targets. */
+/* Per-channel normalisation x_n = (x - mean) / std of inputs and targets,
+ * outputs mapped back by y * std + mean.  std: finite and nonzero; a negative
+ * value flips the channel's sign.  The averaging is linear and acts on each
+ * channel alone, so training with a random sign (and scale) per channel and
+ * step keeps the network from tying one channel's output to another
+ * channel's input.  EINVAL otherwise. */
 int sedimi_nn_set_norm(sedimi_ctx* ctx, const double* mean4, const double* std4);
+/* Channel groups of the network: 1 (default, every hidden channel sees every
+ * field) or 4.  With 4, the 32 hidden channels split into 4 groups of 8 and
+ * group k reads and writes field k only: every weight joining two groups is
+ * zeroed now and held at zero (sedimi_nn_set_params and sedimi_nn_init zero
+ * it, and each training step zeroes its gradient before Adam), so the output
+ * for one field depends on that field's input alone, as the averaging of
+ * Eq. 12 does (the diffusion acts on each field separately).  The setting
+ * travels in the network blob and the state blob.  EINVAL for other values. */
+int sedimi_nn_set_groups(sedimi_ctx* ctx, int groups);
 /* Per-channel weights w of the training loss (default 1 each): the loss is
  * sum_ch w_ch mean over cells of (y - target)^2 / 4.  Weights that equalise
  * the channels' errors let a channel with a small error (the solid fraction)

@@ -126,6 +126,7 @@ def lib():
         L.sedimi_set_avg_mode.argtypes = [P, I]
         L.sedimi_nn_param_count.argtypes = [P, C.POINTER(i64)]
         L.sedimi_nn_init.argtypes = [P, C.c_uint64]
+        L.sedimi_nn_set_groups.argtypes = [P, C.c_int]
         L.sedimi_nn_set_params.argtypes = [P, P, i64]
         L.sedimi_nn_get_params.argtypes = [P, P, i64]
         L.sedimi_nn_get_grads.argtypes = [P, P, i64]
@@ -343,6 +344,10 @@ class Sedimi:
 
     def nn_init(self, seed=0):
         self._chk(self._L.sedimi_nn_init(self._ctx, int(seed)))
+
+    def nn_set_groups(self, groups):
+        """1: hidden channels shared by all fields; 4: one group of 8 per field."""
+        self._chk(self._L.sedimi_nn_set_groups(self._ctx, int(groups)))
 
     def nn_set_params(self, p):
         p = np.ascontiguousarray(p, np.float32)

@@ -69,6 +69,8 @@ unsigned launch_nn_loss(int ncell, const float* y, const double* smooth, const N
                         __bf16* dy, double* part, hipStream_t s);
 void launch_adam(int64_t n, float* w, float* m, float* v, const float* g, float lr, float b1,
                  float b2, float eps, int64_t t, hipStream_t s);
+// Zero one layer's cross-group weights (4 groups; see sedimi_nn_set_groups).
+void launch_group_mask(float* a, int cin, int cout, hipStream_t s);
 void launch_pack(const float* w, int cin, int cout, __bf16* fwd, __bf16* adj, hipStream_t s);
 
 }  // namespace sedimi

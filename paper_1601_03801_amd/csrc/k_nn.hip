@@ -749,6 +749,17 @@ __global__ void k_adam(int64_t n, float* __restrict__ w, float* __restrict__ m,
   w[k] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
 }
 
+// Zero the entries of one layer's weights a[27][cin][cout] that join two
+// different channel groups.  A side with 4 channels has one field per group;
+// a wider side splits into 4 equal groups of consecutive channels.
+__global__ void k_group_mask(float* __restrict__ a, int cin, int cout) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 27 * cin * cout) return;
+  const int i = (q / cout) % cin, o = q % cout;
+  const int gi = cin == 4 ? i : i / (cin / 4), go = cout == 4 ? o : o / (cout / 4);
+  if (gi != go) a[q] = 0.0f;
+}
+
 // Pack one layer's FP32 weights w[27][cin][cout] into the BF16 layouts the
 // convolution kernel reads: forward and (for layers > 1) the transposed
 // adjoint used by the data gradient.
@@ -948,6 +959,9 @@ void launch_adam(int64_t n, float* w, float* m, float* v, const float* g, float 
                  float b2, float eps, int64_t t, hipStream_t s) {
   float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
   hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, s, n, w, m, v, g, lr, b1, b2, eps, c1, c2);
+}
+void launch_group_mask(float* a, int cin, int cout, hipStream_t s) {
+  hipLaunchKernelGGL(k_group_mask, dim3(nblk(27 * cin * cout)), dim3(256), 0, s, a, cin, cout);
 }
 void launch_pack(const float* w, int cin, int cout, __bf16* fwd, __bf16* adj, hipStream_t s) {
   hipLaunchKernelGGL(k_pack, dim3(nblk(27 * cin * cout)), dim3(256), 0, s, w, cin, cout, fwd, adj);

@@ -76,6 +76,7 @@ struct sedimi_ctx {
   NNBufs nn;
   NNNorm norm{{0, 0, 0, 0}, {1, 1, 1, 1}, {1, 1, 1, 1}};
   int64_t adam_t = 0;
+  int nn_groups = 1;  // 4: one channel group per field, cross-group weights held at zero
   int64_t nn_calls = 0, nn_fallbacks = 0;
   double nn_last_check = 0.0;
   int64_t cap = 0;
@@ -1421,7 +1422,7 @@ struct StateHeader {
   double nn_last_check, last_residual;
   int32_t avg_mode, have_particles, last_direct, check_blocks;
   uint32_t swapped;  // double buffers in their second position: vel, omg, pos, rb
-  int32_t pad1;
+  int32_t nn_groups;
   NNNorm norm;
   // the device parameters (every physical parameter the kernels and the
   // workspace's derived tables and fields depend on), particle count zeroed
@@ -1487,6 +1488,7 @@ int sedimi_get_state(sedimi_ctx* c, void* buf, size_t cap, size_t* size_out) {
   h.nn_last_check = c->nn_last_check, h.last_residual = c->last_residual;
   h.avg_mode = c->avg_mode, h.have_particles = c->have_particles ? 1 : 0;
   h.last_direct = c->last_direct ? 1 : 0, h.check_blocks = c->check_blocks;
+  h.nn_groups = c->nn_groups;
   h.norm = c->norm;
   memcpy(&h.P, &c->P, sizeof(DevParams));  // bytes, padding included
   h.P.n = 0;
@@ -1529,7 +1531,7 @@ int sedimi_set_state(sedimi_ctx* c, const void* buf, size_t size) {
     return fail(c, SEDIMI_EINVAL, "state blob from a context with other parameters");
   if (h.avg_mode < SEDIMI_AVG_PLAIN || h.avg_mode > SEDIMI_AVG_SURROGATE ||
       (h.avg_mode != SEDIMI_AVG_PLAIN && !c->prm.nn_enable) || h.check_blocks < 0 ||
-      h.step < 0 || h.adam_t < 0)
+      h.step < 0 || h.adam_t < 0 || (h.nn_groups != 1 && h.nn_groups != 4))
     return fail(c, SEDIMI_EINVAL, "state blob out of range");
   HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipMemcpy(c->ws, (const char*)buf + sizeof(h), c->ws_bytes, hipMemcpyHostToDevice));
@@ -1545,6 +1547,7 @@ int sedimi_set_state(sedimi_ctx* c, const void* buf, size_t size) {
   c->nn_last_check = h.nn_last_check, c->last_residual = h.last_residual;
   c->avg_mode = h.avg_mode, c->have_particles = h.have_particles != 0;
   c->last_direct = h.last_direct != 0, c->check_blocks = h.check_blocks;
+  c->nn_groups = h.nn_groups;
   c->norm = h.norm;
   return SEDIMI_OK;
 }
@@ -1636,6 +1639,12 @@ void nn_pack_all(sedimi_ctx* c) {
                 c->stream);
 }
 
+// Zero the cross-group entries of a parameter-shaped array (weights, their
+// gradient or Adam moments); biases are per channel and stay.
+void nn_mask_groups(sedimi_ctx* c, float* a) {
+  for (int l = 0; l < 6; ++l) launch_group_mask(a + nn_woff(l), nn_cin(l), nn_cout(l), c->stream);
+}
+
 // Network forward on the RAW field into nn.y and the SMOOTH field.  keep:
 // store the pre-activations needed by the backward pass.
 void nn_run_forward(sedimi_ctx* c, bool keep) {
@@ -1708,8 +1717,16 @@ int sedimi_nn_init(sedimi_ctx* c, uint64_t seed) {
   const int64_t P = nn_count();
   std::vector<float> w((size_t)P, 0.0f);
   uint64_t s = seed;
-  for (int l = 0; l < 5; ++l) {  // the last layer starts at zero: output = input
-    const double sd = sqrt(2.0 / (27.0 * nn_cin(l)));
+  // Variance-preserving scale for a leaky ReLU of slope alpha (2 / (1 + alpha^2)
+  // over the fan-in: 1 / fan-in for the linear network), and the four
+  // residual branches at 1/sqrt(4) of it so that the residual stream's
+  // variance stays within a small factor of the first layer's instead of
+  // growing with depth.  The last layer starts at zero: output = skip.
+  // With 4 channel groups a hidden channel's fan-in is its own group's share.
+  const double a = c->prm.nn_alpha;
+  for (int l = 0; l < 5; ++l) {
+    const double fan = 27.0 * nn_cin(l) / c->nn_groups;
+    const double sd = sqrt(2.0 / ((1.0 + a * a) * fan)) * (l >= 1 ? 0.5 : 1.0);
     const int64_t nw = 27LL * nn_cin(l) * nn_cout(l);
     for (int64_t k = 0; k < nw; k += 2) {
       double u1 = ((mix64(s) >> 11) + 0.5) * (1.0 / 9007199254740992.0);
@@ -1728,6 +1745,7 @@ int sedimi_nn_set_params(sedimi_ctx* c, const float* p, int64_t n) {
   const int64_t P = nn_count();
   if (!p || n != P) return fail(c, SEDIMI_EINVAL, "parameter vector has the wrong length");
   HIPCHK(c, hipMemcpyAsync(c->nn.w, p, sizeof(float) * P, hipMemcpyHostToDevice, c->stream));
+  if (c->nn_groups == 4) nn_mask_groups(c, c->nn.w);
   HIPCHK(c, hipMemsetAsync(c->nn.m, 0, sizeof(float) * P, c->stream));
   HIPCHK(c, hipMemsetAsync(c->nn.v, 0, sizeof(float) * P, c->stream));
   for (int l = 0; l < 6; ++l) {
@@ -1753,11 +1771,11 @@ int sedimi_nn_get_params(sedimi_ctx* c, float* p, int64_t n) {
 
 struct NNSaveHeader {
   char magic[8];
-  int64_t count, adam_t;
+  int64_t count, adam_t, groups;
   double alpha;
   double mean[4], std[4], lw[4];
 };
-constexpr char kNNMagic[8] = {'S', 'E', 'D', 'I', 'N', 'N', '0', '1'};
+constexpr char kNNMagic[8] = {'S', 'E', 'D', 'I', 'N', 'N', '0', '2'};
 
 int sedimi_nn_save(sedimi_ctx* c, void* buf, size_t cap, size_t* size_out) {
   int rc = need_nn(c);
@@ -1770,7 +1788,7 @@ int sedimi_nn_save(sedimi_ctx* c, void* buf, size_t cap, size_t* size_out) {
   NNSaveHeader h;
   memset(&h, 0, sizeof(h));
   memcpy(h.magic, kNNMagic, sizeof(h.magic));
-  h.count = P, h.adam_t = c->adam_t, h.alpha = c->prm.nn_alpha;
+  h.count = P, h.adam_t = c->adam_t, h.groups = c->nn_groups, h.alpha = c->prm.nn_alpha;
   for (int k = 0; k < 4; ++k)
     h.mean[k] = c->norm.mean[k], h.std[k] = c->norm.std[k], h.lw[k] = c->norm.lw[k];
   memcpy(buf, &h, sizeof(h));
@@ -1791,14 +1809,16 @@ int sedimi_nn_load(sedimi_ctx* c, const void* buf, size_t size) {
   if (!buf || size < sizeof(h)) return fail(c, SEDIMI_EINVAL, "network blob too short");
   memcpy(&h, buf, sizeof(h));
   if (memcmp(h.magic, kNNMagic, sizeof(h.magic)) != 0 || h.count != P ||
-      size != sizeof(h) + 3 * sizeof(float) * (size_t)P || h.adam_t < 0)
+      size != sizeof(h) + 3 * sizeof(float) * (size_t)P || h.adam_t < 0 ||
+      (h.groups != 1 && h.groups != 4))
     return fail(c, SEDIMI_EINVAL, "not a network blob of this architecture");
   if (h.alpha != c->prm.nn_alpha)
     return fail(c, SEDIMI_EINVAL, "network blob trained with another leaky-ReLU slope");
   for (int k = 0; k < 4; ++k)
-    if (!(h.std[k] > 0) || !std::isfinite(h.mean[k]) || !(h.lw[k] >= 0))
+    if (!(h.std[k] != 0 && std::isfinite(h.std[k])) || !std::isfinite(h.mean[k]) || !(h.lw[k] >= 0))
       return fail(c, SEDIMI_EINVAL, "network blob with an invalid standardisation");
   const float* body = reinterpret_cast<const float*>(static_cast<const char*>(buf) + sizeof(h));
+  c->nn_groups = (int)h.groups;
   rc = sedimi_nn_set_params(c, body, P);  // parameters, packed copies; zeroes the moments
   if (rc) return rc;
   HIPCHK(c, hipMemcpyAsync(c->nn.m, body + (size_t)P, sizeof(float) * P, hipMemcpyHostToDevice,
@@ -1826,10 +1846,27 @@ int sedimi_nn_set_norm(sedimi_ctx* c, const double* mean4, const double* std4) {
   if (rc) return rc;
   if (!mean4 || !std4) return fail(c, SEDIMI_EINVAL, "null normalisation");
   for (int k = 0; k < 4; ++k) {
-    if (!(std4[k] > 0)) return fail(c, SEDIMI_EINVAL, "std must be positive");
+    if (!(std4[k] != 0 && std::isfinite(std4[k]) && std::isfinite(mean4[k])))
+      return fail(c, SEDIMI_EINVAL, "std must be finite and nonzero, mean finite");
     c->norm.mean[k] = mean4[k];
     c->norm.std[k] = std4[k];
   }
+  return SEDIMI_OK;
+}
+
+int sedimi_nn_set_groups(sedimi_ctx* c, int groups) {
+  int rc = need_nn(c);
+  if (rc) return rc;
+  if (groups != 1 && groups != 4) return fail(c, SEDIMI_EINVAL, "channel groups must be 1 or 4");
+  c->nn_groups = groups;
+  if (groups == 4) {
+    nn_mask_groups(c, c->nn.w);
+    nn_mask_groups(c, c->nn.m);
+    nn_mask_groups(c, c->nn.v);
+    nn_pack_all(c);
+  }
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return SEDIMI_OK;
 }
 
@@ -1914,6 +1951,7 @@ int sedimi_nn_train_step(sedimi_ctx* c, double lr, double* loss) {
   launch_conv_dw(4, kNNC, geom(c, 0, 0), b.xb, b.dz[0], b.part, b.part_b, b.g + nn_woff(0),
                  b.g + nn_woff(0) + 27LL * 4 * kNNC, dwb, c->stream);
   const int64_t P = nn_count();
+  if (c->nn_groups == 4) nn_mask_groups(c, b.g);
   c->adam_t += 1;
   launch_adam(P, b.w, b.m, b.v, b.g, (float)lr, 0.9f, 0.999f, 1e-8f, c->adam_t, c->stream);
   nn_pack_all(c);

@@ -195,3 +195,58 @@ def test_save_load_resumes_training_exactly():
     other = sm.Sedimi(prm, 1, d_max=0.5e-3, nn=True, nn_alpha=0.5)
     with pytest.raises(sm.SedimiError):
         other.nn_load(blob)
+
+
+def test_channel_groups_keep_fields_apart():
+    """With 4 channel groups (sedimi_nn_set_groups) each field's output depends
+    on that field's input alone, as the averaging's does: the weights joining
+    two groups are zero after the initialisation and stay zero through
+    training steps, new drag inputs leave the solid fraction's output
+    bit-identical, and the setting travels in the network blob."""
+    import paper_1601_03801_amd as sm
+    shape = (16, 12, 10)
+    n = int(np.prod(shape))
+    rng = np.random.default_rng(9)
+    g, _ = mesh_ctx(shape)
+    with pytest.raises(sm.SedimiError):
+        g.nn_set_groups(3)
+    g.nn_set_groups(4)
+    g.nn_init(5)
+    g.nn_set_norm(np.zeros(4), np.array([0.3, 0.2, 0.25, 0.1]))
+
+    def check_mask(p):
+        off = 0
+        for ci, co in [(4, 32)] + [(32, 32)] * 4 + [(32, 4)]:
+            w = p[off:off + 27 * ci * co].reshape(27, ci, co)
+            gi = np.arange(ci) if ci == 4 else np.arange(ci) // (ci // 4)
+            go = np.arange(co) if co == 4 else np.arange(co) // (co // 4)
+            cross = gi[:, None] != go[None, :]
+            assert np.all(w[:, cross] == 0), (ci, co)
+            assert np.any(w[:, ~cross] != 0), (ci, co)
+            off += 27 * ci * co + co
+
+    for _ in range(3):
+        g.set_field(0, rng.random((4, n)) ** 3)
+        g.smooth(4)
+        g.nn_train_step(1e-3)
+    check_mask(g.nn_get_params())
+    raw = rng.random((4, n)) ** 3
+    g.set_field(0, raw)
+    g.nn_forward()
+    y1 = g.get_field(1)
+    raw2 = raw.copy()
+    raw2[1:] = rng.random((3, n))
+    g.set_field(0, raw2)
+    g.nn_forward()
+    y2 = g.get_field(1)
+    assert np.array_equal(y1[0], y2[0])
+    assert not np.array_equal(y1[1], y2[1])
+    b, _ = mesh_ctx(shape)
+    b.nn_load(g.nn_save())
+    b.set_field(0, raw2)
+    b.nn_forward()
+    assert np.array_equal(b.get_field(1), y2)
+    b.set_field(0, raw)
+    b.smooth(4)
+    b.nn_train_step(1e-3)
+    check_mask(b.nn_get_params())

@@ -12,13 +12,18 @@ and the time of the network's forward pass, of the check, of the direct
 plain solve and of the iterative plain solve (Chebyshev, the route of meshes
 the direct solve does not diagonalise), each from HIP events.
 
+The network has one channel group per field (sedimi_nn_set_groups), and each
+training snapshot's drag is computed from that snapshot's own smoothed solid
+fraction.
+
 What must hold: the network is at least as close to the plain solve as its
 skip on every channel (its last layer starts at zero, so training can only
 have moved it from S x by descending the loss), both are far closer than the
-raw field, the check's estimate stays within a factor of the measured error,
-checked mode falls back exactly when that estimate exceeds the bound, and
-the forward pass is faster than the iterative solve.  Whether it beats the
-direct solve is stated, not asserted: on this mesh it does not."""
+raw field, the solid fraction is within the 1e-3 bound of the plain solve,
+the check's estimate stays within a factor of the measured error, checked
+mode keeps the network's field exactly when that estimate is within the
+bound, and the forward pass is faster than the iterative solve.  Whether it
+beats the direct solve is stated, not asserted: on this mesh it does not."""
 import json
 import math
 
@@ -31,7 +36,7 @@ pytestmark = pytest.mark.gpu
 
 TRAIN, HELD = (2000, 2001, 2002, 2003), 2010
 N = 500_000
-STEPS = 400
+STEPS = 600
 
 
 def _timed(torch, fn, reps=5):
@@ -71,6 +76,7 @@ def test_network_error_and_time_against_the_plain_solve():
 
     def snapshot():
         g.translate(rng.uniform(0, prm["Lx"]), rng.uniform(0, prm["Ly"]))
+        g.average()
         g.compute_forces()
         g.deposit()
 
@@ -81,6 +87,7 @@ def test_network_error_and_time_against_the_plain_solve():
         raws.append(g.get_field(0))
     rms = np.sqrt((np.stack(raws) ** 2).mean(axis=(0, 2))) + 1e-30
     g.nn_set_norm(np.zeros(4), rms)
+    g.nn_set_groups(4)
     g.nn_init(3)
     losses = []
     for it in range(STEPS):
@@ -88,7 +95,7 @@ def test_network_error_and_time_against_the_plain_solve():
             load(TRAIN[(it // 10) % len(TRAIN)])
         snapshot()
         g.smooth(4)
-        lr = 1e-6 + 0.5 * (1e-4 - 1e-6) * (1 + math.cos(math.pi * it / STEPS))
+        lr = 1e-6 + 0.5 * (3e-4 - 1e-6) * (1 + math.cos(math.pi * it / STEPS))
         losses.append(g.nn_train_step(lr))
     print(f"gain: loss {np.mean(losses[:5]):.3e} -> {np.mean(losses[-5:]):.3e}", flush=True)
 
@@ -131,6 +138,7 @@ def test_network_error_and_time_against_the_plain_solve():
     for c in range(4):
         assert err["network"][c] <= err["skip"][c] * 1.001, (c, report)
         assert err["skip"][c] < 0.5 * err["raw"][c], (c, report)
+    assert err["network"][0] < bound, report
     # the decision is taken on the solid fraction
     assert 0.5 * err["network"][0] - 1e-4 < est[0] < 2.0 * err["network"][0] + 1e-4, report
     assert report["checked_mode_fell_back"] == bool(est[0] > bound), report
