@@ -207,6 +207,8 @@ typedef struct {
   double nn_check_trunc;  /* mass of the check's Green's function outside its window */
   int32_t nn_check_window[3]; /* the window's half widths in cells (x, y, z) */
   int32_t nn_check_columns;   /* z-columns the check samples */
+  int64_t graph_steps;        /* sedimi_step calls run from a captured graph (the
+                                 capturing call included; see sedimi_set_step_graphs) */
 } sedimi_stats;
 
 /* Device time per phase of sedimi_step / sedimi_average, measured with HIP
@@ -262,6 +264,17 @@ int sedimi_compute_forces(sedimi_ctx* ctx, int update_history);
  * every step whose global index is a multiple of average_every, and its
  * solid fraction feeds the drag of the following steps. */
 int sedimi_step(sedimi_ctx* ctx, int nsteps, int average_every);
+/* Replay of sedimi_step from HIP graphs (on by default).  When the steps of a
+ * call contain no averaging other than the plain direct solve (so nothing is
+ * read back inside them), the call's kernel sequence is captured once into a
+ * graph on a stream of the context's own and later calls of the same shape
+ * (same nsteps, average_every and place in the averaging cycle, unchanged
+ * parameters, workspace and particle count) launch that graph on the
+ * context's stream: fewer per-kernel launch costs, identical results.  Up to
+ * 4 graphs are kept per context.  If a capture fails the call runs the
+ * kernels directly and replay stays off for the context.  enable = 0 turns
+ * replay off and frees the graphs. */
+int sedimi_set_step_graphs(sedimi_ctx* ctx, int enable);
 /* Rebuild the neighbour lists now, as sedimi_step does when a particle has
  * moved half the skin (Section 2.5's link-cell search): binning, the stable
  * re-sort by (bin, ID), the pair search and the carry-over of the tangential

@@ -65,7 +65,8 @@ class sedimi_stats(C.Structure):
                 ("mean_contacts", C.c_double), ("nn_calls", C.c_int64),
                 ("nn_fallbacks", C.c_int64), ("nn_last_check", C.c_double),
                 ("particles", C.c_int64), ("nn_check_trunc", C.c_double),
-                ("nn_check_window", C.c_int32 * 3), ("nn_check_columns", C.c_int32)]
+                ("nn_check_window", C.c_int32 * 3), ("nn_check_columns", C.c_int32),
+                ("graph_steps", C.c_int64)]
 
 
 NPHASES = 6
@@ -127,6 +128,7 @@ def lib():
         L.sedimi_nn_param_count.argtypes = [P, C.POINTER(i64)]
         L.sedimi_nn_init.argtypes = [P, C.c_uint64]
         L.sedimi_nn_set_groups.argtypes = [P, C.c_int]
+        L.sedimi_set_step_graphs.argtypes = [P, C.c_int]
         L.sedimi_nn_set_params.argtypes = [P, P, i64]
         L.sedimi_nn_get_params.argtypes = [P, P, i64]
         L.sedimi_nn_get_grads.argtypes = [P, P, i64]
@@ -332,6 +334,10 @@ class Sedimi:
     def set_history(self, records):
         rec = np.ascontiguousarray(records, HISTORY_DTYPE)
         self._chk(self._L.sedimi_set_history(self._ctx, len(rec), _ptr(rec) if len(rec) else None))
+
+    def set_step_graphs(self, enable=True):
+        """Replay step() from captured HIP graphs (on by default)."""
+        self._chk(self._L.sedimi_set_step_graphs(self._ctx, 1 if enable else 0))
 
     def set_avg_mode(self, mode):
         self._chk(self._L.sedimi_set_avg_mode(self._ctx, int(mode)))

@@ -110,7 +110,30 @@ struct sedimi_ctx {
   std::vector<hipEvent_t> pool;
   double prof_ms[SEDIMI_NPHASES] = {0};
   int64_t prof_count[SEDIMI_NPHASES] = {0};
+  // Replayed steps: sedimi_step's kernel sequence captured once into a HIP
+  // graph and launched as one (about 1.6 us per kernel instead of 2.7 us).
+  // An entry is keyed on everything the captured launches baked in.
+  bool graphs_on = true;
+  int64_t graph_steps = 0;           // calls run from a graph
+  hipStream_t cap_stream = nullptr;  // capture needs a stream of its own
+  struct StepGraph {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec = nullptr;
+    DevArrays after{};  // the device-array pointers after the steps
+    bool averaged = false, last_direct = false;
+    int64_t last_iters = 0;
+    int check_blocks = 0;
+    uint64_t used = 0;
+  };
+  std::vector<StepGraph> graphs;
+  uint64_t graph_clock = 0;
+  void drop_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  }
   ~sedimi_ctx() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (auto& m : marks) pool.push_back(m.a), pool.push_back(m.b);
     for (auto e : pool) (void)hipEventDestroy(e);
   }
@@ -1108,10 +1131,14 @@ int sedimi_rebuild(sedimi_ctx* c) {
   return flags_to_rc(c, ctl.flags);
 }
 
-int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
-  int rc = need_particles(c);
-  if (rc) return rc;
-  if (nsteps < 0) return fail(c, SEDIMI_EINVAL, "nsteps must be >= 0");
+}  // extern "C"
+
+namespace {
+
+// The kernel sequence of nsteps particle steps (with the averagings that
+// fall in them), enqueued on c->stream; host bookkeeping (buffer swaps, the
+// step counter, the solve's check state) advances as it goes.
+int step_loop(sedimi_ctx* c, int nsteps, int average_every, bool* averaged_out) {
   bool averaged = false;
   // A step whose successor is in this call and is not preceded by an
   // averaging fuses the successor's half kick and drift into its force
@@ -1147,6 +1174,126 @@ int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
       averaged = plain;  // residual partials of the last averaging (plain only)
     }
   }
+  *averaged_out = averaged;
+  return SEDIMI_OK;
+}
+
+// Whether a call's steps can be replayed from a graph: no read-back inside
+// them, i.e. every averaging they contain is the plain direct solve.
+bool step_graphable(const sedimi_ctx* c, int nsteps, int average_every) {
+  if (!c->graphs_on || c->prof || nsteps <= 0 || c->n <= 0) return false;
+  const bool avg_inside =
+      average_every > 0 && (c->step % average_every) + nsteps >= average_every;
+  if (!avg_inside) return true;
+  const bool network = c->avg_mode != SEDIMI_AVG_PLAIN && c->prm.nn_enable;
+  return !network && c->direct && c->prm.avg_ntau > 0;
+}
+
+void put_bytes(std::vector<unsigned char>& k, const void* v, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(v);
+  k.insert(k.end(), b, b + n);
+}
+
+// Everything the captured launches depend on: the device parameters and
+// array pointers passed by value, the parameters the host derives launch
+// arguments from, the call's shape and where it starts in the averaging
+// cycle.
+std::vector<unsigned char> step_key(const sedimi_ctx* c, int nsteps, int average_every) {
+  std::vector<unsigned char> k;
+  const int32_t head[6] = {nsteps, average_every,
+                           average_every > 0 ? (int32_t)(c->step % average_every) : 0,
+                           c->avg_mode, c->direct ? 1 : 0, c->mixed ? 1 : 0};
+  put_bytes(k, head, sizeof(head));
+  put_bytes(k, &c->P, sizeof(c->P));
+  put_bytes(k, &c->A, sizeof(c->A));
+  put_bytes(k, &c->prm, sizeof(c->prm));
+  return k;
+}
+
+constexpr size_t kMaxStepGraphs = 4;
+
+int step_graph(sedimi_ctx* c, int nsteps, int average_every, bool* averaged) {
+  std::vector<unsigned char> key = step_key(c, nsteps, average_every);
+  for (auto& g : c->graphs) {
+    if (g.key != key) continue;
+    HIPCHK(c, hipGraphLaunch(g.exec, c->stream));
+    c->A = g.after;
+    c->step += nsteps;
+    if (g.averaged) {
+      c->last_iters = g.last_iters;
+      c->last_direct = g.last_direct;
+      c->check_blocks = g.check_blocks;
+    }
+    *averaged = g.averaged;
+    g.used = ++c->graph_clock;
+    ++c->graph_steps;
+    return SEDIMI_OK;
+  }
+  if (!c->cap_stream) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  // capture records and runs nothing: keep the host state to restore if it fails
+  const DevArrays A0 = c->A;
+  const int64_t step0 = c->step, iters0 = c->last_iters;
+  const bool direct0 = c->last_direct;
+  const int blocks0 = c->check_blocks;
+  hipStream_t user = c->stream;
+  c->stream = c->cap_stream;
+  hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed);
+  int rc = SEDIMI_OK;
+  bool av = false;
+  hipGraph_t graph = nullptr;
+  if (e == hipSuccess) {
+    rc = step_loop(c, nsteps, average_every, &av);
+    const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+    if (e2 != hipSuccess) e = e2;
+  }
+  c->stream = user;
+  hipGraphExec_t exec = nullptr;
+  if (e == hipSuccess && rc == SEDIMI_OK && graph)
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess || rc != SEDIMI_OK || !exec) {
+    // take these steps eagerly and do not try again on this context
+    (void)hipGetLastError();
+    c->A = A0, c->step = step0, c->last_iters = iters0;
+    c->last_direct = direct0, c->check_blocks = blocks0;
+    c->graphs_on = false;
+    return step_loop(c, nsteps, average_every, averaged);
+  }
+  sedimi_ctx::StepGraph g;
+  g.key = std::move(key);
+  g.exec = exec;
+  g.after = c->A;
+  g.averaged = av;
+  g.last_direct = c->last_direct;
+  g.last_iters = c->last_iters;
+  g.check_blocks = c->check_blocks;
+  g.used = ++c->graph_clock;
+  if (c->graphs.size() >= kMaxStepGraphs) {
+    size_t lru = 0;
+    for (size_t i = 1; i < c->graphs.size(); ++i)
+      if (c->graphs[i].used < c->graphs[lru].used) lru = i;
+    (void)hipGraphExecDestroy(c->graphs[lru].exec);
+    c->graphs.erase(c->graphs.begin() + (long)lru);
+  }
+  c->graphs.push_back(std::move(g));
+  HIPCHK(c, hipGraphLaunch(exec, c->stream));
+  ++c->graph_steps;
+  *averaged = av;
+  return SEDIMI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
+  int rc = need_particles(c);
+  if (rc) return rc;
+  if (nsteps < 0) return fail(c, SEDIMI_EINVAL, "nsteps must be >= 0");
+  bool averaged = false;
+  rc = step_graphable(c, nsteps, average_every) ? step_graph(c, nsteps, average_every, &averaged)
+                                                 : step_loop(c, nsteps, average_every, &averaged);
+  if (rc) return rc;
   HIPCHK(c, hipGetLastError());
   Ctl ctl;
   rc = read_ctl(c, &ctl);
@@ -1154,6 +1301,13 @@ int sedimi_step(sedimi_ctx* c, int nsteps, int average_every) {
   rc = flags_to_rc(c, ctl.flags);
   if (rc) return rc;
   if (averaged) return check_solve(c, c->P.nch_avg);
+  return SEDIMI_OK;
+}
+
+int sedimi_set_step_graphs(sedimi_ctx* c, int enable) {
+  if (!c) return SEDIMI_EINVAL;
+  c->graphs_on = enable != 0;
+  if (!c->graphs_on) c->drop_graphs();
   return SEDIMI_OK;
 }
 
@@ -1574,6 +1728,7 @@ int sedimi_get_stats(sedimi_ctx* c, sedimi_stats* out) {
   out->nn_check_window[1] = c->green.ry;
   out->nn_check_window[2] = c->green.rz;
   out->nn_check_columns = c->green_cols;
+  out->graph_steps = c->graph_steps;
   out->particles = c->n;
   if (c->have_particles && c->n > 0) {
     const size_t n = (size_t)c->n;
