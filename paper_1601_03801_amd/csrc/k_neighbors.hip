@@ -194,9 +194,17 @@ __global__ void k_copyback(DevParams P, DevArrays A) {
 // class, and each slot's tangential history is matched by partner ID against
 // the contact rows of q's pre-sort position, whose IDs are held in
 // registers.
+// WRAP (at least 5 bins on each periodic axis): a candidate's periodic image
+// is known from its bin alone.  A neighbour bin reached without wrapping lies
+// within 2 bins, i.e. within L/2, where the minimum image is the plain
+// difference; one reached across the seam lies beyond L/2, where it is the
+// difference -/+ L.  Adding that per-bin shift is the very operation the
+// minimum-image selection would pick, so the distances, and the lists, are
+// bit-identical, for a fifth of the instructions per candidate.
 constexpr int kBuildStride = 31;  // LDS row of a lane: >= max_neighbors, odd (no bank conflicts)
 static_assert(kBuildStride >= 30, "a lane's LDS row must hold max_neighbors (<= 30) slots");
-template <typename H>
+constexpr int kWrapMinBins = 5;
+template <typename H, bool WRAP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_build(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
   __shared__ int park[kBlock * kBuildStride];
@@ -221,6 +229,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
       const int cz = bz + r / 3 - 1;
       if (cz < 0 || cz >= P.nbz) continue;
       int cy = by + r % 3 - 1;
+      const double sy = cy < 0 ? -P.Ly : (cy >= P.nby ? P.Ly : 0.0);
       cy = cy < 0 ? cy + P.nby : (cy >= P.nby ? cy - P.nby : cy);
       const int base = (cz * P.nby + cy) * P.nbx;
       int bs[3], be[3];
@@ -233,12 +242,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
       }
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
+        const double sx = t == 0 ? (bx == 0 ? -P.Lx : 0.0) : (t == 2 && bx + 1 == P.nbx ? P.Lx : 0.0);
 #pragma unroll 4
         for (int j = bs[t]; j < be[t]; ++j) {
           if (j == q) continue;
           const double4 xj = A.pos[j];
-          const double ddx = min_image(xj.x - xi.x, P.Lx, P.hLx);
-          const double ddy = min_image(xj.y - xi.y, P.Ly, P.hLy);
+          const double ddx = WRAP ? (xj.x - xi.x) + sx : min_image(xj.x - xi.x, P.Lx, P.hLx);
+          const double ddy = WRAP ? (xj.y - xi.y) + sy : min_image(xj.y - xi.y, P.Ly, P.hLy);
           const double ddz = xj.z - xi.z;
           const double s2 = ddx * ddx + ddy * ddy + ddz * ddz;
           const double rs = xi.w + xj.w;
@@ -476,10 +486,15 @@ void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixe
   // the list build is latency bound: every particle gets its own lane (the
   // grid a multiple of the XCD count for the block renumbering)
   const unsigned gb = xcd_grid(nblk(P.n) < 8192 ? nblk(P.n) : 8192);
-  if (mixed)
-    hipLaunchKernelGGL(k_build<float>, dim3(gb), dim3(kBlock), 0, s, P, A);
+  const bool wrap = P.nbx >= kWrapMinBins && P.nby >= kWrapMinBins;
+  if (mixed && wrap)
+    hipLaunchKernelGGL((k_build<float, true>), dim3(gb), dim3(kBlock), 0, s, P, A);
+  else if (mixed)
+    hipLaunchKernelGGL((k_build<float, false>), dim3(gb), dim3(kBlock), 0, s, P, A);
+  else if (wrap)
+    hipLaunchKernelGGL((k_build<double, true>), dim3(gb), dim3(kBlock), 0, s, P, A);
   else
-    hipLaunchKernelGGL(k_build<double>, dim3(gb), dim3(kBlock), 0, s, P, A);
+    hipLaunchKernelGGL((k_build<double, false>), dim3(gb), dim3(kBlock), 0, s, P, A);
 }
 
 }  // namespace sedimi
