@@ -31,7 +31,8 @@ constexpr double kPi = 3.14159265358979323846;
 
 // Cell of each particle and its rank among the cell's members.  Sorted
 // particles that share a cell mostly sit in the same wave: each group of
-// lanes with one cell takes its ranks with a single atomic add.
+// lanes with one cell takes its ranks with a single atomic add
+// (wave_ranks).
 __global__ void k_cellkey(DevParams P, DevArrays A) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = q < P.n;
@@ -45,19 +46,7 @@ __global__ void k_cellkey(DevParams P, DevArrays A) {
     A.key[q] = k;
   }
   // every lane of the wave is still active here (no early return above)
-  unsigned long long active = __ballot(valid);
-  const int lane = __lane_id();
-  int rank = 0;
-  while (active) {
-    const int leader = __ffsll((long long)active) - 1;
-    const int kl = __shfl(k, leader);
-    const unsigned long long grp = __ballot(k == kl) & active;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&A.cell_count[kl], (int)__popcll(grp));
-    base = __shfl(base, leader);
-    if ((grp >> lane) & 1ull) rank = base + (int)__popcll(grp & ((1ull << lane) - 1ull));
-    active &= ~grp;
-  }
+  const int rank = wave_ranks(A.cell_count, k, valid);
   if (valid) A.rank[q] = rank;
 }
 
@@ -69,37 +58,30 @@ __global__ void k_cellscatter(DevParams P, DevArrays A) {
 }
 
 // One lane per cell: order the members by particle ID (the high half of each
-// (ID, index) key), then sum in that order.  A cell of up to kSortRegs
-// members is sorted in registers by a bitonic network (padded with keys above
-// every real one) and written back; a larger one by insertion in place.
+// (ID, index) key): a cell of up to kSortRegs members is sorted in registers
+// by a bitonic network (padded with keys above every real one) and written
+// back, a larger one by insertion in place.  Then the block's cells, which
+// own one contiguous range of the sorted keys, gather their members' volume
+// and drag into LDS together, kDepChunk members at a time (many gathers in
+// flight instead of a few per lane), and each lane sums its cell's members
+// from there in ID order.
 constexpr int kSortRegs = 32;
+constexpr int kDepChunk = 512;
 
-__device__ __forceinline__ void cell_add(const DevArrays& A, int q, bool flux, double& v,
-                                         double& fx, double& fy, double& fz, double& qx,
-                                         double& qy, double& qz) {
+__global__ __launch_bounds__(kBlock) void k_cellsum(DevParams P, DevArrays A) {
 #pragma clang fp contract(off)
-  const double d = 2.0 * A.pos[q].w;
-  const double V = (kPi / 6.0) * d * d * d;
-  v += V;
-  const double4 f = A.fdr[q];
-  fx += f.x;
-  fy += f.y;
-  fz += f.z;
-  if (flux) {
-    const double4 u = A.vel[q];
-    qx += V * u.x;
-    qy += V * u.y;
-    qz += V * u.z;
-  }
-}
-
-__global__ void k_cellsum(DevParams P, DevArrays A) {
-#pragma clang fp contract(off)
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= P.ncell) return;
-  const int s = A.cell_start[c], e = A.cell_start[c + 1], m = e - s;
+  __shared__ double sv[kDepChunk], sfx[kDepChunk], sfy[kDepChunk], sfz[kDepChunk];
+  __shared__ double sqx[kDepChunk], sqy[kDepChunk], sqz[kDepChunk];
+  const int c0 = blockIdx.x * kBlock;
+  const int c = c0 + threadIdx.x;
+  const bool valid = c < P.ncell;
   const bool flux = P.nch_avg == 7;
-  double v = 0.0, fx = 0.0, fy = 0.0, fz = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
+  int s = 0, e = 0;
+  if (valid) {
+    s = A.cell_start[c];
+    e = A.cell_start[c + 1];
+  }
+  const int m = e - s;
   if (m > 0 && m <= kSortRegs) {
     // unconditional loads (clamped to the last member), padded after it
     unsigned long long key[kSortRegs];
@@ -139,10 +121,46 @@ __global__ void k_cellsum(DevParams P, DevArrays A) {
       A.cperm[j + 1] = key;
     }
   }
-  // the members in ID order
-#pragma unroll 4
-  for (int i = s; i < e; ++i)
-    cell_add(A, (int)(unsigned)(A.cperm[i] & 0xffffffffull), flux, v, fx, fy, fz, qx, qy, qz);
+  // the block's range of sorted keys (written above by its own lanes)
+  const int cl = c0 + kBlock < P.ncell ? c0 + kBlock : P.ncell;
+  const int seg0 = A.cell_start[c0], seg1 = A.cell_start[cl];
+  __syncthreads();
+  double v = 0.0, fx = 0.0, fy = 0.0, fz = 0.0, qx = 0.0, qy = 0.0, qz = 0.0;
+  for (int base = seg0; base < seg1; base += kDepChunk) {
+    const int cnt = seg1 - base < kDepChunk ? seg1 - base : kDepChunk;
+    for (int t = threadIdx.x; t < cnt; t += kBlock) {
+      const int q = (int)(unsigned)(A.cperm[base + t] & 0xffffffffull);
+      const double d = 2.0 * A.pos[q].w;
+      const double V = (kPi / 6.0) * d * d * d;
+      const double4 f = A.fdr[q];
+      sv[t] = V;
+      sfx[t] = f.x;
+      sfy[t] = f.y;
+      sfz[t] = f.z;
+      if (flux) {
+        const double4 u = A.vel[q];
+        sqx[t] = V * u.x;
+        sqy[t] = V * u.y;
+        sqz[t] = V * u.z;
+      }
+    }
+    __syncthreads();
+    // this cell's members in the chunk, in ID order
+    const int lo = s > base ? s : base, hi = e < base + cnt ? e : base + cnt;
+    for (int i = lo - base; i < hi - base; ++i) {
+      v += sv[i];
+      fx += sfx[i];
+      fy += sfy[i];
+      fz += sfz[i];
+      if (flux) {
+        qx += sqx[i];
+        qy += sqy[i];
+        qz += sqz[i];
+      }
+    }
+    __syncthreads();
+  }
+  if (!valid) return;
   const size_t nc = (size_t)P.ncell;
   // each cell divides by its own volume (one per plane on a graded mesh)
   const double Vc = P.graded ? A.zgeo[zgeo_volumes(P.nz) + c / (P.nx * P.ny)] : P.Vc;

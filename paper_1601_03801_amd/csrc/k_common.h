@@ -71,6 +71,34 @@ __device__ __forceinline__ void kick_drift_one(const DevParams& P, const DevArra
   if (over && __lane_id() == __ffsll((long long)over) - 1) atomicOr(rb, 1);
 }
 
+// Counting-sort ranks for a whole wave (every lane calls it): each valid lane
+// gets a slot among the members of its key, counts[key] growing by the
+// number of lanes with that key.  The lanes are grouped by key first (ballots
+// only), then every group's first lane adds its group's size with one atomic,
+// all groups at once, so a wave waits for one atomic round trip, not one per
+// key.  Which slots a key's lanes get depends on the order the atomics of
+// different waves land in; the callers order each key's members afterwards.
+__device__ __forceinline__ int wave_ranks(int* counts, int key, bool valid) {
+  unsigned long long active = __ballot(valid);
+  const int lane = __lane_id();
+  int leader = lane, within = 0, size = 0;
+  while (active) {
+    const int l = __ffsll((long long)active) - 1;
+    const int kl = __shfl(key, l);
+    const unsigned long long grp = __ballot(valid && key == kl) & active;
+    if ((grp >> lane) & 1ull) {
+      leader = l;
+      within = (int)__popcll(grp & ((1ull << lane) - 1ull));
+      size = (int)__popcll(grp);
+    }
+    active &= ~grp;
+  }
+  int base = 0;
+  if (valid && leader == lane) base = atomicAdd(&counts[key], size);
+  base = __shfl(base, leader);
+  return base + within;
+}
+
 // Cell of height z on a graded mesh with faces zf[0..nz]: the k with
 // zf[k] <= z < zf[k + 1] (a point on a face belongs to the upper cell);
 // below the mesh (or NaN) the first cell, at or above the top the last.

@@ -81,19 +81,7 @@ __device__ __forceinline__ void keys_one(const DevParams& P, const DevArrays& A,
     b = A.bin_rank[bin_of(P, x.x, x.y, x.z)];
     A.key[p] = b;
   }
-  unsigned long long active = __ballot(valid);
-  const int lane = __lane_id();
-  int rank = 0;
-  while (active) {
-    const int leader = __ffsll((long long)active) - 1;
-    const int bl = __shfl(b, leader);
-    const unsigned long long grp = __ballot(b == bl) & active;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&A.bin_count[bl], (int)__popcll(grp));
-    base = __shfl(base, leader);
-    if ((grp >> lane) & 1ull) rank = base + (int)__popcll(grp & ((1ull << lane) - 1ull));
-    active &= ~grp;
-  }
+  const int rank = wave_ranks(A.bin_count, b, valid);
   if (valid) A.rank[p] = rank;
 }
 
