@@ -149,25 +149,6 @@ __global__ void k_permute(DevParams P, DevArrays A) {
   }
 }
 
-__global__ void k_copyback(DevParams P, DevArrays A) {
-  if (!gate(A.rb)) return;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < P.n;
-       q += gridDim.x * blockDim.x) {
-    A.pos[q] = A.pos_t[q];
-    A.vel[q] = A.vel_t[q];
-    A.omg[q] = A.omg_t[q];
-    A.acc[q] = A.acc_t[q];
-    A.alp[q] = A.alp_t[q];
-    A.fdr[q] = A.fdr_t[q];
-    A.wxi[q] = A.wxi_t[q];
-    A.wxi[(size_t)P.n + q] = A.wxi_t[(size_t)P.n + q];
-    A.id[q] = A.id_t[q];
-  }
-  // the bin counts are no longer needed: clear them for the next rebuild
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < P.nbins; b += gridDim.x * blockDim.x)
-    A.bin_count[b] = 0;
-}
-
 // Neighbour list of particle q: every particle in the 27 surrounding bins
 // within (pair range + skin), ordered by class: overlapping (in contact)
 // first, then within the lubrication range, then the rest; in bin-scan order
@@ -203,7 +184,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
   for (int q = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; q < P.n;
        q += gridDim.x * blockDim.x) {
     const int N = P.n;
-    const double4 xi = A.pos[q];
+    // the re-sorted state is still in the _t copies: the build reads
+    // positions, IDs and wall histories there and copies particle q back
+    const double4 xi = A.pos_t[q];
     const int bx = bin_coord(xi.x, P.hbx, P.nbx), by = bin_coord(xi.y, P.hby, P.nby),
               bz = bin_coord(xi.z, P.hbz, P.nbz);
     const int cxm = bx == 0 ? P.nbx - 1 : bx - 1, cxp = bx + 1 == P.nbx ? 0 : bx + 1;
@@ -234,7 +217,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 #pragma unroll 4
         for (int j = bs[t]; j < be[t]; ++j) {
           if (j == q) continue;
-          const double4 xj = A.pos[j];
+          const double4 xj = A.pos_t[j];
           const double ddx = WRAP ? (xj.x - xi.x) + sx : min_image(xj.x - xi.x, P.Lx, P.hLx);
           const double ddy = WRAP ? (xj.y - xi.y) + sy : min_image(xj.y - xi.y, P.Ly, P.hLy);
           const double ddz = xj.z - xi.z;
@@ -284,7 +267,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
       const int j = row[k];
       A.nbr[(size_t)w * N + q] = j;
       if (nc > 0) {
-        const int pid = A.id[j];
+        const int pid = A.id_t[j];
         int hit = -1;  // partner IDs in a list are distinct: at most one row matches
 #pragma unroll
         for (int r = 0; r < kMaxContacts; ++r) hit = cid[r] == pid ? r : hit;
@@ -297,11 +280,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         }
       }
     }
-    if (A.wxi[q].w != 0.0) mask |= 1u << 30;
-    if (A.wxi[(size_t)N + q].w != 0.0) mask |= 1u << 31;
+    const double4 wall0 = A.wxi_t[q], wall1 = A.wxi_t[(size_t)N + q];
+    if (wall0.w != 0.0) mask |= 1u << 30;
+    if (wall1.w != 0.0) mask |= 1u << 31;
     A.hmask[q] = mask;
     if (matched != nc) atomicOr(&A.ctl->flags, kFlagLost);
+    A.pos[q] = xi;
+    A.vel[q] = A.vel_t[q];
+    A.omg[q] = A.omg_t[q];
+    A.acc[q] = A.acc_t[q];
+    A.alp[q] = A.alp_t[q];
+    A.fdr[q] = A.fdr_t[q];
+    A.wxi[q] = wall0;
+    A.wxi[(size_t)N + q] = wall1;
+    A.id[q] = A.id_t[q];
   }
+  // the bin counts are no longer needed: clear them for the next rebuild
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < P.nbins; b += gridDim.x * blockDim.x)
+    A.bin_count[b] = 0;
   // the largest list: one atomic per wave, not per particle (all lanes of
   // the wave are back together here)
   for (int o = 32; o > 0; o >>= 1) {
@@ -459,7 +455,7 @@ void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixe
   if (P.n <= 0) return;
   unsigned g = gated_grid(P.n);
   // the bin counts are zero here: set_particles clears them and every
-  // rebuild clears them again in k_copyback
+  // rebuild clears them again in k_build
   if (!from_slots)
     hipLaunchKernelGGL((k_compact_keys<double, false>), dim3(g), dim3(kBlock), 0, s, P, A);
   else if (mixed)
@@ -470,7 +466,6 @@ void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixe
   hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_binsort, dim3(gated_grid(P.nbins)), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_permute, dim3(g), dim3(kBlock), 0, s, P, A);
-  hipLaunchKernelGGL(k_copyback, dim3(g), dim3(kBlock), 0, s, P, A);
   // the list build is latency bound: every particle gets its own lane (the
   // grid a multiple of the XCD count for the block renumbering)
   const unsigned gb = xcd_grid(nblk(P.n) < 8192 ? nblk(P.n) : 8192);
