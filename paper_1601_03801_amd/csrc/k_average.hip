@@ -417,14 +417,15 @@ template <bool COMB>
 __global__ void k_applyA(Stencil S, const double* __restrict__ in, double* __restrict__ out,
                          double alpha, double beta, double gamma,
                          const double* __restrict__ other) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= S.nx) return;
+  // one lane per cell over the flat index (full waves whatever n_x is);
+  // the channel is blockIdx.z
   const size_t off = (size_t)blockIdx.z * S.ncell;
   const double* x = in + off;
   const int plane = S.nx * S.ny;
-  for (int jk = blockIdx.y; jk < S.ny * S.nz; jk += gridDim.y) {
+  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < S.ncell;
+       c += gridDim.x * blockDim.x) {
+    const int i = c % S.nx, jk = c / S.nx;
     const int j = jk % S.ny, k = jk / S.ny;
-    const int c = jk * S.nx + i;
     const double xc = x[c];
     const int ip = i + 1 == S.nx ? c - i : c + 1;
     const int im = i == 0 ? c + S.nx - 1 : c - 1;
@@ -460,7 +461,7 @@ constexpr int kMaxCh = 7;
 __global__ void k_check(int ncell, int nch, const double* __restrict__ Ay,
                         const double* __restrict__ raw, const double* __restrict__ y,
                         uint64_t seed, uint64_t thresh, double* __restrict__ part) {
-  __shared__ double s[2 * kMaxCh][kBlock];
+  __shared__ double s[kBlock / 64][2 * kMaxCh];
   int c = blockIdx.x * blockDim.x + threadIdx.x;
   double v[2 * kMaxCh];
 #pragma unroll
@@ -475,18 +476,26 @@ __global__ void k_check(int ncell, int nch, const double* __restrict__ Ay,
       v[kMaxCh + ch] = y[o] * y[o];
     }
   }
+  // butterfly within each wave, then the waves' sums in wave order: a fixed
+  // order, so the partials are reproducible
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-  for (int q = 0; q < 2 * kMaxCh; ++q) s[q][threadIdx.x] = v[q];
-  __syncthreads();
-  for (int w = kBlock / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w)
-      for (int q = 0; q < 2 * kMaxCh; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + w];
-    __syncthreads();
+  for (int q = 0; q < 2 * kMaxCh; ++q) {
+    if ((q < kMaxCh ? q : q - kMaxCh) >= nch) continue;
+    double x = v[q];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) s[wid][q] = x;
   }
+  __syncthreads();
   if (threadIdx.x == 0)
     for (int ch = 0; ch < nch; ++ch) {
-      part[(size_t)blockIdx.x * 2 * nch + ch] = s[ch][0];
-      part[(size_t)blockIdx.x * 2 * nch + nch + ch] = s[kMaxCh + ch][0];
+      double r = 0.0, yy = 0.0;
+      for (int w = 0; w < kBlock / 64; ++w) {
+        r += s[w][ch];
+        yy += s[w][kMaxCh + ch];
+      }
+      part[(size_t)blockIdx.x * 2 * nch + ch] = r;
+      part[(size_t)blockIdx.x * 2 * nch + nch + ch] = yy;
     }
 }
 
@@ -594,8 +603,7 @@ const double* apply_An(const DevParams& P, DevArrays& A, const double* y, int nc
                        double tau, hipStream_t s) {
   double dtau = tau / (ntau > 0 ? ntau : 1);
   const Stencil S = make_stencil(P, A, dtau);
-  const int rows = P.ny * P.nz;
-  dim3 grid((unsigned)((P.nx + kBlock - 1) / kBlock), (unsigned)(rows < 65535 ? rows : 65535), nch);
+  const dim3 grid(nblk(P.ncell), 1, nch);
   const double* cur = y;
   double* bufs[2] = {A.sd0, A.sd1};
   for (int m = 0; m < ntau; ++m) {
@@ -642,8 +650,7 @@ int launch_check_bdf2(const DevParams& P, DevArrays& A, int nch, int ntau, doubl
   const int N = ntau > 0 ? ntau : 1;
   const double dtau = tau / N;
   const Stencil S = make_stencil(P, A, dtau);
-  const int rows = P.ny * P.nz;
-  dim3 grid((unsigned)((P.nx + kBlock - 1) / kBlock), (unsigned)(rows < 65535 ? rows : 65535), nch);
+  const dim3 grid(nblk(P.ncell), 1, nch);
   // A = I + M, so (3 + 2M) x = 2 A x + x
   auto comb = [&](const double* in, double* out, double al, double be, double ga,
                   const double* other) {
