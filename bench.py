@@ -67,8 +67,8 @@ def averaging_rooflines(n, ncell, dep_ms, smooth_ms, direct, mesh, nch=4):
 # written).  Valid only for the kernel sources it was measured on.
 FORCE_PMC = {
     ("bed1m", "fp64"): {
-        "fetch_kib": 315500.6, "write_kib": 277638.8, "fetch_scale": 2.0, "write_scale": 1.0,
-        "sources_sha256": "46dcf1d43f7fe3e77ef26ad31735112f75495dfad7053a441342305b92a5bc13",
+        "fetch_kib": 315483.9, "write_kib": 277638.8, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sources_sha256": "6d36f929c818e89a59d1c3c663da8b621c4c82267fcf6eb72f50a198f02f2707",
         "profile": "profiles/k_forces_bed1m_fp64.md"},
 }
 FORCE_SOURCES = ("k_forces.hip", "k_common.h", "sedimi_internal.h")
