@@ -39,7 +39,7 @@ namespace sedimi {
 
 namespace {
 
-constexpr int kTM = 64, kTN = 64, kTK = 16;
+constexpr int kTN = 64, kTK = 16;
 
 // C[b] = alpha * A[b] * B[b] (row-major, FP64), optional spectral epilogue:
 // with a = dtau (lam_m[m] + lam_x[j % nx] + lam_y[j / nx]), C[m][j] is scaled
@@ -64,35 +64,41 @@ struct Gemm {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <bool SPECTRAL>
+// TM rows x kTN columns per block; each of the 4 waves computes a
+// (TM / 2) x 32 quarter as MI x 2 MFMA tiles of 16 x 16.
+template <bool SPECTRAL, int TM>
 __global__ __launch_bounds__(256) void k_gemm64(Gemm g) {
-  __shared__ double As[kTK][kTM + 1];
+  constexpr int MI = TM / 32;
+  __shared__ double As[kTK][TM + 1];
   __shared__ double Bs[kTK][kTN];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;  // the wave's 32 x 32 quarter of the tile
+  const int wm = wave >> 1, wn = wave & 1;  // the wave's quarter of the tile
   const int lr = lane & 15, lk = lane >> 4;
-  const int m0 = blockIdx.y * kTM, n0 = blockIdx.x * kTN;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * kTN;
   const int64_t b = blockIdx.z;
   const double* A = g.A + b * g.sa;
   const double* B = g.B + b * g.sb;
   double* C = g.C + b * g.sc;
-  v4d acc[2][2];
+  v4d acc[MI][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
   // The next K chunk is loaded into registers while the current one, already
   // in LDS, feeds the matrix cores.
-  double ra[4], rb[4];
+  double ra[TM / 16], rb[4];
   auto fetch = [&](int k0) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      // A: 64 rows x 16 k, read along k (contiguous)
+    for (int s = 0; s < TM / 16; ++s) {
+      // A: TM rows x 16 k, read along k (contiguous)
       const int r = (tid >> 4) + 16 * s, c = tid & 15;
       const int m = m0 + r, k = k0 + c;
       ra[s] = (m < g.M && k < g.K) ? A[(int64_t)m * g.lda + k] : 0.0;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
       // B: 16 k x 64 columns, read along the columns (contiguous)
       const int idx = tid + 256 * s;
       const int rr = idx >> 6, cc = idx & 63;
@@ -103,8 +109,9 @@ __global__ __launch_bounds__(256) void k_gemm64(Gemm g) {
   fetch(0);
   for (int k0 = 0; k0 < g.K; k0 += kTK) {
 #pragma unroll
+    for (int s = 0; s < TM / 16; ++s) As[tid & 15][(tid >> 4) + 16 * s] = ra[s];  // k-major
+#pragma unroll
     for (int s = 0; s < 4; ++s) {
-      As[tid & 15][(tid >> 4) + 16 * s] = ra[s];  // stored k-major
       const int idx = tid + 256 * s;
       Bs[idx >> 6][idx & 63] = rb[s];
     }
@@ -114,13 +121,13 @@ __global__ __launch_bounds__(256) void k_gemm64(Gemm g) {
     // of each 16 x 4 / 4 x 16 fragment
 #pragma unroll
     for (int kk = 0; kk < kTK; kk += 4) {
-      double a[2], bb[2];
+      double a[MI], bb[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[kk + lk][wm * 32 + i * 16 + lr];
+      for (int i = 0; i < MI; ++i) a[i] = As[kk + lk][wm * (TM / 2) + i * 16 + lr];
 #pragma unroll
       for (int j = 0; j < 2; ++j) bb[j] = Bs[kk + lk][wn * 32 + j * 16 + lr];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
@@ -130,12 +137,12 @@ __global__ __launch_bounds__(256) void k_gemm64(Gemm g) {
   // result layout (checked on the device): element r of lane (lr, lk) is row
   // lk + 4 r, column lr of each 16 x 16 tile
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int m = m0 + wm * 32 + i * 16 + lk + 4 * r;
+      const int m = m0 + wm * (TM / 2) + i * 16 + lk + 4 * r;
       const int n = n0 + wn * 32 + j * 16 + lr;
       if (m >= g.M || n >= g.N) continue;
       double v = g.alpha * acc[i][j][r];
@@ -161,13 +168,16 @@ __global__ __launch_bounds__(256) void k_gemm64(Gemm g) {
     }
 }
 
+// 32-row tiles: the transform passes move little data per block, so twice
+// the blocks (more waves per SIMD to cover the memory latency) beat the
+// larger tile's operand reuse.
 void gemm(const Gemm& g, int batch, bool spectral, hipStream_t s) {
-  dim3 grid((unsigned)((g.N + kTN - 1) / kTN), (unsigned)((g.M + kTM - 1) / kTM),
-            (unsigned)batch);
+  constexpr int TM = 32;
+  dim3 grid((unsigned)((g.N + kTN - 1) / kTN), (unsigned)((g.M + TM - 1) / TM), (unsigned)batch);
   if (spectral)
-    hipLaunchKernelGGL(k_gemm64<true>, grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_gemm64<true, TM>), grid, dim3(256), 0, s, g);
   else
-    hipLaunchKernelGGL(k_gemm64<false>, grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((k_gemm64<false, TM>), grid, dim3(256), 0, s, g);
 }
 
 }  // namespace
