@@ -380,8 +380,8 @@ int sedimi_nn_init(sedimi_ctx* ctx, uint64_t seed);
 int sedimi_nn_set_params(sedimi_ctx* ctx, const float* p, int64_t n);
 int sedimi_nn_get_params(sedimi_ctx* ctx, float* p, int64_t n);
 /* The trained network as one host blob, so that training resumes exactly: a
- * header (magic, parameter count, leaky-ReLU slope, Adam step count, the
- * per-channel standardisation and loss weights) followed by the FP32
+ * header (magic, parameter count, Adam step count, channel groups, leaky-ReLU
+ * slope, the per-channel standardisation and loss weights) followed by the FP32
  * parameters and Adam's first and second moments (3 x count floats).
  * save: *size_out receives the blob size; the blob is written only if buf is
  * non-NULL and cap >= that size, else ENOMEM when buf is non-NULL.
