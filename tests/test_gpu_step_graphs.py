@@ -81,3 +81,34 @@ def test_steps_with_a_readback_are_not_captured():
             g.step(ns, average_every=5)
         _same(a, b, f"iterative {ns}")
     assert a.stats()["graph_steps"] == 1  # only the middle call has no averaging
+
+
+def test_network_averaging_is_not_captured():
+    """With the network answering the averaging (surrogate mode), a call
+    whose steps include an averaging runs kernel by kernel and a call
+    without one is replayed; both match a context without replay bit for
+    bit."""
+    import paper_1601_03801_amd as sm
+    case = dense_bed(3000, 41)
+    dmax = float(case["d"].max())
+
+    def ctx():
+        g = sm.Sedimi(dict(case["params"]), len(case["d"]), precision="mixed", d_max=dmax,
+                      skin=0.1 * dmax, max_neighbors=24, nn=True, nn_alpha=1.0)
+        g.set_fluid(case["U"], case["gradp"], case["dudt"])
+        g.set_particles(case["x"], case["v"], case["d"], case["rho"], omega=case["w"])
+        g.nn_set_groups(4)
+        g.nn_init(3)
+        g.average()
+        g.set_avg_mode(sm.AVG_SURROGATE)
+        return g
+
+    a, b = ctx(), ctx()
+    b.set_step_graphs(False)
+    for ns in (5, 4, 1, 4):
+        for g in (a, b):
+            g.step(ns, average_every=5)
+        _same(a, b, f"surrogate {ns}")
+    # steps 6-9 and 11-14 have no averaging; 1-5 and 10 end in one
+    assert a.stats()["graph_steps"] == 2
+    assert a.stats()["nn_calls"] == b.stats()["nn_calls"] == 2
