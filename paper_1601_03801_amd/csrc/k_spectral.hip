@@ -168,16 +168,25 @@ __global__ __launch_bounds__(256) void k_gemm64(Gemm g) {
     }
 }
 
-// 32-row tiles: the transform passes move little data per block, so twice
-// the blocks (more waves per SIMD to cover the memory latency) beat the
-// larger tile's operand reuse.
-void gemm(const Gemm& g, int batch, bool spectral, hipStream_t s) {
-  constexpr int TM = 32;
+// Row tile: 64 when that already gives the chip thousands of blocks (the
+// larger tile reuses its B operand twice as often), 32 on smaller fields,
+// where twice the blocks (more waves per SIMD to cover the memory latency)
+// win over that reuse.
+constexpr int64_t kGemmBlocksFor64 = 1024;
+template <int TM>
+void gemm_tm(const Gemm& g, int batch, bool spectral, hipStream_t s) {
   dim3 grid((unsigned)((g.N + kTN - 1) / kTN), (unsigned)((g.M + TM - 1) / TM), (unsigned)batch);
   if (spectral)
     hipLaunchKernelGGL((k_gemm64<true, TM>), grid, dim3(256), 0, s, g);
   else
     hipLaunchKernelGGL((k_gemm64<false, TM>), grid, dim3(256), 0, s, g);
+}
+void gemm(const Gemm& g, int batch, bool spectral, hipStream_t s) {
+  const int64_t blocks64 = (int64_t)((g.N + kTN - 1) / kTN) * ((g.M + 63) / 64) * batch;
+  if (blocks64 >= kGemmBlocksFor64)
+    gemm_tm<64>(g, batch, spectral, s);
+  else
+    gemm_tm<32>(g, batch, spectral, s);
 }
 
 }  // namespace
