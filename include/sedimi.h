@@ -356,7 +356,7 @@ int sedimi_set_avg_mode(sedimi_ctx* ctx, int mode);
  * activations, FP32 accumulation and output.
  * Parameters are a flat FP32 vector: per layer w[27][cin][cout] then b[cout],
  * tap t = (dz+1)*9 + (dy+1)*3 + (dx+1).  The plain solve stays the fallback
- * and the judge: a checked averaging estimates the network's error on a
+ * and the reference: a checked averaging estimates the network's error on a
  * seeded sample of whole z-columns (the nn_sample share of the columns, so of
  * the cells), where the plain solution is the Green's function G of all ntau
  * implicit steps of Eq. 12, (I - dtau L_h)^-ntau, applied to RAW: over a
