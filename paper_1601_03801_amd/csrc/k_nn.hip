@@ -815,71 +815,146 @@ __global__ void k_split_line(int nx, int ny, int nz, int axis, int off0, int nta
   }
 }
 
-// S_z: ntau backward-Euler steps along z with zero-flux walls, in place, for
-// kSplitCols consecutive columns per block held in LDS (FP64 sums, FP32
-// storage).  tab: reciprocal pivots [nz] then the Thomas multipliers [nz] of
-// the tridiagonal (1 + c n_k) u_k - c u_{k-1} - c u_{k+1}, n_k the number of
-// neighbours of plane k.
-constexpr int kSplitCols = 64;
-__global__ __launch_bounds__(kSplitCols) void k_split_z(int nx, int ny, int nz, int ntau,
-                                                        double c, const double* __restrict__ tab,
-                                                        float4* __restrict__ f) {
-  extern __shared__ float4 col[];  // [nz][kSplitCols]
+// The same circulant with the lines staged in LDS, so that each cell is read
+// from memory once and its ntap reads come from LDS: along x a block holds
+// whole x-lines, along y a tile of kSplitTX consecutive x-columns of one
+// z-plane over the whole y-line.  Same taps and FP64 sums in the same order,
+// so the same bits as k_split_line.
+constexpr int kSplitTX = 16;
+__global__ __launch_bounds__(256) void k_split_x_lds(int nx, int ny, int nz, int off0, int ntap,
+                                                     const double* __restrict__ tap,
+                                                     const float4* __restrict__ in,
+                                                     float4* __restrict__ out) {
+  extern __shared__ float4 line[];  // [nx]
+  const int64_t nlines = (int64_t)ny * nz;
+  for (int64_t l = blockIdx.x; l < nlines; l += gridDim.x) {
+    const int64_t base = l * nx;
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) line[i] = in[base + i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) {
+      int q = (i + off0) % nx;
+      q = q < 0 ? q + nx : q;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      for (int t = 0; t < ntap; ++t) {
+        const float4 v = line[q];
+        const double w = tap[t];
+        a0 += w * v.x, a1 += w * v.y, a2 += w * v.z, a3 += w * v.w;
+        q = q + 1 == nx ? 0 : q + 1;
+      }
+      out[base + i] = make_float4((float)a0, (float)a1, (float)a2, (float)a3);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void k_split_y_lds(int nx, int ny, int nz, int off0, int ntap,
+                                                     const double* __restrict__ tap,
+                                                     const float4* __restrict__ in,
+                                                     float4* __restrict__ out) {
+  extern __shared__ float4 tile[];  // [ny][kSplitTX]
+  const int ntx = (nx + kSplitTX - 1) / kSplitTX;
+  const int64_t ntiles = (int64_t)ntx * nz;
+  for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
+    const int k = (int)(b / ntx), x0 = (int)(b % ntx) * kSplitTX;
+    const int tw = nx - x0 < kSplitTX ? nx - x0 : kSplitTX;
+    const int64_t plane = (int64_t)k * ny * nx;
+    for (int e = threadIdx.x; e < ny * kSplitTX; e += blockDim.x) {
+      const int y = e / kSplitTX, x = e % kSplitTX;
+      if (x < tw) tile[e] = in[plane + (int64_t)y * nx + x0 + x];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < ny * kSplitTX; e += blockDim.x) {
+      const int y = e / kSplitTX, x = e % kSplitTX;
+      if (x >= tw) continue;
+      int q = (y + off0) % ny;
+      q = q < 0 ? q + ny : q;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      for (int t = 0; t < ntap; ++t) {
+        const float4 v = tile[q * kSplitTX + x];
+        const double w = tap[t];
+        a0 += w * v.x, a1 += w * v.y, a2 += w * v.z, a3 += w * v.w;
+        q = q + 1 == ny ? 0 : q + 1;
+      }
+      out[plane + (int64_t)y * nx + x0 + x] = make_float4((float)a0, (float)a1, (float)a2, (float)a3);
+    }
+    __syncthreads();
+  }
+}
+
+// S_z: ntau backward-Euler steps along z with zero-flux walls, in place.  A
+// block of 64 lanes takes kSplitCols consecutive columns, one lane per
+// (column, channel) pair, the columns held in LDS as FP32 (FP64 sums):
+// 16 columns x nz planes x 4 channels, 32 KB at nz = 128, so several blocks
+// share a CU.  tab: reciprocal pivots [nz] then the Thomas multipliers [nz]
+// of the tridiagonal (1 + c n_k) u_k - c u_{k-1} - c u_{k+1}, n_k the number
+// of neighbours of plane k.
+constexpr int kSplitCols = 16;
+__global__ __launch_bounds__(64) void k_split_z(int nx, int ny, int nz, int ntau, double c,
+                                                const double* __restrict__ tab,
+                                                float4* __restrict__ f4) {
+  extern __shared__ float col[];  // [nz][kSplitCols * 4]
+  constexpr int W = kSplitCols * 4;
+  float* f = reinterpret_cast<float*>(f4);
   const int64_t plane = (int64_t)nx * ny;
   const int64_t c0 = (int64_t)blockIdx.x * kSplitCols;
-  const int t = threadIdx.x;
-  const bool live = c0 + t < plane;
+  const int t = threadIdx.x;  // column c0 + t / 4, channel t % 4
+  const bool live = c0 + t / 4 < plane;
   for (int k = 0; k < nz; ++k)
-    if (live) col[k * kSplitCols + t] = f[k * plane + c0 + t];
+    if (live) col[k * W + t] = f[(k * plane + c0) * 4 + t];
   if (live && nz > 1) {
     const double* ib = tab;       // 1 / pivot
     const double* gm = tab + nz;  // multiplier of the back substitution
     for (int s = 0; s < ntau; ++s) {
       // forward sweep: u_k = (f_k + c u_{k-1}) / pivot_k
-      float4 v = col[t];
-      double p0 = v.x * ib[0], p1 = v.y * ib[0], p2 = v.z * ib[0], p3 = v.w * ib[0];
-      col[t] = make_float4((float)p0, (float)p1, (float)p2, (float)p3);
+      double p = col[t] * ib[0];
+      col[t] = (float)p;
       for (int k = 1; k < nz; ++k) {
-        v = col[k * kSplitCols + t];
-        p0 = (v.x + c * p0) * ib[k];
-        p1 = (v.y + c * p1) * ib[k];
-        p2 = (v.z + c * p2) * ib[k];
-        p3 = (v.w + c * p3) * ib[k];
-        col[k * kSplitCols + t] = make_float4((float)p0, (float)p1, (float)p2, (float)p3);
+        p = (col[k * W + t] + c * p) * ib[k];
+        col[k * W + t] = (float)p;
       }
       // back substitution: u_k -= gamma_{k+1} u_{k+1}, carried in FP64
       for (int k = nz - 2; k >= 0; --k) {
-        v = col[k * kSplitCols + t];
-        p0 = v.x - gm[k + 1] * p0;
-        p1 = v.y - gm[k + 1] * p1;
-        p2 = v.z - gm[k + 1] * p2;
-        p3 = v.w - gm[k + 1] * p3;
-        col[k * kSplitCols + t] = make_float4((float)p0, (float)p1, (float)p2, (float)p3);
+        p = col[k * W + t] - gm[k + 1] * p;
+        col[k * W + t] = (float)p;
       }
     }
   }
   for (int k = 0; k < nz; ++k)
-    if (live) f[k * plane + c0 + t] = col[k * kSplitCols + t];
+    if (live) f[(k * plane + c0) * 4 + t] = col[k * W + t];
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-size_t split_lds_bytes(int nz) { return (size_t)nz * kSplitCols * sizeof(float4); }
+size_t split_lds_bytes(int nz) { return (size_t)nz * kSplitCols * 4 * sizeof(float); }
 
 void launch_split(int nx, int ny, int nz, int ntau, const SplitTabs& st, const float* in,
                   float* tmp, float* out, hipStream_t s) {
   const int64_t ncell = (int64_t)nx * ny * nz;
   const unsigned g = (unsigned)std::min<int64_t>((ncell + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_split_line, dim3(g), dim3(256), 0, s, nx, ny, nz, 0, st.off0x, st.ntapx,
-                     st.tapx, (const float4*)in, (float4*)tmp);
-  hipLaunchKernelGGL(k_split_line, dim3(g), dim3(256), 0, s, nx, ny, nz, 1, st.off0y, st.ntapy,
-                     st.tapy, (const float4*)tmp, (float4*)out);
+  // LDS-staged lines when a line (x) or a y-tile fits in 32 KB
+  constexpr size_t kSplitLds = 32768;
+  const size_t bx = (size_t)nx * sizeof(float4), by = (size_t)ny * kSplitTX * sizeof(float4);
+  const int64_t nxl = (int64_t)ny * nz, nyt = (int64_t)((nx + kSplitTX - 1) / kSplitTX) * nz;
+  if (bx <= kSplitLds)
+    hipLaunchKernelGGL(k_split_x_lds, dim3((unsigned)std::min<int64_t>(nxl, 8192)), dim3(256), bx,
+                       s, nx, ny, nz, st.off0x, st.ntapx, st.tapx, (const float4*)in,
+                       (float4*)tmp);
+  else
+    hipLaunchKernelGGL(k_split_line, dim3(g), dim3(256), 0, s, nx, ny, nz, 0, st.off0x, st.ntapx,
+                       st.tapx, (const float4*)in, (float4*)tmp);
+  if (by <= kSplitLds)
+    hipLaunchKernelGGL(k_split_y_lds, dim3((unsigned)std::min<int64_t>(nyt, 8192)), dim3(256), by,
+                       s, nx, ny, nz, st.off0y, st.ntapy, st.tapy, (const float4*)tmp,
+                       (float4*)out);
+  else
+    hipLaunchKernelGGL(k_split_line, dim3(g), dim3(256), 0, s, nx, ny, nz, 1, st.off0y, st.ntapy,
+                       st.tapy, (const float4*)tmp, (float4*)out);
   const int64_t plane = (int64_t)nx * ny;
   hipLaunchKernelGGL(k_split_z, dim3((unsigned)((plane + kSplitCols - 1) / kSplitCols)),
-                     dim3(kSplitCols), split_lds_bytes(nz), s, nx, ny, nz, ntau, st.cz, st.ztab,
-                     (float4*)out);
+                     dim3(kSplitCols * 4), split_lds_bytes(nz), s, nx, ny, nz, ntau, st.cz,
+                     st.ztab, (float4*)out);
 }
 
 size_t nn_packed_elems(int cin, int cout) {
