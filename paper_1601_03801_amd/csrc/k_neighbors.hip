@@ -156,10 +156,13 @@ __global__ void k_permute(DevParams P, DevArrays A) {
 // lockstep and runs the contact and lubrication code for a slot when any lane
 // needs it, so putting each list's contacts first about halves the slots
 // that run the contact code (and touch the tangential history).
-// One pass over the bins, a row of three (consecutive x) at a time: a row's
-// member ranges are loaded together (two memory round trips per row, not per
-// bin), then its candidates are tested in bin-scan order and parked with
-// their class in the lane's row of LDS.  The list is then written class by
+// One pass over the bins, a row of three (consecutive x) at a time: the
+// bin ranks of the next row are loaded while a row is tested, a row's three
+// member ranges are loaded together and joined into one run of candidates,
+// whose positions are loaded kBuildBatch at a time (a lane waits on one
+// memory round trip per batch, not per candidate or per bin).  Candidates
+// are tested in bin-scan order and parked with their class in the lane's row
+// of LDS.  The list is then written class by
 // class, and each slot's tangential history is matched by partner ID against
 // the contact rows of q's pre-sort position, whose IDs are held in
 // registers.
@@ -173,6 +176,7 @@ __global__ void k_permute(DevParams P, DevArrays A) {
 constexpr int kBuildStride = 31;  // LDS row of a lane: >= max_neighbors, odd (no bank conflicts)
 static_assert(kBuildStride >= 30, "a lane's LDS row must hold max_neighbors (<= 30) slots");
 constexpr int kWrapMinBins = 5;
+constexpr int kBuildBatch = 6;  // candidate loads in flight per lane
 template <typename H, bool WRAP>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) void k_build(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
@@ -195,44 +199,89 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     // and more than maxn overflow the list
     int seen = 0;
     unsigned long long cls = 0;  // 2 bits of class per kept candidate
-#pragma unroll 1
-    for (int r = 0; r < 9; ++r) {
+    // bin ranks of a row (all -1 when the row lies outside the grid in z) and
+    // the bounds of its three member ranges: a row's ranges are loaded while
+    // the row before it is tested, and its ranks one row earlier still
+    auto row_ranks = [&](int r, int (&rk)[3]) {
       const int cz = bz + r / 3 - 1;
-      if (cz < 0 || cz >= P.nbz) continue;
-      int cy = by + r % 3 - 1;
-      const double sy = cy < 0 ? -P.Ly : (cy >= P.nby ? P.Ly : 0.0);
-      cy = cy < 0 ? cy + P.nby : (cy >= P.nby ? cy - P.nby : cy);
-      const int base = (cz * P.nby + cy) * P.nbx;
-      int bs[3], be[3];
+      rk[0] = rk[1] = rk[2] = -1;
+      if (r < 9 && cz >= 0 && cz < P.nbz) {
+        int cy = by + r % 3 - 1;
+        cy = cy < 0 ? cy + P.nby : (cy >= P.nby ? cy - P.nby : cy);
+        const int base = (cz * P.nby + cy) * P.nbx;
+        rk[0] = A.bin_rank[base + cxm];
+        rk[1] = A.bin_rank[base + bx];
+        rk[2] = A.bin_rank[base + cxp];
+      }
+    };
+    auto row_bounds = [&](const int (&rk)[3], int (&lo)[3], int (&hi)[3]) {
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
-        const int bin = A.bin_rank[base + (t == 0 ? cxm : (t == 1 ? bx : cxp))];
-        bs[t] = A.bin_start[bin];
-        be[t] = A.bin_start[bin + 1];
-        if (be[t] - bs[t] > kMaxBinMembers) be[t] = bs[t];  // flagged by k_binsort
+        lo[t] = rk[0] >= 0 ? A.bin_start[rk[t]] : 0;
+        hi[t] = rk[0] >= 0 ? A.bin_start[rk[t] + 1] : 0;
+      }
+    };
+    int rk_next[3], lo[3], hi[3];
+    row_ranks(0, rk_next);
+    row_bounds(rk_next, lo, hi);
+    row_ranks(1, rk_next);
+    const double sx0 = bx == 0 ? -P.Lx : 0.0, sx2 = bx + 1 == P.nbx ? P.Lx : 0.0;
+#pragma unroll 1
+    for (int r = 0; r < 9; ++r) {
+      int lo_next[3], hi_next[3];
+      row_bounds(rk_next, lo_next, hi_next);
+      row_ranks(r + 2, rk_next);
+      {
+        const int cyr = by + r % 3 - 1;
+        const double sy = cyr < 0 ? -P.Ly : (cyr >= P.nby ? P.Ly : 0.0);
+        // the row's three member ranges as one run of candidates (a crowded
+        // bin, flagged by k_binsort, counts as empty; a row outside the grid
+        // has none)
+        const int s0 = lo[0], s1 = lo[1], s2 = lo[2];
+        int n0 = hi[0] - s0, n1 = hi[1] - s1, n2 = hi[2] - s2;
+        n0 = n0 > kMaxBinMembers ? 0 : n0;
+        n1 = n1 > kMaxBinMembers ? 0 : n1;
+        n2 = n2 > kMaxBinMembers ? 0 : n2;
+        const int n01 = n0 + n1, nrow = n01 + n2;
+        // kBuildBatch candidates' loads in flight at once, then tested in
+        // scan order
+        for (int c0 = 0; c0 < nrow; c0 += kBuildBatch) {
+          int js[kBuildBatch];
+          double4 xs[kBuildBatch];
+#pragma unroll
+          for (int u = 0; u < kBuildBatch; ++u) {
+            const int c = c0 + u;
+            js[u] = c < n0 ? s0 + c : (c < n01 ? s1 + (c - n0) : s2 + (c - n01));
+            xs[u] = c < nrow ? A.pos_t[js[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+          }
+#pragma unroll
+          for (int u = 0; u < kBuildBatch; ++u) {
+            const int c = c0 + u;
+            const int j = js[u];
+            if (c >= nrow || j == q) continue;
+            const double4 xj = xs[u];
+            const double sx = c < n0 ? sx0 : (c < n01 ? 0.0 : sx2);
+            const double ddx = WRAP ? (xj.x - xi.x) + sx : min_image(xj.x - xi.x, P.Lx, P.hLx);
+            const double ddy = WRAP ? (xj.y - xi.y) + sy : min_image(xj.y - xi.y, P.Ly, P.hLy);
+            const double ddz = xj.z - xi.z;
+            const double s2 = ddx * ddx + ddy * ddy + ddz * ddz;
+            const double rs = xi.w + xj.w;
+            const double Rl = rs + P.lub_out * rs + P.skin;
+            if (!(s2 < Rl * Rl * (1.0 + 1e-9))) continue;
+            const double Rp = rs + P.lub_out * rs;
+            const unsigned long long k = s2 < rs * rs ? 0 : (s2 < Rp * Rp ? 1 : 2);
+            if (seen < P.maxn) {
+              row[seen] = j;
+              cls |= k << (2 * seen);
+            }
+            ++seen;
+          }
+        }
       }
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
-        const double sx = t == 0 ? (bx == 0 ? -P.Lx : 0.0) : (t == 2 && bx + 1 == P.nbx ? P.Lx : 0.0);
-#pragma unroll 4
-        for (int j = bs[t]; j < be[t]; ++j) {
-          if (j == q) continue;
-          const double4 xj = A.pos_t[j];
-          const double ddx = WRAP ? (xj.x - xi.x) + sx : min_image(xj.x - xi.x, P.Lx, P.hLx);
-          const double ddy = WRAP ? (xj.y - xi.y) + sy : min_image(xj.y - xi.y, P.Ly, P.hLy);
-          const double ddz = xj.z - xi.z;
-          const double s2 = ddx * ddx + ddy * ddy + ddz * ddz;
-          const double rs = xi.w + xj.w;
-          const double Rl = rs + P.lub_out * rs + P.skin;
-          if (!(s2 < Rl * Rl * (1.0 + 1e-9))) continue;
-          const double Rp = rs + P.lub_out * rs;
-          const unsigned long long c = s2 < rs * rs ? 0 : (s2 < Rp * Rp ? 1 : 2);
-          if (seen < P.maxn) {
-            row[seen] = j;
-            cls |= c << (2 * seen);
-          }
-          ++seen;
-        }
+        lo[t] = lo_next[t];
+        hi[t] = hi_next[t];
       }
     }
     int cnt = seen;
@@ -260,24 +309,54 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
       w1 += c == 0;
       w2 += c != 2;
     }
-#pragma unroll 2
-    for (int k = 0; k < cnt; ++k) {
-      const int c = (int)((cls >> (2 * k)) & 3ull);
-      const int w = c == 0 ? w0++ : (c == 1 ? w1++ : w2++);
-      const int j = row[k];
-      A.nbr[(size_t)w * N + q] = j;
-      if (nc > 0) {
-        const int pid = A.id_t[j];
-        int hit = -1;  // partner IDs in a list are distinct: at most one row matches
+    // slots kBuildBatch at a time: the partners' IDs are gathered together,
+    // then the matched history rows, so a lane waits on two memory round
+    // trips per batch rather than on one or two per slot
+#pragma unroll 1
+    for (int k0 = 0; k0 < cnt; k0 += kBuildBatch) {
+      int jj[kBuildBatch], pid[kBuildBatch];
 #pragma unroll
-        for (int r = 0; r < kMaxContacts; ++r) hit = cid[r] == pid ? r : hit;
-        if (hit >= 0) {
-          hx[(size_t)w * N + q] = (H)A.cxi[((size_t)0 * kMaxContacts + hit) * N + p];
-          hy[(size_t)w * N + q] = (H)A.cxi[((size_t)1 * kMaxContacts + hit) * N + p];
-          hz[(size_t)w * N + q] = (H)A.cxi[((size_t)2 * kMaxContacts + hit) * N + p];
-          mask |= 1u << w;
-          ++matched;
+      for (int u = 0; u < kBuildBatch; ++u) {
+        const int k = k0 + u;
+        jj[u] = k < cnt ? row[k] : 0;
+        pid[u] = (k < cnt && nc > 0) ? A.id_t[jj[u]] : -1;
+      }
+      int hw[kBuildBatch], hr[kBuildBatch];
+#pragma unroll
+      for (int u = 0; u < kBuildBatch; ++u) {
+        const int k = k0 + u;
+        hw[u] = 0;
+        hr[u] = -1;
+        if (k < cnt) {
+          const int c = (int)((cls >> (2 * k)) & 3ull);
+          const int w = c == 0 ? w0++ : (c == 1 ? w1++ : w2++);
+          A.nbr[(size_t)w * N + q] = jj[u];
+          // partner IDs in a list are distinct: at most one row matches
+          int hit = -1;
+#pragma unroll
+          for (int r = 0; r < kMaxContacts; ++r) hit = pid[u] >= 0 && cid[r] == pid[u] ? r : hit;
+          hw[u] = w;
+          hr[u] = hit;
         }
+      }
+      double gx[kBuildBatch], gy[kBuildBatch], gz[kBuildBatch];
+#pragma unroll
+      for (int u = 0; u < kBuildBatch; ++u) {
+        gx[u] = gy[u] = gz[u] = 0.0;
+        if (hr[u] >= 0) {
+          gx[u] = A.cxi[((size_t)0 * kMaxContacts + hr[u]) * N + p];
+          gy[u] = A.cxi[((size_t)1 * kMaxContacts + hr[u]) * N + p];
+          gz[u] = A.cxi[((size_t)2 * kMaxContacts + hr[u]) * N + p];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kBuildBatch; ++u) {
+        if (hr[u] < 0) continue;
+        hx[(size_t)hw[u] * N + q] = (H)gx[u];
+        hy[(size_t)hw[u] * N + q] = (H)gy[u];
+        hz[(size_t)hw[u] * N + q] = (H)gz[u];
+        mask |= 1u << hw[u];
+        ++matched;
       }
     }
     const double4 wall0 = A.wxi_t[q], wall1 = A.wxi_t[(size_t)N + q];
