@@ -69,7 +69,7 @@ __device__ __forceinline__ void compact_one(const DevParams& P, const DevArrays&
 }
 
 // Bin key of particle p (bins in Morton order) and its rank among the bin's
-// members (any order: k_binsort orders each bin by ID).  Particles still in
+// members (any order: k_permute orders each bin by ID).  Particles still in
 // the last sorted order mostly share a bin with their wave neighbours: each
 // group of lanes with one bin takes its ranks with a single atomic add.
 // Every lane of the wave calls this (valid says whether p is a particle).
@@ -109,34 +109,29 @@ __global__ void k_scatter(DevParams P, DevArrays A) {
   }
 }
 
-// Order each bin's members by particle ID (bins hold a handful of particles).
-__global__ void k_binsort(DevParams P, DevArrays A) {
-  if (!gate(A.rb)) return;
-  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < P.nbins;
-       b += gridDim.x * blockDim.x) {
-    int s = A.bin_start[b], e = A.bin_start[b + 1];
-    if (e - s > kMaxBinMembers) {
-      atomicOr(&A.ctl->flags, kFlagCrowded);
-      continue;
-    }
-    for (int i = s + 1; i < e; ++i) {
-      int p = A.perm[i];
-      int key = A.id[p];
-      int j = i - 1;
-      while (j >= s && A.id[A.perm[j]] > key) {
-        A.perm[j + 1] = A.perm[j];
-        --j;
-      }
-      A.perm[j + 1] = p;
-    }
-  }
-}
-
+// Second half of the re-sort: k_scatter left each bin's members in arbitrary
+// order; every element takes its rank by particle ID among its bin's members
+// (bins hold a handful of particles, so each counts them all) and copies its
+// state into the spare copies at that place.  The sorted permutation goes to
+// A.rank, free once k_scatter has run, for the list build.  A crowded bin
+// keeps the scatter order and raises kFlagCrowded.
 __global__ void k_permute(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
-  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < P.n;
-       q += gridDim.x * blockDim.x) {
-    int p = A.perm[q];
+  for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < P.n;
+       m += gridDim.x * blockDim.x) {
+    const int p = A.perm[m];
+    const int b = A.key[p];
+    const int s = A.bin_start[b], e = A.bin_start[b + 1];
+    int q = m;
+    if (e - s > kMaxBinMembers) {
+      if (m == s) atomicOr(&A.ctl->flags, kFlagCrowded);
+    } else {
+      const int idp = A.id[p];
+      int r = 0;
+      for (int t = s; t < e; ++t) r += A.id[A.perm[t]] < idp;
+      q = s + r;
+    }
+    A.rank[q] = p;
     A.pos_t[q] = A.pos[p];
     A.vel_t[q] = A.vel[p];
     A.omg_t[q] = A.omg[p];
@@ -235,7 +230,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
         const int cyr = by + r % 3 - 1;
         const double sy = cyr < 0 ? -P.Ly : (cyr >= P.nby ? P.Ly : 0.0);
         // the row's three member ranges as one run of candidates (a crowded
-        // bin, flagged by k_binsort, counts as empty; a row outside the grid
+        // bin, flagged by k_permute, counts as empty; a row outside the grid
         // has none)
         const int s0 = lo[0], s1 = lo[1], s2 = lo[2];
         int n0 = hi[0] - s0, n1 = hi[1] - s1, n2 = hi[2] - s2;
@@ -292,8 +287,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
     most = cnt > most ? cnt : most;
     A.ncnt[q] = cnt;
     A.xb[q] = xi;
-    // contact rows of the pre-sort position perm[q]: partner IDs in registers
-    const int p = A.perm[q];
+    // contact rows of the pre-sort position p (the sorted permutation that
+    // k_permute left in A.rank): partner IDs in registers
+    const int p = A.rank[q];
     const int nc = A.ccnt[p];
     int cid[kMaxContacts];
 #pragma unroll
@@ -543,7 +539,6 @@ void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixe
     hipLaunchKernelGGL((k_compact_keys<double, true>), dim3(g), dim3(kBlock), 0, s, P, A);
   launch_exclusive_scan(A.bin_count, A.bin_start, P.nbins, A.scan_tmp, true, A.rb, s);
   hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, P, A);
-  hipLaunchKernelGGL(k_binsort, dim3(gated_grid(P.nbins)), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_permute, dim3(g), dim3(kBlock), 0, s, P, A);
   // the list build is latency bound: every particle gets its own lane (the
   // grid a multiple of the XCD count for the block renumbering)
