@@ -21,6 +21,10 @@ namespace {
 
 __device__ __forceinline__ bool gate(const int* flag) { return *flag != 0; }
 
+// exclusive scans of int counts: 1024 items per block
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kBlock * kScanItems;
+
 __global__ void k_zero_ints(int* p, int64_t n, int gated, const int* flag) {
   if (gated && !gate(flag)) return;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -101,12 +105,23 @@ __global__ void k_compact_keys(DevParams P, DevArrays A) {
 }
 
 
+// Scatter by bin, finishing the bin scan on the way: bin_count holds each
+// bin's exclusive prefix within its scan tile and scan_tmp the exclusive
+// offsets of the tiles, the total last (k_scan_bins).  A particle's slot is
+// its bin's start plus its rank; the blocks also write the final bin starts.
 __global__ void k_scatter(DevParams P, DevArrays A) {
   if (!gate(A.rb)) return;
+  const int* toff = A.scan_tmp;
   for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P.n;
        p += gridDim.x * blockDim.x) {
-    A.perm[A.bin_start[A.key[p]] + A.rank[p]] = p;
+    const int b = A.key[p];
+    A.perm[A.bin_count[b] + toff[b / kScanTile] + A.rank[p]] = p;
   }
+  for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < P.nbins;
+       b += gridDim.x * blockDim.x)
+    A.bin_start[b] = A.bin_count[b] + toff[b / kScanTile];
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    A.bin_start[P.nbins] = toff[(P.nbins + kScanTile - 1) / kScanTile];
 }
 
 // Second half of the re-sort: k_scatter left each bin's members in arbitrary
@@ -383,8 +398,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) voi
 }
 
 // ---- exclusive scan of int counts (2 passes, 1024 items per block) ----
-constexpr int kScanItems = 4;
-constexpr int kScanTile = kBlock * kScanItems;
 
 __device__ int block_exclusive(int v, int* lds, int* total) {
   int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -443,6 +456,55 @@ __global__ void k_scan_add(int* start, int n, const int* tile_sums, int ntiles, 
   for (int k = threadIdx.x; k < kScanTile; k += kBlock)
     if (base + k < n) start[base + k] += off;
   if (b == ntiles - 1 && threadIdx.x == 0) start[n] = off + tile_sums[b];
+}
+
+// The bin scan in one launch: each block turns its tile of counts in place
+// into exclusive prefixes within the tile and publishes the tile's total;
+// the block that finishes last (one atomic counter, nobody waits) turns the
+// totals into exclusive tile offsets, with the grand total after them, and
+// resets the counter.  k_scatter adds the offsets.  One block per tile.
+__global__ void k_scan_bins(int* cnt, int n, int* tiles, int* done, const int* flag) {
+  if (!gate(flag)) return;
+  __shared__ int lds[kBlock / 64];
+  __shared__ int last;
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int sum = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? cnt[base + k] : 0;
+    sum += v[k];
+  }
+  int tot;
+  int ex = block_exclusive(sum, lds, &tot);
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) cnt[base + k] = ex;
+    ex += v[k];
+  }
+  if (threadIdx.x == 0) {
+    tiles[blockIdx.x] = tot;
+    __threadfence();
+    last = atomicAdd(done, 1) == (int)gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int nt = gridDim.x;
+  const int per = (nt + kBlock - 1) / kBlock;
+  const int t0 = threadIdx.x * per, t1 = t0 + per < nt ? t0 + per : nt;
+  int part = 0;
+  for (int t = t0; t < t1; ++t)
+    part += __hip_atomic_load(&tiles[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  int total;
+  int off = block_exclusive(part, lds, &total);
+  for (int t = t0; t < t1; ++t) {
+    const int x = __hip_atomic_load(&tiles[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    tiles[t] = off;
+    off += x;
+  }
+  if (threadIdx.x == 0) {
+    tiles[nt] = total;
+    *done = 0;
+  }
 }
 
 // Which neighbour slots of each particle are in the pair set right now (the
@@ -537,7 +599,8 @@ void launch_rebuild(const DevParams& P, DevArrays& A, bool from_slots, bool mixe
     hipLaunchKernelGGL((k_compact_keys<float, true>), dim3(g), dim3(kBlock), 0, s, P, A);
   else
     hipLaunchKernelGGL((k_compact_keys<double, true>), dim3(g), dim3(kBlock), 0, s, P, A);
-  launch_exclusive_scan(A.bin_count, A.bin_start, P.nbins, A.scan_tmp, true, A.rb, s);
+  hipLaunchKernelGGL(k_scan_bins, dim3((P.nbins + kScanTile - 1) / kScanTile), dim3(kBlock), 0, s,
+                     A.bin_count, P.nbins, A.scan_tmp, &A.ctl->scan_done, A.rb);
   hipLaunchKernelGGL(k_scatter, dim3(g), dim3(kBlock), 0, s, P, A);
   hipLaunchKernelGGL(k_permute, dim3(g), dim3(kBlock), 0, s, P, A);
   // the list build is latency bound: every particle gets its own lane (the

@@ -69,7 +69,9 @@ struct Ctl {
   int max_nbr;      // largest neighbour count at a build
   int rebuild_alt;
   long long rebuilds;
-  long long pad1[5];
+  int scan_done;    // tiles of the bin scan finished so far (0 between scans)
+  int pad0;
+  long long pad1[4];
 };
 
 // Offsets into DevArrays::zgeo for a mesh of nz planes.
