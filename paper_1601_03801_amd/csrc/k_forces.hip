@@ -402,14 +402,22 @@ __device__ __forceinline__ void pair_force(const DevParams& P, const DevArrays& 
 // (bins in Morton order): the block stages the state of its own particles
 // (and of kWin particles on each side) in LDS and reads a neighbour's state
 // from there when it falls in that window, from global memory otherwise.  On
-// a deposited bed 73% of neighbour reads fall in the block itself; windows of
-// +-64 / +-128 (80% / 82%) measured no faster.
+// a deposited bed 73% of neighbour reads fall in a 256-particle block itself;
+// windows of +-64 / +-128 (80% / 82%, staging up to twice the block) measured
+// no faster, while 512-particle blocks, which stage only their own particles,
+// are 0.7% faster in FP64 (1024 no faster again).
 constexpr int kWin = 0;
-constexpr int kStage = kBlock + 2 * kWin;
+// particles per block: 512 in FP64 (4 waves per SIMD either way: two blocks
+// of 48 KB per CU), 256 in FP32 (which runs 5 waves per SIMD)
+template <typename R>
+constexpr int force_block() {
+  return sizeof(R) == 8 ? 512 : 256;
+}
+template <int NS>
 struct Staged {
-  double4 pos[kStage];
-  double4 vel[kStage];
-  double4 omg[kStage];  // .w = particle ID
+  double4 pos[NS];
+  double4 vel[NS];
+  double4 omg[NS];  // .w = particle ID
 };
 
 // Occupancy: the kernel is bound by the memory latency each SIMD can hide,
@@ -418,10 +426,12 @@ struct Staged {
 // waves on the 10M-sphere bed); the FP64 kernels keep the compiler's choice
 // (4 waves: forcing 5 spills inside the loop).
 template <typename R, int MODE>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1)))
+__global__ __launch_bounds__(force_block<R>()) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 5 : 1)))
 void k_forces(DevParams P, DevArrays A, int update_history) {
-  __shared__ Staged S;
-  const int base = xcd_block(blockIdx.x, gridDim.x) * kBlock;
+  constexpr int kFB = force_block<R>();
+  constexpr int kStage = kFB + 2 * kWin;
+  __shared__ Staged<kStage> S;
+  const int base = xcd_block(blockIdx.x, gridDim.x) * kFB;
   const int i = base + threadIdx.x;
   if (i == 0 && *A.rb) {
     A.ctl->rebuilds += 1;
@@ -429,7 +439,7 @@ void k_forces(DevParams P, DevArrays A, int update_history) {
   }
   const int N = P.n;
   const int wlo = base - kWin;
-  for (int t = threadIdx.x; t < kStage; t += kBlock) {
+  for (int t = threadIdx.x; t < kStage; t += kFB) {
     const int g = wlo + t;
     if (g >= 0 && g < N) {
       S.pos[t] = A.pos[g];
@@ -607,22 +617,25 @@ __global__ void k_pack_eps(DevParams P, DevArrays A) {
 void launch_forces(const DevParams& P, DevArrays& A, int mode, bool update_history,
                    bool mixed, hipStream_t s) {
   if (P.n <= 0) return;
-  unsigned g = xcd_grid((P.n + kBlock - 1) / kBlock);
   int u = update_history ? 1 : 0;
   if (mixed) {
+    constexpr int fb = force_block<float>();
+    const unsigned g = xcd_grid((P.n + fb - 1) / fb);
     if (mode == 0)
-      hipLaunchKernelGGL((k_forces<float, 0>), dim3(g), dim3(kBlock), 0, s, P, A, u);
+      hipLaunchKernelGGL((k_forces<float, 0>), dim3(g), dim3(fb), 0, s, P, A, u);
     else if (mode == 2)
-      hipLaunchKernelGGL((k_forces<float, 2>), dim3(g), dim3(kBlock), 0, s, P, A, u);
+      hipLaunchKernelGGL((k_forces<float, 2>), dim3(g), dim3(fb), 0, s, P, A, u);
     else
-      hipLaunchKernelGGL((k_forces<float, 1>), dim3(g), dim3(kBlock), 0, s, P, A, u);
+      hipLaunchKernelGGL((k_forces<float, 1>), dim3(g), dim3(fb), 0, s, P, A, u);
   } else {
+    constexpr int fb = force_block<double>();
+    const unsigned g = xcd_grid((P.n + fb - 1) / fb);
     if (mode == 0)
-      hipLaunchKernelGGL((k_forces<double, 0>), dim3(g), dim3(kBlock), 0, s, P, A, u);
+      hipLaunchKernelGGL((k_forces<double, 0>), dim3(g), dim3(fb), 0, s, P, A, u);
     else if (mode == 2)
-      hipLaunchKernelGGL((k_forces<double, 2>), dim3(g), dim3(kBlock), 0, s, P, A, u);
+      hipLaunchKernelGGL((k_forces<double, 2>), dim3(g), dim3(fb), 0, s, P, A, u);
     else
-      hipLaunchKernelGGL((k_forces<double, 1>), dim3(g), dim3(kBlock), 0, s, P, A, u);
+      hipLaunchKernelGGL((k_forces<double, 1>), dim3(g), dim3(fb), 0, s, P, A, u);
   }
 }
 
