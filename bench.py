@@ -67,8 +67,8 @@ def averaging_rooflines(n, ncell, dep_ms, smooth_ms, direct, mesh, nch=4):
 # written).  Valid only for the kernel sources it was measured on.
 FORCE_PMC = {
     ("bed1m", "fp64"): {
-        "fetch_kib": 315483.9, "write_kib": 277638.8, "fetch_scale": 2.0, "write_scale": 1.0,
-        "sources_sha256": "6d36f929c818e89a59d1c3c663da8b621c4c82267fcf6eb72f50a198f02f2707",
+        "fetch_kib": 290952.6, "write_kib": 280519.1, "fetch_scale": 2.0, "write_scale": 1.0,
+        "sources_sha256": "a9a4c805a345f3170f926cc8cd1f646cb74b7d0c953bba65b7e68550a8c1e1db",
         "profile": "profiles/k_forces_bed1m_fp64.md"},
 }
 FORCE_SOURCES = ("k_forces.hip", "k_common.h", "sedimi_internal.h")
