@@ -166,16 +166,15 @@ __global__ void k_permute(DevParams P, DevArrays A) {
 // lockstep and runs the contact and lubrication code for a slot when any lane
 // needs it, so putting each list's contacts first about halves the slots
 // that run the contact code (and touch the tangential history).
-// One pass over the bins, a row of three (consecutive x) at a time: the
-// bin ranks of the next row are loaded while a row is tested, a row's three
-// member ranges are loaded together and joined into one run of candidates,
-// whose positions are loaded kBuildBatch at a time (a lane waits on one
-// memory round trip per batch, not per candidate or per bin).  Candidates
-// are tested in bin-scan order and parked with their class in the lane's row
-// of LDS.  The list is then written class by
-// class, and each slot's tangential history is matched by partner ID against
-// the contact rows of q's pre-sort position, whose IDs are held in
-// registers.
+// One pass over the bins, a row of three (consecutive x) at a time: while a
+// row is tested, the member ranges of the next row and the bin ranks of the
+// one after are loaded; a row's three ranges are joined into one run of
+// candidates, whose positions are loaded kBuildBatch at a time (a lane waits
+// on one memory round trip per batch, not per candidate or per bin).
+// Candidates are tested in bin-scan order and parked with their class in the
+// lane's row of LDS.  The list is then written class by class, and each
+// slot's tangential history is matched by partner ID against the contact
+// rows of q's pre-sort position, whose IDs are held in registers.
 // WRAP (at least 5 bins on each periodic axis): a candidate's periodic image
 // is known from its bin alone.  A neighbour bin reached without wrapping lies
 // within 2 bins, i.e. within L/2, where the minimum image is the plain
